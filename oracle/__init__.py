@@ -1,0 +1,246 @@
+"""Independent FP64 CPU oracle for the H^2 x X product and block CG.
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the benchmark's CPU
+baseline leg may import this package; the product path never does.  It shares no
+code with the HIP library (``paper_2509_17257_amd``) and imports nothing from it.
+
+Everything that follows the paper lives in ``h2_oracle.c`` (cluster tree, block
+tree, Chebyshev H^2 representation, forward / list-wise multiplication /
+backward product, block CG).  This module marshals numpy arrays in and out and
+adds the few dense checks that are plain linear algebra (dense kernel matrix,
+dense Cholesky solve).
+
+Pins: every function here is checked by ``tests/test_oracle_*.py`` against facts
+fixed by the paper's definitions or by mathematics (partition of unity,
+polynomial reproduction, nestedness, exactness for a polynomial kernel,
+dense-assembly identity, closed-form solves).  The absolute interpolation error
+for the exponential kernel is "parity unpinned": the paper gives no value for
+it; only its geometric decay in the interpolation order is checked.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import build as _build
+
+KERNEL_EXP, KERNEL_POLY, KERNEL_CONST = 0, 1, 2
+_KERNELS = {"exp": KERNEL_EXP, "poly": KERNEL_POLY, "const": KERNEL_CONST}
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = _build.build(force=False)
+    lib = C.CDLL(path)
+    P = C.c_void_p
+    I64 = C.c_int64
+    D = C.c_double
+    lib.orc_build.restype = P
+    lib.orc_build.argtypes = [P, I64, C.c_int, D, D, D, C.c_int, C.c_int]
+    lib.orc_free.argtypes = [P]
+    lib.orc_info.argtypes = [P, P]
+    lib.orc_get_tree.argtypes = [P] * 12
+    lib.orc_get_blocks.argtypes = [P] * 5
+    lib.orc_get_lists.argtypes = [P] * 3
+    for nm in ("orc_get_nodes", "orc_get_V", "orc_get_E", "orc_get_S", "orc_get_N",
+               "orc_set_S", "orc_set_N", "orc_set_E"):
+        getattr(lib, nm).argtypes = [P, P]
+    lib.orc_basis_direct.argtypes = [P, I64, P]
+    lib.orc_set_ell.argtypes = [P, D]
+    lib.orc_matmul.argtypes = [P, I64, D, P, D, P]
+    lib.orc_matmul_recursive.argtypes = [P, I64, D, P, D, P]
+    lib.orc_forward_transform.argtypes = [P, I64, P, P]
+    lib.orc_dense.argtypes = [P, P]
+    lib.orc_dense_dell.argtypes = [P, P]
+    lib.orc_block_cg.restype = I64
+    lib.orc_block_cg.argtypes = [P, I64, P, P, D, I64, C.c_int, P, P]
+    lib.orc_cg1.restype = I64
+    lib.orc_cg1.argtypes = [P, P, P, D, I64]
+    lib.orc_num_threads.restype = C.c_int
+    lib.orc_set_threads.argtypes = [C.c_int]
+    _lib = lib
+    return lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def num_threads() -> int:
+    return int(_load().orc_num_threads())
+
+
+def set_threads(t: int) -> None:
+    _load().orc_set_threads(int(t))
+
+
+class OracleH2:
+    """H^2 approximation of g(x_i, x_j) + shift * delta_ij built from the paper's definitions."""
+
+    def __init__(self, points, *, kernel="exp", ell=0.5, shift=1.0, eta=1.0, leaf=32, p=3):
+        lib = _load()
+        pts = np.ascontiguousarray(points, dtype=np.float64)
+        if pts.ndim != 2 or pts.shape[1] != 3:
+            raise ValueError("points must be n x 3")
+        self.n = pts.shape[0]
+        self.kernel = _KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
+        self.ell, self.shift, self.eta, self.leaf, self.p = float(ell), float(shift), float(eta), int(leaf), int(p)
+        self.k = self.p ** 3
+        self._h = lib.orc_build(_ptr(pts), self.n, self.kernel, self.ell, self.shift, self.eta, self.leaf, self.p)
+        if not self._h:
+            raise ValueError("oracle build failed")
+        self.points = pts
+        info = np.zeros(16, dtype=np.int64)
+        lib.orc_info(self._h, _ptr(info))
+        (self.n, self.C, self.leaves, self.n_adm, self.n_near, self.near_entries,
+         self.depth, self.k, self.p, self.nb) = [int(v) for v in info[:10]]
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            _load().orc_free(self._h)
+            self._h = None
+
+    # -- structure ---------------------------------------------------------
+    def tree(self) -> dict:
+        C_ = self.C
+        out = dict(perm=np.zeros(self.n, np.int64))
+        for nm in ("first", "size", "son0", "son1", "parent", "depth"):
+            out[nm] = np.zeros(C_, np.int64)
+        for nm in ("blo", "bhi", "ilo", "ihi"):
+            out[nm] = np.zeros((C_, 3), np.float64)
+        _load().orc_get_tree(self._h, *[_ptr(out[nm]) for nm in
+                                        ("perm", "first", "size", "son0", "son1", "parent", "depth",
+                                         "blo", "bhi", "ilo", "ihi")])
+        return out
+
+    def blocks(self) -> dict:
+        nb = self.nb
+        bt, bs, boff = np.zeros(nb, np.int64), np.zeros(nb, np.int64), np.zeros(nb, np.int64)
+        badm = np.zeros(nb, np.int32)
+        _load().orc_get_blocks(self._h, _ptr(bt), _ptr(bs), _ptr(badm), _ptr(boff))
+        lp = np.zeros(self.C + 1, np.int64)
+        lb = np.zeros(nb, np.int64)
+        _load().orc_get_lists(self._h, _ptr(lp), _ptr(lb))
+        return dict(t=bt, s=bs, adm=badm.astype(bool), off=boff, list_ptr=lp, list_blk=lb)
+
+    def nodes(self) -> np.ndarray:
+        a = np.zeros((self.C, self.k, 3))
+        _load().orc_get_nodes(self._h, _ptr(a))
+        return a
+
+    def V(self) -> np.ndarray:
+        a = np.zeros((self.n, self.k))
+        _load().orc_get_V(self._h, _ptr(a))
+        return a
+
+    def E(self) -> np.ndarray:
+        a = np.zeros((self.C, self.k, self.k))
+        _load().orc_get_E(self._h, _ptr(a))
+        return a
+
+    def S(self) -> np.ndarray:
+        a = np.zeros((self.n_adm, self.k, self.k))
+        _load().orc_get_S(self._h, _ptr(a))
+        return a
+
+    def N(self) -> np.ndarray:
+        a = np.zeros(self.near_entries)
+        _load().orc_get_N(self._h, _ptr(a))
+        return a
+
+    def set_S(self, S: np.ndarray) -> None:
+        S = np.ascontiguousarray(S, dtype=np.float64)
+        assert S.size == self.n_adm * self.k * self.k
+        _load().orc_set_S(self._h, _ptr(S))
+
+    def set_N(self, N: np.ndarray) -> None:
+        N = np.ascontiguousarray(N, dtype=np.float64)
+        assert N.size == self.near_entries
+        _load().orc_set_N(self._h, _ptr(N))
+
+    def set_E(self, E: np.ndarray) -> None:
+        E = np.ascontiguousarray(E, dtype=np.float64)
+        assert E.size == self.C * self.k * self.k
+        _load().orc_set_E(self._h, _ptr(E))
+
+    def set_ell(self, ell: float) -> None:
+        self.ell = float(ell)
+        _load().orc_set_ell(self._h, self.ell)
+
+    def basis_direct(self, c: int) -> np.ndarray:
+        sz = int(self.tree()["size"][c])
+        a = np.zeros((sz, self.k))
+        _load().orc_basis_direct(self._h, int(c), _ptr(a))
+        return a
+
+    # -- products ----------------------------------------------------------
+    def matmul(self, X, alpha=1.0, beta=0.0, Y=None, recursive=False) -> np.ndarray:
+        """Y <- beta Y + alpha A_H2 X (X, Y: n x m, original point order)."""
+        X = np.ascontiguousarray(X, dtype=np.float64)
+        squeeze = X.ndim == 1
+        if squeeze:
+            X = X[:, None].copy()
+        m = X.shape[1]
+        out = np.zeros((self.n, m)) if Y is None else np.ascontiguousarray(Y, dtype=np.float64).reshape(self.n, m).copy()
+        fn = _load().orc_matmul_recursive if recursive else _load().orc_matmul
+        fn(self._h, m, float(alpha), _ptr(X), float(beta), _ptr(out))
+        return out[:, 0] if squeeze else out
+
+    def forward_transform(self, X) -> np.ndarray:
+        X = np.ascontiguousarray(X, dtype=np.float64)
+        m = X.shape[1]
+        xh = np.zeros((self.C, self.k, m))
+        _load().orc_forward_transform(self._h, m, _ptr(X), _ptr(xh))
+        return xh
+
+    def dense(self) -> np.ndarray:
+        if self.n > 8192:
+            raise ValueError("dense assembly only for n <= 8192")
+        A = np.zeros((self.n, self.n))
+        _load().orc_dense(self._h, _ptr(A))
+        return A
+
+    def dense_dell(self) -> np.ndarray:
+        if self.n > 8192:
+            raise ValueError("dense assembly only for n <= 8192")
+        A = np.zeros((self.n, self.n))
+        _load().orc_dense_dell(self._h, _ptr(A))
+        return A
+
+    # -- solvers -----------------------------------------------------------
+    def block_cg(self, B, X0=None, rtol=1e-8, max_iter=10000, freeze_converged=False):
+        B = np.ascontiguousarray(B, dtype=np.float64)
+        m = B.shape[1]
+        X = np.zeros_like(B) if X0 is None else np.ascontiguousarray(X0, dtype=np.float64).copy()
+        ci = np.zeros(m, np.int64)
+        st = np.zeros(m, np.int32)
+        it = _load().orc_block_cg(self._h, m, _ptr(B), _ptr(X), float(rtol), int(max_iter),
+                                  int(bool(freeze_converged)), _ptr(ci), _ptr(st))
+        return X, dict(iters=int(it), col_iters=ci, status=st)
+
+    def cg1(self, b, x0=None, rtol=1e-8, max_iter=10000):
+        b = np.ascontiguousarray(b, dtype=np.float64).reshape(-1)
+        x = np.zeros_like(b) if x0 is None else np.ascontiguousarray(x0, dtype=np.float64).reshape(-1).copy()
+        it = _load().orc_cg1(self._h, _ptr(b), _ptr(x), float(rtol), int(max_iter))
+        return x, int(it)
+
+
+def kernel_matrix(points, *, kernel="exp", ell=0.5, shift=1.0) -> np.ndarray:
+    """The exact dense matrix g(x_i, x_j) + shift * delta_ij (no H^2 approximation)."""
+    P = np.asarray(points, dtype=np.float64)
+    kern = _KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
+    if kern == KERNEL_EXP:
+        D = np.sqrt(((P[:, None, :] - P[None, :, :]) ** 2).sum(-1))
+        A = np.exp(-D / ell)
+    elif kern == KERNEL_POLY:
+        A = (1.0 + P @ P.T) ** 2
+    else:
+        A = np.ones((P.shape[0], P.shape[0]))
+    A[np.diag_indices_from(A)] += shift
+    return A

@@ -1,0 +1,862 @@
+/*
+ * Independent FP64 CPU oracle for the H^2-matrix x block-of-vectors product and
+ * block CG ("On efficient block Krylov solvers for H^2-matrices", arXiv 2509.17257).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or call
+ * this file; only the tests, the smoke check and the CPU-baseline leg of the
+ * benchmark do.  It shares no code, header, table or helper with the HIP path.
+ *
+ * Plain and slow on purpose: recursion where the paper recurses, plain loops for
+ * every small matrix product, FP64 everywhere (except the explicitly emulated
+ * low-precision operator), OpenMP only where the paper itself runs "parfor".
+ * Build: gcc -O2 -fopenmp -ffp-contract=off -shared -fPIC (see oracle/build.py).
+ *
+ * Readings of the paper where it is silent (each is also listed in the design
+ * notes): binary bounding-box bisection at the box midpoint of the widest
+ * dimension; leaf when |t| <= leaf size; tight boxes for diam/dist, equality is
+ * admissible, dist 0 never is; first-kind Chebyshev tensor interpolation with
+ * nu = jx + p*jy + p^2*jz; W == V (real symmetric kernel); the shift sits in the
+ * diagonal near-field blocks; lists C_t are processed for every cluster t.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+enum { ORC_KERNEL_EXP = 0, ORC_KERNEL_POLY = 1, ORC_KERNEL_CONST = 2 };
+
+typedef struct {
+    /* problem (section 2: index set I = J, points as the supports Omega_i) */
+    int64_t n;
+    double *pts; /* n x 3, original order */
+    int kernel;
+    double ell, shift, eta;
+    int leaf, p, k;
+
+    /* cluster tree T_I (Definition "Cluster tree"), clusters numbered in pre-order */
+    int64_t C;
+    int64_t *first, *size, *son0, *son1, *parent, *depth;
+    double *blo, *bhi;   /* tight bounding boxes, C x 3 */
+    double *ilo, *ihi;   /* interpolation boxes, C x 3 */
+    double *nodes;       /* Chebyshev tensor nodes, C x k x 3 */
+    int64_t *perm;       /* tree position -> original index */
+
+    /* leaves of the block tree T_{IxJ} (Definition "Block tree"), in pre-order */
+    int64_t nb, bcap;
+    int64_t *bt, *bs;
+    int *badm;
+    int64_t n_adm, n_near, near_entries;
+    int64_t *boff;       /* offset of each leaf block's matrix in S (adm) or N (near) */
+
+    /* lists C_t of prepare_addeval (Algorithm "prepare_addeval") */
+    int64_t *list_ptr;   /* C + 1 */
+    int64_t *list_blk;   /* nb, block ids grouped by row cluster, in block pre-order */
+
+    /* H^2 representation */
+    double *V;           /* n x k, leaf matrices, rows in tree order */
+    double *E;           /* C x k x k, transfer matrices (root's entry unused) */
+    double *S;           /* n_adm x k x k coupling matrices */
+    double *N;           /* near_entries, near-field blocks row-major |t| x |s| */
+} orc_h2;
+
+/* ------------------------------------------------------------------------ */
+/* kernel function g and its derivative in ell                               */
+
+static double orc_dist3(const double *a, const double *b) {
+    double dx = a[0] - b[0], dy = a[1] - b[1], dz = a[2] - b[2];
+    return sqrt(dx * dx + dy * dy + dz * dz);
+}
+
+static double orc_g(const orc_h2 *h, const double *a, const double *b) {
+    if (h->kernel == ORC_KERNEL_EXP) return exp(-orc_dist3(a, b) / h->ell);
+    if (h->kernel == ORC_KERNEL_POLY) {
+        double d = 1.0 + a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+        return d * d;
+    }
+    return 1.0;
+}
+
+/* d g / d ell for the exponential kernel: (r / ell^2) exp(-r / ell); 0 otherwise */
+static double orc_dg(const orc_h2 *h, const double *a, const double *b) {
+    if (h->kernel != ORC_KERNEL_EXP) return 0.0;
+    double r = orc_dist3(a, b);
+    return (r / (h->ell * h->ell)) * exp(-r / h->ell);
+}
+
+/* ------------------------------------------------------------------------ */
+/* cluster tree: recursive binary bisection                                  */
+
+static void orc_tight_box(orc_h2 *h, int64_t c) {
+    for (int d = 0; d < 3; ++d) {
+        double lo = h->pts[3 * h->perm[h->first[c]] + d], hi = lo;
+        for (int64_t i = 1; i < h->size[c]; ++i) {
+            double v = h->pts[3 * h->perm[h->first[c] + i] + d];
+            if (v < lo) lo = v;
+            if (v > hi) hi = v;
+        }
+        h->blo[3 * c + d] = lo;
+        h->bhi[3 * c + d] = hi;
+    }
+}
+
+static int64_t orc_build_cluster(orc_h2 *h, int64_t first, int64_t size, int64_t parent,
+                                 int64_t depth, int64_t *tmp) {
+    int64_t c = h->C++;
+    h->first[c] = first;
+    h->size[c] = size;
+    h->parent[c] = parent;
+    h->depth[c] = depth;
+    h->son0[c] = h->son1[c] = -1;
+    orc_tight_box(h, c);
+    if (size <= h->leaf) return c;
+    int dstar = 0;
+    double ext = h->bhi[3 * c] - h->blo[3 * c];
+    for (int d = 1; d < 3; ++d) {
+        double e = h->bhi[3 * c + d] - h->blo[3 * c + d];
+        if (e > ext) { ext = e; dstar = d; }
+    }
+    if (ext == 0.0) return c; /* all points coincide */
+    double mid = 0.5 * (h->blo[3 * c + dstar] + h->bhi[3 * c + dstar]);
+    /* stable partition: points strictly below mid first, then the rest */
+    int64_t n0 = 0, n1 = 0;
+    for (int64_t i = 0; i < size; ++i) {
+        int64_t g = h->perm[first + i];
+        if (h->pts[3 * g + dstar] < mid) h->perm[first + n0++] = g;
+        else tmp[n1++] = g;
+    }
+    for (int64_t i = 0; i < n1; ++i) h->perm[first + n0 + i] = tmp[i];
+    if (n0 == 0 || n1 == 0) return c; /* degenerate split: keep as leaf */
+    h->son0[c] = orc_build_cluster(h, first, n0, c, depth + 1, tmp);
+    h->son1[c] = orc_build_cluster(h, first + n0, n1, c, depth + 1, tmp);
+    return c;
+}
+
+/* ------------------------------------------------------------------------ */
+/* block tree with the standard admissibility condition                       */
+
+static double orc_diam(const orc_h2 *h, int64_t c) {
+    double s = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        double e = h->bhi[3 * c + d] - h->blo[3 * c + d];
+        s += e * e;
+    }
+    return sqrt(s);
+}
+
+static double orc_dist(const orc_h2 *h, int64_t t, int64_t s) {
+    double acc = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        double g = 0.0;
+        double a = h->blo[3 * s + d] - h->bhi[3 * t + d];
+        double b = h->blo[3 * t + d] - h->bhi[3 * s + d];
+        if (a > g) g = a;
+        if (b > g) g = b;
+        acc += g * g;
+    }
+    return sqrt(acc);
+}
+
+static int orc_admissible(const orc_h2 *h, int64_t t, int64_t s) {
+    double dist = orc_dist(h, t, s);
+    if (!(dist > 0.0)) return 0;
+    double dt = orc_diam(h, t), ds = orc_diam(h, s);
+    double dm = dt > ds ? dt : ds;
+    return dm <= h->eta * dist;
+}
+
+static void orc_add_block(orc_h2 *h, int64_t t, int64_t s, int adm) {
+    if (h->nb == h->bcap) {
+        h->bcap = h->bcap ? 2 * h->bcap : 1024;
+        h->bt = realloc(h->bt, sizeof(int64_t) * h->bcap);
+        h->bs = realloc(h->bs, sizeof(int64_t) * h->bcap);
+        h->badm = realloc(h->badm, sizeof(int) * h->bcap);
+    }
+    h->bt[h->nb] = t;
+    h->bs[h->nb] = s;
+    h->badm[h->nb] = adm;
+    h->nb++;
+}
+
+static int orc_is_leaf(const orc_h2 *h, int64_t c) { return h->son0[c] < 0; }
+
+static void orc_build_blocks(orc_h2 *h, int64_t t, int64_t s) {
+    if (orc_admissible(h, t, s)) { orc_add_block(h, t, s, 1); return; }
+    int lt = orc_is_leaf(h, t), ls = orc_is_leaf(h, s);
+    if (lt && ls) { orc_add_block(h, t, s, 0); return; }
+    if (lt) {
+        orc_build_blocks(h, t, h->son0[s]);
+        orc_build_blocks(h, t, h->son1[s]);
+    } else if (ls) {
+        orc_build_blocks(h, h->son0[t], s);
+        orc_build_blocks(h, h->son1[t], s);
+    } else {
+        orc_build_blocks(h, h->son0[t], h->son0[s]);
+        orc_build_blocks(h, h->son0[t], h->son1[s]);
+        orc_build_blocks(h, h->son1[t], h->son0[s]);
+        orc_build_blocks(h, h->son1[t], h->son1[s]);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Chebyshev interpolation: nodes, Lagrange polynomials, V, E, S, N           */
+
+#define ORC_TAU 1e-10
+
+static void orc_interp_boxes_and_nodes(orc_h2 *h) {
+    const int p = h->p, k = h->k;
+    const double pi = acos(-1.0);
+    for (int64_t c = 0; c < h->C; ++c) {
+        double nd[3][16];
+        for (int d = 0; d < 3; ++d) {
+            double lo = h->blo[3 * c + d], hi = h->bhi[3 * c + d];
+            if (hi - lo < ORC_TAU) {
+                double ctr = 0.5 * (lo + hi);
+                lo = ctr - 0.5 * ORC_TAU;
+                hi = ctr + 0.5 * ORC_TAU;
+            }
+            h->ilo[3 * c + d] = lo;
+            h->ihi[3 * c + d] = hi;
+            double ctr = 0.5 * (lo + hi), half = 0.5 * (hi - lo);
+            for (int j = 0; j < p; ++j) nd[d][j] = ctr + half * cos((2.0 * j + 1.0) * pi / (2.0 * p));
+        }
+        for (int jz = 0; jz < p; ++jz)
+            for (int jy = 0; jy < p; ++jy)
+                for (int jx = 0; jx < p; ++jx) {
+                    int nu = jx + p * jy + p * p * jz;
+                    double *o = &h->nodes[((size_t)c * k + nu) * 3];
+                    o[0] = nd[0][jx];
+                    o[1] = nd[1][jy];
+                    o[2] = nd[2][jz];
+                }
+    }
+}
+
+/* one-dimensional Chebyshev node j of cluster c in dimension d */
+static double orc_node1(const orc_h2 *h, int64_t c, int d, int j) {
+    int p = h->p;
+    int nu = (d == 0) ? j : (d == 1 ? p * j : p * p * j);
+    return h->nodes[((size_t)c * h->k + nu) * 3 + d];
+}
+
+/* L_{c,j}(x) in dimension d: prod_{i != j} (x - xi_i) / (xi_j - xi_i) */
+static double orc_lagrange(const orc_h2 *h, int64_t c, int d, int j, double x) {
+    double v = 1.0, xj = orc_node1(h, c, d, j);
+    for (int i = 0; i < h->p; ++i) {
+        if (i == j) continue;
+        double xi = orc_node1(h, c, d, i);
+        v *= (x - xi) / (xj - xi);
+    }
+    return v;
+}
+
+/* tensor Lagrange polynomial nu of cluster c at the point x */
+static double orc_lagrange3(const orc_h2 *h, int64_t c, int nu, const double *x) {
+    int p = h->p;
+    int jx = nu % p, jy = (nu / p) % p, jz = nu / (p * p);
+    return orc_lagrange(h, c, 0, jx, x[0]) * orc_lagrange(h, c, 1, jy, x[1]) *
+           orc_lagrange(h, c, 2, jz, x[2]);
+}
+
+static void orc_fill_matrices(orc_h2 *h) {
+    const int k = h->k;
+    /* leaf matrices V_t[i, nu] = L_{t,nu}(x_i) */
+    for (int64_t c = 0; c < h->C; ++c) {
+        if (!orc_is_leaf(h, c)) continue;
+        for (int64_t i = 0; i < h->size[c]; ++i) {
+            int64_t row = h->first[c] + i;
+            const double *x = &h->pts[3 * h->perm[row]];
+            for (int nu = 0; nu < k; ++nu) h->V[row * k + nu] = orc_lagrange3(h, c, nu, x);
+        }
+    }
+    /* transfer matrices E_{t'}[nu', nu] = L_{t,nu}(xi_{t',nu'}) for t' in sons(t) */
+    for (int64_t c = 0; c < h->C; ++c) {
+        int64_t par = h->parent[c];
+        if (par < 0) continue;
+        for (int a = 0; a < k; ++a) {
+            const double *xi = &h->nodes[((size_t)c * k + a) * 3];
+            for (int nu = 0; nu < k; ++nu) h->E[((size_t)c * k + a) * k + nu] = orc_lagrange3(h, par, nu, xi);
+        }
+    }
+    /* coupling and near-field blocks */
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t b = 0; b < h->nb; ++b) {
+        int64_t t = h->bt[b], s = h->bs[b];
+        if (h->badm[b]) {
+            double *Sb = &h->S[h->boff[b]];
+            for (int nu = 0; nu < k; ++nu)
+                for (int mu = 0; mu < k; ++mu)
+                    Sb[nu * k + mu] = orc_g(h, &h->nodes[((size_t)t * k + nu) * 3], &h->nodes[((size_t)s * k + mu) * 3]);
+        } else {
+            double *Nb = &h->N[h->boff[b]];
+            for (int64_t i = 0; i < h->size[t]; ++i)
+                for (int64_t j = 0; j < h->size[s]; ++j) {
+                    int64_t gi = h->perm[h->first[t] + i], gj = h->perm[h->first[s] + j];
+                    double v = orc_g(h, &h->pts[3 * gi], &h->pts[3 * gj]);
+                    if (gi == gj) v += h->shift;
+                    Nb[i * h->size[s] + j] = v;
+                }
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* construction                                                             */
+
+orc_h2 *orc_build(const double *pts, int64_t n, int kernel, double ell, double shift, double eta,
+                  int leaf, int p) {
+    if (n <= 0 || p < 1 || p > 16 || leaf < 1) return NULL;
+    orc_h2 *h = calloc(1, sizeof(orc_h2));
+    h->n = n;
+    h->kernel = kernel;
+    h->ell = ell;
+    h->shift = shift;
+    h->eta = eta;
+    h->leaf = leaf;
+    h->p = p;
+    h->k = p * p * p;
+    h->pts = malloc(sizeof(double) * 3 * n);
+    memcpy(h->pts, pts, sizeof(double) * 3 * n);
+    int64_t cap = 2 * n;
+    h->first = malloc(sizeof(int64_t) * cap);
+    h->size = malloc(sizeof(int64_t) * cap);
+    h->son0 = malloc(sizeof(int64_t) * cap);
+    h->son1 = malloc(sizeof(int64_t) * cap);
+    h->parent = malloc(sizeof(int64_t) * cap);
+    h->depth = malloc(sizeof(int64_t) * cap);
+    h->blo = malloc(sizeof(double) * 3 * cap);
+    h->bhi = malloc(sizeof(double) * 3 * cap);
+    h->perm = malloc(sizeof(int64_t) * n);
+    for (int64_t i = 0; i < n; ++i) h->perm[i] = i;
+    int64_t *tmp = malloc(sizeof(int64_t) * n);
+    orc_build_cluster(h, 0, n, -1, 0, tmp);
+    free(tmp);
+
+    orc_build_blocks(h, 0, 0);
+
+    /* matrix offsets of the leaf blocks */
+    h->boff = malloc(sizeof(int64_t) * (h->nb ? h->nb : 1));
+    int64_t so = 0, no = 0;
+    for (int64_t b = 0; b < h->nb; ++b) {
+        if (h->badm[b]) { h->boff[b] = so; so += (int64_t)h->k * h->k; h->n_adm++; }
+        else { h->boff[b] = no; no += h->size[h->bt[b]] * h->size[h->bs[b]]; h->n_near++; }
+    }
+    h->near_entries = no;
+
+    /* prepare_addeval: each leaf block goes to the list of its row cluster */
+    h->list_ptr = calloc(h->C + 1, sizeof(int64_t));
+    h->list_blk = malloc(sizeof(int64_t) * (h->nb ? h->nb : 1));
+    for (int64_t b = 0; b < h->nb; ++b) h->list_ptr[h->bt[b] + 1]++;
+    for (int64_t c = 0; c < h->C; ++c) h->list_ptr[c + 1] += h->list_ptr[c];
+    int64_t *fill = calloc((size_t)h->C + 1, sizeof(int64_t));
+    for (int64_t b = 0; b < h->nb; ++b) {
+        int64_t t = h->bt[b];
+        h->list_blk[h->list_ptr[t] + fill[t]++] = b;
+    }
+    free(fill);
+
+    h->ilo = malloc(sizeof(double) * 3 * h->C);
+    h->ihi = malloc(sizeof(double) * 3 * h->C);
+    h->nodes = malloc(sizeof(double) * 3 * h->C * h->k);
+    orc_interp_boxes_and_nodes(h);
+
+    h->V = malloc(sizeof(double) * n * h->k);
+    h->E = calloc((size_t)h->C * h->k * h->k, sizeof(double));
+    h->S = malloc(sizeof(double) * (so ? so : 1));
+    h->N = malloc(sizeof(double) * (no ? no : 1));
+    orc_fill_matrices(h);
+    return h;
+}
+
+void orc_free(orc_h2 *h) {
+    if (!h) return;
+    free(h->pts); free(h->first); free(h->size); free(h->son0); free(h->son1);
+    free(h->parent); free(h->depth); free(h->blo); free(h->bhi); free(h->ilo); free(h->ihi);
+    free(h->nodes); free(h->perm); free(h->bt); free(h->bs); free(h->badm); free(h->boff);
+    free(h->list_ptr); free(h->list_blk); free(h->V); free(h->E); free(h->S); free(h->N);
+    free(h);
+}
+
+/* info[0..9] = n, C, leaves, n_adm, n_near, near_entries, max depth, k, p, n blocks */
+void orc_info(const orc_h2 *h, int64_t *info) {
+    int64_t leaves = 0, dmax = 0;
+    for (int64_t c = 0; c < h->C; ++c) {
+        if (orc_is_leaf(h, c)) leaves++;
+        if (h->depth[c] > dmax) dmax = h->depth[c];
+    }
+    info[0] = h->n; info[1] = h->C; info[2] = leaves; info[3] = h->n_adm; info[4] = h->n_near;
+    info[5] = h->near_entries; info[6] = dmax; info[7] = h->k; info[8] = h->p; info[9] = h->nb;
+}
+
+void orc_get_tree(const orc_h2 *h, int64_t *perm, int64_t *first, int64_t *size, int64_t *son0,
+                  int64_t *son1, int64_t *parent, int64_t *depth, double *blo, double *bhi,
+                  double *ilo, double *ihi) {
+    memcpy(perm, h->perm, sizeof(int64_t) * h->n);
+    memcpy(first, h->first, sizeof(int64_t) * h->C);
+    memcpy(size, h->size, sizeof(int64_t) * h->C);
+    memcpy(son0, h->son0, sizeof(int64_t) * h->C);
+    memcpy(son1, h->son1, sizeof(int64_t) * h->C);
+    memcpy(parent, h->parent, sizeof(int64_t) * h->C);
+    memcpy(depth, h->depth, sizeof(int64_t) * h->C);
+    memcpy(blo, h->blo, sizeof(double) * 3 * h->C);
+    memcpy(bhi, h->bhi, sizeof(double) * 3 * h->C);
+    memcpy(ilo, h->ilo, sizeof(double) * 3 * h->C);
+    memcpy(ihi, h->ihi, sizeof(double) * 3 * h->C);
+}
+
+void orc_get_blocks(const orc_h2 *h, int64_t *bt, int64_t *bs, int32_t *badm, int64_t *boff) {
+    for (int64_t b = 0; b < h->nb; ++b) {
+        bt[b] = h->bt[b]; bs[b] = h->bs[b]; badm[b] = h->badm[b]; boff[b] = h->boff[b];
+    }
+}
+
+void orc_get_lists(const orc_h2 *h, int64_t *list_ptr, int64_t *list_blk) {
+    memcpy(list_ptr, h->list_ptr, sizeof(int64_t) * (h->C + 1));
+    memcpy(list_blk, h->list_blk, sizeof(int64_t) * h->nb);
+}
+
+void orc_get_nodes(const orc_h2 *h, double *nodes) { memcpy(nodes, h->nodes, sizeof(double) * 3 * h->C * h->k); }
+void orc_get_V(const orc_h2 *h, double *V) { memcpy(V, h->V, sizeof(double) * h->n * h->k); }
+void orc_get_E(const orc_h2 *h, double *E) { memcpy(E, h->E, sizeof(double) * h->C * h->k * h->k); }
+void orc_get_S(const orc_h2 *h, double *S) { memcpy(S, h->S, sizeof(double) * h->n_adm * h->k * h->k); }
+void orc_get_N(const orc_h2 *h, double *N) { memcpy(N, h->N, sizeof(double) * h->near_entries); }
+
+/* Direct Lagrange evaluation of the basis of ANY cluster c (leaf or not) at the
+ * points of c, in tree order: out is |c| x k.  Used to pin nestedness. */
+void orc_basis_direct(const orc_h2 *h, int64_t c, double *out) {
+    for (int64_t i = 0; i < h->size[c]; ++i) {
+        const double *x = &h->pts[3 * h->perm[h->first[c] + i]];
+        for (int nu = 0; nu < h->k; ++nu) out[i * h->k + nu] = orc_lagrange3(h, c, nu, x);
+    }
+}
+
+/* Replace the stored matrices (used by tests that perturb S or inject a mistake). */
+void orc_set_S(orc_h2 *h, const double *S) { memcpy(h->S, S, sizeof(double) * h->n_adm * h->k * h->k); }
+void orc_set_N(orc_h2 *h, const double *N) { memcpy(h->N, N, sizeof(double) * h->near_entries); }
+void orc_set_E(orc_h2 *h, const double *E) { memcpy(h->E, E, sizeof(double) * h->C * h->k * h->k); }
+
+/* Re-evaluate S and N for a new length scale ell (same tree and bases). */
+void orc_set_ell(orc_h2 *h, double ell) {
+    h->ell = ell;
+    orc_fill_matrices(h);
+}
+
+/* ------------------------------------------------------------------------ */
+/* H^2 x X: forward transformation, list-wise multiplication phase, backward  */
+/* X, Y are n x m row-major in ORIGINAL point order.                          */
+
+typedef struct {
+    const orc_h2 *h;
+    int64_t m;
+    const double *X;
+    double *xh, *yh; /* C x k x m */
+} orc_mm;
+
+/* Forward: leaf x_s = W_s^* x|_s ; inner x_s = sum_{s' in sons} E_{s'}^* x_{s'} */
+static void orc_forward(orc_mm *w, int64_t s) {
+    const orc_h2 *h = w->h;
+    const int k = h->k;
+    const int64_t m = w->m;
+    double *xs = &w->xh[(size_t)s * k * m];
+    if (orc_is_leaf(h, s)) {
+        for (int nu = 0; nu < k; ++nu)
+            for (int64_t j = 0; j < m; ++j) {
+                double acc = 0.0;
+                for (int64_t i = 0; i < h->size[s]; ++i) {
+                    int64_t row = h->first[s] + i;
+                    acc += h->V[row * k + nu] * w->X[h->perm[row] * m + j];
+                }
+                xs[nu * m + j] = acc;
+            }
+        return;
+    }
+    int64_t sons[2] = {h->son0[s], h->son1[s]};
+    /* sons in parallel (P_Forward), then the parent sums sequentially */
+    for (int q = 0; q < 2; ++q) orc_forward(w, sons[q]);
+    for (int q = 0; q < 2; ++q) {
+        const double *E = &h->E[(size_t)sons[q] * k * k];
+        const double *xq = &w->xh[(size_t)sons[q] * k * m];
+        for (int nu = 0; nu < k; ++nu)
+            for (int64_t j = 0; j < m; ++j) {
+                double acc = 0.0;
+                for (int a = 0; a < k; ++a) acc += E[a * k + nu] * xq[a * m + j];
+                xs[nu * m + j] += acc;
+            }
+    }
+}
+
+/* Backward: inner y_{t'} += E_{t'} y_t then recurse ; leaf y|_t += V_t y_t */
+static void orc_backward(const orc_mm *w, int64_t t, double *Y) {
+    const orc_h2 *h = w->h;
+    const int k = h->k;
+    const int64_t m = w->m;
+    double *yt = &w->yh[(size_t)t * k * m];
+    if (orc_is_leaf(h, t)) {
+        for (int64_t i = 0; i < h->size[t]; ++i) {
+            int64_t row = h->first[t] + i;
+            double *yrow = &Y[h->perm[row] * m];
+            for (int64_t j = 0; j < m; ++j) {
+                double acc = 0.0;
+                for (int nu = 0; nu < k; ++nu) acc += h->V[row * k + nu] * yt[nu * m + j];
+                yrow[j] += acc;
+            }
+        }
+        return;
+    }
+    int64_t sons[2] = {h->son0[t], h->son1[t]};
+    for (int q = 0; q < 2; ++q) {
+        const double *E = &h->E[(size_t)sons[q] * k * k];
+        double *yq = &w->yh[(size_t)sons[q] * k * m];
+        for (int a = 0; a < k; ++a)
+            for (int64_t j = 0; j < m; ++j) {
+                double acc = 0.0;
+                for (int nu = 0; nu < k; ++nu) acc += E[a * k + nu] * yt[nu * m + j];
+                yq[a * m + j] += acc;
+            }
+        orc_backward(w, sons[q], Y);
+    }
+}
+
+/* list_addeval for one row cluster t: admissible -> y_t += alpha S_b x_s,
+ * inadmissible -> y|_t += alpha G|_{t x s} x|_s.  Owns y_t and the rows of t. */
+static void orc_list_addeval(const orc_mm *w, int64_t t, double alpha, double *Y) {
+    const orc_h2 *h = w->h;
+    const int k = h->k;
+    const int64_t m = w->m;
+    for (int64_t q = h->list_ptr[t]; q < h->list_ptr[t + 1]; ++q) {
+        int64_t b = h->list_blk[q], s = h->bs[b];
+        if (h->badm[b]) {
+            const double *Sb = &h->S[h->boff[b]];
+            const double *xs = &w->xh[(size_t)s * k * m];
+            double *yt = &w->yh[(size_t)t * k * m];
+            for (int nu = 0; nu < k; ++nu)
+                for (int64_t j = 0; j < m; ++j) {
+                    double acc = 0.0;
+                    for (int mu = 0; mu < k; ++mu) acc += Sb[nu * k + mu] * xs[mu * m + j];
+                    yt[nu * m + j] += alpha * acc;
+                }
+        } else {
+            const double *Nb = &h->N[h->boff[b]];
+            int64_t ns = h->size[s];
+            for (int64_t i = 0; i < h->size[t]; ++i) {
+                double *yrow = &Y[h->perm[h->first[t] + i] * m];
+                for (int64_t j = 0; j < m; ++j) {
+                    double acc = 0.0;
+                    for (int64_t c = 0; c < ns; ++c) acc += Nb[i * ns + c] * w->X[h->perm[h->first[s] + c] * m + j];
+                    yrow[j] += alpha * acc;
+                }
+            }
+        }
+    }
+}
+
+/* Y <- beta Y + alpha A_H2 X  (H2_mvm in its matrix form) */
+void orc_matmul(const orc_h2 *h, int64_t m, double alpha, const double *X, double beta, double *Y) {
+    orc_mm w;
+    w.h = h;
+    w.m = m;
+    w.X = X;
+    size_t cw = (size_t)h->C * h->k * m;
+    w.xh = calloc(cw ? cw : 1, sizeof(double));
+    w.yh = calloc(cw ? cw : 1, sizeof(double));
+    for (int64_t i = 0; i < h->n * m; ++i) Y[i] = (beta == 0.0) ? 0.0 : beta * Y[i];
+
+    /* forward: the leaf products are independent (sons in parallel), the transfer
+     * sums run in the recursion after them */
+    {
+        const int k = h->k;
+#pragma omp parallel for schedule(dynamic, 4)
+        for (int64_t s = 0; s < h->C; ++s) {
+            if (!orc_is_leaf(h, s)) continue;
+            double *xs = &w.xh[(size_t)s * k * m];
+            for (int nu = 0; nu < k; ++nu)
+                for (int64_t j = 0; j < m; ++j) {
+                    double acc = 0.0;
+                    for (int64_t i = 0; i < h->size[s]; ++i) {
+                        int64_t row = h->first[s] + i;
+                        acc += h->V[row * k + nu] * X[h->perm[row] * m + j];
+                    }
+                    xs[nu * m + j] = acc;
+                }
+        }
+    }
+    /* transfer part of the forward recursion (leaves already done above) */
+    {
+        /* post-order walk: clusters are in pre-order, so iterate from the back */
+        const int k = h->k;
+        for (int64_t s = h->C - 1; s >= 0; --s) {
+            if (orc_is_leaf(h, s)) continue;
+            double *xs = &w.xh[(size_t)s * k * m];
+            int64_t sons[2] = {h->son0[s], h->son1[s]};
+            for (int q = 0; q < 2; ++q) {
+                const double *E = &h->E[(size_t)sons[q] * k * k];
+                const double *xq = &w.xh[(size_t)sons[q] * k * m];
+                for (int nu = 0; nu < k; ++nu)
+                    for (int64_t j = 0; j < m; ++j) {
+                        double acc = 0.0;
+                        for (int a = 0; a < k; ++a) acc += E[a * k + nu] * xq[a * m + j];
+                        xs[nu * m + j] += acc;
+                    }
+            }
+        }
+    }
+    /* multiplication phase: every cluster's list, clusters in parallel */
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t t = 0; t < h->C; ++t) orc_list_addeval(&w, t, alpha, Y);
+    /* backward */
+    orc_backward(&w, 0, Y);
+    free(w.xh);
+    free(w.yh);
+}
+
+/* Same product, but the forward transformation runs the plain recursion of the
+ * paper's sequential Forward (used to pin the parallel variant against it). */
+void orc_matmul_recursive(const orc_h2 *h, int64_t m, double alpha, const double *X, double beta, double *Y) {
+    orc_mm w;
+    w.h = h;
+    w.m = m;
+    w.X = X;
+    size_t cw = (size_t)h->C * h->k * m;
+    w.xh = calloc(cw ? cw : 1, sizeof(double));
+    w.yh = calloc(cw ? cw : 1, sizeof(double));
+    for (int64_t i = 0; i < h->n * m; ++i) Y[i] = (beta == 0.0) ? 0.0 : beta * Y[i];
+    orc_forward(&w, 0);
+    for (int64_t t = 0; t < h->C; ++t) orc_list_addeval(&w, t, alpha, Y);
+    orc_backward(&w, 0, Y);
+    free(w.xh);
+    free(w.yh);
+}
+
+/* Forward transform only: xh (C x k x m) of X (n x m, original order). */
+void orc_forward_transform(const orc_h2 *h, int64_t m, const double *X, double *xh) {
+    orc_mm w;
+    w.h = h;
+    w.m = m;
+    w.X = X;
+    w.xh = xh;
+    w.yh = NULL;
+    memset(xh, 0, sizeof(double) * h->C * h->k * m);
+    orc_forward(&w, 0);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Dense assembly of A_H2 from its definition (n x n, original order)         */
+
+/* full cluster basis V_t (|t| x k): leaf matrix, or [V_{t0} E_{t0}; V_{t1} E_{t1}] */
+static void orc_basis_full(const orc_h2 *h, int64_t t, double *out) {
+    const int k = h->k;
+    if (orc_is_leaf(h, t)) {
+        memcpy(out, &h->V[h->first[t] * k], sizeof(double) * h->size[t] * k);
+        return;
+    }
+    int64_t sons[2] = {h->son0[t], h->son1[t]};
+    int64_t row0 = 0;
+    for (int q = 0; q < 2; ++q) {
+        int64_t sq = sons[q];
+        double *Vq = malloc(sizeof(double) * h->size[sq] * k);
+        orc_basis_full(h, sq, Vq);
+        const double *E = &h->E[(size_t)sq * k * k];
+        for (int64_t i = 0; i < h->size[sq]; ++i)
+            for (int nu = 0; nu < k; ++nu) {
+                double acc = 0.0;
+                for (int a = 0; a < k; ++a) acc += Vq[i * k + a] * E[a * k + nu];
+                out[(row0 + i) * k + nu] = acc;
+            }
+        row0 += h->size[sq];
+        free(Vq);
+    }
+}
+
+void orc_dense(const orc_h2 *h, double *A) {
+    const int k = h->k;
+    const int64_t n = h->n;
+    memset(A, 0, sizeof(double) * n * n);
+    for (int64_t b = 0; b < h->nb; ++b) {
+        int64_t t = h->bt[b], s = h->bs[b], nt = h->size[t], ns = h->size[s];
+        if (h->badm[b]) {
+            double *Vt = malloc(sizeof(double) * nt * k), *Vs = malloc(sizeof(double) * ns * k);
+            double *VS = malloc(sizeof(double) * nt * k);
+            orc_basis_full(h, t, Vt);
+            orc_basis_full(h, s, Vs);
+            const double *Sb = &h->S[h->boff[b]];
+            for (int64_t i = 0; i < nt; ++i)
+                for (int mu = 0; mu < k; ++mu) {
+                    double acc = 0.0;
+                    for (int nu = 0; nu < k; ++nu) acc += Vt[i * k + nu] * Sb[nu * k + mu];
+                    VS[i * k + mu] = acc;
+                }
+            for (int64_t i = 0; i < nt; ++i)
+                for (int64_t j = 0; j < ns; ++j) {
+                    double acc = 0.0;
+                    for (int mu = 0; mu < k; ++mu) acc += VS[i * k + mu] * Vs[j * k + mu];
+                    A[h->perm[h->first[t] + i] * n + h->perm[h->first[s] + j]] = acc;
+                }
+            free(Vt); free(Vs); free(VS);
+        } else {
+            const double *Nb = &h->N[h->boff[b]];
+            for (int64_t i = 0; i < nt; ++i)
+                for (int64_t j = 0; j < ns; ++j)
+                    A[h->perm[h->first[t] + i] * n + h->perm[h->first[s] + j]] = Nb[i * ns + j];
+        }
+    }
+}
+
+/* Dense derivative d A_H2 / d ell (same structure: V, E fixed; S and N depend on ell). */
+void orc_dense_dell(const orc_h2 *h, double *A) {
+    const int k = h->k;
+    const int64_t n = h->n;
+    memset(A, 0, sizeof(double) * n * n);
+    double *dS = malloc(sizeof(double) * k * k);
+    for (int64_t b = 0; b < h->nb; ++b) {
+        int64_t t = h->bt[b], s = h->bs[b], nt = h->size[t], ns = h->size[s];
+        if (h->badm[b]) {
+            for (int nu = 0; nu < k; ++nu)
+                for (int mu = 0; mu < k; ++mu)
+                    dS[nu * k + mu] = orc_dg(h, &h->nodes[((size_t)t * k + nu) * 3], &h->nodes[((size_t)s * k + mu) * 3]);
+            double *Vt = malloc(sizeof(double) * nt * k), *Vs = malloc(sizeof(double) * ns * k);
+            orc_basis_full(h, t, Vt);
+            orc_basis_full(h, s, Vs);
+            for (int64_t i = 0; i < nt; ++i)
+                for (int64_t j = 0; j < ns; ++j) {
+                    double acc = 0.0;
+                    for (int nu = 0; nu < k; ++nu) {
+                        double inner = 0.0;
+                        for (int mu = 0; mu < k; ++mu) inner += dS[nu * k + mu] * Vs[j * k + mu];
+                        acc += Vt[i * k + nu] * inner;
+                    }
+                    A[h->perm[h->first[t] + i] * n + h->perm[h->first[s] + j]] = acc;
+                }
+            free(Vt); free(Vs);
+        } else {
+            for (int64_t i = 0; i < nt; ++i)
+                for (int64_t j = 0; j < ns; ++j) {
+                    int64_t gi = h->perm[h->first[t] + i], gj = h->perm[h->first[s] + j];
+                    A[gi * n + gj] = orc_dg(h, &h->pts[3 * gi], &h->pts[3 * gj]);
+                }
+        }
+    }
+    free(dS);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Conjugate gradients                                                      */
+
+static double orc_dot_col(int64_t n, int64_t m, const double *u, const double *v, int64_t j) {
+    double acc = 0.0;
+    for (int64_t i = 0; i < n; ++i) acc += u[i * m + j] * v[i * m + j];
+    return acc;
+}
+
+/*
+ * Block CG with m independent systems (the paper's block CG: one H^2 x P product
+ * per iteration, per-column step sizes, stop when every column has converged).
+ * X holds X0 on entry and the iterate on exit.  Stopping rule per column:
+ * ||r_i|| <= rtol ||b_i||.  A column whose beta_i <= 0 or non-finite is frozen.
+ * freeze_converged != 0 stops updating columns once they have converged.
+ * Returns the number of iterations; col_iters[i] = the iteration at which column
+ * i first met the tolerance (what a single-RHS CG would run); status[i]: 0 ok,
+ * 1 breakdown (frozen), 2 not converged within max_iter.
+ */
+int64_t orc_block_cg(const orc_h2 *h, int64_t m, const double *B, double *X, double rtol,
+                     int64_t max_iter, int freeze_converged, int64_t *col_iters, int32_t *status) {
+    const int64_t n = h->n;
+    double *R = malloc(sizeof(double) * n * m), *P = malloc(sizeof(double) * n * m);
+    double *Ap = malloc(sizeof(double) * n * m);
+    double *bn = malloc(sizeof(double) * m);
+    int *frozen = calloc(m, sizeof(int)), *seen = calloc(m, sizeof(int));
+    int x0_zero = 1;
+    for (int64_t i = 0; i < n * m; ++i) if (X[i] != 0.0) { x0_zero = 0; break; }
+    if (x0_zero) memcpy(R, B, sizeof(double) * n * m);
+    else {
+        orc_matmul(h, m, 1.0, X, 0.0, R);
+        for (int64_t i = 0; i < n * m; ++i) R[i] = B[i] - R[i];
+    }
+    memcpy(P, R, sizeof(double) * n * m);
+    for (int64_t j = 0; j < m; ++j) {
+        bn[j] = sqrt(orc_dot_col(n, m, B, B, j));
+        col_iters[j] = 0;
+        status[j] = 0;
+    }
+    int64_t it = 0;
+    for (;;) {
+        int all = 1;
+        int *conv = malloc(sizeof(int) * m);
+        for (int64_t j = 0; j < m; ++j) {
+            double rn = sqrt(orc_dot_col(n, m, R, R, j));
+            conv[j] = (rn <= rtol * bn[j]);
+            if (conv[j] && !seen[j]) { seen[j] = 1; col_iters[j] = it; }
+            if (!conv[j] && !frozen[j]) all = 0;
+        }
+        if (all || it >= max_iter) {
+            for (int64_t j = 0; j < m; ++j) {
+                if (!conv[j] && !frozen[j]) status[j] = 2;
+                if (!seen[j]) col_iters[j] = it;
+            }
+            free(conv);
+            break;
+        }
+        orc_matmul(h, m, 1.0, P, 0.0, Ap);
+        for (int64_t j = 0; j < m; ++j) {
+            if (frozen[j] || (freeze_converged && conv[j])) continue;
+            double beta = orc_dot_col(n, m, P, Ap, j);
+            double alpha = orc_dot_col(n, m, P, R, j) / beta;
+            if (!(beta > 0.0) || !isfinite(alpha)) { frozen[j] = 1; status[j] = 1; continue; }
+            for (int64_t i = 0; i < n; ++i) {
+                X[i * m + j] += alpha * P[i * m + j];
+                R[i * m + j] -= alpha * Ap[i * m + j];
+            }
+            double gamma = orc_dot_col(n, m, Ap, R, j) / beta;
+            for (int64_t i = 0; i < n; ++i) P[i * m + j] = R[i * m + j] - gamma * P[i * m + j];
+        }
+        free(conv);
+        it++;
+    }
+    free(R); free(P); free(Ap); free(bn); free(frozen); free(seen);
+    return it;
+}
+
+/* The paper's single-RHS CG (relative stopping rule), for the per-column pin. */
+int64_t orc_cg1(const orc_h2 *h, const double *b, double *x, double rtol, int64_t max_iter) {
+    const int64_t n = h->n;
+    double *r = malloc(sizeof(double) * n), *p = malloc(sizeof(double) * n), *a = malloc(sizeof(double) * n);
+    int x0_zero = 1;
+    for (int64_t i = 0; i < n; ++i) if (x[i] != 0.0) { x0_zero = 0; break; }
+    if (x0_zero) memcpy(r, b, sizeof(double) * n);
+    else {
+        orc_matmul(h, 1, 1.0, x, 0.0, r);
+        for (int64_t i = 0; i < n; ++i) r[i] = b[i] - r[i];
+    }
+    memcpy(p, r, sizeof(double) * n);
+    double bn = sqrt(orc_dot_col(n, 1, b, b, 0));
+    int64_t it = 0;
+    while (sqrt(orc_dot_col(n, 1, r, r, 0)) > rtol * bn && it < max_iter) {
+        orc_matmul(h, 1, 1.0, p, 0.0, a);
+        double beta = orc_dot_col(n, 1, p, a, 0);
+        double alpha = orc_dot_col(n, 1, p, r, 0) / beta;
+        if (!(beta > 0.0) || !isfinite(alpha)) break;
+        for (int64_t i = 0; i < n; ++i) { x[i] += alpha * p[i]; r[i] -= alpha * a[i]; }
+        double gamma = orc_dot_col(n, 1, a, r, 0) / beta;
+        for (int64_t i = 0; i < n; ++i) p[i] = r[i] - gamma * p[i];
+        it++;
+    }
+    free(r); free(p); free(a);
+    return it;
+}
+
+int orc_num_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+void orc_set_threads(int t) {
+#ifdef _OPENMP
+    if (t > 0) omp_set_num_threads(t);
+#else
+    (void)t;
+#endif
+}

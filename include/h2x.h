@@ -1,0 +1,191 @@
+/*
+ * h2x -- H^2-matrix x block-of-vectors products and block CG on AMD MI355X (gfx950).
+ *
+ * C ABI of the library paper_2509_17257_amd/libh2x.so.  The operations follow
+ * "On efficient block Krylov solvers for H^2-matrices" (arXiv 2509.17257):
+ *
+ *   - the cluster tree, block tree and admissibility condition of section 2
+ *     (Definitions "Cluster tree", "Block tree", the standard admissibility
+ *     condition max(diam) <= eta * dist) and the per-row-cluster block lists of
+ *     Algorithm "prepare_addeval" (section 3);
+ *   - the H^2 representation of section 2 (nested cluster basis with transfer
+ *     matrices, coupling matrices S_b for admissible leaves, dense near-field
+ *     blocks), built by tensor Chebyshev interpolation of the kernel
+ *     g(x, y) = exp(-|x - y| / ell), plus shift * delta_ij on the diagonal;
+ *   - the product Y <- beta Y + alpha A X of Algorithm "H2_mvm" in its matrix
+ *     form (section 4): forward transformation, multiplication phase over the
+ *     lists C_t of every cluster, backward transformation;
+ *   - block CG (section 5.1): m independent CG iterations sharing one H^2 x P
+ *     product per iteration, stopping when every column has converged.
+ *
+ * Conventions
+ *   - Every call returns h2x_status and never throws.  On a non-OK status,
+ *     h2x_last_error() returns a thread-local message.
+ *   - Arguments are validated before anything is launched (H2X_EINVAL,
+ *     H2X_ENOMEM for a workspace that is too small).  A failing HIP call gives
+ *     H2X_EHIP.
+ *   - Device memory is owned by the caller: the library never allocates device
+ *     memory.  Every entry point that needs device storage takes a workspace
+ *     pointer and its size, obtained from the matching *_workspace_bytes call.
+ *     Workspaces must be 256-byte aligned.
+ *   - Streams are the caller's (a hipStream_t passed as void*; NULL is the null
+ *     stream).  Calls marked "async" only enqueue work on that stream.
+ *   - Dense blocks of vectors (X, Y, B) are row-major n x m with leading
+ *     dimension ld >= m, in the caller's original point order, FP64.
+ *   - Handles are not thread-safe; use one handle per thread or lock.
+ */
+#ifndef H2X_H
+#define H2X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    H2X_OK = 0,
+    H2X_EINVAL = 1,       /* invalid argument */
+    H2X_ENOMEM = 2,       /* workspace too small */
+    H2X_EHIP = 3,         /* a HIP runtime call failed */
+    H2X_EBREAKDOWN = 4,   /* CG breakdown (p^T A p <= 0 or non-finite) in >= 1 column */
+    H2X_ENOCONV = 5,      /* CG reached max_iter with >= 1 unconverged column */
+    H2X_EUNSUPPORTED = 6  /* option not supported by this build */
+} h2x_status;
+
+/* Storage / compute precision of the H^2 operator (V, E, S; near field see h2x_mat_create). */
+typedef enum { H2X_F64 = 0, H2X_F32 = 1, H2X_BF16 = 2 } h2x_prec;
+
+typedef enum {
+    H2X_KERNEL_EXP = 0,   /* g = exp(-|x - y| / ell) + shift * delta_ij                */
+    H2X_KERNEL_POLY = 1,  /* g = (1 + x.y)^2 + shift * delta_ij; reproduced exactly by
+                             interpolation order >= 3 (a test kernel)                    */
+    H2X_KERNEL_CONST = 2  /* g = 1 + shift * delta_ij, i.e. A = shift I + 1 1^T (test)  */
+} h2x_kernel;
+
+typedef struct {
+    h2x_kernel kernel;
+    double ell;         /* length scale of the exponential kernel, > 0            */
+    double shift;       /* added to every diagonal entry                           */
+    double eta;         /* admissibility parameter, > 0                            */
+    int32_t leaf_size;  /* a cluster with <= leaf_size points is a leaf, >= 1      */
+    int32_t cheb_order; /* Chebyshev nodes per dimension p, 1..8; rank k = p^3    */
+} h2x_params;
+
+typedef struct {
+    int64_t n, clusters, leaves, n_adm, n_near, near_entries;
+    int32_t depth, k;
+    int64_t bytes_operator[3]; /* V + E + S bytes per h2x_prec, near field excluded */
+    int64_t bytes_near;        /* near-field bytes at FP64                          */
+} h2x_stats;
+
+typedef struct h2x_plan h2x_plan; /* host topology: trees, lists, permutation */
+typedef struct h2x_mat h2x_mat;   /* a plan plus views into a filled device workspace */
+
+/* ---- planning (host only, no GPU needed) -------------------------------- */
+
+/* Build the cluster tree (binary bisection of the tight bounding box at the
+ * midpoint of its widest dimension, points strictly below the midpoint first;
+ * a cluster is a leaf when it has <= leaf_size points or all its points
+ * coincide), the block tree (admissible when dist > 0 and
+ * max(diam_t, diam_s) <= eta * dist of the tight boxes) and the lists C_t.
+ * pts: host, n x 3 row-major, read during the call only. */
+h2x_status h2x_plan_create(const double *pts, int64_t n, const h2x_params *prm, h2x_plan **out);
+void h2x_plan_destroy(h2x_plan *plan);
+h2x_status h2x_plan_stats(const h2x_plan *plan, h2x_stats *out);
+
+/* perm[i] = original index of the point at tree position i (host, n entries). */
+h2x_status h2x_plan_perm(const h2x_plan *plan, int64_t *perm);
+
+/* Clusters in pre-order (host arrays of `clusters` entries, caller-owned; any
+ * pointer may be NULL): first tree position, size, parent (-1 for the root),
+ * sons (-1 for leaves), depth. */
+h2x_status h2x_plan_clusters(const h2x_plan *plan, int64_t *first, int64_t *size, int64_t *parent,
+                             int64_t *son0, int64_t *son1, int64_t *depth);
+
+/* Admissible leaves in the library's storage order (row cluster ascending; in
+ * block-tree pre-order within a row): row and column cluster of each of the
+ * n_adm coupling matrices.  Near-field leaves likewise (n_near entries). */
+h2x_status h2x_plan_blocks(const h2x_plan *plan, int64_t *adm_t, int64_t *adm_s, int64_t *near_t,
+                           int64_t *near_s);
+
+/* ---- operator ------------------------------------------------------------ */
+
+/* Bytes of device workspace an operator needs (topology + V, E, S in `storage`
+ * precision + near field; the near field is FP64 for H2X_F64 and FP32 for the
+ * low-precision storages). */
+size_t h2x_mat_workspace_bytes(const h2x_plan *plan, h2x_prec storage);
+
+/* Upload the topology and fill V, E, S and the near field on the device.
+ * dev_ws must stay valid (and untouched) until h2x_mat_destroy.  The plan must
+ * outlive the operator.  Blocking: returns after the fill has completed. */
+h2x_status h2x_mat_create(const h2x_plan *plan, h2x_prec storage, void *dev_ws, size_t ws_bytes,
+                          void *hip_stream, h2x_mat **out);
+void h2x_mat_destroy(h2x_mat *mat);
+
+/* ---- product ------------------------------------------------------------- */
+
+#define H2X_TREE_ORDER 1 /* X and Y are in tree order (rows permuted by perm) */
+
+/* Bytes of device workspace h2x_matmul needs for m columns (x-hat, y-hat). */
+size_t h2x_matmul_workspace_bytes(const h2x_mat *A, int64_t m);
+
+/* Y <- beta Y + alpha A X, A the H^2 matrix (async).  X: device, n x m, ldx;
+ * Y: device, n x m, ldy; X and Y must not overlap.  beta == 0 ignores Y's
+ * contents (NaN-safe).  m >= 1. */
+h2x_status h2x_matmul(const h2x_mat *A, int64_t m, double alpha, const double *X, int64_t ldx,
+                      double beta, double *Y, int64_t ldy, int32_t flags, void *dev_ws,
+                      size_t ws_bytes, void *hip_stream);
+
+/* Same product as h2x_matmul, with HIP events recorded on the stream around
+ * each stage.  Blocking: returns after the product has completed, with the
+ * stage durations in milliseconds in stage_ms[H2X_NUM_STAGES] (host array):
+ * forward leaf, forward transfer passes, coupling, backward transfer passes,
+ * leaf basis + near field. */
+#define H2X_NUM_STAGES 5
+h2x_status h2x_matmul_timed(const h2x_mat *A, int64_t m, double alpha, const double *X, int64_t ldx,
+                            double beta, double *Y, int64_t ldy, int32_t flags, void *dev_ws,
+                            size_t ws_bytes, void *hip_stream, double *stage_ms);
+
+/* ---- block CG ------------------------------------------------------------ */
+
+typedef struct {
+    double rtol;              /* stop column i when ||r_i|| <= rtol ||b_i||              */
+    int32_t max_iter;         /* iterations of the shared loop                           */
+    int32_t freeze_converged; /* 0: converged columns keep iterating (the paper's rule);
+                                 1: converged columns stop updating                       */
+    int32_t check_every;      /* read the device convergence flag every this many steps */
+} h2x_cg_params;
+
+typedef struct {
+    int32_t iters;       /* iterations of the shared loop                             */
+    int32_t status;      /* H2X_OK, H2X_EBREAKDOWN or H2X_ENOCONV                     */
+    double *col_relres;  /* host, m entries or NULL: final ||r_i|| / ||b_i|| (recursive) */
+    int32_t *col_iters;  /* host, m entries or NULL: iteration at which column i first met
+                            the tolerance (iters if it never did)                      */
+    int32_t *col_status; /* host, m entries or NULL: 0 ok, 1 breakdown, 2 not converged */
+} h2x_cg_info;
+
+size_t h2x_block_cg_workspace_bytes(const h2x_mat *A, int64_t m);
+
+/* Solve A X = B for m right-hand sides with block CG: one H^2 x P product per
+ * iteration, per-column step sizes (the paper's block CG).  B: device n x m,
+ * ldb; X: device n x m, ldx, holds X0 on entry and the iterate on exit.  A
+ * column whose p^T A p is <= 0 or non-finite is frozen and reported.
+ * Blocking: returns after the solve.  The return value reports argument and
+ * HIP errors only; the solver outcome (H2X_OK, H2X_EBREAKDOWN, H2X_ENOCONV)
+ * is info->status, with per-column detail.  info may be NULL. */
+h2x_status h2x_block_cg(const h2x_mat *A, const h2x_cg_params *prm, int64_t m, const double *B,
+                        int64_t ldb, double *X, int64_t ldx, void *dev_ws, size_t ws_bytes,
+                        h2x_cg_info *info, void *hip_stream);
+
+/* ---- misc ------------------------------------------------------------------ */
+
+const char *h2x_last_error(void);
+const char *h2x_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* H2X_H */

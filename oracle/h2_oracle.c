@@ -800,6 +800,9 @@ int64_t orc_block_cg(const orc_h2 *h, int64_t m, const double *B, double *X, dou
         orc_matmul(h, m, 1.0, P, 0.0, Ap);
         for (int64_t j = 0; j < m; ++j) {
             if (frozen[j] || (freeze_converged && conv[j])) continue;
+            /* an exactly zero residual is an exact solution: nothing to update (the
+             * step size would be 0/0) */
+            if (orc_dot_col(n, m, R, R, j) == 0.0) continue;
             double beta = orc_dot_col(n, m, P, Ap, j);
             double alpha = orc_dot_col(n, m, P, R, j) / beta;
             if (!(beta > 0.0) || !isfinite(alpha)) { frozen[j] = 1; status[j] = 1; continue; }

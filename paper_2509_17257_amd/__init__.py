@@ -1,0 +1,254 @@
+"""h2x: H^2-matrix x block-of-vectors products and block CG on AMD MI355X.
+
+Thin Python binding of the C ABI in ``include/h2x.h`` (library ``libh2x.so``
+next to this file).  Every step of the computation runs in the library's HIP
+kernels; this module only marshals arguments.  PyTorch provides device memory
+(workspaces, inputs, outputs) and the current stream.  There is no CPU
+fallback: if the library is missing, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+__all__ = ["Plan", "H2Matrix", "h2_matmul", "block_cg_solve", "library_path", "load_library",
+           "F64", "F32", "BF16", "TREE_ORDER"]
+
+F64, F32, BF16 = 0, 1, 2
+_PREC = {"f64": F64, "f32": F32, "bf16": BF16, F64: F64, F32: F32, BF16: BF16}
+_KERNEL = {"exp": 0, "poly": 1, "const": 2}
+TREE_ORDER = 1
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_lib = None
+
+
+def library_path() -> str:
+    return os.path.join(_HERE, "libh2x.so")
+
+
+class H2xError(RuntimeError):
+    pass
+
+
+class _Params(C.Structure):
+    _fields_ = [("kernel", C.c_int), ("ell", C.c_double), ("shift", C.c_double), ("eta", C.c_double),
+                ("leaf_size", C.c_int32), ("cheb_order", C.c_int32)]
+
+
+class _Stats(C.Structure):
+    _fields_ = [("n", C.c_int64), ("clusters", C.c_int64), ("leaves", C.c_int64), ("n_adm", C.c_int64),
+                ("n_near", C.c_int64), ("near_entries", C.c_int64), ("depth", C.c_int32), ("k", C.c_int32),
+                ("bytes_operator", C.c_int64 * 3), ("bytes_near", C.c_int64)]
+
+
+class _CgParams(C.Structure):
+    _fields_ = [("rtol", C.c_double), ("max_iter", C.c_int32), ("freeze_converged", C.c_int32),
+                ("check_every", C.c_int32)]
+
+
+class _CgInfo(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("status", C.c_int32), ("col_relres", C.POINTER(C.c_double)),
+                ("col_iters", C.POINTER(C.c_int32)), ("col_status", C.POINTER(C.c_int32))]
+
+
+def load_library():
+    """Load libh2x.so (built by ``paper_2509_17257_amd.build``); raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = library_path()
+    if not os.path.exists(path):
+        raise H2xError(f"{path} is not built; run paper_2509_17257_amd/build.py (no CPU fallback exists)")
+    lib = C.CDLL(path)
+    P, I64, D, I32, SZ = C.c_void_p, C.c_int64, C.c_double, C.c_int32, C.c_size_t
+    sig = {
+        "h2x_plan_create": (C.c_int, [P, I64, C.POINTER(_Params), C.POINTER(P)]),
+        "h2x_plan_destroy": (None, [P]),
+        "h2x_plan_stats": (C.c_int, [P, C.POINTER(_Stats)]),
+        "h2x_plan_perm": (C.c_int, [P, P]),
+        "h2x_plan_clusters": (C.c_int, [P, P, P, P, P, P, P]),
+        "h2x_plan_blocks": (C.c_int, [P, P, P, P, P]),
+        "h2x_mat_workspace_bytes": (SZ, [P, C.c_int]),
+        "h2x_mat_create": (C.c_int, [P, C.c_int, P, SZ, P, C.POINTER(P)]),
+        "h2x_mat_destroy": (None, [P]),
+        "h2x_matmul_workspace_bytes": (SZ, [P, I64]),
+        "h2x_matmul": (C.c_int, [P, I64, D, P, I64, D, P, I64, I32, P, SZ, P]),
+        "h2x_matmul_timed": (C.c_int, [P, I64, D, P, I64, D, P, I64, I32, P, SZ, P, P]),
+        "h2x_block_cg_workspace_bytes": (SZ, [P, I64]),
+        "h2x_block_cg": (C.c_int, [P, C.POINTER(_CgParams), I64, P, I64, P, I64, P, SZ, C.POINTER(_CgInfo), P]),
+        "h2x_last_error": (C.c_char_p, []),
+        "h2x_version": (C.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status: int, what: str):
+    if status != 0:
+        msg = load_library().h2x_last_error().decode()
+        raise H2xError(f"{what} failed with status {status}: {msg}")
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+class Plan:
+    """Host topology: cluster tree, block tree, lists (h2x_plan_create)."""
+
+    def __init__(self, points, *, kernel="exp", ell=0.5, shift=1.0, eta=1.0, leaf=32, p=3):
+        lib = load_library()
+        pts = np.ascontiguousarray(points, dtype=np.float64)
+        if pts.ndim != 2 or pts.shape[1] != 3:
+            raise ValueError("points must be n x 3")
+        prm = _Params(_KERNEL[kernel] if isinstance(kernel, str) else int(kernel), float(ell), float(shift),
+                      float(eta), int(leaf), int(p))
+        h = C.c_void_p()
+        _check(lib.h2x_plan_create(_ptr(pts), pts.shape[0], C.byref(prm), C.byref(h)), "h2x_plan_create")
+        self._h = h
+        self.params = dict(kernel=kernel, ell=ell, shift=shift, eta=eta, leaf=leaf, p=p)
+        st = _Stats()
+        _check(lib.h2x_plan_stats(h, C.byref(st)), "h2x_plan_stats")
+        self.n, self.C, self.leaves = st.n, st.clusters, st.leaves
+        self.n_adm, self.n_near, self.near_entries = st.n_adm, st.n_near, st.near_entries
+        self.depth, self.k = st.depth, st.k
+        self.bytes_operator = list(st.bytes_operator)
+        self.bytes_near = st.bytes_near
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.h2x_plan_destroy(self._h)
+            self._h = None
+
+    def perm(self) -> np.ndarray:
+        a = np.zeros(self.n, np.int64)
+        _check(load_library().h2x_plan_perm(self._h, _ptr(a)), "h2x_plan_perm")
+        return a
+
+    def clusters(self) -> dict:
+        out = {nm: np.zeros(self.C, np.int64) for nm in ("first", "size", "parent", "son0", "son1", "depth")}
+        _check(load_library().h2x_plan_clusters(self._h, *[_ptr(out[nm]) for nm in
+                                                          ("first", "size", "parent", "son0", "son1", "depth")]),
+               "h2x_plan_clusters")
+        return out
+
+    def blocks(self) -> dict:
+        at, as_ = np.zeros(self.n_adm, np.int64), np.zeros(self.n_adm, np.int64)
+        nt, ns = np.zeros(self.n_near, np.int64), np.zeros(self.n_near, np.int64)
+        _check(load_library().h2x_plan_blocks(self._h, _ptr(at), _ptr(as_), _ptr(nt), _ptr(ns)), "h2x_plan_blocks")
+        return dict(adm_t=at, adm_s=as_, near_t=nt, near_s=ns)
+
+
+def _stream(torch, device):
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class H2Matrix:
+    """An H^2 operator filled on the GPU (h2x_mat_create) inside a torch-owned workspace."""
+
+    def __init__(self, points_or_plan, *, storage="f64", device="cuda", **params):
+        import torch
+        lib = load_library()
+        self.plan = points_or_plan if isinstance(points_or_plan, Plan) else Plan(points_or_plan, **params)
+        self.storage = _PREC[storage]
+        self.device = torch.device(device)
+        nbytes = lib.h2x_mat_workspace_bytes(self.plan._h, self.storage)
+        if nbytes == 0:
+            raise H2xError("h2x_mat_workspace_bytes returned 0")
+        self._ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        h = C.c_void_p()
+        _check(lib.h2x_mat_create(self.plan._h, self.storage, C.c_void_p(self._ws.data_ptr()), nbytes,
+                                  _stream(torch, self.device), C.byref(h)), "h2x_mat_create")
+        self._h = h
+        self.n, self.k = self.plan.n, self.plan.k
+        self._mm_ws = {}
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.h2x_mat_destroy(self._h)
+            self._h = None
+
+    def workspace(self, m: int, kind: str = "matmul"):
+        import torch
+        key = (kind, m)
+        ws = self._mm_ws.get(key)
+        if ws is None:
+            f = load_library().h2x_matmul_workspace_bytes if kind == "matmul" else \
+                load_library().h2x_block_cg_workspace_bytes
+            nb = f(self._h, m)
+            ws = torch.empty(max(nb, 256), dtype=torch.uint8, device=self.device)
+            self._mm_ws[key] = ws
+        return ws
+
+
+STAGES = ("forward_leaf", "forward_transfer", "coupling", "backward_transfer", "leaf_near")
+
+
+def h2_matmul(A: H2Matrix, X, *, alpha=1.0, beta=0.0, out=None, tree_order=False, stage_ms=None):
+    """Y <- beta Y + alpha A X on the GPU (h2x_matmul).  X: (n, m) float64 CUDA tensor.
+
+    With ``stage_ms`` (a float64 numpy array of len(STAGES)) the product runs through
+    h2x_matmul_timed and the per-stage durations in ms are written into it (blocking)."""
+    import torch
+    squeeze = X.dim() == 1
+    X2 = X.reshape(-1, 1) if squeeze else X
+    if X2.dtype != torch.float64 or X2.device.type != "cuda" or X2.stride(1) != 1:
+        raise ValueError("X must be a row-major float64 CUDA tensor")
+    n, m = X2.shape
+    if n != A.n:
+        raise ValueError("X has the wrong number of rows")
+    if out is None:
+        if beta != 0.0:
+            raise ValueError("beta != 0 needs out")
+        out = torch.empty((n, m), dtype=torch.float64, device=X2.device)
+    Y = out.reshape(-1, 1) if out.dim() == 1 else out
+    if Y.stride(1) != 1:
+        raise ValueError("out must be row-major")
+    ws = A.workspace(m)
+    args = (A._h, m, float(alpha), C.c_void_p(X2.data_ptr()), X2.stride(0), float(beta), C.c_void_p(Y.data_ptr()),
+            Y.stride(0), TREE_ORDER if tree_order else 0, C.c_void_p(ws.data_ptr()), ws.numel(),
+            _stream(torch, X2.device))
+    if stage_ms is None:
+        _check(load_library().h2x_matmul(*args), "h2x_matmul")
+    else:
+        assert stage_ms.dtype == np.float64 and stage_ms.size >= len(STAGES)
+        _check(load_library().h2x_matmul_timed(*args, _ptr(stage_ms)), "h2x_matmul_timed")
+    return out
+
+
+@dataclass
+class CgInfo:
+    iters: int
+    status: int
+    col_relres: np.ndarray
+    col_iters: np.ndarray
+    col_status: np.ndarray
+
+
+def block_cg_solve(A: H2Matrix, B, X0=None, *, rtol=1e-8, max_iter=10000, freeze_converged=False,
+                   check_every=4):
+    """Solve A X = B (block CG, h2x_block_cg).  Returns (X, CgInfo)."""
+    import torch
+    if B.dtype != torch.float64 or B.device.type != "cuda" or B.dim() != 2 or B.stride(1) != 1:
+        raise ValueError("B must be a row-major (n, m) float64 CUDA tensor")
+    n, m = B.shape
+    X = torch.zeros_like(B) if X0 is None else X0.clone()
+    ws = A.workspace(m, "cg")
+    rel = np.zeros(m)
+    its = np.zeros(m, np.int32)
+    sts = np.zeros(m, np.int32)
+    info = _CgInfo(0, 0, rel.ctypes.data_as(C.POINTER(C.c_double)), its.ctypes.data_as(C.POINTER(C.c_int32)),
+                   sts.ctypes.data_as(C.POINTER(C.c_int32)))
+    prm = _CgParams(float(rtol), int(max_iter), int(bool(freeze_converged)), int(check_every))
+    _check(load_library().h2x_block_cg(A._h, C.byref(prm), m, C.c_void_p(B.data_ptr()), B.stride(0),
+                                       C.c_void_p(X.data_ptr()), X.stride(0), C.c_void_p(ws.data_ptr()), ws.numel(),
+                                       C.byref(info), _stream(torch, B.device)), "h2x_block_cg")
+    return X, CgInfo(info.iters, info.status, rel, its, sts)

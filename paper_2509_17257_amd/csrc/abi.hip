@@ -1,0 +1,268 @@
+// C ABI entry points: argument validation, workspace layout, dispatch.
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "device.hpp"
+
+namespace h2x {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string &msg) { g_err = msg; }
+
+}  // namespace h2x
+
+using namespace h2x;
+
+namespace {
+
+h2x_status fail(h2x_status s, const std::string &msg) {
+    set_error(msg);
+    return s;
+}
+
+h2x_status hip_fail(const char *where, hipError_t e) {
+    return fail(H2X_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+bool aligned(const void *p) { return ((uintptr_t)p % kAlign) == 0; }
+
+template <typename T>
+hipError_t upload(T *dst, const std::vector<T> &src, hipStream_t st) {
+    if (src.empty()) return hipSuccess;
+    return hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, st);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *h2x_last_error(void) { return g_err.c_str(); }
+const char *h2x_version(void) { return "h2x 0.1 gfx950"; }
+
+h2x_status h2x_plan_create(const double *pts, int64_t n, const h2x_params *prm, h2x_plan **out) {
+    if (!out) return fail(H2X_EINVAL, "h2x_plan_create: out is NULL");
+    *out = nullptr;
+    if (!pts || !prm) return fail(H2X_EINVAL, "h2x_plan_create: NULL argument");
+    if (n < 1 || n > (int64_t)1 << 30) return fail(H2X_EINVAL, "h2x_plan_create: n must be in [1, 2^30]");
+    if (prm->cheb_order < 1 || prm->cheb_order > 8)
+        return fail(H2X_EINVAL, "h2x_plan_create: cheb_order must be in [1, 8]");
+    if (prm->leaf_size < 1) return fail(H2X_EINVAL, "h2x_plan_create: leaf_size must be >= 1");
+    if (!(prm->eta > 0.0)) return fail(H2X_EINVAL, "h2x_plan_create: eta must be > 0");
+    if (prm->kernel < H2X_KERNEL_EXP || prm->kernel > H2X_KERNEL_CONST)
+        return fail(H2X_EINVAL, "h2x_plan_create: unknown kernel");
+    if (prm->kernel == H2X_KERNEL_EXP && !(prm->ell > 0.0))
+        return fail(H2X_EINVAL, "h2x_plan_create: ell must be > 0");
+    for (int64_t i = 0; i < 3 * n; ++i)
+        if (!std::isfinite(pts[i])) return fail(H2X_EINVAL, "h2x_plan_create: non-finite point coordinate");
+    std::string err;
+    Plan *P = build_plan(pts, n, *prm, err);
+    if (!P) return fail(H2X_EINVAL, "h2x_plan_create: " + err);
+    *out = new h2x_plan{P};
+    return H2X_OK;
+}
+
+void h2x_plan_destroy(h2x_plan *plan) {
+    if (!plan) return;
+    delete plan->p;
+    delete plan;
+}
+
+h2x_status h2x_plan_stats(const h2x_plan *plan, h2x_stats *out) {
+    if (!plan || !out) return fail(H2X_EINVAL, "h2x_plan_stats: NULL argument");
+    const Plan &P = *plan->p;
+    std::memset(out, 0, sizeof(*out));
+    out->n = P.n;
+    out->clusters = P.C;
+    out->leaves = (int64_t)P.leaves.size();
+    out->n_adm = (int64_t)P.adm_col.size();
+    out->n_near = (int64_t)P.near_col.size();
+    out->near_entries = P.near_entries;
+    out->depth = P.depth_max;
+    out->k = P.k;
+    const int64_t ent = P.n * P.k + (int64_t)(P.C - 1) * P.k * P.k + out->n_adm * P.k * P.k;
+    out->bytes_operator[H2X_F64] = 8 * ent;
+    out->bytes_operator[H2X_F32] = 4 * ent;
+    out->bytes_operator[H2X_BF16] = 2 * ent;
+    out->bytes_near = 8 * P.near_entries;
+    return H2X_OK;
+}
+
+h2x_status h2x_plan_perm(const h2x_plan *plan, int64_t *perm) {
+    if (!plan || !perm) return fail(H2X_EINVAL, "h2x_plan_perm: NULL argument");
+    std::memcpy(perm, plan->p->perm.data(), sizeof(int64_t) * plan->p->n);
+    return H2X_OK;
+}
+
+h2x_status h2x_plan_clusters(const h2x_plan *plan, int64_t *first, int64_t *size, int64_t *parent, int64_t *son0,
+                             int64_t *son1, int64_t *depth) {
+    if (!plan) return fail(H2X_EINVAL, "h2x_plan_clusters: NULL plan");
+    const Plan &P = *plan->p;
+    for (int32_t c = 0; c < P.C; ++c) {
+        if (first) first[c] = P.first[c];
+        if (size) size[c] = P.size[c];
+        if (parent) parent[c] = P.parent[c];
+        if (son0) son0[c] = P.son0[c];
+        if (son1) son1[c] = P.son1[c];
+        if (depth) depth[c] = P.depth[c];
+    }
+    return H2X_OK;
+}
+
+h2x_status h2x_plan_blocks(const h2x_plan *plan, int64_t *adm_t, int64_t *adm_s, int64_t *near_t, int64_t *near_s) {
+    if (!plan) return fail(H2X_EINVAL, "h2x_plan_blocks: NULL plan");
+    const Plan &P = *plan->p;
+    for (int32_t t = 0; t < P.C; ++t)
+        for (int64_t b = P.adm_ptr[t]; b < P.adm_ptr[t + 1]; ++b) {
+            if (adm_t) adm_t[b] = t;
+            if (adm_s) adm_s[b] = P.adm_col[b];
+        }
+    for (size_t l = 0; l < P.leaves.size(); ++l)
+        for (int64_t q = P.near_ptr[l]; q < P.near_ptr[l + 1]; ++q) {
+            if (near_t) near_t[q] = P.leaves[l];
+            if (near_s) near_s[q] = P.near_col[q];
+        }
+    return H2X_OK;
+}
+
+size_t h2x_mat_workspace_bytes(const h2x_plan *plan, h2x_prec storage) {
+    if (!plan || storage < H2X_F64 || storage > H2X_BF16) return 0;
+    return mat_layout(*plan->p, storage, nullptr, nullptr);
+}
+
+h2x_status h2x_mat_create(const h2x_plan *plan, h2x_prec storage, void *dev_ws, size_t ws_bytes, void *hip_stream,
+                          h2x_mat **out) {
+    if (!out) return fail(H2X_EINVAL, "h2x_mat_create: out is NULL");
+    *out = nullptr;
+    if (!plan || !dev_ws) return fail(H2X_EINVAL, "h2x_mat_create: NULL argument");
+    if (storage < H2X_F64 || storage > H2X_BF16) return fail(H2X_EINVAL, "h2x_mat_create: bad storage precision");
+    if (!aligned(dev_ws)) return fail(H2X_EINVAL, "h2x_mat_create: workspace not 256-byte aligned");
+    const Plan &P = *plan->p;
+    const size_t need = mat_layout(P, storage, nullptr, nullptr);
+    if (ws_bytes < need) return fail(H2X_ENOMEM, "h2x_mat_create: workspace too small");
+    auto *M = new h2x_mat{};
+    M->plan = plan;
+    M->ws_bytes = need;
+    mat_layout(P, storage, &M->dm, (char *)dev_ws);
+    DevMat &d = M->dm;
+    hipStream_t st = (hipStream_t)hip_stream;
+
+    std::vector<int32_t> adm_row(P.adm_col.size()), near_row(P.near_col.size());
+    for (int32_t t = 0; t < P.C; ++t)
+        for (int64_t b = P.adm_ptr[t]; b < P.adm_ptr[t + 1]; ++b) adm_row[b] = t;
+    for (size_t l = 0; l < P.leaves.size(); ++l)
+        for (int64_t q = P.near_ptr[l]; q < P.near_ptr[l + 1]; ++q) near_row[q] = P.leaves[l];
+
+    hipError_t e = hipSuccess;
+    auto up = [&](auto *dst, const auto &src) {
+        if (e == hipSuccess) e = upload(dst, src, st);
+    };
+    up(d.first, P.first);
+    up(d.size, P.size);
+    up(d.parent, P.parent);
+    up(d.son0, P.son0);
+    up(d.son1, P.son1);
+    up(d.leaves, P.leaves);
+    up(d.lvl_all, P.lvl_all);
+    up(d.lvl_inner, P.lvl_inner);
+    up(d.adm_ptr, P.adm_ptr);
+    up(d.adm_col, P.adm_col);
+    up(d.adm_row, adm_row);
+    up(d.near_ptr, P.near_ptr);
+    up(d.near_col, P.near_col);
+    up(d.near_row, near_row);
+    up(d.near_off, P.near_off);
+    up(d.perm, P.perm);
+    up(d.pts, P.pts_tree);
+    up(d.box, P.box);
+    if (e == hipSuccess) e = launch_fill(d, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        delete M;
+        return hip_fail("h2x_mat_create", e);
+    }
+    *out = M;
+    return H2X_OK;
+}
+
+void h2x_mat_destroy(h2x_mat *mat) { delete mat; }
+
+size_t h2x_matmul_workspace_bytes(const h2x_mat *A, int64_t m) {
+    if (!A || m < 1) return 0;
+    return matmul_ws_bytes(A->dm, m);
+}
+
+}  // extern "C"
+
+namespace {
+
+h2x_status validate_matmul(const char *who, const h2x_mat *A, int64_t m, const double *X, int64_t ldx, const double *Y,
+                           int64_t ldy, int32_t flags, void *dev_ws, size_t ws_bytes) {
+    const std::string w(who);
+    if (!A || !X || !Y || !dev_ws) return fail(H2X_EINVAL, w + ": NULL argument");
+    if (m < 1 || ldx < m || ldy < m) return fail(H2X_EINVAL, w + ": need m >= 1, ldx >= m, ldy >= m");
+    if (flags & ~H2X_TREE_ORDER) return fail(H2X_EINVAL, w + ": unknown flags");
+    if (!aligned(dev_ws)) return fail(H2X_EINVAL, w + ": workspace not 256-byte aligned");
+    if (ws_bytes < matmul_ws_bytes(A->dm, m)) return fail(H2X_ENOMEM, w + ": workspace too small");
+    const int64_t n = A->dm.n;
+    const char *x0 = (const char *)X, *x1 = (const char *)(X + (n - 1) * ldx + m);
+    const char *y0 = (const char *)Y, *y1 = (const char *)(Y + (n - 1) * ldy + m);
+    if (x0 < y1 && y0 < x1) return fail(H2X_EINVAL, w + ": X and Y overlap");
+    return H2X_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+h2x_status h2x_matmul(const h2x_mat *A, int64_t m, double alpha, const double *X, int64_t ldx, double beta, double *Y,
+                      int64_t ldy, int32_t flags, void *dev_ws, size_t ws_bytes, void *hip_stream) {
+    h2x_status s = validate_matmul("h2x_matmul", A, m, X, ldx, Y, ldy, flags, dev_ws, ws_bytes);
+    if (s != H2X_OK) return s;
+    hipError_t e = run_matmul(A->dm, m, alpha, X, ldx, beta, Y, ldy, (flags & H2X_TREE_ORDER) != 0, (char *)dev_ws,
+                              (hipStream_t)hip_stream);
+    if (e != hipSuccess) return hip_fail("h2x_matmul", e);
+    return H2X_OK;
+}
+
+h2x_status h2x_matmul_timed(const h2x_mat *A, int64_t m, double alpha, const double *X, int64_t ldx, double beta,
+                            double *Y, int64_t ldy, int32_t flags, void *dev_ws, size_t ws_bytes, void *hip_stream,
+                            double *stage_ms) {
+    if (!stage_ms) return fail(H2X_EINVAL, "h2x_matmul_timed: stage_ms is NULL");
+    h2x_status s = validate_matmul("h2x_matmul_timed", A, m, X, ldx, Y, ldy, flags, dev_ws, ws_bytes);
+    if (s != H2X_OK) return s;
+    hipEvent_t ev[H2X_NUM_STAGES + 1] = {};
+    hipError_t e = hipSuccess;
+    for (int i = 0; i <= H2X_NUM_STAGES && e == hipSuccess; ++i) e = hipEventCreate(&ev[i]);
+    hipStream_t st = (hipStream_t)hip_stream;
+    if (e == hipSuccess)
+        e = run_matmul(A->dm, m, alpha, X, ldx, beta, Y, ldy, (flags & H2X_TREE_ORDER) != 0, (char *)dev_ws, st, ev);
+    if (e == hipSuccess) e = hipEventSynchronize(ev[H2X_NUM_STAGES]);
+    for (int i = 0; i < H2X_NUM_STAGES && e == hipSuccess; ++i) {
+        float ms = 0.f;
+        e = hipEventElapsedTime(&ms, ev[i], ev[i + 1]);
+        stage_ms[i] = ms;
+    }
+    for (auto &x : ev)
+        if (x) (void)hipEventDestroy(x);
+    if (e != hipSuccess) return hip_fail("h2x_matmul_timed", e);
+    return H2X_OK;
+}
+
+size_t h2x_block_cg_workspace_bytes(const h2x_mat *A, int64_t m) {
+    if (!A || m < 1) return 0;
+    return cg_ws_bytes(A->dm, m);
+}
+
+h2x_status h2x_block_cg(const h2x_mat *A, const h2x_cg_params *prm, int64_t m, const double *B, int64_t ldb,
+                        double *X, int64_t ldx, void *dev_ws, size_t ws_bytes, h2x_cg_info *info, void *hip_stream) {
+    if (!A || !prm || !B || !X || !dev_ws) return fail(H2X_EINVAL, "h2x_block_cg: NULL argument");
+    if (m < 1 || ldb < m || ldx < m) return fail(H2X_EINVAL, "h2x_block_cg: need m >= 1, ldb >= m, ldx >= m");
+    if (!(prm->rtol >= 0.0) || prm->max_iter < 0) return fail(H2X_EINVAL, "h2x_block_cg: bad rtol or max_iter");
+    if (!aligned(dev_ws)) return fail(H2X_EINVAL, "h2x_block_cg: workspace not 256-byte aligned");
+    return run_block_cg(A->dm, *prm, m, B, ldb, X, ldx, (char *)dev_ws, ws_bytes, info, (hipStream_t)hip_stream);
+}
+
+}  // extern "C"

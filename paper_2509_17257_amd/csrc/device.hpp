@@ -1,0 +1,76 @@
+// Internal device-side layout of an H^2 operator and the launchers of each stage.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "plan.hpp"
+
+namespace h2x {
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t v, size_t a = kAlign) { return (v + a - 1) / a * a; }
+
+// Flat device arrays of one operator, all inside the caller's workspace.
+struct DevMat {
+    int64_t n = 0;
+    int32_t C = 0, L = 0, k = 0, p = 0, depth_max = 0, max_leaf = 0;
+    int64_t n_adm = 0, n_near = 0, near_entries = 0;
+    h2x_prec storage = H2X_F64;
+    int swz = 0;  // coupling-matrix layout (see s_index)
+    int kernel = 0;
+    double ell = 0, shift = 0;
+
+    // topology
+    int32_t *first = nullptr, *size = nullptr, *parent = nullptr, *son0 = nullptr, *son1 = nullptr;
+    int32_t *leaves = nullptr, *lvl_all = nullptr, *lvl_inner = nullptr;
+    int64_t *adm_ptr = nullptr;  // C + 1
+    int32_t *adm_col = nullptr;  // n_adm
+    int32_t *adm_row = nullptr;  // n_adm (row cluster of each block)
+    int64_t *near_ptr = nullptr; // L + 1
+    int32_t *near_col = nullptr; // n_near
+    int32_t *near_row = nullptr; // n_near (row leaf cluster)
+    int64_t *near_off = nullptr; // n_near
+    int64_t *perm = nullptr;     // n
+    double *pts = nullptr;       // n x 3 tree order
+    double *box = nullptr;       // C x 6
+    double *nodes = nullptr;     // C x k x 3
+
+    // operator (element type per `storage`; near field FP64 or FP32)
+    void *V = nullptr;   // n x k
+    void *E = nullptr;   // C x k x k
+    void *S = nullptr;   // n_adm x k x k
+    void *N = nullptr;   // near_entries
+
+    // host copies of the level tables (launch sizes)
+    const Plan *plan = nullptr;
+};
+
+inline int s_swizzled(const DevMat &dm) { return dm.swz; }
+
+size_t mat_layout(const Plan &P, h2x_prec storage, DevMat *dm, char *base);
+
+hipError_t launch_fill(const DevMat &dm, hipStream_t st);
+
+size_t matmul_ws_bytes(const DevMat &dm, int64_t m);
+// ev (optional): 6 events recorded before the first stage and after each stage
+hipError_t run_matmul(const DevMat &dm, int64_t m, double alpha, const double *X, int64_t ldx, double beta,
+                      double *Y, int64_t ldy, bool tree_order, char *ws, hipStream_t st,
+                      hipEvent_t *ev = nullptr);
+
+size_t cg_ws_bytes(const DevMat &dm, int64_t m);
+h2x_status run_block_cg(const DevMat &dm, const h2x_cg_params &prm, int64_t m, const double *B, int64_t ldb,
+                        double *X, int64_t ldx, char *ws, size_t ws_bytes, h2x_cg_info *info, hipStream_t st);
+
+}  // namespace h2x
+
+struct h2x_plan {
+    h2x::Plan *p;
+};
+
+struct h2x_mat {
+    const h2x_plan *plan;
+    h2x::DevMat dm;
+    size_t ws_bytes;
+};

@@ -1,0 +1,211 @@
+// Device-side construction of the H^2 representation (section 2): Chebyshev
+// tensor nodes per cluster, leaf matrices V_t, transfer matrices E_t, coupling
+// matrices S_b of the admissible leaves and dense near-field blocks.  The
+// operator can be tens of GB (coupling matrices dominate), so it is generated
+// where it is used, directly into the caller's workspace.
+#include <cmath>
+
+#include "device.hpp"
+#include "types.hpp"
+
+namespace h2x {
+
+namespace {
+
+template <typename T>
+T *carve(size_t &off, char *base, size_t count) {
+    off = align_up(off);
+    T *ptr = base ? (T *)(base + off) : nullptr;
+    off += count * sizeof(T);
+    return ptr;
+}
+
+__device__ inline double kernel_g(int kernel, double ell, const double *a, const double *b) {
+    if (kernel == H2X_KERNEL_EXP) {
+        double dx = a[0] - b[0], dy = a[1] - b[1], dz = a[2] - b[2];
+        return exp(-sqrt(dx * dx + dy * dy + dz * dz) / ell);
+    }
+    if (kernel == H2X_KERNEL_POLY) {
+        double d = 1.0 + a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+        return d * d;
+    }
+    return 1.0;
+}
+
+// one-dimensional Lagrange polynomial j of the nodes nd[0..p) at x
+__device__ inline double lagrange1(const double *nd, int p, int j, double x) {
+    double v = 1.0, xj = nd[j];
+    for (int i = 0; i < p; ++i) {
+        if (i == j) continue;
+        v *= (x - nd[i]) / (xj - nd[i]);
+    }
+    return v;
+}
+
+// tensor nodes: nu = jx + p*jy + p^2*jz, first-kind Chebyshev points of the box
+__global__ void k_nodes(int32_t C, int p, const double *__restrict__ box, double *__restrict__ nodes) {
+    const int k = p * p * p;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)C * k) return;
+    const int32_t c = (int32_t)(idx / k);
+    const int nu = (int)(idx % k);
+    const int jj[3] = {nu % p, (nu / p) % p, nu / (p * p)};
+    for (int d = 0; d < 3; ++d) {
+        double lo = box[6 * c + d], hi = box[6 * c + 3 + d];
+        double ctr = 0.5 * (lo + hi), half = 0.5 * (hi - lo);
+        nodes[idx * 3 + d] = ctr + half * cos((2.0 * jj[d] + 1.0) * M_PI / (2.0 * p));
+    }
+}
+
+__device__ inline void nodes1d(const double *nodes, int32_t c, int p, int d, double *nd) {
+    const int k = p * p * p;
+    const int stride = d == 0 ? 1 : (d == 1 ? p : p * p);
+    for (int j = 0; j < p; ++j) nd[j] = nodes[((int64_t)c * k + (int64_t)j * stride) * 3 + d];
+}
+
+// V_t[i, nu] = L_{t,jx}(x_i) L_{t,jy}(y_i) L_{t,jz}(z_i) for the leaf t (one block per leaf)
+template <typename T>
+__global__ void k_fill_V(int p, const int32_t *__restrict__ leaves, const int32_t *__restrict__ first,
+                         const int32_t *__restrict__ size, const double *__restrict__ pts,
+                         const double *__restrict__ nodes, T *__restrict__ V) {
+    const int k = p * p * p;
+    const int32_t t = leaves[blockIdx.x];
+    __shared__ double nd[3][16];
+    if (threadIdx.x < 3 * p) {
+        int d = threadIdx.x / p, j = threadIdx.x % p;
+        const int stride = d == 0 ? 1 : (d == 1 ? p : p * p);
+        nd[d][j] = nodes[((int64_t)t * k + (int64_t)j * stride) * 3 + d];
+    }
+    __syncthreads();
+    const int64_t rows = size[t];
+    for (int64_t e = threadIdx.x; e < rows * k; e += blockDim.x) {
+        const int64_t i = first[t] + e / k;
+        const int nu = (int)(e % k);
+        const double *x = &pts[3 * i];
+        double v = lagrange1(nd[0], p, nu % p, x[0]) * lagrange1(nd[1], p, (nu / p) % p, x[1]) *
+                   lagrange1(nd[2], p, nu / (p * p), x[2]);
+        V[i * k + nu] = from_double<T>(v);
+    }
+}
+
+// E_c[a, nu] = L_{parent(c), nu}(xi_{c, a}) (one block per non-root cluster)
+template <typename T>
+__global__ void k_fill_E(int p, const int32_t *__restrict__ parent, const double *__restrict__ nodes,
+                         T *__restrict__ E) {
+    const int k = p * p * p;
+    const int32_t c = blockIdx.x + 1;  // the root has no transfer matrix
+    const int32_t par = parent[c];
+    __shared__ double nd[3][16];
+    if (threadIdx.x < 3 * p) {
+        int d = threadIdx.x / p, j = threadIdx.x % p;
+        const int stride = d == 0 ? 1 : (d == 1 ? p : p * p);
+        nd[d][j] = nodes[((int64_t)par * k + (int64_t)j * stride) * 3 + d];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < k * k; e += blockDim.x) {
+        const int a = e / k, nu = e % k;
+        const double *x = &nodes[((int64_t)c * k + a) * 3];
+        double v = lagrange1(nd[0], p, nu % p, x[0]) * lagrange1(nd[1], p, (nu / p) % p, x[1]) *
+                   lagrange1(nd[2], p, nu / (p * p), x[2]);
+        E[(int64_t)c * k * k + e] = from_double<T>(v);
+    }
+}
+
+// S_b[nu, mu] = g(xi_{t,nu}, xi_{s,mu}), stored in the layout the coupling kernel reads
+template <typename T>
+__global__ void k_fill_S(int k, int kernel, double ell, const int32_t *__restrict__ adm_row,
+                         const int32_t *__restrict__ adm_col, const double *__restrict__ nodes,
+                         T *__restrict__ S, int swz) {
+    const int64_t b = blockIdx.x;
+    const int32_t t = adm_row[b], s = adm_col[b];
+    for (int e = threadIdx.x; e < k * k; e += blockDim.x) {
+        const int nu = e / k, mu = e % k;
+        double v = kernel_g(kernel, ell, &nodes[((int64_t)t * k + nu) * 3], &nodes[((int64_t)s * k + mu) * 3]);
+        S[b * k * k + s_index(swz, k, nu, mu)] = from_double<T>(v);
+    }
+}
+
+// N_(t,s)[i, j] = g(x_i, x_j) + shift [i == j], row-major |t| x |s|
+template <typename TN>
+__global__ void k_fill_N(int kernel, double ell, double shift, const int32_t *__restrict__ near_row,
+                         const int32_t *__restrict__ near_col, const int64_t *__restrict__ near_off,
+                         const int32_t *__restrict__ first, const int32_t *__restrict__ size,
+                         const double *__restrict__ pts, TN *__restrict__ N) {
+    const int64_t q = blockIdx.x;
+    const int32_t t = near_row[q], s = near_col[q];
+    const int64_t nt = size[t], ns = size[s], ft = first[t], fs = first[s];
+    TN *Nb = N + near_off[q];
+    for (int64_t e = threadIdx.x; e < nt * ns; e += blockDim.x) {
+        const int64_t i = ft + e / ns, j = fs + e % ns;
+        double v = kernel_g(kernel, ell, &pts[3 * i], &pts[3 * j]);
+        if (i == j) v += shift;
+        Nb[e] = (TN)v;
+    }
+}
+
+template <typename T, typename TN>
+hipError_t fill_typed(const DevMat &dm, hipStream_t st) {
+    const int64_t ck = (int64_t)dm.C * dm.k;
+    hipLaunchKernelGGL(k_nodes, dim3((unsigned)((ck + 255) / 256)), dim3(256), 0, st, dm.C, dm.p, dm.box, dm.nodes);
+    if (dm.L > 0)
+        hipLaunchKernelGGL(k_fill_V<T>, dim3(dm.L), dim3(256), 0, st, dm.p, dm.leaves, dm.first, dm.size, dm.pts,
+                           dm.nodes, (T *)dm.V);
+    if (dm.C > 1)
+        hipLaunchKernelGGL(k_fill_E<T>, dim3(dm.C - 1), dim3(256), 0, st, dm.p, dm.parent, dm.nodes, (T *)dm.E);
+    if (dm.n_adm > 0)
+        hipLaunchKernelGGL(k_fill_S<T>, dim3((unsigned)dm.n_adm), dim3(256), 0, st, dm.k, dm.kernel, dm.ell,
+                           dm.adm_row, dm.adm_col, dm.nodes, (T *)dm.S, s_swizzled(dm));
+    if (dm.n_near > 0)
+        hipLaunchKernelGGL(k_fill_N<TN>, dim3((unsigned)dm.n_near), dim3(256), 0, st, dm.kernel, dm.ell, dm.shift,
+                           dm.near_row, dm.near_col, dm.near_off, dm.first, dm.size, dm.pts, (TN *)dm.N);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+size_t mat_layout(const Plan &P, h2x_prec storage, DevMat *dm, char *base) {
+    size_t cur = 0;
+    const int32_t C = P.C, L = (int32_t)P.leaves.size(), k = P.k;
+    const int64_t n = P.n, na = (int64_t)P.adm_col.size(), nn = (int64_t)P.near_col.size();
+    DevMat d;
+    d.n = n; d.C = C; d.L = L; d.k = k; d.p = P.p; d.depth_max = P.depth_max; d.max_leaf = P.max_leaf;
+    d.n_adm = na; d.n_near = nn; d.near_entries = P.near_entries; d.storage = storage;
+    d.kernel = P.prm.kernel; d.ell = P.prm.ell; d.shift = P.prm.shift; d.plan = &P;
+    d.first = carve<int32_t>(cur, base, C);
+    d.size = carve<int32_t>(cur, base, C);
+    d.parent = carve<int32_t>(cur, base, C);
+    d.son0 = carve<int32_t>(cur, base, C);
+    d.son1 = carve<int32_t>(cur, base, C);
+    d.leaves = carve<int32_t>(cur, base, L);
+    d.lvl_all = carve<int32_t>(cur, base, C);
+    d.lvl_inner = carve<int32_t>(cur, base, P.lvl_inner.size() + 1);
+    d.adm_ptr = carve<int64_t>(cur, base, C + 1);
+    d.adm_col = carve<int32_t>(cur, base, na + 1);
+    d.adm_row = carve<int32_t>(cur, base, na + 1);
+    d.near_ptr = carve<int64_t>(cur, base, L + 1);
+    d.near_col = carve<int32_t>(cur, base, nn + 1);
+    d.near_row = carve<int32_t>(cur, base, nn + 1);
+    d.near_off = carve<int64_t>(cur, base, nn + 1);
+    d.perm = carve<int64_t>(cur, base, n);
+    d.pts = carve<double>(cur, base, 3 * n);
+    d.box = carve<double>(cur, base, 6 * (size_t)C);
+    d.nodes = carve<double>(cur, base, 3 * (size_t)C * k);
+    const size_t es = storage == H2X_F64 ? 8 : (storage == H2X_F32 ? 4 : 2);
+    const size_t ens = storage == H2X_F64 ? 8 : 4;
+    d.V = carve<char>(cur, base, es * (size_t)n * k);
+    d.E = carve<char>(cur, base, es * (size_t)C * k * k);
+    d.S = carve<char>(cur, base, es * (size_t)(na ? na : 1) * k * k);
+    d.N = carve<char>(cur, base, ens * (size_t)(P.near_entries ? P.near_entries : 1));
+    if (dm) *dm = d;
+    return align_up(cur);
+}
+
+hipError_t launch_fill(const DevMat &dm, hipStream_t st) {
+    switch (dm.storage) {
+        case H2X_F64: return fill_typed<double, double>(dm, st);
+        case H2X_F32: return fill_typed<float, float>(dm, st);
+        default: return fill_typed<bf16_t, float>(dm, st);
+    }
+}
+
+}  // namespace h2x

@@ -1,0 +1,355 @@
+// H^2 x X (Algorithm "H2_mvm" in its matrix form, section 4):
+//   forward transformation  x_s = V_s^T X|_s at leaves, x_t = sum_{t'} E_{t'}^T x_{t'} upwards
+//   multiplication phase    y_t = sum_{(t,s) in C_t, admissible} S_b x_s   for every cluster t
+//   backward transformation y_{t'} += E_{t'} y_t downwards,
+//                            Y|_t = beta Y|_t + alpha (V_t y_t + sum_{(t,s) near} N_b X|_s) at leaves
+// Ownership follows the paper's race-free rules: a parent sums its sons (no two
+// writers of x_t), each row cluster owns its list and its rows of Y (no two
+// writers of y_t or Y|_t).  No floating-point atomics: results are
+// bitwise reproducible run to run.
+//
+// Every stage is a batch of small GEMMs.  This file holds the generic kernels
+// (any rank k, any leaf size, any m): 256 threads stage 64 x 64 operand tiles
+// and 64 x 32 column tiles in LDS, each thread accumulates 8 outputs.
+#include "device.hpp"
+#include "matmul_mfma.hpp"
+#include "types.hpp"
+
+namespace h2x {
+
+namespace {
+
+constexpr int TR = 64;  // output rows / contraction chunk per tile
+constexpr int TC = 32;  // columns of X per work-group (grid.y)
+
+template <typename T, typename Acc>
+__device__ inline Acc ld_op(const T *p) { return (Acc)to_double(*p); }
+
+// operand rounding of a right-hand factor to the storage precision T
+template <typename T, typename Acc>
+__device__ inline Acc round_op(double v) { return (Acc)to_double(from_double<T>(v)); }
+
+template <typename Acc>
+__device__ inline void tile_fma(Acc acc[8], const Acc (*As)[TR + 1], const Acc (*Bs)[TC], int kc, int rg, int j) {
+    for (int c = 0; c < kc; ++c) {
+        const Acc b = Bs[c][j];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc[q] += As[rg + 8 * q][c] * b;
+    }
+}
+
+// x_t = V_t^T X|_t for each leaf t
+template <typename T, typename Acc>
+__global__ __launch_bounds__(256) void k_fwd_leaf(int k, int64_t m, const int32_t *__restrict__ leaves,
+                                                  const int32_t *__restrict__ first, const int32_t *__restrict__ size,
+                                                  const int64_t *__restrict__ perm, const T *__restrict__ V,
+                                                  const double *__restrict__ X, int64_t ldx, int tree_order,
+                                                  Acc *__restrict__ xh, int64_t ldh) {
+    __shared__ Acc As[TR][TR + 1];
+    __shared__ Acc Bs[TR][TC];
+    const int32_t t = leaves[blockIdx.x];
+    const int64_t j0 = (int64_t)blockIdx.y * TC;
+    const int mc = (int)min<int64_t>(TC, m - j0);
+    const int tid = threadIdx.x, rg = tid >> 5, j = tid & 31;
+    const int64_t r0 = first[t];
+    const int nt = size[t];
+    for (int n0 = 0; n0 < k; n0 += TR) {
+        Acc acc[8] = {};
+        for (int i0 = 0; i0 < nt; i0 += TR) {
+            const int ic = min(TR, nt - i0);
+            for (int e = tid; e < TR * TR; e += 256) {
+                const int i = e / TR, nu = e % TR;
+                As[nu][i] = (i < ic && n0 + nu < k) ? ld_op<T, Acc>(&V[(r0 + i0 + i) * k + n0 + nu]) : Acc(0);
+            }
+            for (int e = tid; e < TR * TC; e += 256) {
+                const int i = e / TC, jj = e % TC;
+                Acc v = 0;
+                if (i < ic && jj < mc) {
+                    int64_t row = r0 + i0 + i;
+                    if (!tree_order) row = perm[row];
+                    v = round_op<T, Acc>(X[row * ldx + j0 + jj]);
+                }
+                Bs[i][jj] = v;
+            }
+            __syncthreads();
+            tile_fma(acc, As, Bs, ic, rg, j);
+            __syncthreads();
+        }
+        if (j < mc)
+            for (int q = 0; q < 8; ++q) {
+                const int nu = n0 + rg + 8 * q;
+                if (nu < k) xh[((int64_t)t * k + nu) * ldh + j0 + j] = acc[q];
+            }
+    }
+}
+
+// x_t = E_{t0}^T x_{t0} + E_{t1}^T x_{t1} for the inner clusters of one depth
+template <typename T, typename Acc>
+__global__ __launch_bounds__(256) void k_up(int k, int64_t m, const int32_t *__restrict__ list,
+                                            const int32_t *__restrict__ son0, const int32_t *__restrict__ son1,
+                                            const T *__restrict__ E, Acc *__restrict__ xh, int64_t ldh) {
+    __shared__ Acc As[TR][TR + 1];
+    __shared__ Acc Bs[TR][TC];
+    const int32_t t = list[blockIdx.x];
+    const int64_t j0 = (int64_t)blockIdx.y * TC;
+    const int mc = (int)min<int64_t>(TC, m - j0);
+    const int tid = threadIdx.x, rg = tid >> 5, j = tid & 31;
+    const int32_t sons[2] = {son0[t], son1[t]};
+    for (int n0 = 0; n0 < k; n0 += TR) {
+        Acc acc[8] = {};
+        for (int q2 = 0; q2 < 2; ++q2) {
+            const int32_t s = sons[q2];
+            const T *Es = E + (int64_t)s * k * k;
+            for (int a0 = 0; a0 < k; a0 += TR) {
+                const int ac = min(TR, k - a0);
+                for (int e = tid; e < TR * TR; e += 256) {
+                    const int a = e / TR, nu = e % TR;
+                    As[nu][a] = (a < ac && n0 + nu < k) ? ld_op<T, Acc>(&Es[(int64_t)(a0 + a) * k + n0 + nu]) : Acc(0);
+                }
+                for (int e = tid; e < TR * TC; e += 256) {
+                    const int a = e / TC, jj = e % TC;
+                    Bs[a][jj] = (a < ac && jj < mc)
+                                    ? round_op<T, Acc>((double)xh[((int64_t)s * k + a0 + a) * ldh + j0 + jj])
+                                    : Acc(0);
+                }
+                __syncthreads();
+                tile_fma(acc, As, Bs, ac, rg, j);
+                __syncthreads();
+            }
+        }
+        if (j < mc)
+            for (int q = 0; q < 8; ++q) {
+                const int nu = n0 + rg + 8 * q;
+                if (nu < k) xh[((int64_t)t * k + nu) * ldh + j0 + j] = acc[q];
+            }
+    }
+}
+
+// y_t = sum over the admissible blocks of row cluster t of S_b x_s (every cluster)
+template <typename T, typename Acc>
+__global__ __launch_bounds__(256) void k_coupling(int k, int64_t m, const int64_t *__restrict__ adm_ptr,
+                                                  const int32_t *__restrict__ adm_col, const T *__restrict__ S,
+                                                  const Acc *__restrict__ xh, Acc *__restrict__ yh, int64_t ldh) {
+    __shared__ Acc As[TR][TR + 1];
+    __shared__ Acc Bs[TR][TC];
+    const int32_t t = blockIdx.x;
+    const int64_t j0 = (int64_t)blockIdx.y * TC;
+    const int mc = (int)min<int64_t>(TC, m - j0);
+    const int tid = threadIdx.x, rg = tid >> 5, j = tid & 31;
+    const int64_t b0 = adm_ptr[t], b1 = adm_ptr[t + 1];
+    for (int n0 = 0; n0 < k; n0 += TR) {
+        Acc acc[8] = {};
+        for (int64_t b = b0; b < b1; ++b) {
+            const int32_t s = adm_col[b];
+            const T *Sb = S + b * k * k;
+            for (int u0 = 0; u0 < k; u0 += TR) {
+                const int uc = min(TR, k - u0);
+                for (int e = tid; e < TR * TR; e += 256) {
+                    const int nu = e / TR, mu = e % TR;
+                    As[nu][mu] = (mu < uc && n0 + nu < k) ? ld_op<T, Acc>(&Sb[(int64_t)(n0 + nu) * k + u0 + mu]) : Acc(0);
+                }
+                for (int e = tid; e < TR * TC; e += 256) {
+                    const int mu = e / TC, jj = e % TC;
+                    Bs[mu][jj] = (mu < uc && jj < mc)
+                                     ? round_op<T, Acc>((double)xh[((int64_t)s * k + u0 + mu) * ldh + j0 + jj])
+                                     : Acc(0);
+                }
+                __syncthreads();
+                tile_fma(acc, As, Bs, uc, rg, j);
+                __syncthreads();
+            }
+        }
+        if (j < mc)
+            for (int q = 0; q < 8; ++q) {
+                const int nu = n0 + rg + 8 * q;
+                if (nu < k) yh[((int64_t)t * k + nu) * ldh + j0 + j] = acc[q];
+            }
+    }
+}
+
+// y_c += E_c y_parent(c) for the clusters of one depth >= 1
+template <typename T, typename Acc>
+__global__ __launch_bounds__(256) void k_down(int k, int64_t m, const int32_t *__restrict__ list,
+                                              const int32_t *__restrict__ parent, const T *__restrict__ E,
+                                              Acc *__restrict__ yh, int64_t ldh) {
+    __shared__ Acc As[TR][TR + 1];
+    __shared__ Acc Bs[TR][TC];
+    const int32_t c = list[blockIdx.x];
+    const int32_t par = parent[c];
+    const int64_t j0 = (int64_t)blockIdx.y * TC;
+    const int mc = (int)min<int64_t>(TC, m - j0);
+    const int tid = threadIdx.x, rg = tid >> 5, j = tid & 31;
+    const T *Ec = E + (int64_t)c * k * k;
+    for (int a0 = 0; a0 < k; a0 += TR) {
+        Acc acc[8] = {};
+        for (int u0 = 0; u0 < k; u0 += TR) {
+            const int uc = min(TR, k - u0);
+            for (int e = tid; e < TR * TR; e += 256) {
+                const int a = e / TR, nu = e % TR;
+                As[a][nu] = (nu < uc && a0 + a < k) ? ld_op<T, Acc>(&Ec[(int64_t)(a0 + a) * k + u0 + nu]) : Acc(0);
+            }
+            for (int e = tid; e < TR * TC; e += 256) {
+                const int nu = e / TC, jj = e % TC;
+                Bs[nu][jj] = (nu < uc && jj < mc)
+                                 ? round_op<T, Acc>((double)yh[((int64_t)par * k + u0 + nu) * ldh + j0 + jj])
+                                 : Acc(0);
+            }
+            __syncthreads();
+            tile_fma(acc, As, Bs, uc, rg, j);
+            __syncthreads();
+        }
+        if (j < mc)
+            for (int q = 0; q < 8; ++q) {
+                const int a = a0 + rg + 8 * q;
+                if (a < k) yh[((int64_t)c * k + a) * ldh + j0 + j] += acc[q];
+            }
+    }
+}
+
+// Y|_t = beta Y|_t + alpha (V_t y_t + sum_{near (t,s)} N_b X|_s) for each leaf t
+template <typename T, typename TN, typename Acc>
+__global__ __launch_bounds__(256) void k_leaf_near(int k, int64_t m, const int32_t *__restrict__ leaves,
+                                                   const int32_t *__restrict__ first, const int32_t *__restrict__ size,
+                                                   const int64_t *__restrict__ perm, const T *__restrict__ V,
+                                                   const Acc *__restrict__ yh, int64_t ldh,
+                                                   const int64_t *__restrict__ near_ptr,
+                                                   const int32_t *__restrict__ near_col,
+                                                   const int64_t *__restrict__ near_off, const TN *__restrict__ N,
+                                                   const double *__restrict__ X, int64_t ldx, double alpha,
+                                                   double beta, double *__restrict__ Y, int64_t ldy, int tree_order) {
+    __shared__ Acc As[TR][TR + 1];
+    __shared__ Acc Bs[TR][TC];
+    const int32_t l = blockIdx.x;
+    const int32_t t = leaves[l];
+    const int64_t j0 = (int64_t)blockIdx.y * TC;
+    const int mc = (int)min<int64_t>(TC, m - j0);
+    const int tid = threadIdx.x, rg = tid >> 5, j = tid & 31;
+    const int64_t r0 = first[t];
+    const int nt = size[t];
+    for (int i0 = 0; i0 < nt; i0 += TR) {
+        const int ic = min(TR, nt - i0);
+        Acc acc[8] = {};
+        for (int u0 = 0; u0 < k; u0 += TR) {
+            const int uc = min(TR, k - u0);
+            for (int e = tid; e < TR * TR; e += 256) {
+                const int i = e / TR, nu = e % TR;
+                As[i][nu] = (i < ic && nu < uc) ? ld_op<T, Acc>(&V[(r0 + i0 + i) * k + u0 + nu]) : Acc(0);
+            }
+            for (int e = tid; e < TR * TC; e += 256) {
+                const int nu = e / TC, jj = e % TC;
+                Bs[nu][jj] = (nu < uc && jj < mc)
+                                 ? round_op<T, Acc>((double)yh[((int64_t)t * k + u0 + nu) * ldh + j0 + jj])
+                                 : Acc(0);
+            }
+            __syncthreads();
+            tile_fma(acc, As, Bs, uc, rg, j);
+            __syncthreads();
+        }
+        for (int64_t q = near_ptr[l]; q < near_ptr[l + 1]; ++q) {
+            const int32_t s = near_col[q];
+            const int ns = size[s];
+            const int64_t fs = first[s];
+            const TN *Nb = N + near_off[q];
+            for (int c0 = 0; c0 < ns; c0 += TR) {
+                const int cc = min(TR, ns - c0);
+                for (int e = tid; e < TR * TR; e += 256) {
+                    const int i = e / TR, c = e % TR;
+                    As[i][c] = (i < ic && c < cc) ? ld_op<TN, Acc>(&Nb[(int64_t)(i0 + i) * ns + c0 + c]) : Acc(0);
+                }
+                for (int e = tid; e < TR * TC; e += 256) {
+                    const int c = e / TC, jj = e % TC;
+                    Acc v = 0;
+                    if (c < cc && jj < mc) {
+                        int64_t row = fs + c0 + c;
+                        if (!tree_order) row = perm[row];
+                        v = round_op<TN, Acc>(X[row * ldx + j0 + jj]);
+                    }
+                    Bs[c][jj] = v;
+                }
+                __syncthreads();
+                tile_fma(acc, As, Bs, cc, rg, j);
+                __syncthreads();
+            }
+        }
+        if (j < mc)
+            for (int q = 0; q < 8; ++q) {
+                const int i = rg + 8 * q;
+                if (i < ic) {
+                    int64_t row = r0 + i0 + i;
+                    if (!tree_order) row = perm[row];
+                    double *y = &Y[row * ldy + j0 + j];
+                    const double v = alpha * (double)acc[q];
+                    *y = (beta == 0.0) ? v : beta * *y + v;
+                }
+            }
+    }
+}
+
+template <typename Acc>
+size_t hat_bytes(const DevMat &dm, int64_t m) {
+    return align_up(sizeof(Acc) * (size_t)dm.C * dm.k * (size_t)m);
+}
+
+template <typename T, typename TN, typename Acc>
+hipError_t matmul_typed(const DevMat &dm, int64_t m, double alpha, const double *X, int64_t ldx, double beta,
+                        double *Y, int64_t ldy, bool tree_order, char *ws, hipStream_t st, hipEvent_t *ev) {
+    auto mark = [&](int i) {
+        if (ev) (void)hipEventRecord(ev[i], st);
+    };
+    const Plan &P = *dm.plan;
+    const int64_t ldh = m;
+    Acc *xh = (Acc *)ws;
+    Acc *yh = (Acc *)(ws + hat_bytes<Acc>(dm, m));
+    const unsigned gy = (unsigned)((m + TC - 1) / TC);
+    const int to = tree_order ? 1 : 0;
+    const T *V = (const T *)dm.V, *E = (const T *)dm.E, *S = (const T *)dm.S;
+
+    mark(0);
+    hipLaunchKernelGGL((k_fwd_leaf<T, Acc>), dim3(dm.L, gy), dim3(256), 0, st, dm.k, m, dm.leaves, dm.first, dm.size,
+                       dm.perm, V, X, ldx, to, xh, ldh);
+    mark(1);
+    for (int d = dm.depth_max - 1; d >= 0; --d) {
+        const int32_t b = P.lvl_inner_ptr[d], e = P.lvl_inner_ptr[d + 1];
+        if (e > b)
+            hipLaunchKernelGGL((k_up<T, Acc>), dim3(e - b, gy), dim3(256), 0, st, dm.k, m, dm.lvl_inner + b, dm.son0,
+                               dm.son1, E, xh, ldh);
+    }
+    mark(2);
+    if (!launch_coupling_fast<T, Acc>(dm, m, xh, yh, ldh, st))
+        hipLaunchKernelGGL((k_coupling<T, Acc>), dim3(dm.C, gy), dim3(256), 0, st, dm.k, m, dm.adm_ptr, dm.adm_col, S,
+                           xh, yh, ldh);
+    mark(3);
+    for (int d = 1; d <= dm.depth_max; ++d) {
+        const int32_t b = P.lvl_ptr[d], e = P.lvl_ptr[d + 1];
+        if (e > b)
+            hipLaunchKernelGGL((k_down<T, Acc>), dim3(e - b, gy), dim3(256), 0, st, dm.k, m, dm.lvl_all + b, dm.parent,
+                               E, yh, ldh);
+    }
+    mark(4);
+    hipLaunchKernelGGL((k_leaf_near<T, TN, Acc>), dim3(dm.L, gy), dim3(256), 0, st, dm.k, m, dm.leaves, dm.first,
+                       dm.size, dm.perm, V, yh, ldh, dm.near_ptr, dm.near_col, dm.near_off, (const TN *)dm.N, X, ldx,
+                       alpha, beta, Y, ldy, to);
+    mark(5);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+size_t matmul_ws_bytes(const DevMat &dm, int64_t m) {
+    if (dm.storage == H2X_F64) return 2 * hat_bytes<double>(dm, m);
+    return 2 * hat_bytes<float>(dm, m);
+}
+
+hipError_t run_matmul(const DevMat &dm, int64_t m, double alpha, const double *X, int64_t ldx, double beta, double *Y,
+                      int64_t ldy, bool tree_order, char *ws, hipStream_t st, hipEvent_t *ev) {
+    switch (dm.storage) {
+        case H2X_F64:
+            return matmul_typed<double, double, double>(dm, m, alpha, X, ldx, beta, Y, ldy, tree_order, ws, st, ev);
+        case H2X_F32:
+            return matmul_typed<float, float, float>(dm, m, alpha, X, ldx, beta, Y, ldy, tree_order, ws, st, ev);
+        default:
+            return matmul_typed<bf16_t, float, float>(dm, m, alpha, X, ldx, beta, Y, ldy, tree_order, ws, st, ev);
+    }
+}
+
+}  // namespace h2x

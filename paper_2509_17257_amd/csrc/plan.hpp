@@ -1,0 +1,51 @@
+// Internal host-side structures of the h2x library (not part of the C ABI).
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/h2x.h"
+
+namespace h2x {
+
+// Host topology produced by the planner.  Clusters are numbered in pre-order,
+// so the points of every cluster occupy one contiguous range of tree positions.
+struct Plan {
+    int64_t n = 0;
+    h2x_params prm{};
+    int32_t p = 0, k = 0;
+
+    std::vector<int64_t> perm;      // tree position -> original index
+    std::vector<double> pts_tree;   // n x 3, tree order
+
+    int32_t C = 0;                  // clusters
+    std::vector<int32_t> first, size, parent, son0, son1, depth;
+    std::vector<double> box;        // C x 6: interpolation box lo[3], hi[3]
+    int32_t depth_max = 0;
+
+    std::vector<int32_t> leaves;    // leaf cluster ids, pre-order (= tree-position order)
+    std::vector<int32_t> leaf_index;  // cluster id -> leaf index or -1
+
+    // clusters grouped by depth (all clusters) for the level-synchronous passes
+    std::vector<int32_t> lvl_ptr;   // depth_max + 2
+    std::vector<int32_t> lvl_all;   // cluster ids by depth
+    std::vector<int32_t> lvl_inner_ptr;  // depth_max + 2
+    std::vector<int32_t> lvl_inner;      // inner cluster ids by depth
+
+    // admissible leaves, CSR by row cluster
+    std::vector<int64_t> adm_ptr;   // C + 1
+    std::vector<int32_t> adm_col;   // n_adm
+    // near-field leaves, CSR by row leaf (indexed by leaf index)
+    std::vector<int64_t> near_ptr;  // L + 1
+    std::vector<int32_t> near_col;  // column cluster id
+    std::vector<int64_t> near_off;  // offset of the block in the near-field array
+    int64_t near_entries = 0;
+    int32_t max_leaf = 0;           // largest leaf size
+};
+
+Plan *build_plan(const double *pts, int64_t n, const h2x_params &prm, std::string &err);
+
+void set_error(const std::string &msg);
+
+}  // namespace h2x

@@ -1,0 +1,210 @@
+// Host planner: cluster tree, block tree and row-cluster lists (section 2 and
+// Algorithm "prepare_addeval" of section 3), laid out as flat CSR arrays for the
+// device.  Iterative (explicit stacks) so deep trees cannot overflow the call
+// stack.  Built with -ffp-contract=off: the admissibility test compares
+// floating-point distances, and its outcome must not depend on FMA contraction.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "plan.hpp"
+
+namespace h2x {
+
+namespace {
+
+struct Pending {
+    int64_t first, size;
+    int32_t parent, depth;
+    int which;  // 0: first son of parent, 1: second son
+};
+
+double box_diam(const double *lo, const double *hi) {
+    double s = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        double e = hi[d] - lo[d];
+        s += e * e;
+    }
+    return std::sqrt(s);
+}
+
+double box_dist(const double *lo_t, const double *hi_t, const double *lo_s, const double *hi_s) {
+    double s = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        double g = std::max(0.0, std::max(lo_s[d] - hi_t[d], lo_t[d] - hi_s[d]));
+        s += g * g;
+    }
+    return std::sqrt(s);
+}
+
+}  // namespace
+
+Plan *build_plan(const double *pts, int64_t n, const h2x_params &prm, std::string &err) {
+    auto *P = new Plan();
+    P->n = n;
+    P->prm = prm;
+    P->p = prm.cheb_order;
+    P->k = prm.cheb_order * prm.cheb_order * prm.cheb_order;
+    P->perm.resize(n);
+    for (int64_t i = 0; i < n; ++i) P->perm[i] = i;
+
+    // tight boxes while building; interpolation boxes derived afterwards
+    std::vector<double> tlo, thi;
+    const int64_t cap = 2 * n;
+    P->first.reserve(cap);
+
+    std::vector<Pending> stack;
+    stack.push_back({0, n, -1, 0, 0});
+    while (!stack.empty()) {
+        Pending q = stack.back();
+        stack.pop_back();
+        const int32_t id = P->C++;
+        P->first.push_back((int32_t)q.first);
+        P->size.push_back((int32_t)q.size);
+        P->parent.push_back(q.parent);
+        P->son0.push_back(-1);
+        P->son1.push_back(-1);
+        P->depth.push_back(q.depth);
+        if (q.parent >= 0) (q.which == 0 ? P->son0 : P->son1)[q.parent] = id;
+        P->depth_max = std::max(P->depth_max, q.depth);
+
+        double lo[3], hi[3];
+        for (int d = 0; d < 3; ++d) lo[d] = hi[d] = pts[3 * P->perm[q.first] + d];
+        for (int64_t i = q.first + 1; i < q.first + q.size; ++i)
+            for (int d = 0; d < 3; ++d) {
+                double v = pts[3 * P->perm[i] + d];
+                lo[d] = std::min(lo[d], v);
+                hi[d] = std::max(hi[d], v);
+            }
+        for (int d = 0; d < 3; ++d) { tlo.push_back(lo[d]); thi.push_back(hi[d]); }
+
+        if (q.size <= prm.leaf_size) continue;
+        int dim = 0;
+        for (int d = 1; d < 3; ++d)
+            if (hi[d] - lo[d] > hi[dim] - lo[dim]) dim = d;
+        if (hi[dim] - lo[dim] == 0.0) continue;
+        const double mid = 0.5 * (lo[dim] + hi[dim]);
+        auto b = P->perm.begin() + q.first;
+        auto cut = std::stable_partition(b, b + q.size, [&](int64_t g) { return pts[3 * g + dim] < mid; });
+        const int64_t n0 = cut - b;
+        if (n0 == 0 || n0 == q.size) continue;
+        // second son pushed first so the first son's subtree is numbered next (pre-order)
+        stack.push_back({q.first + n0, q.size - n0, id, q.depth + 1, 1});
+        stack.push_back({q.first, n0, id, q.depth + 1, 0});
+    }
+    const int32_t C = P->C;
+
+    // interpolation boxes: tight box, widened to 1e-10 where it is flatter than that
+    const double tau = 1e-10;
+    P->box.resize((size_t)C * 6);
+    for (int32_t c = 0; c < C; ++c)
+        for (int d = 0; d < 3; ++d) {
+            double lo = tlo[3 * c + d], hi = thi[3 * c + d];
+            if (hi - lo < tau) {
+                double ctr = 0.5 * (lo + hi);
+                lo = ctr - 0.5 * tau;
+                hi = ctr + 0.5 * tau;
+            }
+            P->box[6 * c + d] = lo;
+            P->box[6 * c + 3 + d] = hi;
+        }
+
+    P->pts_tree.resize((size_t)n * 3);
+    for (int64_t i = 0; i < n; ++i)
+        for (int d = 0; d < 3; ++d) P->pts_tree[3 * i + d] = pts[3 * P->perm[i] + d];
+
+    P->leaf_index.assign(C, -1);
+    for (int32_t c = 0; c < C; ++c)
+        if (P->son0[c] < 0) {
+            P->leaf_index[c] = (int32_t)P->leaves.size();
+            P->leaves.push_back(c);
+            P->max_leaf = std::max(P->max_leaf, P->size[c]);
+        }
+
+    // clusters by depth
+    const int32_t D = P->depth_max + 1;
+    P->lvl_ptr.assign(D + 1, 0);
+    P->lvl_inner_ptr.assign(D + 1, 0);
+    for (int32_t c = 0; c < C; ++c) {
+        P->lvl_ptr[P->depth[c] + 1]++;
+        if (P->son0[c] >= 0) P->lvl_inner_ptr[P->depth[c] + 1]++;
+    }
+    for (int32_t d = 0; d < D; ++d) {
+        P->lvl_ptr[d + 1] += P->lvl_ptr[d];
+        P->lvl_inner_ptr[d + 1] += P->lvl_inner_ptr[d];
+    }
+    P->lvl_all.resize(C);
+    P->lvl_inner.resize(P->lvl_inner_ptr[D]);
+    {
+        std::vector<int32_t> fa(P->lvl_ptr.begin(), P->lvl_ptr.end() - 1);
+        std::vector<int32_t> fi(P->lvl_inner_ptr.begin(), P->lvl_inner_ptr.end() - 1);
+        for (int32_t c = 0; c < C; ++c) {
+            P->lvl_all[fa[P->depth[c]]++] = c;
+            if (P->son0[c] >= 0) P->lvl_inner[fi[P->depth[c]]++] = c;
+        }
+    }
+
+    // block tree: depth-first with an explicit stack; children pushed in reverse
+    // so leaves are emitted in pre-order
+    std::vector<std::pair<int32_t, int32_t>> bstack;
+    std::vector<std::pair<int32_t, int32_t>> adm, near;
+    bstack.push_back({0, 0});
+    auto tl = [&](int32_t c) { return &tlo[3 * c]; };
+    auto th = [&](int32_t c) { return &thi[3 * c]; };
+    while (!bstack.empty()) {
+        auto [t, s] = bstack.back();
+        bstack.pop_back();
+        const double dist = box_dist(tl(t), th(t), tl(s), th(s));
+        if (dist > 0.0) {
+            const double dm = std::max(box_diam(tl(t), th(t)), box_diam(tl(s), th(s)));
+            if (dm <= prm.eta * dist) { adm.push_back({t, s}); continue; }
+        }
+        const bool lt = P->son0[t] < 0, ls = P->son0[s] < 0;
+        if (lt && ls) { near.push_back({t, s}); continue; }
+        if (lt) {
+            bstack.push_back({t, P->son1[s]});
+            bstack.push_back({t, P->son0[s]});
+        } else if (ls) {
+            bstack.push_back({P->son1[t], s});
+            bstack.push_back({P->son0[t], s});
+        } else {
+            bstack.push_back({P->son1[t], P->son1[s]});
+            bstack.push_back({P->son1[t], P->son0[s]});
+            bstack.push_back({P->son0[t], P->son1[s]});
+            bstack.push_back({P->son0[t], P->son0[s]});
+        }
+    }
+
+    // CSR by row cluster; a stable counting sort keeps block pre-order in a row
+    P->adm_ptr.assign(C + 1, 0);
+    for (auto &b : adm) P->adm_ptr[b.first + 1]++;
+    for (int32_t c = 0; c < C; ++c) P->adm_ptr[c + 1] += P->adm_ptr[c];
+    P->adm_col.resize(adm.size());
+    {
+        std::vector<int64_t> f(P->adm_ptr.begin(), P->adm_ptr.end() - 1);
+        for (auto &b : adm) P->adm_col[f[b.first]++] = b.second;
+    }
+    const int32_t L = (int32_t)P->leaves.size();
+    P->near_ptr.assign(L + 1, 0);
+    for (auto &b : near) P->near_ptr[P->leaf_index[b.first] + 1]++;
+    for (int32_t l = 0; l < L; ++l) P->near_ptr[l + 1] += P->near_ptr[l];
+    P->near_col.resize(near.size());
+    P->near_off.resize(near.size());
+    {
+        std::vector<int64_t> f(P->near_ptr.begin(), P->near_ptr.end() - 1);
+        for (auto &b : near) P->near_col[f[P->leaf_index[b.first]]++] = b.second;
+    }
+    int64_t off = 0;
+    for (int32_t l = 0; l < L; ++l) {
+        const int32_t t = P->leaves[l];
+        for (int64_t q = P->near_ptr[l]; q < P->near_ptr[l + 1]; ++q) {
+            P->near_off[q] = off;
+            off += (int64_t)P->size[t] * P->size[P->near_col[q]];
+        }
+    }
+    P->near_entries = off;
+    (void)err;
+    return P;
+}
+
+}  // namespace h2x

@@ -1,0 +1,84 @@
+"""Host-side checks of the C-ABI library (no GPU needed).
+
+* libh2x.so loads and exports every function declared in include/h2x.h.
+* The native planner reproduces the oracle's cluster tree, block tree and lists
+  exactly (same rules, written independently): permutation, cluster ranges,
+  and the set of admissible / near-field leaves with the within-row order of
+  the prepare_addeval lists.
+* Argument validation returns H2X_EINVAL without touching a GPU.
+"""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2509_17257_amd as h2x
+from paper_2509_17257_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "h2x.h")).read()
+    return sorted(set(re.findall(r"\b(h2x_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = h2x.load_library()
+    names = _declared()
+    assert len(names) >= 15
+    for nm in names:
+        assert hasattr(lib, nm), nm
+    assert lib.h2x_version().decode().startswith("h2x")
+
+
+@pytest.mark.parametrize("wl,n", [("sphere", 3000), ("cube", 5000), ("line", 700)])
+@pytest.mark.parametrize("leaf,eta,p", [(32, 1.0, 3), (64, 1.0, 4), (16, 2.0, 2), (8, 0.5, 3)])
+def test_planner_matches_oracle_structure(wl, n, leaf, eta, p):
+    P = {"sphere": W.sphere_points, "cube": W.cube_points, "line": W.line_points}[wl](n, 71)
+    o = oracle.OracleH2(P, leaf=leaf, eta=eta, p=p)
+    pl = h2x.Plan(P, leaf=leaf, eta=eta, p=p)
+    assert (pl.n, pl.C, pl.leaves, pl.n_adm, pl.n_near, pl.near_entries, pl.depth) == \
+        (o.n, o.C, o.leaves, o.n_adm, o.n_near, o.near_entries, o.depth)
+    ot = o.tree()
+    np.testing.assert_array_equal(pl.perm(), ot["perm"])
+    cl = pl.clusters()
+    for nm in ("first", "size", "parent", "son0", "son1", "depth"):
+        np.testing.assert_array_equal(cl[nm], ot[nm], err_msg=nm)
+    ob = o.blocks()
+    # oracle lists grouped by row cluster, in block pre-order within a row
+    lists_adm = [(int(ob["t"][b]), int(ob["s"][b])) for b in ob["list_blk"] if ob["adm"][b]]
+    lists_near = [(int(ob["t"][b]), int(ob["s"][b])) for b in ob["list_blk"] if not ob["adm"][b]]
+    pb = pl.blocks()
+    assert list(zip(pb["adm_t"].tolist(), pb["adm_s"].tolist())) == lists_adm
+    assert list(zip(pb["near_t"].tolist(), pb["near_s"].tolist())) == lists_near
+
+
+def test_stats_bytes():
+    P = W.sphere_points(2000, 72)
+    pl = h2x.Plan(P, leaf=32, p=3)
+    k = 27
+    ent = pl.n * k + (pl.C - 1) * k * k + pl.n_adm * k * k
+    assert pl.bytes_operator == [8 * ent, 4 * ent, 2 * ent]
+    assert pl.bytes_near == 8 * pl.near_entries
+
+
+def test_invalid_arguments_rejected():
+    P = W.sphere_points(100, 73)
+    for kw in (dict(p=0), dict(p=9), dict(leaf=0), dict(eta=0.0), dict(ell=-1.0)):
+        with pytest.raises(h2x.H2xError):
+            h2x.Plan(P, **kw)
+    bad = P.copy()
+    bad[3, 1] = np.nan
+    with pytest.raises(h2x.H2xError):
+        h2x.Plan(bad)
+    lib = h2x.load_library()
+    h = C.c_void_p()
+    assert lib.h2x_plan_create(None, 10, None, C.byref(h)) == 1
+    assert b"NULL" in lib.h2x_last_error()
+    # workspace queries on NULL handles return 0 instead of crashing
+    assert lib.h2x_mat_workspace_bytes(None, 0) == 0
+    assert lib.h2x_matmul_workspace_bytes(None, 4) == 0

@@ -1,0 +1,117 @@
+"""GPU block CG (C ABI h2x_block_cg) against the CPU oracle's block CG.
+
+Two FP64 implementations with different summation orders drift apart over many
+iterations, so parity is checked in three ways: the first iterates (fixed
+max_iter) agree to 1e-12 per column; end to end, iteration counts agree within
+one, both true residuals meet the tolerance and the solutions agree within
+10 * kappa * rtol; and the closed-form inverse of the constant kernel.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2509_17257_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _h2x():
+    import paper_2509_17257_amd as h2x
+    return h2x
+
+
+def _colrel(a, b):
+    den = np.linalg.norm(b, axis=0)
+    den[den == 0] = 1.0
+    return (np.linalg.norm(a - b, axis=0) / den).max()
+
+
+@pytest.fixture(scope="module")
+def small():
+    h2x = _h2x()
+    w = W.SMALL
+    P = w.points()
+    o = oracle.OracleH2(P, **w.params())
+    A = h2x.H2Matrix(P, **w.params())
+    return o, A, w.rhs()
+
+
+def _solve(A, B, **kw):
+    h2x = _h2x()
+    Bd = torch.from_numpy(np.ascontiguousarray(B)).cuda()
+    X0 = kw.pop("X0", None)
+    if X0 is not None:
+        X0 = torch.from_numpy(np.ascontiguousarray(X0)).cuda()
+    X, info = h2x.block_cg_solve(A, Bd, X0, **kw)
+    return X.cpu().numpy(), info
+
+
+@pytest.mark.parametrize("iters", [1, 2, 5])
+def test_first_iterates_match(small, iters):
+    o, A, B = small
+    Xo, io = o.block_cg(B, rtol=1e-8, max_iter=iters)
+    Xg, ig = _solve(A, B, rtol=1e-8, max_iter=iters, check_every=1)
+    assert ig.iters == io["iters"] == iters
+    assert _colrel(Xg, Xo) <= 1e-12
+
+
+def test_end_to_end(small):
+    o, A, B = small
+    rtol = 1e-8
+    Xo, io = o.block_cg(B, rtol=rtol)
+    Xg, ig = _solve(A, B, rtol=rtol)
+    assert ig.status == 0 and np.all(ig.col_status == 0)
+    assert abs(ig.iters - io["iters"]) <= 1
+    assert np.all(np.abs(ig.col_iters - io["col_iters"]) <= 1)
+    res = np.linalg.norm(B - o.matmul(Xg), axis=0) / np.linalg.norm(B, axis=0)
+    assert res.max() <= 2 * rtol
+    Ad = o.dense()
+    ev = np.linalg.eigvalsh(Ad)
+    kappa = ev[-1] / ev[0]
+    assert _colrel(Xg, Xo) <= 10 * kappa * rtol
+    assert np.all(ig.col_relres <= rtol)
+
+
+def test_initial_guess_and_freeze(small):
+    o, A, B = small
+    X0 = 0.1 * W.rhs(B.shape[0], B.shape[1], 96)
+    Xg, ig = _solve(A, B, X0=X0, rtol=1e-8)
+    res = np.linalg.norm(B - o.matmul(Xg), axis=0) / np.linalg.norm(B, axis=0)
+    assert res.max() <= 2e-8
+    Xf, iff = _solve(A, B, rtol=1e-8, freeze_converged=True)
+    res = np.linalg.norm(B - o.matmul(Xf), axis=0) / np.linalg.norm(B, axis=0)
+    assert res.max() <= 2e-8
+
+
+def test_constant_kernel_closed_form():
+    h2x = _h2x()
+    n, sigma = 900, 0.8
+    P = W.sphere_points(n, 97)
+    A = h2x.H2Matrix(P, kernel="const", shift=sigma, leaf=32, p=2)
+    B = W.rhs(n, 5, 98)
+    X, info = _solve(A, B, rtol=1e-12, check_every=1)
+    Xcf = (B - B.sum(0, keepdims=True) / (sigma + n)) / sigma
+    assert _colrel(X, Xcf) <= 1e-10
+    assert info.iters <= 2
+
+
+def test_breakdown_and_noconv_reported():
+    h2x = _h2x()
+    P = W.sphere_points(600, 99)
+    A = h2x.H2Matrix(P, leaf=32, p=3, shift=-200.0)
+    B = W.rhs(600, 3, 100)
+    X, info = _solve(A, B, rtol=1e-8, max_iter=300)
+    assert info.status != 0 and np.any(info.col_status != 0)
+    A2 = h2x.H2Matrix(P, leaf=32, p=3)
+    X, info = _solve(A2, B, rtol=1e-14, max_iter=3)
+    assert info.iters == 3 and info.status == 5 and np.all(info.col_status == 2)
+
+
+def test_zero_rhs_column(small):
+    o, A, B = small
+    B = B.copy()
+    B[:, 2] = 0.0
+    Xg, ig = _solve(A, B, rtol=1e-8)
+    assert np.all(Xg[:, 2] == 0.0)
+    assert ig.status == 0

@@ -1,0 +1,145 @@
+"""GPU parity of the H^2 x X product (C ABI h2x_matmul) against the CPU oracle.
+
+Bar (FP64): per column, ||Y_gpu - Y_oracle|| / ||Y_oracle|| <= 1e-12, on the same
+seeded inputs, at sizes that span several tiles and ragged tails, at the full
+FP64 throughput size, and on the edge cases (m = 1, ragged m, leaves larger
+than one tile, no admissible block, a single leaf, alpha/beta, tree order).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2509_17257_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def _h2x():
+    import paper_2509_17257_amd as h2x
+    return h2x
+
+
+def _colrel(a, b):
+    den = np.linalg.norm(b, axis=0)
+    den[den == 0] = 1.0
+    return (np.linalg.norm(a - b, axis=0) / den).max()
+
+
+def _pair(P, **kw):
+    h2x = _h2x()
+    return oracle.OracleH2(P, **kw), h2x.H2Matrix(P, **kw)
+
+
+def _gpu(A, X, **kw):
+    h2x = _h2x()
+    Xd = torch.from_numpy(np.ascontiguousarray(X)).cuda()
+    if "out" in kw and isinstance(kw["out"], np.ndarray):
+        kw["out"] = torch.from_numpy(np.ascontiguousarray(kw["out"])).cuda()
+    Y = h2x.h2_matmul(A, Xd, **kw)
+    torch.cuda.synchronize()
+    return Y.cpu().numpy()
+
+
+CASES = [
+    # name, points, params, m
+    ("small-k27-m4", lambda: W.SMALL.points(), W.SMALL.params(), 4),
+    ("small-k27-m1", lambda: W.SMALL.points(), W.SMALL.params(), 1),
+    ("small-k27-m37", lambda: W.SMALL.points(), W.SMALL.params(), 37),
+    ("sphere-k64-m32", lambda: W.sphere_points(6000, 81), dict(ell=0.5, shift=1.0, eta=1.0, leaf=64, p=4), 32),
+    ("cube-k64-m5", lambda: W.cube_points(7000, 82), dict(ell=0.25, shift=0.5, eta=1.0, leaf=64, p=4), 5),
+    ("cube-k8-leaf100", lambda: W.cube_points(3000, 83), dict(ell=0.3, shift=0.5, eta=1.5, leaf=100, p=2), 3),
+    ("line-k27", lambda: W.line_points(2000, 84), dict(ell=0.2, shift=1.0, eta=1.0, leaf=16, p=3), 7),
+    ("sphere-k125-m9", lambda: W.sphere_points(3000, 85), dict(ell=0.5, shift=1.0, eta=1.0, leaf=64, p=5), 9),
+]
+
+
+@pytest.mark.parametrize("name,pts,prm,m", CASES, ids=[c[0] for c in CASES])
+def test_matmul_matches_oracle(name, pts, prm, m):
+    P = pts()
+    o, A = _pair(P, **prm)
+    X = W.rhs(P.shape[0], m, 90 + m)
+    ref = o.matmul(X)
+    got = _gpu(A, X)
+    err = _colrel(got, ref)
+    print(f"{name}: n={P.shape[0]} adm={o.n_adm} near={o.n_near} max col rel err={err:.3e}")
+    assert err <= TOL
+
+
+def test_polynomial_kernel_equals_dense():
+    P = W.sphere_points(3000, 86)
+    h2x = _h2x()
+    A = h2x.H2Matrix(P, kernel="poly", shift=0.75, leaf=32, p=3)
+    X = W.rhs(3000, 6, 87)
+    ref = oracle.kernel_matrix(P, kernel="poly", shift=0.75) @ X
+    assert _colrel(_gpu(A, X), ref) <= TOL
+
+
+@pytest.mark.parametrize("kw", [dict(leaf=16, eta=1e-12), dict(leaf=1000)])
+def test_dense_only_cases(kw):
+    P = W.sphere_points(700, 88)
+    h2x = _h2x()
+    A = h2x.H2Matrix(P, ell=0.5, shift=1.0, p=3, **kw)
+    assert A.plan.n_adm == 0
+    X = W.rhs(700, 33, 89)
+    ref = oracle.kernel_matrix(P, ell=0.5, shift=1.0) @ X
+    assert _colrel(_gpu(A, X), ref) <= TOL
+
+
+def test_alpha_beta_and_tree_order():
+    P = W.SMALL.points()
+    o, A = _pair(P, **W.SMALL.params())
+    X = W.rhs(P.shape[0], 6, 91)
+    Y0 = W.rhs(P.shape[0], 6, 92)
+    ref = o.matmul(X, alpha=-0.7, beta=1.3, Y=Y0)
+    got = _gpu(A, X, alpha=-0.7, beta=1.3, out=Y0.copy())
+    assert _colrel(got, ref) <= TOL
+    # beta = 0 ignores NaN in the output buffer
+    nanY = np.full_like(Y0, np.nan)
+    got = _gpu(A, X, alpha=2.0, beta=0.0, out=nanY)
+    assert _colrel(got, 2.0 * o.matmul(X)) <= TOL
+    # tree-ordered input and output
+    perm = A.plan.perm()
+    got_t = _gpu(A, X[perm], tree_order=True)
+    back = np.empty_like(got_t)
+    back[perm] = got_t
+    assert _colrel(back, o.matmul(X)) <= TOL
+
+
+def test_bitwise_deterministic_and_column_independent():
+    P = W.sphere_points(5000, 93)
+    h2x = _h2x()
+    A = h2x.H2Matrix(P, leaf=64, p=4)
+    X = W.rhs(5000, 16, 94)
+    a = _gpu(A, X)
+    b = _gpu(A, X)
+    np.testing.assert_array_equal(a, b)
+    for i in (0, 7, 15):
+        c = _gpu(A, X[:, i:i + 1].copy())
+        assert _colrel(c, a[:, i:i + 1]) <= 1e-14
+
+
+def test_full_fp64_workload():
+    """The FP64 throughput workload at full size (n = 65536, k = 64, m = 32)."""
+    w = W.FP64
+    P = w.points()
+    o, A = _pair(P, **w.params())
+    X = w.rhs()
+    ref = o.matmul(X)
+    got = _gpu(A, X)
+    err = _colrel(got, ref)
+    print(f"{w.name}: adm={o.n_adm} near={o.n_near} max col rel err={err:.3e}")
+    assert err <= TOL
+
+
+def test_invalid_arguments_on_gpu():
+    h2x = _h2x()
+    P = W.sphere_points(500, 95)
+    A = h2x.H2Matrix(P, leaf=32, p=3)
+    X = torch.zeros((500, 4), dtype=torch.float64, device="cuda")
+    with pytest.raises(h2x.H2xError):
+        h2x.h2_matmul(A, X, out=X)  # X and Y overlap
+    with pytest.raises(ValueError):
+        h2x.h2_matmul(A, torch.zeros((499, 4), dtype=torch.float64, device="cuda"))

@@ -170,6 +170,7 @@ h2x_status h2x_mat_create(const h2x_plan *plan, h2x_prec storage, void *dev_ws, 
     up(d.adm_ptr, P.adm_ptr);
     up(d.adm_col, P.adm_col);
     up(d.adm_row, adm_row);
+    up(d.cpl_order, P.cpl_order);
     up(d.near_ptr, P.near_ptr);
     up(d.near_col, P.near_col);
     up(d.near_row, near_row);

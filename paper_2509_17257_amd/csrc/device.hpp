@@ -28,6 +28,7 @@ struct DevMat {
     int64_t *adm_ptr = nullptr;  // C + 1
     int32_t *adm_col = nullptr;  // n_adm
     int32_t *adm_row = nullptr;  // n_adm (row cluster of each block)
+    int32_t *cpl_order = nullptr;  // C, launch order of the coupling rows
     int64_t *near_ptr = nullptr; // L + 1
     int32_t *near_col = nullptr; // n_near
     int32_t *near_row = nullptr; // n_near (row leaf cluster)

@@ -171,6 +171,7 @@ size_t mat_layout(const Plan &P, h2x_prec storage, DevMat *dm, char *base) {
     d.n = n; d.C = C; d.L = L; d.k = k; d.p = P.p; d.depth_max = P.depth_max; d.max_leaf = P.max_leaf;
     d.n_adm = na; d.n_near = nn; d.near_entries = P.near_entries; d.storage = storage;
     d.kernel = P.prm.kernel; d.ell = P.prm.ell; d.shift = P.prm.shift; d.plan = &P;
+    d.swz = (storage == H2X_F64 && k == 64) ? 1 : 0;
     d.first = carve<int32_t>(cur, base, C);
     d.size = carve<int32_t>(cur, base, C);
     d.parent = carve<int32_t>(cur, base, C);
@@ -182,6 +183,7 @@ size_t mat_layout(const Plan &P, h2x_prec storage, DevMat *dm, char *base) {
     d.adm_ptr = carve<int64_t>(cur, base, C + 1);
     d.adm_col = carve<int32_t>(cur, base, na + 1);
     d.adm_row = carve<int32_t>(cur, base, na + 1);
+    d.cpl_order = carve<int32_t>(cur, base, C);
     d.near_ptr = carve<int64_t>(cur, base, L + 1);
     d.near_col = carve<int32_t>(cur, base, nn + 1);
     d.near_row = carve<int32_t>(cur, base, nn + 1);

@@ -129,7 +129,8 @@ __global__ __launch_bounds__(256) void k_up(int k, int64_t m, const int32_t *__r
 template <typename T, typename Acc>
 __global__ __launch_bounds__(256) void k_coupling(int k, int64_t m, const int64_t *__restrict__ adm_ptr,
                                                   const int32_t *__restrict__ adm_col, const T *__restrict__ S,
-                                                  const Acc *__restrict__ xh, Acc *__restrict__ yh, int64_t ldh) {
+                                                  int swz, const Acc *__restrict__ xh, Acc *__restrict__ yh,
+                                                  int64_t ldh) {
     __shared__ Acc As[TR][TR + 1];
     __shared__ Acc Bs[TR][TC];
     const int32_t t = blockIdx.x;
@@ -146,7 +147,7 @@ __global__ __launch_bounds__(256) void k_coupling(int k, int64_t m, const int64_
                 const int uc = min(TR, k - u0);
                 for (int e = tid; e < TR * TR; e += 256) {
                     const int nu = e / TR, mu = e % TR;
-                    As[nu][mu] = (mu < uc && n0 + nu < k) ? ld_op<T, Acc>(&Sb[(int64_t)(n0 + nu) * k + u0 + mu]) : Acc(0);
+                    As[nu][mu] = (mu < uc && n0 + nu < k) ? ld_op<T, Acc>(&Sb[s_index(swz, k, n0 + nu, u0 + mu)]) : Acc(0);
                 }
                 for (int e = tid; e < TR * TC; e += 256) {
                     const int mu = e / TC, jj = e % TC;
@@ -317,7 +318,7 @@ hipError_t matmul_typed(const DevMat &dm, int64_t m, double alpha, const double 
     mark(2);
     if (!launch_coupling_fast<T, Acc>(dm, m, xh, yh, ldh, st))
         hipLaunchKernelGGL((k_coupling<T, Acc>), dim3(dm.C, gy), dim3(256), 0, st, dm.k, m, dm.adm_ptr, dm.adm_col, S,
-                           xh, yh, ldh);
+                           dm.swz, xh, yh, ldh);
     mark(3);
     for (int d = 1; d <= dm.depth_max; ++d) {
         const int32_t b = P.lvl_ptr[d], e = P.lvl_ptr[d + 1];

@@ -1,15 +1,163 @@
-// Matrix-core (MFMA) coupling kernel for the FP64 operator.
+// Matrix-core (MFMA) coupling kernel for the FP64 operator with k = 64:
+//   y_t = sum_{(t,s) in C_t, admissible} S_b x_s     for every row cluster t.
+//
+// One work-group (4 waves) owns one row cluster t and a slab of up to 64
+// columns; wave w owns rows 16w..16w+15 of y_t.  For each block of the list,
+// the work-group stages x_s (64 x 16*NJ) in LDS (double-buffered, next block
+// loaded while the current one is multiplied) and each wave streams its
+// 16 x 64 slice of S_b straight from HBM into registers (one 16-byte load per
+// lane per pair of k-steps; S is stored in that operand order, see s_index),
+// also one block ahead.  v_mfma_f64_16x16x4f64 accumulates in registers; y_t
+// is written once.  No atomics: each row cluster has exactly one owner.
+//
+// Work-groups are mapped to rows so that each XCD (work-groups are dealt to
+// the 8 XCDs round-robin) gets one contiguous eighth of the rows in tree
+// order: neighbouring row clusters share most column clusters, so their x_s
+// reads hit the XCD's L2.  Within an eighth, longer lists go first.
 #pragma once
+
+#include <algorithm>
+#include <type_traits>
 
 #include "device.hpp"
 
 namespace h2x {
 
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+constexpr int kMfmaK = 64;
+
+template <int NJ>
+__global__ __launch_bounds__(256) void k_coupling_mfma_f64(int64_t m, int32_t C, int32_t rows_per_xcd,
+                                                           const int32_t *__restrict__ order,
+                                                           const int64_t *__restrict__ adm_ptr,
+                                                           const int32_t *__restrict__ adm_col,
+                                                           const double *__restrict__ S,
+                                                           const double *__restrict__ xh, double *__restrict__ yh,
+                                                           int64_t ldh) {
+    constexpr int MC = 16 * NJ;   // columns per work-group
+    constexpr int LDX = MC + 1;   // padded LDS row
+    __shared__ double xs[2][kMfmaK * LDX];
+    const int slot = (blockIdx.x & 7) * rows_per_xcd + (blockIdx.x >> 3);
+    if (slot >= C) return;
+    const int32_t t = order[slot];
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    const int lr = lane & 15, lq = lane >> 4;
+    const int64_t j0 = (int64_t)blockIdx.y * MC;
+    const int mc = (int)min<int64_t>(MC, m - j0);
+    const int64_t b0 = adm_ptr[t], b1 = adm_ptr[t + 1];
+
+    dbl4 acc[NJ];
+#pragma unroll
+    for (int J = 0; J < NJ; ++J) acc[J] = dbl4{0.0, 0.0, 0.0, 0.0};
+
+    if (b1 > b0) {
+        // x_s staging: element e = row * MC + col, MC * 64 elements over 256 threads
+        constexpr int XPT = (kMfmaK * MC) / 256;  // elements per thread (4 * NJ)
+        double xv[XPT];
+        auto load_x = [&](int32_t s) {
+            const double *src = xh + (int64_t)s * kMfmaK * ldh + j0;
+#pragma unroll
+            for (int u = 0; u < XPT; ++u) {
+                const int e = tid + 256 * u, r = e / MC, c = e % MC;
+                xv[u] = c < mc ? src[(int64_t)r * ldh + c] : 0.0;
+            }
+        };
+        auto store_x = [&](int buf) {
+#pragma unroll
+            for (int u = 0; u < XPT; ++u) {
+                const int e = tid + 256 * u, r = e / MC, c = e % MC;
+                xs[buf][r * LDX + c] = xv[u];
+            }
+        };
+        typedef double dbl2 __attribute__((ext_vector_type(2)));
+        dbl2 sa[8], sn[8];
+        auto load_s = [&](int64_t b, dbl2 *dst) {
+            const dbl2 *src = (const dbl2 *)(S + b * kMfmaK * kMfmaK) + (int64_t)w * 8 * 64 + lane;
+#pragma unroll
+            for (int kk2 = 0; kk2 < 8; ++kk2) dst[kk2] = __builtin_nontemporal_load(src + kk2 * 64);
+        };
+
+        load_x(adm_col[b0]);
+        load_s(b0, sa);
+        store_x(0);
+        __syncthreads();
+        for (int64_t b = b0; b < b1; ++b) {
+            const int buf = (int)((b - b0) & 1);
+            const bool more = b + 1 < b1;
+            if (more) {
+                load_x(adm_col[b + 1]);
+                load_s(b + 1, sn);
+            }
+            const double *xb = xs[buf];
+#pragma unroll
+            for (int kk2 = 0; kk2 < 8; ++kk2) {
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const double a = h ? sa[kk2].y : sa[kk2].x;
+                    const int krow = 4 * (2 * kk2 + h) + lq;
+#pragma unroll
+                    for (int J = 0; J < NJ; ++J) {
+                        const double bv = xb[krow * LDX + 16 * J + lr];
+                        acc[J] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc[J], 0, 0, 0);
+                    }
+                }
+            }
+            if (more) {
+                store_x(buf ^ 1);
+#pragma unroll
+                for (int kk2 = 0; kk2 < 8; ++kk2) sa[kk2] = sn[kk2];
+            }
+            __syncthreads();
+        }
+    }
+    // D layout of the 16x16x4 f64 MFMA: lane l, register r -> row l / 16 + 4 r, column l % 16
+#pragma unroll
+    for (int J = 0; J < NJ; ++J) {
+        const int col = 16 * J + lr;
+        if (col < mc) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = 16 * w + lq + 4 * r;
+                yh[((int64_t)t * kMfmaK + row) * ldh + j0 + col] = acc[J][r];
+            }
+        }
+    }
+}
+
 // Launches the matrix-core coupling stage when the operator's layout supports
 // it; returns false (launching nothing) otherwise.
 template <typename T, typename Acc>
-bool launch_coupling_fast(const DevMat &, int64_t, const Acc *, Acc *, int64_t, hipStream_t) {
-    return false;
+bool launch_coupling_fast(const DevMat &dm, int64_t m, const Acc *xh, Acc *yh, int64_t ldh, hipStream_t st) {
+    if constexpr (!std::is_same<T, double>::value || !std::is_same<Acc, double>::value) {
+        return false;
+    } else {
+        if (dm.swz != 1 || dm.k != kMfmaK || !dm.cpl_order) return false;
+        const int nj = (int)std::min<int64_t>(4, (m + 15) / 16);
+        const int mcols = 16 * nj;
+        const int32_t rpx = (dm.C + 7) / 8;
+        const dim3 grid((unsigned)(8 * rpx), (unsigned)((m + mcols - 1) / mcols));
+        const double *S = (const double *)dm.S;
+        switch (nj) {
+            case 1:
+                hipLaunchKernelGGL(k_coupling_mfma_f64<1>, grid, dim3(256), 0, st, m, dm.C, rpx, dm.cpl_order,
+                                   dm.adm_ptr, dm.adm_col, S, xh, yh, ldh);
+                break;
+            case 2:
+                hipLaunchKernelGGL(k_coupling_mfma_f64<2>, grid, dim3(256), 0, st, m, dm.C, rpx, dm.cpl_order,
+                                   dm.adm_ptr, dm.adm_col, S, xh, yh, ldh);
+                break;
+            case 3:
+                hipLaunchKernelGGL(k_coupling_mfma_f64<3>, grid, dim3(256), 0, st, m, dm.C, rpx, dm.cpl_order,
+                                   dm.adm_ptr, dm.adm_col, S, xh, yh, ldh);
+                break;
+            default:
+                hipLaunchKernelGGL(k_coupling_mfma_f64<4>, grid, dim3(256), 0, st, m, dm.C, rpx, dm.cpl_order,
+                                   dm.adm_ptr, dm.adm_col, S, xh, yh, ldh);
+                break;
+        }
+        return true;
+    }
 }
 
 }  // namespace h2x

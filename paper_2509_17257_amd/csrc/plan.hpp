@@ -42,6 +42,10 @@ struct Plan {
     std::vector<int64_t> near_off;  // offset of the block in the near-field array
     int64_t near_entries = 0;
     int32_t max_leaf = 0;           // largest leaf size
+
+    // launch order of the row clusters in the coupling stage: the rows are cut
+    // into 8 contiguous eighths (one per XCD), longest list first within each
+    std::vector<int32_t> cpl_order; // C
 };
 
 Plan *build_plan(const double *pts, int64_t n, const h2x_params &prm, std::string &err);

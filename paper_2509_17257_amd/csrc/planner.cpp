@@ -203,6 +203,16 @@ Plan *build_plan(const double *pts, int64_t n, const h2x_params &prm, std::strin
         }
     }
     P->near_entries = off;
+
+    const int32_t rpx = (C + 7) / 8;
+    P->cpl_order.resize(C);
+    for (int32_t c = 0; c < C; ++c) P->cpl_order[c] = c;
+    for (int32_t x = 0; x < 8; ++x) {
+        const int32_t lo = std::min(C, x * rpx), hi = std::min(C, (x + 1) * rpx);
+        std::stable_sort(P->cpl_order.begin() + lo, P->cpl_order.begin() + hi, [&](int32_t a, int32_t b) {
+            return P->adm_ptr[a + 1] - P->adm_ptr[a] > P->adm_ptr[b + 1] - P->adm_ptr[b];
+        });
+    }
     (void)err;
     return P;
 }

@@ -83,6 +83,8 @@ def main():
     ap.add_argument("--workload", default="sphere-n65536-k64-m32")
     ap.add_argument("--cg", type=int, default=1, help="also time block CG to 1e-8")
     ap.add_argument("--cpu-baseline-s", type=float, default=12.0, help="0 disables the oracle timing")
+    ap.add_argument("--copy-calibration-gib", type=float, default=0.0,
+                    help="only run a plain device copy of this many GiB (to scale HBM traffic counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -93,6 +95,16 @@ def main():
 
     import paper_2509_17257_amd as h2x
     from paper_2509_17257_amd import workloads as W
+
+    if args.copy_calibration_gib > 0:
+        nbytes = int(args.copy_calibration_gib * 2**30) // 8 * 8
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": nbytes, "copies": 3}), flush=True)
+        return
 
     w = W.WORKLOADS[args.workload]
     dev = torch.device("cuda:0")

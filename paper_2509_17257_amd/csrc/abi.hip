@@ -174,7 +174,8 @@ h2x_status h2x_mat_create(const h2x_plan *plan, h2x_prec storage, void *dev_ws, 
     up(d.near_ptr, P.near_ptr);
     up(d.near_col, P.near_col);
     up(d.near_row, near_row);
-    up(d.near_off, P.near_off);
+    up(d.near_off, d.near_t ? P.near_off_t : P.near_off);
+    up(d.vt_off, P.vt_off);
     up(d.perm, P.perm);
     up(d.pts, P.pts_tree);
     up(d.box, P.box);

@@ -18,7 +18,8 @@ struct DevMat {
     int32_t C = 0, L = 0, k = 0, p = 0, depth_max = 0, max_leaf = 0;
     int64_t n_adm = 0, n_near = 0, near_entries = 0;
     h2x_prec storage = H2X_F64;
-    int swz = 0;  // coupling-matrix layout (see s_index)
+    int swz = 0;     // coupling-matrix layout (see s_index)
+    int near_t = 0;  // near-field blocks stored transposed (|s| x |t| row-major)
     int kernel = 0;
     double ell = 0, shift = 0;
 
@@ -32,7 +33,8 @@ struct DevMat {
     int64_t *near_ptr = nullptr; // L + 1
     int32_t *near_col = nullptr; // n_near
     int32_t *near_row = nullptr; // n_near (row leaf cluster)
-    int64_t *near_off = nullptr; // n_near
+    int64_t *near_off = nullptr; // n_near (offsets in the layout selected by near_t)
+    int64_t *vt_off = nullptr;   // L, offsets of the transposed leaf bases (matrix-core layout)
     int64_t *perm = nullptr;     // n
     double *pts = nullptr;       // n x 3 tree order
     double *box = nullptr;       // C x 6
@@ -42,7 +44,8 @@ struct DevMat {
     void *V = nullptr;   // n x k
     void *E = nullptr;   // C x k x k
     void *S = nullptr;   // n_adm x k x k
-    void *N = nullptr;   // near_entries
+    void *N = nullptr;   // near field (row-major blocks, or transposed and padded when near_t)
+    void *Vt = nullptr;  // transposed leaf bases (matrix-core layout only)
 
     // host copies of the level tables (launch sizes)
     const Plan *plan = nullptr;

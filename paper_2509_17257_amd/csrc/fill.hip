@@ -67,7 +67,8 @@ __device__ inline void nodes1d(const double *nodes, int32_t c, int p, int d, dou
 template <typename T>
 __global__ void k_fill_V(int p, const int32_t *__restrict__ leaves, const int32_t *__restrict__ first,
                          const int32_t *__restrict__ size, const double *__restrict__ pts,
-                         const double *__restrict__ nodes, T *__restrict__ V) {
+                         const double *__restrict__ nodes, T *__restrict__ V, T *__restrict__ Vt,
+                         const int64_t *__restrict__ vt_off) {
     const int k = p * p * p;
     const int32_t t = leaves[blockIdx.x];
     __shared__ double nd[3][16];
@@ -85,6 +86,13 @@ __global__ void k_fill_V(int p, const int32_t *__restrict__ leaves, const int32_
         double v = lagrange1(nd[0], p, nu % p, x[0]) * lagrange1(nd[1], p, (nu / p) % p, x[1]) *
                    lagrange1(nd[2], p, nu / (p * p), x[2]);
         V[i * k + nu] = from_double<T>(v);
+        if (Vt) {
+            // transposed copy: k x nt2 (rows padded to even length, padding zero)
+            const int64_t nt2 = rows + (rows & 1), il = i - first[t];
+            T *vt = Vt + vt_off[blockIdx.x];
+            vt[nu * nt2 + il] = from_double<T>(v);
+            if ((rows & 1) && il == rows - 1) vt[nu * nt2 + rows] = from_double<T>(0.0);
+        }
     }
 }
 
@@ -125,22 +133,26 @@ __global__ void k_fill_S(int k, int kernel, double ell, const int32_t *__restric
     }
 }
 
-// N_(t,s)[i, j] = g(x_i, x_j) + shift [i == j], row-major |t| x |s|
+// N_(t,s)[i, j] = g(x_i, x_j) + shift [i == j], row-major |t| x |s|, or stored
+// transposed when trans != 0: |s| rows of length |t| padded to even, padding zero
 template <typename TN>
 __global__ void k_fill_N(int kernel, double ell, double shift, const int32_t *__restrict__ near_row,
                          const int32_t *__restrict__ near_col, const int64_t *__restrict__ near_off,
                          const int32_t *__restrict__ first, const int32_t *__restrict__ size,
-                         const double *__restrict__ pts, TN *__restrict__ N) {
+                         const double *__restrict__ pts, TN *__restrict__ N, int trans) {
     const int64_t q = blockIdx.x;
     const int32_t t = near_row[q], s = near_col[q];
     const int64_t nt = size[t], ns = size[s], ft = first[t], fs = first[s];
     TN *Nb = N + near_off[q];
+    const int64_t nt2 = nt + (nt & 1);
     for (int64_t e = threadIdx.x; e < nt * ns; e += blockDim.x) {
-        const int64_t i = ft + e / ns, j = fs + e % ns;
+        const int64_t il = e / ns, jl = e % ns, i = ft + il, j = fs + jl;
         double v = kernel_g(kernel, ell, &pts[3 * i], &pts[3 * j]);
         if (i == j) v += shift;
-        Nb[e] = (TN)v;
+        Nb[trans ? jl * nt2 + il : e] = (TN)v;
     }
+    if (trans && (nt & 1))
+        for (int64_t jl = threadIdx.x; jl < ns; jl += blockDim.x) Nb[jl * nt2 + nt] = (TN)0;
 }
 
 template <typename T, typename TN>
@@ -149,7 +161,7 @@ hipError_t fill_typed(const DevMat &dm, hipStream_t st) {
     hipLaunchKernelGGL(k_nodes, dim3((unsigned)((ck + 255) / 256)), dim3(256), 0, st, dm.C, dm.p, dm.box, dm.nodes);
     if (dm.L > 0)
         hipLaunchKernelGGL(k_fill_V<T>, dim3(dm.L), dim3(256), 0, st, dm.p, dm.leaves, dm.first, dm.size, dm.pts,
-                           dm.nodes, (T *)dm.V);
+                           dm.nodes, (T *)dm.V, (T *)dm.Vt, dm.vt_off);
     if (dm.C > 1)
         hipLaunchKernelGGL(k_fill_E<T>, dim3(dm.C - 1), dim3(256), 0, st, dm.p, dm.parent, dm.nodes, (T *)dm.E);
     if (dm.n_adm > 0)
@@ -157,7 +169,8 @@ hipError_t fill_typed(const DevMat &dm, hipStream_t st) {
                            dm.adm_row, dm.adm_col, dm.nodes, (T *)dm.S, s_swizzled(dm));
     if (dm.n_near > 0)
         hipLaunchKernelGGL(k_fill_N<TN>, dim3((unsigned)dm.n_near), dim3(256), 0, st, dm.kernel, dm.ell, dm.shift,
-                           dm.near_row, dm.near_col, dm.near_off, dm.first, dm.size, dm.pts, (TN *)dm.N);
+                           dm.near_row, dm.near_col, dm.near_off, dm.first, dm.size, dm.pts, (TN *)dm.N,
+                           dm.near_t);
     return hipGetLastError();
 }
 
@@ -172,6 +185,7 @@ size_t mat_layout(const Plan &P, h2x_prec storage, DevMat *dm, char *base) {
     d.n_adm = na; d.n_near = nn; d.near_entries = P.near_entries; d.storage = storage;
     d.kernel = P.prm.kernel; d.ell = P.prm.ell; d.shift = P.prm.shift; d.plan = &P;
     d.swz = (storage == H2X_F64 && k == 64) ? 1 : 0;
+    d.near_t = d.swz;
     d.first = carve<int32_t>(cur, base, C);
     d.size = carve<int32_t>(cur, base, C);
     d.parent = carve<int32_t>(cur, base, C);
@@ -188,6 +202,7 @@ size_t mat_layout(const Plan &P, h2x_prec storage, DevMat *dm, char *base) {
     d.near_col = carve<int32_t>(cur, base, nn + 1);
     d.near_row = carve<int32_t>(cur, base, nn + 1);
     d.near_off = carve<int64_t>(cur, base, nn + 1);
+    d.vt_off = carve<int64_t>(cur, base, L + 1);
     d.perm = carve<int64_t>(cur, base, n);
     d.pts = carve<double>(cur, base, 3 * n);
     d.box = carve<double>(cur, base, 6 * (size_t)C);
@@ -197,7 +212,9 @@ size_t mat_layout(const Plan &P, h2x_prec storage, DevMat *dm, char *base) {
     d.V = carve<char>(cur, base, es * (size_t)n * k);
     d.E = carve<char>(cur, base, es * (size_t)C * k * k);
     d.S = carve<char>(cur, base, es * (size_t)(na ? na : 1) * k * k);
-    d.N = carve<char>(cur, base, ens * (size_t)(P.near_entries ? P.near_entries : 1));
+    const int64_t nstored = d.near_t ? P.near_entries_t : P.near_entries;
+    d.N = carve<char>(cur, base, ens * (size_t)(nstored ? nstored : 1) + 16);
+    d.Vt = d.near_t ? carve<char>(cur, base, es * (size_t)P.vt_entries) : nullptr;
     if (dm) *dm = d;
     return align_up(cur);
 }

@@ -11,8 +11,12 @@
 // Every stage is a batch of small GEMMs.  This file holds the generic kernels
 // (any rank k, any leaf size, any m): 256 threads stage 64 x 64 operand tiles
 // and 64 x 32 column tiles in LDS, each thread accumulates 8 outputs.
+#include <functional>
+#include <type_traits>
+
 #include "device.hpp"
 #include "matmul_mfma.hpp"
+#include "stages_mfma.hpp"
 #include "types.hpp"
 
 namespace h2x {
@@ -217,7 +221,8 @@ __global__ __launch_bounds__(256) void k_leaf_near(int k, int64_t m, const int32
                                                    const int32_t *__restrict__ near_col,
                                                    const int64_t *__restrict__ near_off, const TN *__restrict__ N,
                                                    const double *__restrict__ X, int64_t ldx, double alpha,
-                                                   double beta, double *__restrict__ Y, int64_t ldy, int tree_order) {
+                                                   double beta, double *__restrict__ Y, int64_t ldy, int tree_order,
+                                                   int near_t) {
     __shared__ Acc As[TR][TR + 1];
     __shared__ Acc Bs[TR][TC];
     const int32_t l = blockIdx.x;
@@ -255,7 +260,8 @@ __global__ __launch_bounds__(256) void k_leaf_near(int k, int64_t m, const int32
                 const int cc = min(TR, ns - c0);
                 for (int e = tid; e < TR * TR; e += 256) {
                     const int i = e / TR, c = e % TR;
-                    As[i][c] = (i < ic && c < cc) ? ld_op<TN, Acc>(&Nb[(int64_t)(i0 + i) * ns + c0 + c]) : Acc(0);
+                    const int64_t o = near_t ? (int64_t)(c0 + c) * (nt + (nt & 1)) + i0 + i : (int64_t)(i0 + i) * ns + c0 + c;
+                    As[i][c] = (i < ic && c < cc) ? ld_op<TN, Acc>(&Nb[o]) : Acc(0);
                 }
                 for (int e = tid; e < TR * TC; e += 256) {
                     const int c = e / TC, jj = e % TC;
@@ -286,9 +292,57 @@ __global__ __launch_bounds__(256) void k_leaf_near(int k, int64_t m, const int32
     }
 }
 
+inline int64_t even_ld(int64_t m) { return m + (m & 1); }
+
+// All five stages on the matrix cores (FP64 operator, k = 64).
+template <int NJ>
+void matmul_mfma_f64(const DevMat &dm, int64_t m, double alpha, const double *X, int64_t ldx, double beta, double *Y,
+                     int64_t ldy, int to, double *xh, double *yh, int64_t ldh, double *xt_ws, hipStream_t st,
+                     const std::function<void(int)> &mark) {
+    const Plan &P = *dm.plan;
+    const unsigned gy = (unsigned)((m + 16 * NJ - 1) / (16 * NJ));
+    constexpr int NP = NJ > 2 ? 2 : 1;  // leaf stage: 32 or 64 columns per work-group
+    const double *V = (const double *)dm.V, *E = (const double *)dm.E;
+    mark(0);
+    // the leaf stage reads X in tree order, 16 bytes per lane: copy it unless it already is
+    const double *Xt = X;
+    int64_t ldxt = ldx;
+    if (!to || (ldx & 1) || ((uintptr_t)X & 15)) {
+        ldxt = even_ld(m);
+        const int64_t cnt = dm.n * ldxt;
+        hipLaunchKernelGGL(mfma::k_gather, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, dm.n, m,
+                           to ? nullptr : dm.perm, X, ldx, xt_ws, ldxt);
+        Xt = xt_ws;
+    }
+    hipLaunchKernelGGL(mfma::k_fwd_leaf<NJ>, dim3(dm.L, gy), dim3(256), 0, st, m, dm.leaves, dm.first, dm.size,
+                       dm.perm, V, Xt, ldxt, 1, xh, ldh);
+    mark(1);
+    for (int d = dm.depth_max - 1; d >= 0; --d) {
+        const int32_t b = P.lvl_inner_ptr[d], e = P.lvl_inner_ptr[d + 1];
+        if (e > b)
+            hipLaunchKernelGGL(mfma::k_up<NJ>, dim3(e - b, gy), dim3(256), 0, st, m, dm.lvl_inner + b, dm.son0,
+                               dm.son1, E, xh, ldh);
+    }
+    mark(2);
+    launch_coupling_fast<double, double>(dm, m, xh, yh, ldh, st);
+    mark(3);
+    for (int d = 1; d <= dm.depth_max; ++d) {
+        const int32_t b = P.lvl_ptr[d], e = P.lvl_ptr[d + 1];
+        if (e > b)
+            hipLaunchKernelGGL(mfma::k_down<NJ>, dim3(e - b, gy), dim3(256), 0, st, m, dm.lvl_all + b, dm.parent, E,
+                               yh, ldh);
+    }
+    mark(4);
+    const unsigned gl = (unsigned)((m + 32 * NP - 1) / (32 * NP));
+    hipLaunchKernelGGL(mfma::k_leaf_direct<NP>, dim3(8 * ((dm.L + 7) / 8), gl), dim3(256), 0, st, m, dm.L, dm.leaves,
+                       dm.first, dm.size, dm.perm, (const double *)dm.Vt, dm.vt_off, yh, ldh, dm.near_ptr,
+                       dm.near_col, dm.near_off, (const double *)dm.N, Xt, ldxt, alpha, beta, Y, ldy, to, 1);
+    mark(5);
+}
+
 template <typename Acc>
 size_t hat_bytes(const DevMat &dm, int64_t m) {
-    return align_up(sizeof(Acc) * (size_t)dm.C * dm.k * (size_t)m);
+    return align_up(sizeof(Acc) * (size_t)dm.C * dm.k * (size_t)even_ld(m));
 }
 
 template <typename T, typename TN, typename Acc>
@@ -298,12 +352,26 @@ hipError_t matmul_typed(const DevMat &dm, int64_t m, double alpha, const double 
         if (ev) (void)hipEventRecord(ev[i], st);
     };
     const Plan &P = *dm.plan;
-    const int64_t ldh = m;
+    const int64_t ldh = (dm.swz == 1) ? even_ld(m) : m;
     Acc *xh = (Acc *)ws;
     Acc *yh = (Acc *)(ws + hat_bytes<Acc>(dm, m));
     const unsigned gy = (unsigned)((m + TC - 1) / TC);
     const int to = tree_order ? 1 : 0;
     const T *V = (const T *)dm.V, *E = (const T *)dm.E, *S = (const T *)dm.S;
+
+    if constexpr (std::is_same<T, double>::value && std::is_same<Acc, double>::value) {
+        if (dm.swz == 1 && dm.k == mfma::K) {
+            const std::function<void(int)> mk = mark;
+            double *xt = (double *)(ws + 2 * hat_bytes<Acc>(dm, m));
+            switch ((int)std::min<int64_t>(4, (m + 15) / 16)) {
+                case 1: matmul_mfma_f64<1>(dm, m, alpha, X, ldx, beta, Y, ldy, to, xh, yh, ldh, xt, st, mk); break;
+                case 2: matmul_mfma_f64<2>(dm, m, alpha, X, ldx, beta, Y, ldy, to, xh, yh, ldh, xt, st, mk); break;
+                case 3: matmul_mfma_f64<3>(dm, m, alpha, X, ldx, beta, Y, ldy, to, xh, yh, ldh, xt, st, mk); break;
+                default: matmul_mfma_f64<4>(dm, m, alpha, X, ldx, beta, Y, ldy, to, xh, yh, ldh, xt, st, mk); break;
+            }
+            return hipGetLastError();
+        }
+    }
 
     mark(0);
     hipLaunchKernelGGL((k_fwd_leaf<T, Acc>), dim3(dm.L, gy), dim3(256), 0, st, dm.k, m, dm.leaves, dm.first, dm.size,
@@ -329,7 +397,7 @@ hipError_t matmul_typed(const DevMat &dm, int64_t m, double alpha, const double 
     mark(4);
     hipLaunchKernelGGL((k_leaf_near<T, TN, Acc>), dim3(dm.L, gy), dim3(256), 0, st, dm.k, m, dm.leaves, dm.first,
                        dm.size, dm.perm, V, yh, ldh, dm.near_ptr, dm.near_col, dm.near_off, (const TN *)dm.N, X, ldx,
-                       alpha, beta, Y, ldy, to);
+                       alpha, beta, Y, ldy, to, dm.near_t);
     mark(5);
     return hipGetLastError();
 }
@@ -337,7 +405,8 @@ hipError_t matmul_typed(const DevMat &dm, int64_t m, double alpha, const double 
 }  // namespace
 
 size_t matmul_ws_bytes(const DevMat &dm, int64_t m) {
-    if (dm.storage == H2X_F64) return 2 * hat_bytes<double>(dm, m);
+    // x-hat, y-hat, and the tree-ordered copy of X used by the matrix-core path
+    if (dm.storage == H2X_F64) return 2 * hat_bytes<double>(dm, m) + align_up(sizeof(double) * (size_t)dm.n * even_ld(m));
     return 2 * hat_bytes<float>(dm, m);
 }
 

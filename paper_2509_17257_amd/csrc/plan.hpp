@@ -41,6 +41,12 @@ struct Plan {
     std::vector<int32_t> near_col;  // column cluster id
     std::vector<int64_t> near_off;  // offset of the block in the near-field array
     int64_t near_entries = 0;
+    // matrix-core layout: near blocks stored transposed with rows padded to an
+    // even length, and a per-leaf transposed copy of the leaf basis (k x |t| padded)
+    std::vector<int64_t> near_off_t;
+    int64_t near_entries_t = 0;
+    std::vector<int64_t> vt_off;    // L
+    int64_t vt_entries = 0;
     int32_t max_leaf = 0;           // largest leaf size
 
     // launch order of the row clusters in the coupling stage: the rows are cut

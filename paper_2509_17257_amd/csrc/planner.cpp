@@ -203,6 +203,22 @@ Plan *build_plan(const double *pts, int64_t n, const h2x_params &prm, std::strin
         }
     }
     P->near_entries = off;
+    P->near_off_t.resize(near.size());
+    P->vt_off.resize(L);
+    off = 0;
+    int64_t voff = 0;
+    for (int32_t l = 0; l < L; ++l) {
+        const int32_t t = P->leaves[l];
+        const int64_t nt2 = P->size[t] + (P->size[t] & 1);
+        P->vt_off[l] = voff;
+        voff += (int64_t)P->k * nt2;
+        for (int64_t q = P->near_ptr[l]; q < P->near_ptr[l + 1]; ++q) {
+            P->near_off_t[q] = off;
+            off += nt2 * P->size[P->near_col[q]];
+        }
+    }
+    P->near_entries_t = off;
+    P->vt_entries = voff;
 
     const int32_t rpx = (C + 7) / 8;
     P->cpl_order.resize(C);

@@ -1,0 +1,420 @@
+// Matrix-core (MFMA) kernels for the FP64 operator with k = 64: forward leaf
+// transform, upward and downward transfer passes, and the leaf stage
+// (near field and leaf basis).  Each work-group (4 waves) computes one output
+// tile of 64 rows x 16*NJ columns; wave w owns rows 16w..16w+15.  Operands are
+// staged through LDS with coalesced global loads (a near-field block is one
+// contiguous |t| x |s| array), then v_mfma_f64_16x16x4f64 accumulates in
+// registers.  Contraction lengths are padded to a multiple of 4 with zeros in
+// LDS, rows beyond the block are never written back.
+#pragma once
+
+#include "device.hpp"
+
+namespace h2x {
+namespace mfma {
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+constexpr int K = 64;     // rank handled by these kernels
+constexpr int LDA = K + 1;  // padded LDS row of the left operand
+
+template <int NJ>
+struct Smem {  // operand tiles of one work-group
+    static constexpr int MC = 16 * NJ;
+    static constexpr int LDB = MC + 1;
+    double a[64 * LDA];
+    double b[64 * LDB];
+};
+
+// index split e -> (e / d, e % d) for e < 4096, d <= 64, via a float reciprocal:
+// (e + 0.5) / d is at least 0.5 / d away from an integer, far above the error
+__device__ inline void split(int e, int d, float inv_d, int &q, int &r) {
+    q = (int)((e + 0.5f) * inv_d);
+    r = e - q * d;
+}
+
+// One term A B of a sum accumulated into a 64 x 16*NJ tile.
+// A: arows x acols row-major at a (row stride lda); trans == false puts
+// A[i][c] at LDS row i (contraction over c), trans == true puts it at LDS row c
+// (contraction over i).  B: contraction-length rows, row r at
+// b + row(r) * ldb with row(r) = perm ? perm[brow0 + r] : brow0 + r.
+struct Term {
+    const double *a;
+    int64_t lda;
+    int arows, acols;
+    bool trans;
+    const double *b;
+    int64_t ldb;
+    const int64_t *perm;
+    int64_t brow0;
+    __device__ int klen() const { return trans ? arows : acols; }
+};
+
+template <int NJ>
+struct Regs {
+    double a[16];
+    double b[4 * NJ];
+};
+
+// global -> registers: all loads of a term issued back to back
+template <int NJ>
+__device__ inline void load_term(const Term &d, int mc, Regs<NJ> &R) {
+    constexpr int MC = 16 * NJ;
+    const int tid = threadIdx.x, total = d.arows * d.acols;
+    if (total > 0) {
+        const float inv = 1.0f / (float)d.acols;
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int e = tid + 256 * u;
+            int i, c;
+            split(e, d.acols, inv, i, c);
+            R.a[u] = e < total ? d.a[(int64_t)i * d.lda + c] : 0.0;
+        }
+    }
+    const int kl = d.klen();
+#pragma unroll
+    for (int u = 0; u < 4 * NJ; ++u) {
+        const int e = tid + 256 * u, r = e / MC, c = e % MC;
+        double v = 0.0;
+        if (r < kl && c < mc) {
+            const int64_t g = d.perm ? d.perm[d.brow0 + r] : d.brow0 + r;
+            v = d.b[g * d.ldb + c];
+        }
+        R.b[u] = v;
+    }
+}
+
+// registers -> LDS.  The right operand tile is rewritten in full (zeros past the
+// contraction length), so stale left-operand padding only ever meets zeros;
+// the tiles are cleared once per kernel so that padding is finite.
+template <int NJ>
+__device__ inline void store_term(const Term &d, const Regs<NJ> &R, Smem<NJ> &sm) {
+    constexpr int MC = 16 * NJ, LDB = MC + 1;
+    const int tid = threadIdx.x, total = d.arows * d.acols;
+    const float inv = 1.0f / (float)max(d.acols, 1);
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        const int e = tid + 256 * u;
+        if (e < total) {
+            int i, c;
+            split(e, d.acols, inv, i, c);
+            if (d.trans) sm.a[c * LDA + i] = R.a[u];
+            else sm.a[i * LDA + c] = R.a[u];
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < 4 * NJ; ++u) {
+        const int e = tid + 256 * u, r = e / MC, c = e % MC;
+        sm.b[r * LDB + c] = R.b[u];
+    }
+}
+
+template <int NJ>
+__device__ inline void clear(Smem<NJ> &sm) {
+    constexpr int NA = 64 * LDA, NB = 64 * Smem<NJ>::LDB;
+    for (int e = threadIdx.x; e < NA; e += 256) sm.a[e] = 0.0;
+    for (int e = threadIdx.x; e < NB; e += 256) sm.b[e] = 0.0;
+    __syncthreads();
+}
+
+template <int NJ>
+__device__ inline void mma(const double *As, const double *Bs, int kpad, dbl4 *acc) {
+    constexpr int LDB = 16 * NJ + 1;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int lr = lane & 15, lq = lane >> 4;
+    const double *arow = As + (16 * w + lr) * LDA + lq;
+    const double *bcol = Bs + lq * LDB + lr;
+    for (int kk = 0; kk < kpad; kk += 4) {
+        const double a = arow[kk];
+#pragma unroll
+        for (int J = 0; J < NJ; ++J) acc[J] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bcol[kk * LDB + 16 * J], acc[J], 0, 0, 0);
+    }
+}
+
+template <int NJ>
+__device__ inline void zero(dbl4 *acc) {
+#pragma unroll
+    for (int J = 0; J < NJ; ++J) acc[J] = dbl4{0.0, 0.0, 0.0, 0.0};
+}
+
+__device__ inline int dkpad4(int v) { return (v + 3) & ~3; }
+
+// acc += sum_{q < nq} A_q B_q; the next term's global loads are in flight while
+// the matrix cores work on the current one.  A term with no columns adds nothing.
+template <int NJ, typename F>
+__device__ inline void accumulate(Smem<NJ> &sm, dbl4 *acc, int nq, int mc, F term) {
+    if (nq <= 0) return;
+    Regs<NJ> R;
+    Term d = term(0);
+    load_term<NJ>(d, mc, R);
+    for (int q = 0; q < nq; ++q) {
+        store_term<NJ>(d, R, sm);
+        __syncthreads();
+        const int kp = dkpad4(d.klen());
+        if (q + 1 < nq) {
+            d = term(q + 1);
+            load_term<NJ>(d, mc, R);
+        }
+        mma<NJ>(sm.a, sm.b, kp, acc);
+        __syncthreads();
+    }
+}
+
+// result element (lane, J, r) -> (row, col) of the 64 x 16*NJ tile
+__device__ inline int out_row(int r) { return 16 * (threadIdx.x >> 6) + ((threadIdx.x & 63) >> 4) + 4 * r; }
+__device__ inline int out_col(int J) { return 16 * J + (threadIdx.x & 15); }
+
+// x_t = V_t^T X|_t for each leaf t
+template <int NJ>
+__global__ __launch_bounds__(256) void k_fwd_leaf(int64_t m, const int32_t *__restrict__ leaves,
+                                                  const int32_t *__restrict__ first, const int32_t *__restrict__ size,
+                                                  const int64_t *__restrict__ perm, const double *__restrict__ V,
+                                                  const double *__restrict__ X, int64_t ldx, int tree_order,
+                                                  double *__restrict__ xh, int64_t ldh) {
+    __shared__ Smem<NJ> sm;
+    const int32_t t = leaves[blockIdx.x];
+    const int64_t j0 = (int64_t)blockIdx.y * Smem<NJ>::MC;
+    const int mc = (int)min<int64_t>(Smem<NJ>::MC, m - j0);
+    const int64_t r0 = first[t];
+    const int nt = size[t];
+    clear<NJ>(sm);
+    dbl4 acc[NJ];
+    zero<NJ>(acc);
+    const int64_t *pm = tree_order ? nullptr : perm;
+    accumulate<NJ>(sm, acc, (nt + 63) / 64, mc, [&](int q) {
+        const int i0 = 64 * q;
+        return Term{V + (r0 + i0) * K, K, min(64, nt - i0), K, true, X + j0, ldx, pm, r0 + i0};
+    });
+#pragma unroll
+    for (int J = 0; J < NJ; ++J)
+        if (out_col(J) < mc)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) xh[((int64_t)t * K + out_row(r)) * ldh + j0 + out_col(J)] = acc[J][r];
+}
+
+// x_t = E_{t0}^T x_{t0} + E_{t1}^T x_{t1} for the inner clusters in `list`
+template <int NJ>
+__global__ __launch_bounds__(256) void k_up(int64_t m, const int32_t *__restrict__ list,
+                                            const int32_t *__restrict__ son0, const int32_t *__restrict__ son1,
+                                            const double *__restrict__ E, double *__restrict__ xh, int64_t ldh) {
+    __shared__ Smem<NJ> sm;
+    const int32_t t = list[blockIdx.x];
+    const int64_t j0 = (int64_t)blockIdx.y * Smem<NJ>::MC;
+    const int mc = (int)min<int64_t>(Smem<NJ>::MC, m - j0);
+    clear<NJ>(sm);
+    dbl4 acc[NJ];
+    zero<NJ>(acc);
+    const int32_t s0 = son0[t], s1 = son1[t];
+    accumulate<NJ>(sm, acc, 2, mc, [&](int q) {
+        const int32_t s = q ? s1 : s0;
+        return Term{E + (int64_t)s * K * K, K, K, K, true, xh + j0, ldh, nullptr, (int64_t)s * K};
+    });
+#pragma unroll
+    for (int J = 0; J < NJ; ++J)
+        if (out_col(J) < mc)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) xh[((int64_t)t * K + out_row(r)) * ldh + j0 + out_col(J)] = acc[J][r];
+}
+
+// y_c += E_c y_parent(c) for the clusters in `list`
+template <int NJ>
+__global__ __launch_bounds__(256) void k_down(int64_t m, const int32_t *__restrict__ list,
+                                              const int32_t *__restrict__ parent, const double *__restrict__ E,
+                                              double *__restrict__ yh, int64_t ldh) {
+    __shared__ Smem<NJ> sm;
+    const int32_t c = list[blockIdx.x];
+    const int32_t par = parent[c];
+    const int64_t j0 = (int64_t)blockIdx.y * Smem<NJ>::MC;
+    const int mc = (int)min<int64_t>(Smem<NJ>::MC, m - j0);
+    dbl4 acc[NJ];
+    zero<NJ>(acc);
+    accumulate<NJ>(sm, acc, 1, mc, [&](int) {
+        return Term{E + (int64_t)c * K * K, K, K, K, false, yh + j0, ldh, nullptr, (int64_t)par * K};
+    });
+#pragma unroll
+    for (int J = 0; J < NJ; ++J)
+        if (out_col(J) < mc)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) yh[((int64_t)c * K + out_row(r)) * ldh + j0 + out_col(J)] += acc[J][r];
+}
+
+// Leaf stage in the transposed orientation Y_t^T = X_s^T N_ts^T: the
+// matrix-core M dimension runs over columns of X, N over rows of the leaf.
+// Near-field blocks are stored transposed (|s| rows of length |t| padded to
+// even), and the leaf basis also has a transposed copy (k rows of length |t|
+// padded to even).  Every operand load is then 16 bytes per lane: a lane
+// holds two neighbouring rows (or columns), so one load feeds the "even" and
+// the "odd" 16-row (16-column) tile.  Tile (J = 2p + hj, I = 2g + h) holds
+// columns 32p + 2m' + hj and rows 32g + 2n' + h, m', n' = 0..15.
+// The 4 waves of a work-group split the leaf's terms (the basis term V_t y_t
+// and the near blocks, dealt round-robin) and each computes all 64 rows x
+// 32*NP columns of its partial sum, in rounds of four k-steps with the next
+// round's loads in flight during the current round's MFMAs.  The four partial
+// tiles are then added in LDS in wave order (fixed, so the result is
+// reproducible).  Leaves are dealt to XCDs in contiguous eighths so that
+// neighbouring leaves, which share near-field partners, read the same rows of
+// X through one L2.
+//   Y|_t = beta Y|_t + alpha (basis ? V_t y_t : 0) + alpha sum_s N_ts X|_s
+typedef double dbl2 __attribute__((ext_vector_type(2)));
+
+template <int NP>
+struct Round {
+    dbl2 b[2][4];   // [row half g][k-step u]: rows 32g + 2 lr + {0, 1}
+    dbl2 a[NP][4];  // [column half p][k-step u]: columns 32p + 2 lr + {0, 1}
+};
+
+__device__ inline dbl2 ld2(const double *p) { return *(const dbl2 *)p; }
+
+template <int NP>
+__global__ __launch_bounds__(256, NP == 1 ? 2 : 1) void k_leaf_direct(int64_t m, int32_t L, const int32_t *__restrict__ leaves,
+                                                     const int32_t *__restrict__ first,
+                                                     const int32_t *__restrict__ size,
+                                                     const int64_t *__restrict__ perm, const double *__restrict__ Vt,
+                                                     const int64_t *__restrict__ vt_off,
+                                                     const double *__restrict__ yh, int64_t ldh,
+                                                     const int64_t *__restrict__ near_ptr,
+                                                     const int32_t *__restrict__ near_col,
+                                                     const int64_t *__restrict__ near_off,
+                                                     const double *__restrict__ Nt, const double *__restrict__ Xt,
+                                                     int64_t ldxt, double alpha, double beta, double *__restrict__ Y,
+                                                     int64_t ldy, int tree_order, int basis) {
+    constexpr int MC = 32 * NP, LDR = MC + 1;
+    __shared__ double red[64 * LDR];
+    const int32_t per_xcd = (L + 7) / 8;
+    const int32_t l = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+    if (l >= L) return;
+    const int32_t t = leaves[l];
+    const int nt = size[t];
+    const int64_t nt2 = nt + (nt & 1);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, lq = lane >> 4;
+    const int64_t r0 = first[t];
+    const int64_t j0 = (int64_t)blockIdx.y * MC;
+    const int mc = (int)min<int64_t>(MC, m - j0);
+    bool col_ok[NP];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) col_ok[p] = 32 * p + 2 * lr < mc;
+    const int64_t q0 = near_ptr[l];
+    const int nitems = (int)(near_ptr[l + 1] - q0) + basis;  // item 0 is the basis term when basis != 0
+
+    for (int i0 = 0; i0 < nt; i0 += 64) {
+        const int ic = min(64, nt - i0);
+        const int nhalf = (ic + 31) >> 5;  // 32-row halves present (wave-uniform)
+        bool row_ok[2];
+#pragma unroll
+        for (int g = 0; g < 2; ++g) row_ok[g] = 32 * g + 2 * lr < ic;
+        dbl4 acc[2 * NP][4];
+#pragma unroll
+        for (int J = 0; J < 2 * NP; ++J)
+#pragma unroll
+            for (int I = 0; I < 4; ++I) acc[J][I] = dbl4{0.0, 0.0, 0.0, 0.0};
+
+        // item e, k-steps kb..kb+15 -> registers.  Right operand: rows (k) of a
+        // transposed block with row stride nt2; left operand: rows (k) of X or y_t.
+        auto load = [&](int e, int kb, Round<NP> &R) {
+            const double *bb, *ab;
+            int64_t lda;
+            int kl;
+            if (basis && e == 0) {
+                bb = Vt + vt_off[l] + i0 + 2 * lr;                       // V_t^T[nu][i]
+                ab = yh + (int64_t)t * K * ldh + j0 + 2 * lr;            // y_t[nu][j]
+                lda = ldh;
+                kl = K;
+            } else {
+                const int64_t q = q0 + e - basis;
+                const int32_t s = near_col[q];
+                bb = Nt + near_off[q] + i0 + 2 * lr;                     // N_ts^T[c][i]
+                ab = Xt + (int64_t)first[s] * ldxt + j0 + 2 * lr;        // X_s[c][j]
+                lda = ldxt;
+                kl = size[s];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int c = kb + 4 * u + lq;
+                const bool cok = c < kl;
+#pragma unroll
+                for (int g = 0; g < 2; ++g)
+                    R.b[g][u] = (cok && row_ok[g]) ? ld2(bb + c * nt2 + 32 * g) : dbl2{0.0, 0.0};
+#pragma unroll
+                for (int p = 0; p < NP; ++p)
+                    R.a[p][u] = (cok && col_ok[p]) ? ld2(ab + c * lda + 32 * p) : dbl2{0.0, 0.0};
+            }
+        };
+        auto klen = [&](int e) { return (basis && e == 0) ? K : (int)size[near_col[q0 + e - basis]]; };
+
+        int e = w;
+        if (e < nitems) {
+            Round<NP> cur, nxt;
+            int kb = 0, len = klen(e);
+            load(e, kb, cur);
+            for (;;) {
+                int en = e, kbn = kb + 16, lenn = len;
+                if (kbn >= len) {
+                    en = e + 4;
+                    kbn = 0;
+                    if (en < nitems) lenn = klen(en);
+                }
+                const bool more = en < nitems;
+                if (more) load(en, kbn, nxt);
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int g = 0; g < 2; ++g)
+                        if (g < nhalf)
+#pragma unroll
+                            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                                for (int p = 0; p < NP; ++p)
+#pragma unroll
+                                    for (int hj = 0; hj < 2; ++hj)
+                                        acc[2 * p + hj][2 * g + h] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                                            cur.a[p][u][hj], cur.b[g][u][h], acc[2 * p + hj][2 * g + h], 0, 0, 0);
+                if (!more) break;
+                cur = nxt;
+                e = en;
+                kb = kbn;
+                len = lenn;
+            }
+        }
+        // partial tiles of the 4 waves, added in wave order.  Lane l, register r of
+        // tile (J = 2p + hj, I = 2g + h) -> column 32p + 2 (l / 16 + 4 r) + hj,
+        // row 32g + 2 (l % 16) + h.
+        for (int ww = 0; ww < 4; ++ww) {
+            if (w == ww)
+#pragma unroll
+                for (int J = 0; J < 2 * NP; ++J)
+#pragma unroll
+                    for (int I = 0; I < 4; ++I)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const int col = 32 * (J >> 1) + 2 * (lq + 4 * r) + (J & 1);
+                            const int row = 32 * (I >> 1) + 2 * lr + (I & 1);
+                            double *cell = &red[row * LDR + col];
+                            *cell = (ww == 0) ? acc[J][I][r] : *cell + acc[J][I][r];
+                        }
+            __syncthreads();
+        }
+        for (int x = threadIdx.x; x < ic * MC; x += 256) {
+            const int i = x / MC, j = x % MC;
+            if (j < mc) {
+                int64_t row = r0 + i0 + i;
+                if (!tree_order) row = perm[row];
+                double *y = &Y[row * ldy + j0 + j];
+                const double v = alpha * red[i * LDR + j];
+                *y = (beta == 0.0) ? v : beta * *y + v;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// rows of X into tree order with an even leading dimension: Xt[i] = X[perm[i]] (zero padding)
+__global__ void k_gather(int64_t n, int64_t m, const int64_t *__restrict__ perm, const double *__restrict__ X,
+                         int64_t ldx, double *__restrict__ Xt, int64_t ldt) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * ldt) return;
+    const int64_t i = e / ldt, j = e % ldt;
+    Xt[e] = j < m ? X[(perm ? perm[i] : i) * ldx + j] : 0.0;
+}
+
+}  // namespace mfma
+}  // namespace h2x

@@ -53,6 +53,11 @@ CASES = [
     ("cube-k8-leaf100", lambda: W.cube_points(3000, 83), dict(ell=0.3, shift=0.5, eta=1.5, leaf=100, p=2), 3),
     ("line-k27", lambda: W.line_points(2000, 84), dict(ell=0.2, shift=1.0, eta=1.0, leaf=16, p=3), 7),
     ("sphere-k125-m9", lambda: W.sphere_points(3000, 85), dict(ell=0.5, shift=1.0, eta=1.0, leaf=64, p=5), 9),
+    ("cube-k64-m64", lambda: W.cube_points(5000, 101), dict(ell=0.25, shift=0.5, eta=1.0, leaf=64, p=4), 64),
+    ("sphere-k64-m100", lambda: W.sphere_points(4000, 102), dict(ell=0.5, shift=1.0, eta=1.0, leaf=64, p=4), 100),
+    ("sphere-k64-leaf150-m17", lambda: W.sphere_points(4000, 103), dict(ell=0.5, shift=1.0, eta=1.0, leaf=150, p=4),
+     17),
+    ("line-k64-m3", lambda: W.line_points(3000, 104), dict(ell=0.2, shift=1.0, eta=1.0, leaf=40, p=4), 3),
 ]
 
 

@@ -97,13 +97,27 @@ def main():
     from paper_2509_17257_amd import workloads as W
 
     if args.copy_calibration_gib > 0:
+        # plain device copy of a known size (scales the HBM traffic counters) and the
+        # bandwidth a copy and a read-only reduction reach on this device
         nbytes = int(args.copy_calibration_gib * 2**30) // 8 * 8
         src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
         dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
+        reps = 10
+        dst.copy_(src)
         torch.cuda.synchronize()
-        print(json.dumps({"copy_calibration_bytes": nbytes, "copies": 3}), flush=True)
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        e0.record()
+        for _ in range(reps):
+            dst.copy_(src)
+        e1.record()
+        for _ in range(reps):
+            src.sum()
+        e2.record()
+        torch.cuda.synchronize()
+        copy_gbs = 2 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+        read_gbs = nbytes * reps / (e1.elapsed_time(e2) * 1e-3) / 1e9
+        print(json.dumps({"copy_calibration_bytes": nbytes, "copies": reps + 1, "copy_gbs": round(copy_gbs, 1),
+                          "read_gbs": round(read_gbs, 1)}), flush=True)
         return
 
     w = W.WORKLOADS[args.workload]

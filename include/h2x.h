@@ -141,8 +141,8 @@ h2x_status h2x_matmul(const h2x_mat *A, int64_t m, double alpha, const double *X
 /* Same product as h2x_matmul, with HIP events recorded on the stream around
  * each stage.  Blocking: returns after the product has completed, with the
  * stage durations in milliseconds in stage_ms[H2X_NUM_STAGES] (host array):
- * forward leaf, forward transfer passes, coupling, backward transfer passes,
- * leaf basis + near field. */
+ * forward leaf (including any reordering of X), forward transfer passes,
+ * coupling, backward transfer passes, leaf stage (leaf basis and near field). */
 #define H2X_NUM_STAGES 5
 h2x_status h2x_matmul_timed(const h2x_mat *A, int64_t m, double alpha, const double *X, int64_t ldx,
                             double beta, double *Y, int64_t ldy, int32_t flags, void *dev_ws,

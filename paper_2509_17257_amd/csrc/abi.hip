@@ -182,7 +182,7 @@ h2x_status h2x_mat_create(const h2x_plan *plan, h2x_prec storage, void *dev_ws, 
     if (e == hipSuccess) e = launch_fill(d, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) {
-        delete M;
+        h2x_mat_destroy(M);
         return hip_fail("h2x_mat_create", e);
     }
     *out = M;
@@ -235,14 +235,15 @@ h2x_status h2x_matmul_timed(const h2x_mat *A, int64_t m, double alpha, const dou
     if (!stage_ms) return fail(H2X_EINVAL, "h2x_matmul_timed: stage_ms is NULL");
     h2x_status s = validate_matmul("h2x_matmul_timed", A, m, X, ldx, Y, ldy, flags, dev_ws, ws_bytes);
     if (s != H2X_OK) return s;
-    hipEvent_t ev[H2X_NUM_STAGES + 1] = {};
+    hipEvent_t ev[7] = {};
     hipError_t e = hipSuccess;
-    for (int i = 0; i <= H2X_NUM_STAGES && e == hipSuccess; ++i) e = hipEventCreate(&ev[i]);
+    for (int i = 0; i < 7 && e == hipSuccess; ++i) e = hipEventCreate(&ev[i]);
     hipStream_t st = (hipStream_t)hip_stream;
     if (e == hipSuccess)
         e = run_matmul(A->dm, m, alpha, X, ldx, beta, Y, ldy, (flags & H2X_TREE_ORDER) != 0, (char *)dev_ws, st, ev);
-    if (e == hipSuccess) e = hipEventSynchronize(ev[H2X_NUM_STAGES]);
-    for (int i = 0; i < H2X_NUM_STAGES && e == hipSuccess; ++i) {
+    if (e == hipSuccess) e = hipEventSynchronize(ev[5]);
+    if (e == hipSuccess) e = hipEventSynchronize(ev[6]);
+    for (int i = 0; i < 5 && e == hipSuccess; ++i) {
         float ms = 0.f;
         e = hipEventElapsedTime(&ms, ev[i], ev[i + 1]);
         stage_ms[i] = ms;

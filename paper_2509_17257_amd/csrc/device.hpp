@@ -49,6 +49,7 @@ struct DevMat {
 
     // host copies of the level tables (launch sizes)
     const Plan *plan = nullptr;
+
 };
 
 inline int s_swizzled(const DevMat &dm) { return dm.swz; }
@@ -58,7 +59,9 @@ size_t mat_layout(const Plan &P, h2x_prec storage, DevMat *dm, char *base);
 hipError_t launch_fill(const DevMat &dm, hipStream_t st);
 
 size_t matmul_ws_bytes(const DevMat &dm, int64_t m);
-// ev (optional): 6 events recorded before the first stage and after each stage
+// ev (optional): 7 events recorded on the stream: before the first stage, after
+// each of the 5 stages, and (ev[6]) after the near field, which the matrix-core
+// path fuses into the leaf stage
 hipError_t run_matmul(const DevMat &dm, int64_t m, double alpha, const double *X, int64_t ldx, double beta,
                       double *Y, int64_t ldy, bool tree_order, char *ws, hipStream_t st,
                       hipEvent_t *ev = nullptr);

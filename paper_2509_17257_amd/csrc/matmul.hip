@@ -298,7 +298,7 @@ inline int64_t even_ld(int64_t m) { return m + (m & 1); }
 template <int NJ>
 void matmul_mfma_f64(const DevMat &dm, int64_t m, double alpha, const double *X, int64_t ldx, double beta, double *Y,
                      int64_t ldy, int to, double *xh, double *yh, int64_t ldh, double *xt_ws, hipStream_t st,
-                     const std::function<void(int)> &mark) {
+                     const std::function<void(int)> &mark, hipEvent_t *ev) {
     const Plan &P = *dm.plan;
     const unsigned gy = (unsigned)((m + 16 * NJ - 1) / (16 * NJ));
     constexpr int NP = NJ > 2 ? 2 : 1;  // leaf stage: 32 or 64 columns per work-group
@@ -317,7 +317,7 @@ void matmul_mfma_f64(const DevMat &dm, int64_t m, double alpha, const double *X,
     hipLaunchKernelGGL(mfma::k_fwd_leaf<NJ>, dim3(dm.L, gy), dim3(256), 0, st, m, dm.leaves, dm.first, dm.size,
                        dm.perm, V, Xt, ldxt, 1, xh, ldh);
     mark(1);
-    for (int d = dm.depth_max - 1; d >= 0; --d) {
+    for (int d = dm.depth_max - 1; d >= P.adm_depth; --d) {
         const int32_t b = P.lvl_inner_ptr[d], e = P.lvl_inner_ptr[d + 1];
         if (e > b)
             hipLaunchKernelGGL(mfma::k_up<NJ>, dim3(e - b, gy), dim3(256), 0, st, m, dm.lvl_inner + b, dm.son0,
@@ -326,18 +326,20 @@ void matmul_mfma_f64(const DevMat &dm, int64_t m, double alpha, const double *X,
     mark(2);
     launch_coupling_fast<double, double>(dm, m, xh, yh, ldh, st);
     mark(3);
-    for (int d = 1; d <= dm.depth_max; ++d) {
+    for (int d = std::max(1, P.adm_depth + 1); d <= dm.depth_max; ++d) {
         const int32_t b = P.lvl_ptr[d], e = P.lvl_ptr[d + 1];
         if (e > b)
             hipLaunchKernelGGL(mfma::k_down<NJ>, dim3(e - b, gy), dim3(256), 0, st, m, dm.lvl_all + b, dm.parent, E,
                                yh, ldh);
     }
     mark(4);
+    // Y = beta Y + alpha (V y-hat + N X)
     const unsigned gl = (unsigned)((m + 32 * NP - 1) / (32 * NP));
     hipLaunchKernelGGL(mfma::k_leaf_direct<NP>, dim3(8 * ((dm.L + 7) / 8), gl), dim3(256), 0, st, m, dm.L, dm.leaves,
                        dm.first, dm.size, dm.perm, (const double *)dm.Vt, dm.vt_off, yh, ldh, dm.near_ptr,
-                       dm.near_col, dm.near_off, (const double *)dm.N, Xt, ldxt, alpha, beta, Y, ldy, to, 1);
+                       dm.near_col, dm.near_off, (const double *)dm.N, Xt, ldxt, alpha, beta, Y, ldy, to, 1, 1);
     mark(5);
+    if (ev) (void)hipEventRecord(ev[6], st);
 }
 
 template <typename Acc>
@@ -364,10 +366,10 @@ hipError_t matmul_typed(const DevMat &dm, int64_t m, double alpha, const double 
             const std::function<void(int)> mk = mark;
             double *xt = (double *)(ws + 2 * hat_bytes<Acc>(dm, m));
             switch ((int)std::min<int64_t>(4, (m + 15) / 16)) {
-                case 1: matmul_mfma_f64<1>(dm, m, alpha, X, ldx, beta, Y, ldy, to, xh, yh, ldh, xt, st, mk); break;
-                case 2: matmul_mfma_f64<2>(dm, m, alpha, X, ldx, beta, Y, ldy, to, xh, yh, ldh, xt, st, mk); break;
-                case 3: matmul_mfma_f64<3>(dm, m, alpha, X, ldx, beta, Y, ldy, to, xh, yh, ldh, xt, st, mk); break;
-                default: matmul_mfma_f64<4>(dm, m, alpha, X, ldx, beta, Y, ldy, to, xh, yh, ldh, xt, st, mk); break;
+                case 1: matmul_mfma_f64<1>(dm, m, alpha, X, ldx, beta, Y, ldy, to, xh, yh, ldh, xt, st, mk, ev); break;
+                case 2: matmul_mfma_f64<2>(dm, m, alpha, X, ldx, beta, Y, ldy, to, xh, yh, ldh, xt, st, mk, ev); break;
+                case 3: matmul_mfma_f64<3>(dm, m, alpha, X, ldx, beta, Y, ldy, to, xh, yh, ldh, xt, st, mk, ev); break;
+                default: matmul_mfma_f64<4>(dm, m, alpha, X, ldx, beta, Y, ldy, to, xh, yh, ldh, xt, st, mk, ev); break;
             }
             return hipGetLastError();
         }
@@ -377,7 +379,7 @@ hipError_t matmul_typed(const DevMat &dm, int64_t m, double alpha, const double 
     hipLaunchKernelGGL((k_fwd_leaf<T, Acc>), dim3(dm.L, gy), dim3(256), 0, st, dm.k, m, dm.leaves, dm.first, dm.size,
                        dm.perm, V, X, ldx, to, xh, ldh);
     mark(1);
-    for (int d = dm.depth_max - 1; d >= 0; --d) {
+    for (int d = dm.depth_max - 1; d >= P.adm_depth; --d) {
         const int32_t b = P.lvl_inner_ptr[d], e = P.lvl_inner_ptr[d + 1];
         if (e > b)
             hipLaunchKernelGGL((k_up<T, Acc>), dim3(e - b, gy), dim3(256), 0, st, dm.k, m, dm.lvl_inner + b, dm.son0,
@@ -388,7 +390,7 @@ hipError_t matmul_typed(const DevMat &dm, int64_t m, double alpha, const double 
         hipLaunchKernelGGL((k_coupling<T, Acc>), dim3(dm.C, gy), dim3(256), 0, st, dm.k, m, dm.adm_ptr, dm.adm_col, S,
                            dm.swz, xh, yh, ldh);
     mark(3);
-    for (int d = 1; d <= dm.depth_max; ++d) {
+    for (int d = std::max(1, P.adm_depth + 1); d <= dm.depth_max; ++d) {
         const int32_t b = P.lvl_ptr[d], e = P.lvl_ptr[d + 1];
         if (e > b)
             hipLaunchKernelGGL((k_down<T, Acc>), dim3(e - b, gy), dim3(256), 0, st, dm.k, m, dm.lvl_all + b, dm.parent,
@@ -399,6 +401,7 @@ hipError_t matmul_typed(const DevMat &dm, int64_t m, double alpha, const double 
                        dm.size, dm.perm, V, yh, ldh, dm.near_ptr, dm.near_col, dm.near_off, (const TN *)dm.N, X, ldx,
                        alpha, beta, Y, ldy, to, dm.near_t);
     mark(5);
+    if (ev) (void)hipEventRecord(ev[6], st);
     return hipGetLastError();
 }
 

@@ -32,6 +32,9 @@ struct Plan {
     std::vector<int32_t> lvl_all;   // cluster ids by depth
     std::vector<int32_t> lvl_inner_ptr;  // depth_max + 2
     std::vector<int32_t> lvl_inner;      // inner cluster ids by depth
+    // shallowest depth of a cluster in an admissible block: x-hat above it is
+    // never read and y-hat above it stays zero, so the transfer passes stop there
+    int32_t adm_depth = 0;
 
     // admissible leaves, CSR by row cluster
     std::vector<int64_t> adm_ptr;   // C + 1

@@ -203,6 +203,8 @@ Plan *build_plan(const double *pts, int64_t n, const h2x_params &prm, std::strin
         }
     }
     P->near_entries = off;
+    P->adm_depth = P->depth_max + 1;
+    for (auto &b : adm) P->adm_depth = std::min(P->adm_depth, std::min(P->depth[b.first], P->depth[b.second]));
     P->near_off_t.resize(near.size());
     P->vt_off.resize(L);
     off = 0;

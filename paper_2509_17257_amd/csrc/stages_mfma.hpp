@@ -254,7 +254,7 @@ __global__ __launch_bounds__(256) void k_down(int64_t m, const int32_t *__restri
 // reproducible).  Leaves are dealt to XCDs in contiguous eighths so that
 // neighbouring leaves, which share near-field partners, read the same rows of
 // X through one L2.
-//   Y|_t = beta Y|_t + alpha (basis ? V_t y_t : 0) + alpha sum_s N_ts X|_s
+//   Y|_t = beta Y|_t + alpha (basis ? V_t y_t : 0) + alpha (near ? sum_s N_ts X|_s : 0)
 typedef double dbl2 __attribute__((ext_vector_type(2)));
 
 template <int NP>
@@ -277,7 +277,7 @@ __global__ __launch_bounds__(256, NP == 1 ? 2 : 1) void k_leaf_direct(int64_t m,
                                                      const int64_t *__restrict__ near_off,
                                                      const double *__restrict__ Nt, const double *__restrict__ Xt,
                                                      int64_t ldxt, double alpha, double beta, double *__restrict__ Y,
-                                                     int64_t ldy, int tree_order, int basis) {
+                                                     int64_t ldy, int tree_order, int basis, int near) {
     constexpr int MC = 32 * NP, LDR = MC + 1;
     __shared__ double red[64 * LDR];
     const int32_t per_xcd = (L + 7) / 8;
@@ -294,7 +294,11 @@ __global__ __launch_bounds__(256, NP == 1 ? 2 : 1) void k_leaf_direct(int64_t m,
 #pragma unroll
     for (int p = 0; p < NP; ++p) col_ok[p] = 32 * p + 2 * lr < mc;
     const int64_t q0 = near_ptr[l];
-    const int nitems = (int)(near_ptr[l + 1] - q0) + basis;  // item 0 is the basis term when basis != 0
+    // items: nb parts of the basis term (k-ranges of 64 / nb), then the near blocks;
+    // without near blocks the basis term is split over the 4 waves
+    const int nb = basis ? (near ? 1 : 4) : 0;
+    const int kbase = K / max(nb, 1);
+    const int nitems = (near ? (int)(near_ptr[l + 1] - q0) : 0) + nb;
 
     for (int i0 = 0; i0 < nt; i0 += 64) {
         const int ic = min(64, nt - i0);
@@ -314,13 +318,13 @@ __global__ __launch_bounds__(256, NP == 1 ? 2 : 1) void k_leaf_direct(int64_t m,
             const double *bb, *ab;
             int64_t lda;
             int kl;
-            if (basis && e == 0) {
-                bb = Vt + vt_off[l] + i0 + 2 * lr;                       // V_t^T[nu][i]
-                ab = yh + (int64_t)t * K * ldh + j0 + 2 * lr;            // y_t[nu][j]
+            if (e < nb) {
+                bb = Vt + vt_off[l] + (int64_t)e * kbase * nt2 + i0 + 2 * lr;   // V_t^T[nu][i]
+                ab = yh + ((int64_t)t * K + e * kbase) * ldh + j0 + 2 * lr;     // y_t[nu][j]
                 lda = ldh;
-                kl = K;
+                kl = kbase;
             } else {
-                const int64_t q = q0 + e - basis;
+                const int64_t q = q0 + e - nb;
                 const int32_t s = near_col[q];
                 bb = Nt + near_off[q] + i0 + 2 * lr;                     // N_ts^T[c][i]
                 ab = Xt + (int64_t)first[s] * ldxt + j0 + 2 * lr;        // X_s[c][j]
@@ -339,7 +343,7 @@ __global__ __launch_bounds__(256, NP == 1 ? 2 : 1) void k_leaf_direct(int64_t m,
                     R.a[p][u] = (cok && col_ok[p]) ? ld2(ab + c * lda + 32 * p) : dbl2{0.0, 0.0};
             }
         };
-        auto klen = [&](int e) { return (basis && e == 0) ? K : (int)size[near_col[q0 + e - basis]]; };
+        auto klen = [&](int e) { return e < nb ? kbase : (int)size[near_col[q0 + e - nb]]; };
 
         int e = w;
         if (e < nitems) {

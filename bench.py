@@ -55,6 +55,26 @@ def coupling_flops(plan, m):
     return 2 * plan.n_adm * plan.k * plan.k * m
 
 
+def measured_traffic(kernel_profile):
+    """HBM bytes per launch from a committed rocprofv3 PMC summary (FETCH_SIZE and WRITE_SIZE
+    scaled by a plain-copy calibration), or None when the kernel source has changed since."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", kernel_profile)
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if "=" in line and not line.lstrip().startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    src = os.path.join(ROOT, kv.get("kernel_source", ""))
+    if not os.path.isfile(src) or hashlib.sha256(open(src, "rb").read()).hexdigest() != kv.get("kernel_source_sha256"):
+        return None
+    return int(1024 * (float(kv["fetch_size_kib_per_launch"]) * float(kv["fetch_scale"]) +
+                       float(kv["write_size_kib_per_launch"]) * float(kv["write_scale"])))
+
+
 def cpu_baseline(w, P, X, plan, budget_s):
     import oracle
 
@@ -173,6 +193,8 @@ def main():
     else:
         roof = dict(bound="mfma", achieved=round(c_tf, 2), peak=PEAK_FP64_TFLOPS, unit="TFLOP/s",
                     frac=round(c_tf / PEAK_FP64_TFLOPS, 4), traffic=None)
+    if w.name == "sphere-n65536-k64-m32":
+        roof["traffic"] = measured_traffic("coupling_f64_sphere-n65536-k64-m32.pmc.txt")
     roof.update(kernel="coupling", kernel_ms=round(float(c_ms), 5), kernel_bytes=int(cb), kernel_flops=int(cf))
     log("[bench] stages ms: " + ", ".join(f"{n}={v:.4f}" for n, v in zip(h2x.STAGES, stage)))
 

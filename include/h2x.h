@@ -159,8 +159,9 @@ typedef struct {
 } h2x_cg_params;
 
 typedef struct {
-    int32_t iters;       /* iterations of the shared loop                             */
+    int32_t iters;       /* iterations of the shared loop (refined solve: all inner iterations) */
     int32_t status;      /* H2X_OK, H2X_EBREAKDOWN or H2X_ENOCONV                     */
+    int32_t outer_iters; /* refinement steps (h2x_block_cg_refine); 0 otherwise        */
     double *col_relres;  /* host, m entries or NULL: final ||r_i|| / ||b_i|| (recursive) */
     int32_t *col_iters;  /* host, m entries or NULL: iteration at which column i first met
                             the tolerance (iters if it never did)                      */
@@ -179,6 +180,22 @@ size_t h2x_block_cg_workspace_bytes(const h2x_mat *A, int64_t m);
 h2x_status h2x_block_cg(const h2x_mat *A, const h2x_cg_params *prm, int64_t m, const double *B,
                         int64_t ldb, double *X, int64_t ldx, void *dev_ws, size_t ws_bytes,
                         h2x_cg_info *info, void *hip_stream);
+
+/* Mixed precision: FP64 iterative refinement around block CG with a
+ * low-precision operator (spec precision pattern; the paper itself is FP64).
+ * A: the FP64 operator (H2X_F64 storage); A_lo: the same plan stored in FP32 or
+ * BF16 (its products accumulate in FP32).  Outer step: R = B - A X in FP64; stop
+ * when every column has ||R_i|| <= rtol ||B_i||; otherwise solve A_lo D = R with
+ * block CG (FP64 vectors, dot products and step sizes) to inner->rtol relative to
+ * ||R_i||, and set X += D.  At most max_outer steps.  Blocking.  info->iters is the
+ * total number of inner iterations, info->outer_iters the number of steps,
+ * info->col_relres the final FP64 true residuals ||B_i - A X_i|| / ||B_i||,
+ * info->status H2X_ENOCONV if rtol was not met. */
+size_t h2x_block_cg_refine_workspace_bytes(const h2x_mat *A, const h2x_mat *A_lo, int64_t m);
+h2x_status h2x_block_cg_refine(const h2x_mat *A, const h2x_mat *A_lo, const h2x_cg_params *inner, double rtol,
+                               int32_t max_outer, int64_t m, const double *B, int64_t ldb, double *X,
+                               int64_t ldx, void *dev_ws, size_t ws_bytes, h2x_cg_info *info,
+                               void *hip_stream);
 
 /* ---- misc ------------------------------------------------------------------ */
 

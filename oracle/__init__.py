@@ -62,6 +62,12 @@ def _load():
     lib.orc_block_cg.argtypes = [P, I64, P, P, D, I64, C.c_int, P, P]
     lib.orc_cg1.restype = I64
     lib.orc_cg1.argtypes = [P, P, P, D, I64]
+    lib.orc_matmul_lowp.argtypes = [P, C.c_int, I64, D, P, D, P]
+    lib.orc_block_cg_lowp.restype = I64
+    lib.orc_block_cg_lowp.argtypes = [P, C.c_int, I64, P, P, D, I64, P, P]
+    lib.orc_refine_cg.restype = I64
+    lib.orc_refine_cg.argtypes = [P, C.c_int, I64, P, P, D, D, I64, I64, P]
+    lib.orc_round_bf16_array.argtypes = [P, P, I64]
     lib.orc_num_threads.restype = C.c_int
     lib.orc_set_threads.argtypes = [C.c_int]
     _lib = lib
@@ -192,6 +198,26 @@ class OracleH2:
         fn(self._h, m, float(alpha), _ptr(X), float(beta), _ptr(out))
         return out[:, 0] if squeeze else out
 
+    def matmul_lowp(self, X, prec, alpha=1.0, beta=0.0, Y=None) -> np.ndarray:
+        """Emulated low-precision operator (prec "f32" or "bf16"): V, E, S rounded to the
+        storage type, near field to FP32, FP32 accumulation."""
+        pr = {"f32": 1, "bf16": 2}[prec]
+        X = np.ascontiguousarray(X, dtype=np.float64)
+        m = X.shape[1]
+        out = np.zeros((self.n, m)) if Y is None else np.ascontiguousarray(Y, dtype=np.float64).copy()
+        _load().orc_matmul_lowp(self._h, pr, m, float(alpha), _ptr(X), float(beta), _ptr(out))
+        return out
+
+    def refine_cg(self, B, prec, rtol=1e-10, inner_rtol=1e-4, max_outer=50, max_inner=10000):
+        """FP64 iterative refinement around block CG with the low-precision operator."""
+        pr = {"f32": 1, "bf16": 2}[prec]
+        B = np.ascontiguousarray(B, dtype=np.float64)
+        X = np.zeros_like(B)
+        tot = np.zeros(1, np.int64)
+        outer = _load().orc_refine_cg(self._h, pr, B.shape[1], _ptr(B), _ptr(X), float(rtol), float(inner_rtol),
+                                      int(max_outer), int(max_inner), _ptr(tot))
+        return X, dict(outer=int(outer), inner=int(tot[0]))
+
     def forward_transform(self, X) -> np.ndarray:
         X = np.ascontiguousarray(X, dtype=np.float64)
         m = X.shape[1]
@@ -229,6 +255,14 @@ class OracleH2:
         x = np.zeros_like(b) if x0 is None else np.ascontiguousarray(x0, dtype=np.float64).reshape(-1).copy()
         it = _load().orc_cg1(self._h, _ptr(b), _ptr(x), float(rtol), int(max_iter))
         return x, int(it)
+
+
+def round_bf16(values) -> np.ndarray:
+    """The oracle's bfloat16 rounding of FP32 values (returned as FP32)."""
+    a = np.ascontiguousarray(values, dtype=np.float32)
+    out = np.empty_like(a)
+    _load().orc_round_bf16_array(_ptr(a), _ptr(out), a.size)
+    return out
 
 
 def kernel_matrix(points, *, kernel="exp", ell=0.5, shift=1.0) -> np.ndarray:

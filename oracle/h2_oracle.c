@@ -642,6 +642,125 @@ void orc_forward_transform(const orc_h2 *h, int64_t m, const double *X, double *
 }
 
 /* ------------------------------------------------------------------------ */
+/* Low-precision operator (emulated).  V, E, S are rounded to the storage type
+ * (prec 1: FP32, 2: bfloat16), the near field to FP32; every small product
+ * rounds its right-hand factor to the same type and accumulates in FP32.
+ * bfloat16 rounding: the FP64 value is rounded to FP32 (nearest even), then
+ * the FP32 value to bfloat16 (nearest even on the upper 16 bits).            */
+
+static float orc_round_bf16(float f) {
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) { u |= 0x00400000u; }
+    else u = u + 0x7fffu + ((u >> 16) & 1u);
+    u &= 0xffff0000u;
+    float r;
+    memcpy(&r, &u, 4);
+    return r;
+}
+
+/* exported for the rounding pin: bfloat16 rounding of FP32 values */
+void orc_round_bf16_array(const float *in, float *out, int64_t count) {
+    for (int64_t i = 0; i < count; ++i) out[i] = orc_round_bf16(in[i]);
+}
+
+/* round an FP64 value to the storage type, returned as FP32 */
+static float orc_q(int prec, double v) {
+    float f = (float)v;
+    return prec == 2 ? orc_round_bf16(f) : f;
+}
+
+void orc_matmul_lowp(const orc_h2 *h, int prec, int64_t m, double alpha, const double *X, double beta, double *Y) {
+    const int k = h->k;
+    const int64_t n = h->n;
+    size_t cw = (size_t)h->C * k * m;
+    float *xh = calloc(cw ? cw : 1, sizeof(float)), *yh = calloc(cw ? cw : 1, sizeof(float));
+    float *acc = calloc((size_t)n * m, sizeof(float));
+    for (int64_t i = 0; i < n * m; ++i) Y[i] = (beta == 0.0) ? 0.0 : beta * Y[i];
+    /* forward: leaves, then transfers bottom-up */
+    for (int64_t s = 0; s < h->C; ++s) {
+        if (!orc_is_leaf(h, s)) continue;
+        for (int nu = 0; nu < k; ++nu)
+            for (int64_t j = 0; j < m; ++j) {
+                float a = 0.0f;
+                for (int64_t i = 0; i < h->size[s]; ++i) {
+                    int64_t row = h->first[s] + i;
+                    a += orc_q(prec, h->V[row * k + nu]) * orc_q(prec, X[h->perm[row] * m + j]);
+                }
+                xh[((size_t)s * k + nu) * m + j] = a;
+            }
+    }
+    for (int64_t s = h->C - 1; s >= 0; --s) {
+        if (orc_is_leaf(h, s)) continue;
+        int64_t sons[2] = {h->son0[s], h->son1[s]};
+        for (int nu = 0; nu < k; ++nu)
+            for (int64_t j = 0; j < m; ++j) {
+                float a = 0.0f;
+                for (int q = 0; q < 2; ++q) {
+                    const double *E = &h->E[(size_t)sons[q] * k * k];
+                    for (int b = 0; b < k; ++b)
+                        a += orc_q(prec, E[b * k + nu]) * orc_q(prec, xh[((size_t)sons[q] * k + b) * m + j]);
+                }
+                xh[((size_t)s * k + nu) * m + j] = a;
+            }
+    }
+    /* multiplication phase, every cluster's list */
+    for (int64_t t = 0; t < h->C; ++t)
+        for (int nu = 0; nu < k; ++nu)
+            for (int64_t j = 0; j < m; ++j) {
+                float a = 0.0f;
+                for (int64_t q = h->list_ptr[t]; q < h->list_ptr[t + 1]; ++q) {
+                    int64_t b = h->list_blk[q], s = h->bs[b];
+                    if (!h->badm[b]) continue;
+                    const double *Sb = &h->S[h->boff[b]];
+                    for (int mu = 0; mu < k; ++mu)
+                        a += orc_q(prec, Sb[nu * k + mu]) * orc_q(prec, xh[((size_t)s * k + mu) * m + j]);
+                }
+                yh[((size_t)t * k + nu) * m + j] = a;
+            }
+    /* backward transfers top-down (pre-order visits parents first) */
+    for (int64_t c = 1; c < h->C; ++c) {
+        int64_t par = h->parent[c];
+        const double *E = &h->E[(size_t)c * k * k];
+        for (int b = 0; b < k; ++b)
+            for (int64_t j = 0; j < m; ++j) {
+                float a = 0.0f;
+                for (int nu = 0; nu < k; ++nu) a += orc_q(prec, E[b * k + nu]) * orc_q(prec, yh[((size_t)par * k + nu) * m + j]);
+                yh[((size_t)c * k + b) * m + j] += a;
+            }
+    }
+    /* leaves: basis and near field, accumulated together in FP32 */
+    for (int64_t t = 0; t < h->C; ++t) {
+        if (!orc_is_leaf(h, t)) continue;
+        for (int64_t i = 0; i < h->size[t]; ++i) {
+            int64_t row = h->first[t] + i;
+            for (int64_t j = 0; j < m; ++j) {
+                float a = 0.0f;
+                for (int nu = 0; nu < k; ++nu) a += orc_q(prec, h->V[row * k + nu]) * orc_q(prec, yh[((size_t)t * k + nu) * m + j]);
+                for (int64_t q = h->list_ptr[t]; q < h->list_ptr[t + 1]; ++q) {
+                    int64_t b = h->list_blk[q], s = h->bs[b];
+                    if (h->badm[b]) continue;
+                    const double *Nb = &h->N[h->boff[b]];
+                    int64_t ns = h->size[s];
+                    for (int64_t c = 0; c < ns; ++c)
+                        a += (float)Nb[i * ns + c] * (float)X[h->perm[h->first[s] + c] * m + j];
+                }
+                Y[h->perm[row] * m + j] += alpha * (double)a;
+            }
+        }
+    }
+    free(xh); free(yh); free(acc);
+}
+
+/* Mixed-precision solve: FP64 iterative refinement around block CG with the
+ * low-precision operator.  Outer step: R = B - A X with the FP64 operator; stop
+ * when every column has ||R_i|| <= rtol ||B_i||; otherwise solve A_lo D = R by
+ * block CG (FP64 vectors and dot products) to inner_rtol and set X += D.
+ * Returns the number of outer steps; *inner_total receives the inner iterations. */
+int64_t orc_refine_cg(const orc_h2 *h, int prec, int64_t m, const double *B, double *X, double rtol,
+                      double inner_rtol, int64_t max_outer, int64_t max_inner, int64_t *inner_total);
+
+/* ------------------------------------------------------------------------ */
 /* Dense assembly of A_H2 from its definition (n x n, original order)         */
 
 /* full cluster basis V_t (|t| x k): leaf matrix, or [V_{t0} E_{t0}; V_{t1} E_{t1}] */
@@ -759,8 +878,25 @@ static double orc_dot_col(int64_t n, int64_t m, const double *u, const double *v
  * i first met the tolerance (what a single-RHS CG would run); status[i]: 0 ok,
  * 1 breakdown (frozen), 2 not converged within max_iter.
  */
+typedef void (*orc_op_fn)(const orc_h2 *h, int prec, int64_t m, double alpha, const double *X, double beta, double *Y);
+
+static void orc_op_f64(const orc_h2 *h, int prec, int64_t m, double alpha, const double *X, double beta, double *Y) {
+    (void)prec;
+    orc_matmul(h, m, alpha, X, beta, Y);
+}
+
+static int64_t orc_block_cg_op(const orc_h2 *h, orc_op_fn op, int prec, int64_t m, const double *B, double *X,
+                               double rtol, int64_t max_iter, int freeze_converged, int64_t *col_iters,
+                               int32_t *status);
+
 int64_t orc_block_cg(const orc_h2 *h, int64_t m, const double *B, double *X, double rtol,
                      int64_t max_iter, int freeze_converged, int64_t *col_iters, int32_t *status) {
+    return orc_block_cg_op(h, orc_op_f64, 0, m, B, X, rtol, max_iter, freeze_converged, col_iters, status);
+}
+
+static int64_t orc_block_cg_op(const orc_h2 *h, orc_op_fn op, int prec, int64_t m, const double *B, double *X,
+                               double rtol, int64_t max_iter, int freeze_converged, int64_t *col_iters,
+                               int32_t *status) {
     const int64_t n = h->n;
     double *R = malloc(sizeof(double) * n * m), *P = malloc(sizeof(double) * n * m);
     double *Ap = malloc(sizeof(double) * n * m);
@@ -770,7 +906,7 @@ int64_t orc_block_cg(const orc_h2 *h, int64_t m, const double *B, double *X, dou
     for (int64_t i = 0; i < n * m; ++i) if (X[i] != 0.0) { x0_zero = 0; break; }
     if (x0_zero) memcpy(R, B, sizeof(double) * n * m);
     else {
-        orc_matmul(h, m, 1.0, X, 0.0, R);
+        op(h, prec, m, 1.0, X, 0.0, R);
         for (int64_t i = 0; i < n * m; ++i) R[i] = B[i] - R[i];
     }
     memcpy(P, R, sizeof(double) * n * m);
@@ -797,7 +933,7 @@ int64_t orc_block_cg(const orc_h2 *h, int64_t m, const double *B, double *X, dou
             free(conv);
             break;
         }
-        orc_matmul(h, m, 1.0, P, 0.0, Ap);
+        op(h, prec, m, 1.0, P, 0.0, Ap);
         for (int64_t j = 0; j < m; ++j) {
             if (frozen[j] || (freeze_converged && conv[j])) continue;
             /* an exactly zero residual is an exact solution: nothing to update (the
@@ -818,6 +954,39 @@ int64_t orc_block_cg(const orc_h2 *h, int64_t m, const double *B, double *X, dou
     }
     free(R); free(P); free(Ap); free(bn); free(frozen); free(seen);
     return it;
+}
+
+static void orc_op_lowp(const orc_h2 *h, int prec, int64_t m, double alpha, const double *X, double beta, double *Y) {
+    orc_matmul_lowp(h, prec, m, alpha, X, beta, Y);
+}
+
+int64_t orc_block_cg_lowp(const orc_h2 *h, int prec, int64_t m, const double *B, double *X, double rtol,
+                          int64_t max_iter, int64_t *col_iters, int32_t *status) {
+    return orc_block_cg_op(h, orc_op_lowp, prec, m, B, X, rtol, max_iter, 0, col_iters, status);
+}
+
+int64_t orc_refine_cg(const orc_h2 *h, int prec, int64_t m, const double *B, double *X, double rtol,
+                      double inner_rtol, int64_t max_outer, int64_t max_inner, int64_t *inner_total) {
+    const int64_t n = h->n;
+    double *R = malloc(sizeof(double) * n * m), *D = malloc(sizeof(double) * n * m);
+    int64_t *ci = malloc(sizeof(int64_t) * m);
+    int32_t *st = malloc(sizeof(int32_t) * m);
+    *inner_total = 0;
+    int64_t outer = 0;
+    for (;;) {
+        memcpy(R, B, sizeof(double) * n * m);
+        orc_matmul(h, m, -1.0, X, 1.0, R);
+        int done = 1;
+        for (int64_t j = 0; j < m; ++j)
+            if (sqrt(orc_dot_col(n, m, R, R, j)) > rtol * sqrt(orc_dot_col(n, m, B, B, j))) done = 0;
+        if (done || outer >= max_outer) break;
+        memset(D, 0, sizeof(double) * n * m);
+        *inner_total += orc_block_cg_op(h, orc_op_lowp, prec, m, R, D, inner_rtol, max_inner, 0, ci, st);
+        for (int64_t i = 0; i < n * m; ++i) X[i] += D[i];
+        outer++;
+    }
+    free(R); free(D); free(ci); free(st);
+    return outer;
 }
 
 /* The paper's single-RHS CG (relative stopping rule), for the per-column pin. */

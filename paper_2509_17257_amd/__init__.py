@@ -14,7 +14,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
-__all__ = ["Plan", "H2Matrix", "h2_matmul", "block_cg_solve", "library_path", "load_library",
+__all__ = ["Plan", "H2Matrix", "h2_matmul", "block_cg_solve", "block_cg_refine", "library_path", "load_library",
            "F64", "F32", "BF16", "TREE_ORDER"]
 
 F64, F32, BF16 = 0, 1, 2
@@ -51,7 +51,8 @@ class _CgParams(C.Structure):
 
 
 class _CgInfo(C.Structure):
-    _fields_ = [("iters", C.c_int32), ("status", C.c_int32), ("col_relres", C.POINTER(C.c_double)),
+    _fields_ = [("iters", C.c_int32), ("status", C.c_int32), ("outer_iters", C.c_int32),
+                ("col_relres", C.POINTER(C.c_double)),
                 ("col_iters", C.POINTER(C.c_int32)), ("col_status", C.POINTER(C.c_int32))]
 
 
@@ -80,6 +81,9 @@ def load_library():
         "h2x_matmul_timed": (C.c_int, [P, I64, D, P, I64, D, P, I64, I32, P, SZ, P, P]),
         "h2x_block_cg_workspace_bytes": (SZ, [P, I64]),
         "h2x_block_cg": (C.c_int, [P, C.POINTER(_CgParams), I64, P, I64, P, I64, P, SZ, C.POINTER(_CgInfo), P]),
+        "h2x_block_cg_refine_workspace_bytes": (SZ, [P, P, I64]),
+        "h2x_block_cg_refine": (C.c_int, [P, P, C.POINTER(_CgParams), D, I32, I64, P, I64, P, I64, P, SZ,
+                                          C.POINTER(_CgInfo), P]),
         "h2x_last_error": (C.c_char_p, []),
         "h2x_version": (C.c_char_p, []),
     }
@@ -231,6 +235,16 @@ class CgInfo:
     col_relres: np.ndarray
     col_iters: np.ndarray
     col_status: np.ndarray
+    outer_iters: int = 0
+
+
+def _new_info(m):
+    rel = np.zeros(m)
+    its = np.zeros(m, np.int32)
+    sts = np.zeros(m, np.int32)
+    info = _CgInfo(0, 0, 0, rel.ctypes.data_as(C.POINTER(C.c_double)), its.ctypes.data_as(C.POINTER(C.c_int32)),
+                   sts.ctypes.data_as(C.POINTER(C.c_int32)))
+    return info, rel, its, sts
 
 
 def block_cg_solve(A: H2Matrix, B, X0=None, *, rtol=1e-8, max_iter=10000, freeze_converged=False,
@@ -242,13 +256,30 @@ def block_cg_solve(A: H2Matrix, B, X0=None, *, rtol=1e-8, max_iter=10000, freeze
     n, m = B.shape
     X = torch.zeros_like(B) if X0 is None else X0.clone()
     ws = A.workspace(m, "cg")
-    rel = np.zeros(m)
-    its = np.zeros(m, np.int32)
-    sts = np.zeros(m, np.int32)
-    info = _CgInfo(0, 0, rel.ctypes.data_as(C.POINTER(C.c_double)), its.ctypes.data_as(C.POINTER(C.c_int32)),
-                   sts.ctypes.data_as(C.POINTER(C.c_int32)))
+    info, rel, its, sts = _new_info(m)
     prm = _CgParams(float(rtol), int(max_iter), int(bool(freeze_converged)), int(check_every))
     _check(load_library().h2x_block_cg(A._h, C.byref(prm), m, C.c_void_p(B.data_ptr()), B.stride(0),
                                        C.c_void_p(X.data_ptr()), X.stride(0), C.c_void_p(ws.data_ptr()), ws.numel(),
                                        C.byref(info), _stream(torch, B.device)), "h2x_block_cg")
     return X, CgInfo(info.iters, info.status, rel, its, sts)
+
+
+def block_cg_refine(A: H2Matrix, A_lo: H2Matrix, B, *, rtol=1e-10, inner_rtol=1e-4, max_outer=50,
+                    max_inner=10000, check_every=4):
+    """Mixed precision: FP64 refinement around block CG with the low-precision A_lo
+    (h2x_block_cg_refine).  A and A_lo must share one Plan.  Returns (X, CgInfo)."""
+    import torch
+    if B.dtype != torch.float64 or B.device.type != "cuda" or B.dim() != 2 or B.stride(1) != 1:
+        raise ValueError("B must be a row-major (n, m) float64 CUDA tensor")
+    n, m = B.shape
+    X = torch.zeros_like(B)
+    lib = load_library()
+    nb = lib.h2x_block_cg_refine_workspace_bytes(A._h, A_lo._h, m)
+    ws = torch.empty(max(nb, 256), dtype=torch.uint8, device=B.device)
+    info, rel, its, sts = _new_info(m)
+    prm = _CgParams(float(inner_rtol), int(max_inner), 0, int(check_every))
+    _check(lib.h2x_block_cg_refine(A._h, A_lo._h, C.byref(prm), float(rtol), int(max_outer), m,
+                                   C.c_void_p(B.data_ptr()), B.stride(0), C.c_void_p(X.data_ptr()), X.stride(0),
+                                   C.c_void_p(ws.data_ptr()), ws.numel(), C.byref(info), _stream(torch, B.device)),
+           "h2x_block_cg_refine")
+    return X, CgInfo(info.iters, info.status, rel, its, sts, info.outer_iters)

@@ -268,4 +268,23 @@ h2x_status h2x_block_cg(const h2x_mat *A, const h2x_cg_params *prm, int64_t m, c
     return run_block_cg(A->dm, *prm, m, B, ldb, X, ldx, (char *)dev_ws, ws_bytes, info, (hipStream_t)hip_stream);
 }
 
+size_t h2x_block_cg_refine_workspace_bytes(const h2x_mat *A, const h2x_mat *A_lo, int64_t m) {
+    if (!A || !A_lo || m < 1) return 0;
+    return refine_ws_bytes(A->dm, A_lo->dm, m);
+}
+
+h2x_status h2x_block_cg_refine(const h2x_mat *A, const h2x_mat *A_lo, const h2x_cg_params *inner, double rtol,
+                               int32_t max_outer, int64_t m, const double *B, int64_t ldb, double *X, int64_t ldx,
+                               void *dev_ws, size_t ws_bytes, h2x_cg_info *info, void *hip_stream) {
+    if (!A || !A_lo || !inner || !B || !X || !dev_ws) return fail(H2X_EINVAL, "h2x_block_cg_refine: NULL argument");
+    if (A->plan != A_lo->plan) return fail(H2X_EINVAL, "h2x_block_cg_refine: A and A_lo must share one plan");
+    if (A->dm.storage != H2X_F64) return fail(H2X_EINVAL, "h2x_block_cg_refine: A must be stored in FP64");
+    if (m < 1 || ldb < m || ldx < m) return fail(H2X_EINVAL, "h2x_block_cg_refine: need m >= 1, ldb >= m, ldx >= m");
+    if (!(rtol >= 0.0) || max_outer < 0 || !(inner->rtol >= 0.0) || inner->max_iter < 0)
+        return fail(H2X_EINVAL, "h2x_block_cg_refine: bad tolerance or iteration limit");
+    if (!aligned(dev_ws)) return fail(H2X_EINVAL, "h2x_block_cg_refine: workspace not 256-byte aligned");
+    return run_refine(A->dm, A_lo->dm, *inner, rtol, max_outer, m, B, ldb, X, ldx, (char *)dev_ws, ws_bytes, info,
+                      (hipStream_t)hip_stream);
+}
+
 }  // extern "C"

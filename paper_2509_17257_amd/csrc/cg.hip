@@ -232,9 +232,131 @@ CgWs cg_layout(const DevMat &dm, int64_t m, char *base) {
     return w;
 }
 
+// R = B (leading dimensions ldb -> m)
+__global__ void k_copy_ld(int64_t n, int64_t m, const double *__restrict__ src, int64_t lds, double *__restrict__ dst,
+                          int64_t ldd) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * m) return;
+    const int64_t i = e / m, j = e % m;
+    dst[i * ldd + j] = src[i * lds + j];
+}
+
+// X += D
+__global__ void k_axpy_ld(int64_t n, int64_t m, const double *__restrict__ D, double *__restrict__ X, int64_t ldx) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * m) return;
+    const int64_t i = e / m, j = e % m;
+    X[i * ldx + j] += D[e];
+}
+
+__global__ void k_zero(int64_t count, double *__restrict__ p) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < count) p[e] = 0.0;
+}
+
+// squared column norms of two n x m blocks, in a fixed order: out[0..m) and out[m..2m)
+__global__ void k_sum_parts(int64_t m, int nblk, const double *part, double *out) {
+    for (int64_t j = threadIdx.x; j < m; j += blockDim.x) {
+        out[j] = sum_part(part, 0, nblk, m, j);
+        out[m + j] = sum_part(part, 1, nblk, m, j);
+    }
+}
+
+struct RefineWs {
+    double *B, *R, *D, *part, *norms;
+    char *mm, *cg;
+    int nblk;
+    size_t bytes;
+};
+
+RefineWs refine_layout(const DevMat &hi, const DevMat &lo, int64_t m, char *base) {
+    RefineWs w{};
+    size_t off = 0;
+    auto carve = [&](size_t bytes) {
+        off = align_up(off);
+        char *p = base ? base + off : nullptr;
+        off += bytes;
+        return p;
+    };
+    const size_t nm = (size_t)hi.n * m * sizeof(double);
+    w.nblk = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (hi.n + 63) / 64));
+    w.B = (double *)carve(nm);
+    w.R = (double *)carve(nm);
+    w.D = (double *)carve(nm);
+    w.part = (double *)carve(2 * (size_t)w.nblk * m * sizeof(double));
+    w.norms = (double *)carve(2 * m * sizeof(double));
+    w.mm = carve(matmul_ws_bytes(hi, m));
+    w.cg = carve(cg_layout(lo, m, nullptr).bytes);
+    w.bytes = align_up(off);
+    return w;
+}
+
 }  // namespace
 
 size_t cg_ws_bytes(const DevMat &dm, int64_t m) { return cg_layout(dm, m, nullptr).bytes; }
+
+size_t refine_ws_bytes(const DevMat &hi, const DevMat &lo, int64_t m) { return refine_layout(hi, lo, m, nullptr).bytes; }
+
+h2x_status run_refine(const DevMat &hi, const DevMat &lo, const h2x_cg_params &inner, double rtol, int32_t max_outer,
+                      int64_t m, const double *B, int64_t ldb, double *X, int64_t ldx, char *ws, size_t ws_bytes,
+                      h2x_cg_info *info, hipStream_t st) {
+    RefineWs w = refine_layout(hi, lo, m, ws);
+    if (ws_bytes < w.bytes) {
+        set_error("h2x_block_cg_refine: workspace too small");
+        return H2X_ENOMEM;
+    }
+    const int64_t n = hi.n, nm = n * m;
+    const unsigned g1 = (unsigned)((nm + 255) / 256);
+    const dim3 gd(w.nblk, (unsigned)((m + kDotCols - 1) / kDotCols));
+    auto fail = [&](hipError_t e) {
+        set_error(std::string("h2x_block_cg_refine: ") + hipGetErrorString(e));
+        return H2X_EHIP;
+    };
+    hipLaunchKernelGGL(k_copy_ld, dim3(g1), dim3(256), 0, st, n, m, B, ldb, w.B, m);
+    std::vector<double> norms(2 * m);
+    int32_t outer = 0, inner_total = 0, status = H2X_OK;
+    for (;;) {
+        // R = B - A X in FP64; squared norms of R and B
+        hipLaunchKernelGGL(k_copy, dim3(g1), dim3(256), 0, st, nm, (const double *)w.B, w.R);
+        hipError_t e = run_matmul(hi, m, -1.0, X, ldx, 1.0, w.R, m, false, w.mm, st);
+        if (e != hipSuccess) return fail(e);
+        hipLaunchKernelGGL(k_dots, gd, dim3(256), 0, st, n, m, w.nblk, w.R, w.R, w.B, w.B, w.part,
+                           (const CgState *)nullptr);
+        hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, st, m, w.nblk, w.part, w.norms);
+        e = hipMemcpyAsync(norms.data(), w.norms, 2 * m * sizeof(double), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return fail(e);
+        bool done = true;
+        for (int64_t j = 0; j < m; ++j)
+            if (std::sqrt(norms[j]) > rtol * std::sqrt(norms[m + j])) done = false;
+        if (done) break;
+        if (outer >= max_outer) {
+            status = H2X_ENOCONV;
+            break;
+        }
+        // A_lo D = R by block CG, then X += D
+        hipLaunchKernelGGL(k_zero, dim3(g1), dim3(256), 0, st, nm, w.D);
+        h2x_cg_info ii{};
+        h2x_status s = run_block_cg(lo, inner, m, w.R, m, w.D, m, w.cg, cg_layout(lo, m, nullptr).bytes, &ii, st);
+        if (s != H2X_OK) return s;
+        inner_total += ii.iters;
+        hipLaunchKernelGGL(k_axpy_ld, dim3(g1), dim3(256), 0, st, n, m, w.D, X, ldx);
+        ++outer;
+    }
+    if (info) {
+        info->iters = inner_total;
+        info->outer_iters = outer;
+        info->status = status;
+        for (int64_t j = 0; j < m; ++j) {
+            const double rn = std::sqrt(norms[j]), bn = std::sqrt(norms[m + j]);
+            const double rel = bn > 0 ? rn / bn : rn;
+            if (info->col_relres) info->col_relres[j] = rel;
+            if (info->col_iters) info->col_iters[j] = inner_total;
+            if (info->col_status) info->col_status[j] = rel <= rtol ? 0 : 2;
+        }
+    }
+    return H2X_OK;
+}
 
 h2x_status run_block_cg(const DevMat &dm, const h2x_cg_params &prm, int64_t m, const double *B, int64_t ldb,
                         double *X, int64_t ldx, char *ws, size_t ws_bytes, h2x_cg_info *info, hipStream_t st) {
@@ -303,6 +425,7 @@ h2x_status run_block_cg(const DevMat &dm, const h2x_cg_params &prm, int64_t m, c
     if (info) {
         info->iters = hs.iter;
         info->status = status;
+        info->outer_iters = 0;
         for (int64_t j = 0; j < m; ++j) {
             if (info->col_relres) info->col_relres[j] = bn[j] > 0 ? std::sqrt(rr[j]) / bn[j] : std::sqrt(rr[j]);
             if (info->col_iters) info->col_iters[j] = fc[j] >= 0 ? fc[j] : hs.iter;

@@ -1,0 +1,69 @@
+"""Mixed precision on the GPU: FP32 / BF16 operators (FP32 accumulation) against
+the oracle's emulation of the same operator, and FP64 iterative refinement.
+
+Bars: the GPU low-precision product agrees with the oracle's emulated one to
+1e-5 (FP32) / 1e-4 (BF16) per column -- both accumulate in FP32 in different
+orders, and a bfloat16 rounding of an FP32 intermediate can fall on either side
+of a tie between the two orders; both differ from the FP64 product by an amount
+of the storage type's size; refinement reaches an FP64 true residual of 1e-10.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2509_17257_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = {"f32": 1e-5, "bf16": 1e-4}
+ERR_RANGE = {"f32": (1e-9, 2e-6), "bf16": (1e-4, 3e-2)}
+
+
+def _colrel(a, b):
+    return (np.linalg.norm(a - b, axis=0) / np.linalg.norm(b, axis=0)).max()
+
+
+CASES = [
+    ("small-k27-m4", lambda: W.SMALL.points(), W.SMALL.params(), 4),
+    ("sphere-k64-m32", lambda: W.sphere_points(5000, 131), dict(ell=0.5, shift=1.0, eta=1.0, leaf=64, p=4), 32),
+    ("cube-k64-m7", lambda: W.cube_points(6000, 132), dict(ell=0.25, shift=0.5, eta=1.0, leaf=64, p=4), 7),
+]
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+@pytest.mark.parametrize("name,pts,prm,m", CASES, ids=[c[0] for c in CASES])
+def test_lowp_product(name, pts, prm, m, prec):
+    import paper_2509_17257_amd as h2x
+    P = pts()
+    o = oracle.OracleH2(P, **prm)
+    A = h2x.H2Matrix(P, storage=prec, **prm)
+    X = W.rhs(P.shape[0], m, 133)
+    got = h2x.h2_matmul(A, torch.from_numpy(X).cuda()).cpu().numpy()
+    emu = o.matmul_lowp(X, prec)
+    ref = o.matmul(X)
+    e_emu, e64 = _colrel(got, emu), _colrel(got, ref)
+    print(f"{name} {prec}: vs emulated {e_emu:.2e}, vs FP64 {e64:.2e}")
+    assert e_emu <= TOL[prec]
+    lo, hi = ERR_RANGE[prec]
+    assert lo < e64 < hi
+
+
+@pytest.mark.parametrize("prec,inner", [("f32", 1e-5), ("bf16", 1e-2)])
+def test_refinement(prec, inner):
+    import paper_2509_17257_amd as h2x
+    w = W.SMALL
+    P = w.points()
+    o = oracle.OracleH2(P, **w.params())
+    plan = h2x.Plan(P, **w.params())
+    A = h2x.H2Matrix(plan, storage="f64")
+    A_lo = h2x.H2Matrix(plan, storage=prec)
+    B = w.rhs()
+    X, info = h2x.block_cg_refine(A, A_lo, torch.from_numpy(B).cuda(), rtol=1e-10, inner_rtol=inner)
+    X = X.cpu().numpy()
+    res = np.linalg.norm(B - o.matmul(X), axis=0) / np.linalg.norm(B, axis=0)
+    print(f"refine {prec}: outer {info.outer_iters}, inner {info.iters}, oracle residual {res.max():.2e}")
+    assert info.status == 0 and res.max() <= 1.5e-10
+    assert np.all(info.col_relres <= 1e-10)
+    Xf, _ = o.block_cg(B, rtol=1e-12)
+    assert _colrel(X, Xf) <= 1e-6

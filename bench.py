@@ -95,6 +95,77 @@ def cpu_baseline(w, P, X, plan, budget_s):
                        f"(OpenMP, forward / list-wise multiplication / backward of the paper)")
 
 
+def time_products(h2x, torch, A, X, Y, steps):
+    h2x.h2_matmul(A, X, out=Y)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        h2x.h2_matmul(A, X, out=Y)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def precision_report(args, torch, h2x, W):
+    """FP64, FP32 and BF16 operators on the precision workload (n = 262144 in the unit cube,
+    exp(-r/0.25) + 0.5 I, k = 64, m = 64): product time and algorithmic GB/s, error of each
+    product against the FP64 product, FP64 block CG to 1e-8 and FP64-refined solves to 1e-10."""
+    w = W.WORKLOADS["cube-n262144-k64-m64"]
+    dev = torch.device("cuda:0")
+    P = w.points()
+    t0 = time.perf_counter()
+    plan = h2x.Plan(P, **w.params())
+    log(f"[precision] plan {time.perf_counter() - t0:.1f} s: C={plan.C} adm={plan.n_adm} near={plan.near_entries}")
+    X = torch.from_numpy(w.rhs()).to(dev)
+    m = w.m
+    out = {"workload": w.name, "n": w.n, "k": w.k, "m": m, "n_adm": plan.n_adm, "near_entries": plan.near_entries}
+    ops = {}
+    Y64 = None
+    for prec, s_b, s_n in (("f64", 8, 8), ("f32", 4, 4), ("bf16", 2, 4)):
+        t0 = time.perf_counter()
+        A = h2x.H2Matrix(plan, storage=prec, device=dev)
+        torch.cuda.synchronize()
+        Y = torch.empty_like(X)
+        ms = time_products(h2x, torch, A, X, Y, args.steps)
+        B_alg = alg_bytes(plan, m, s_b=s_b, s_n=s_n)
+        rec = {"setup_s": round(time.perf_counter() - t0, 2), "ms_per_product": round(ms, 3),
+               "alg_gbs": round(B_alg / (ms * 1e-3) / 1e9, 1), "alg_bytes": int(B_alg)}
+        if prec == "f64":
+            Y64 = Y.clone()
+        else:
+            rec["max_col_rel_err_vs_f64"] = ((Y - Y64).norm(dim=0) / Y64.norm(dim=0)).max().item()
+        ops[prec] = A
+        out[prec] = rec
+        log(f"[precision] {prec}: {rec}")
+    B = X
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Xs, info = h2x.block_cg_solve(ops["f64"], B, rtol=1e-8, max_iter=args.max_cg_iter)
+    torch.cuda.synchronize()
+    out["cg_f64_1e-8"] = {"time_s": round(time.perf_counter() - t0, 3), "iters": info.iters, "status": info.status}
+    log(f"[precision] FP64 block CG to 1e-8: {out['cg_f64_1e-8']}")
+    t0 = time.perf_counter()
+    Xs, info = h2x.block_cg_solve(ops["f64"], B, rtol=1e-10, max_iter=args.max_cg_iter)
+    torch.cuda.synchronize()
+    out["cg_f64_1e-10"] = {"time_s": round(time.perf_counter() - t0, 3), "iters": info.iters, "status": info.status}
+    log(f"[precision] FP64 block CG to 1e-10: {out['cg_f64_1e-10']}")
+    for prec, inner in (("f32", 1e-6), ("bf16", 1e-2)):
+        t0 = time.perf_counter()
+        log(f"[precision] refining with the {prec} operator (inner rtol {inner})")
+        Xr, info = h2x.block_cg_refine(ops["f64"], ops[prec], B, rtol=1e-10, inner_rtol=inner, max_outer=6,
+                                       max_inner=args.max_cg_iter)
+        torch.cuda.synchronize()
+        R = torch.empty_like(B)
+        h2x.h2_matmul(ops["f64"], Xr, out=R)
+        res = ((B - R).norm(dim=0) / B.norm(dim=0)).max().item()
+        out[f"refine_{prec}_1e-10"] = {"time_s": round(time.perf_counter() - t0, 3), "outer": info.outer_iters,
+                                       "inner_iters": info.iters, "status": info.status, "true_relres": res,
+                                       "inner_rtol": inner}
+        log(f"[precision] refined {prec}: {out[f'refine_{prec}_1e-10']}")
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -102,7 +173,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="sphere-n65536-k64-m32")
     ap.add_argument("--cg", type=int, default=1, help="also time block CG to 1e-8")
+    ap.add_argument("--max-cg-iter", type=int, default=5000)
     ap.add_argument("--cpu-baseline-s", type=float, default=12.0, help="0 disables the oracle timing")
+    ap.add_argument("--precision-report", action="store_true",
+                    help="report FP64 / FP32 / BF16 products and FP64 vs refined block CG on the precision workload")
     ap.add_argument("--copy-calibration-gib", type=float, default=0.0,
                     help="only run a plain device copy of this many GiB (to scale HBM traffic counters) and exit")
     args = ap.parse_args()
@@ -138,6 +212,10 @@ def main():
         read_gbs = nbytes * reps / (e1.elapsed_time(e2) * 1e-3) / 1e9
         print(json.dumps({"copy_calibration_bytes": nbytes, "copies": reps + 1, "copy_gbs": round(copy_gbs, 1),
                           "read_gbs": round(read_gbs, 1)}), flush=True)
+        return
+
+    if args.precision_report:
+        precision_report(args, torch, h2x, W)
         return
 
     w = W.WORKLOADS[args.workload]

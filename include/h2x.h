@@ -187,7 +187,10 @@ h2x_status h2x_block_cg(const h2x_mat *A, const h2x_cg_params *prm, int64_t m, c
  * BF16 (its products accumulate in FP32).  Outer step: R = B - A X in FP64; stop
  * when every column has ||R_i|| <= rtol ||B_i||; otherwise solve A_lo D = R with
  * block CG (FP64 vectors, dot products and step sizes) to inner->rtol relative to
- * ||R_i||, and set X += D.  At most max_outer steps.  Blocking.  info->iters is the
+ * ||R_i||, and set X += D.  At most max_outer steps; a step that does not halve
+ * the worst column's relative residual is a stall, and two stalls end the solve
+ * with H2X_ENOCONV (the low-precision operator is too far from A for this
+ * system's conditioning).  Blocking.  info->iters is the
  * total number of inner iterations, info->outer_iters the number of steps,
  * info->col_relres the final FP64 true residuals ||B_i - A X_i|| / ||B_i||,
  * info->status H2X_ENOCONV if rtol was not met. */

@@ -755,7 +755,9 @@ void orc_matmul_lowp(const orc_h2 *h, int prec, int64_t m, double alpha, const d
 /* Mixed-precision solve: FP64 iterative refinement around block CG with the
  * low-precision operator.  Outer step: R = B - A X with the FP64 operator; stop
  * when every column has ||R_i|| <= rtol ||B_i||; otherwise solve A_lo D = R by
- * block CG (FP64 vectors and dot products) to inner_rtol and set X += D.
+ * block CG (FP64 vectors and dot products) to inner_rtol and set X += D.  A step
+ * that does not halve the worst column's relative residual is a stall; the
+ * refinement stops after two (the low-precision operator is then too far from A).
  * Returns the number of outer steps; *inner_total receives the inner iterations. */
 int64_t orc_refine_cg(const orc_h2 *h, int prec, int64_t m, const double *B, double *X, double rtol,
                       double inner_rtol, int64_t max_outer, int64_t max_inner, int64_t *inner_total);
@@ -972,14 +974,22 @@ int64_t orc_refine_cg(const orc_h2 *h, int prec, int64_t m, const double *B, dou
     int64_t *ci = malloc(sizeof(int64_t) * m);
     int32_t *st = malloc(sizeof(int32_t) * m);
     *inner_total = 0;
-    int64_t outer = 0;
+    int64_t outer = 0, stalls = 0;
+    double prev = INFINITY;
     for (;;) {
         memcpy(R, B, sizeof(double) * n * m);
         orc_matmul(h, m, -1.0, X, 1.0, R);
         int done = 1;
-        for (int64_t j = 0; j < m; ++j)
-            if (sqrt(orc_dot_col(n, m, R, R, j)) > rtol * sqrt(orc_dot_col(n, m, B, B, j))) done = 0;
-        if (done || outer >= max_outer) break;
+        double worst = 0.0;
+        for (int64_t j = 0; j < m; ++j) {
+            double rel = sqrt(orc_dot_col(n, m, R, R, j)) / sqrt(orc_dot_col(n, m, B, B, j));
+            if (rel > rtol) done = 0;
+            if (rel > worst) worst = rel;
+        }
+        /* a step that does not halve the worst relative residual is a stall; two stalls stop */
+        if (worst > 0.5 * prev) stalls++;
+        prev = worst;
+        if (done || outer >= max_outer || stalls >= 2) break;
         memset(D, 0, sizeof(double) * n * m);
         *inner_total += orc_block_cg_op(h, orc_op_lowp, prec, m, R, D, inner_rtol, max_inner, 0, ci, st);
         for (int64_t i = 0; i < n * m; ++i) X[i] += D[i];

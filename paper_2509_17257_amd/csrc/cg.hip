@@ -314,7 +314,8 @@ h2x_status run_refine(const DevMat &hi, const DevMat &lo, const h2x_cg_params &i
     };
     hipLaunchKernelGGL(k_copy_ld, dim3(g1), dim3(256), 0, st, n, m, B, ldb, w.B, m);
     std::vector<double> norms(2 * m);
-    int32_t outer = 0, inner_total = 0, status = H2X_OK;
+    int32_t outer = 0, inner_total = 0, status = H2X_OK, stalls = 0;
+    double prev = HUGE_VAL;
     for (;;) {
         // R = B - A X in FP64; squared norms of R and B
         hipLaunchKernelGGL(k_copy, dim3(g1), dim3(256), 0, st, nm, (const double *)w.B, w.R);
@@ -327,10 +328,17 @@ h2x_status run_refine(const DevMat &hi, const DevMat &lo, const h2x_cg_params &i
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         if (e != hipSuccess) return fail(e);
         bool done = true;
-        for (int64_t j = 0; j < m; ++j)
-            if (std::sqrt(norms[j]) > rtol * std::sqrt(norms[m + j])) done = false;
+        double worst = 0.0;
+        for (int64_t j = 0; j < m; ++j) {
+            const double bn = std::sqrt(norms[m + j]), rn = std::sqrt(norms[j]);
+            if (rn > rtol * bn) done = false;
+            worst = std::max(worst, bn > 0 ? rn / bn : rn);
+        }
+        // a step that does not halve the worst relative residual is a stall; two stalls stop
+        if (worst > 0.5 * prev) ++stalls;
+        prev = worst;
         if (done) break;
-        if (outer >= max_outer) {
+        if (outer >= max_outer || stalls >= 2) {
             status = H2X_ENOCONV;
             break;
         }

@@ -314,8 +314,18 @@ def main():
         h2x.h2_matmul(A, Xs, out=R)
         res = ((B - R).norm(dim=0) / B.norm(dim=0)).max().item()
         out["block_cg"] = {"rtol": 1e-8, "time_s": round(cg_s, 4), "iters": info.iters, "status": info.status,
-                           "max_true_relres": res, "precision": "f64"}
+                           "max_true_relres": res, "precision": "f64", "variant": "independent"}
         log(f"[bench] block CG: {info.iters} iterations, {cg_s:.3f} s, true rel res {res:.2e}")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Xs, info = h2x.block_cg_solve(A, B, rtol=1e-8, max_iter=5000, variant="shared")
+        torch.cuda.synchronize()
+        cg_s = time.perf_counter() - t0
+        h2x.h2_matmul(A, Xs, out=R)
+        res = ((B - R).norm(dim=0) / B.norm(dim=0)).max().item()
+        out["block_cg_shared"] = {"rtol": 1e-8, "time_s": round(cg_s, 4), "iters": info.iters, "status": info.status,
+                                  "max_true_relres": res, "precision": "f64", "variant": "shared"}
+        log(f"[bench] shared-space block CG: {info.iters} iterations, {cg_s:.3f} s, true rel res {res:.2e}")
 
     if args.cpu_baseline_s > 0:
         log(f"[bench] timing the CPU oracle for ~{args.cpu_baseline_s:.0f} s")

@@ -156,7 +156,19 @@ typedef struct {
     int32_t freeze_converged; /* 0: converged columns keep iterating (the paper's rule);
                                  1: converged columns stop updating                       */
     int32_t check_every;      /* read the device convergence flag every this many steps */
+    int32_t variant;          /* H2X_CG_INDEPENDENT or H2X_CG_SHARED                     */
 } h2x_cg_params;
+
+/* H2X_CG_INDEPENDENT: the paper's block CG -- m independent CG iterations that
+ *   share only the H^2 x P product (section 5.1).
+ * H2X_CG_SHARED: block CG over one shared block Krylov space (O'Leary's block CG,
+ *   which the paper cites as the alternative that enriches the Krylov space):
+ *   m x m Gram matrices, their Cholesky factorizations and a Cholesky-QR
+ *   orthonormalisation of the search block with deflation of directions whose
+ *   remaining norm falls below 1e-6 of the largest; m <= 64; freeze_converged
+ *   and check_every are ignored (convergence is read every iteration). */
+#define H2X_CG_INDEPENDENT 0
+#define H2X_CG_SHARED 1
 
 typedef struct {
     int32_t iters;       /* iterations of the shared loop (refined solve: all inner iterations) */

@@ -68,6 +68,8 @@ def _load():
     lib.orc_refine_cg.restype = I64
     lib.orc_refine_cg.argtypes = [P, C.c_int, I64, P, P, D, D, I64, I64, P]
     lib.orc_round_bf16_array.argtypes = [P, P, I64]
+    lib.orc_block_cg_shared.restype = I64
+    lib.orc_block_cg_shared.argtypes = [P, I64, P, P, D, I64, D, P, P]
     lib.orc_num_threads.restype = C.c_int
     lib.orc_set_threads.argtypes = [C.c_int]
     _lib = lib
@@ -249,6 +251,18 @@ class OracleH2:
         it = _load().orc_block_cg(self._h, m, _ptr(B), _ptr(X), float(rtol), int(max_iter),
                                   int(bool(freeze_converged)), _ptr(ci), _ptr(st))
         return X, dict(iters=int(it), col_iters=ci, status=st)
+
+    def block_cg_shared(self, B, X0=None, rtol=1e-8, max_iter=10000, drop=1e-6):
+        """Block CG over one shared block Krylov space (m x m Gram matrices, Cholesky,
+        Cholesky-QR orthonormalisation with deflation of dependent directions)."""
+        B = np.ascontiguousarray(B, dtype=np.float64)
+        m = B.shape[1]
+        X = np.zeros_like(B) if X0 is None else np.ascontiguousarray(X0, dtype=np.float64).copy()
+        rk = np.zeros(1, np.int64)
+        st = np.zeros(m, np.int32)
+        it = _load().orc_block_cg_shared(self._h, m, _ptr(B), _ptr(X), float(rtol), int(max_iter), float(drop),
+                                         _ptr(rk), _ptr(st))
+        return X, dict(iters=int(it), rank_min=int(rk[0]), status=st)
 
     def cg1(self, b, x0=None, rtol=1e-8, max_iter=10000):
         b = np.ascontiguousarray(b, dtype=np.float64).reshape(-1)

@@ -999,6 +999,185 @@ int64_t orc_refine_cg(const orc_h2 *h, int prec, int64_t m, const double *B, dou
     return outer;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Block CG with one shared block Krylov space (O'Leary's block CG, cited by  */
+/* the paper as the alternative that enriches the Krylov space).  The search  */
+/* block is kept orthonormal; directions that become linearly dependent are  */
+/* dropped (deflation), so the m x m Gram matrices stay positive definite.    */
+
+/* G = U^T V for n x m blocks (m x m, row-major) */
+static void orc_gram(int64_t n, int64_t m, const double *U, const double *V, double *G) {
+    for (int64_t a = 0; a < m; ++a)
+        for (int64_t b = 0; b < m; ++b) {
+            double acc = 0.0;
+            for (int64_t i = 0; i < n; ++i) acc += U[i * m + a] * V[i * m + b];
+            G[a * m + b] = acc;
+        }
+}
+
+/* Y += sign * U C for an n x m block U and an m x m matrix C */
+static void orc_block_axpy(int64_t n, int64_t m, double sign, const double *U, const double *C, double *Y) {
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t b = 0; b < m; ++b) {
+            double acc = 0.0;
+            for (int64_t a = 0; a < m; ++a) acc += U[i * m + a] * C[a * m + b];
+            Y[i * m + b] += sign * acc;
+        }
+}
+
+/* Orthonormalise the columns of Z (n x m) into P: pivoted Cholesky of W = Z^T Z
+ * picks the columns in order of decreasing remaining norm and stops when the
+ * remaining squared norm is below drop^2 times the largest initial one; the kept
+ * columns give P = Z_kept L^{-T}; a second Cholesky QR of the kept block (no
+ * pivoting, no dropping) restores FP64 orthogonality.  Dropped columns of P are
+ * zero; active[j] marks kept columns.  Returns the rank.
+ * lv[q * m + j] is the factor entry of column j at pivot step q, dg[q] its diagonal. */
+static void orc_apply_inv_lt(int64_t n, int64_t m, int64_t rank, const int64_t *piv, const double *lv,
+                             const double *dg, const double *T, double *P) {
+    memset(P, 0, sizeof(double) * n * m);
+    for (int64_t q = 0; q < rank; ++q) {
+        int64_t c = piv[q];
+        for (int64_t i = 0; i < n; ++i) {
+            double v = T[i * m + c];
+            for (int64_t r = 0; r < q; ++r) v -= P[i * m + piv[r]] * lv[r * m + c];
+            P[i * m + c] = v / dg[q];
+        }
+    }
+}
+
+static int64_t orc_orth(int64_t n, int64_t m, const double *Z, double *P, int *active, double drop) {
+    double *W = malloc(sizeof(double) * m * m), *lv = calloc(m * m, sizeof(double));
+    double *dg = malloc(sizeof(double) * m), *d = malloc(sizeof(double) * m);
+    double *T = malloc(sizeof(double) * n * m);
+    int64_t *piv = malloc(sizeof(int64_t) * m);
+    /* pass 1: pivoted Cholesky of Z^T Z with dropping */
+    orc_gram(n, m, Z, Z, W);
+    double dmax = 0.0;
+    for (int64_t j = 0; j < m; ++j) {
+        d[j] = W[j * m + j];
+        active[j] = 0;
+        if (d[j] > dmax) dmax = d[j];
+    }
+    int64_t rank = 0;
+    while (rank < m) {
+        int64_t best = -1;
+        for (int64_t j = 0; j < m; ++j)
+            if (!active[j] && (best < 0 || d[j] > d[best])) best = j;
+        if (!(dmax > 0.0) || !(d[best] > drop * drop * dmax)) break;
+        active[best] = 1;
+        piv[rank] = best;
+        dg[rank] = sqrt(d[best]);
+        for (int64_t j = 0; j < m; ++j) {
+            if (active[j]) continue;
+            double v = W[j * m + best];
+            for (int64_t q = 0; q < rank; ++q) v -= lv[q * m + j] * lv[q * m + best];
+            lv[rank * m + j] = v / dg[rank];
+            d[j] -= lv[rank * m + j] * lv[rank * m + j];
+        }
+        rank++;
+    }
+    orc_apply_inv_lt(n, m, rank, piv, lv, dg, Z, P);
+    /* pass 2: Cholesky QR of the kept block, same pivot order */
+    memcpy(T, P, sizeof(double) * n * m);
+    orc_gram(n, m, T, T, W);
+    memset(lv, 0, sizeof(double) * m * m);
+    for (int64_t q = 0; q < rank; ++q) {
+        int64_t c = piv[q];
+        double v = W[c * m + c];
+        for (int64_t r = 0; r < q; ++r) v -= lv[r * m + c] * lv[r * m + c];
+        dg[q] = sqrt(v > 0.0 ? v : 0.0);
+        for (int64_t q2 = q + 1; q2 < rank; ++q2) {
+            int64_t c2 = piv[q2];
+            double u = W[c2 * m + c];
+            for (int64_t r = 0; r < q; ++r) u -= lv[r * m + c2] * lv[r * m + c];
+            lv[q * m + c2] = u / dg[q];
+        }
+    }
+    orc_apply_inv_lt(n, m, rank, piv, lv, dg, T, P);
+    free(W); free(lv); free(dg); free(d); free(T); free(piv);
+    return rank;
+}
+
+/* Solve G C = F for the active indices (G symmetric positive definite on them),
+ * C and F m x m; inactive rows of C are zero.  Returns 0, or 1 if G is not
+ * positive definite on the active set. */
+static int orc_spd_solve(int64_t m, const int *active, const double *G, const double *F, double *C) {
+    int64_t r = 0, *idx = malloc(sizeof(int64_t) * m);
+    for (int64_t j = 0; j < m; ++j) if (active[j]) idx[r++] = j;
+    double *L = calloc(r > 0 ? r * r : 1, sizeof(double));
+    int bad = 0;
+    for (int64_t a = 0; a < r && !bad; ++a) {
+        double v = G[idx[a] * m + idx[a]];
+        for (int64_t q = 0; q < a; ++q) v -= L[a * r + q] * L[a * r + q];
+        if (!(v > 0.0)) { bad = 1; break; }
+        L[a * r + a] = sqrt(v);
+        for (int64_t b = a + 1; b < r; ++b) {
+            double u = G[idx[b] * m + idx[a]];
+            for (int64_t q = 0; q < a; ++q) u -= L[b * r + q] * L[a * r + q];
+            L[b * r + a] = u / L[a * r + a];
+        }
+    }
+    memset(C, 0, sizeof(double) * m * m);
+    if (!bad)
+        for (int64_t col = 0; col < m; ++col) {
+            double *y = malloc(sizeof(double) * (r ? r : 1));
+            for (int64_t a = 0; a < r; ++a) {  /* L y = F[idx, col] */
+                double v = F[idx[a] * m + col];
+                for (int64_t q = 0; q < a; ++q) v -= L[a * r + q] * y[q];
+                y[a] = v / L[a * r + a];
+            }
+            for (int64_t a = r - 1; a >= 0; --a) {  /* L^T c = y */
+                double v = y[a];
+                for (int64_t q = a + 1; q < r; ++q) v -= L[q * r + a] * C[idx[q] * m + col];
+                C[idx[a] * m + col] = v / L[a * r + a];
+            }
+            free(y);
+        }
+    free(L); free(idx);
+    return bad;
+}
+
+/* Returns the number of iterations; *rank_min receives the smallest rank of the
+ * search block; status[j]: 0 converged, 2 not converged, 1 breakdown. */
+int64_t orc_block_cg_shared(const orc_h2 *h, int64_t m, const double *B, double *X, double rtol, int64_t max_iter,
+                            double drop, int64_t *rank_min, int32_t *status) {
+    const int64_t n = h->n;
+    double *R = malloc(sizeof(double) * n * m), *P = malloc(sizeof(double) * n * m);
+    double *Q = malloc(sizeof(double) * n * m), *Z = malloc(sizeof(double) * n * m);
+    double *G = malloc(sizeof(double) * m * m), *F = malloc(sizeof(double) * m * m);
+    double *Lam = malloc(sizeof(double) * m * m), *bn = malloc(sizeof(double) * m);
+    int *active = malloc(sizeof(int) * m);
+    orc_matmul(h, m, 1.0, X, 0.0, R);
+    for (int64_t i = 0; i < n * m; ++i) R[i] = B[i] - R[i];
+    for (int64_t j = 0; j < m; ++j) { bn[j] = sqrt(orc_dot_col(n, m, B, B, j)); status[j] = 0; }
+    *rank_min = orc_orth(n, m, R, P, active, drop);
+    int64_t it = 0;
+    int broke = 0;
+    for (;;) {
+        int all = 1;
+        for (int64_t j = 0; j < m; ++j)
+            if (sqrt(orc_dot_col(n, m, R, R, j)) > rtol * bn[j]) all = 0;
+        if (all || it >= max_iter) break;
+        orc_matmul(h, m, 1.0, P, 0.0, Q);
+        orc_gram(n, m, P, Q, G);          /* G = P^T A P */
+        orc_gram(n, m, P, R, F);          /* F = P^T R   */
+        if (orc_spd_solve(m, active, G, F, Lam)) { broke = 1; break; }
+        orc_block_axpy(n, m, 1.0, P, Lam, X);
+        orc_block_axpy(n, m, -1.0, Q, Lam, R);
+        orc_gram(n, m, Q, R, F);          /* F = (A P)^T R */
+        if (orc_spd_solve(m, active, G, F, Lam)) { broke = 1; break; }
+        memcpy(Z, R, sizeof(double) * n * m);
+        orc_block_axpy(n, m, -1.0, P, Lam, Z);  /* Z = R + P Psi, Psi = -G^{-1} (A P)^T R */
+        int64_t r = orc_orth(n, m, Z, P, active, drop);
+        if (r < *rank_min) *rank_min = r;
+        it++;
+    }
+    for (int64_t j = 0; j < m; ++j)
+        if (sqrt(orc_dot_col(n, m, R, R, j)) > rtol * bn[j]) status[j] = broke ? 1 : 2;
+    free(R); free(P); free(Q); free(Z); free(G); free(F); free(Lam); free(bn); free(active);
+    return it;
+}
+
 /* The paper's single-RHS CG (relative stopping rule), for the per-column pin. */
 int64_t orc_cg1(const orc_h2 *h, const double *b, double *x, double rtol, int64_t max_iter) {
     const int64_t n = h->n;

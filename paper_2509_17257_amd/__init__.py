@@ -47,7 +47,11 @@ class _Stats(C.Structure):
 
 class _CgParams(C.Structure):
     _fields_ = [("rtol", C.c_double), ("max_iter", C.c_int32), ("freeze_converged", C.c_int32),
-                ("check_every", C.c_int32)]
+                ("check_every", C.c_int32), ("variant", C.c_int32)]
+
+
+CG_INDEPENDENT, CG_SHARED = 0, 1
+_VARIANT = {"independent": CG_INDEPENDENT, "shared": CG_SHARED, CG_INDEPENDENT: CG_INDEPENDENT, CG_SHARED: CG_SHARED}
 
 
 class _CgInfo(C.Structure):
@@ -248,8 +252,10 @@ def _new_info(m):
 
 
 def block_cg_solve(A: H2Matrix, B, X0=None, *, rtol=1e-8, max_iter=10000, freeze_converged=False,
-                   check_every=4):
-    """Solve A X = B (block CG, h2x_block_cg).  Returns (X, CgInfo)."""
+                   check_every=4, variant="independent"):
+    """Solve A X = B (block CG, h2x_block_cg).  variant "independent": the paper's m
+    independent CG iterations sharing the product; "shared": one shared block Krylov
+    space with m x m Gram matrices.  Returns (X, CgInfo)."""
     import torch
     if B.dtype != torch.float64 or B.device.type != "cuda" or B.dim() != 2 or B.stride(1) != 1:
         raise ValueError("B must be a row-major (n, m) float64 CUDA tensor")
@@ -257,7 +263,7 @@ def block_cg_solve(A: H2Matrix, B, X0=None, *, rtol=1e-8, max_iter=10000, freeze
     X = torch.zeros_like(B) if X0 is None else X0.clone()
     ws = A.workspace(m, "cg")
     info, rel, its, sts = _new_info(m)
-    prm = _CgParams(float(rtol), int(max_iter), int(bool(freeze_converged)), int(check_every))
+    prm = _CgParams(float(rtol), int(max_iter), int(bool(freeze_converged)), int(check_every), _VARIANT[variant])
     _check(load_library().h2x_block_cg(A._h, C.byref(prm), m, C.c_void_p(B.data_ptr()), B.stride(0),
                                        C.c_void_p(X.data_ptr()), X.stride(0), C.c_void_p(ws.data_ptr()), ws.numel(),
                                        C.byref(info), _stream(torch, B.device)), "h2x_block_cg")
@@ -277,7 +283,7 @@ def block_cg_refine(A: H2Matrix, A_lo: H2Matrix, B, *, rtol=1e-10, inner_rtol=1e
     nb = lib.h2x_block_cg_refine_workspace_bytes(A._h, A_lo._h, m)
     ws = torch.empty(max(nb, 256), dtype=torch.uint8, device=B.device)
     info, rel, its, sts = _new_info(m)
-    prm = _CgParams(float(inner_rtol), int(max_inner), 0, int(check_every))
+    prm = _CgParams(float(inner_rtol), int(max_inner), 0, int(check_every), CG_INDEPENDENT)
     _check(lib.h2x_block_cg_refine(A._h, A_lo._h, C.byref(prm), float(rtol), int(max_outer), m,
                                    C.c_void_p(B.data_ptr()), B.stride(0), C.c_void_p(X.data_ptr()), X.stride(0),
                                    C.c_void_p(ws.data_ptr()), ws.numel(), C.byref(info), _stream(torch, B.device)),

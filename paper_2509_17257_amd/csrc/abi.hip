@@ -1,4 +1,5 @@
 // C ABI entry points: argument validation, workspace layout, dispatch.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -256,7 +257,7 @@ h2x_status h2x_matmul_timed(const h2x_mat *A, int64_t m, double alpha, const dou
 
 size_t h2x_block_cg_workspace_bytes(const h2x_mat *A, int64_t m) {
     if (!A || m < 1) return 0;
-    return cg_ws_bytes(A->dm, m);
+    return std::max(cg_ws_bytes(A->dm, m), bcg_ws_bytes(A->dm, m));
 }
 
 h2x_status h2x_block_cg(const h2x_mat *A, const h2x_cg_params *prm, int64_t m, const double *B, int64_t ldb,
@@ -265,6 +266,10 @@ h2x_status h2x_block_cg(const h2x_mat *A, const h2x_cg_params *prm, int64_t m, c
     if (m < 1 || ldb < m || ldx < m) return fail(H2X_EINVAL, "h2x_block_cg: need m >= 1, ldb >= m, ldx >= m");
     if (!(prm->rtol >= 0.0) || prm->max_iter < 0) return fail(H2X_EINVAL, "h2x_block_cg: bad rtol or max_iter");
     if (!aligned(dev_ws)) return fail(H2X_EINVAL, "h2x_block_cg: workspace not 256-byte aligned");
+    if (prm->variant == H2X_CG_SHARED)
+        return run_block_cg_shared(A->dm, *prm, m, B, ldb, X, ldx, (char *)dev_ws, ws_bytes, info,
+                                   (hipStream_t)hip_stream);
+    if (prm->variant != H2X_CG_INDEPENDENT) return fail(H2X_EINVAL, "h2x_block_cg: unknown variant");
     return run_block_cg(A->dm, *prm, m, B, ldb, X, ldx, (char *)dev_ws, ws_bytes, info, (hipStream_t)hip_stream);
 }
 

@@ -1,0 +1,442 @@
+// Block CG over one shared block Krylov space (O'Leary's block CG, which the
+// paper cites as the variant that enriches the Krylov space), FP64 throughout:
+//   Q = A P,  G = P^T Q,  Lambda = G^{-1} P^T R,  X += P Lambda,  R -= Q Lambda,
+//   Psi = -G^{-1} Q^T R,  P = orth(R + P Psi).
+// The search block P is kept orthonormal by Cholesky QR applied twice; the
+// first pass pivots on the largest remaining column norm and drops directions
+// whose remaining norm falls below 1e-6 of the largest (deflation), so the
+// m x m Gram matrices stay positive definite when columns become dependent.
+// Dropped columns of P are zero; all m x m work uses the active index set.
+//
+// Tall-skinny products (U^T V, U C) stream the n x m blocks once; the m x m
+// factorizations run in one work-group.  Gram matrices are reduced in two
+// fixed-order passes, so the solve is bitwise reproducible.  The host reads the
+// convergence state after every iteration.
+#include <cmath>
+#include <vector>
+
+#include "device.hpp"
+
+namespace h2x {
+
+namespace {
+
+constexpr int kMaxM = 64;      // block size limit of this variant
+constexpr double kDrop = 1e-6; // deflation threshold (relative column norm)
+constexpr int kGramRows = 16;  // rows staged per step in the Gram kernel
+
+struct BcgState {
+    int32_t rank, all_conv, iter, breakdown;
+    int32_t active[kMaxM];
+    int32_t piv[kMaxM];
+    int32_t conv[kMaxM];
+    int32_t first_conv[kMaxM];
+    double bnorm[kMaxM];
+    double rnorm[kMaxM];
+};
+
+// part[(pair * nblk + blk) * m * m + a * m + b] = sum over the block's rows of U[i][a] V[i][b]
+__global__ __launch_bounds__(256) void k_gram_part(int64_t n, int m, int nblk, const double *__restrict__ U0,
+                                                   const double *__restrict__ V0, const double *__restrict__ U1,
+                                                   const double *__restrict__ V1, double *__restrict__ part) {
+    __shared__ double su[2][kGramRows][kMaxM], sv[2][kGramRows][kMaxM];
+    const int tid = threadIdx.x, mm = m * m;
+    const int npair = U1 ? 2 : 1;
+    const int64_t rows = (n + nblk - 1) / nblk;
+    const int64_t r0 = (int64_t)blockIdx.x * rows, r1 = min(n, r0 + rows);
+    double acc[2][16] = {};
+    for (int64_t c0 = r0; c0 < r1; c0 += kGramRows) {
+        const int cr = (int)min<int64_t>(kGramRows, r1 - c0);
+        for (int e = tid; e < kGramRows * m; e += 256) {
+            const int i = e / m, a = e % m;
+            const bool ok = i < cr;
+            su[0][i][a] = ok ? U0[(c0 + i) * m + a] : 0.0;
+            sv[0][i][a] = ok ? V0[(c0 + i) * m + a] : 0.0;
+            if (npair == 2) {
+                su[1][i][a] = ok ? U1[(c0 + i) * m + a] : 0.0;
+                sv[1][i][a] = ok ? V1[(c0 + i) * m + a] : 0.0;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+            if (q < npair)
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int e = tid + 256 * u;
+                if (e < mm) {
+                    const int a = e / m, b = e % m;
+                    double s = acc[q][u];
+                    for (int i = 0; i < kGramRows; ++i) s += su[q][i][a] * sv[q][i][b];
+                    acc[q][u] = s;
+                }
+            }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+        if (q < npair)
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int e = tid + 256 * u;
+            if (e < mm) part[((int64_t)q * nblk + blockIdx.x) * mm + e] = acc[q][u];
+        }
+}
+
+// G_q[e] = sum over blocks (fixed order) of the partial sums
+__global__ void k_gram_sum(int m, int nblk, const double *__restrict__ part, double *__restrict__ G0,
+                           double *__restrict__ G1) {
+    const int mm = m * m;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    const int q = blockIdx.y;
+    if (e >= mm) return;
+    double s = 0.0;
+    for (int b = 0; b < nblk; ++b) s += part[((int64_t)q * nblk + b) * mm + e];
+    (q ? G1 : G0)[e] = s;
+}
+
+// out = beta Yin + alpha U C  (n x m blocks, C m x m; Yin may alias out, beta == 0 ignores it)
+__global__ __launch_bounds__(256) void k_tsmm(int64_t n, int m, const double *__restrict__ U,
+                                              const double *__restrict__ Cm, const double *Yin, double *out,
+                                              double alpha, double beta, int rows_per_wg) {
+    __shared__ double sc[kMaxM * kMaxM];
+    for (int e = threadIdx.x; e < m * m; e += 256) sc[e] = Cm[e];
+    __syncthreads();
+    const int64_t r0 = (int64_t)blockIdx.x * rows_per_wg;
+    const int64_t r1 = min(n, r0 + rows_per_wg);
+    for (int64_t e = r0 * m + threadIdx.x; e < r1 * m; e += 256) {
+        const int64_t i = e / m;
+        const int b = (int)(e % m);
+        const double *u = U + i * m;
+        double s = 0.0;
+        for (int a = 0; a < m; ++a) s += u[a] * sc[a * m + b];
+        out[e] = (beta == 0.0) ? alpha * s : beta * Yin[e] + alpha * s;
+    }
+}
+
+// C = sign * G^{-1} F on the active index set (Cholesky of G restricted to it);
+// inactive rows of C are zero.  Sets breakdown if G is not positive definite there.
+__global__ __launch_bounds__(256) void k_bcg_solve(int m, const double *__restrict__ G, const double *__restrict__ F,
+                                                   double *__restrict__ Cm, double sign, BcgState *st) {
+    __shared__ double L[kMaxM][kMaxM + 1];
+    __shared__ int idx[kMaxM];
+    __shared__ int r, bad;
+    const int tid = threadIdx.x;
+    if (tid == 0) {
+        int c = 0;
+        for (int j = 0; j < m; ++j)
+            if (st->active[j]) idx[c++] = j;
+        r = c;
+        bad = 0;
+    }
+    __syncthreads();
+    for (int e = tid; e < r * r; e += 256) L[e / r][e % r] = G[idx[e / r] * m + idx[e % r]];
+    __syncthreads();
+    // right-looking Cholesky, lower triangle
+    for (int k = 0; k < r; ++k) {
+        if (tid == 0) {
+            const double v = L[k][k];
+            if (!(v > 0.0)) bad = 1;
+            L[k][k] = sqrt(v > 0.0 ? v : 1.0);
+        }
+        __syncthreads();
+        for (int i = k + 1 + tid; i < r; i += 256) L[i][k] /= L[k][k];
+        __syncthreads();
+        for (int e = tid; e < (r - k - 1) * (r - k - 1); e += 256) {
+            const int i = k + 1 + e / (r - k - 1), j = k + 1 + e % (r - k - 1);
+            if (j <= i) L[i][j] -= L[i][k] * L[j][k];
+        }
+        __syncthreads();
+    }
+    if (tid == 0 && bad) st->breakdown = 1;
+    // one column of F per thread: forward then backward substitution
+    for (int col = tid; col < m; col += 256) {
+        double y[kMaxM];
+        for (int a = 0; a < r; ++a) {
+            double v = F[idx[a] * m + col];
+            for (int q = 0; q < a; ++q) v -= L[a][q] * y[q];
+            y[a] = v / L[a][a];
+        }
+        for (int a = r - 1; a >= 0; --a) {
+            double v = y[a];
+            for (int q = a + 1; q < r; ++q) v -= L[q][a] * y[q];
+            y[a] = v / L[a][a];
+        }
+        for (int j = 0; j < m; ++j) Cm[j * m + col] = 0.0;
+        for (int a = 0; a < r; ++a) Cm[idx[a] * m + col] = sign * y[a];
+    }
+}
+
+// Inverse of the upper-triangular T (T[q'][q] = lv[q'][piv[q]] for q' < q, T[q][q] = dg[q]),
+// scattered to M[piv[q']][piv[q]] (all other entries zero): Z M has orthonormalised columns.
+__device__ inline void write_tinv(int m, int r, const double (*lv)[kMaxM + 1], const double *dg, const int *piv,
+                                  double *M) {
+    for (int e = threadIdx.x; e < m * m; e += 256) M[e] = 0.0;
+    __syncthreads();
+    for (int q = threadIdx.x; q < r; q += 256) {
+        double x[kMaxM];
+        x[q] = 1.0 / dg[q];
+        for (int a = q - 1; a >= 0; --a) {
+            double v = 0.0;
+            for (int c = a + 1; c <= q; ++c) v += lv[a][piv[c]] * x[c];
+            x[a] = -v / dg[a];
+        }
+        for (int a = 0; a <= q; ++a) M[piv[a] * m + piv[q]] = x[a];
+    }
+}
+
+// first Cholesky-QR pass: pivoted Cholesky of W = Z^T Z with deflation
+__global__ __launch_bounds__(256) void k_bcg_orth1(int m, const double *__restrict__ W, double *__restrict__ M,
+                                                   BcgState *st) {
+    __shared__ double lv[kMaxM][kMaxM + 1];
+    __shared__ double d[kMaxM], dg[kMaxM];
+    __shared__ int piv[kMaxM], act[kMaxM];
+    __shared__ int rank, stop, best;
+    __shared__ double dmax;
+    const int tid = threadIdx.x;
+    for (int j = tid; j < m; j += 256) {
+        d[j] = W[j * m + j];
+        act[j] = 0;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double mx = 0.0;
+        for (int j = 0; j < m; ++j) mx = fmax(mx, d[j]);
+        dmax = mx;
+        rank = 0;
+        stop = 0;
+    }
+    __syncthreads();
+    for (int k = 0; k < m; ++k) {
+        if (tid == 0) {
+            int b = -1;
+            for (int j = 0; j < m; ++j)
+                if (!act[j] && (b < 0 || d[j] > d[b])) b = j;
+            if (b < 0 || !(dmax > 0.0) || !(d[b] > kDrop * kDrop * dmax)) {
+                stop = 1;
+            } else {
+                act[b] = 1;
+                piv[k] = b;
+                dg[k] = sqrt(d[b]);
+                best = b;
+                rank = k + 1;
+            }
+        }
+        __syncthreads();
+        if (stop) break;
+        for (int j = tid; j < m; j += 256) {
+            if (act[j]) continue;
+            double v = W[j * m + best];
+            for (int q = 0; q < k; ++q) v -= lv[q][j] * lv[q][best];
+            lv[k][j] = v / dg[k];
+            d[j] -= lv[k][j] * lv[k][j];
+        }
+        // lv[k][best] is read by later steps: the pivot's own column of step k
+        if (tid == 0) lv[k][best] = dg[k];
+        __syncthreads();
+    }
+    write_tinv(m, rank, lv, dg, piv, M);
+    if (tid == 0) st->rank = rank;
+    for (int j = tid; j < m; j += 256) {
+        st->active[j] = act[j];
+        st->piv[j] = j < rank ? piv[j] : -1;
+    }
+}
+
+// second Cholesky-QR pass: plain Cholesky of W2 = P1^T P1 on the kept columns, pivot order
+__global__ __launch_bounds__(256) void k_bcg_orth2(int m, const double *__restrict__ W, double *__restrict__ M,
+                                                   const BcgState *st) {
+    __shared__ double lv[kMaxM][kMaxM + 1];
+    __shared__ double dg[kMaxM];
+    __shared__ int piv[kMaxM];
+    const int tid = threadIdx.x, r = st->rank;
+    for (int j = tid; j < r; j += 256) piv[j] = st->piv[j];
+    __syncthreads();
+    for (int q = 0; q < r; ++q) {
+        if (tid == 0) {
+            const int c = piv[q];
+            double v = W[c * m + c];
+            for (int a = 0; a < q; ++a) v -= lv[a][c] * lv[a][c];
+            dg[q] = sqrt(v > 0.0 ? v : 0.0);
+        }
+        __syncthreads();
+        for (int q2 = q + 1 + tid; q2 < r; q2 += 256) {
+            const int c = piv[q], c2 = piv[q2];
+            double u = W[c2 * m + c];
+            for (int a = 0; a < q; ++a) u -= lv[a][c2] * lv[a][c];
+            lv[q][c2] = u / dg[q];
+        }
+        __syncthreads();
+    }
+    write_tinv(m, r, lv, dg, piv, M);
+}
+
+// convergence from the diagonal of R^T R
+__global__ void k_bcg_conv(int m, const double *__restrict__ RR, double rtol, BcgState *st, int init) {
+    __shared__ int notconv;
+    if (threadIdx.x == 0) notconv = 0;
+    __syncthreads();
+    const int it = init ? 0 : st->iter + 1;
+    for (int j = threadIdx.x; j < m; j += blockDim.x) {
+        const double rn = sqrt(RR[j * m + j]);
+        st->rnorm[j] = rn;
+        const int c = rn <= rtol * st->bnorm[j];
+        st->conv[j] = c;
+        if (init) st->first_conv[j] = c ? 0 : -1;
+        else if (c && st->first_conv[j] < 0) st->first_conv[j] = it;
+        if (!c) atomicOr(&notconv, 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        st->iter = it;
+        st->all_conv = notconv ? 0 : 1;
+        if (init) st->breakdown = 0;
+    }
+}
+
+__global__ void k_bcg_bnorm(int m, const double *__restrict__ BB, BcgState *st) {
+    for (int j = threadIdx.x; j < m; j += blockDim.x) st->bnorm[j] = sqrt(BB[j * m + j]);
+}
+
+__global__ void k_copy_rows(int64_t n, int64_t m, const int64_t *__restrict__ perm, const double *__restrict__ src,
+                            int64_t lds, double *__restrict__ dst, int scatter) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * m) return;
+    const int64_t i = e / m, j = e % m;
+    if (scatter) dst[perm[i] * lds + j] = src[e];
+    else dst[e] = src[perm[i] * lds + j];
+}
+
+struct BcgWs {
+    double *Bt, *Xt, *R, *P, *Q, *Z, *P1, *part, *G, *F, *C, *Wm, *RR, *M;
+    BcgState *st;
+    char *mm;
+    int nblk;
+    size_t bytes;
+};
+
+BcgWs bcg_layout(const DevMat &dm, int64_t m, char *base) {
+    BcgWs w{};
+    size_t off = 0;
+    auto carve = [&](size_t bytes) {
+        off = align_up(off);
+        char *p = base ? base + off : nullptr;
+        off += bytes;
+        return p;
+    };
+    const size_t nm = (size_t)dm.n * m * sizeof(double), mm = (size_t)m * m * sizeof(double);
+    w.nblk = (int)std::min<int64_t>(256, std::max<int64_t>(1, (dm.n + 255) / 256));
+    for (double **p : {&w.Bt, &w.Xt, &w.R, &w.P, &w.Q, &w.Z, &w.P1}) *p = (double *)carve(nm);
+    w.part = (double *)carve(2 * (size_t)w.nblk * mm);
+    for (double **p : {&w.G, &w.F, &w.C, &w.Wm, &w.RR, &w.M}) *p = (double *)carve(mm);
+    w.st = (BcgState *)carve(sizeof(BcgState));
+    w.mm = carve(matmul_ws_bytes(dm, m));
+    w.bytes = align_up(off);
+    return w;
+}
+
+}  // namespace
+
+size_t bcg_ws_bytes(const DevMat &dm, int64_t m) { return bcg_layout(dm, m, nullptr).bytes; }
+
+h2x_status run_block_cg_shared(const DevMat &dm, const h2x_cg_params &prm, int64_t m, const double *B, int64_t ldb,
+                               double *X, int64_t ldx, char *ws, size_t ws_bytes, h2x_cg_info *info,
+                               hipStream_t st) {
+    if (m > kMaxM) {
+        set_error("h2x_block_cg: the shared-space variant supports m <= 64");
+        return H2X_EINVAL;
+    }
+    BcgWs w = bcg_layout(dm, m, ws);
+    if (ws_bytes < w.bytes) {
+        set_error("h2x_block_cg: workspace too small");
+        return H2X_ENOMEM;
+    }
+    const int64_t n = dm.n, nm = n * m;
+    const int mi = (int)m;
+    const unsigned g1 = (unsigned)((nm + 255) / 256);
+    const int rpw = std::max(1, 2048 / mi);
+    const unsigned gt = (unsigned)((n + rpw - 1) / rpw);
+    const dim3 gs((unsigned)((m * m + 255) / 256), 2);
+    auto fail = [&](hipError_t e) {
+        set_error(std::string("h2x_block_cg: ") + hipGetErrorString(e));
+        return H2X_EHIP;
+    };
+    auto gram2 = [&](const double *U0, const double *V0, const double *U1, const double *V1, double *G0,
+                     double *G1) {
+        hipLaunchKernelGGL(k_gram_part, dim3(w.nblk), dim3(256), 0, st, n, mi, w.nblk, U0, V0, U1, V1, w.part);
+        hipLaunchKernelGGL(k_gram_sum, dim3(gs.x, U1 ? 2 : 1), dim3(256), 0, st, mi, w.nblk, (const double *)w.part,
+                           G0, G1);
+    };
+    auto tsmm = [&](const double *U, const double *Cm, const double *Yin, double *out, double alpha, double beta) {
+        hipLaunchKernelGGL(k_tsmm, dim3(gt), dim3(256), 0, st, n, mi, U, Cm, Yin, out, alpha, beta, rpw);
+    };
+    auto orth = [&](const double *Zs) {
+        gram2(Zs, Zs, nullptr, nullptr, w.Wm, nullptr);
+        hipLaunchKernelGGL(k_bcg_orth1, dim3(1), dim3(256), 0, st, mi, (const double *)w.Wm, w.M, w.st);
+        tsmm(Zs, w.M, nullptr, w.P1, 1.0, 0.0);
+        gram2(w.P1, w.P1, nullptr, nullptr, w.Wm, nullptr);
+        hipLaunchKernelGGL(k_bcg_orth2, dim3(1), dim3(256), 0, st, mi, (const double *)w.Wm, w.M,
+                           (const BcgState *)w.st);
+        tsmm(w.P1, w.M, nullptr, w.P, 1.0, 0.0);
+    };
+
+    hipLaunchKernelGGL(k_copy_rows, dim3(g1), dim3(256), 0, st, n, m, dm.perm, B, ldb, w.Bt, 0);
+    hipLaunchKernelGGL(k_copy_rows, dim3(g1), dim3(256), 0, st, n, m, dm.perm, (const double *)X, ldx, w.Xt, 0);
+    hipError_t e = hipMemcpyAsync(w.R, w.Bt, nm * sizeof(double), hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) e = run_matmul(dm, m, -1.0, w.Xt, m, 1.0, w.R, m, true, w.mm, st);
+    if (e != hipSuccess) return fail(e);
+    gram2(w.Bt, w.Bt, w.R, w.R, w.G, w.RR);
+    hipLaunchKernelGGL(k_bcg_bnorm, dim3(1), dim3(64), 0, st, mi, (const double *)w.G, w.st);
+    hipLaunchKernelGGL(k_bcg_conv, dim3(1), dim3(64), 0, st, mi, (const double *)w.RR, prm.rtol, w.st, 1);
+    orth(w.R);
+
+    BcgState hs{};
+    int32_t status = H2X_OK, rank_min = (int32_t)m;
+    for (int32_t it = 0;; ++it) {
+        e = hipMemcpyAsync(&hs, w.st, sizeof(BcgState), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return fail(e);
+        rank_min = std::min(rank_min, hs.rank);
+        if (hs.breakdown) {
+            status = H2X_EBREAKDOWN;
+            break;
+        }
+        if (hs.all_conv) break;
+        if (it >= prm.max_iter || hs.rank == 0) {
+            status = H2X_ENOCONV;
+            break;
+        }
+        e = run_matmul(dm, m, 1.0, w.P, m, 0.0, w.Q, m, true, w.mm, st);
+        if (e != hipSuccess) return fail(e);
+        gram2(w.P, w.Q, w.P, w.R, w.G, w.F);  // G = P^T A P, F = P^T R
+        hipLaunchKernelGGL(k_bcg_solve, dim3(1), dim3(256), 0, st, mi, (const double *)w.G, (const double *)w.F, w.C,
+                           1.0, w.st);
+        tsmm(w.P, w.C, w.Xt, w.Xt, 1.0, 1.0);   // X += P Lambda
+        tsmm(w.Q, w.C, w.R, w.R, -1.0, 1.0);    // R -= Q Lambda
+        gram2(w.Q, w.R, w.R, w.R, w.F, w.RR);   // F = (A P)^T R, RR = R^T R
+        hipLaunchKernelGGL(k_bcg_conv, dim3(1), dim3(64), 0, st, mi, (const double *)w.RR, prm.rtol, w.st, 0);
+        hipLaunchKernelGGL(k_bcg_solve, dim3(1), dim3(256), 0, st, mi, (const double *)w.G, (const double *)w.F, w.C,
+                           -1.0, w.st);
+        tsmm(w.P, w.C, w.R, w.Z, 1.0, 1.0);     // Z = R + P Psi
+        orth(w.Z);
+    }
+    hipLaunchKernelGGL(k_copy_rows, dim3(g1), dim3(256), 0, st, n, m, dm.perm, (const double *)w.Xt, ldx, X, 1);
+    e = hipMemcpyAsync(&hs, w.st, sizeof(BcgState), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return fail(e);
+    if (info) {
+        info->iters = hs.iter;
+        info->status = status;
+        info->outer_iters = 0;
+        for (int64_t j = 0; j < m; ++j) {
+            const double bn = hs.bnorm[j], rn = hs.rnorm[j];
+            if (info->col_relres) info->col_relres[j] = bn > 0 ? rn / bn : rn;
+            if (info->col_iters) info->col_iters[j] = hs.first_conv[j] >= 0 ? hs.first_conv[j] : hs.iter;
+            if (info->col_status) info->col_status[j] = hs.conv[j] ? 0 : (status == H2X_EBREAKDOWN ? 1 : 2);
+        }
+    }
+    (void)rank_min;
+    return H2X_OK;
+}
+
+}  // namespace h2x

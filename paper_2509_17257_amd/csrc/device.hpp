@@ -70,6 +70,11 @@ size_t cg_ws_bytes(const DevMat &dm, int64_t m);
 h2x_status run_block_cg(const DevMat &dm, const h2x_cg_params &prm, int64_t m, const double *B, int64_t ldb,
                         double *X, int64_t ldx, char *ws, size_t ws_bytes, h2x_cg_info *info, hipStream_t st);
 
+size_t bcg_ws_bytes(const DevMat &dm, int64_t m);
+h2x_status run_block_cg_shared(const DevMat &dm, const h2x_cg_params &prm, int64_t m, const double *B, int64_t ldb,
+                               double *X, int64_t ldx, char *ws, size_t ws_bytes, h2x_cg_info *info,
+                               hipStream_t st);
+
 size_t refine_ws_bytes(const DevMat &hi, const DevMat &lo, int64_t m);
 h2x_status run_refine(const DevMat &hi, const DevMat &lo, const h2x_cg_params &inner, double rtol, int32_t max_outer,
                       int64_t m, const double *B, int64_t ldb, double *X, int64_t ldx, char *ws, size_t ws_bytes,

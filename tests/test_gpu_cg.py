@@ -120,3 +120,51 @@ def test_zero_rhs_column(small):
     Xg, ig = _solve(A, B, rtol=1e-8)
     assert np.all(Xg[:, 2] == 0.0)
     assert ig.status == 0
+
+
+# ---- shared block Krylov space variant (m x m Gram matrices, Cholesky, QR) ----
+
+@pytest.mark.parametrize("iters", [1, 2, 5])
+def test_shared_first_iterates_match(small, iters):
+    o, A, B = small
+    Xo, io = o.block_cg_shared(B, rtol=1e-8, max_iter=iters)
+    Xg, ig = _solve(A, B, rtol=1e-8, max_iter=iters, variant="shared")
+    assert ig.iters == io["iters"] == iters
+    assert _colrel(Xg, Xo) <= 1e-12
+
+
+def test_shared_end_to_end(small):
+    o, A, B = small
+    rtol = 1e-8
+    Xo, io = o.block_cg_shared(B, rtol=rtol)
+    Xg, ig = _solve(A, B, rtol=rtol, variant="shared")
+    assert ig.status == 0 and np.all(ig.col_status == 0)
+    slack = max(2, int(0.05 * io["iters"]))
+    assert abs(ig.iters - io["iters"]) <= slack
+    res = np.linalg.norm(B - o.matmul(Xg), axis=0) / np.linalg.norm(B, axis=0)
+    assert res.max() <= 2 * rtol
+    Ad = o.dense()
+    ev = np.linalg.eigvalsh(Ad)
+    assert _colrel(Xg, Xo) <= 10 * (ev[-1] / ev[0]) * rtol
+    _, ind = o.block_cg(B, rtol=rtol)
+    assert ig.iters < ind["iters"]
+
+
+def test_shared_deflation_and_limits(small):
+    import paper_2509_17257_amd as h2x
+    o, A, B = small
+    Bx = np.ascontiguousarray(np.c_[B[:, [0, 0, 2]], np.zeros(B.shape[0])])
+    Xo, io = o.block_cg_shared(Bx, rtol=1e-8)
+    Xg, ig = _solve(A, Bx, rtol=1e-8, variant="shared")
+    assert ig.status == 0
+    assert abs(ig.iters - io["iters"]) <= max(2, int(0.05 * io["iters"]))
+    res = np.linalg.norm(Bx - o.matmul(Xg), axis=0) / np.maximum(np.linalg.norm(Bx, axis=0), 1e-300)
+    assert res.max() <= 2e-8
+    assert np.all(Xg[:, 3] == 0.0)
+    # m = 1 is plain CG
+    x1, it1 = o.cg1(B[:, 0], rtol=1e-10)
+    X1, i1 = _solve(A, B[:, :1].copy(), rtol=1e-10, variant="shared")
+    assert abs(i1.iters - it1) <= max(2, int(0.05 * it1))
+    assert np.abs(X1[:, 0] - x1).max() <= 1e-8 * np.abs(x1).max()
+    with pytest.raises(h2x.H2xError):
+        _solve(A, W.rhs(B.shape[0], 65, 7), rtol=1e-8, variant="shared")

@@ -80,3 +80,58 @@ def test_indefinite_shift_flags_breakdown():
     B = W.rhs(n, 3, 67)
     X, info = h.block_cg(B, rtol=1e-8, max_iter=500)
     assert np.any(info["status"] != 0)
+
+
+# ---- block CG over one shared block Krylov space (m x m Gram matrices) ----
+
+def test_shared_block_cg_matches_dense_and_beats_independent(small):
+    h, B = small
+    A = h.dense()
+    Xd = sla.cho_solve(sla.cho_factor(A), B)
+    ev = np.linalg.eigvalsh(A)
+    kappa = ev[-1] / ev[0]
+    X, info = h.block_cg_shared(B, rtol=1e-8)
+    _, ind = h.block_cg(B, rtol=1e-8)
+    assert np.all(info["status"] == 0) and info["rank_min"] == B.shape[1]
+    rel = np.linalg.norm(X - Xd, axis=0) / np.linalg.norm(Xd, axis=0)
+    assert rel.max() <= kappa * 1e-8
+    res = np.linalg.norm(B - A @ X, axis=0) / np.linalg.norm(B, axis=0)
+    assert res.max() <= 1e-8
+    # the shared space contains every column's own Krylov space
+    assert info["iters"] < ind["iters"]
+
+
+def test_shared_block_cg_single_column_is_cg(small):
+    h, B = small
+    x1, it1 = h.cg1(B[:, 0], rtol=1e-10)
+    X1, info = h.block_cg_shared(B[:, :1].copy(), rtol=1e-10)
+    assert abs(info["iters"] - it1) <= 1
+    assert np.abs(X1[:, 0] - x1).max() <= 1e-9 * np.abs(x1).max()
+
+
+def test_shared_block_cg_deflates_dependent_columns(small):
+    h, B = small
+    ref, rinfo = h.block_cg_shared(np.ascontiguousarray(B[:, [0, 2]]), rtol=1e-8)
+    cases = {
+        "duplicate": np.ascontiguousarray(B[:, [0, 0, 2]]),
+        "zero": np.c_[B[:, [0, 2]], np.zeros(h.n)],
+        "combination": np.c_[B[:, [0, 2]], B[:, 0] - 2.0 * B[:, 2]],
+    }
+    for name, Bx in cases.items():
+        X, info = h.block_cg_shared(Bx, rtol=1e-8)
+        assert np.all(info["status"] == 0), name
+        assert info["rank_min"] == 2, name
+        assert abs(info["iters"] - rinfo["iters"]) <= 3, (name, info, rinfo)
+        res = np.linalg.norm(Bx - h.matmul(X), axis=0) / np.maximum(np.linalg.norm(Bx, axis=0), 1e-300)
+        assert res.max() <= 1e-8, name
+
+
+def test_shared_block_cg_constant_kernel():
+    n, sigma = 800, 0.8
+    P = W.sphere_points(n, 63)
+    h = oracle.OracleH2(P, kernel="const", leaf=32, p=2, shift=sigma)
+    B = W.rhs(n, 3, 64)
+    X, info = h.block_cg_shared(B, rtol=1e-12)
+    Xcf = (B - np.ones((n, 1)) * (B.sum(0, keepdims=True) / (sigma + n))) / sigma
+    np.testing.assert_allclose(X, Xcf, rtol=0, atol=1e-9 * np.abs(Xcf).max())
+    assert info["iters"] <= 2

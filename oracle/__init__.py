@@ -68,6 +68,8 @@ def _load():
     lib.orc_refine_cg.restype = I64
     lib.orc_refine_cg.argtypes = [P, C.c_int, I64, P, P, D, D, I64, I64, P]
     lib.orc_round_bf16_array.argtypes = [P, P, I64]
+    lib.orc_matmul_adjoint.argtypes = [P, I64, D, P, D, P]
+    lib.orc_grad.argtypes = [P, I64, P, P, P, P, P]
     lib.orc_block_cg_shared.restype = I64
     lib.orc_block_cg_shared.argtypes = [P, I64, P, P, D, I64, D, P, P]
     lib.orc_num_threads.restype = C.c_int
@@ -219,6 +221,26 @@ class OracleH2:
         outer = _load().orc_refine_cg(self._h, pr, B.shape[1], _ptr(B), _ptr(X), float(rtol), float(inner_rtol),
                                       int(max_outer), int(max_inner), _ptr(tot))
         return X, dict(outer=int(outer), inner=int(tot[0]))
+
+    def matmul_adjoint(self, X, alpha=1.0, beta=0.0, Y=None) -> np.ndarray:
+        """Y <- beta Y + alpha A^T X through the column lists (transposed blocks)."""
+        X = np.ascontiguousarray(X, dtype=np.float64)
+        m = X.shape[1]
+        out = np.zeros((self.n, m)) if Y is None else np.ascontiguousarray(Y, dtype=np.float64).copy()
+        _load().orc_matmul_adjoint(self._h, m, float(alpha), _ptr(X), float(beta), _ptr(out))
+        return out
+
+    def grad(self, X, dY, want_dS=True, want_dN=True):
+        """Gradients of <dY, A X>: dS (n_adm x k x k, block-tree order), dN (near entries,
+        row-major per block), dell (scalar)."""
+        X = np.ascontiguousarray(X, dtype=np.float64)
+        dY = np.ascontiguousarray(dY, dtype=np.float64)
+        dS = np.zeros((self.n_adm, self.k, self.k)) if want_dS else None
+        dN = np.zeros(self.near_entries) if want_dN else None
+        dl = np.zeros(1)
+        _load().orc_grad(self._h, X.shape[1], _ptr(X), _ptr(dY), _ptr(dS) if want_dS else None,
+                         _ptr(dN) if want_dN else None, _ptr(dl))
+        return dS, dN, float(dl[0])
 
     def forward_transform(self, X) -> np.ndarray:
         X = np.ascontiguousarray(X, dtype=np.float64)

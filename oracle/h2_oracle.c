@@ -763,6 +763,101 @@ int64_t orc_refine_cg(const orc_h2 *h, int prec, int64_t m, const double *B, dou
                       double inner_rtol, int64_t max_outer, int64_t max_inner, int64_t *inner_total);
 
 /* ------------------------------------------------------------------------ */
+/* Differentiation.                                                          */
+/* Adjoint product Y <- beta Y + alpha A^T X: the forward transformation of X,  */
+/* then for every column cluster s the blocks (t, s) of its column list:       */
+/* admissible y_s += alpha S_b^T x_t, inadmissible y|_s += alpha G|_{t x s}^T x|_t, */
+/* then the backward transformation (W == V).                                 */
+void orc_matmul_adjoint(const orc_h2 *h, int64_t m, double alpha, const double *X, double beta, double *Y) {
+    const int k = h->k;
+    size_t cw = (size_t)h->C * k * m;
+    orc_mm w;
+    w.h = h;
+    w.m = m;
+    w.X = X;
+    w.xh = calloc(cw ? cw : 1, sizeof(double));
+    w.yh = calloc(cw ? cw : 1, sizeof(double));
+    for (int64_t i = 0; i < h->n * m; ++i) Y[i] = (beta == 0.0) ? 0.0 : beta * Y[i];
+    orc_forward(&w, 0);
+    /* column lists: every leaf block grouped by its column cluster, block order */
+    int64_t *cptr = calloc(h->C + 1, sizeof(int64_t)), *cblk = malloc(sizeof(int64_t) * (h->nb ? h->nb : 1));
+    for (int64_t b = 0; b < h->nb; ++b) cptr[h->bs[b] + 1]++;
+    for (int64_t c = 0; c < h->C; ++c) cptr[c + 1] += cptr[c];
+    int64_t *fill = calloc(h->C + 1, sizeof(int64_t));
+    for (int64_t b = 0; b < h->nb; ++b) cblk[cptr[h->bs[b]] + fill[h->bs[b]]++] = b;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t s = 0; s < h->C; ++s)
+        for (int64_t q = cptr[s]; q < cptr[s + 1]; ++q) {
+            int64_t b = cblk[q], t = h->bt[b];
+            if (h->badm[b]) {
+                const double *Sb = &h->S[h->boff[b]];
+                const double *xt = &w.xh[(size_t)t * k * m];
+                double *ys = &w.yh[(size_t)s * k * m];
+                for (int mu = 0; mu < k; ++mu)
+                    for (int64_t j = 0; j < m; ++j) {
+                        double acc = 0.0;
+                        for (int nu = 0; nu < k; ++nu) acc += Sb[nu * k + mu] * xt[nu * m + j];
+                        ys[mu * m + j] += alpha * acc;
+                    }
+            } else {
+                const double *Nb = &h->N[h->boff[b]];
+                int64_t nt = h->size[t], ns = h->size[s];
+                for (int64_t c = 0; c < ns; ++c) {
+                    double *yrow = &Y[h->perm[h->first[s] + c] * m];
+                    for (int64_t j = 0; j < m; ++j) {
+                        double acc = 0.0;
+                        for (int64_t i = 0; i < nt; ++i) acc += Nb[i * ns + c] * X[h->perm[h->first[t] + i] * m + j];
+                        yrow[j] += alpha * acc;
+                    }
+                }
+            }
+        }
+    orc_backward(&w, 0, Y);
+    free(cptr); free(cblk); free(fill); free(w.xh); free(w.yh);
+}
+
+/* Gradients of L = <dY, A X> (sum over all entries):
+ *   dS_b = dyhat_t xhat_s^T  (k x k) for every admissible block, xhat / dyhat the
+ *          forward transforms of X and dY;
+ *   dN_b = dY|_t X|_s^T      (|t| x |s|) for every near-field block;
+ *   dell = sum_b <dS_b/dell, dS_b> + sum_b <dN_b/dell, dN_b>, with
+ *          dg/dell = (r / ell^2) exp(-r / ell) at the Chebyshev nodes / points
+ *          (V and E do not depend on ell).
+ * dS / dN (nullable) are laid out like S / N; dell (nullable) receives the scalar. */
+void orc_grad(const orc_h2 *h, int64_t m, const double *X, const double *dY, double *dS, double *dN, double *dell) {
+    const int k = h->k;
+    size_t cw = (size_t)h->C * k * m;
+    double *xh = calloc(cw ? cw : 1, sizeof(double)), *dh = calloc(cw ? cw : 1, sizeof(double));
+    orc_forward_transform(h, m, X, xh);
+    orc_forward_transform(h, m, dY, dh);
+    double total = 0.0;
+    for (int64_t b = 0; b < h->nb; ++b) {
+        int64_t t = h->bt[b], s = h->bs[b];
+        if (h->badm[b]) {
+            for (int nu = 0; nu < k; ++nu)
+                for (int mu = 0; mu < k; ++mu) {
+                    double acc = 0.0;
+                    for (int64_t j = 0; j < m; ++j) acc += dh[((size_t)t * k + nu) * m + j] * xh[((size_t)s * k + mu) * m + j];
+                    if (dS) dS[h->boff[b] + nu * k + mu] = acc;
+                    total += orc_dg(h, &h->nodes[((size_t)t * k + nu) * 3], &h->nodes[((size_t)s * k + mu) * 3]) * acc;
+                }
+        } else {
+            int64_t nt = h->size[t], ns = h->size[s];
+            for (int64_t i = 0; i < nt; ++i)
+                for (int64_t c = 0; c < ns; ++c) {
+                    int64_t gi = h->perm[h->first[t] + i], gj = h->perm[h->first[s] + c];
+                    double acc = 0.0;
+                    for (int64_t j = 0; j < m; ++j) acc += dY[gi * m + j] * X[gj * m + j];
+                    if (dN) dN[h->boff[b] + i * ns + c] = acc;
+                    total += orc_dg(h, &h->pts[3 * gi], &h->pts[3 * gj]) * acc;
+                }
+        }
+    }
+    if (dell) *dell = total;
+    free(xh); free(dh);
+}
+
+/* ------------------------------------------------------------------------ */
 /* Dense assembly of A_H2 from its definition (n x n, original order)         */
 
 /* full cluster basis V_t (|t| x k): leaf matrix, or [V_{t0} E_{t0}; V_{t1} E_{t1}] */
@@ -1047,7 +1142,7 @@ static void orc_apply_inv_lt(int64_t n, int64_t m, int64_t rank, const int64_t *
 
 static int64_t orc_orth(int64_t n, int64_t m, const double *Z, double *P, int *active, double drop) {
     double *W = malloc(sizeof(double) * m * m), *lv = calloc(m * m, sizeof(double));
-    double *dg = malloc(sizeof(double) * m), *d = malloc(sizeof(double) * m);
+    double *dg = calloc(m, sizeof(double)), *d = malloc(sizeof(double) * m);
     double *T = malloc(sizeof(double) * n * m);
     int64_t *piv = malloc(sizeof(int64_t) * m);
     /* pass 1: pivoted Cholesky of Z^T Z with dropping */

@@ -212,6 +212,59 @@ h2x_status h2x_block_cg_refine(const h2x_mat *A, const h2x_mat *A_lo, const h2x_
                                int64_t ldx, void *dev_ws, size_t ws_bytes, h2x_cg_info *info,
                                void *hip_stream);
 
+/* ---- differentiation ------------------------------------------------------- */
+/* The paper's products use the row lists C_t of section 3 ("prepare_addeval");
+ * the adjoint swaps the roles of row and column cluster (lists by column
+ * cluster, transposed coupling and near-field blocks), with the same forward
+ * and backward transformations, since the row and column bases coincide (W = V,
+ * section 2).  The gradients are those of L = <dY, A X> (sum of the entrywise
+ * products) with respect to the stored blocks of the representation of section 2
+ * and to the kernel length scale ell.  FP64 operators with rank k <= 64 only
+ * (H2X_EUNSUPPORTED otherwise). */
+
+/* Bytes of device workspace h2x_matmul_adjoint needs for m columns. */
+size_t h2x_matmul_adjoint_workspace_bytes(const h2x_mat *A, int64_t m);
+
+/* Y <- beta Y + alpha A^T X (async): every column cluster s collects
+ * S_b^T x-hat_t over the admissible blocks b = (t, s) of its column, and every
+ * leaf s collects N_ts^T X|_t over the near-field blocks of its column.  X, Y:
+ * device, n x m, original point order; must not overlap; beta == 0 ignores Y. */
+h2x_status h2x_matmul_adjoint(const h2x_mat *A, int64_t m, double alpha, const double *X, int64_t ldx,
+                              double beta, double *Y, int64_t ldy, void *dev_ws, size_t ws_bytes,
+                              void *hip_stream);
+
+/* Bytes of device workspace h2x_grad needs for m columns. */
+size_t h2x_grad_workspace_bytes(const h2x_mat *A, int64_t m);
+
+/* Gradients of L = <dY, A X> (async).  X, dY: device n x m (original order).
+ * Outputs (device, any may be NULL to skip it):
+ *   dS:   n_adm x k x k row-major, in the storage order of h2x_plan_blocks:
+ *         dS_b = dyhat_t xhat_s^T, xhat / dyhat the forward transformations;
+ *   dN:   near_entries doubles, the blocks in the storage order of
+ *         h2x_plan_blocks, each |t| x |s| row-major in tree order of the points:
+ *         dN_b = dY|_t X|_s^T;
+ *   dell: one double, dL/dell = sum_b <dS_b/dell, dS_b> + sum_b <dN_b/dell, dN_b>
+ *         with d g / d ell = (r / ell^2) exp(-r / ell) (0 for the test kernels);
+ *         reduced in a fixed order (bitwise reproducible). */
+h2x_status h2x_grad(const h2x_mat *A, int64_t m, const double *X, int64_t ldx, const double *dY,
+                    int64_t lddy, double *dS, double *dN, double *dell, void *dev_ws, size_t ws_bytes,
+                    void *hip_stream);
+
+/* Refill the coupling matrices and the near field for a new kernel length scale
+ * (the cluster tree, block tree, bases and transfers do not depend on ell).
+ * Blocking: returns after the refill. */
+h2x_status h2x_mat_set_ell(h2x_mat *A, double ell, void *hip_stream);
+
+/* Copy the coupling matrices S_b (FP64 operators) to out (device, n_adm x k x k
+ * doubles, row-major S_b[nu][mu] = g(xi_t,nu, xi_s,mu), blocks in the storage
+ * order of h2x_plan_blocks), whatever the internal layout (async). */
+h2x_status h2x_mat_coupling(const h2x_mat *A, double *out, void *hip_stream);
+
+/* Replace the coupling matrices S_b (FP64 operators) by in (device, same layout
+ * as h2x_mat_coupling), e.g. after a gradient step on them (async; in must stay
+ * valid until the copy has run).  h2x_mat_set_ell refills them from the kernel. */
+h2x_status h2x_mat_set_coupling(h2x_mat *A, const double *in, void *hip_stream);
+
 /* ---- misc ------------------------------------------------------------------ */
 
 const char *h2x_last_error(void);

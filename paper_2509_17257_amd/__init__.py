@@ -14,8 +14,8 @@ from dataclasses import dataclass
 
 import numpy as np
 
-__all__ = ["Plan", "H2Matrix", "h2_matmul", "block_cg_solve", "block_cg_refine", "library_path", "load_library",
-           "F64", "F32", "BF16", "TREE_ORDER"]
+__all__ = ["Plan", "H2Matrix", "h2_matmul", "h2_matmul_adjoint", "h2_grad", "block_cg_solve", "block_cg_refine",
+           "library_path", "load_library", "F64", "F32", "BF16", "TREE_ORDER"]
 
 F64, F32, BF16 = 0, 1, 2
 _PREC = {"f64": F64, "f32": F32, "bf16": BF16, F64: F64, F32: F32, BF16: BF16}
@@ -88,6 +88,13 @@ def load_library():
         "h2x_block_cg_refine_workspace_bytes": (SZ, [P, P, I64]),
         "h2x_block_cg_refine": (C.c_int, [P, P, C.POINTER(_CgParams), D, I32, I64, P, I64, P, I64, P, SZ,
                                           C.POINTER(_CgInfo), P]),
+        "h2x_matmul_adjoint_workspace_bytes": (SZ, [P, I64]),
+        "h2x_matmul_adjoint": (C.c_int, [P, I64, D, P, I64, D, P, I64, P, SZ, P]),
+        "h2x_grad_workspace_bytes": (SZ, [P, I64]),
+        "h2x_grad": (C.c_int, [P, I64, P, I64, P, I64, P, P, P, P, SZ, P]),
+        "h2x_mat_set_ell": (C.c_int, [P, D, P]),
+        "h2x_mat_coupling": (C.c_int, [P, P, P]),
+        "h2x_mat_set_coupling": (C.c_int, [P, P, P]),
         "h2x_last_error": (C.c_char_p, []),
         "h2x_version": (C.c_char_p, []),
     }
@@ -177,6 +184,7 @@ class H2Matrix:
                                   _stream(torch, self.device), C.byref(h)), "h2x_mat_create")
         self._h = h
         self.n, self.k = self.plan.n, self.plan.k
+        self.ell = float(self.plan.params["ell"])
         self._mm_ws = {}
 
     def __del__(self):
@@ -184,17 +192,45 @@ class H2Matrix:
             _lib.h2x_mat_destroy(self._h)
             self._h = None
 
+    _WS = {"matmul": "h2x_matmul_workspace_bytes", "cg": "h2x_block_cg_workspace_bytes",
+           "adjoint": "h2x_matmul_adjoint_workspace_bytes", "grad": "h2x_grad_workspace_bytes"}
+
     def workspace(self, m: int, kind: str = "matmul"):
         import torch
         key = (kind, m)
         ws = self._mm_ws.get(key)
         if ws is None:
-            f = load_library().h2x_matmul_workspace_bytes if kind == "matmul" else \
-                load_library().h2x_block_cg_workspace_bytes
-            nb = f(self._h, m)
+            nb = getattr(load_library(), self._WS[kind])(self._h, m)
             ws = torch.empty(max(nb, 256), dtype=torch.uint8, device=self.device)
             self._mm_ws[key] = ws
         return ws
+
+    def set_ell(self, ell: float) -> None:
+        """Refill S and the near field for a new kernel length scale (h2x_mat_set_ell)."""
+        import torch
+        _check(load_library().h2x_mat_set_ell(self._h, float(ell), _stream(torch, self.device)), "h2x_mat_set_ell")
+        self.ell = float(ell)
+
+    def coupling(self):
+        """The coupling matrices as an (n_adm, k, k) float64 CUDA tensor (h2x_mat_coupling)."""
+        import torch
+        out = torch.empty((self.plan.n_adm, self.k, self.k), dtype=torch.float64, device=self.device)
+        if self.plan.n_adm:
+            _check(load_library().h2x_mat_coupling(self._h, C.c_void_p(out.data_ptr()), _stream(torch, self.device)),
+                   "h2x_mat_coupling")
+        return out
+
+    def set_coupling(self, S) -> None:
+        """Overwrite the coupling matrices with an (n_adm, k, k) float64 CUDA tensor
+        (h2x_mat_set_coupling)."""
+        import torch
+        if S.dtype != torch.float64 or S.device.type != "cuda" or tuple(S.shape) != (self.plan.n_adm, self.k, self.k):
+            raise ValueError("S must be an (n_adm, k, k) float64 CUDA tensor")
+        S = S.contiguous()
+        if self.plan.n_adm:
+            _check(load_library().h2x_mat_set_coupling(self._h, C.c_void_p(S.data_ptr()), _stream(torch, self.device)),
+                   "h2x_mat_set_coupling")
+            torch.cuda.current_stream(self.device).synchronize()
 
 
 STAGES = ("forward_leaf", "forward_transfer", "coupling", "backward_transfer", "leaf_near")
@@ -230,6 +266,51 @@ def h2_matmul(A: H2Matrix, X, *, alpha=1.0, beta=0.0, out=None, tree_order=False
         assert stage_ms.dtype == np.float64 and stage_ms.size >= len(STAGES)
         _check(load_library().h2x_matmul_timed(*args, _ptr(stage_ms)), "h2x_matmul_timed")
     return out
+
+
+def _rowmajor(T, n, what):
+    import torch
+    if T.dtype != torch.float64 or T.device.type != "cuda" or T.dim() != 2 or T.stride(1) != 1 or T.shape[0] != n:
+        raise ValueError(f"{what} must be a row-major (n, m) float64 CUDA tensor")
+
+
+def h2_matmul_adjoint(A: H2Matrix, X, *, alpha=1.0, beta=0.0, out=None):
+    """Y <- beta Y + alpha A^T X through the column lists (h2x_matmul_adjoint)."""
+    import torch
+    _rowmajor(X, A.n, "X")
+    n, m = X.shape
+    if out is None:
+        if beta != 0.0:
+            raise ValueError("beta != 0 needs out")
+        out = torch.empty((n, m), dtype=torch.float64, device=X.device)
+    _rowmajor(out, n, "out")
+    ws = A.workspace(m, "adjoint")
+    _check(load_library().h2x_matmul_adjoint(A._h, m, float(alpha), C.c_void_p(X.data_ptr()), X.stride(0),
+                                             float(beta), C.c_void_p(out.data_ptr()), out.stride(0),
+                                             C.c_void_p(ws.data_ptr()), ws.numel(), _stream(torch, X.device)),
+           "h2x_matmul_adjoint")
+    return out
+
+
+def h2_grad(A: H2Matrix, X, dY, *, want_dS=True, want_dN=False, want_dell=True):
+    """Gradients of <dY, A X> (h2x_grad): returns (dS, dN, dell) as CUDA tensors, None
+    where not requested.  dS: (n_adm, k, k) in the order of Plan.blocks(); dN: the
+    near-field blocks, each |t| x |s| row-major in tree order, concatenated; dell: 0-d."""
+    import torch
+    _rowmajor(X, A.n, "X")
+    _rowmajor(dY, A.n, "dY")
+    if dY.shape != X.shape:
+        raise ValueError("X and dY must have the same shape")
+    m = X.shape[1]
+    dev = X.device
+    dS = torch.empty((A.plan.n_adm, A.k, A.k), dtype=torch.float64, device=dev) if want_dS else None
+    dN = torch.empty(A.plan.near_entries, dtype=torch.float64, device=dev) if want_dN else None
+    dl = torch.empty((), dtype=torch.float64, device=dev) if want_dell else None
+    ws = A.workspace(m, "grad")
+    vp = lambda t: C.c_void_p(t.data_ptr()) if t is not None and t.numel() else None
+    _check(load_library().h2x_grad(A._h, m, vp(X), X.stride(0), vp(dY), dY.stride(0), vp(dS), vp(dN), vp(dl),
+                                   C.c_void_p(ws.data_ptr()), ws.numel(), _stream(torch, dev)), "h2x_grad")
+    return dS, dN, dl
 
 
 @dataclass

@@ -177,6 +177,11 @@ h2x_status h2x_mat_create(const h2x_plan *plan, h2x_prec storage, void *dev_ws, 
     up(d.near_row, near_row);
     up(d.near_off, d.near_t ? P.near_off_t : P.near_off);
     up(d.vt_off, P.vt_off);
+    up(d.near_off_rm, P.near_off);
+    up(d.adm_cptr, P.adm_cptr);
+    up(d.adm_cblk, P.adm_cblk);
+    up(d.near_cptr, P.near_cptr);
+    up(d.near_cblk, P.near_cblk);
     up(d.perm, P.perm);
     up(d.pts, P.pts_tree);
     up(d.box, P.box);
@@ -271,6 +276,73 @@ h2x_status h2x_block_cg(const h2x_mat *A, const h2x_cg_params *prm, int64_t m, c
                                    (hipStream_t)hip_stream);
     if (prm->variant != H2X_CG_INDEPENDENT) return fail(H2X_EINVAL, "h2x_block_cg: unknown variant");
     return run_block_cg(A->dm, *prm, m, B, ldb, X, ldx, (char *)dev_ws, ws_bytes, info, (hipStream_t)hip_stream);
+}
+
+size_t h2x_matmul_adjoint_workspace_bytes(const h2x_mat *A, int64_t m) {
+    if (!A || m < 1) return 0;
+    return adjoint_ws_bytes(A->dm, m);
+}
+
+size_t h2x_grad_workspace_bytes(const h2x_mat *A, int64_t m) {
+    if (!A || m < 1) return 0;
+    return grad_ws_bytes(A->dm, m);
+}
+
+h2x_status h2x_matmul_adjoint(const h2x_mat *A, int64_t m, double alpha, const double *X, int64_t ldx, double beta,
+                              double *Y, int64_t ldy, void *dev_ws, size_t ws_bytes, void *hip_stream) {
+    if (!A || !X || !Y || !dev_ws) return fail(H2X_EINVAL, "h2x_matmul_adjoint: NULL argument");
+    if (A->dm.storage != H2X_F64 || A->dm.k > 64)
+        return fail(H2X_EUNSUPPORTED, "h2x_matmul_adjoint: FP64 operators with k <= 64 only");
+    if (m < 1 || ldx < m || ldy < m) return fail(H2X_EINVAL, "h2x_matmul_adjoint: need m >= 1, ldx >= m, ldy >= m");
+    if (!aligned(dev_ws)) return fail(H2X_EINVAL, "h2x_matmul_adjoint: workspace not 256-byte aligned");
+    if (ws_bytes < adjoint_ws_bytes(A->dm, m)) return fail(H2X_ENOMEM, "h2x_matmul_adjoint: workspace too small");
+    const int64_t n = A->dm.n;
+    const char *x0 = (const char *)X, *x1 = (const char *)(X + (n - 1) * ldx + m);
+    const char *y0 = (const char *)Y, *y1 = (const char *)(Y + (n - 1) * ldy + m);
+    if (x0 < y1 && y0 < x1) return fail(H2X_EINVAL, "h2x_matmul_adjoint: X and Y overlap");
+    hipError_t e = run_matmul_adjoint(A->dm, m, alpha, X, ldx, beta, Y, ldy, (char *)dev_ws, (hipStream_t)hip_stream);
+    if (e != hipSuccess) return hip_fail("h2x_matmul_adjoint", e);
+    return H2X_OK;
+}
+
+h2x_status h2x_grad(const h2x_mat *A, int64_t m, const double *X, int64_t ldx, const double *dY, int64_t lddy,
+                    double *dS, double *dN, double *dell, void *dev_ws, size_t ws_bytes, void *hip_stream) {
+    if (!A || !X || !dY || !dev_ws) return fail(H2X_EINVAL, "h2x_grad: NULL argument");
+    if (A->dm.storage != H2X_F64 || A->dm.k > 64)
+        return fail(H2X_EUNSUPPORTED, "h2x_grad: FP64 operators with k <= 64 only");
+    if (m < 1 || ldx < m || lddy < m) return fail(H2X_EINVAL, "h2x_grad: need m >= 1, ldx >= m, lddy >= m");
+    if (!aligned(dev_ws)) return fail(H2X_EINVAL, "h2x_grad: workspace not 256-byte aligned");
+    if (ws_bytes < grad_ws_bytes(A->dm, m)) return fail(H2X_ENOMEM, "h2x_grad: workspace too small");
+    if (!dS && !dN && !dell) return H2X_OK;
+    hipError_t e = run_grad(A->dm, m, X, ldx, dY, lddy, dS, dN, dell, (char *)dev_ws, (hipStream_t)hip_stream);
+    if (e != hipSuccess) return hip_fail("h2x_grad", e);
+    return H2X_OK;
+}
+
+h2x_status h2x_mat_set_ell(h2x_mat *A, double ell, void *hip_stream) {
+    if (!A) return fail(H2X_EINVAL, "h2x_mat_set_ell: NULL operator");
+    if (!(ell > 0.0) || !std::isfinite(ell)) return fail(H2X_EINVAL, "h2x_mat_set_ell: ell must be finite and > 0");
+    hipStream_t st = (hipStream_t)hip_stream;
+    hipError_t e = refill_ell(A->dm, ell, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail("h2x_mat_set_ell", e);
+    return H2X_OK;
+}
+
+h2x_status h2x_mat_coupling(const h2x_mat *A, double *out, void *hip_stream) {
+    if (!A || !out) return fail(H2X_EINVAL, "h2x_mat_coupling: NULL argument");
+    if (A->dm.storage != H2X_F64) return fail(H2X_EUNSUPPORTED, "h2x_mat_coupling: FP64 operators only");
+    hipError_t e = run_read_coupling(A->dm, out, (hipStream_t)hip_stream);
+    if (e != hipSuccess) return hip_fail("h2x_mat_coupling", e);
+    return H2X_OK;
+}
+
+h2x_status h2x_mat_set_coupling(h2x_mat *A, const double *in, void *hip_stream) {
+    if (!A || !in) return fail(H2X_EINVAL, "h2x_mat_set_coupling: NULL argument");
+    if (A->dm.storage != H2X_F64) return fail(H2X_EUNSUPPORTED, "h2x_mat_set_coupling: FP64 operators only");
+    hipError_t e = run_write_coupling(A->dm, in, (hipStream_t)hip_stream);
+    if (e != hipSuccess) return hip_fail("h2x_mat_set_coupling", e);
+    return H2X_OK;
 }
 
 size_t h2x_block_cg_refine_workspace_bytes(const h2x_mat *A, const h2x_mat *A_lo, int64_t m) {

@@ -35,6 +35,9 @@ struct DevMat {
     int32_t *near_row = nullptr; // n_near (row leaf cluster)
     int64_t *near_off = nullptr; // n_near (offsets in the layout selected by near_t)
     int64_t *vt_off = nullptr;   // L, offsets of the transposed leaf bases (matrix-core layout)
+    int64_t *near_off_rm = nullptr;  // n_near, offsets of row-major |t| x |s| blocks (gradient output)
+    int64_t *adm_cptr = nullptr, *adm_cblk = nullptr;    // admissible blocks by column cluster
+    int64_t *near_cptr = nullptr, *near_cblk = nullptr;  // near-field blocks by column leaf
     int64_t *perm = nullptr;     // n
     double *pts = nullptr;       // n x 3 tree order
     double *box = nullptr;       // C x 6
@@ -69,6 +72,23 @@ hipError_t run_matmul(const DevMat &dm, int64_t m, double alpha, const double *X
 size_t cg_ws_bytes(const DevMat &dm, int64_t m);
 h2x_status run_block_cg(const DevMat &dm, const h2x_cg_params &prm, int64_t m, const double *B, int64_t ldb,
                         double *X, int64_t ldx, char *ws, size_t ws_bytes, h2x_cg_info *info, hipStream_t st);
+
+// forward transformation of X into x-hat (leaves and every cluster at or below the
+// shallowest admissible depth); FP64 operators only
+hipError_t run_forward_transform(const DevMat &dm, int64_t m, const double *X, int64_t ldx, bool tree_order,
+                                 double *xh, int64_t ldh, double *xt_ws, hipStream_t st);
+hipError_t run_down_pass(const DevMat &dm, int64_t m, double *yh, int64_t ldh, hipStream_t st);
+
+// adjoint product Y = beta Y + alpha A^T X (column lists, transposed blocks)
+hipError_t run_matmul_adjoint(const DevMat &dm, int64_t m, double alpha, const double *X, int64_t ldx, double beta,
+                              double *Y, int64_t ldy, char *ws, hipStream_t st);
+size_t adjoint_ws_bytes(const DevMat &dm, int64_t m);
+size_t grad_ws_bytes(const DevMat &dm, int64_t m);
+hipError_t run_grad(const DevMat &dm, int64_t m, const double *X, int64_t ldx, const double *dY, int64_t lddy,
+                    double *dS, double *dN, double *dell, char *ws, hipStream_t st);
+hipError_t refill_ell(DevMat &dm, double ell, hipStream_t st);
+hipError_t run_read_coupling(const DevMat &dm, double *out, hipStream_t st);
+hipError_t run_write_coupling(const DevMat &dm, const double *in, hipStream_t st);
 
 size_t bcg_ws_bytes(const DevMat &dm, int64_t m);
 h2x_status run_block_cg_shared(const DevMat &dm, const h2x_cg_params &prm, int64_t m, const double *B, int64_t ldb,

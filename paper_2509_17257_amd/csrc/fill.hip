@@ -174,7 +174,28 @@ hipError_t fill_typed(const DevMat &dm, hipStream_t st) {
     return hipGetLastError();
 }
 
+template <typename T, typename TN>
+hipError_t refill_typed(const DevMat &dm, hipStream_t st) {
+    if (dm.n_adm > 0)
+        hipLaunchKernelGGL(k_fill_S<T>, dim3((unsigned)dm.n_adm), dim3(256), 0, st, dm.k, dm.kernel, dm.ell,
+                           dm.adm_row, dm.adm_col, dm.nodes, (T *)dm.S, s_swizzled(dm));
+    if (dm.n_near > 0)
+        hipLaunchKernelGGL(k_fill_N<TN>, dim3((unsigned)dm.n_near), dim3(256), 0, st, dm.kernel, dm.ell, dm.shift,
+                           dm.near_row, dm.near_col, dm.near_off, dm.first, dm.size, dm.pts, (TN *)dm.N,
+                           dm.near_t);
+    return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t refill_ell(DevMat &dm, double ell, hipStream_t st) {
+    dm.ell = ell;
+    switch (dm.storage) {
+        case H2X_F64: return refill_typed<double, double>(dm, st);
+        case H2X_F32: return refill_typed<float, float>(dm, st);
+        default: return refill_typed<bf16_t, float>(dm, st);
+    }
+}
 
 size_t mat_layout(const Plan &P, h2x_prec storage, DevMat *dm, char *base) {
     size_t cur = 0;
@@ -203,6 +224,11 @@ size_t mat_layout(const Plan &P, h2x_prec storage, DevMat *dm, char *base) {
     d.near_row = carve<int32_t>(cur, base, nn + 1);
     d.near_off = carve<int64_t>(cur, base, nn + 1);
     d.vt_off = carve<int64_t>(cur, base, L + 1);
+    d.near_off_rm = carve<int64_t>(cur, base, nn + 1);
+    d.adm_cptr = carve<int64_t>(cur, base, C + 1);
+    d.adm_cblk = carve<int64_t>(cur, base, na + 1);
+    d.near_cptr = carve<int64_t>(cur, base, L + 1);
+    d.near_cblk = carve<int64_t>(cur, base, nn + 1);
     d.perm = carve<int64_t>(cur, base, n);
     d.pts = carve<double>(cur, base, 3 * n);
     d.box = carve<double>(cur, base, 6 * (size_t)C);

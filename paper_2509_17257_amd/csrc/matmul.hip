@@ -407,6 +407,66 @@ hipError_t matmul_typed(const DevMat &dm, int64_t m, double alpha, const double 
 
 }  // namespace
 
+hipError_t run_forward_transform(const DevMat &dm, int64_t m, const double *X, int64_t ldx, bool tree_order,
+                                 double *xh, int64_t ldh, double *xt_ws, hipStream_t st) {
+    const Plan &P = *dm.plan;
+    const double *V = (const double *)dm.V, *E = (const double *)dm.E;
+    if (dm.swz == 1 && dm.k == mfma::K) {
+        const double *Xt = X;
+        int64_t ldxt = ldx;
+        if (!tree_order || (ldx & 1) || ((uintptr_t)X & 15)) {
+            ldxt = even_ld(m);
+            const int64_t cnt = dm.n * ldxt;
+            hipLaunchKernelGGL(mfma::k_gather, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, dm.n, m,
+                               tree_order ? nullptr : dm.perm, X, ldx, xt_ws, ldxt);
+            Xt = xt_ws;
+        }
+        const int nj = (int)std::min<int64_t>(4, (m + 15) / 16);
+        const unsigned gy = (unsigned)((m + 16 * nj - 1) / (16 * nj));
+        auto launch = [&](auto NJc) {
+            constexpr int NJ = decltype(NJc)::value;
+            hipLaunchKernelGGL(mfma::k_fwd_leaf<NJ>, dim3(dm.L, gy), dim3(256), 0, st, m, dm.leaves, dm.first, dm.size,
+                               dm.perm, V, Xt, ldxt, 1, xh, ldh);
+            for (int d = dm.depth_max - 1; d >= P.adm_depth; --d) {
+                const int32_t b = P.lvl_inner_ptr[d], e = P.lvl_inner_ptr[d + 1];
+                if (e > b)
+                    hipLaunchKernelGGL(mfma::k_up<NJ>, dim3(e - b, gy), dim3(256), 0, st, m, dm.lvl_inner + b,
+                                       dm.son0, dm.son1, E, xh, ldh);
+            }
+        };
+        switch (nj) {
+            case 1: launch(std::integral_constant<int, 1>{}); break;
+            case 2: launch(std::integral_constant<int, 2>{}); break;
+            case 3: launch(std::integral_constant<int, 3>{}); break;
+            default: launch(std::integral_constant<int, 4>{}); break;
+        }
+        return hipGetLastError();
+    }
+    const unsigned gy = (unsigned)((m + TC - 1) / TC);
+    hipLaunchKernelGGL((k_fwd_leaf<double, double>), dim3(dm.L, gy), dim3(256), 0, st, dm.k, m, dm.leaves, dm.first,
+                       dm.size, dm.perm, V, X, ldx, tree_order ? 1 : 0, xh, ldh);
+    for (int d = dm.depth_max - 1; d >= P.adm_depth; --d) {
+        const int32_t b = P.lvl_inner_ptr[d], e = P.lvl_inner_ptr[d + 1];
+        if (e > b)
+            hipLaunchKernelGGL((k_up<double, double>), dim3(e - b, gy), dim3(256), 0, st, dm.k, m, dm.lvl_inner + b,
+                               dm.son0, dm.son1, E, xh, ldh);
+    }
+    return hipGetLastError();
+}
+
+hipError_t run_down_pass(const DevMat &dm, int64_t m, double *yh, int64_t ldh, hipStream_t st) {
+    const Plan &P = *dm.plan;
+    const double *E = (const double *)dm.E;
+    const unsigned gy = (unsigned)((m + TC - 1) / TC);
+    for (int d = std::max(1, P.adm_depth + 1); d <= dm.depth_max; ++d) {
+        const int32_t b = P.lvl_ptr[d], e = P.lvl_ptr[d + 1];
+        if (e > b)
+            hipLaunchKernelGGL((k_down<double, double>), dim3(e - b, gy), dim3(256), 0, st, dm.k, m, dm.lvl_all + b,
+                               dm.parent, E, yh, ldh);
+    }
+    return hipGetLastError();
+}
+
 size_t matmul_ws_bytes(const DevMat &dm, int64_t m) {
     // x-hat, y-hat, and the tree-ordered copy of X used by the matrix-core path
     if (dm.storage == H2X_F64) return 2 * hat_bytes<double>(dm, m) + align_up(sizeof(double) * (size_t)dm.n * even_ld(m));

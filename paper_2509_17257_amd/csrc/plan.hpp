@@ -52,6 +52,13 @@ struct Plan {
     int64_t vt_entries = 0;
     int32_t max_leaf = 0;           // largest leaf size
 
+    // column lists for the adjoint: admissible blocks by column cluster (entries are
+    // indices into the row-ordered arrays), near-field blocks by column leaf
+    std::vector<int64_t> adm_cptr;  // C + 1
+    std::vector<int64_t> adm_cblk;  // n_adm
+    std::vector<int64_t> near_cptr; // L + 1
+    std::vector<int64_t> near_cblk; // n_near
+
     // launch order of the row clusters in the coupling stage: the rows are cut
     // into 8 contiguous eighths (one per XCD), longest list first within each
     std::vector<int32_t> cpl_order; // C

@@ -203,6 +203,23 @@ Plan *build_plan(const double *pts, int64_t n, const h2x_params &prm, std::strin
         }
     }
     P->near_entries = off;
+    // column lists (stable: row order within a column)
+    P->adm_cptr.assign(C + 1, 0);
+    for (int32_t s = 0; s < (int32_t)P->adm_col.size(); ++s) P->adm_cptr[P->adm_col[s] + 1]++;
+    for (int32_t c = 0; c < C; ++c) P->adm_cptr[c + 1] += P->adm_cptr[c];
+    P->adm_cblk.resize(P->adm_col.size());
+    {
+        std::vector<int64_t> f(P->adm_cptr.begin(), P->adm_cptr.end() - 1);
+        for (int64_t b = 0; b < (int64_t)P->adm_col.size(); ++b) P->adm_cblk[f[P->adm_col[b]]++] = b;
+    }
+    P->near_cptr.assign(L + 1, 0);
+    for (size_t q = 0; q < near.size(); ++q) P->near_cptr[P->leaf_index[P->near_col[q]] + 1]++;
+    for (int32_t l = 0; l < L; ++l) P->near_cptr[l + 1] += P->near_cptr[l];
+    P->near_cblk.resize(near.size());
+    {
+        std::vector<int64_t> f(P->near_cptr.begin(), P->near_cptr.end() - 1);
+        for (int64_t q = 0; q < (int64_t)near.size(); ++q) P->near_cblk[f[P->leaf_index[P->near_col[q]]]++] = q;
+    }
     P->adm_depth = P->depth_max + 1;
     for (auto &b : adm) P->adm_depth = std::min(P->adm_depth, std::min(P->depth[b.first], P->depth[b.second]));
     P->near_off_t.resize(near.size());

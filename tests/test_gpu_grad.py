@@ -1,0 +1,252 @@
+"""GPU parity of the differentiation entry points against the CPU oracle.
+
+* h2x_matmul_adjoint equals the oracle's adjoint product (column lists,
+  transposed blocks) to 1e-12 per column, on the symmetric operator and on one
+  made non-symmetric by a perturbed coupling block (h2x_mat_set_coupling), where
+  A^T differs from A.
+* h2x_grad: dS and dN equal the oracle's, block by block (matched through the
+  (t, s) pairs of both block orders), to 1e-12 of the largest entry; d ell equals
+  the oracle's within the rounding bound 1e-12 * sum |d g/d ell| |D| <=
+  1e-12 * (sum |dS| + sum |dN|) / (e ell), since |d g / d ell| <= 1 / (e ell).
+* h2x_mat_set_ell reproduces an operator built at the new length scale; d ell
+  agrees with a central difference of <dY, A(ell) X> (h = 1e-6).
+* torch.autograd: h2_apply's gradients equal the entry points' outputs; h2_solve's
+  implicit adjoint agrees with dense linear algebra on the assembled H^2 matrix
+  (oracle) and with a central difference of tight solves.
+* The differentiation workload at full size (131072 sphere points, k = 64, m = 16):
+  adjoint = product (symmetry), d ell against a central difference, and dS on
+  sampled blocks against the oracle's forward transformations.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2509_17257_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def _h2x():
+    import paper_2509_17257_amd as h2x
+    return h2x
+
+
+def _colrel(a, b):
+    den = np.linalg.norm(b, axis=0)
+    den[den == 0] = 1.0
+    return (np.linalg.norm(a - b, axis=0) / den).max()
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+CASES = [
+    ("small-k27-m4", lambda: W.SMALL.points(), W.SMALL.params(), 4),
+    ("sphere-k64-m32", lambda: W.sphere_points(6000, 181), dict(ell=0.5, shift=1.0, eta=1.0, leaf=64, p=4), 32),
+    ("cube-k64-m5", lambda: W.cube_points(7000, 182), dict(ell=0.25, shift=0.5, eta=1.0, leaf=64, p=4), 5),
+    ("cube-k8-leaf100-m3", lambda: W.cube_points(3000, 183), dict(ell=0.3, shift=0.5, eta=1.5, leaf=100, p=2), 3),
+    ("line-k27-m1", lambda: W.line_points(2000, 184), dict(ell=0.2, shift=1.0, eta=1.0, leaf=16, p=3), 1),
+    ("sphere-k64-m37", lambda: W.sphere_points(4000, 185), dict(ell=0.5, shift=1.0, eta=1.0, leaf=64, p=4), 37),
+]
+
+
+def _block_maps(o, pl):
+    """Oracle entry offsets of the library's blocks, in the library's storage order."""
+    ob = o.blocks()
+    adm = {(int(t), int(s)): int(f) for t, s, a, f in zip(ob["t"], ob["s"], ob["adm"], ob["off"]) if a}
+    near = {(int(t), int(s)): int(f) for t, s, a, f in zip(ob["t"], ob["s"], ob["adm"], ob["off"]) if not a}
+    pb = pl.blocks()
+    s_idx = np.array([adm[(int(t), int(s))] // (o.k * o.k) for t, s in zip(pb["adm_t"], pb["adm_s"])], np.int64)
+    n_off = np.array([near[(int(t), int(s))] for t, s in zip(pb["near_t"], pb["near_s"])], np.int64)
+    return s_idx, n_off
+
+
+@pytest.mark.parametrize("name,pts,prm,m", CASES, ids=[c[0] for c in CASES])
+def test_adjoint_and_grad_match_oracle(name, pts, prm, m):
+    h2x = _h2x()
+    P = pts()
+    n = P.shape[0]
+    o = oracle.OracleH2(P, **prm)
+    A = h2x.H2Matrix(P, **prm)
+    X, dY = W.rhs(n, m, 190 + m), W.rhs(n, m, 290 + m)
+    Xd, dYd = _dev(X), _dev(dY)
+
+    got = h2x.h2_matmul_adjoint(A, dYd).cpu().numpy()
+    err_adj = _colrel(got, o.matmul_adjoint(dY))
+    Y0 = W.rhs(n, m, 390 + m)
+    got2 = h2x.h2_matmul_adjoint(A, dYd, alpha=-0.5, beta=2.0, out=_dev(Y0)).cpu().numpy()
+    err_ab = _colrel(got2, o.matmul_adjoint(dY, alpha=-0.5, beta=2.0, Y=Y0))
+
+    dS, dN, dl = h2x.h2_grad(A, Xd, dYd, want_dS=True, want_dN=True, want_dell=True)
+    torch.cuda.synchronize()
+    oS, oN, odl = o.grad(X, dY)
+    s_idx, n_off = _block_maps(o, A.plan)
+    dS = dS.cpu().numpy()
+    err_S = np.abs(dS - oS[s_idx]).max() / max(np.abs(oS).max(), 1e-300) if o.n_adm else 0.0
+    # near-field blocks are contiguous in both layouts; compare block by block
+    dN = dN.cpu().numpy()
+    pb = A.plan.blocks()
+    cl = A.plan.clusters()
+    lib_off = 0
+    err_N = 0.0
+    for q in range(A.plan.n_near):
+        sz = int(cl["size"][pb["near_t"][q]] * cl["size"][pb["near_s"][q]])
+        a, b = dN[lib_off:lib_off + sz], oN[n_off[q]:n_off[q] + sz]
+        err_N = max(err_N, np.abs(a - b).max())
+        lib_off += sz
+    err_N /= np.abs(oN).max()
+    bound = 1e-12 * (np.abs(oS).sum() + np.abs(oN).sum()) / (math.e * prm["ell"])
+    err_l = abs(float(dl.cpu()) - odl)
+    print(f"{name}: adm={o.n_adm} near={o.n_near} adjoint {err_adj:.2e} (ab {err_ab:.2e}) dS {err_S:.2e} "
+          f"dN {err_N:.2e} dell {float(dl.cpu()):.12e} vs {odl:.12e} (diff {err_l:.2e}, bound {bound:.2e})")
+    assert err_adj <= TOL and err_ab <= TOL
+    assert err_S <= TOL and err_N <= TOL
+    assert err_l <= bound
+
+
+def test_adjoint_follows_transpose_of_nonsymmetric_operator():
+    h2x = _h2x()
+    P = W.sphere_points(5000, 186)
+    prm = dict(ell=0.5, shift=1.0, eta=1.0, leaf=64, p=4)
+    o = oracle.OracleH2(P, **prm)
+    A = h2x.H2Matrix(P, **prm)
+    s_idx, _ = _block_maps(o, A.plan)
+    S = o.S()
+    rng = np.random.default_rng(187)
+    S2 = S.copy()
+    for b in rng.choice(o.n_adm, 5, replace=False):
+        S2[b] += 0.05 * rng.standard_normal((o.k, o.k))
+    o.set_S(S2)
+    A.set_coupling(_dev(S2[s_idx]))
+    np.testing.assert_array_equal(A.coupling().cpu().numpy(), S2[s_idx])
+    X = W.rhs(5000, 6, 188)
+    ref_t, ref = o.matmul_adjoint(X), o.matmul(X)
+    assert _colrel(ref_t, ref) > 1e-6  # A^T differs from A
+    got_t = h2x.h2_matmul_adjoint(A, _dev(X)).cpu().numpy()
+    got = h2x.h2_matmul(A, _dev(X)).cpu().numpy()
+    print(f"nonsymmetric: adjoint {_colrel(got_t, ref_t):.2e} product {_colrel(got, ref):.2e}")
+    assert _colrel(got_t, ref_t) <= TOL and _colrel(got, ref) <= TOL
+
+
+def test_set_ell_and_dell_finite_difference():
+    h2x = _h2x()
+    P = W.sphere_points(6000, 189)
+    prm = dict(ell=0.5, shift=1.0, eta=1.0, leaf=64, p=4)
+    A = h2x.H2Matrix(P, **prm)
+    X, dY = W.rhs(6000, 8, 190), W.rhs(6000, 8, 191)
+    Xd, dYd = _dev(X), _dev(dY)
+    _, _, dl = h2x.h2_grad(A, Xd, dYd, want_dS=False)
+    dl = float(dl.cpu())
+    h = 1e-6
+    L = []
+    for e in (0.5 + h, 0.5 - h):
+        A.set_ell(e)
+        L.append(float((dYd * h2x.h2_matmul(A, Xd)).sum().cpu()))
+    fd = (L[0] - L[1]) / (2 * h)
+    A.set_ell(0.3)
+    o3 = oracle.OracleH2(P, **dict(prm, ell=0.3))
+    err = _colrel(h2x.h2_matmul(A, Xd).cpu().numpy(), o3.matmul(X))
+    print(f"dell {dl:.10e} fd {fd:.10e} rel {abs(dl - fd) / abs(dl):.2e}; set_ell product err {err:.2e}")
+    assert abs(dl - fd) <= 1e-6 * abs(dl)
+    assert err <= TOL
+
+
+def test_autograd_apply_matches_entry_points():
+    h2x = _h2x()
+    from paper_2509_17257_amd.autograd import h2_apply
+    P = W.sphere_points(5000, 192)
+    A = h2x.H2Matrix(P, ell=0.5, shift=1.0, eta=1.0, leaf=64, p=4)
+    X = _dev(W.rhs(5000, 4, 193)).requires_grad_(True)
+    Wt = _dev(W.rhs(5000, 4, 194))
+    ell = torch.tensor(0.45, dtype=torch.float64, requires_grad=True)
+    A.set_ell(0.45)
+    S = A.coupling().requires_grad_(True)
+    Y = h2_apply(A, X, ell, S)
+    (Wt * Y).sum().backward()
+    Xd = X.detach()
+    dX = h2x.h2_matmul_adjoint(A, Wt)
+    dS, _, dl = h2x.h2_grad(A, Xd, Wt)
+    torch.testing.assert_close(X.grad, dX, rtol=0, atol=0)
+    torch.testing.assert_close(S.grad, dS, rtol=0, atol=0)
+    assert float(ell.grad) == float(dl.cpu())
+    assert ell.grad.device.type == "cpu"
+    # the forward step ran the operator at ell = 0.45
+    o = oracle.OracleH2(P, ell=0.45, shift=1.0, eta=1.0, leaf=64, p=4)
+    assert _colrel(Y.detach().cpu().numpy(), o.matmul(Xd.cpu().numpy())) <= TOL
+
+
+def test_autograd_solve_implicit_adjoint():
+    h2x = _h2x()
+    from paper_2509_17257_amd.autograd import h2_solve
+    P = W.SMALL.points()
+    prm = W.SMALL.params()
+    n = P.shape[0]
+    A = h2x.H2Matrix(P, **prm)
+    o = oracle.OracleH2(P, **prm)
+    Bn, Cn = W.rhs(n, 3, 195), W.rhs(n, 3, 196)
+    B = _dev(Bn).requires_grad_(True)
+    ell = torch.tensor(float(prm["ell"]), dtype=torch.float64, requires_grad=True)
+    X = h2_solve(A, B, ell, rtol=1e-13)
+    (_dev(Cn) * X).sum().backward()
+    # dense reference on the assembled H^2 matrix (oracle)
+    Ad, dAd = o.dense(), o.dense_dell()
+    Xr = np.linalg.solve(Ad, Bn)
+    lam = np.linalg.solve(Ad, Cn)
+    dl_ref = -np.sum(lam * (dAd @ Xr))
+    errB = _colrel(B.grad.cpu().numpy(), lam)
+    errX = _colrel(X.detach().cpu().numpy(), Xr)
+    # central difference of tight solves (h = 1e-4: truncation ~h^2, solve noise ~1e-13 / h)
+    h = 1e-4
+    L = []
+    for e in (prm["ell"] + h, prm["ell"] - h):
+        A.set_ell(e)
+        Xe, info = h2x.block_cg_solve(A, _dev(Bn), rtol=1e-14, max_iter=2000)
+        L.append(float((_dev(Cn) * Xe).sum().cpu()))
+    fd = (L[0] - L[1]) / (2 * h)
+    g = float(ell.grad)
+    print(f"solve: X err {errX:.2e} dB err {errB:.2e} dell {g:.10e} dense {dl_ref:.10e} fd {fd:.10e}")
+    assert errX <= 1e-9 and errB <= 1e-9
+    assert abs(g - dl_ref) <= 1e-9 * abs(dl_ref)
+    assert abs(g - fd) <= 1e-6 * abs(g)
+
+
+def test_grad_workload_full_size():
+    """The differentiation workload at full size, checked by properties and samples."""
+    h2x = _h2x()
+    wl = W.GRADIENT
+    P = wl.points()
+    n, m = P.shape[0], wl.m
+    prm = wl.params()
+    A = h2x.H2Matrix(P, **prm)
+    X, dY = wl.rhs(), W.rhs(n, m, 2100 + wl.index)
+    Xd, dYd = _dev(X), _dev(dY)
+    adj = h2x.h2_matmul_adjoint(A, dYd)
+    fwd = h2x.h2_matmul(A, dYd)
+    err_sym = _colrel(adj.cpu().numpy(), fwd.cpu().numpy())
+    dS, _, dl = h2x.h2_grad(A, Xd, dYd)
+    dl = float(dl.cpu())
+    h = 1e-6
+    L = []
+    for e in (prm["ell"] + h, prm["ell"] - h):
+        A.set_ell(e)
+        L.append(float((dYd * h2x.h2_matmul(A, Xd)).sum().cpu()))
+    fd = (L[0] - L[1]) / (2 * h)
+    # sampled coupling gradients from the oracle's forward transformations
+    o = oracle.OracleH2(P, **prm)
+    xh, dh = o.forward_transform(X), o.forward_transform(dY)
+    pb = A.plan.blocks()
+    rng = np.random.default_rng(197)
+    idx = rng.choice(A.plan.n_adm, 64, replace=False)
+    dS_s = dS[torch.from_numpy(idx).cuda()].cpu().numpy()
+    ref = np.stack([dh[pb["adm_t"][b]] @ xh[pb["adm_s"][b]].T for b in idx])
+    err_S = np.abs(dS_s - ref).max() / np.abs(ref).max()
+    print(f"full size n={n}: adjoint-vs-product {err_sym:.2e}, dell {dl:.10e} fd {fd:.10e}, sampled dS {err_S:.2e}")
+    assert err_sym <= TOL
+    assert abs(dl - fd) <= 1e-6 * abs(dl)
+    assert err_S <= TOL

@@ -166,6 +166,62 @@ def precision_report(args, torch, h2x, W):
     print(json.dumps(out), flush=True)
 
 
+def grad_report(args, torch, h2x, W):
+    """Differentiation workload (n = 131072 on the sphere, exp(-r/0.5) + I, k = 64, m = 16, FP64):
+    forward product, adjoint product, gradients (dS and dell; dell only), block-CG solve to
+    1e-8 and its implicit-adjoint backward (a second solve plus the gradient kernels)."""
+    from paper_2509_17257_amd.autograd import h2_solve
+    w = W.WORKLOADS["sphere-n131072-k64-m16"]
+    dev = torch.device("cuda:0")
+    A = h2x.H2Matrix(w.points(), device=dev, **w.params())
+    plan = A.plan
+    m = w.m
+    X = torch.from_numpy(w.rhs()).to(dev)
+    dY = torch.from_numpy(W.rhs(w.n, m, 2100 + w.index)).to(dev)
+    out = {"workload": w.name, "n": w.n, "k": w.k, "m": m, "n_adm": plan.n_adm, "near_entries": plan.near_entries}
+    log(f"[grad] {w.name}: C={plan.C} adm={plan.n_adm} near entries={plan.near_entries}")
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    Y = torch.empty_like(X)
+    reps = max(3, min(args.steps, 50))
+    B_alg = alg_bytes(plan, m)
+    ms = timed(lambda: h2x.h2_matmul(A, X, out=Y), reps)
+    out["forward"] = {"ms": round(ms, 4), "alg_gbs": round(B_alg / (ms * 1e-3) / 1e9, 1)}
+    ms = timed(lambda: h2x.h2_matmul_adjoint(A, dY, out=Y), reps)
+    out["adjoint"] = {"ms": round(ms, 4), "alg_gbs": round(B_alg / (ms * 1e-3) / 1e9, 1)}
+    dS_bytes = 8 * plan.n_adm * plan.k * plan.k
+    ms = timed(lambda: h2x.h2_grad(A, X, dY, want_dS=True, want_dell=True), reps)
+    out["grad_dS_dell"] = {"ms": round(ms, 4), "dS_bytes": dS_bytes, "dS_write_gbs": round(dS_bytes / (ms * 1e-3) / 1e9, 1)}
+    ms = timed(lambda: h2x.h2_grad(A, X, dY, want_dS=False, want_dell=True), reps)
+    out["grad_dell"] = {"ms": round(ms, 4)}
+    log(f"[grad] {out}")
+    B = X
+    ell = torch.tensor(w.ell, dtype=torch.float64, requires_grad=True)
+    Bg = B.clone().requires_grad_(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Xs = h2_solve(A, Bg, ell, rtol=1e-8, max_iter=args.max_cg_iter)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    (dY * Xs).sum().backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    out["solve_1e-8"] = {"time_s": round(t1 - t0, 3)}
+    out["implicit_adjoint_backward"] = {"time_s": round(t2 - t1, 3), "dell": float(ell.grad)}
+    log(f"[grad] solve {t1 - t0:.3f} s, implicit-adjoint backward {t2 - t1:.3f} s")
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -177,6 +233,8 @@ def main():
     ap.add_argument("--cpu-baseline-s", type=float, default=12.0, help="0 disables the oracle timing")
     ap.add_argument("--precision-report", action="store_true",
                     help="report FP64 / FP32 / BF16 products and FP64 vs refined block CG on the precision workload")
+    ap.add_argument("--grad-report", action="store_true",
+                    help="time the adjoint product, gradients and implicit-adjoint solve on the differentiation workload")
     ap.add_argument("--copy-calibration-gib", type=float, default=0.0,
                     help="only run a plain device copy of this many GiB (to scale HBM traffic counters) and exit")
     args = ap.parse_args()
@@ -216,6 +274,9 @@ def main():
 
     if args.precision_report:
         precision_report(args, torch, h2x, W)
+        return
+    if args.grad_report:
+        grad_report(args, torch, h2x, W)
         return
 
     w = W.WORKLOADS[args.workload]

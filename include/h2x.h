@@ -110,6 +110,18 @@ h2x_status h2x_plan_clusters(const h2x_plan *plan, int64_t *first, int64_t *size
 h2x_status h2x_plan_blocks(const h2x_plan *plan, int64_t *adm_t, int64_t *adm_s, int64_t *near_t,
                            int64_t *near_s);
 
+/* Block-diagonal union of `count` plans (host, count >= 1): one plan whose
+ * operator is diag(A_1, ..., A_count), each system keeping its own cluster tree,
+ * blocks, lists and kernel parameters (kernel, ell, shift, leaf size, eta).  All
+ * plans must have the same cheb_order.  Rows (original and tree order) are the
+ * systems' rows concatenated in order.  Used to run many independent systems
+ * with one launch per stage and level.  The inputs stay owned by the caller. */
+h2x_status h2x_plan_merge(const h2x_plan *const *plans, int32_t count, h2x_plan **out);
+
+/* Number of systems of a plan (1 unless merged) and, if row_offsets is not
+ * NULL, the first row of each system plus the total (count + 1 host entries). */
+h2x_status h2x_plan_systems(const h2x_plan *plan, int32_t *count, int64_t *row_offsets);
+
 /* ---- operator ------------------------------------------------------------ */
 
 /* Bytes of device workspace an operator needs (topology + V, E, S in `storage`
@@ -157,6 +169,9 @@ typedef struct {
                                  1: converged columns stop updating                       */
     int32_t check_every;      /* read the device convergence flag every this many steps */
     int32_t variant;          /* H2X_CG_INDEPENDENT or H2X_CG_SHARED                     */
+    int32_t graph;            /* H2X_CG_INDEPENDENT: 1 captures check_every iterations (the
+                                 product and the CG kernels) once into a HIP graph on a
+                                 private stream and replays it; 0 launches every kernel     */
 } h2x_cg_params;
 
 /* H2X_CG_INDEPENDENT: the paper's block CG -- m independent CG iterations that
@@ -178,12 +193,18 @@ typedef struct {
     int32_t *col_iters;  /* host, m entries or NULL: iteration at which column i first met
                             the tolerance (iters if it never did)                      */
     int32_t *col_status; /* host, m entries or NULL: 0 ok, 1 breakdown, 2 not converged */
+    int32_t *sys_iters;  /* host, one entry per system or NULL: iteration at which the
+                            system stopped (every column converged or broken down)   */
 } h2x_cg_info;
 
 size_t h2x_block_cg_workspace_bytes(const h2x_mat *A, int64_t m);
 
 /* Solve A X = B for m right-hand sides with block CG: one H^2 x P product per
- * iteration, per-column step sizes (the paper's block CG).  B: device n x m,
+ * iteration, per-column step sizes (the paper's block CG).  For an operator on
+ * a merged plan (h2x_plan_merge) every system is solved independently in the
+ * same iterations: dot products, step sizes and convergence per system and
+ * column, and a system stops updating once all its columns have converged; the
+ * per-column info arrays then hold systems x m entries, system-major.  B: device n x m,
  * ldb; X: device n x m, ldx, holds X0 on entry and the iterate on exit.  A
  * column whose p^T A p is <= 0 or non-finite is frozen and reported.
  * Blocking: returns after the solve.  The return value reports argument and
@@ -211,6 +232,31 @@ h2x_status h2x_block_cg_refine(const h2x_mat *A, const h2x_mat *A_lo, const h2x_
                                int32_t max_outer, int64_t m, const double *B, int64_t ldb, double *X,
                                int64_t ldx, void *dev_ws, size_t ws_bytes, h2x_cg_info *info,
                                void *hip_stream);
+
+/* ---- batches ---------------------------------------------------------------- */
+/* A batch is a list of operators (typically one merged plan per Chebyshev order
+ * and storage precision) whose rows are concatenated in order: operator j owns
+ * rows [r_j, r_j + n_j) of every n_total x m block passed to the batch calls.
+ * The batch only refers to the operators, which must outlive it. */
+typedef struct h2x_batch h2x_batch;
+h2x_status h2x_batch_create(const h2x_mat *const *mats, int32_t count, h2x_batch **out);
+void h2x_batch_destroy(h2x_batch *batch);
+
+/* Y <- beta Y + alpha diag(A_1, ...) X over all operators of the batch (async). */
+size_t h2x_batch_matmul_workspace_bytes(const h2x_batch *batch, int64_t m);
+h2x_status h2x_batch_matmul(const h2x_batch *batch, int64_t m, double alpha, const double *X, int64_t ldx,
+                            double beta, double *Y, int64_t ldy, int32_t flags, void *dev_ws, size_t ws_bytes,
+                            void *hip_stream);
+
+/* Block CG (H2X_CG_INDEPENDENT) on every system of the batch at once: each
+ * iteration runs the products of all operators and one set of CG kernels over
+ * all rows, with per-system dot products and convergence (see h2x_block_cg).
+ * info arrays hold (total systems) x m entries.  Columns of B that are zero
+ * converge at once, so systems with fewer right-hand sides pad B with zeros. */
+size_t h2x_batch_block_cg_workspace_bytes(const h2x_batch *batch, int64_t m);
+h2x_status h2x_batch_block_cg(const h2x_batch *batch, const h2x_cg_params *prm, int64_t m, const double *B,
+                              int64_t ldb, double *X, int64_t ldx, void *dev_ws, size_t ws_bytes,
+                              h2x_cg_info *info, void *hip_stream);
 
 /* ---- differentiation ------------------------------------------------------- */
 /* The paper's products use the row lists C_t of section 3 ("prepare_addeval");

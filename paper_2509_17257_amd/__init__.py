@@ -14,8 +14,9 @@ from dataclasses import dataclass
 
 import numpy as np
 
-__all__ = ["Plan", "H2Matrix", "h2_matmul", "h2_matmul_adjoint", "h2_grad", "block_cg_solve", "block_cg_refine",
-           "library_path", "load_library", "F64", "F32", "BF16", "TREE_ORDER"]
+__all__ = ["Plan", "H2Matrix", "Batch", "h2_matmul", "h2_matmul_adjoint", "h2_grad", "block_cg_solve",
+           "block_cg_refine", "batch_matmul", "batch_block_cg_solve", "library_path", "load_library", "F64", "F32",
+           "BF16", "TREE_ORDER"]
 
 F64, F32, BF16 = 0, 1, 2
 _PREC = {"f64": F64, "f32": F32, "bf16": BF16, F64: F64, F32: F32, BF16: BF16}
@@ -47,7 +48,7 @@ class _Stats(C.Structure):
 
 class _CgParams(C.Structure):
     _fields_ = [("rtol", C.c_double), ("max_iter", C.c_int32), ("freeze_converged", C.c_int32),
-                ("check_every", C.c_int32), ("variant", C.c_int32)]
+                ("check_every", C.c_int32), ("variant", C.c_int32), ("graph", C.c_int32)]
 
 
 CG_INDEPENDENT, CG_SHARED = 0, 1
@@ -57,7 +58,8 @@ _VARIANT = {"independent": CG_INDEPENDENT, "shared": CG_SHARED, CG_INDEPENDENT: 
 class _CgInfo(C.Structure):
     _fields_ = [("iters", C.c_int32), ("status", C.c_int32), ("outer_iters", C.c_int32),
                 ("col_relres", C.POINTER(C.c_double)),
-                ("col_iters", C.POINTER(C.c_int32)), ("col_status", C.POINTER(C.c_int32))]
+                ("col_iters", C.POINTER(C.c_int32)), ("col_status", C.POINTER(C.c_int32)),
+                ("sys_iters", C.POINTER(C.c_int32))]
 
 
 def load_library():
@@ -77,6 +79,15 @@ def load_library():
         "h2x_plan_perm": (C.c_int, [P, P]),
         "h2x_plan_clusters": (C.c_int, [P, P, P, P, P, P, P]),
         "h2x_plan_blocks": (C.c_int, [P, P, P, P, P]),
+        "h2x_plan_merge": (C.c_int, [P, I32, C.POINTER(P)]),
+        "h2x_plan_systems": (C.c_int, [P, C.POINTER(I32), P]),
+        "h2x_batch_create": (C.c_int, [P, I32, C.POINTER(P)]),
+        "h2x_batch_destroy": (None, [P]),
+        "h2x_batch_matmul_workspace_bytes": (SZ, [P, I64]),
+        "h2x_batch_matmul": (C.c_int, [P, I64, D, P, I64, D, P, I64, I32, P, SZ, P]),
+        "h2x_batch_block_cg_workspace_bytes": (SZ, [P, I64]),
+        "h2x_batch_block_cg": (C.c_int, [P, C.POINTER(_CgParams), I64, P, I64, P, I64, P, SZ, C.POINTER(_CgInfo),
+                                         P]),
         "h2x_mat_workspace_bytes": (SZ, [P, C.c_int]),
         "h2x_mat_create": (C.c_int, [P, C.c_int, P, SZ, P, C.POINTER(P)]),
         "h2x_mat_destroy": (None, [P]),
@@ -119,16 +130,21 @@ def _ptr(a: np.ndarray):
 class Plan:
     """Host topology: cluster tree, block tree, lists (h2x_plan_create)."""
 
-    def __init__(self, points, *, kernel="exp", ell=0.5, shift=1.0, eta=1.0, leaf=32, p=3):
+    def __init__(self, points, *, kernel="exp", ell=0.5, shift=1.0, eta=1.0, leaf=32, p=3, _handle=None,
+                 _parts=None):
         lib = load_library()
-        pts = np.ascontiguousarray(points, dtype=np.float64)
-        if pts.ndim != 2 or pts.shape[1] != 3:
-            raise ValueError("points must be n x 3")
-        prm = _Params(_KERNEL[kernel] if isinstance(kernel, str) else int(kernel), float(ell), float(shift),
-                      float(eta), int(leaf), int(p))
-        h = C.c_void_p()
-        _check(lib.h2x_plan_create(_ptr(pts), pts.shape[0], C.byref(prm), C.byref(h)), "h2x_plan_create")
+        if _handle is None:
+            pts = np.ascontiguousarray(points, dtype=np.float64)
+            if pts.ndim != 2 or pts.shape[1] != 3:
+                raise ValueError("points must be n x 3")
+            prm = _Params(_KERNEL[kernel] if isinstance(kernel, str) else int(kernel), float(ell), float(shift),
+                          float(eta), int(leaf), int(p))
+            h = C.c_void_p()
+            _check(lib.h2x_plan_create(_ptr(pts), pts.shape[0], C.byref(prm), C.byref(h)), "h2x_plan_create")
+        else:
+            h = _handle
         self._h = h
+        self._parts = _parts
         self.params = dict(kernel=kernel, ell=ell, shift=shift, eta=eta, leaf=leaf, p=p)
         st = _Stats()
         _check(lib.h2x_plan_stats(h, C.byref(st)), "h2x_plan_stats")
@@ -142,6 +158,24 @@ class Plan:
         if getattr(self, "_h", None) and _lib is not None:
             _lib.h2x_plan_destroy(self._h)
             self._h = None
+
+    @classmethod
+    def merge(cls, plans):
+        """Block-diagonal union of plans with one Chebyshev order (h2x_plan_merge)."""
+        plans = list(plans)
+        arr = (C.c_void_p * len(plans))(*[p._h for p in plans])
+        h = C.c_void_p()
+        _check(load_library().h2x_plan_merge(arr, len(plans), C.byref(h)), "h2x_plan_merge")
+        p0 = plans[0].params
+        return cls(None, _handle=h, _parts=plans, **dict(p0, ell=float("nan"), shift=float("nan")))
+
+    def systems(self) -> np.ndarray:
+        """First row of every system plus the total (h2x_plan_systems)."""
+        cnt = C.c_int32()
+        _check(load_library().h2x_plan_systems(self._h, C.byref(cnt), None), "h2x_plan_systems")
+        off = np.zeros(cnt.value + 1, np.int64)
+        _check(load_library().h2x_plan_systems(self._h, C.byref(cnt), _ptr(off)), "h2x_plan_systems")
+        return off
 
     def perm(self) -> np.ndarray:
         a = np.zeros(self.n, np.int64)
@@ -321,34 +355,46 @@ class CgInfo:
     col_iters: np.ndarray
     col_status: np.ndarray
     outer_iters: int = 0
+    sys_iters: np.ndarray = None
 
 
-def _new_info(m):
-    rel = np.zeros(m)
-    its = np.zeros(m, np.int32)
-    sts = np.zeros(m, np.int32)
-    info = _CgInfo(0, 0, 0, rel.ctypes.data_as(C.POINTER(C.c_double)), its.ctypes.data_as(C.POINTER(C.c_int32)),
-                   sts.ctypes.data_as(C.POINTER(C.c_int32)))
-    return info, rel, its, sts
+def _new_info(m, nsys=1):
+    rel = np.zeros(nsys * m)
+    its = np.zeros(nsys * m, np.int32)
+    sts = np.zeros(nsys * m, np.int32)
+    sys = np.zeros(nsys, np.int32)
+    i32 = lambda a: a.ctypes.data_as(C.POINTER(C.c_int32))
+    info = _CgInfo(0, 0, 0, rel.ctypes.data_as(C.POINTER(C.c_double)), i32(its), i32(sts), i32(sys))
+    return info, rel, its, sts, sys
+
+
+def _info(info, rel, its, sts, sys, nsys, m):
+    shp = (nsys, m) if nsys > 1 else (m,)
+    return CgInfo(info.iters, info.status, rel.reshape(shp), its.reshape(shp), sts.reshape(shp), info.outer_iters,
+                  sys)
 
 
 def block_cg_solve(A: H2Matrix, B, X0=None, *, rtol=1e-8, max_iter=10000, freeze_converged=False,
-                   check_every=4, variant="independent"):
+                   check_every=4, variant="independent", graph=False):
     """Solve A X = B (block CG, h2x_block_cg).  variant "independent": the paper's m
     independent CG iterations sharing the product; "shared": one shared block Krylov
-    space with m x m Gram matrices.  Returns (X, CgInfo)."""
+    space with m x m Gram matrices.  graph: replay check_every captured iterations as
+    one HIP graph.  On a merged plan every system is solved on its own (info arrays
+    are systems x m).  Returns (X, CgInfo)."""
     import torch
     if B.dtype != torch.float64 or B.device.type != "cuda" or B.dim() != 2 or B.stride(1) != 1:
         raise ValueError("B must be a row-major (n, m) float64 CUDA tensor")
     n, m = B.shape
     X = torch.zeros_like(B) if X0 is None else X0.clone()
     ws = A.workspace(m, "cg")
-    info, rel, its, sts = _new_info(m)
-    prm = _CgParams(float(rtol), int(max_iter), int(bool(freeze_converged)), int(check_every), _VARIANT[variant])
+    nsys = len(A.plan.systems()) - 1
+    info, rel, its, sts, sys = _new_info(m, nsys)
+    prm = _CgParams(float(rtol), int(max_iter), int(bool(freeze_converged)), int(check_every), _VARIANT[variant],
+                    int(bool(graph)))
     _check(load_library().h2x_block_cg(A._h, C.byref(prm), m, C.c_void_p(B.data_ptr()), B.stride(0),
                                        C.c_void_p(X.data_ptr()), X.stride(0), C.c_void_p(ws.data_ptr()), ws.numel(),
                                        C.byref(info), _stream(torch, B.device)), "h2x_block_cg")
-    return X, CgInfo(info.iters, info.status, rel, its, sts)
+    return X, _info(info, rel, its, sts, sys, nsys, m)
 
 
 def block_cg_refine(A: H2Matrix, A_lo: H2Matrix, B, *, rtol=1e-10, inner_rtol=1e-4, max_outer=50,
@@ -363,10 +409,104 @@ def block_cg_refine(A: H2Matrix, A_lo: H2Matrix, B, *, rtol=1e-10, inner_rtol=1e
     lib = load_library()
     nb = lib.h2x_block_cg_refine_workspace_bytes(A._h, A_lo._h, m)
     ws = torch.empty(max(nb, 256), dtype=torch.uint8, device=B.device)
-    info, rel, its, sts = _new_info(m)
-    prm = _CgParams(float(inner_rtol), int(max_inner), 0, int(check_every), CG_INDEPENDENT)
+    info, rel, its, sts, sys = _new_info(m)
+    prm = _CgParams(float(inner_rtol), int(max_inner), 0, int(check_every), CG_INDEPENDENT, 0)
     _check(lib.h2x_block_cg_refine(A._h, A_lo._h, C.byref(prm), float(rtol), int(max_outer), m,
                                    C.c_void_p(B.data_ptr()), B.stride(0), C.c_void_p(X.data_ptr()), X.stride(0),
                                    C.c_void_p(ws.data_ptr()), ws.numel(), C.byref(info), _stream(torch, B.device)),
            "h2x_block_cg_refine")
-    return X, CgInfo(info.iters, info.status, rel, its, sts, info.outer_iters)
+    return X, _info(info, rel, its, sts, sys, 1, m)
+
+
+class Batch:
+    """Many independent systems (h2x_batch): systems with one Chebyshev order and
+    storage share one merged plan and operator, so every product stage is one launch
+    over all of them.  Rows of every batch-wide block are the systems' rows
+    concatenated in ``order`` (the operators' order; ``order[i]`` lists the system
+    indices, in the caller's numbering, of operator i)."""
+
+    def __init__(self, systems, *, storage="f64", device="cuda"):
+        """systems: list of (points, params dict) pairs."""
+        import torch
+        groups = {}
+        for i, (pts, prm) in enumerate(systems):
+            groups.setdefault(int(prm.get("p", 3)), []).append(i)
+        self.device = torch.device(device)
+        self.order, self.plans, self.mats = [], [], []
+        self._parts = []
+        for p in sorted(groups):
+            idx = groups[p]
+            parts = [Plan(systems[i][0], **systems[i][1]) for i in idx]
+            merged = Plan.merge(parts)
+            self._parts.append(parts)
+            self.plans.append(merged)
+            self.mats.append(H2Matrix(merged, storage=storage, device=self.device))
+            self.order.append(idx)
+        self.sizes = np.array([len(systems[i][0]) for i in range(len(systems))], np.int64)
+        perm = [i for idx in self.order for i in idx]
+        self.system_order = np.array(perm, np.int64)
+        self.row_offsets = np.zeros(len(perm) + 1, np.int64)
+        self.row_offsets[1:] = np.cumsum(self.sizes[self.system_order])
+        self.n = int(self.row_offsets[-1])
+        arr = (C.c_void_p * len(self.mats))(*[a._h for a in self.mats])
+        h = C.c_void_p()
+        _check(load_library().h2x_batch_create(arr, len(self.mats), C.byref(h)), "h2x_batch_create")
+        self._h = h
+        self._ws = {}
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.h2x_batch_destroy(self._h)
+            self._h = None
+
+    def rows(self, i: int):
+        """Row range of system i (caller's numbering) in batch-wide blocks."""
+        pos = int(np.nonzero(self.system_order == i)[0][0])
+        return int(self.row_offsets[pos]), int(self.row_offsets[pos + 1])
+
+    def workspace(self, m, kind):
+        import torch
+        ws = self._ws.get((kind, m))
+        if ws is None:
+            f = {"matmul": "h2x_batch_matmul_workspace_bytes", "cg": "h2x_batch_block_cg_workspace_bytes"}[kind]
+            nb = getattr(load_library(), f)(self._h, m)
+            ws = torch.empty(max(nb, 256), dtype=torch.uint8, device=self.device)
+            self._ws[(kind, m)] = ws
+        return ws
+
+
+def batch_matmul(batch: Batch, X, *, alpha=1.0, beta=0.0, out=None):
+    """Y <- beta Y + alpha diag(A_1, ...) X over the batch (h2x_batch_matmul)."""
+    import torch
+    _rowmajor(X, batch.n, "X")
+    m = X.shape[1]
+    if out is None:
+        if beta != 0.0:
+            raise ValueError("beta != 0 needs out")
+        out = torch.empty_like(X)
+    _rowmajor(out, batch.n, "out")
+    ws = batch.workspace(m, "matmul")
+    _check(load_library().h2x_batch_matmul(batch._h, m, float(alpha), C.c_void_p(X.data_ptr()), X.stride(0),
+                                           float(beta), C.c_void_p(out.data_ptr()), out.stride(0), 0,
+                                           C.c_void_p(ws.data_ptr()), ws.numel(), _stream(torch, X.device)),
+           "h2x_batch_matmul")
+    return out
+
+
+def batch_block_cg_solve(batch: Batch, B, *, rtol=1e-8, max_iter=10000, check_every=4, graph=True):
+    """Block CG on every system of the batch at once (h2x_batch_block_cg).  Systems with
+    fewer right-hand sides pad B with zero columns.  Returns (X, CgInfo) with info arrays
+    in the batch's system order (batch.system_order)."""
+    import torch
+    _rowmajor(B, batch.n, "B")
+    m = B.shape[1]
+    X = torch.zeros_like(B)
+    ws = batch.workspace(m, "cg")
+    nsys = len(batch.system_order)
+    info, rel, its, sts, sys = _new_info(m, nsys)
+    prm = _CgParams(float(rtol), int(max_iter), 0, int(check_every), CG_INDEPENDENT, int(bool(graph)))
+    _check(load_library().h2x_batch_block_cg(batch._h, C.byref(prm), m, C.c_void_p(B.data_ptr()), B.stride(0),
+                                             C.c_void_p(X.data_ptr()), X.stride(0), C.c_void_p(ws.data_ptr()),
+                                             ws.numel(), C.byref(info), _stream(torch, B.device)),
+           "h2x_batch_block_cg")
+    return X, _info(info, rel, its, sts, sys, nsys, m)

@@ -71,6 +71,31 @@ void h2x_plan_destroy(h2x_plan *plan) {
     delete plan;
 }
 
+h2x_status h2x_plan_merge(const h2x_plan *const *plans, int32_t count, h2x_plan **out) {
+    if (!out) return fail(H2X_EINVAL, "h2x_plan_merge: out is NULL");
+    *out = nullptr;
+    if (!plans || count < 1) return fail(H2X_EINVAL, "h2x_plan_merge: need count >= 1 plans");
+    std::vector<const Plan *> parts;
+    for (int32_t i = 0; i < count; ++i) {
+        if (!plans[i]) return fail(H2X_EINVAL, "h2x_plan_merge: NULL plan");
+        parts.push_back(plans[i]->p);
+    }
+    std::string err;
+    Plan *P = merge_plans(parts, err);
+    if (!P) return fail(H2X_EINVAL, "h2x_plan_merge: " + err);
+    *out = new h2x_plan{P};
+    return H2X_OK;
+}
+
+h2x_status h2x_plan_systems(const h2x_plan *plan, int32_t *count, int64_t *row_offsets) {
+    if (!plan || !count) return fail(H2X_EINVAL, "h2x_plan_systems: NULL argument");
+    const Plan &P = *plan->p;
+    *count = P.nsys();
+    if (row_offsets)
+        for (int32_t i = 0; i <= P.nsys(); ++i) row_offsets[i] = P.sys_row[i];
+    return H2X_OK;
+}
+
 h2x_status h2x_plan_stats(const h2x_plan *plan, h2x_stats *out) {
     if (!plan || !out) return fail(H2X_EINVAL, "h2x_plan_stats: NULL argument");
     const Plan &P = *plan->p;
@@ -271,11 +296,81 @@ h2x_status h2x_block_cg(const h2x_mat *A, const h2x_cg_params *prm, int64_t m, c
     if (m < 1 || ldb < m || ldx < m) return fail(H2X_EINVAL, "h2x_block_cg: need m >= 1, ldb >= m, ldx >= m");
     if (!(prm->rtol >= 0.0) || prm->max_iter < 0) return fail(H2X_EINVAL, "h2x_block_cg: bad rtol or max_iter");
     if (!aligned(dev_ws)) return fail(H2X_EINVAL, "h2x_block_cg: workspace not 256-byte aligned");
+    if (prm->variant == H2X_CG_SHARED && A->dm.plan->nsys() > 1)
+        return fail(H2X_EUNSUPPORTED, "h2x_block_cg: the shared-space variant is not for merged plans");
     if (prm->variant == H2X_CG_SHARED)
         return run_block_cg_shared(A->dm, *prm, m, B, ldb, X, ldx, (char *)dev_ws, ws_bytes, info,
                                    (hipStream_t)hip_stream);
     if (prm->variant != H2X_CG_INDEPENDENT) return fail(H2X_EINVAL, "h2x_block_cg: unknown variant");
     return run_block_cg(A->dm, *prm, m, B, ldb, X, ldx, (char *)dev_ws, ws_bytes, info, (hipStream_t)hip_stream);
+}
+
+h2x_status h2x_batch_create(const h2x_mat *const *mats, int32_t count, h2x_batch **out) {
+    if (!out) return fail(H2X_EINVAL, "h2x_batch_create: out is NULL");
+    *out = nullptr;
+    if (!mats || count < 1) return fail(H2X_EINVAL, "h2x_batch_create: need count >= 1 operators");
+    auto *b = new h2x_batch{};
+    for (int32_t i = 0; i < count; ++i) {
+        if (!mats[i]) {
+            delete b;
+            return fail(H2X_EINVAL, "h2x_batch_create: NULL operator");
+        }
+        b->mats.push_back(mats[i]);
+        b->dms.push_back(&mats[i]->dm);
+    }
+    *out = b;
+    return H2X_OK;
+}
+
+void h2x_batch_destroy(h2x_batch *batch) { delete batch; }
+
+size_t h2x_batch_matmul_workspace_bytes(const h2x_batch *batch, int64_t m) {
+    if (!batch || m < 1) return 0;
+    size_t b = 0;
+    for (auto *d : batch->dms) b = std::max(b, matmul_ws_bytes(*d, m));
+    return b;
+}
+
+h2x_status h2x_batch_matmul(const h2x_batch *batch, int64_t m, double alpha, const double *X, int64_t ldx,
+                            double beta, double *Y, int64_t ldy, int32_t flags, void *dev_ws, size_t ws_bytes,
+                            void *hip_stream) {
+    if (!batch || !X || !Y || !dev_ws) return fail(H2X_EINVAL, "h2x_batch_matmul: NULL argument");
+    if (m < 1 || ldx < m || ldy < m) return fail(H2X_EINVAL, "h2x_batch_matmul: need m >= 1, ldx >= m, ldy >= m");
+    if (flags & ~H2X_TREE_ORDER) return fail(H2X_EINVAL, "h2x_batch_matmul: unknown flags");
+    if (!aligned(dev_ws)) return fail(H2X_EINVAL, "h2x_batch_matmul: workspace not 256-byte aligned");
+    if (ws_bytes < h2x_batch_matmul_workspace_bytes(batch, m))
+        return fail(H2X_ENOMEM, "h2x_batch_matmul: workspace too small");
+    int64_t n = 0;
+    for (auto *d : batch->dms) n += d->n;
+    const char *x0 = (const char *)X, *x1 = (const char *)(X + (n - 1) * ldx + m);
+    const char *y0 = (const char *)Y, *y1 = (const char *)(Y + (n - 1) * ldy + m);
+    if (x0 < y1 && y0 < x1) return fail(H2X_EINVAL, "h2x_batch_matmul: X and Y overlap");
+    int64_t r = 0;
+    for (auto *d : batch->dms) {
+        hipError_t e = run_matmul(*d, m, alpha, X + r * ldx, ldx, beta, Y + r * ldy, ldy, (flags & H2X_TREE_ORDER) != 0,
+                                  (char *)dev_ws, (hipStream_t)hip_stream);
+        if (e != hipSuccess) return hip_fail("h2x_batch_matmul", e);
+        r += d->n;
+    }
+    return H2X_OK;
+}
+
+size_t h2x_batch_block_cg_workspace_bytes(const h2x_batch *batch, int64_t m) {
+    if (!batch || m < 1) return 0;
+    return cg_batch_ws_bytes(batch->dms.data(), (int32_t)batch->dms.size(), m);
+}
+
+h2x_status h2x_batch_block_cg(const h2x_batch *batch, const h2x_cg_params *prm, int64_t m, const double *B,
+                              int64_t ldb, double *X, int64_t ldx, void *dev_ws, size_t ws_bytes, h2x_cg_info *info,
+                              void *hip_stream) {
+    if (!batch || !prm || !B || !X || !dev_ws) return fail(H2X_EINVAL, "h2x_batch_block_cg: NULL argument");
+    if (m < 1 || ldb < m || ldx < m) return fail(H2X_EINVAL, "h2x_batch_block_cg: need m >= 1, ldb >= m, ldx >= m");
+    if (!(prm->rtol >= 0.0) || prm->max_iter < 0) return fail(H2X_EINVAL, "h2x_batch_block_cg: bad rtol or max_iter");
+    if (prm->variant != H2X_CG_INDEPENDENT)
+        return fail(H2X_EUNSUPPORTED, "h2x_batch_block_cg: only the independent variant");
+    if (!aligned(dev_ws)) return fail(H2X_EINVAL, "h2x_batch_block_cg: workspace not 256-byte aligned");
+    return run_block_cg_batch(batch->dms.data(), (int32_t)batch->dms.size(), *prm, m, B, ldb, X, ldx, (char *)dev_ws,
+                              ws_bytes, info, (hipStream_t)hip_stream);
 }
 
 size_t h2x_matmul_adjoint_workspace_bytes(const h2x_mat *A, int64_t m) {
@@ -310,6 +405,7 @@ h2x_status h2x_grad(const h2x_mat *A, int64_t m, const double *X, int64_t ldx, c
     if (!A || !X || !dY || !dev_ws) return fail(H2X_EINVAL, "h2x_grad: NULL argument");
     if (A->dm.storage != H2X_F64 || A->dm.k > 64)
         return fail(H2X_EUNSUPPORTED, "h2x_grad: FP64 operators with k <= 64 only");
+    if (A->dm.plan->nsys() > 1) return fail(H2X_EUNSUPPORTED, "h2x_grad: not for merged plans");
     if (m < 1 || ldx < m || lddy < m) return fail(H2X_EINVAL, "h2x_grad: need m >= 1, ldx >= m, lddy >= m");
     if (!aligned(dev_ws)) return fail(H2X_EINVAL, "h2x_grad: workspace not 256-byte aligned");
     if (ws_bytes < grad_ws_bytes(A->dm, m)) return fail(H2X_ENOMEM, "h2x_grad: workspace too small");
@@ -322,6 +418,7 @@ h2x_status h2x_grad(const h2x_mat *A, int64_t m, const double *X, int64_t ldx, c
 h2x_status h2x_mat_set_ell(h2x_mat *A, double ell, void *hip_stream) {
     if (!A) return fail(H2X_EINVAL, "h2x_mat_set_ell: NULL operator");
     if (!(ell > 0.0) || !std::isfinite(ell)) return fail(H2X_EINVAL, "h2x_mat_set_ell: ell must be finite and > 0");
+    if (A->dm.plan->nsys() > 1) return fail(H2X_EUNSUPPORTED, "h2x_mat_set_ell: not for merged plans");
     hipStream_t st = (hipStream_t)hip_stream;
     hipError_t e = refill_ell(A->dm, ell, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -356,6 +453,7 @@ h2x_status h2x_block_cg_refine(const h2x_mat *A, const h2x_mat *A_lo, const h2x_
     if (!A || !A_lo || !inner || !B || !X || !dev_ws) return fail(H2X_EINVAL, "h2x_block_cg_refine: NULL argument");
     if (A->plan != A_lo->plan) return fail(H2X_EINVAL, "h2x_block_cg_refine: A and A_lo must share one plan");
     if (A->dm.storage != H2X_F64) return fail(H2X_EINVAL, "h2x_block_cg_refine: A must be stored in FP64");
+    if (A->dm.plan->nsys() > 1) return fail(H2X_EUNSUPPORTED, "h2x_block_cg_refine: not for merged plans");
     if (m < 1 || ldb < m || ldx < m) return fail(H2X_EINVAL, "h2x_block_cg_refine: need m >= 1, ldb >= m, ldx >= m");
     if (!(rtol >= 0.0) || max_outer < 0 || !(inner->rtol >= 0.0) || inner->max_iter < 0)
         return fail(H2X_EINVAL, "h2x_block_cg_refine: bad tolerance or iteration limit");

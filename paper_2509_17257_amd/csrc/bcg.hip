@@ -428,6 +428,7 @@ h2x_status run_block_cg_shared(const DevMat &dm, const h2x_cg_params &prm, int64
         info->iters = hs.iter;
         info->status = status;
         info->outer_iters = 0;
+        if (info->sys_iters) info->sys_iters[0] = hs.iter;
         for (int64_t j = 0; j < m; ++j) {
             const double bn = hs.bnorm[j], rn = hs.rnorm[j];
             if (info->col_relres) info->col_relres[j] = bn > 0 ? rn / bn : rn;

@@ -26,9 +26,19 @@ struct CgState {
     int32_t all_conv, skip, iter, pad;
 };
 
-struct CgCols {  // per-column arrays, m entries each
+struct CgCols {  // per (system, column) arrays, nseg * m entries each, system-major
     double *bnorm, *rr, *beta, *alpha, *gamma;
     int32_t *frozen, *conv, *first_conv, *status, *act;
+};
+
+// Dot-product blocks: block b covers rows [blk_r0[b], blk_r0[b + 1]) of system
+// blk_seg[b]; system s owns blocks [seg_blk[s], seg_blk[s + 1]).  A system stops
+// (seg_done) once all its columns have converged or broken down.
+struct Segs {
+    const int64_t *blk_r0;
+    const int32_t *blk_seg, *seg_blk;
+    int32_t *seg_done, *seg_iters;
+    int32_t nseg;
 };
 
 __global__ void k_gather_rows(int64_t n, int64_t m, const int64_t *__restrict__ perm, const double *__restrict__ src,
@@ -52,16 +62,14 @@ __global__ void k_copy(int64_t count, const double *__restrict__ src, double *__
     if (e < count) dst[e] = src[e];
 }
 
-// Partial sums of up to two column-wise dot products over one block of rows:
-// part[(pair * nblk + blk) * m + j].  Row ownership is fixed, the reduction
-// order too.
-__device__ inline void block_dots(int64_t n, int64_t m, int nblk, const double *u0, const double *v0,
+// Partial sums of up to two column-wise dot products over rows [r0, r1):
+// part[(pair * nblk + blockIdx.x) * m + j].  Row ownership is fixed, the
+// reduction order too.
+__device__ inline void block_dots(int64_t r0, int64_t r1, int64_t m, int nblk, const double *u0, const double *v0,
                                   const double *u1, const double *v1, double *part) {
     __shared__ double red[2][8][kDotCols];
     const int tid = threadIdx.x, rg = tid >> 5, jl = tid & 31;
     const int64_t j = (int64_t)blockIdx.y * kDotCols + jl;
-    const int64_t rows = (n + nblk - 1) / nblk;
-    const int64_t r0 = (int64_t)blockIdx.x * rows, r1 = min(n, r0 + rows);
     double s0 = 0.0, s1 = 0.0;
     if (j < m)
         for (int64_t i = r0 + rg; i < r1; i += 8) {
@@ -79,11 +87,20 @@ __device__ inline void block_dots(int64_t n, int64_t m, int nblk, const double *
     }
 }
 
+// rows split evenly over nblk blocks (one system)
 __global__ __launch_bounds__(256) void k_dots(int64_t n, int64_t m, int nblk, const double *u0, const double *v0,
-                                              const double *u1, const double *v1, double *part,
-                                              const CgState *state) {
+                                              const double *u1, const double *v1, double *part) {
+    const int64_t rows = (n + nblk - 1) / nblk;
+    const int64_t r0 = (int64_t)blockIdx.x * rows;
+    block_dots(r0, min(n, r0 + rows), m, nblk, u0, v0, u1, v1, part);
+}
+
+// rows split by the system tables
+__global__ __launch_bounds__(256) void k_sdots(int64_t m, int nblk, Segs sg, const double *u0, const double *v0,
+                                               const double *u1, const double *v1, double *part,
+                                               const CgState *state) {
     if (state && state->skip) return;
-    block_dots(n, m, nblk, u0, v0, u1, v1, part);
+    block_dots(sg.blk_r0[blockIdx.x], sg.blk_r0[blockIdx.x + 1], m, nblk, u0, v0, u1, v1, part);
 }
 
 __device__ inline double sum_part(const double *part, int pair, int nblk, int64_t m, int64_t j) {
@@ -92,120 +109,192 @@ __device__ inline double sum_part(const double *part, int pair, int nblk, int64_
     return s;
 }
 
-// initial norms: pairs (B, B) and (R, R)
-__global__ void k_cg_init(int64_t m, int nblk, const double *part, double rtol, CgState *state, CgCols cols) {
-    __shared__ int notconv;
-    if (threadIdx.x == 0) notconv = 0;
+__device__ inline double sum_seg(const double *part, int pair, int nblk, int64_t m, const Segs &sg, int seg,
+                                 int64_t j) {
+    double s = 0.0;
+    for (int b = sg.seg_blk[seg]; b < sg.seg_blk[seg + 1]; ++b) s += part[((int64_t)pair * nblk + b) * m + j];
+    return s;
+}
+
+// a system is done when each of its columns has converged or broken down; the
+// iteration stops when every system is done
+__device__ inline void systems_done(int64_t m, int it, CgState *state, const CgCols &cols, const Segs &sg) {
+    __shared__ int notdone;
+    if (threadIdx.x == 0) notdone = 0;
     __syncthreads();
-    for (int64_t j = threadIdx.x; j < m; j += blockDim.x) {
-        const double bb = sum_part(part, 0, nblk, m, j), rr = sum_part(part, 1, nblk, m, j);
-        cols.bnorm[j] = sqrt(bb);
-        cols.rr[j] = rr;
-        const int c = sqrt(rr) <= rtol * sqrt(bb);
-        cols.conv[j] = c;
-        cols.first_conv[j] = c ? 0 : -1;
-        cols.frozen[j] = 0;
-        cols.status[j] = 0;
-        cols.act[j] = 0;
-        if (!c) atomicOr(&notconv, 1);
+    for (int s = threadIdx.x; s < sg.nseg; s += blockDim.x) {
+        if (sg.seg_done[s]) continue;
+        int d = 1;
+        for (int64_t j = 0; j < m; ++j) d &= cols.conv[s * m + j] | cols.frozen[s * m + j];
+        if (d) {
+            sg.seg_done[s] = 1;
+            sg.seg_iters[s] = it;
+        } else {
+            atomicOr(&notdone, 1);
+        }
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        state->all_conv = notconv ? 0 : 1;
-        state->skip = 0;
-        state->iter = 0;
+        state->iter = it;
+        state->all_conv = notdone ? 0 : 1;
     }
 }
 
-// pairs (P, AP) and (P, R): beta_i, alpha_i, breakdown detection
+// initial norms: pairs (B, B) and (R, R)
+__global__ void k_cg_init(int64_t m, int nblk, const double *part, double rtol, CgState *state, CgCols cols, Segs sg) {
+    for (int64_t e = threadIdx.x; e < sg.nseg * m; e += blockDim.x) {
+        const int s = (int)(e / m);
+        const int64_t j = e % m;
+        const double bb = sum_seg(part, 0, nblk, m, sg, s, j), rr = sum_seg(part, 1, nblk, m, sg, s, j);
+        cols.bnorm[e] = sqrt(bb);
+        cols.rr[e] = rr;
+        const int c = sqrt(rr) <= rtol * sqrt(bb);
+        cols.conv[e] = c;
+        cols.first_conv[e] = c ? 0 : -1;
+        cols.frozen[e] = 0;
+        cols.status[e] = 0;
+        cols.act[e] = 0;
+    }
+    for (int s = threadIdx.x; s < sg.nseg; s += blockDim.x) {
+        sg.seg_done[s] = 0;
+        sg.seg_iters[s] = 0;
+    }
+    if (threadIdx.x == 0) state->skip = 0;
+    __syncthreads();
+    systems_done(m, 0, state, cols, sg);
+}
+
+// pairs (P, AP) and (P, R): beta, alpha, breakdown detection
 __global__ void k_cg_alpha(int64_t m, int nblk, const double *part, int freeze_converged, CgState *state,
-                           CgCols cols) {
+                           CgCols cols, Segs sg) {
     const int skip = state->all_conv;
     __syncthreads();
     if (threadIdx.x == 0) state->skip = skip;
     if (skip) return;
-    for (int64_t j = threadIdx.x; j < m; j += blockDim.x) {
-        const double beta = sum_part(part, 0, nblk, m, j), rho = sum_part(part, 1, nblk, m, j);
+    for (int64_t e = threadIdx.x; e < sg.nseg * m; e += blockDim.x) {
+        const int s = (int)(e / m);
+        const int64_t j = e % m;
         // an exactly zero residual is an exact solution: nothing to update
-        int act = !cols.frozen[j] && !(freeze_converged && cols.conv[j]) && cols.rr[j] > 0.0;
-        double alpha = 0.0;
+        int act = !sg.seg_done[s] && !cols.frozen[e] && !(freeze_converged && cols.conv[e]) && cols.rr[e] > 0.0;
+        double alpha = 0.0, beta = 0.0;
         if (act) {
+            beta = sum_seg(part, 0, nblk, m, sg, s, j);
+            const double rho = sum_seg(part, 1, nblk, m, sg, s, j);
             alpha = rho / beta;
             if (!(beta > 0.0) || !isfinite(alpha)) {
-                cols.frozen[j] = 1;
-                cols.status[j] = 1;
+                cols.frozen[e] = 1;
+                cols.status[e] = 1;
                 act = 0;
                 alpha = 0.0;
             }
         }
-        cols.beta[j] = beta;
-        cols.alpha[j] = alpha;
-        cols.act[j] = act;
+        cols.beta[e] = beta;
+        cols.alpha[e] = alpha;
+        cols.act[e] = act;
     }
 }
 
 // x += alpha p, r -= alpha a for active columns; then partial sums of <a, r>, <r, r>
-__global__ __launch_bounds__(256) void k_cg_update_xr(int64_t n, int64_t m, int nblk, double *X, double *R,
+__global__ __launch_bounds__(256) void k_cg_update_xr(int64_t m, int nblk, Segs sg, double *X, double *R,
                                                       const double *P, const double *AP, double *part,
                                                       const CgState *state, CgCols cols) {
     if (state->skip) return;
     const int tid = threadIdx.x, rg = tid >> 5, jl = tid & 31;
     const int64_t j = (int64_t)blockIdx.y * kDotCols + jl;
-    const int64_t rows = (n + nblk - 1) / nblk;
-    const int64_t r0 = (int64_t)blockIdx.x * rows, r1 = min(n, r0 + rows);
-    if (j < m && cols.act[j]) {
-        const double a = cols.alpha[j];
+    const int64_t r0 = sg.blk_r0[blockIdx.x], r1 = sg.blk_r0[blockIdx.x + 1];
+    const int64_t e = (int64_t)sg.blk_seg[blockIdx.x] * m + j;
+    if (j < m && cols.act[e]) {
+        const double a = cols.alpha[e];
         for (int64_t i = r0 + rg; i < r1; i += 8) {
             X[i * m + j] += a * P[i * m + j];
             R[i * m + j] -= a * AP[i * m + j];
         }
     }
     // each thread re-reads only the rows it just wrote, so no barrier is needed
-    block_dots(n, m, nblk, AP, R, R, R, part);
+    block_dots(r0, r1, m, nblk, AP, R, R, R, part);
 }
 
-// gamma_i, convergence test, iteration count
-__global__ void k_cg_gamma(int64_t m, int nblk, const double *part, double rtol, CgState *state, CgCols cols) {
+// gamma, convergence test, iteration count
+__global__ void k_cg_gamma(int64_t m, int nblk, const double *part, double rtol, CgState *state, CgCols cols,
+                           Segs sg) {
     if (state->skip) return;
-    __shared__ int notconv;
-    if (threadIdx.x == 0) notconv = 0;
-    __syncthreads();
     const int it = state->iter + 1;
-    for (int64_t j = threadIdx.x; j < m; j += blockDim.x) {
-        const double ar = sum_part(part, 0, nblk, m, j), rr = sum_part(part, 1, nblk, m, j);
-        cols.gamma[j] = cols.act[j] ? ar / cols.beta[j] : 0.0;
-        cols.rr[j] = rr;
-        const int c = sqrt(rr) <= rtol * cols.bnorm[j];
-        cols.conv[j] = c;
-        if (c && cols.first_conv[j] < 0) cols.first_conv[j] = it;
-        if (!c && !cols.frozen[j]) atomicOr(&notconv, 1);
+    for (int64_t e = threadIdx.x; e < sg.nseg * m; e += blockDim.x) {
+        const int s = (int)(e / m);
+        if (sg.seg_done[s]) continue;
+        const int64_t j = e % m;
+        const double ar = sum_seg(part, 0, nblk, m, sg, s, j), rr = sum_seg(part, 1, nblk, m, sg, s, j);
+        cols.gamma[e] = cols.act[e] ? ar / cols.beta[e] : 0.0;
+        cols.rr[e] = rr;
+        const int c = sqrt(rr) <= rtol * cols.bnorm[e];
+        cols.conv[e] = c;
+        if (c && cols.first_conv[e] < 0) cols.first_conv[e] = it;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        state->iter = it;
-        state->all_conv = notconv ? 0 : 1;
-    }
+    systems_done(m, it, state, cols, sg);
 }
 
 // p = r - gamma p for active columns
-__global__ void k_cg_update_p(int64_t n, int64_t m, const double *R, double *P, const CgState *state, CgCols cols) {
+__global__ __launch_bounds__(256) void k_cg_update_p(int64_t m, Segs sg, const double *R, double *P,
+                                                     const CgState *state, CgCols cols) {
     if (state->skip) return;
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= n * m) return;
-    const int64_t j = e % m;
-    if (cols.act[j]) P[e] = R[e] - cols.gamma[j] * P[e];
+    const int tid = threadIdx.x, rg = tid >> 5, jl = tid & 31;
+    const int64_t j = (int64_t)blockIdx.y * kDotCols + jl;
+    const int64_t e = (int64_t)sg.blk_seg[blockIdx.x] * m + j;
+    if (j >= m || !cols.act[e]) return;
+    const double g = cols.gamma[e];
+    for (int64_t i = sg.blk_r0[blockIdx.x] + rg; i < sg.blk_r0[blockIdx.x + 1]; i += 8)
+        P[i * m + j] = R[i * m + j] - g * P[i * m + j];
+}
+
+// Rows of the concatenated systems: operator j owns rows [row0[j], row0[j] + n_j)
+// (its own original or tree order); its systems follow in order.
+struct Layout {
+    std::vector<int64_t> row0;
+    std::vector<int64_t> blk_r0;
+    std::vector<int32_t> blk_seg, seg_blk;
+    int64_t n = 0;
+    int32_t nseg = 0, nblk = 0;
+    size_t mm_bytes = 0;
+};
+
+Layout make_layout(const DevMat *const *mats, int32_t nmat, int64_t m) {
+    Layout L;
+    L.seg_blk.push_back(0);
+    for (int32_t q = 0; q < nmat; ++q) {
+        const DevMat &dm = *mats[q];
+        const Plan &P = *dm.plan;
+        L.row0.push_back(L.n);
+        for (int32_t s = 0; s < P.nsys(); ++s) {
+            const int64_t a = L.n + P.sys_row[s], ns = P.sys_row[s + 1] - P.sys_row[s];
+            const int64_t nb = std::min<int64_t>(1024, std::max<int64_t>(1, (ns + 63) / 64));
+            const int64_t rows = (ns + nb - 1) / nb;
+            for (int64_t b = 0; b < nb; ++b) {
+                L.blk_r0.push_back(a + std::min(ns, b * rows));
+                L.blk_seg.push_back(L.nseg);
+            }
+            ++L.nseg;
+            L.seg_blk.push_back((int32_t)L.blk_seg.size());
+        }
+        L.n += dm.n;
+        L.mm_bytes = std::max(L.mm_bytes, matmul_ws_bytes(dm, m));
+    }
+    L.blk_r0.push_back(L.n);
+    L.nblk = (int32_t)L.blk_seg.size();
+    return L;
 }
 
 struct CgWs {
     double *Bt, *Xt, *R, *P, *AP, *part;
     CgState *state;
     CgCols cols;
+    int64_t *blk_r0;
+    int32_t *blk_seg, *seg_blk, *seg_done, *seg_iters;
     char *mm;
-    int nblk;
     size_t bytes;
 };
 
-CgWs cg_layout(const DevMat &dm, int64_t m, char *base) {
+CgWs cg_layout(const Layout &L, int64_t m, char *base) {
     CgWs w{};
     size_t off = 0;
     auto carve = [&](size_t bytes) {
@@ -214,20 +303,24 @@ CgWs cg_layout(const DevMat &dm, int64_t m, char *base) {
         off += bytes;
         return p;
     };
-    const size_t nm = (size_t)dm.n * m * sizeof(double);
-    w.nblk = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (dm.n + 63) / 64));
+    const size_t nm = (size_t)L.n * m * sizeof(double), sm = (size_t)L.nseg * m;
     w.Bt = (double *)carve(nm);
     w.Xt = (double *)carve(nm);
     w.R = (double *)carve(nm);
     w.P = (double *)carve(nm);
     w.AP = (double *)carve(nm);
-    w.part = (double *)carve(2 * (size_t)w.nblk * m * sizeof(double));
+    w.part = (double *)carve(2 * (size_t)L.nblk * m * sizeof(double));
     w.state = (CgState *)carve(sizeof(CgState));
     double **dcols[5] = {&w.cols.bnorm, &w.cols.rr, &w.cols.beta, &w.cols.alpha, &w.cols.gamma};
-    for (auto d : dcols) *d = (double *)carve(m * sizeof(double));
+    for (auto d : dcols) *d = (double *)carve(sm * sizeof(double));
     int32_t **icols[5] = {&w.cols.frozen, &w.cols.conv, &w.cols.first_conv, &w.cols.status, &w.cols.act};
-    for (auto d : icols) *d = (int32_t *)carve(m * sizeof(int32_t));
-    w.mm = carve(matmul_ws_bytes(dm, m));
+    for (auto d : icols) *d = (int32_t *)carve(sm * sizeof(int32_t));
+    w.blk_r0 = (int64_t *)carve((L.nblk + 1) * sizeof(int64_t));
+    w.blk_seg = (int32_t *)carve(L.nblk * sizeof(int32_t));
+    w.seg_blk = (int32_t *)carve((L.nseg + 1) * sizeof(int32_t));
+    w.seg_done = (int32_t *)carve(L.nseg * sizeof(int32_t));
+    w.seg_iters = (int32_t *)carve(L.nseg * sizeof(int32_t));
+    w.mm = carve(L.mm_bytes);
     w.bytes = align_up(off);
     return w;
 }
@@ -286,14 +379,21 @@ RefineWs refine_layout(const DevMat &hi, const DevMat &lo, int64_t m, char *base
     w.part = (double *)carve(2 * (size_t)w.nblk * m * sizeof(double));
     w.norms = (double *)carve(2 * m * sizeof(double));
     w.mm = carve(matmul_ws_bytes(hi, m));
-    w.cg = carve(cg_layout(lo, m, nullptr).bytes);
+    w.cg = carve(cg_ws_bytes(lo, m));
     w.bytes = align_up(off);
     return w;
 }
 
 }  // namespace
 
-size_t cg_ws_bytes(const DevMat &dm, int64_t m) { return cg_layout(dm, m, nullptr).bytes; }
+size_t cg_batch_ws_bytes(const DevMat *const *mats, int32_t nmat, int64_t m) {
+    return cg_layout(make_layout(mats, nmat, m), m, nullptr).bytes;
+}
+
+size_t cg_ws_bytes(const DevMat &dm, int64_t m) {
+    const DevMat *p = &dm;
+    return cg_batch_ws_bytes(&p, 1, m);
+}
 
 size_t refine_ws_bytes(const DevMat &hi, const DevMat &lo, int64_t m) { return refine_layout(hi, lo, m, nullptr).bytes; }
 
@@ -321,8 +421,7 @@ h2x_status run_refine(const DevMat &hi, const DevMat &lo, const h2x_cg_params &i
         hipLaunchKernelGGL(k_copy, dim3(g1), dim3(256), 0, st, nm, (const double *)w.B, w.R);
         hipError_t e = run_matmul(hi, m, -1.0, X, ldx, 1.0, w.R, m, false, w.mm, st);
         if (e != hipSuccess) return fail(e);
-        hipLaunchKernelGGL(k_dots, gd, dim3(256), 0, st, n, m, w.nblk, w.R, w.R, w.B, w.B, w.part,
-                           (const CgState *)nullptr);
+        hipLaunchKernelGGL(k_dots, gd, dim3(256), 0, st, n, m, w.nblk, w.R, w.R, w.B, w.B, w.part);
         hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, st, m, w.nblk, w.part, w.norms);
         e = hipMemcpyAsync(norms.data(), w.norms, 2 * m * sizeof(double), hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -345,7 +444,7 @@ h2x_status run_refine(const DevMat &hi, const DevMat &lo, const h2x_cg_params &i
         // A_lo D = R by block CG, then X += D
         hipLaunchKernelGGL(k_zero, dim3(g1), dim3(256), 0, st, nm, w.D);
         h2x_cg_info ii{};
-        h2x_status s = run_block_cg(lo, inner, m, w.R, m, w.D, m, w.cg, cg_layout(lo, m, nullptr).bytes, &ii, st);
+        h2x_status s = run_block_cg(lo, inner, m, w.R, m, w.D, m, w.cg, cg_ws_bytes(lo, m), &ii, st);
         if (s != H2X_OK) return s;
         inner_total += ii.iters;
         hipLaunchKernelGGL(k_axpy_ld, dim3(g1), dim3(256), 0, st, n, m, w.D, X, ldx);
@@ -355,6 +454,7 @@ h2x_status run_refine(const DevMat &hi, const DevMat &lo, const h2x_cg_params &i
         info->iters = inner_total;
         info->outer_iters = outer;
         info->status = status;
+        if (info->sys_iters) info->sys_iters[0] = inner_total;
         for (int64_t j = 0; j < m; ++j) {
             const double rn = std::sqrt(norms[j]), bn = std::sqrt(norms[m + j]);
             const double rel = bn > 0 ? rn / bn : rn;
@@ -366,66 +466,151 @@ h2x_status run_refine(const DevMat &hi, const DevMat &lo, const h2x_cg_params &i
     return H2X_OK;
 }
 
-h2x_status run_block_cg(const DevMat &dm, const h2x_cg_params &prm, int64_t m, const double *B, int64_t ldb,
-                        double *X, int64_t ldx, char *ws, size_t ws_bytes, h2x_cg_info *info, hipStream_t st) {
-    CgWs w = cg_layout(dm, m, ws);
+h2x_status run_block_cg_batch(const DevMat *const *mats, int32_t nmat, const h2x_cg_params &prm, int64_t m,
+                              const double *B, int64_t ldb, double *X, int64_t ldx, char *ws, size_t ws_bytes,
+                              h2x_cg_info *info, hipStream_t st) {
+    const Layout L = make_layout(mats, nmat, m);
+    CgWs w = cg_layout(L, m, ws);
     if (ws_bytes < w.bytes) {
         set_error("h2x_block_cg: workspace too small");
         return H2X_ENOMEM;
     }
-    const int64_t n = dm.n, nm = n * m;
+    const int64_t n = L.n, nm = n * m;
     const unsigned g1 = (unsigned)((nm + 255) / 256);
-    const dim3 gd(w.nblk, (unsigned)((m + kDotCols - 1) / kDotCols));
+    const int nblk = L.nblk;
+    const dim3 gd(nblk, (unsigned)((m + kDotCols - 1) / kDotCols));
+    const Segs sg{w.blk_r0, w.blk_seg, w.seg_blk, w.seg_done, w.seg_iters, L.nseg};
+    hipStream_t cs = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t ev = nullptr;
+    auto cleanup = [&]() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (ev) (void)hipEventDestroy(ev);
+        if (cs) (void)hipStreamDestroy(cs);
+        exec = nullptr;
+        graph = nullptr;
+        ev = nullptr;
+        cs = nullptr;
+    };
     auto fail = [&](hipError_t e) {
+        cleanup();
         set_error(std::string("h2x_block_cg: ") + hipGetErrorString(e));
         return H2X_EHIP;
     };
+    hipError_t e = hipMemcpyAsync(w.blk_r0, L.blk_r0.data(), L.blk_r0.size() * sizeof(int64_t),
+                                  hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(w.blk_seg, L.blk_seg.data(), L.blk_seg.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                           st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(w.seg_blk, L.seg_blk.data(), L.seg_blk.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                           st);
+    if (e != hipSuccess) return fail(e);
 
-    hipLaunchKernelGGL(k_gather_rows, dim3(g1), dim3(256), 0, st, n, m, dm.perm, B, ldb, w.Bt, m);
-    hipLaunchKernelGGL(k_gather_rows, dim3(g1), dim3(256), 0, st, n, m, dm.perm, (const double *)X, ldx, w.Xt, m);
+    // the product of one iteration, operator by operator on its own rows
+    auto product = [&](const double *Pv, double *APv, double alpha, double beta, hipStream_t s) {
+        for (int32_t q = 0; q < nmat; ++q) {
+            const int64_t r = L.row0[q] * m;
+            hipError_t ee = run_matmul(*mats[q], m, alpha, Pv + r, m, beta, APv + r, m, true, w.mm, s);
+            if (ee != hipSuccess) return ee;
+        }
+        return hipSuccess;
+    };
+    auto iteration = [&](hipStream_t s) {
+        hipError_t ee = product(w.P, w.AP, 1.0, 0.0, s);
+        if (ee != hipSuccess) return ee;
+        hipLaunchKernelGGL(k_sdots, gd, dim3(256), 0, s, m, nblk, sg, w.P, w.AP, w.P, w.R, w.part,
+                           (const CgState *)w.state);
+        hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(256), 0, s, m, nblk, w.part, prm.freeze_converged, w.state,
+                           w.cols, sg);
+        hipLaunchKernelGGL(k_cg_update_xr, gd, dim3(256), 0, s, m, nblk, sg, w.Xt, w.R, w.P, w.AP, w.part,
+                           (const CgState *)w.state, w.cols);
+        hipLaunchKernelGGL(k_cg_gamma, dim3(1), dim3(256), 0, s, m, nblk, w.part, prm.rtol, w.state, w.cols, sg);
+        hipLaunchKernelGGL(k_cg_update_p, gd, dim3(256), 0, s, m, sg, w.R, w.P, (const CgState *)w.state, w.cols);
+        return hipGetLastError();
+    };
+
+    for (int32_t q = 0; q < nmat; ++q) {
+        const DevMat &dm = *mats[q];
+        const int64_t r = L.row0[q];
+        const unsigned gq = (unsigned)((dm.n * m + 255) / 256);
+        hipLaunchKernelGGL(k_gather_rows, dim3(gq), dim3(256), 0, st, dm.n, m, dm.perm, B + r * ldb, ldb,
+                           w.Bt + r * m, m);
+        hipLaunchKernelGGL(k_gather_rows, dim3(gq), dim3(256), 0, st, dm.n, m, dm.perm, (const double *)X + r * ldx,
+                           ldx, w.Xt + r * m, m);
+    }
     // R = B - A X0, P = R
     hipLaunchKernelGGL(k_copy, dim3(g1), dim3(256), 0, st, nm, w.Bt, w.R);
-    hipError_t e = run_matmul(dm, m, -1.0, w.Xt, m, 1.0, w.R, m, true, w.mm, st);
+    e = product(w.Xt, w.R, -1.0, 1.0, st);
     if (e != hipSuccess) return fail(e);
     hipLaunchKernelGGL(k_copy, dim3(g1), dim3(256), 0, st, nm, w.R, w.P);
-    hipLaunchKernelGGL(k_dots, gd, dim3(256), 0, st, n, m, w.nblk, w.Bt, w.Bt, w.R, w.R, w.part,
+    hipLaunchKernelGGL(k_sdots, gd, dim3(256), 0, st, m, nblk, sg, w.Bt, w.Bt, w.R, w.R, w.part,
                        (const CgState *)nullptr);
-    hipLaunchKernelGGL(k_cg_init, dim3(1), dim3(256), 0, st, m, w.nblk, w.part, prm.rtol, w.state, w.cols);
+    hipLaunchKernelGGL(k_cg_init, dim3(1), dim3(256), 0, st, m, nblk, w.part, prm.rtol, w.state, w.cols, sg);
 
     const int check = prm.check_every > 0 ? prm.check_every : 1;
-    CgState hs{};
-    for (int32_t it = 0;; ++it) {
-        if (it % check == 0 || it >= prm.max_iter) {
-            e = hipMemcpyAsync(&hs, w.state, sizeof(CgState), hipMemcpyDeviceToHost, st);
-            if (e == hipSuccess) e = hipStreamSynchronize(st);
-            if (e != hipSuccess) return fail(e);
-            if (hs.all_conv || it >= prm.max_iter) break;
-        }
-        e = run_matmul(dm, m, 1.0, w.P, m, 0.0, w.AP, m, true, w.mm, st);
+    hipStream_t run = st;
+    if (prm.graph) {
+        // check_every iterations captured once into one graph on a private stream
+        // (the caller's stream may be the null stream, which cannot be captured)
+        e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventRecord(ev, st);
+        if (e == hipSuccess) e = hipStreamWaitEvent(cs, ev, 0);
+        if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return fail(e);
-        hipLaunchKernelGGL(k_dots, gd, dim3(256), 0, st, n, m, w.nblk, w.P, w.AP, w.P, w.R, w.part,
-                           (const CgState *)nullptr);
-        hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(256), 0, st, m, w.nblk, w.part, prm.freeze_converged, w.state,
-                           w.cols);
-        hipLaunchKernelGGL(k_cg_update_xr, gd, dim3(256), 0, st, n, m, w.nblk, w.Xt, w.R, w.P, w.AP, w.part,
-                           (const CgState *)w.state, w.cols);
-        hipLaunchKernelGGL(k_cg_gamma, dim3(1), dim3(256), 0, st, m, w.nblk, w.part, prm.rtol, w.state, w.cols);
-        hipLaunchKernelGGL(k_cg_update_p, dim3(g1), dim3(256), 0, st, n, m, w.R, w.P, (const CgState *)w.state,
-                           w.cols);
+        for (int c = 0; c < check && e == hipSuccess; ++c) e = iteration(cs);
+        hipError_t e2 = hipStreamEndCapture(cs, &graph);
+        if (e == hipSuccess) e = e2;
+        if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) return fail(e);
+        run = cs;
     }
-    hipLaunchKernelGGL(k_scatter_rows, dim3(g1), dim3(256), 0, st, n, m, dm.perm, w.Xt, m, X, ldx);
-    std::vector<double> rr(m), bn(m);
-    std::vector<int32_t> fc(m), stt(m), fr(m), cv(m);
+    CgState hs{};
+    for (int32_t it = 0;;) {
+        e = hipMemcpyAsync(&hs, w.state, sizeof(CgState), hipMemcpyDeviceToHost, run);
+        if (e == hipSuccess) e = hipStreamSynchronize(run);
+        if (e != hipSuccess) return fail(e);
+        if (hs.all_conv || it >= prm.max_iter) break;
+        if (exec && it + check <= prm.max_iter) {
+            e = hipGraphLaunch(exec, run);
+            it += check;
+        } else {
+            const int steps = (int)std::min<int64_t>(check, prm.max_iter - it);
+            for (int c = 0; c < steps && e == hipSuccess; ++c) e = iteration(run);
+            it += steps;
+        }
+        if (e != hipSuccess) return fail(e);
+    }
+    if (run != st) {
+        e = hipStreamSynchronize(run);
+        if (e != hipSuccess) return fail(e);
+    }
+    for (int32_t q = 0; q < nmat; ++q) {
+        const DevMat &dm = *mats[q];
+        const int64_t r = L.row0[q];
+        const unsigned gq = (unsigned)((dm.n * m + 255) / 256);
+        hipLaunchKernelGGL(k_scatter_rows, dim3(gq), dim3(256), 0, st, dm.n, m, dm.perm, w.Xt + r * m, m,
+                           X + r * ldx, ldx);
+    }
+    const size_t sm = (size_t)L.nseg * m;
+    std::vector<double> rr(sm), bn(sm);
+    std::vector<int32_t> fc(sm), stt(sm), cv(sm), si(L.nseg), sd(L.nseg);
     e = hipMemcpyAsync(&hs, w.state, sizeof(CgState), hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(rr.data(), w.cols.rr, m * sizeof(double), hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(bn.data(), w.cols.bnorm, m * sizeof(double), hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(fc.data(), w.cols.first_conv, m * 4, hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(stt.data(), w.cols.status, m * 4, hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(cv.data(), w.cols.conv, m * 4, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(rr.data(), w.cols.rr, sm * sizeof(double), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(bn.data(), w.cols.bnorm, sm * sizeof(double), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(fc.data(), w.cols.first_conv, sm * 4, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(stt.data(), w.cols.status, sm * 4, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(cv.data(), w.cols.conv, sm * 4, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(si.data(), w.seg_iters, L.nseg * 4, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(sd.data(), w.seg_done, L.nseg * 4, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return fail(e);
+    cleanup();
     int32_t status = H2X_OK;
-    for (int64_t j = 0; j < m; ++j) {
+    for (size_t j = 0; j < sm; ++j) {
         if (stt[j] == 0 && !cv[j]) stt[j] = 2;
         if (stt[j] == 1) status = H2X_EBREAKDOWN;
         else if (stt[j] == 2 && status == H2X_OK) status = H2X_ENOCONV;
@@ -434,13 +619,22 @@ h2x_status run_block_cg(const DevMat &dm, const h2x_cg_params &prm, int64_t m, c
         info->iters = hs.iter;
         info->status = status;
         info->outer_iters = 0;
-        for (int64_t j = 0; j < m; ++j) {
+        for (size_t j = 0; j < sm; ++j) {
+            const int32_t cap = sd[j / m] ? si[j / m] : hs.iter;
             if (info->col_relres) info->col_relres[j] = bn[j] > 0 ? std::sqrt(rr[j]) / bn[j] : std::sqrt(rr[j]);
-            if (info->col_iters) info->col_iters[j] = fc[j] >= 0 ? fc[j] : hs.iter;
+            if (info->col_iters) info->col_iters[j] = fc[j] >= 0 ? fc[j] : cap;
             if (info->col_status) info->col_status[j] = stt[j];
         }
+        if (info->sys_iters)
+            for (int32_t s = 0; s < L.nseg; ++s) info->sys_iters[s] = sd[s] ? si[s] : hs.iter;
     }
     return H2X_OK;
+}
+
+h2x_status run_block_cg(const DevMat &dm, const h2x_cg_params &prm, int64_t m, const double *B, int64_t ldb,
+                        double *X, int64_t ldx, char *ws, size_t ws_bytes, h2x_cg_info *info, hipStream_t st) {
+    const DevMat *p = &dm;
+    return run_block_cg_batch(&p, 1, prm, m, B, ldb, X, ldx, ws, ws_bytes, info, st);
 }
 
 }  // namespace h2x

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <vector>
 
 #include "plan.hpp"
 
@@ -70,6 +71,10 @@ hipError_t run_matmul(const DevMat &dm, int64_t m, double alpha, const double *X
                       hipEvent_t *ev = nullptr);
 
 size_t cg_ws_bytes(const DevMat &dm, int64_t m);
+size_t cg_batch_ws_bytes(const DevMat *const *mats, int32_t nmat, int64_t m);
+h2x_status run_block_cg_batch(const DevMat *const *mats, int32_t nmat, const h2x_cg_params &prm, int64_t m,
+                              const double *B, int64_t ldb, double *X, int64_t ldx, char *ws, size_t ws_bytes,
+                              h2x_cg_info *info, hipStream_t st);
 h2x_status run_block_cg(const DevMat &dm, const h2x_cg_params &prm, int64_t m, const double *B, int64_t ldb,
                         double *X, int64_t ldx, char *ws, size_t ws_bytes, h2x_cg_info *info, hipStream_t st);
 
@@ -110,4 +115,9 @@ struct h2x_mat {
     const h2x_plan *plan;
     h2x::DevMat dm;
     size_t ws_bytes;
+};
+
+struct h2x_batch {
+    std::vector<const h2x_mat *> mats;
+    std::vector<const h2x::DevMat *> dms;
 };

@@ -155,6 +155,28 @@ __global__ void k_fill_N(int kernel, double ell, double shift, const int32_t *__
         for (int64_t jl = threadIdx.x; jl < ns; jl += blockDim.x) Nb[jl * nt2 + nt] = (TN)0;
 }
 
+// coupling matrices and near field, system by system (each with its own kernel
+// parameters; a one-system operator uses the operator's current ones)
+template <typename T, typename TN>
+hipError_t fill_SN(const DevMat &dm, hipStream_t st) {
+    const Plan &P = *dm.plan;
+    const int32_t ns = P.nsys();
+    for (int32_t i = 0; i < ns; ++i) {
+        const int kernel = ns == 1 ? dm.kernel : (int)P.sys_prm[i].kernel;
+        const double ell = ns == 1 ? dm.ell : P.sys_prm[i].ell, shift = ns == 1 ? dm.shift : P.sys_prm[i].shift;
+        const int64_t a = P.sys_adm[i], na = P.sys_adm[i + 1] - a;
+        const int64_t q = P.sys_near[i], nq = P.sys_near[i + 1] - q;
+        if (na > 0)
+            hipLaunchKernelGGL(k_fill_S<T>, dim3((unsigned)na), dim3(256), 0, st, dm.k, kernel, ell, dm.adm_row + a,
+                               dm.adm_col + a, dm.nodes, (T *)dm.S + a * dm.k * dm.k, s_swizzled(dm));
+        if (nq > 0)
+            hipLaunchKernelGGL(k_fill_N<TN>, dim3((unsigned)nq), dim3(256), 0, st, kernel, ell, shift,
+                               dm.near_row + q, dm.near_col + q, dm.near_off + q, dm.first, dm.size, dm.pts,
+                               (TN *)dm.N, dm.near_t);
+    }
+    return hipGetLastError();
+}
+
 template <typename T, typename TN>
 hipError_t fill_typed(const DevMat &dm, hipStream_t st) {
     const int64_t ck = (int64_t)dm.C * dm.k;
@@ -164,26 +186,12 @@ hipError_t fill_typed(const DevMat &dm, hipStream_t st) {
                            dm.nodes, (T *)dm.V, (T *)dm.Vt, dm.vt_off);
     if (dm.C > 1)
         hipLaunchKernelGGL(k_fill_E<T>, dim3(dm.C - 1), dim3(256), 0, st, dm.p, dm.parent, dm.nodes, (T *)dm.E);
-    if (dm.n_adm > 0)
-        hipLaunchKernelGGL(k_fill_S<T>, dim3((unsigned)dm.n_adm), dim3(256), 0, st, dm.k, dm.kernel, dm.ell,
-                           dm.adm_row, dm.adm_col, dm.nodes, (T *)dm.S, s_swizzled(dm));
-    if (dm.n_near > 0)
-        hipLaunchKernelGGL(k_fill_N<TN>, dim3((unsigned)dm.n_near), dim3(256), 0, st, dm.kernel, dm.ell, dm.shift,
-                           dm.near_row, dm.near_col, dm.near_off, dm.first, dm.size, dm.pts, (TN *)dm.N,
-                           dm.near_t);
-    return hipGetLastError();
+    return fill_SN<T, TN>(dm, st);
 }
 
 template <typename T, typename TN>
 hipError_t refill_typed(const DevMat &dm, hipStream_t st) {
-    if (dm.n_adm > 0)
-        hipLaunchKernelGGL(k_fill_S<T>, dim3((unsigned)dm.n_adm), dim3(256), 0, st, dm.k, dm.kernel, dm.ell,
-                           dm.adm_row, dm.adm_col, dm.nodes, (T *)dm.S, s_swizzled(dm));
-    if (dm.n_near > 0)
-        hipLaunchKernelGGL(k_fill_N<TN>, dim3((unsigned)dm.n_near), dim3(256), 0, st, dm.kernel, dm.ell, dm.shift,
-                           dm.near_row, dm.near_col, dm.near_off, dm.first, dm.size, dm.pts, (TN *)dm.N,
-                           dm.near_t);
-    return hipGetLastError();
+    return fill_SN<T, TN>(dm, st);
 }
 
 }  // namespace

@@ -62,9 +62,22 @@ struct Plan {
     // launch order of the row clusters in the coupling stage: the rows are cut
     // into 8 contiguous eighths (one per XCD), longest list first within each
     std::vector<int32_t> cpl_order; // C
+
+    // independent systems (a merged plan is the block-diagonal union of several
+    // cluster trees; a plan from build_plan holds one system).  System i owns
+    // tree positions / original rows [sys_row[i], sys_row[i+1]), clusters
+    // [sys_C[i], sys_C[i+1]), admissible blocks [sys_adm[i], sys_adm[i+1]) and
+    // near-field blocks [sys_near[i], sys_near[i+1]); its kernel parameters are sys_prm[i].
+    std::vector<h2x_params> sys_prm;
+    std::vector<int64_t> sys_row, sys_C, sys_adm, sys_near;
+    int32_t nsys() const { return (int32_t)sys_prm.size(); }
 };
 
 Plan *build_plan(const double *pts, int64_t n, const h2x_params &prm, std::string &err);
+// Block-diagonal union of plans with one Chebyshev order (any sizes, kernels,
+// length scales, shifts, leaf sizes and eta): the systems keep their own trees,
+// blocks and lists; every per-level array holds the clusters of all systems.
+Plan *merge_plans(const std::vector<const Plan *> &parts, std::string &err);
 
 void set_error(const std::string &msg);
 

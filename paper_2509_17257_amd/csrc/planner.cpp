@@ -37,6 +37,21 @@ double box_dist(const double *lo_t, const double *hi_t, const double *lo_s, cons
     return std::sqrt(s);
 }
 
+// launch order of the coupling rows: 8 contiguous eighths (one per XCD), longest
+// list first within each
+void coupling_order(Plan &P) {
+    const int32_t C = P.C;
+    const int32_t rpx = (C + 7) / 8;
+    P.cpl_order.resize(C);
+    for (int32_t c = 0; c < C; ++c) P.cpl_order[c] = c;
+    for (int32_t x = 0; x < 8; ++x) {
+        const int32_t lo = std::min(C, x * rpx), hi = std::min(C, (x + 1) * rpx);
+        std::stable_sort(P.cpl_order.begin() + lo, P.cpl_order.begin() + hi, [&](int32_t a, int32_t b) {
+            return P.adm_ptr[a + 1] - P.adm_ptr[a] > P.adm_ptr[b + 1] - P.adm_ptr[b];
+        });
+    }
+}
+
 }  // namespace
 
 Plan *build_plan(const double *pts, int64_t n, const h2x_params &prm, std::string &err) {
@@ -239,16 +254,123 @@ Plan *build_plan(const double *pts, int64_t n, const h2x_params &prm, std::strin
     P->near_entries_t = off;
     P->vt_entries = voff;
 
-    const int32_t rpx = (C + 7) / 8;
-    P->cpl_order.resize(C);
-    for (int32_t c = 0; c < C; ++c) P->cpl_order[c] = c;
-    for (int32_t x = 0; x < 8; ++x) {
-        const int32_t lo = std::min(C, x * rpx), hi = std::min(C, (x + 1) * rpx);
-        std::stable_sort(P->cpl_order.begin() + lo, P->cpl_order.begin() + hi, [&](int32_t a, int32_t b) {
-            return P->adm_ptr[a + 1] - P->adm_ptr[a] > P->adm_ptr[b + 1] - P->adm_ptr[b];
-        });
-    }
+    coupling_order(*P);
+    P->sys_prm.assign(1, prm);
+    P->sys_row = {0, n};
+    P->sys_C = {0, (int64_t)C};
+    P->sys_adm = {0, (int64_t)P->adm_col.size()};
+    P->sys_near = {0, (int64_t)P->near_col.size()};
     (void)err;
+    return P;
+}
+
+Plan *merge_plans(const std::vector<const Plan *> &parts, std::string &err) {
+    if (parts.empty()) {
+        err = "no plans to merge";
+        return nullptr;
+    }
+    for (const Plan *q : parts)
+        if (q->p != parts[0]->p) {
+            err = "all merged plans must have the same Chebyshev order";
+            return nullptr;
+        }
+    auto *P = new Plan();
+    P->prm = parts[0]->prm;
+    P->p = parts[0]->p;
+    P->k = parts[0]->k;
+    P->depth_max = 0;
+    P->adm_depth = 1 << 30;
+    for (const Plan *q : parts) {
+        P->depth_max = std::max(P->depth_max, q->depth_max);
+        P->adm_depth = std::min(P->adm_depth, q->adm_depth);
+        P->max_leaf = std::max(P->max_leaf, q->max_leaf);
+    }
+    P->sys_row.push_back(0);
+    P->sys_C.push_back(0);
+    P->sys_adm.push_back(0);
+    P->sys_near.push_back(0);
+    P->adm_ptr.push_back(0);
+    P->near_ptr.push_back(0);
+    P->adm_cptr.push_back(0);
+    P->near_cptr.push_back(0);
+    int64_t n0 = 0, c0 = 0, l0 = 0, a0 = 0, q0 = 0, e0 = 0, et0 = 0, v0 = 0;
+    for (const Plan *q : parts) {
+        const int32_t cs = (int32_t)c0;
+        auto sh = [cs](int32_t c) { return c < 0 ? c : c + cs; };
+        for (int64_t i = 0; i < q->n; ++i) P->perm.push_back(n0 + q->perm[i]);
+        P->pts_tree.insert(P->pts_tree.end(), q->pts_tree.begin(), q->pts_tree.end());
+        for (int32_t c = 0; c < q->C; ++c) {
+            P->first.push_back((int32_t)(q->first[c] + n0));
+            P->size.push_back(q->size[c]);
+            P->parent.push_back(sh(q->parent[c]));
+            P->son0.push_back(sh(q->son0[c]));
+            P->son1.push_back(sh(q->son1[c]));
+            P->depth.push_back(q->depth[c]);
+            P->leaf_index.push_back(q->leaf_index[c] < 0 ? -1 : (int32_t)(q->leaf_index[c] + l0));
+        }
+        P->box.insert(P->box.end(), q->box.begin(), q->box.end());
+        for (int32_t t : q->leaves) P->leaves.push_back(t + cs);
+        for (int32_t c = 0; c < q->C; ++c) P->adm_ptr.push_back(q->adm_ptr[c + 1] + a0);
+        for (int32_t s : q->adm_col) P->adm_col.push_back(s + cs);
+        for (int32_t c = 0; c < q->C; ++c) P->adm_cptr.push_back(q->adm_cptr[c + 1] + a0);
+        for (int64_t b : q->adm_cblk) P->adm_cblk.push_back(b + a0);
+        const int32_t L = (int32_t)q->leaves.size();
+        for (int32_t l = 0; l < L; ++l) {
+            P->near_ptr.push_back(q->near_ptr[l + 1] + q0);
+            P->near_cptr.push_back(q->near_cptr[l + 1] + q0);
+            P->vt_off.push_back(q->vt_off[l] + v0);
+        }
+        for (size_t b = 0; b < q->near_col.size(); ++b) {
+            P->near_col.push_back(q->near_col[b] + cs);
+            P->near_off.push_back(q->near_off[b] + e0);
+            P->near_off_t.push_back(q->near_off_t[b] + et0);
+            P->near_cblk.push_back(q->near_cblk[b] + q0);
+        }
+        for (size_t i = 0; i < q->sys_prm.size(); ++i) {
+            P->sys_prm.push_back(q->sys_prm[i]);
+            P->sys_row.push_back(q->sys_row[i + 1] + n0);
+            P->sys_C.push_back(q->sys_C[i + 1] + c0);
+            P->sys_adm.push_back(q->sys_adm[i + 1] + a0);
+            P->sys_near.push_back(q->sys_near[i + 1] + q0);
+        }
+        n0 += q->n;
+        c0 += q->C;
+        l0 += L;
+        a0 += (int64_t)q->adm_col.size();
+        q0 += (int64_t)q->near_col.size();
+        e0 += q->near_entries;
+        et0 += q->near_entries_t;
+        v0 += q->vt_entries;
+    }
+    if (c0 >= (int64_t)1 << 31 || n0 >= (int64_t)1 << 31) {
+        err = "merged plan too large";
+        delete P;
+        return nullptr;
+    }
+    P->n = n0;
+    P->C = (int32_t)c0;
+    P->near_entries = e0;
+    P->near_entries_t = et0;
+    P->vt_entries = v0;
+    // per-level lists: level d of every system, systems in order
+    const int32_t D = P->depth_max + 1;
+    P->lvl_ptr.assign(D + 1, 0);
+    P->lvl_inner_ptr.assign(D + 1, 0);
+    for (int d = 0; d < D; ++d) {
+        int64_t cc = 0;
+        for (const Plan *q : parts) {
+            if (d <= q->depth_max) {
+                for (int32_t i = q->lvl_ptr[d]; i < q->lvl_ptr[d + 1]; ++i)
+                    P->lvl_all.push_back(q->lvl_all[i] + (int32_t)cc);
+                for (int32_t i = q->lvl_inner_ptr[d]; i < q->lvl_inner_ptr[d + 1]; ++i)
+                    P->lvl_inner.push_back(q->lvl_inner[i] + (int32_t)cc);
+            }
+            cc += q->C;
+        }
+        P->lvl_ptr[d + 1] = (int32_t)P->lvl_all.size();
+        P->lvl_inner_ptr[d + 1] = (int32_t)P->lvl_inner.size();
+    }
+    coupling_order(*P);
     return P;
 }
 

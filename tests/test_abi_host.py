@@ -82,3 +82,40 @@ def test_invalid_arguments_rejected():
     # workspace queries on NULL handles return 0 instead of crashing
     assert lib.h2x_mat_workspace_bytes(None, 0) == 0
     assert lib.h2x_matmul_workspace_bytes(None, 4) == 0
+
+
+def test_merged_plan_is_the_concatenation_of_its_systems():
+    specs = [(W.sphere_points(900, 401), dict(leaf=32, p=3, ell=0.5)),
+             (W.cube_points(1500, 402), dict(leaf=16, p=3, ell=0.3, eta=1.5, shift=0.5)),
+             (W.line_points(300, 403), dict(leaf=8, p=3, ell=0.2)),
+             (W.sphere_points(2000, 404), dict(leaf=64, p=3, ell=0.9))]
+    parts = [h2x.Plan(P, **kw) for P, kw in specs]
+    mp = h2x.Plan.merge(parts)
+    assert mp.n == sum(p.n for p in parts) and mp.C == sum(p.C for p in parts)
+    assert (mp.n_adm, mp.n_near, mp.near_entries) == (sum(p.n_adm for p in parts), sum(p.n_near for p in parts),
+                                                       sum(p.near_entries for p in parts))
+    assert mp.depth == max(p.depth for p in parts)
+    np.testing.assert_array_equal(mp.systems(), np.r_[0, np.cumsum([p.n for p in parts])])
+    n0 = c0 = 0
+    cl, pb, perm = mp.clusters(), mp.blocks(), mp.perm()
+    a0 = q0 = 0
+    for p in parts:
+        c = p.clusters()
+        sl = slice(c0, c0 + p.C)
+        np.testing.assert_array_equal(cl["first"][sl], c["first"] + n0)
+        np.testing.assert_array_equal(cl["size"][sl], c["size"])
+        np.testing.assert_array_equal(cl["depth"][sl], c["depth"])
+        for nm in ("parent", "son0", "son1"):
+            np.testing.assert_array_equal(cl[nm][sl], np.where(c[nm] < 0, -1, c[nm] + c0), err_msg=nm)
+        np.testing.assert_array_equal(perm[n0:n0 + p.n], p.perm() + n0)
+        b = p.blocks()
+        np.testing.assert_array_equal(pb["adm_t"][a0:a0 + p.n_adm], b["adm_t"] + c0)
+        np.testing.assert_array_equal(pb["adm_s"][a0:a0 + p.n_adm], b["adm_s"] + c0)
+        np.testing.assert_array_equal(pb["near_t"][q0:q0 + p.n_near], b["near_t"] + c0)
+        np.testing.assert_array_equal(pb["near_s"][q0:q0 + p.n_near], b["near_s"] + c0)
+        n0 += p.n
+        c0 += p.C
+        a0 += p.n_adm
+        q0 += p.n_near
+    with pytest.raises(h2x.H2xError):
+        h2x.Plan.merge([parts[0], h2x.Plan(W.sphere_points(500, 405), leaf=32, p=4)])

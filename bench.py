@@ -222,6 +222,100 @@ def grad_report(args, torch, h2x, W):
     print(json.dumps(out), flush=True)
 
 
+def batch_report(args, torch, h2x, W):
+    """Batching workload: 64 independent systems (n log-uniform in [2048, 32768] on spheres,
+    ell ~ U[0.2, 1], shift 1, k = 27 or 64, m = 1..32).  Batched product (one merged
+    operator per Chebyshev order) against a loop of per-system products; batched block CG
+    to 1e-8 with and without the HIP-graph step against a loop of per-system solves; the
+    batched product with FP32 storage."""
+    systems = W.batch_systems()
+    dev = torch.device("cuda:0")
+    pts = [s.points() for s in systems]
+    prms = [dict(ell=s.ell, shift=s.shift, eta=1.0, leaf=s.leaf, p=s.p) for s in systems]
+    t0 = time.perf_counter()
+    batch = h2x.Batch(list(zip(pts, prms)), device=dev)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    m = max(s.m for s in systems)
+    Bh = np.zeros((batch.n, m))
+    for i, s in enumerate(systems):
+        r0, r1 = batch.rows(i)
+        Bh[r0:r1, :s.m] = s.rhs()
+    B = torch.from_numpy(Bh).to(dev)
+    Y = torch.empty_like(B)
+    parts = {i: p for grp, ps in zip(batch.order, batch._parts) for i, p in zip(grp, ps)}
+    alg = sum(alg_bytes(parts[i], s.m) for i, s in enumerate(systems))
+    alg_pad = sum(alg_bytes(parts[i], m) for i in range(len(systems)))
+    out = {"workload": f"batch-{len(systems)}-spheres", "systems": len(systems), "n_total": batch.n,
+           "m_max": m, "setup_s": round(setup_s, 2),
+           "n_adm_total": int(sum(p.n_adm for p in batch.plans)),
+           "near_entries_total": int(sum(p.near_entries for p in batch.plans)),
+           "alg_bytes_per_product": int(alg), "alg_bytes_padded_m": int(alg_pad)}
+    log(f"[batch] {len(systems)} systems, n total {batch.n}, setup {setup_s:.1f} s")
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    reps = max(3, min(args.steps, 50))
+    ms = timed(lambda: h2x.batch_matmul(batch, B, out=Y), reps)
+    out["batched_product"] = {"ms": round(ms, 4), "alg_gbs": round(alg / (ms * 1e-3) / 1e9, 1),
+                              "products_per_s": round(1e3 / ms, 1)}
+    # the same products one system at a time (each with its own m)
+    mats = [h2x.H2Matrix(parts[i], device=dev) for i in range(len(systems))]
+    Xs = [B[batch.rows(i)[0]:batch.rows(i)[1], :s.m].contiguous() for i, s in enumerate(systems)]
+    Ys = [torch.empty_like(x) for x in Xs]
+
+    def loop():
+        for A, x, y in zip(mats, Xs, Ys):
+            h2x.h2_matmul(A, x, out=y)
+    ms_loop = timed(loop, max(3, reps // 4))
+    out["per_system_loop"] = {"ms": round(ms_loop, 4), "alg_gbs": round(alg / (ms_loop * 1e-3) / 1e9, 1)}
+    log(f"[batch] product: batched {ms:.3f} ms, per-system loop {ms_loop:.3f} ms")
+    for graph in (True, False):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        X, info = h2x.batch_block_cg_solve(batch, B, rtol=1e-8, max_iter=args.max_cg_iter, graph=graph)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[f"batched_cg_graph{int(graph)}"] = {"time_s": round(dt, 3), "iters": info.iters, "status": info.status,
+                                               "sys_iters_min": int(info.sys_iters.min()),
+                                               "sys_iters_max": int(info.sys_iters.max())}
+        log(f"[batch] batched CG graph={graph}: {dt:.3f} s, {info.iters} iterations")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tot = 0
+    for A, b in zip(mats, Xs):
+        _, info = h2x.block_cg_solve(A, b, rtol=1e-8, max_iter=args.max_cg_iter)
+        tot += info.iters
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    out["per_system_cg_loop"] = {"time_s": round(dt, 3), "iters_total": tot}
+    log(f"[batch] per-system CG loop: {dt:.3f} s")
+    del mats
+    b32 = h2x.Batch(list(zip(pts, prms)), storage="f32", device=dev)
+    Y32 = torch.empty_like(B)
+    ms32 = timed(lambda: h2x.batch_matmul(b32, B, out=Y32), reps)
+    h2x.batch_matmul(batch, B, out=Y)
+    err = 0.0
+    for i, s in enumerate(systems):
+        r0, r1 = batch.rows(i)
+        a, b = Y32[r0:r1, :s.m], Y[r0:r1, :s.m]
+        err = max(err, ((a - b).norm(dim=0) / b.norm(dim=0)).max().item())
+    alg32 = sum(alg_bytes(parts[i], s.m, s_b=4, s_n=4) for i, s in enumerate(systems))
+    out["batched_product_f32"] = {"ms": round(ms32, 4), "alg_gbs": round(alg32 / (ms32 * 1e-3) / 1e9, 1),
+                                  "max_col_rel_err_vs_f64": err}
+    log(f"[batch] {out}")
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -233,6 +327,8 @@ def main():
     ap.add_argument("--cpu-baseline-s", type=float, default=12.0, help="0 disables the oracle timing")
     ap.add_argument("--precision-report", action="store_true",
                     help="report FP64 / FP32 / BF16 products and FP64 vs refined block CG on the precision workload")
+    ap.add_argument("--batch-report", action="store_true",
+                    help="batched products and block CG over the 64-system batching workload")
     ap.add_argument("--grad-report", action="store_true",
                     help="time the adjoint product, gradients and implicit-adjoint solve on the differentiation workload")
     ap.add_argument("--copy-calibration-gib", type=float, default=0.0,
@@ -277,6 +373,9 @@ def main():
         return
     if args.grad_report:
         grad_report(args, torch, h2x, W)
+        return
+    if args.batch_report:
+        batch_report(args, torch, h2x, W)
         return
 
     w = W.WORKLOADS[args.workload]

@@ -21,6 +21,7 @@ struct DevMat {
     h2x_prec storage = H2X_F64;
     int swz = 0;     // coupling-matrix layout (see s_index)
     int near_t = 0;  // near-field blocks stored transposed (|s| x |t| row-major)
+    int mc = 0;      // every stage runs on the matrix cores (FP64, k = 64 or k <= 32)
     int kernel = 0;
     double ell = 0, shift = 0;
 

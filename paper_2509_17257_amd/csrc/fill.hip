@@ -214,7 +214,9 @@ size_t mat_layout(const Plan &P, h2x_prec storage, DevMat *dm, char *base) {
     d.n_adm = na; d.n_near = nn; d.near_entries = P.near_entries; d.storage = storage;
     d.kernel = P.prm.kernel; d.ell = P.prm.ell; d.shift = P.prm.shift; d.plan = &P;
     d.swz = (storage == H2X_F64 && k == 64) ? 1 : 0;
-    d.near_t = d.swz;
+    // matrix-core layout (transposed near field, transposed leaf bases): FP64, k = 64 or k <= 32
+    d.mc = (storage == H2X_F64 && (k == 64 || k <= 32)) ? 1 : 0;
+    d.near_t = d.mc;
     d.first = carve<int32_t>(cur, base, C);
     d.size = carve<int32_t>(cur, base, C);
     d.parent = carve<int32_t>(cur, base, C);

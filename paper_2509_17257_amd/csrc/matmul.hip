@@ -294,7 +294,7 @@ __global__ __launch_bounds__(256) void k_leaf_near(int k, int64_t m, const int32
 
 inline int64_t even_ld(int64_t m) { return m + (m & 1); }
 
-// All five stages on the matrix cores (FP64 operator, k = 64).
+// All five stages on the matrix cores (FP64 operator, k = 64 or k <= 32).
 template <int NJ>
 void matmul_mfma_f64(const DevMat &dm, int64_t m, double alpha, const double *X, int64_t ldx, double beta, double *Y,
                      int64_t ldy, int to, double *xh, double *yh, int64_t ldh, double *xt_ws, hipStream_t st,
@@ -314,14 +314,14 @@ void matmul_mfma_f64(const DevMat &dm, int64_t m, double alpha, const double *X,
                            to ? nullptr : dm.perm, X, ldx, xt_ws, ldxt);
         Xt = xt_ws;
     }
-    hipLaunchKernelGGL(mfma::k_fwd_leaf<NJ>, dim3(dm.L, gy), dim3(256), 0, st, m, dm.leaves, dm.first, dm.size,
-                       dm.perm, V, Xt, ldxt, 1, xh, ldh);
+    hipLaunchKernelGGL(mfma::k_fwd_leaf<NJ>, dim3(dm.L, gy), dim3(256), 0, st, dm.k, m, dm.leaves, dm.first,
+                       dm.size, dm.perm, V, Xt, ldxt, 1, xh, ldh);
     mark(1);
     for (int d = dm.depth_max - 1; d >= P.adm_depth; --d) {
         const int32_t b = P.lvl_inner_ptr[d], e = P.lvl_inner_ptr[d + 1];
         if (e > b)
-            hipLaunchKernelGGL(mfma::k_up<NJ>, dim3(e - b, gy), dim3(256), 0, st, m, dm.lvl_inner + b, dm.son0,
-                               dm.son1, E, xh, ldh);
+            hipLaunchKernelGGL(mfma::k_up<NJ>, dim3(e - b, gy), dim3(256), 0, st, dm.k, m, dm.lvl_inner + b,
+                               dm.son0, dm.son1, E, xh, ldh);
     }
     mark(2);
     launch_coupling_fast<double, double>(dm, m, xh, yh, ldh, st);
@@ -329,13 +329,14 @@ void matmul_mfma_f64(const DevMat &dm, int64_t m, double alpha, const double *X,
     for (int d = std::max(1, P.adm_depth + 1); d <= dm.depth_max; ++d) {
         const int32_t b = P.lvl_ptr[d], e = P.lvl_ptr[d + 1];
         if (e > b)
-            hipLaunchKernelGGL(mfma::k_down<NJ>, dim3(e - b, gy), dim3(256), 0, st, m, dm.lvl_all + b, dm.parent, E,
-                               yh, ldh);
+            hipLaunchKernelGGL(mfma::k_down<NJ>, dim3(e - b, gy), dim3(256), 0, st, dm.k, m, dm.lvl_all + b,
+                               dm.parent, E, yh, ldh);
     }
     mark(4);
     // Y = beta Y + alpha (V y-hat + N X)
     const unsigned gl = (unsigned)((m + 32 * NP - 1) / (32 * NP));
-    hipLaunchKernelGGL(mfma::k_leaf_direct<NP>, dim3(8 * ((dm.L + 7) / 8), gl), dim3(256), 0, st, m, dm.L, dm.leaves,
+    hipLaunchKernelGGL(mfma::k_leaf_direct<NP>, dim3(8 * ((dm.L + 7) / 8), gl), dim3(256), 0, st, dm.k, m, dm.L,
+                       dm.leaves,
                        dm.first, dm.size, dm.perm, (const double *)dm.Vt, dm.vt_off, yh, ldh, dm.near_ptr,
                        dm.near_col, dm.near_off, (const double *)dm.N, Xt, ldxt, alpha, beta, Y, ldy, to, 1, 1);
     mark(5);
@@ -354,7 +355,7 @@ hipError_t matmul_typed(const DevMat &dm, int64_t m, double alpha, const double 
         if (ev) (void)hipEventRecord(ev[i], st);
     };
     const Plan &P = *dm.plan;
-    const int64_t ldh = (dm.swz == 1) ? even_ld(m) : m;
+    const int64_t ldh = dm.mc ? even_ld(m) : m;
     Acc *xh = (Acc *)ws;
     Acc *yh = (Acc *)(ws + hat_bytes<Acc>(dm, m));
     const unsigned gy = (unsigned)((m + TC - 1) / TC);
@@ -362,7 +363,7 @@ hipError_t matmul_typed(const DevMat &dm, int64_t m, double alpha, const double 
     const T *V = (const T *)dm.V, *E = (const T *)dm.E, *S = (const T *)dm.S;
 
     if constexpr (std::is_same<T, double>::value && std::is_same<Acc, double>::value) {
-        if (dm.swz == 1 && dm.k == mfma::K) {
+        if (dm.mc) {
             const std::function<void(int)> mk = mark;
             double *xt = (double *)(ws + 2 * hat_bytes<Acc>(dm, m));
             switch ((int)std::min<int64_t>(4, (m + 15) / 16)) {
@@ -411,7 +412,7 @@ hipError_t run_forward_transform(const DevMat &dm, int64_t m, const double *X, i
                                  double *xh, int64_t ldh, double *xt_ws, hipStream_t st) {
     const Plan &P = *dm.plan;
     const double *V = (const double *)dm.V, *E = (const double *)dm.E;
-    if (dm.swz == 1 && dm.k == mfma::K) {
+    if (dm.mc) {
         const double *Xt = X;
         int64_t ldxt = ldx;
         if (!tree_order || (ldx & 1) || ((uintptr_t)X & 15)) {
@@ -425,12 +426,12 @@ hipError_t run_forward_transform(const DevMat &dm, int64_t m, const double *X, i
         const unsigned gy = (unsigned)((m + 16 * nj - 1) / (16 * nj));
         auto launch = [&](auto NJc) {
             constexpr int NJ = decltype(NJc)::value;
-            hipLaunchKernelGGL(mfma::k_fwd_leaf<NJ>, dim3(dm.L, gy), dim3(256), 0, st, m, dm.leaves, dm.first, dm.size,
-                               dm.perm, V, Xt, ldxt, 1, xh, ldh);
+            hipLaunchKernelGGL(mfma::k_fwd_leaf<NJ>, dim3(dm.L, gy), dim3(256), 0, st, dm.k, m, dm.leaves, dm.first,
+                               dm.size, dm.perm, V, Xt, ldxt, 1, xh, ldh);
             for (int d = dm.depth_max - 1; d >= P.adm_depth; --d) {
                 const int32_t b = P.lvl_inner_ptr[d], e = P.lvl_inner_ptr[d + 1];
                 if (e > b)
-                    hipLaunchKernelGGL(mfma::k_up<NJ>, dim3(e - b, gy), dim3(256), 0, st, m, dm.lvl_inner + b,
+                    hipLaunchKernelGGL(mfma::k_up<NJ>, dim3(e - b, gy), dim3(256), 0, st, dm.k, m, dm.lvl_inner + b,
                                        dm.son0, dm.son1, E, xh, ldh);
             }
         };

@@ -1,4 +1,5 @@
-// Matrix-core (MFMA) coupling kernel for the FP64 operator with k = 64:
+// Matrix-core (MFMA) coupling kernels for the FP64 operator (k = 64 below; a
+// small-rank variant for k <= 32 further down):
 //   y_t = sum_{(t,s) in C_t, admissible} S_b x_s     for every row cluster t.
 //
 // One work-group (4 waves) owns one row cluster t and a slab of up to 64
@@ -125,6 +126,122 @@ __global__ __launch_bounds__(256) void k_coupling_mfma_f64(int64_t m, int32_t C,
     }
 }
 
+// Coupling for small ranks (k <= 32, row-major k x k coupling matrices).  One
+// work-group of 2 waves owns one row cluster t and a slab of 16*NJ columns;
+// wave w owns rows 16w..16w+15 of y_t (rows past k are zero in the operand and
+// never written).  The k-steps of the 16x16x4 MFMA are permuted so that a lane
+// owns two neighbouring columns of S_b per pair of k-steps: lane (r, g), g =
+// lane / 16, takes columns 8q + 2g and 8q + 2g + 1 in k-steps 2q and 2q + 1, so
+// its two S values are adjacent in memory; x_s (staged in LDS, double-buffered)
+// is read with the same permutation.  S_b is streamed from HBM one block ahead.
+// Work-groups are mapped to rows by XCD eighths as in the k = 64 kernel.
+template <int NJ>
+__global__ __launch_bounds__(128) void k_coupling_mfma_small(int k, int64_t m, int32_t C, int32_t rows_per_xcd,
+                                                             const int32_t *__restrict__ order,
+                                                             const int64_t *__restrict__ adm_ptr,
+                                                             const int32_t *__restrict__ adm_col,
+                                                             const double *__restrict__ S,
+                                                             const double *__restrict__ xh, double *__restrict__ yh,
+                                                             int64_t ldh) {
+    constexpr int MC = 16 * NJ;
+    constexpr int LDX = MC + 1;
+    __shared__ double xs[2][32 * LDX];
+    const int slot = (blockIdx.x & 7) * rows_per_xcd + (blockIdx.x >> 3);
+    if (slot >= C) return;
+    const int32_t t = order[slot];
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    const int lr = lane & 15, g = lane >> 4;
+    const int64_t j0 = (int64_t)blockIdx.y * MC;
+    const int mc = (int)min<int64_t>(MC, m - j0);
+    const int64_t b0 = adm_ptr[t], b1 = adm_ptr[t + 1];
+    const int nq = (k + 7) >> 3;          // pairs of k-steps (8 columns of S each)
+    const int nu = 16 * w + lr;           // row of S_b held by this lane
+    const bool row_ok = nu < k;
+
+    dbl4 acc[NJ];
+#pragma unroll
+    for (int J = 0; J < NJ; ++J) acc[J] = dbl4{0.0, 0.0, 0.0, 0.0};
+
+    if (b1 > b0) {
+        constexpr int XPT = (32 * MC) / 128;  // x_s elements per thread (4 * NJ)
+        double xv[XPT];
+        auto load_x = [&](int32_t s) {
+            const double *src = xh + (int64_t)s * k * ldh + j0;
+#pragma unroll
+            for (int u = 0; u < XPT; ++u) {
+                const int e = tid + 128 * u, r = e / MC, c = e % MC;
+                xv[u] = (r < k && c < mc) ? src[(int64_t)r * ldh + c] : 0.0;
+            }
+        };
+        auto store_x = [&](int buf) {
+#pragma unroll
+            for (int u = 0; u < XPT; ++u) {
+                const int e = tid + 128 * u, r = e / MC, c = e % MC;
+                xs[buf][r * LDX + c] = xv[u];
+            }
+        };
+        double sa[4][2], sn[4][2];
+        auto load_s = [&](int64_t b, double (*dst)[2]) {
+            const double *src = S + b * k * k + (int64_t)nu * k;
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int mu = 8 * q + 2 * g + h;
+                    dst[q][h] = (row_ok && mu < k) ? __builtin_nontemporal_load(src + mu) : 0.0;
+                }
+        };
+
+        load_x(adm_col[b0]);
+        load_s(b0, sa);
+        store_x(0);
+        __syncthreads();
+        for (int64_t b = b0; b < b1; ++b) {
+            const int buf = (int)((b - b0) & 1);
+            const bool more = b + 1 < b1;
+            if (more) {
+                load_x(adm_col[b + 1]);
+                load_s(b + 1, sn);
+            }
+            const double *xb = xs[buf];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (q < nq) {
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const int krow = 8 * q + 2 * g + h;
+#pragma unroll
+                        for (int J = 0; J < NJ; ++J) {
+                            const double bv = xb[krow * LDX + 16 * J + lr];
+                            acc[J] = __builtin_amdgcn_mfma_f64_16x16x4f64(sa[q][h], bv, acc[J], 0, 0, 0);
+                        }
+                    }
+                }
+            }
+            if (more) {
+                store_x(buf ^ 1);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    sa[q][0] = sn[q][0];
+                    sa[q][1] = sn[q][1];
+                }
+            }
+            __syncthreads();
+        }
+    }
+#pragma unroll
+    for (int J = 0; J < NJ; ++J) {
+        const int col = 16 * J + lr;
+        if (col < mc) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = 16 * w + g + 4 * r;
+                if (row < k) yh[((int64_t)t * k + row) * ldh + j0 + col] = acc[J][r];
+            }
+        }
+    }
+}
+
 // Launches the matrix-core coupling stage when the operator's layout supports
 // it; returns false (launching nothing) otherwise.
 template <typename T, typename Acc>
@@ -132,12 +249,27 @@ bool launch_coupling_fast(const DevMat &dm, int64_t m, const Acc *xh, Acc *yh, i
     if constexpr (!std::is_same<T, double>::value || !std::is_same<Acc, double>::value) {
         return false;
     } else {
-        if (dm.swz != 1 || dm.k != kMfmaK || !dm.cpl_order) return false;
+        if (!dm.mc || !dm.cpl_order) return false;
         const int nj = (int)std::min<int64_t>(4, (m + 15) / 16);
         const int mcols = 16 * nj;
         const int32_t rpx = (dm.C + 7) / 8;
         const dim3 grid((unsigned)(8 * rpx), (unsigned)((m + mcols - 1) / mcols));
         const double *S = (const double *)dm.S;
+        if (dm.k <= 32) {
+            auto go = [&](auto NJc) {
+                constexpr int NJ = decltype(NJc)::value;
+                hipLaunchKernelGGL(k_coupling_mfma_small<NJ>, grid, dim3(128), 0, st, dm.k, m, dm.C, rpx,
+                                   dm.cpl_order, dm.adm_ptr, dm.adm_col, S, xh, yh, ldh);
+            };
+            switch (nj) {
+                case 1: go(std::integral_constant<int, 1>{}); break;
+                case 2: go(std::integral_constant<int, 2>{}); break;
+                case 3: go(std::integral_constant<int, 3>{}); break;
+                default: go(std::integral_constant<int, 4>{}); break;
+            }
+            return true;
+        }
+        if (dm.swz != 1 || dm.k != kMfmaK) return false;
         switch (nj) {
             case 1:
                 hipLaunchKernelGGL(k_coupling_mfma_f64<1>, grid, dim3(256), 0, st, m, dm.C, rpx, dm.cpl_order,

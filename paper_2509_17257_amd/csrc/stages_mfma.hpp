@@ -1,7 +1,8 @@
-// Matrix-core (MFMA) kernels for the FP64 operator with k = 64: forward leaf
-// transform, upward and downward transfer passes, and the leaf stage
+// Matrix-core (MFMA) kernels for the FP64 operator with rank k <= 64: forward
+// leaf transform, upward and downward transfer passes, and the leaf stage
 // (near field and leaf basis).  Each work-group (4 waves) computes one output
-// tile of 64 rows x 16*NJ columns; wave w owns rows 16w..16w+15.  Operands are
+// tile of 64 rows x 16*NJ columns; wave w owns rows 16w..16w+15 (waves whose
+// rows all lie beyond k skip the multiplications).  Operands are
 // staged through LDS with coalesced global loads (a near-field block is one
 // contiguous |t| x |s| array), then v_mfma_f64_16x16x4f64 accumulates in
 // registers.  Contraction lengths are padded to a multiple of 4 with zeros in
@@ -15,7 +16,7 @@ namespace mfma {
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
-constexpr int K = 64;     // rank handled by these kernels
+constexpr int K = 64;     // largest rank handled by these kernels
 constexpr int LDA = K + 1;  // padded LDS row of the left operand
 
 template <int NJ>
@@ -118,9 +119,10 @@ __device__ inline void clear(Smem<NJ> &sm) {
 }
 
 template <int NJ>
-__device__ inline void mma(const double *As, const double *Bs, int kpad, dbl4 *acc) {
+__device__ inline void mma(const double *As, const double *Bs, int kpad, int rows, dbl4 *acc) {
     constexpr int LDB = 16 * NJ + 1;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (16 * w >= rows) return;  // wave-uniform: no output row of this wave exists
     const int lr = lane & 15, lq = lane >> 4;
     const double *arow = As + (16 * w + lr) * LDA + lq;
     const double *bcol = Bs + lq * LDB + lr;
@@ -142,7 +144,7 @@ __device__ inline int dkpad4(int v) { return (v + 3) & ~3; }
 // acc += sum_{q < nq} A_q B_q; the next term's global loads are in flight while
 // the matrix cores work on the current one.  A term with no columns adds nothing.
 template <int NJ, typename F>
-__device__ inline void accumulate(Smem<NJ> &sm, dbl4 *acc, int nq, int mc, F term) {
+__device__ inline void accumulate(Smem<NJ> &sm, dbl4 *acc, int nq, int mc, int rows, F term) {
     if (nq <= 0) return;
     Regs<NJ> R;
     Term d = term(0);
@@ -155,7 +157,7 @@ __device__ inline void accumulate(Smem<NJ> &sm, dbl4 *acc, int nq, int mc, F ter
             d = term(q + 1);
             load_term<NJ>(d, mc, R);
         }
-        mma<NJ>(sm.a, sm.b, kp, acc);
+        mma<NJ>(sm.a, sm.b, kp, rows, acc);
         __syncthreads();
     }
 }
@@ -166,7 +168,7 @@ __device__ inline int out_col(int J) { return 16 * J + (threadIdx.x & 15); }
 
 // x_t = V_t^T X|_t for each leaf t
 template <int NJ>
-__global__ __launch_bounds__(256) void k_fwd_leaf(int64_t m, const int32_t *__restrict__ leaves,
+__global__ __launch_bounds__(256) void k_fwd_leaf(int k, int64_t m, const int32_t *__restrict__ leaves,
                                                   const int32_t *__restrict__ first, const int32_t *__restrict__ size,
                                                   const int64_t *__restrict__ perm, const double *__restrict__ V,
                                                   const double *__restrict__ X, int64_t ldx, int tree_order,
@@ -181,20 +183,21 @@ __global__ __launch_bounds__(256) void k_fwd_leaf(int64_t m, const int32_t *__re
     dbl4 acc[NJ];
     zero<NJ>(acc);
     const int64_t *pm = tree_order ? nullptr : perm;
-    accumulate<NJ>(sm, acc, (nt + 63) / 64, mc, [&](int q) {
+    accumulate<NJ>(sm, acc, (nt + 63) / 64, mc, k, [&](int q) {
         const int i0 = 64 * q;
-        return Term{V + (r0 + i0) * K, K, min(64, nt - i0), K, true, X + j0, ldx, pm, r0 + i0};
+        return Term{V + (r0 + i0) * k, k, min(64, nt - i0), k, true, X + j0, ldx, pm, r0 + i0};
     });
 #pragma unroll
     for (int J = 0; J < NJ; ++J)
         if (out_col(J) < mc)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) xh[((int64_t)t * K + out_row(r)) * ldh + j0 + out_col(J)] = acc[J][r];
+            for (int r = 0; r < 4; ++r)
+                if (out_row(r) < k) xh[((int64_t)t * k + out_row(r)) * ldh + j0 + out_col(J)] = acc[J][r];
 }
 
 // x_t = E_{t0}^T x_{t0} + E_{t1}^T x_{t1} for the inner clusters in `list`
 template <int NJ>
-__global__ __launch_bounds__(256) void k_up(int64_t m, const int32_t *__restrict__ list,
+__global__ __launch_bounds__(256) void k_up(int k, int64_t m, const int32_t *__restrict__ list,
                                             const int32_t *__restrict__ son0, const int32_t *__restrict__ son1,
                                             const double *__restrict__ E, double *__restrict__ xh, int64_t ldh) {
     __shared__ Smem<NJ> sm;
@@ -205,20 +208,21 @@ __global__ __launch_bounds__(256) void k_up(int64_t m, const int32_t *__restrict
     dbl4 acc[NJ];
     zero<NJ>(acc);
     const int32_t s0 = son0[t], s1 = son1[t];
-    accumulate<NJ>(sm, acc, 2, mc, [&](int q) {
+    accumulate<NJ>(sm, acc, 2, mc, k, [&](int q) {
         const int32_t s = q ? s1 : s0;
-        return Term{E + (int64_t)s * K * K, K, K, K, true, xh + j0, ldh, nullptr, (int64_t)s * K};
+        return Term{E + (int64_t)s * k * k, k, k, k, true, xh + j0, ldh, nullptr, (int64_t)s * k};
     });
 #pragma unroll
     for (int J = 0; J < NJ; ++J)
         if (out_col(J) < mc)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) xh[((int64_t)t * K + out_row(r)) * ldh + j0 + out_col(J)] = acc[J][r];
+            for (int r = 0; r < 4; ++r)
+                if (out_row(r) < k) xh[((int64_t)t * k + out_row(r)) * ldh + j0 + out_col(J)] = acc[J][r];
 }
 
 // y_c += E_c y_parent(c) for the clusters in `list`
 template <int NJ>
-__global__ __launch_bounds__(256) void k_down(int64_t m, const int32_t *__restrict__ list,
+__global__ __launch_bounds__(256) void k_down(int k, int64_t m, const int32_t *__restrict__ list,
                                               const int32_t *__restrict__ parent, const double *__restrict__ E,
                                               double *__restrict__ yh, int64_t ldh) {
     __shared__ Smem<NJ> sm;
@@ -228,14 +232,15 @@ __global__ __launch_bounds__(256) void k_down(int64_t m, const int32_t *__restri
     const int mc = (int)min<int64_t>(Smem<NJ>::MC, m - j0);
     dbl4 acc[NJ];
     zero<NJ>(acc);
-    accumulate<NJ>(sm, acc, 1, mc, [&](int) {
-        return Term{E + (int64_t)c * K * K, K, K, K, false, yh + j0, ldh, nullptr, (int64_t)par * K};
+    accumulate<NJ>(sm, acc, 1, mc, k, [&](int) {
+        return Term{E + (int64_t)c * k * k, k, k, k, false, yh + j0, ldh, nullptr, (int64_t)par * k};
     });
 #pragma unroll
     for (int J = 0; J < NJ; ++J)
         if (out_col(J) < mc)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) yh[((int64_t)c * K + out_row(r)) * ldh + j0 + out_col(J)] += acc[J][r];
+            for (int r = 0; r < 4; ++r)
+                if (out_row(r) < k) yh[((int64_t)c * k + out_row(r)) * ldh + j0 + out_col(J)] += acc[J][r];
 }
 
 // Leaf stage in the transposed orientation Y_t^T = X_s^T N_ts^T: the
@@ -266,7 +271,7 @@ struct Round {
 __device__ inline dbl2 ld2(const double *p) { return *(const dbl2 *)p; }
 
 template <int NP>
-__global__ __launch_bounds__(256, NP == 1 ? 2 : 1) void k_leaf_direct(int64_t m, int32_t L, const int32_t *__restrict__ leaves,
+__global__ __launch_bounds__(256, NP == 1 ? 2 : 1) void k_leaf_direct(int k, int64_t m, int32_t L, const int32_t *__restrict__ leaves,
                                                      const int32_t *__restrict__ first,
                                                      const int32_t *__restrict__ size,
                                                      const int64_t *__restrict__ perm, const double *__restrict__ Vt,
@@ -294,10 +299,10 @@ __global__ __launch_bounds__(256, NP == 1 ? 2 : 1) void k_leaf_direct(int64_t m,
 #pragma unroll
     for (int p = 0; p < NP; ++p) col_ok[p] = 32 * p + 2 * lr < mc;
     const int64_t q0 = near_ptr[l];
-    // items: nb parts of the basis term (k-ranges of 64 / nb), then the near blocks;
-    // without near blocks the basis term is split over the 4 waves
+    // items: nb parts of the basis term (k-ranges of ceil(k / nb)), then the near
+    // blocks; without near blocks the basis term is split over the 4 waves
     const int nb = basis ? (near ? 1 : 4) : 0;
-    const int kbase = K / max(nb, 1);
+    const int kbase = (k + max(nb, 1) - 1) / max(nb, 1);
     const int nitems = (near ? (int)(near_ptr[l + 1] - q0) : 0) + nb;
 
     for (int i0 = 0; i0 < nt; i0 += 64) {
@@ -320,9 +325,9 @@ __global__ __launch_bounds__(256, NP == 1 ? 2 : 1) void k_leaf_direct(int64_t m,
             int kl;
             if (e < nb) {
                 bb = Vt + vt_off[l] + (int64_t)e * kbase * nt2 + i0 + 2 * lr;   // V_t^T[nu][i]
-                ab = yh + ((int64_t)t * K + e * kbase) * ldh + j0 + 2 * lr;     // y_t[nu][j]
+                ab = yh + ((int64_t)t * k + e * kbase) * ldh + j0 + 2 * lr;     // y_t[nu][j]
                 lda = ldh;
-                kl = kbase;
+                kl = min(kbase, k - e * kbase);
             } else {
                 const int64_t q = q0 + e - nb;
                 const int32_t s = near_col[q];
@@ -343,7 +348,7 @@ __global__ __launch_bounds__(256, NP == 1 ? 2 : 1) void k_leaf_direct(int64_t m,
                     R.a[p][u] = (cok && col_ok[p]) ? ld2(ab + c * lda + 32 * p) : dbl2{0.0, 0.0};
             }
         };
-        auto klen = [&](int e) { return e < nb ? kbase : (int)size[near_col[q0 + e - nb]]; };
+        auto klen = [&](int e) { return e < nb ? min(kbase, k - e * kbase) : (int)size[near_col[q0 + e - nb]]; };
 
         int e = w;
         if (e < nitems) {

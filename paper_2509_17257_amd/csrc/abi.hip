@@ -207,6 +207,10 @@ h2x_status h2x_mat_create(const h2x_plan *plan, h2x_prec storage, void *dev_ws, 
     up(d.adm_cblk, P.adm_cblk);
     up(d.near_cptr, P.near_cptr);
     up(d.near_cblk, P.near_cblk);
+    std::vector<int32_t> sys_of(P.C);
+    for (int32_t i = 0; i < P.nsys(); ++i)
+        for (int64_t c = P.sys_C[i]; c < P.sys_C[i + 1]; ++c) sys_of[c] = i;
+    up(d.sys_of, sys_of);
     up(d.perm, P.perm);
     up(d.pts, P.pts_tree);
     up(d.box, P.box);

@@ -109,43 +109,48 @@ __device__ inline double sum_part(const double *part, int pair, int nblk, int64_
     return s;
 }
 
-__device__ inline double sum_seg(const double *part, int pair, int nblk, int64_t m, const Segs &sg, int seg,
-                                 int64_t j) {
-    double s = 0.0;
-    for (int b = sg.seg_blk[seg]; b < sg.seg_blk[seg + 1]; ++b) s += part[((int64_t)pair * nblk + b) * m + j];
-    return s;
-}
-
-// a system is done when each of its columns has converged or broken down; the
-// iteration stops when every system is done
-__device__ inline void systems_done(int64_t m, int it, CgState *state, const CgCols &cols, const Segs &sg) {
-    __shared__ int notdone;
-    if (threadIdx.x == 0) notdone = 0;
-    __syncthreads();
-    for (int s = threadIdx.x; s < sg.nseg; s += blockDim.x) {
-        if (sg.seg_done[s]) continue;
-        int d = 1;
-        for (int64_t j = 0; j < m; ++j) d &= cols.conv[s * m + j] | cols.frozen[s * m + j];
-        if (d) {
-            sg.seg_done[s] = 1;
-            sg.seg_iters[s] = it;
-        } else {
-            atomicOr(&notdone, 1);
+// The per-column scalar work runs with one work-group per system.  Column sums
+// of the two partial-sum pairs over the system's blocks are formed in a fixed
+// order: thread (r, j) adds blocks r, r + R, ... of column j, then the R partial
+// sums are added in order of r.  fn(j, e, s0, s1) handles entry e = s * m + j
+// and returns whether the column is still open (not converged, not broken down).
+template <typename F>
+__device__ inline bool for_columns(int64_t m, int nblk, const double *part, const Segs &sg, int s, F fn) {
+    __shared__ double red[2][256];
+    __shared__ int open;
+    const int tid = threadIdx.x;
+    const int mm = (int)min<int64_t>(m, 256), R = 256 / mm;
+    const int r = tid / mm, jl = tid % mm;
+    const int b0 = sg.seg_blk[s], b1 = sg.seg_blk[s + 1];
+    if (tid == 0) open = 0;
+    for (int64_t jc = 0; jc < m; jc += mm) {
+        const int64_t j = jc + jl;
+        double a = 0.0, c = 0.0;
+        if (r < R && j < m)
+            for (int bb = b0 + r; bb < b1; bb += R) {
+                a += part[(int64_t)bb * m + j];
+                c += part[((int64_t)nblk + bb) * m + j];
+            }
+        red[0][tid] = a;
+        red[1][tid] = c;
+        __syncthreads();
+        if (tid < mm && j < m) {
+            double s0 = 0.0, s1 = 0.0;
+            for (int q = 0; q < R; ++q) {
+                s0 += red[0][q * mm + tid];
+                s1 += red[1][q * mm + tid];
+            }
+            if (fn(j, (int64_t)s * m + j, s0, s1)) atomicOr(&open, 1);
         }
+        __syncthreads();
     }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        state->iter = it;
-        state->all_conv = notdone ? 0 : 1;
-    }
+    return open != 0;
 }
 
-// initial norms: pairs (B, B) and (R, R)
-__global__ void k_cg_init(int64_t m, int nblk, const double *part, double rtol, CgState *state, CgCols cols, Segs sg) {
-    for (int64_t e = threadIdx.x; e < sg.nseg * m; e += blockDim.x) {
-        const int s = (int)(e / m);
-        const int64_t j = e % m;
-        const double bb = sum_seg(part, 0, nblk, m, sg, s, j), rr = sum_seg(part, 1, nblk, m, sg, s, j);
+// initial norms: pairs (B, B) and (R, R); one work-group per system
+__global__ void k_cg_init(int64_t m, int nblk, const double *part, double rtol, CgCols cols, Segs sg) {
+    const int s = blockIdx.x;
+    const bool open = for_columns(m, nblk, part, sg, s, [&](int64_t, int64_t e, double bb, double rr) {
         cols.bnorm[e] = sqrt(bb);
         cols.rr[e] = rr;
         const int c = sqrt(rr) <= rtol * sqrt(bb);
@@ -154,32 +159,49 @@ __global__ void k_cg_init(int64_t m, int nblk, const double *part, double rtol, 
         cols.frozen[e] = 0;
         cols.status[e] = 0;
         cols.act[e] = 0;
-    }
-    for (int s = threadIdx.x; s < sg.nseg; s += blockDim.x) {
-        sg.seg_done[s] = 0;
+        cols.alpha[e] = 0.0;
+        cols.gamma[e] = 0.0;
+        return !c;
+    });
+    if (threadIdx.x == 0) {
+        sg.seg_done[s] = open ? 0 : 1;
         sg.seg_iters[s] = 0;
     }
-    if (threadIdx.x == 0) state->skip = 0;
-    __syncthreads();
-    systems_done(m, 0, state, cols, sg);
 }
 
-// pairs (P, AP) and (P, R): beta, alpha, breakdown detection
+// every system done -> stop; counts the iteration (init: starts at 0)
+__global__ void k_cg_state(int init, CgState *state, Segs sg) {
+    __shared__ int open;
+    if (!init && state->skip) return;
+    if (threadIdx.x == 0) open = 0;
+    __syncthreads();
+    for (int s = threadIdx.x; s < sg.nseg; s += blockDim.x)
+        if (!sg.seg_done[s]) atomicOr(&open, 1);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        state->all_conv = open ? 0 : 1;
+        if (init) {
+            state->iter = 0;
+            state->skip = 0;
+        } else {
+            state->iter += 1;
+        }
+    }
+}
+
+// pairs (P, AP) and (P, R): beta, alpha, breakdown detection; one work-group per system
 __global__ void k_cg_alpha(int64_t m, int nblk, const double *part, int freeze_converged, CgState *state,
                            CgCols cols, Segs sg) {
     const int skip = state->all_conv;
-    __syncthreads();
-    if (threadIdx.x == 0) state->skip = skip;
+    if (blockIdx.x == 0 && threadIdx.x == 0) state->skip = skip;
     if (skip) return;
-    for (int64_t e = threadIdx.x; e < sg.nseg * m; e += blockDim.x) {
-        const int s = (int)(e / m);
-        const int64_t j = e % m;
+    const int s = blockIdx.x;
+    const int done = sg.seg_done[s];
+    for_columns(m, nblk, part, sg, s, [&](int64_t, int64_t e, double beta, double rho) {
         // an exactly zero residual is an exact solution: nothing to update
-        int act = !sg.seg_done[s] && !cols.frozen[e] && !(freeze_converged && cols.conv[e]) && cols.rr[e] > 0.0;
-        double alpha = 0.0, beta = 0.0;
+        int act = !done && !cols.frozen[e] && !(freeze_converged && cols.conv[e]) && cols.rr[e] > 0.0;
+        double alpha = 0.0;
         if (act) {
-            beta = sum_seg(part, 0, nblk, m, sg, s, j);
-            const double rho = sum_seg(part, 1, nblk, m, sg, s, j);
             alpha = rho / beta;
             if (!(beta > 0.0) || !isfinite(alpha)) {
                 cols.frozen[e] = 1;
@@ -191,7 +213,8 @@ __global__ void k_cg_alpha(int64_t m, int nblk, const double *part, int freeze_c
         cols.beta[e] = beta;
         cols.alpha[e] = alpha;
         cols.act[e] = act;
-    }
+        return false;
+    });
 }
 
 // x += alpha p, r -= alpha a for active columns; then partial sums of <a, r>, <r, r>
@@ -214,24 +237,25 @@ __global__ __launch_bounds__(256) void k_cg_update_xr(int64_t m, int nblk, Segs 
     block_dots(r0, r1, m, nblk, AP, R, R, R, part);
 }
 
-// gamma, convergence test, iteration count
-__global__ void k_cg_gamma(int64_t m, int nblk, const double *part, double rtol, CgState *state, CgCols cols,
+// gamma, convergence test; one work-group per system
+__global__ void k_cg_gamma(int64_t m, int nblk, const double *part, double rtol, const CgState *state, CgCols cols,
                            Segs sg) {
     if (state->skip) return;
+    const int s = blockIdx.x;
+    if (sg.seg_done[s]) return;  // uniform over the work-group
     const int it = state->iter + 1;
-    for (int64_t e = threadIdx.x; e < sg.nseg * m; e += blockDim.x) {
-        const int s = (int)(e / m);
-        if (sg.seg_done[s]) continue;
-        const int64_t j = e % m;
-        const double ar = sum_seg(part, 0, nblk, m, sg, s, j), rr = sum_seg(part, 1, nblk, m, sg, s, j);
+    const bool open = for_columns(m, nblk, part, sg, s, [&](int64_t, int64_t e, double ar, double rr) {
         cols.gamma[e] = cols.act[e] ? ar / cols.beta[e] : 0.0;
         cols.rr[e] = rr;
         const int c = sqrt(rr) <= rtol * cols.bnorm[e];
         cols.conv[e] = c;
         if (c && cols.first_conv[e] < 0) cols.first_conv[e] = it;
+        return !c && !cols.frozen[e];
+    });
+    if (threadIdx.x == 0 && !open) {
+        sg.seg_done[s] = 1;
+        sg.seg_iters[s] = it;
     }
-    __syncthreads();
-    systems_done(m, it, state, cols, sg);
 }
 
 // p = r - gamma p for active columns
@@ -251,6 +275,7 @@ __global__ __launch_bounds__(256) void k_cg_update_p(int64_t m, Segs sg, const d
 // (its own original or tree order); its systems follow in order.
 struct Layout {
     std::vector<int64_t> row0;
+    std::vector<int32_t> seg0;  // first system of each operator
     std::vector<int64_t> blk_r0;
     std::vector<int32_t> blk_seg, seg_blk;
     int64_t n = 0;
@@ -265,6 +290,7 @@ Layout make_layout(const DevMat *const *mats, int32_t nmat, int64_t m) {
         const DevMat &dm = *mats[q];
         const Plan &P = *dm.plan;
         L.row0.push_back(L.n);
+        L.seg0.push_back(L.nseg);
         for (int32_t s = 0; s < P.nsys(); ++s) {
             const int64_t a = L.n + P.sys_row[s], ns = P.sys_row[s + 1] - P.sys_row[s];
             const int64_t nb = std::min<int64_t>(1024, std::max<int64_t>(1, (ns + 63) / 64));
@@ -509,25 +535,29 @@ h2x_status run_block_cg_batch(const DevMat *const *mats, int32_t nmat, const h2x
                            st);
     if (e != hipSuccess) return fail(e);
 
-    // the product of one iteration, operator by operator on its own rows
-    auto product = [&](const double *Pv, double *APv, double alpha, double beta, hipStream_t s) {
+    // the product of one iteration, operator by operator on its own rows; with
+    // skip, the clusters of systems that have stopped are left out
+    auto product = [&](const double *Pv, double *APv, double alpha, double beta, bool skip, hipStream_t s) {
         for (int32_t q = 0; q < nmat; ++q) {
             const int64_t r = L.row0[q] * m;
-            hipError_t ee = run_matmul(*mats[q], m, alpha, Pv + r, m, beta, APv + r, m, true, w.mm, s);
+            hipError_t ee = run_matmul(*mats[q], m, alpha, Pv + r, m, beta, APv + r, m, true, w.mm, s, nullptr,
+                                       skip ? w.seg_done + L.seg0[q] : nullptr);
             if (ee != hipSuccess) return ee;
         }
         return hipSuccess;
     };
     auto iteration = [&](hipStream_t s) {
-        hipError_t ee = product(w.P, w.AP, 1.0, 0.0, s);
+        hipError_t ee = product(w.P, w.AP, 1.0, 0.0, true, s);
         if (ee != hipSuccess) return ee;
         hipLaunchKernelGGL(k_sdots, gd, dim3(256), 0, s, m, nblk, sg, w.P, w.AP, w.P, w.R, w.part,
                            (const CgState *)w.state);
-        hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(256), 0, s, m, nblk, w.part, prm.freeze_converged, w.state,
-                           w.cols, sg);
+        hipLaunchKernelGGL(k_cg_alpha, dim3(L.nseg), dim3(256), 0, s, m, nblk, w.part, prm.freeze_converged,
+                           w.state, w.cols, sg);
         hipLaunchKernelGGL(k_cg_update_xr, gd, dim3(256), 0, s, m, nblk, sg, w.Xt, w.R, w.P, w.AP, w.part,
                            (const CgState *)w.state, w.cols);
-        hipLaunchKernelGGL(k_cg_gamma, dim3(1), dim3(256), 0, s, m, nblk, w.part, prm.rtol, w.state, w.cols, sg);
+        hipLaunchKernelGGL(k_cg_gamma, dim3(L.nseg), dim3(256), 0, s, m, nblk, w.part, prm.rtol,
+                           (const CgState *)w.state, w.cols, sg);
+        hipLaunchKernelGGL(k_cg_state, dim3(1), dim3(256), 0, s, 0, w.state, sg);
         hipLaunchKernelGGL(k_cg_update_p, gd, dim3(256), 0, s, m, sg, w.R, w.P, (const CgState *)w.state, w.cols);
         return hipGetLastError();
     };
@@ -543,12 +573,13 @@ h2x_status run_block_cg_batch(const DevMat *const *mats, int32_t nmat, const h2x
     }
     // R = B - A X0, P = R
     hipLaunchKernelGGL(k_copy, dim3(g1), dim3(256), 0, st, nm, w.Bt, w.R);
-    e = product(w.Xt, w.R, -1.0, 1.0, st);
+    e = product(w.Xt, w.R, -1.0, 1.0, false, st);
     if (e != hipSuccess) return fail(e);
     hipLaunchKernelGGL(k_copy, dim3(g1), dim3(256), 0, st, nm, w.R, w.P);
     hipLaunchKernelGGL(k_sdots, gd, dim3(256), 0, st, m, nblk, sg, w.Bt, w.Bt, w.R, w.R, w.part,
                        (const CgState *)nullptr);
-    hipLaunchKernelGGL(k_cg_init, dim3(1), dim3(256), 0, st, m, nblk, w.part, prm.rtol, w.state, w.cols, sg);
+    hipLaunchKernelGGL(k_cg_init, dim3(L.nseg), dim3(256), 0, st, m, nblk, w.part, prm.rtol, w.cols, sg);
+    hipLaunchKernelGGL(k_cg_state, dim3(1), dim3(256), 0, st, 1, w.state, sg);
 
     const int check = prm.check_every > 0 ? prm.check_every : 1;
     hipStream_t run = st;

@@ -40,6 +40,7 @@ struct DevMat {
     int64_t *near_off_rm = nullptr;  // n_near, offsets of row-major |t| x |s| blocks (gradient output)
     int64_t *adm_cptr = nullptr, *adm_cblk = nullptr;    // admissible blocks by column cluster
     int64_t *near_cptr = nullptr, *near_cblk = nullptr;  // near-field blocks by column leaf
+    int32_t *sys_of = nullptr;   // C, system of each cluster
     int64_t *perm = nullptr;     // n
     double *pts = nullptr;       // n x 3 tree order
     double *box = nullptr;       // C x 6
@@ -59,6 +60,15 @@ struct DevMat {
 
 inline int s_swizzled(const DevMat &dm) { return dm.swz; }
 
+// Work of clusters whose system has stopped can be left out of a product: flag
+// holds one entry per system (nonzero: stopped), sys_of the system of each
+// cluster.  A default-constructed Skip leaves nothing out.
+struct Skip {
+    const int32_t *flag = nullptr;
+    const int32_t *sys_of = nullptr;
+    __device__ bool operator()(int32_t c) const { return flag && flag[sys_of[c]]; }
+};
+
 size_t mat_layout(const Plan &P, h2x_prec storage, DevMat *dm, char *base);
 
 hipError_t launch_fill(const DevMat &dm, hipStream_t st);
@@ -67,9 +77,12 @@ size_t matmul_ws_bytes(const DevMat &dm, int64_t m);
 // ev (optional): 7 events recorded on the stream: before the first stage, after
 // each of the 5 stages, and (ev[6]) after the near field, which the matrix-core
 // path fuses into the leaf stage
+// skip (optional, device, one flag per system of the plan): clusters of systems
+// whose flag is set are left out (their rows of Y are not written); honoured on
+// the matrix-core path
 hipError_t run_matmul(const DevMat &dm, int64_t m, double alpha, const double *X, int64_t ldx, double beta,
                       double *Y, int64_t ldy, bool tree_order, char *ws, hipStream_t st,
-                      hipEvent_t *ev = nullptr);
+                      hipEvent_t *ev = nullptr, const int32_t *skip = nullptr);
 
 size_t cg_ws_bytes(const DevMat &dm, int64_t m);
 size_t cg_batch_ws_bytes(const DevMat *const *mats, int32_t nmat, int64_t m);

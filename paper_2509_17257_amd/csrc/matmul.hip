@@ -298,7 +298,7 @@ inline int64_t even_ld(int64_t m) { return m + (m & 1); }
 template <int NJ>
 void matmul_mfma_f64(const DevMat &dm, int64_t m, double alpha, const double *X, int64_t ldx, double beta, double *Y,
                      int64_t ldy, int to, double *xh, double *yh, int64_t ldh, double *xt_ws, hipStream_t st,
-                     const std::function<void(int)> &mark, hipEvent_t *ev) {
+                     const std::function<void(int)> &mark, hipEvent_t *ev, const int32_t *skip) {
     const Plan &P = *dm.plan;
     const unsigned gy = (unsigned)((m + 16 * NJ - 1) / (16 * NJ));
     constexpr int NP = NJ > 2 ? 2 : 1;  // leaf stage: 32 or 64 columns per work-group
@@ -314,23 +314,24 @@ void matmul_mfma_f64(const DevMat &dm, int64_t m, double alpha, const double *X,
                            to ? nullptr : dm.perm, X, ldx, xt_ws, ldxt);
         Xt = xt_ws;
     }
+    const Skip sk{skip, dm.sys_of};
     hipLaunchKernelGGL(mfma::k_fwd_leaf<NJ>, dim3(dm.L, gy), dim3(256), 0, st, dm.k, m, dm.leaves, dm.first,
-                       dm.size, dm.perm, V, Xt, ldxt, 1, xh, ldh);
+                       dm.size, dm.perm, V, Xt, ldxt, 1, xh, ldh, sk);
     mark(1);
     for (int d = dm.depth_max - 1; d >= P.adm_depth; --d) {
         const int32_t b = P.lvl_inner_ptr[d], e = P.lvl_inner_ptr[d + 1];
         if (e > b)
             hipLaunchKernelGGL(mfma::k_up<NJ>, dim3(e - b, gy), dim3(256), 0, st, dm.k, m, dm.lvl_inner + b,
-                               dm.son0, dm.son1, E, xh, ldh);
+                               dm.son0, dm.son1, E, xh, ldh, sk);
     }
     mark(2);
-    launch_coupling_fast<double, double>(dm, m, xh, yh, ldh, st);
+    launch_coupling_fast<double, double>(dm, m, xh, yh, ldh, st, sk);
     mark(3);
     for (int d = std::max(1, P.adm_depth + 1); d <= dm.depth_max; ++d) {
         const int32_t b = P.lvl_ptr[d], e = P.lvl_ptr[d + 1];
         if (e > b)
             hipLaunchKernelGGL(mfma::k_down<NJ>, dim3(e - b, gy), dim3(256), 0, st, dm.k, m, dm.lvl_all + b,
-                               dm.parent, E, yh, ldh);
+                               dm.parent, E, yh, ldh, sk);
     }
     mark(4);
     // Y = beta Y + alpha (V y-hat + N X)
@@ -338,7 +339,7 @@ void matmul_mfma_f64(const DevMat &dm, int64_t m, double alpha, const double *X,
     hipLaunchKernelGGL(mfma::k_leaf_direct<NP>, dim3(8 * ((dm.L + 7) / 8), gl), dim3(256), 0, st, dm.k, m, dm.L,
                        dm.leaves,
                        dm.first, dm.size, dm.perm, (const double *)dm.Vt, dm.vt_off, yh, ldh, dm.near_ptr,
-                       dm.near_col, dm.near_off, (const double *)dm.N, Xt, ldxt, alpha, beta, Y, ldy, to, 1, 1);
+                       dm.near_col, dm.near_off, (const double *)dm.N, Xt, ldxt, alpha, beta, Y, ldy, to, 1, 1, sk);
     mark(5);
     if (ev) (void)hipEventRecord(ev[6], st);
 }
@@ -350,7 +351,8 @@ size_t hat_bytes(const DevMat &dm, int64_t m) {
 
 template <typename T, typename TN, typename Acc>
 hipError_t matmul_typed(const DevMat &dm, int64_t m, double alpha, const double *X, int64_t ldx, double beta,
-                        double *Y, int64_t ldy, bool tree_order, char *ws, hipStream_t st, hipEvent_t *ev) {
+                        double *Y, int64_t ldy, bool tree_order, char *ws, hipStream_t st, hipEvent_t *ev,
+                        const int32_t *skip) {
     auto mark = [&](int i) {
         if (ev) (void)hipEventRecord(ev[i], st);
     };
@@ -361,16 +363,17 @@ hipError_t matmul_typed(const DevMat &dm, int64_t m, double alpha, const double 
     const unsigned gy = (unsigned)((m + TC - 1) / TC);
     const int to = tree_order ? 1 : 0;
     const T *V = (const T *)dm.V, *E = (const T *)dm.E, *S = (const T *)dm.S;
+    (void)skip;  // only the matrix-core path leaves stopped systems out
 
     if constexpr (std::is_same<T, double>::value && std::is_same<Acc, double>::value) {
         if (dm.mc) {
             const std::function<void(int)> mk = mark;
             double *xt = (double *)(ws + 2 * hat_bytes<Acc>(dm, m));
             switch ((int)std::min<int64_t>(4, (m + 15) / 16)) {
-                case 1: matmul_mfma_f64<1>(dm, m, alpha, X, ldx, beta, Y, ldy, to, xh, yh, ldh, xt, st, mk, ev); break;
-                case 2: matmul_mfma_f64<2>(dm, m, alpha, X, ldx, beta, Y, ldy, to, xh, yh, ldh, xt, st, mk, ev); break;
-                case 3: matmul_mfma_f64<3>(dm, m, alpha, X, ldx, beta, Y, ldy, to, xh, yh, ldh, xt, st, mk, ev); break;
-                default: matmul_mfma_f64<4>(dm, m, alpha, X, ldx, beta, Y, ldy, to, xh, yh, ldh, xt, st, mk, ev); break;
+                case 1: matmul_mfma_f64<1>(dm, m, alpha, X, ldx, beta, Y, ldy, to, xh, yh, ldh, xt, st, mk, ev, skip); break;
+                case 2: matmul_mfma_f64<2>(dm, m, alpha, X, ldx, beta, Y, ldy, to, xh, yh, ldh, xt, st, mk, ev, skip); break;
+                case 3: matmul_mfma_f64<3>(dm, m, alpha, X, ldx, beta, Y, ldy, to, xh, yh, ldh, xt, st, mk, ev, skip); break;
+                default: matmul_mfma_f64<4>(dm, m, alpha, X, ldx, beta, Y, ldy, to, xh, yh, ldh, xt, st, mk, ev, skip); break;
             }
             return hipGetLastError();
         }
@@ -387,7 +390,7 @@ hipError_t matmul_typed(const DevMat &dm, int64_t m, double alpha, const double 
                                dm.son1, E, xh, ldh);
     }
     mark(2);
-    if (!launch_coupling_fast<T, Acc>(dm, m, xh, yh, ldh, st))
+    if (!launch_coupling_fast<T, Acc>(dm, m, xh, yh, ldh, st, Skip{}))
         hipLaunchKernelGGL((k_coupling<T, Acc>), dim3(dm.C, gy), dim3(256), 0, st, dm.k, m, dm.adm_ptr, dm.adm_col, S,
                            dm.swz, xh, yh, ldh);
     mark(3);
@@ -427,12 +430,12 @@ hipError_t run_forward_transform(const DevMat &dm, int64_t m, const double *X, i
         auto launch = [&](auto NJc) {
             constexpr int NJ = decltype(NJc)::value;
             hipLaunchKernelGGL(mfma::k_fwd_leaf<NJ>, dim3(dm.L, gy), dim3(256), 0, st, dm.k, m, dm.leaves, dm.first,
-                               dm.size, dm.perm, V, Xt, ldxt, 1, xh, ldh);
+                               dm.size, dm.perm, V, Xt, ldxt, 1, xh, ldh, Skip{});
             for (int d = dm.depth_max - 1; d >= P.adm_depth; --d) {
                 const int32_t b = P.lvl_inner_ptr[d], e = P.lvl_inner_ptr[d + 1];
                 if (e > b)
                     hipLaunchKernelGGL(mfma::k_up<NJ>, dim3(e - b, gy), dim3(256), 0, st, dm.k, m, dm.lvl_inner + b,
-                                       dm.son0, dm.son1, E, xh, ldh);
+                                       dm.son0, dm.son1, E, xh, ldh, Skip{});
             }
         };
         switch (nj) {
@@ -475,14 +478,15 @@ size_t matmul_ws_bytes(const DevMat &dm, int64_t m) {
 }
 
 hipError_t run_matmul(const DevMat &dm, int64_t m, double alpha, const double *X, int64_t ldx, double beta, double *Y,
-                      int64_t ldy, bool tree_order, char *ws, hipStream_t st, hipEvent_t *ev) {
+                      int64_t ldy, bool tree_order, char *ws, hipStream_t st, hipEvent_t *ev, const int32_t *skip) {
     switch (dm.storage) {
         case H2X_F64:
-            return matmul_typed<double, double, double>(dm, m, alpha, X, ldx, beta, Y, ldy, tree_order, ws, st, ev);
+            return matmul_typed<double, double, double>(dm, m, alpha, X, ldx, beta, Y, ldy, tree_order, ws, st, ev,
+                                                        skip);
         case H2X_F32:
-            return matmul_typed<float, float, float>(dm, m, alpha, X, ldx, beta, Y, ldy, tree_order, ws, st, ev);
+            return matmul_typed<float, float, float>(dm, m, alpha, X, ldx, beta, Y, ldy, tree_order, ws, st, ev, skip);
         default:
-            return matmul_typed<bf16_t, float, float>(dm, m, alpha, X, ldx, beta, Y, ldy, tree_order, ws, st, ev);
+            return matmul_typed<bf16_t, float, float>(dm, m, alpha, X, ldx, beta, Y, ldy, tree_order, ws, st, ev, skip);
     }
 }
 

@@ -35,13 +35,14 @@ __global__ __launch_bounds__(256) void k_coupling_mfma_f64(int64_t m, int32_t C,
                                                            const int32_t *__restrict__ adm_col,
                                                            const double *__restrict__ S,
                                                            const double *__restrict__ xh, double *__restrict__ yh,
-                                                           int64_t ldh) {
+                                                           int64_t ldh, Skip skip) {
     constexpr int MC = 16 * NJ;   // columns per work-group
     constexpr int LDX = MC + 1;   // padded LDS row
     __shared__ double xs[2][kMfmaK * LDX];
     const int slot = (blockIdx.x & 7) * rows_per_xcd + (blockIdx.x >> 3);
     if (slot >= C) return;
     const int32_t t = order[slot];
+    if (skip(t)) return;
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     const int lr = lane & 15, lq = lane >> 4;
     const int64_t j0 = (int64_t)blockIdx.y * MC;
@@ -142,13 +143,14 @@ __global__ __launch_bounds__(128) void k_coupling_mfma_small(int k, int64_t m, i
                                                              const int32_t *__restrict__ adm_col,
                                                              const double *__restrict__ S,
                                                              const double *__restrict__ xh, double *__restrict__ yh,
-                                                             int64_t ldh) {
+                                                             int64_t ldh, Skip skip) {
     constexpr int MC = 16 * NJ;
     constexpr int LDX = MC + 1;
     __shared__ double xs[2][32 * LDX];
     const int slot = (blockIdx.x & 7) * rows_per_xcd + (blockIdx.x >> 3);
     if (slot >= C) return;
     const int32_t t = order[slot];
+    if (skip(t)) return;
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     const int lr = lane & 15, g = lane >> 4;
     const int64_t j0 = (int64_t)blockIdx.y * MC;
@@ -245,7 +247,8 @@ __global__ __launch_bounds__(128) void k_coupling_mfma_small(int k, int64_t m, i
 // Launches the matrix-core coupling stage when the operator's layout supports
 // it; returns false (launching nothing) otherwise.
 template <typename T, typename Acc>
-bool launch_coupling_fast(const DevMat &dm, int64_t m, const Acc *xh, Acc *yh, int64_t ldh, hipStream_t st) {
+bool launch_coupling_fast(const DevMat &dm, int64_t m, const Acc *xh, Acc *yh, int64_t ldh, hipStream_t st,
+                          Skip skip) {
     if constexpr (!std::is_same<T, double>::value || !std::is_same<Acc, double>::value) {
         return false;
     } else {
@@ -259,7 +262,7 @@ bool launch_coupling_fast(const DevMat &dm, int64_t m, const Acc *xh, Acc *yh, i
             auto go = [&](auto NJc) {
                 constexpr int NJ = decltype(NJc)::value;
                 hipLaunchKernelGGL(k_coupling_mfma_small<NJ>, grid, dim3(128), 0, st, dm.k, m, dm.C, rpx,
-                                   dm.cpl_order, dm.adm_ptr, dm.adm_col, S, xh, yh, ldh);
+                                   dm.cpl_order, dm.adm_ptr, dm.adm_col, S, xh, yh, ldh, skip);
             };
             switch (nj) {
                 case 1: go(std::integral_constant<int, 1>{}); break;
@@ -273,19 +276,19 @@ bool launch_coupling_fast(const DevMat &dm, int64_t m, const Acc *xh, Acc *yh, i
         switch (nj) {
             case 1:
                 hipLaunchKernelGGL(k_coupling_mfma_f64<1>, grid, dim3(256), 0, st, m, dm.C, rpx, dm.cpl_order,
-                                   dm.adm_ptr, dm.adm_col, S, xh, yh, ldh);
+                                   dm.adm_ptr, dm.adm_col, S, xh, yh, ldh, skip);
                 break;
             case 2:
                 hipLaunchKernelGGL(k_coupling_mfma_f64<2>, grid, dim3(256), 0, st, m, dm.C, rpx, dm.cpl_order,
-                                   dm.adm_ptr, dm.adm_col, S, xh, yh, ldh);
+                                   dm.adm_ptr, dm.adm_col, S, xh, yh, ldh, skip);
                 break;
             case 3:
                 hipLaunchKernelGGL(k_coupling_mfma_f64<3>, grid, dim3(256), 0, st, m, dm.C, rpx, dm.cpl_order,
-                                   dm.adm_ptr, dm.adm_col, S, xh, yh, ldh);
+                                   dm.adm_ptr, dm.adm_col, S, xh, yh, ldh, skip);
                 break;
             default:
                 hipLaunchKernelGGL(k_coupling_mfma_f64<4>, grid, dim3(256), 0, st, m, dm.C, rpx, dm.cpl_order,
-                                   dm.adm_ptr, dm.adm_col, S, xh, yh, ldh);
+                                   dm.adm_ptr, dm.adm_col, S, xh, yh, ldh, skip);
                 break;
         }
         return true;

@@ -172,9 +172,10 @@ __global__ __launch_bounds__(256) void k_fwd_leaf(int k, int64_t m, const int32_
                                                   const int32_t *__restrict__ first, const int32_t *__restrict__ size,
                                                   const int64_t *__restrict__ perm, const double *__restrict__ V,
                                                   const double *__restrict__ X, int64_t ldx, int tree_order,
-                                                  double *__restrict__ xh, int64_t ldh) {
+                                                  double *__restrict__ xh, int64_t ldh, Skip skip) {
     __shared__ Smem<NJ> sm;
     const int32_t t = leaves[blockIdx.x];
+    if (skip(t)) return;
     const int64_t j0 = (int64_t)blockIdx.y * Smem<NJ>::MC;
     const int mc = (int)min<int64_t>(Smem<NJ>::MC, m - j0);
     const int64_t r0 = first[t];
@@ -199,9 +200,11 @@ __global__ __launch_bounds__(256) void k_fwd_leaf(int k, int64_t m, const int32_
 template <int NJ>
 __global__ __launch_bounds__(256) void k_up(int k, int64_t m, const int32_t *__restrict__ list,
                                             const int32_t *__restrict__ son0, const int32_t *__restrict__ son1,
-                                            const double *__restrict__ E, double *__restrict__ xh, int64_t ldh) {
+                                            const double *__restrict__ E, double *__restrict__ xh, int64_t ldh,
+                                            Skip skip) {
     __shared__ Smem<NJ> sm;
     const int32_t t = list[blockIdx.x];
+    if (skip(t)) return;
     const int64_t j0 = (int64_t)blockIdx.y * Smem<NJ>::MC;
     const int mc = (int)min<int64_t>(Smem<NJ>::MC, m - j0);
     clear<NJ>(sm);
@@ -224,9 +227,10 @@ __global__ __launch_bounds__(256) void k_up(int k, int64_t m, const int32_t *__r
 template <int NJ>
 __global__ __launch_bounds__(256) void k_down(int k, int64_t m, const int32_t *__restrict__ list,
                                               const int32_t *__restrict__ parent, const double *__restrict__ E,
-                                              double *__restrict__ yh, int64_t ldh) {
+                                              double *__restrict__ yh, int64_t ldh, Skip skip) {
     __shared__ Smem<NJ> sm;
     const int32_t c = list[blockIdx.x];
+    if (skip(c)) return;
     const int32_t par = parent[c];
     const int64_t j0 = (int64_t)blockIdx.y * Smem<NJ>::MC;
     const int mc = (int)min<int64_t>(Smem<NJ>::MC, m - j0);
@@ -282,13 +286,14 @@ __global__ __launch_bounds__(256, NP == 1 ? 2 : 1) void k_leaf_direct(int k, int
                                                      const int64_t *__restrict__ near_off,
                                                      const double *__restrict__ Nt, const double *__restrict__ Xt,
                                                      int64_t ldxt, double alpha, double beta, double *__restrict__ Y,
-                                                     int64_t ldy, int tree_order, int basis, int near) {
+                                                     int64_t ldy, int tree_order, int basis, int near, Skip skip) {
     constexpr int MC = 32 * NP, LDR = MC + 1;
     __shared__ double red[64 * LDR];
     const int32_t per_xcd = (L + 7) / 8;
     const int32_t l = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
     if (l >= L) return;
     const int32_t t = leaves[l];
+    if (skip(t)) return;
     const int nt = size[t];
     const int64_t nt2 = nt + (nt & 1);
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, lq = lane >> 4;

@@ -1,0 +1,232 @@
+// Matrix-core coupling kernels for the low-precision operators with k = 64:
+//   y_t = sum_{(t,s) in C_t, admissible} S_b x_s     for every row cluster t,
+// S_b stored in FP32 or BF16, x-hat and y-hat in FP32, FP32 accumulation.
+//
+// Same organisation as the FP64 kernel: one work-group (4 waves) per row
+// cluster and slab of 16*NJ columns, wave w owns rows 16w..16w+15, S_b streamed
+// from HBM one block ahead in the lane order of the MFMA operand (layouts 2 and
+// 3 of s_index: one 16-byte load per lane per k-chunk), x_s staged in LDS
+// (double-buffered).  Output layout of both 16x16 MFMAs: register q of lane l
+// holds row 4 (l / 16) + q, column l % 16.
+//
+// FP32: v_mfma_f32_16x16x4f32, lane (r, g) takes columns 16a + 4g + h of S_b in
+//       k-step 4a + h (h = 0..3), so one float4 load serves four k-steps.
+// BF16: v_mfma_f32_16x16x32_bf16, lane (r, g) takes columns 32c + 8g .. + 7 in
+//       k-chunk c; x_s is rounded to BF16 (nearest even) when it is staged and
+//       kept transposed in LDS so that each lane reads its 8 values at once.
+#pragma once
+
+#include <type_traits>
+
+#include "device.hpp"
+#include "types.hpp"
+
+namespace h2x {
+
+typedef float flt4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+template <int NJ>
+__global__ __launch_bounds__(256) void k_coupling_mfma_f32(int64_t m, int32_t C, int32_t rows_per_xcd,
+                                                           const int32_t *__restrict__ order,
+                                                           const int64_t *__restrict__ adm_ptr,
+                                                           const int32_t *__restrict__ adm_col,
+                                                           const float *__restrict__ S, const float *__restrict__ xh,
+                                                           float *__restrict__ yh, int64_t ldh, Skip skip) {
+    constexpr int K = 64, MC = 16 * NJ, LDX = MC + 1;
+    __shared__ float xs[2][K * LDX];
+    const int slot = (blockIdx.x & 7) * rows_per_xcd + (blockIdx.x >> 3);
+    if (slot >= C) return;
+    const int32_t t = order[slot];
+    if (skip(t)) return;
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    const int lr = lane & 15, g = lane >> 4;
+    const int64_t j0 = (int64_t)blockIdx.y * MC;
+    const int mc = (int)min<int64_t>(MC, m - j0);
+    const int64_t b0 = adm_ptr[t], b1 = adm_ptr[t + 1];
+
+    flt4 acc[NJ];
+#pragma unroll
+    for (int J = 0; J < NJ; ++J) acc[J] = flt4{0.f, 0.f, 0.f, 0.f};
+
+    if (b1 > b0) {
+        constexpr int XPT = (K * MC) / 256;
+        float xv[XPT];
+        auto load_x = [&](int32_t s) {
+            const float *src = xh + (int64_t)s * K * ldh + j0;
+#pragma unroll
+            for (int u = 0; u < XPT; ++u) {
+                const int e = tid + 256 * u, r = e / MC, c = e % MC;
+                xv[u] = c < mc ? src[(int64_t)r * ldh + c] : 0.f;
+            }
+        };
+        auto store_x = [&](int buf) {
+#pragma unroll
+            for (int u = 0; u < XPT; ++u) {
+                const int e = tid + 256 * u, r = e / MC, c = e % MC;
+                xs[buf][r * LDX + c] = xv[u];
+            }
+        };
+        flt4 sa[4], sn[4];
+        auto load_s = [&](int64_t b, flt4 *dst) {
+            const flt4 *src = (const flt4 *)(S + b * K * K) + (int64_t)w * 4 * 64 + lane;
+#pragma unroll
+            for (int a = 0; a < 4; ++a) dst[a] = __builtin_nontemporal_load(src + a * 64);
+        };
+
+        load_x(adm_col[b0]);
+        load_s(b0, sa);
+        store_x(0);
+        __syncthreads();
+        for (int64_t b = b0; b < b1; ++b) {
+            const int buf = (int)((b - b0) & 1);
+            const bool more = b + 1 < b1;
+            if (more) {
+                load_x(adm_col[b + 1]);
+                load_s(b + 1, sn);
+            }
+            const float *xb = xs[buf];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int h = 0; h < 4; ++h) {
+                    const int krow = 16 * a + 4 * g + h;
+#pragma unroll
+                    for (int J = 0; J < NJ; ++J)
+                        acc[J] = __builtin_amdgcn_mfma_f32_16x16x4f32(sa[a][h], xb[krow * LDX + 16 * J + lr], acc[J],
+                                                                       0, 0, 0);
+                }
+            if (more) {
+                store_x(buf ^ 1);
+#pragma unroll
+                for (int a = 0; a < 4; ++a) sa[a] = sn[a];
+            }
+            __syncthreads();
+        }
+    }
+#pragma unroll
+    for (int J = 0; J < NJ; ++J) {
+        const int col = 16 * J + lr;
+        if (col < mc)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) yh[((int64_t)t * K + 16 * w + 4 * g + q) * ldh + j0 + col] = acc[J][q];
+    }
+}
+
+template <int NJ>
+__global__ __launch_bounds__(256) void k_coupling_mfma_bf16(int64_t m, int32_t C, int32_t rows_per_xcd,
+                                                            const int32_t *__restrict__ order,
+                                                            const int64_t *__restrict__ adm_ptr,
+                                                            const int32_t *__restrict__ adm_col,
+                                                            const bf16_t *__restrict__ S, const float *__restrict__ xh,
+                                                            float *__restrict__ yh, int64_t ldh, Skip skip) {
+    constexpr int K = 64, MC = 16 * NJ;
+    constexpr int LDT = K + 8;  // LDS row (one column of x_s) in bf16 units, padded against bank conflicts
+    __shared__ uint16_t xs[2][MC * LDT];
+    const int slot = (blockIdx.x & 7) * rows_per_xcd + (blockIdx.x >> 3);
+    if (slot >= C) return;
+    const int32_t t = order[slot];
+    if (skip(t)) return;
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    const int lr = lane & 15, g = lane >> 4;
+    const int64_t j0 = (int64_t)blockIdx.y * MC;
+    const int mc = (int)min<int64_t>(MC, m - j0);
+    const int64_t b0 = adm_ptr[t], b1 = adm_ptr[t + 1];
+
+    flt4 acc[NJ];
+#pragma unroll
+    for (int J = 0; J < NJ; ++J) acc[J] = flt4{0.f, 0.f, 0.f, 0.f};
+
+    if (b1 > b0) {
+        constexpr int XPT = (K * MC) / 256;
+        float xv[XPT];
+        auto load_x = [&](int32_t s) {
+            const float *src = xh + (int64_t)s * K * ldh + j0;
+#pragma unroll
+            for (int u = 0; u < XPT; ++u) {
+                const int e = tid + 256 * u, r = e / MC, c = e % MC;
+                xv[u] = c < mc ? src[(int64_t)r * ldh + c] : 0.f;
+            }
+        };
+        auto store_x = [&](int buf) {  // transposed: column c of x_s is LDS row c
+#pragma unroll
+            for (int u = 0; u < XPT; ++u) {
+                const int e = tid + 256 * u, r = e / MC, c = e % MC;
+                xs[buf][c * LDT + r] = bf16_bits(xv[u]);
+            }
+        };
+        u32x4 sa[2], sn[2];
+        auto load_s = [&](int64_t b, u32x4 *dst) {
+            const u32x4 *src = (const u32x4 *)(S + b * K * K) + (int64_t)w * 2 * 64 + lane;
+#pragma unroll
+            for (int c = 0; c < 2; ++c) dst[c] = __builtin_nontemporal_load(src + c * 64);
+        };
+
+        load_x(adm_col[b0]);
+        load_s(b0, sa);
+        store_x(0);
+        __syncthreads();
+        for (int64_t b = b0; b < b1; ++b) {
+            const int buf = (int)((b - b0) & 1);
+            const bool more = b + 1 < b1;
+            if (more) {
+                load_x(adm_col[b + 1]);
+                load_s(b + 1, sn);
+            }
+            const uint16_t *xb = xs[buf];
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const bf16x8 av = __builtin_bit_cast(bf16x8, sa[c]);
+#pragma unroll
+                for (int J = 0; J < NJ; ++J) {
+                    const u32x4 bb = *(const u32x4 *)(xb + (16 * J + lr) * LDT + 32 * c + 8 * g);
+                    acc[J] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, __builtin_bit_cast(bf16x8, bb), acc[J], 0,
+                                                                      0, 0);
+                }
+            }
+            if (more) {
+                store_x(buf ^ 1);
+                sa[0] = sn[0];
+                sa[1] = sn[1];
+            }
+            __syncthreads();
+        }
+    }
+#pragma unroll
+    for (int J = 0; J < NJ; ++J) {
+        const int col = 16 * J + lr;
+        if (col < mc)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) yh[((int64_t)t * K + 16 * w + 4 * g + q) * ldh + j0 + col] = acc[J][q];
+    }
+}
+
+// Launches the low-precision matrix-core coupling when the layout supports it.
+template <typename T>
+bool launch_coupling_lp(const DevMat &dm, int64_t m, const float *xh, float *yh, int64_t ldh, hipStream_t st,
+                        Skip skip) {
+    const bool f32 = std::is_same<T, float>::value;
+    if (dm.k != 64 || !dm.cpl_order || dm.swz != (f32 ? 2 : 3)) return false;
+    const int nj = (int)std::min<int64_t>(4, (m + 15) / 16);
+    const int32_t rpx = (dm.C + 7) / 8;
+    const dim3 grid((unsigned)(8 * rpx), (unsigned)((m + 16 * nj - 1) / (16 * nj)));
+    auto go = [&](auto NJc) {
+        constexpr int NJ = decltype(NJc)::value;
+        if constexpr (std::is_same<T, float>::value)
+            hipLaunchKernelGGL(k_coupling_mfma_f32<NJ>, grid, dim3(256), 0, st, m, dm.C, rpx, dm.cpl_order,
+                               dm.adm_ptr, dm.adm_col, (const float *)dm.S, xh, yh, ldh, skip);
+        else
+            hipLaunchKernelGGL(k_coupling_mfma_bf16<NJ>, grid, dim3(256), 0, st, m, dm.C, rpx, dm.cpl_order,
+                               dm.adm_ptr, dm.adm_col, (const bf16_t *)dm.S, xh, yh, ldh, skip);
+    };
+    switch (nj) {
+        case 1: go(std::integral_constant<int, 1>{}); break;
+        case 2: go(std::integral_constant<int, 2>{}); break;
+        case 3: go(std::integral_constant<int, 3>{}); break;
+        default: go(std::integral_constant<int, 4>{}); break;
+    }
+    return true;
+}
+
+}  // namespace h2x

@@ -213,10 +213,11 @@ size_t mat_layout(const Plan &P, h2x_prec storage, DevMat *dm, char *base) {
     d.n = n; d.C = C; d.L = L; d.k = k; d.p = P.p; d.depth_max = P.depth_max; d.max_leaf = P.max_leaf;
     d.n_adm = na; d.n_near = nn; d.near_entries = P.near_entries; d.storage = storage;
     d.kernel = P.prm.kernel; d.ell = P.prm.ell; d.shift = P.prm.shift; d.plan = &P;
-    d.swz = (storage == H2X_F64 && k == 64) ? 1 : 0;
+    d.swz = k != 64 ? 0 : (storage == H2X_F64 ? 1 : (storage == H2X_F32 ? 2 : 3));
     // matrix-core layout (transposed near field, transposed leaf bases): FP64, k = 64 or k <= 32
     d.mc = (storage == H2X_F64 && (k == 64 || k <= 32)) ? 1 : 0;
-    d.near_t = d.mc;
+    // low-precision operators with k = 64 use the same transposed near field (FP32) and leaf bases
+    d.near_t = (d.mc || (storage != H2X_F64 && k == 64)) ? 1 : 0;
     d.first = carve<int32_t>(cur, base, C);
     d.size = carve<int32_t>(cur, base, C);
     d.parent = carve<int32_t>(cur, base, C);

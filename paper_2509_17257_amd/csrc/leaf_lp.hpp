@@ -1,0 +1,197 @@
+// Matrix-core leaf stage for the low-precision operators (k = 64): near field in
+// FP32, leaf basis in FP32 or BF16, FP32 accumulation (v_mfma_f32_16x16x4f32):
+//   Y|_t = beta Y|_t + alpha (V_t y_t + sum_s N_ts X|_s).
+// X arrives as an FP32 copy in tree order.  With a BF16 basis, y_t is rounded to
+// BF16 before it multiplies V_t (both factors of a product in the storage type;
+// a product of two BF16 values is exact in FP32).
+//
+// Organisation as in the FP64 leaf kernel: transposed orientation Y_t^T = X_s^T
+// N_ts^T, near-field blocks stored transposed with rows padded to an even length,
+// one 8-byte load per lane feeds an "even" and an "odd" tile, the 4 waves of a
+// work-group share the leaf's terms round-robin and their partial tiles are
+// added in LDS in wave order.  Output layout of the FP32 MFMA: register q of
+// lane l holds row 4 (l / 16) + q (here: a column of Y), column l % 16 (a row).
+#pragma once
+
+#include "device.hpp"
+#include "types.hpp"
+
+namespace h2x {
+namespace lp {
+
+typedef float flt2 __attribute__((ext_vector_type(2)));
+typedef float flt4v __attribute__((ext_vector_type(4)));
+
+__device__ inline flt2 ld2(const float *p) { return *(const flt2 *)p; }
+__device__ inline flt2 ld2(const bf16_t *p) {
+    const uint32_t u = *(const uint32_t *)p;
+    return flt2{__builtin_bit_cast(float, u << 16), __builtin_bit_cast(float, u & 0xffff0000u)};
+}
+__device__ inline float round_bf16(float v) { return __builtin_bit_cast(float, (uint32_t)bf16_bits(v) << 16); }
+
+template <int NP>
+struct Round {
+    flt2 b[2][4];   // [row half g][k-step u]: rows 32g + 2 lr + {0, 1}
+    flt2 a[NP][4];  // [column half p][k-step u]: columns 32p + 2 lr + {0, 1}
+};
+
+template <int NP, typename TV>
+__global__ __launch_bounds__(256, 2) void k_leaf_lp(int k, int64_t m, int32_t L, const int32_t *__restrict__ leaves,
+                                                    const int32_t *__restrict__ first, const int32_t *__restrict__ size,
+                                                    const int64_t *__restrict__ perm, const TV *__restrict__ Vt,
+                                                    const int64_t *__restrict__ vt_off, const float *__restrict__ yh,
+                                                    int64_t ldh, const int64_t *__restrict__ near_ptr,
+                                                    const int32_t *__restrict__ near_col,
+                                                    const int64_t *__restrict__ near_off,
+                                                    const float *__restrict__ Nt, const float *__restrict__ Xt,
+                                                    int64_t ldxt, double alpha, double beta, double *__restrict__ Y,
+                                                    int64_t ldy, int tree_order, int round_y, Skip skip) {
+    constexpr int MC = 32 * NP, LDR = MC + 1;
+    __shared__ float red[64 * LDR];
+    const int32_t per_xcd = (L + 7) / 8;
+    const int32_t l = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+    if (l >= L) return;
+    const int32_t t = leaves[l];
+    if (skip(t)) return;
+    const int nt = size[t];
+    const int64_t nt2 = nt + (nt & 1);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, lq = lane >> 4;
+    const int64_t r0 = first[t];
+    const int64_t j0 = (int64_t)blockIdx.y * MC;
+    const int mc = (int)min<int64_t>(MC, m - j0);
+    bool col_ok[NP];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) col_ok[p] = 32 * p + 2 * lr < mc;
+    const int64_t q0 = near_ptr[l];
+    // items: the basis term, then the near blocks
+    const int nitems = (int)(near_ptr[l + 1] - q0) + 1;
+
+    for (int i0 = 0; i0 < nt; i0 += 64) {
+        const int ic = min(64, nt - i0);
+        const int nhalf = (ic + 31) >> 5;
+        bool row_ok[2];
+#pragma unroll
+        for (int g = 0; g < 2; ++g) row_ok[g] = 32 * g + 2 * lr < ic;
+        flt4v acc[2 * NP][4];
+#pragma unroll
+        for (int J = 0; J < 2 * NP; ++J)
+#pragma unroll
+            for (int I = 0; I < 4; ++I) acc[J][I] = flt4v{0.f, 0.f, 0.f, 0.f};
+
+        auto load = [&](int e, int kb, Round<NP> &R) {
+            int kl;
+            if (e == 0) {
+                const TV *bb = Vt + vt_off[l] + i0 + 2 * lr;              // V_t^T[nu][i]
+                const float *ab = yh + (int64_t)t * k * ldh + j0 + 2 * lr;  // y_t[nu][j]
+                kl = k;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int c = kb + 4 * u + lq;
+                    const bool cok = c < kl;
+#pragma unroll
+                    for (int g = 0; g < 2; ++g)
+                        R.b[g][u] = (cok && row_ok[g]) ? ld2(bb + c * nt2 + 32 * g) : flt2{0.f, 0.f};
+#pragma unroll
+                    for (int p = 0; p < NP; ++p) {
+                        flt2 v = (cok && col_ok[p]) ? ld2(ab + c * ldh + 32 * p) : flt2{0.f, 0.f};
+                        if (round_y) v = flt2{round_bf16(v.x), round_bf16(v.y)};
+                        R.a[p][u] = v;
+                    }
+                }
+            } else {
+                const int64_t q = q0 + e - 1;
+                const int32_t s = near_col[q];
+                const float *bb = Nt + near_off[q] + i0 + 2 * lr;                 // N_ts^T[c][i]
+                const float *ab = Xt + (int64_t)first[s] * ldxt + j0 + 2 * lr;  // X_s[c][j]
+                kl = size[s];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int c = kb + 4 * u + lq;
+                    const bool cok = c < kl;
+#pragma unroll
+                    for (int g = 0; g < 2; ++g)
+                        R.b[g][u] = (cok && row_ok[g]) ? ld2(bb + c * nt2 + 32 * g) : flt2{0.f, 0.f};
+#pragma unroll
+                    for (int p = 0; p < NP; ++p)
+                        R.a[p][u] = (cok && col_ok[p]) ? ld2(ab + c * ldxt + 32 * p) : flt2{0.f, 0.f};
+                }
+            }
+        };
+        auto klen = [&](int e) { return e == 0 ? k : (int)size[near_col[q0 + e - 1]]; };
+
+        int e = w;
+        if (e < nitems) {
+            Round<NP> cur, nxt;
+            int kb = 0, len = klen(e);
+            load(e, kb, cur);
+            for (;;) {
+                int en = e, kbn = kb + 16, lenn = len;
+                if (kbn >= len) {
+                    en = e + 4;
+                    kbn = 0;
+                    if (en < nitems) lenn = klen(en);
+                }
+                const bool more = en < nitems;
+                if (more) load(en, kbn, nxt);
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int g = 0; g < 2; ++g)
+                        if (g < nhalf)
+#pragma unroll
+                            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                                for (int p = 0; p < NP; ++p)
+#pragma unroll
+                                    for (int hj = 0; hj < 2; ++hj)
+                                        acc[2 * p + hj][2 * g + h] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                                            cur.a[p][u][hj], cur.b[g][u][h], acc[2 * p + hj][2 * g + h], 0, 0, 0);
+                if (!more) break;
+                cur = nxt;
+                e = en;
+                kb = kbn;
+                len = lenn;
+            }
+        }
+        // tile (J = 2p + hj, I = 2g + h): register q of lane l -> column 32p + 2 (4 (l / 16) + q) + hj,
+        // row 32g + 2 (l % 16) + h
+        for (int ww = 0; ww < 4; ++ww) {
+            if (w == ww)
+#pragma unroll
+                for (int J = 0; J < 2 * NP; ++J)
+#pragma unroll
+                    for (int I = 0; I < 4; ++I)
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const int col = 32 * (J >> 1) + 2 * (4 * lq + q) + (J & 1);
+                            const int row = 32 * (I >> 1) + 2 * lr + (I & 1);
+                            float *cell = &red[row * LDR + col];
+                            *cell = (ww == 0) ? acc[J][I][q] : *cell + acc[J][I][q];
+                        }
+            __syncthreads();
+        }
+        for (int x = threadIdx.x; x < ic * MC; x += 256) {
+            const int i = x / MC, j = x % MC;
+            if (j < mc) {
+                int64_t row = r0 + i0 + i;
+                if (!tree_order) row = perm[row];
+                double *y = &Y[row * ldy + j0 + j];
+                const double v = alpha * (double)red[i * LDR + j];
+                *y = (beta == 0.0) ? v : beta * *y + v;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// rows of X into tree order as FP32 (nearest) with an even leading dimension, zero padding
+__global__ void k_gather_f32(int64_t n, int64_t m, const int64_t *__restrict__ perm, const double *__restrict__ X,
+                             int64_t ldx, float *__restrict__ Xt, int64_t ldt) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * ldt) return;
+    const int64_t i = e / ldt, j = e % ldt;
+    Xt[e] = j < m ? (float)X[(perm ? perm[i] : i) * ldx + j] : 0.f;
+}
+
+}  // namespace lp
+}  // namespace h2x

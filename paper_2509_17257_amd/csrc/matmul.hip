@@ -15,6 +15,8 @@
 #include <type_traits>
 
 #include "device.hpp"
+#include "coupling_lp.hpp"
+#include "leaf_lp.hpp"
 #include "matmul_mfma.hpp"
 #include "stages_mfma.hpp"
 #include "types.hpp"
@@ -357,7 +359,10 @@ hipError_t matmul_typed(const DevMat &dm, int64_t m, double alpha, const double 
         if (ev) (void)hipEventRecord(ev[i], st);
     };
     const Plan &P = *dm.plan;
-    const int64_t ldh = dm.mc ? even_ld(m) : m;
+    // low-precision operator in the matrix-core layout (k = 64): FP32 matrix-core
+    // coupling and leaf stage, generic transfer passes
+    const bool lpmc = !std::is_same<T, double>::value && dm.near_t && dm.k == 64;
+    const int64_t ldh = (dm.mc || lpmc) ? even_ld(m) : m;
     Acc *xh = (Acc *)ws;
     Acc *yh = (Acc *)(ws + hat_bytes<Acc>(dm, m));
     const unsigned gy = (unsigned)((m + TC - 1) / TC);
@@ -390,7 +395,10 @@ hipError_t matmul_typed(const DevMat &dm, int64_t m, double alpha, const double 
                                dm.son1, E, xh, ldh);
     }
     mark(2);
-    if (!launch_coupling_fast<T, Acc>(dm, m, xh, yh, ldh, st, Skip{}))
+    bool fast = launch_coupling_fast<T, Acc>(dm, m, xh, yh, ldh, st, Skip{});
+    if constexpr (std::is_same<Acc, float>::value && !std::is_same<T, double>::value)
+        if (!fast) fast = launch_coupling_lp<T>(dm, m, xh, yh, ldh, st, Skip{skip, dm.sys_of});
+    if (!fast)
         hipLaunchKernelGGL((k_coupling<T, Acc>), dim3(dm.C, gy), dim3(256), 0, st, dm.k, m, dm.adm_ptr, dm.adm_col, S,
                            dm.swz, xh, yh, ldh);
     mark(3);
@@ -401,6 +409,30 @@ hipError_t matmul_typed(const DevMat &dm, int64_t m, double alpha, const double 
                                E, yh, ldh);
     }
     mark(4);
+    if constexpr (std::is_same<Acc, float>::value && !std::is_same<T, double>::value && std::is_same<TN, float>::value) {
+        if (lpmc) {
+            float *xt = (float *)(ws + 2 * hat_bytes<Acc>(dm, m));
+            const int64_t ldxt = even_ld(m), cnt = dm.n * ldxt;
+            hipLaunchKernelGGL(lp::k_gather_f32, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, dm.n, m,
+                               to ? nullptr : dm.perm, X, ldx, xt, ldxt);
+            const Skip sk{skip, dm.sys_of};
+            const int rb = std::is_same<T, bf16_t>::value ? 1 : 0;
+            const unsigned gl8 = 8 * ((dm.L + 7) / 8);
+            if (m > 32)
+                hipLaunchKernelGGL((lp::k_leaf_lp<2, T>), dim3(gl8, (unsigned)((m + 63) / 64)), dim3(256), 0, st,
+                                   dm.k, m, dm.L, dm.leaves, dm.first, dm.size, dm.perm, (const T *)dm.Vt, dm.vt_off,
+                                   yh, ldh, dm.near_ptr, dm.near_col, dm.near_off, (const float *)dm.N, xt, ldxt,
+                                   alpha, beta, Y, ldy, to, rb, sk);
+            else
+                hipLaunchKernelGGL((lp::k_leaf_lp<1, T>), dim3(gl8, (unsigned)((m + 31) / 32)), dim3(256), 0, st,
+                                   dm.k, m, dm.L, dm.leaves, dm.first, dm.size, dm.perm, (const T *)dm.Vt, dm.vt_off,
+                                   yh, ldh, dm.near_ptr, dm.near_col, dm.near_off, (const float *)dm.N, xt, ldxt,
+                                   alpha, beta, Y, ldy, to, rb, sk);
+            mark(5);
+            if (ev) (void)hipEventRecord(ev[6], st);
+            return hipGetLastError();
+        }
+    }
     hipLaunchKernelGGL((k_leaf_near<T, TN, Acc>), dim3(dm.L, gy), dim3(256), 0, st, dm.k, m, dm.leaves, dm.first,
                        dm.size, dm.perm, V, yh, ldh, dm.near_ptr, dm.near_col, dm.near_off, (const TN *)dm.N, X, ldx,
                        alpha, beta, Y, ldy, to, dm.near_t);
@@ -474,7 +506,8 @@ hipError_t run_down_pass(const DevMat &dm, int64_t m, double *yh, int64_t ldh, h
 size_t matmul_ws_bytes(const DevMat &dm, int64_t m) {
     // x-hat, y-hat, and the tree-ordered copy of X used by the matrix-core path
     if (dm.storage == H2X_F64) return 2 * hat_bytes<double>(dm, m) + align_up(sizeof(double) * (size_t)dm.n * even_ld(m));
-    return 2 * hat_bytes<float>(dm, m);
+    // low precision: x-hat, y-hat, and the FP32 tree-ordered copy of X of the matrix-core leaf stage
+    return 2 * hat_bytes<float>(dm, m) + (dm.near_t ? align_up(sizeof(float) * (size_t)dm.n * even_ld(m)) : 0);
 }
 
 hipError_t run_matmul(const DevMat &dm, int64_t m, double alpha, const double *X, int64_t ldx, double beta, double *Y,

@@ -125,11 +125,12 @@ def precision_report(args, torch, h2x, W):
     for prec, s_b, s_n in (("f64", 8, 8), ("f32", 4, 4), ("bf16", 2, 4)):
         t0 = time.perf_counter()
         A = h2x.H2Matrix(plan, storage=prec, device=dev)
+        tune = A.autotune(m) if args.autotune else None
         torch.cuda.synchronize()
         Y = torch.empty_like(X)
         ms = time_products(h2x, torch, A, X, Y, args.steps)
         B_alg = alg_bytes(plan, m, s_b=s_b, s_n=s_n)
-        rec = {"setup_s": round(time.perf_counter() - t0, 2), "ms_per_product": round(ms, 3),
+        rec = {"setup_s": round(time.perf_counter() - t0, 2), "autotune": tune, "ms_per_product": round(ms, 3),
                "alg_gbs": round(B_alg / (ms * 1e-3) / 1e9, 1), "alg_bytes": int(B_alg)}
         if prec == "f64":
             Y64 = Y.clone()
@@ -252,6 +253,9 @@ def batch_report(args, torch, h2x, W):
            "near_entries_total": int(sum(p.near_entries for p in batch.plans)),
            "alg_bytes_per_product": int(alg), "alg_bytes_padded_m": int(alg_pad)}
     log(f"[batch] {len(systems)} systems, n total {batch.n}, setup {setup_s:.1f} s")
+    if args.autotune:
+        out["autotune"] = batch.autotune(m)
+        log(f"[batch] autotuned: {out['autotune']}")
 
     def timed(fn, reps):
         fn()
@@ -324,6 +328,7 @@ def main():
     ap.add_argument("--workload", default="sphere-n65536-k64-m32")
     ap.add_argument("--cg", type=int, default=1, help="also time block CG to 1e-8")
     ap.add_argument("--max-cg-iter", type=int, default=5000)
+    ap.add_argument("--autotune", type=int, default=1, help="autotune the tile shapes before timing (1) or not (0)")
     ap.add_argument("--cpu-baseline-s", type=float, default=12.0, help="0 disables the oracle timing")
     ap.add_argument("--precision-report", action="store_true",
                     help="report FP64 / FP32 / BF16 products and FP64 vs refined block CG on the precision workload")
@@ -394,6 +399,9 @@ def main():
     log(f"[bench] setup {setup_s:.2f} s; C={plan.C} leaves={plan.leaves} adm={plan.n_adm} near={plan.n_near} "
         f"near entries={plan.near_entries}")
 
+    tune = A.autotune(m) if args.autotune else None
+    if tune:
+        log(f"[bench] autotuned tile shapes: {tune}")
     for _ in range(args.warmup):
         h2x.h2_matmul(A, X, out=Y)
     torch.cuda.synchronize()
@@ -461,6 +469,7 @@ def main():
         "stage_ms": {n: round(float(v), 5) for n, v in zip(h2x.STAGES, stage)},
         "roofline": roof,
         "setup_s": round(setup_s, 3),
+        "autotune": tune,
     }
 
     if args.cg:

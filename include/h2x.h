@@ -233,6 +233,27 @@ h2x_status h2x_block_cg_refine(const h2x_mat *A, const h2x_mat *A_lo, const h2x_
                                int64_t ldx, void *dev_ws, size_t ws_bytes, h2x_cg_info *info,
                                void *hip_stream);
 
+/* ---- tuning ----------------------------------------------------------------- */
+/* Tile shapes of the matrix-core kernels: columns per work-group of the forward
+ * leaf and transfer passes (16 * nj_transfer), of the coupling (16 * nj_coupling)
+ * and of the leaf stage (32 * np_leaf); 0 means the built-in rule. */
+typedef struct {
+    int32_t nj_transfer, nj_coupling, np_leaf;
+    double ms_default; /* product time with the built-in rule */
+    double ms_tuned;   /* product time with the chosen shapes */
+} h2x_tune_info;
+
+/* Autotune the operator for m columns: time the product with each candidate
+ * shape per stage (HIP events, a few runs each, on synthetic right-hand sides
+ * inside the workspace), keep the fastest per stage if the combination beats
+ * the built-in rule, and store the choice in the operator for every column
+ * count with the same ceil(m / 16) (counts above 64 share one entry).  Later
+ * products and solves on the operator use it.  Blocking.  info may be NULL.
+ * Must not run concurrently with other calls on the same operator. */
+size_t h2x_mat_autotune_workspace_bytes(const h2x_mat *A, int64_t m);
+h2x_status h2x_mat_autotune(h2x_mat *A, int64_t m, void *dev_ws, size_t ws_bytes, void *hip_stream,
+                            h2x_tune_info *info);
+
 /* ---- batches ---------------------------------------------------------------- */
 /* A batch is a list of operators (typically one merged plan per Chebyshev order
  * and storage precision) whose rows are concatenated in order: operator j owns

@@ -55,6 +55,11 @@ CG_INDEPENDENT, CG_SHARED = 0, 1
 _VARIANT = {"independent": CG_INDEPENDENT, "shared": CG_SHARED, CG_INDEPENDENT: CG_INDEPENDENT, CG_SHARED: CG_SHARED}
 
 
+class _TuneInfo(C.Structure):
+    _fields_ = [("nj_transfer", C.c_int32), ("nj_coupling", C.c_int32), ("np_leaf", C.c_int32),
+                ("ms_default", C.c_double), ("ms_tuned", C.c_double)]
+
+
 class _CgInfo(C.Structure):
     _fields_ = [("iters", C.c_int32), ("status", C.c_int32), ("outer_iters", C.c_int32),
                 ("col_relres", C.POINTER(C.c_double)),
@@ -106,6 +111,8 @@ def load_library():
         "h2x_mat_set_ell": (C.c_int, [P, D, P]),
         "h2x_mat_coupling": (C.c_int, [P, P, P]),
         "h2x_mat_set_coupling": (C.c_int, [P, P, P]),
+        "h2x_mat_autotune_workspace_bytes": (SZ, [P, I64]),
+        "h2x_mat_autotune": (C.c_int, [P, I64, P, SZ, P, C.POINTER(_TuneInfo)]),
         "h2x_last_error": (C.c_char_p, []),
         "h2x_version": (C.c_char_p, []),
     }
@@ -238,6 +245,19 @@ class H2Matrix:
             ws = torch.empty(max(nb, 256), dtype=torch.uint8, device=self.device)
             self._mm_ws[key] = ws
         return ws
+
+    def autotune(self, m: int) -> dict:
+        """Choose the matrix-core tile shapes for m columns by timing (h2x_mat_autotune);
+        later products and solves with a similar column count use them."""
+        import torch
+        lib = load_library()
+        nb = lib.h2x_mat_autotune_workspace_bytes(self._h, int(m))
+        ws = torch.empty(max(nb, 256), dtype=torch.uint8, device=self.device)
+        info = _TuneInfo()
+        _check(lib.h2x_mat_autotune(self._h, int(m), C.c_void_p(ws.data_ptr()), ws.numel(),
+                                    _stream(torch, self.device), C.byref(info)), "h2x_mat_autotune")
+        return dict(nj_transfer=info.nj_transfer, nj_coupling=info.nj_coupling, np_leaf=info.np_leaf,
+                    ms_default=info.ms_default, ms_tuned=info.ms_tuned)
 
     def set_ell(self, ell: float) -> None:
         """Refill S and the near field for a new kernel length scale (h2x_mat_set_ell)."""
@@ -458,6 +478,10 @@ class Batch:
         if getattr(self, "_h", None) and _lib is not None:
             _lib.h2x_batch_destroy(self._h)
             self._h = None
+
+    def autotune(self, m: int) -> list:
+        """Autotune every operator of the batch for m columns."""
+        return [A.autotune(m) for A in self.mats]
 
     def rows(self, i: int):
         """Row range of system i (caller's numbering) in batch-wide blocks."""

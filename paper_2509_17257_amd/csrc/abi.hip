@@ -309,6 +309,19 @@ h2x_status h2x_block_cg(const h2x_mat *A, const h2x_cg_params *prm, int64_t m, c
     return run_block_cg(A->dm, *prm, m, B, ldb, X, ldx, (char *)dev_ws, ws_bytes, info, (hipStream_t)hip_stream);
 }
 
+size_t h2x_mat_autotune_workspace_bytes(const h2x_mat *A, int64_t m) {
+    if (!A || m < 1) return 0;
+    return autotune_ws_bytes(A->dm, m);
+}
+
+h2x_status h2x_mat_autotune(h2x_mat *A, int64_t m, void *dev_ws, size_t ws_bytes, void *hip_stream,
+                            h2x_tune_info *info) {
+    if (!A || !dev_ws) return fail(H2X_EINVAL, "h2x_mat_autotune: NULL argument");
+    if (m < 1) return fail(H2X_EINVAL, "h2x_mat_autotune: need m >= 1");
+    if (!aligned(dev_ws)) return fail(H2X_EINVAL, "h2x_mat_autotune: workspace not 256-byte aligned");
+    return run_autotune(A->dm, m, (char *)dev_ws, ws_bytes, (hipStream_t)hip_stream, info);
+}
+
 h2x_status h2x_batch_create(const h2x_mat *const *mats, int32_t count, h2x_batch **out) {
     if (!out) return fail(H2X_EINVAL, "h2x_batch_create: out is NULL");
     *out = nullptr;

@@ -205,10 +205,10 @@ __global__ __launch_bounds__(256) void k_coupling_mfma_bf16(int64_t m, int32_t C
 // Launches the low-precision matrix-core coupling when the layout supports it.
 template <typename T>
 bool launch_coupling_lp(const DevMat &dm, int64_t m, const float *xh, float *yh, int64_t ldh, hipStream_t st,
-                        Skip skip) {
+                        Skip skip, int nj_force) {
     const bool f32 = std::is_same<T, float>::value;
     if (dm.k != 64 || !dm.cpl_order || dm.swz != (f32 ? 2 : 3)) return false;
-    const int nj = (int)std::min<int64_t>(4, (m + 15) / 16);
+    const int nj = nj_force ? nj_force : (int)std::min<int64_t>(4, (m + 15) / 16);
     const int32_t rpx = (dm.C + 7) / 8;
     const dim3 grid((unsigned)(8 * rpx), (unsigned)((m + 16 * nj - 1) / (16 * nj)));
     auto go = [&](auto NJc) {

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <vector>
 
@@ -12,6 +13,17 @@ namespace h2x {
 
 constexpr size_t kAlign = 256;
 inline size_t align_up(size_t v, size_t a = kAlign) { return (v + a - 1) / a * a; }
+
+// Tile choices of the matrix-core paths (0: the default rule), filled by the
+// autotuner per bucket of the column count: bucket b holds ceil(m / 16) = b + 1
+// for b < 4, bucket 4 anything wider.
+struct TuneCfg {
+    int8_t nj_transfer = 0;  // 16-column tiles per work-group: forward leaf, transfer passes
+    int8_t nj_coupling = 0;  // 16-column tiles per work-group: coupling
+    int8_t np_leaf = 0;      // 32-column tiles per work-group: leaf stage
+};
+constexpr int kTuneBuckets = 5;
+inline int tune_bucket(int64_t m) { return (int)std::min<int64_t>(kTuneBuckets - 1, (m + 15) / 16 - 1); }
 
 // Flat device arrays of one operator, all inside the caller's workspace.
 struct DevMat {
@@ -56,6 +68,8 @@ struct DevMat {
     // host copies of the level tables (launch sizes)
     const Plan *plan = nullptr;
 
+    TuneCfg tuned[kTuneBuckets];
+
 };
 
 inline int s_swizzled(const DevMat &dm) { return dm.swz; }
@@ -83,6 +97,13 @@ size_t matmul_ws_bytes(const DevMat &dm, int64_t m);
 hipError_t run_matmul(const DevMat &dm, int64_t m, double alpha, const double *X, int64_t ldx, double beta,
                       double *Y, int64_t ldy, bool tree_order, char *ws, hipStream_t st,
                       hipEvent_t *ev = nullptr, const int32_t *skip = nullptr);
+
+// the product with explicit tile choices (the autotuner's candidates)
+hipError_t run_matmul_cfg(const DevMat &dm, const TuneCfg &cfg, int64_t m, double alpha, const double *X, int64_t ldx,
+                          double beta, double *Y, int64_t ldy, bool tree_order, char *ws, hipStream_t st,
+                          hipEvent_t *ev, const int32_t *skip);
+size_t autotune_ws_bytes(const DevMat &dm, int64_t m);
+h2x_status run_autotune(DevMat &dm, int64_t m, char *ws, size_t ws_bytes, hipStream_t st, h2x_tune_info *info);
 
 size_t cg_ws_bytes(const DevMat &dm, int64_t m);
 size_t cg_batch_ws_bytes(const DevMat *const *mats, int32_t nmat, int64_t m);

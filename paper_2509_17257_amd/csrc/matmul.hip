@@ -298,12 +298,13 @@ inline int64_t even_ld(int64_t m) { return m + (m & 1); }
 
 // All five stages on the matrix cores (FP64 operator, k = 64 or k <= 32).
 template <int NJ>
-void matmul_mfma_f64(const DevMat &dm, int64_t m, double alpha, const double *X, int64_t ldx, double beta, double *Y,
-                     int64_t ldy, int to, double *xh, double *yh, int64_t ldh, double *xt_ws, hipStream_t st,
-                     const std::function<void(int)> &mark, hipEvent_t *ev, const int32_t *skip) {
+void matmul_mfma_f64(const DevMat &dm, const TuneCfg &cfg, int64_t m, double alpha, const double *X, int64_t ldx,
+                     double beta, double *Y, int64_t ldy, int to, double *xh, double *yh, int64_t ldh, double *xt_ws,
+                     hipStream_t st, const std::function<void(int)> &mark, hipEvent_t *ev, const int32_t *skip) {
     const Plan &P = *dm.plan;
     const unsigned gy = (unsigned)((m + 16 * NJ - 1) / (16 * NJ));
-    constexpr int NP = NJ > 2 ? 2 : 1;  // leaf stage: 32 or 64 columns per work-group
+    // leaf stage: 32 or 64 columns per work-group
+    const int NP = cfg.np_leaf ? cfg.np_leaf : (m > 32 ? 2 : 1);
     const double *V = (const double *)dm.V, *E = (const double *)dm.E;
     mark(0);
     // the leaf stage reads X in tree order, 16 bytes per lane: copy it unless it already is
@@ -327,7 +328,7 @@ void matmul_mfma_f64(const DevMat &dm, int64_t m, double alpha, const double *X,
                                dm.son0, dm.son1, E, xh, ldh, sk);
     }
     mark(2);
-    launch_coupling_fast<double, double>(dm, m, xh, yh, ldh, st, sk);
+    launch_coupling_fast<double, double>(dm, m, xh, yh, ldh, st, sk, cfg.nj_coupling);
     mark(3);
     for (int d = std::max(1, P.adm_depth + 1); d <= dm.depth_max; ++d) {
         const int32_t b = P.lvl_ptr[d], e = P.lvl_ptr[d + 1];
@@ -338,10 +339,16 @@ void matmul_mfma_f64(const DevMat &dm, int64_t m, double alpha, const double *X,
     mark(4);
     // Y = beta Y + alpha (V y-hat + N X)
     const unsigned gl = (unsigned)((m + 32 * NP - 1) / (32 * NP));
-    hipLaunchKernelGGL(mfma::k_leaf_direct<NP>, dim3(8 * ((dm.L + 7) / 8), gl), dim3(256), 0, st, dm.k, m, dm.L,
-                       dm.leaves,
-                       dm.first, dm.size, dm.perm, (const double *)dm.Vt, dm.vt_off, yh, ldh, dm.near_ptr,
-                       dm.near_col, dm.near_off, (const double *)dm.N, Xt, ldxt, alpha, beta, Y, ldy, to, 1, 1, sk);
+    if (NP == 2)
+        hipLaunchKernelGGL(mfma::k_leaf_direct<2>, dim3(8 * ((dm.L + 7) / 8), gl), dim3(256), 0, st, dm.k, m, dm.L,
+                           dm.leaves, dm.first, dm.size, dm.perm, (const double *)dm.Vt, dm.vt_off, yh, ldh,
+                           dm.near_ptr, dm.near_col, dm.near_off, (const double *)dm.N, Xt, ldxt, alpha, beta, Y, ldy,
+                           to, 1, 1, sk);
+    else
+        hipLaunchKernelGGL(mfma::k_leaf_direct<1>, dim3(8 * ((dm.L + 7) / 8), gl), dim3(256), 0, st, dm.k, m, dm.L,
+                           dm.leaves, dm.first, dm.size, dm.perm, (const double *)dm.Vt, dm.vt_off, yh, ldh,
+                           dm.near_ptr, dm.near_col, dm.near_off, (const double *)dm.N, Xt, ldxt, alpha, beta, Y, ldy,
+                           to, 1, 1, sk);
     mark(5);
     if (ev) (void)hipEventRecord(ev[6], st);
 }
@@ -352,8 +359,8 @@ size_t hat_bytes(const DevMat &dm, int64_t m) {
 }
 
 template <typename T, typename TN, typename Acc>
-hipError_t matmul_typed(const DevMat &dm, int64_t m, double alpha, const double *X, int64_t ldx, double beta,
-                        double *Y, int64_t ldy, bool tree_order, char *ws, hipStream_t st, hipEvent_t *ev,
+hipError_t matmul_typed(const DevMat &dm, const TuneCfg &cfg, int64_t m, double alpha, const double *X, int64_t ldx,
+                        double beta, double *Y, int64_t ldy, bool tree_order, char *ws, hipStream_t st, hipEvent_t *ev,
                         const int32_t *skip) {
     auto mark = [&](int i) {
         if (ev) (void)hipEventRecord(ev[i], st);
@@ -374,11 +381,11 @@ hipError_t matmul_typed(const DevMat &dm, int64_t m, double alpha, const double 
         if (dm.mc) {
             const std::function<void(int)> mk = mark;
             double *xt = (double *)(ws + 2 * hat_bytes<Acc>(dm, m));
-            switch ((int)std::min<int64_t>(4, (m + 15) / 16)) {
-                case 1: matmul_mfma_f64<1>(dm, m, alpha, X, ldx, beta, Y, ldy, to, xh, yh, ldh, xt, st, mk, ev, skip); break;
-                case 2: matmul_mfma_f64<2>(dm, m, alpha, X, ldx, beta, Y, ldy, to, xh, yh, ldh, xt, st, mk, ev, skip); break;
-                case 3: matmul_mfma_f64<3>(dm, m, alpha, X, ldx, beta, Y, ldy, to, xh, yh, ldh, xt, st, mk, ev, skip); break;
-                default: matmul_mfma_f64<4>(dm, m, alpha, X, ldx, beta, Y, ldy, to, xh, yh, ldh, xt, st, mk, ev, skip); break;
+            switch (cfg.nj_transfer ? (int)cfg.nj_transfer : (int)std::min<int64_t>(4, (m + 15) / 16)) {
+                case 1: matmul_mfma_f64<1>(dm, cfg, m, alpha, X, ldx, beta, Y, ldy, to, xh, yh, ldh, xt, st, mk, ev, skip); break;
+                case 2: matmul_mfma_f64<2>(dm, cfg, m, alpha, X, ldx, beta, Y, ldy, to, xh, yh, ldh, xt, st, mk, ev, skip); break;
+                case 3: matmul_mfma_f64<3>(dm, cfg, m, alpha, X, ldx, beta, Y, ldy, to, xh, yh, ldh, xt, st, mk, ev, skip); break;
+                default: matmul_mfma_f64<4>(dm, cfg, m, alpha, X, ldx, beta, Y, ldy, to, xh, yh, ldh, xt, st, mk, ev, skip); break;
             }
             return hipGetLastError();
         }
@@ -395,9 +402,9 @@ hipError_t matmul_typed(const DevMat &dm, int64_t m, double alpha, const double 
                                dm.son1, E, xh, ldh);
     }
     mark(2);
-    bool fast = launch_coupling_fast<T, Acc>(dm, m, xh, yh, ldh, st, Skip{});
+    bool fast = launch_coupling_fast<T, Acc>(dm, m, xh, yh, ldh, st, Skip{}, 0);
     if constexpr (std::is_same<Acc, float>::value && !std::is_same<T, double>::value)
-        if (!fast) fast = launch_coupling_lp<T>(dm, m, xh, yh, ldh, st, Skip{skip, dm.sys_of});
+        if (!fast) fast = launch_coupling_lp<T>(dm, m, xh, yh, ldh, st, Skip{skip, dm.sys_of}, cfg.nj_coupling);
     if (!fast)
         hipLaunchKernelGGL((k_coupling<T, Acc>), dim3(dm.C, gy), dim3(256), 0, st, dm.k, m, dm.adm_ptr, dm.adm_col, S,
                            dm.swz, xh, yh, ldh);
@@ -418,7 +425,7 @@ hipError_t matmul_typed(const DevMat &dm, int64_t m, double alpha, const double 
             const Skip sk{skip, dm.sys_of};
             const int rb = std::is_same<T, bf16_t>::value ? 1 : 0;
             const unsigned gl8 = 8 * ((dm.L + 7) / 8);
-            if (m > 32)
+            if (cfg.np_leaf ? cfg.np_leaf == 2 : m > 32)
                 hipLaunchKernelGGL((lp::k_leaf_lp<2, T>), dim3(gl8, (unsigned)((m + 63) / 64)), dim3(256), 0, st,
                                    dm.k, m, dm.L, dm.leaves, dm.first, dm.size, dm.perm, (const T *)dm.Vt, dm.vt_off,
                                    yh, ldh, dm.near_ptr, dm.near_col, dm.near_off, (const float *)dm.N, xt, ldxt,
@@ -510,17 +517,25 @@ size_t matmul_ws_bytes(const DevMat &dm, int64_t m) {
     return 2 * hat_bytes<float>(dm, m) + (dm.near_t ? align_up(sizeof(float) * (size_t)dm.n * even_ld(m)) : 0);
 }
 
-hipError_t run_matmul(const DevMat &dm, int64_t m, double alpha, const double *X, int64_t ldx, double beta, double *Y,
-                      int64_t ldy, bool tree_order, char *ws, hipStream_t st, hipEvent_t *ev, const int32_t *skip) {
+hipError_t run_matmul_cfg(const DevMat &dm, const TuneCfg &cfg, int64_t m, double alpha, const double *X, int64_t ldx,
+                          double beta, double *Y, int64_t ldy, bool tree_order, char *ws, hipStream_t st,
+                          hipEvent_t *ev, const int32_t *skip) {
     switch (dm.storage) {
         case H2X_F64:
-            return matmul_typed<double, double, double>(dm, m, alpha, X, ldx, beta, Y, ldy, tree_order, ws, st, ev,
-                                                        skip);
+            return matmul_typed<double, double, double>(dm, cfg, m, alpha, X, ldx, beta, Y, ldy, tree_order, ws, st,
+                                                        ev, skip);
         case H2X_F32:
-            return matmul_typed<float, float, float>(dm, m, alpha, X, ldx, beta, Y, ldy, tree_order, ws, st, ev, skip);
+            return matmul_typed<float, float, float>(dm, cfg, m, alpha, X, ldx, beta, Y, ldy, tree_order, ws, st, ev,
+                                                     skip);
         default:
-            return matmul_typed<bf16_t, float, float>(dm, m, alpha, X, ldx, beta, Y, ldy, tree_order, ws, st, ev, skip);
+            return matmul_typed<bf16_t, float, float>(dm, cfg, m, alpha, X, ldx, beta, Y, ldy, tree_order, ws, st, ev,
+                                                      skip);
     }
+}
+
+hipError_t run_matmul(const DevMat &dm, int64_t m, double alpha, const double *X, int64_t ldx, double beta, double *Y,
+                      int64_t ldy, bool tree_order, char *ws, hipStream_t st, hipEvent_t *ev, const int32_t *skip) {
+    return run_matmul_cfg(dm, dm.tuned[tune_bucket(m)], m, alpha, X, ldx, beta, Y, ldy, tree_order, ws, st, ev, skip);
 }
 
 }  // namespace h2x

@@ -248,12 +248,12 @@ __global__ __launch_bounds__(128) void k_coupling_mfma_small(int k, int64_t m, i
 // it; returns false (launching nothing) otherwise.
 template <typename T, typename Acc>
 bool launch_coupling_fast(const DevMat &dm, int64_t m, const Acc *xh, Acc *yh, int64_t ldh, hipStream_t st,
-                          Skip skip) {
+                          Skip skip, int nj_force) {
     if constexpr (!std::is_same<T, double>::value || !std::is_same<Acc, double>::value) {
         return false;
     } else {
         if (!dm.mc || !dm.cpl_order) return false;
-        const int nj = (int)std::min<int64_t>(4, (m + 15) / 16);
+        const int nj = nj_force ? nj_force : (int)std::min<int64_t>(4, (m + 15) / 16);
         const int mcols = 16 * nj;
         const int32_t rpx = (dm.C + 7) / 8;
         const dim3 grid((unsigned)(8 * rpx), (unsigned)((m + mcols - 1) / mcols));

@@ -1,0 +1,125 @@
+// Autotuner of the matrix-core tile shapes.  For one operator and one column
+// count m it times the product with each candidate tile width per stage (HIP
+// events around every stage), keeps the fastest per stage, and stores the
+// choice in the operator's table for m's bucket; later products with a column
+// count in that bucket use it.  Candidates: 16-column tiles per work-group of
+// the forward leaf and transfer passes (1 .. ceil(m / 16), at most 4), of the
+// coupling (same range), 32-column tiles of the leaf stage (1 or 2).
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "device.hpp"
+
+namespace h2x {
+
+namespace {
+
+// deterministic right-hand sides for the timing runs
+__global__ void k_pattern(int64_t count, double *__restrict__ X) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < count) X[e] = (double)((e * 2654435761ll) % 2001 - 1000) * 1e-3;
+}
+
+}  // namespace
+
+size_t autotune_ws_bytes(const DevMat &dm, int64_t m) {
+    return 2 * align_up((size_t)dm.n * m * sizeof(double)) + matmul_ws_bytes(dm, m);
+}
+
+h2x_status run_autotune(DevMat &dm, int64_t m, char *ws, size_t ws_bytes, hipStream_t st, h2x_tune_info *info) {
+    if (ws_bytes < autotune_ws_bytes(dm, m)) {
+        set_error("h2x_mat_autotune: workspace too small");
+        return H2X_ENOMEM;
+    }
+    const size_t nm = align_up((size_t)dm.n * m * sizeof(double));
+    double *X = (double *)ws, *Y = (double *)(ws + nm);
+    char *mm = ws + 2 * nm;
+    hipEvent_t ev[7] = {};
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < 7 && e == hipSuccess; ++i) e = hipEventCreate(&ev[i]);
+    auto done = [&](hipError_t err) {
+        for (auto &x : ev)
+            if (x) (void)hipEventDestroy(x);
+        if (err != hipSuccess) {
+            set_error(std::string("h2x_mat_autotune: ") + hipGetErrorString(err));
+            return H2X_EHIP;
+        }
+        return H2X_OK;
+    };
+    if (e != hipSuccess) return done(e);
+    const int64_t cnt = dm.n * m;
+    hipLaunchKernelGGL(k_pattern, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, cnt, X);
+
+    constexpr int reps = 3;
+    // mean per-stage times of the product with tile choices c (one untimed run first)
+    auto time_cfg = [&](const TuneCfg &c, double *stage) {
+        hipError_t r = run_matmul_cfg(dm, c, m, 1.0, X, m, 0.0, Y, m, false, mm, st, nullptr, nullptr);
+        for (int i = 0; i < 5; ++i) stage[i] = 0.0;
+        for (int q = 0; q < reps && r == hipSuccess; ++q) {
+            r = run_matmul_cfg(dm, c, m, 1.0, X, m, 0.0, Y, m, false, mm, st, ev, nullptr);
+            if (r == hipSuccess) r = hipEventSynchronize(ev[6]);
+            for (int i = 0; i < 5 && r == hipSuccess; ++i) {
+                float ms = 0.f;
+                r = hipEventElapsedTime(&ms, ev[i], ev[i + 1]);
+                stage[i] += ms / reps;
+            }
+        }
+        return r;
+    };
+    auto total = [](const double *s) { return s[0] + s[1] + s[2] + s[3] + s[4]; };
+
+    const int b = tune_bucket(m);
+    const int max_nj = (int)std::min<int64_t>(4, (m + 15) / 16);
+    double s0[5];
+    dm.tuned[b] = TuneCfg{};
+    e = time_cfg(TuneCfg{}, s0);
+    if (e != hipSuccess) return done(e);
+    TuneCfg best{};
+    double best_t = HUGE_VAL, best_c = HUGE_VAL, best_l = HUGE_VAL;
+    for (int nj = 1; nj <= max_nj && e == hipSuccess; ++nj) {
+        double s[5];
+        TuneCfg c{};
+        c.nj_transfer = (int8_t)nj;
+        e = time_cfg(c, s);
+        const double tt = s[0] + s[1] + s[3];  // forward leaf, forward and backward transfer passes
+        if (e == hipSuccess && tt < best_t) {
+            best_t = tt;
+            best.nj_transfer = (int8_t)nj;
+        }
+        c = TuneCfg{};
+        c.nj_coupling = (int8_t)nj;
+        if (e == hipSuccess) e = time_cfg(c, s);
+        if (e == hipSuccess && s[2] < best_c) {
+            best_c = s[2];
+            best.nj_coupling = (int8_t)nj;
+        }
+    }
+    for (int np = 1; np <= (m > 32 ? 2 : 1) && e == hipSuccess; ++np) {
+        double s[5];
+        TuneCfg c{};
+        c.np_leaf = (int8_t)np;
+        e = time_cfg(c, s);
+        if (e == hipSuccess && s[4] < best_l) {
+            best_l = s[4];
+            best.np_leaf = (int8_t)np;
+        }
+    }
+    if (e != hipSuccess) return done(e);
+    double s1[5];
+    e = time_cfg(best, s1);
+    if (e != hipSuccess) return done(e);
+    // keep the default when the combination is not faster
+    const bool use = total(s1) < total(s0);
+    dm.tuned[b] = use ? best : TuneCfg{};
+    if (info) {
+        info->nj_transfer = dm.tuned[b].nj_transfer;
+        info->nj_coupling = dm.tuned[b].nj_coupling;
+        info->np_leaf = dm.tuned[b].np_leaf;
+        info->ms_default = total(s0);
+        info->ms_tuned = use ? total(s1) : total(s0);
+    }
+    return done(hipSuccess);
+}
+
+}  // namespace h2x

@@ -148,3 +148,20 @@ def test_invalid_arguments_on_gpu():
         h2x.h2_matmul(A, X, out=X)  # X and Y overlap
     with pytest.raises(ValueError):
         h2x.h2_matmul(A, torch.zeros((499, 4), dtype=torch.float64, device="cuda"))
+
+
+@pytest.mark.parametrize("storage,m", [("f64", 32), ("f64", 5), ("f64", 64), ("f32", 40), ("bf16", 20)])
+def test_autotune_keeps_results(storage, m):
+    """Autotuned tile shapes change only the work distribution: the product after
+    tuning is bitwise the product before (fixed summation order per element)."""
+    h2x = _h2x()
+    P = W.sphere_points(8000, 121)
+    A = h2x.H2Matrix(P, storage=storage, ell=0.5, shift=1.0, eta=1.0, leaf=64, p=4)
+    X = torch.from_numpy(W.rhs(8000, m, 122)).cuda()
+    before = h2x.h2_matmul(A, X).clone()
+    info = A.autotune(m)
+    after = h2x.h2_matmul(A, X)
+    torch.cuda.synchronize()
+    print(f"{storage} m={m}: {info}")
+    assert info["ms_tuned"] <= info["ms_default"] * 1.0001
+    assert torch.equal(before, after)

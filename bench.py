@@ -164,6 +164,20 @@ def precision_report(args, torch, h2x, W):
                                        "inner_iters": info.iters, "status": info.status, "true_relres": res,
                                        "inner_rtol": inner}
         log(f"[precision] refined {prec}: {out[f'refine_{prec}_1e-10']}")
+    for prec in ("f32", "bf16"):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        log(f"[precision] CG with {prec} iterations and FP64 residual replacement")
+        Xr, info = h2x.block_cg_mixed(ops["f64"], ops[prec], B, rtol=1e-10, delta=0.1, max_iter=args.max_cg_iter,
+                                      graph=True)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        R = torch.empty_like(B)
+        h2x.h2_matmul(ops["f64"], Xr, out=R)
+        res = ((B - R).norm(dim=0) / B.norm(dim=0)).max().item()
+        out[f"mixed_{prec}_1e-10"] = {"time_s": round(dt, 3), "iters": info.iters, "replacements": info.outer_iters,
+                                      "status": info.status, "true_relres": res}
+        log(f"[precision] mixed {prec}: {out[f'mixed_{prec}_1e-10']}")
     print(json.dumps(out), flush=True)
 
 

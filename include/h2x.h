@@ -233,6 +233,23 @@ h2x_status h2x_block_cg_refine(const h2x_mat *A, const h2x_mat *A_lo, const h2x_
                                int64_t ldx, void *dev_ws, size_t ws_bytes, h2x_cg_info *info,
                                void *hip_stream);
 
+/* Mixed precision in one CG run (residual replacement, van der Vorst and Ye,
+ * "Residual replacement strategies for Krylov subspace iterative methods for the
+ * convergence of true residuals", 2000): every iteration is block CG
+ * (H2X_CG_INDEPENDENT) with the low-precision operator A_lo; after an iteration in
+ * which an open column's recursive residual has fallen below delta times its
+ * largest value since the last replacement (checked every prm->check_every
+ * iterations), and whenever every column looks converged, the residual is
+ * recomputed as R = B - A X with the FP64 operator A and the iteration continues
+ * from it with the same search directions.  The solve stops when every column
+ * meets prm->rtol on the recomputed residual.  info->outer_iters is the number
+ * of replacements, info->col_relres the final true residuals.  A and A_lo: one
+ * plan with one system; A stored in FP64.  0 < delta < 1 (0.1 is usual).  Blocking. */
+size_t h2x_block_cg_mixed_workspace_bytes(const h2x_mat *A, const h2x_mat *A_lo, int64_t m);
+h2x_status h2x_block_cg_mixed(const h2x_mat *A, const h2x_mat *A_lo, const h2x_cg_params *prm, double delta,
+                              int64_t m, const double *B, int64_t ldb, double *X, int64_t ldx, void *dev_ws,
+                              size_t ws_bytes, h2x_cg_info *info, void *hip_stream);
+
 /* ---- tuning ----------------------------------------------------------------- */
 /* Tile shapes of the matrix-core kernels: columns per work-group of the forward
  * leaf and transfer passes (16 * nj_transfer), of the coupling (16 * nj_coupling)

@@ -67,6 +67,8 @@ def _load():
     lib.orc_block_cg_lowp.argtypes = [P, C.c_int, I64, P, P, D, I64, P, P]
     lib.orc_refine_cg.restype = I64
     lib.orc_refine_cg.argtypes = [P, C.c_int, I64, P, P, D, D, I64, I64, P]
+    lib.orc_block_cg_mixed.restype = I64
+    lib.orc_block_cg_mixed.argtypes = [P, C.c_int, I64, P, P, D, D, I64, I64, P]
     lib.orc_round_bf16_array.argtypes = [P, P, I64]
     lib.orc_matmul_adjoint.argtypes = [P, I64, D, P, D, P]
     lib.orc_grad.argtypes = [P, I64, P, P, P, P, P]
@@ -221,6 +223,17 @@ class OracleH2:
         outer = _load().orc_refine_cg(self._h, pr, B.shape[1], _ptr(B), _ptr(X), float(rtol), float(inner_rtol),
                                       int(max_outer), int(max_inner), _ptr(tot))
         return X, dict(outer=int(outer), inner=int(tot[0]))
+
+    def block_cg_mixed(self, B, prec, rtol=1e-10, delta=0.1, max_iter=10000, check=4):
+        """Mixed precision in one CG run: iterations with the emulated low-precision
+        operator, the residual recomputed with the FP64 operator (residual replacement)."""
+        pr = {"f32": 1, "bf16": 2}[prec]
+        B = np.ascontiguousarray(B, dtype=np.float64)
+        X = np.zeros_like(B)
+        rep = np.zeros(1, np.int64)
+        it = _load().orc_block_cg_mixed(self._h, pr, B.shape[1], _ptr(B), _ptr(X), float(rtol), float(delta),
+                                        int(max_iter), int(check), _ptr(rep))
+        return X, dict(iters=int(it), replacements=int(rep[0]))
 
     def matmul_adjoint(self, X, alpha=1.0, beta=0.0, Y=None) -> np.ndarray:
         """Y <- beta Y + alpha A^T X through the column lists (transposed blocks)."""

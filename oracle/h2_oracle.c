@@ -1062,6 +1062,90 @@ int64_t orc_block_cg_lowp(const orc_h2 *h, int prec, int64_t m, const double *B,
     return orc_block_cg_op(h, orc_op_lowp, prec, m, B, X, rtol, max_iter, 0, col_iters, status);
 }
 
+/*
+ * Mixed precision in one CG run by residual replacement (van der Vorst and Ye,
+ * 2000): the iterations are the block CG above with the emulated low-precision
+ * operator; the recursive residual of every column is watched, and when an open
+ * column's norm has dropped below delta times its largest value since the last
+ * replacement -- or every column looks converged -- the residual is recomputed
+ * as B - A X with the FP64 operator and the iteration continues from it with
+ * the same search directions.  The decision is taken every `check` iterations
+ * (the GPU reads its state at that cadence); iterations after every column has
+ * converged and before the next check do nothing.  Stops when every column meets
+ * rtol on a recomputed residual.  Returns the iterations performed;
+ * *replacements receives the number of recomputations.
+ */
+int64_t orc_block_cg_mixed(const orc_h2 *h, int prec, int64_t m, const double *B, double *X, double rtol,
+                           double delta, int64_t max_iter, int64_t check, int64_t *replacements) {
+    const int64_t n = h->n;
+    double *R = malloc(sizeof(double) * n * m), *P = malloc(sizeof(double) * n * m);
+    double *Ap = malloc(sizeof(double) * n * m);
+    double *bn = malloc(sizeof(double) * m), *rmax = malloc(sizeof(double) * m);
+    int *frozen = calloc(m, sizeof(int)), *conv = calloc(m, sizeof(int));
+    if (check < 1) check = 1;
+    /* true residual and the quantities that restart from it */
+    #define ORC_REPLACE()                                                        \
+        do {                                                                     \
+            memcpy(R, B, sizeof(double) * n * m);                                \
+            orc_matmul(h, m, -1.0, X, 1.0, R);                                   \
+            for (int64_t j = 0; j < m; ++j) {                                    \
+                rmax[j] = sqrt(orc_dot_col(n, m, R, R, j));                      \
+                conv[j] = rmax[j] <= rtol * bn[j];                               \
+            }                                                                    \
+        } while (0)
+    for (int64_t j = 0; j < m; ++j) bn[j] = sqrt(orc_dot_col(n, m, B, B, j));
+    ORC_REPLACE();
+    memcpy(P, R, sizeof(double) * n * m);
+    int64_t it = 0, done_iters = 0, rep = 0, last_rep = 0;
+    int want = 0;
+    for (;;) {
+        if (it % check == 0 || it >= max_iter) {
+            int all = 1;
+            for (int64_t j = 0; j < m; ++j) if (!conv[j] && !frozen[j]) all = 0;
+            if (it != last_rep && (want || all || it >= max_iter)) {
+                ORC_REPLACE();
+                want = 0;
+                ++rep;
+                last_rep = it;
+                all = 1;
+                for (int64_t j = 0; j < m; ++j) if (!conv[j] && !frozen[j]) all = 0;
+            }
+            if (all || it >= max_iter) break;
+        }
+        int all = 1;
+        for (int64_t j = 0; j < m; ++j) if (!conv[j] && !frozen[j]) all = 0;
+        if (!all) {
+            orc_op_lowp(h, prec, m, 1.0, P, 0.0, Ap);
+            for (int64_t j = 0; j < m; ++j) {
+                if (frozen[j]) continue;
+                if (orc_dot_col(n, m, R, R, j) == 0.0) continue;
+                double beta = orc_dot_col(n, m, P, Ap, j);
+                double alpha = orc_dot_col(n, m, P, R, j) / beta;
+                if (!(beta > 0.0) || !isfinite(alpha)) { frozen[j] = 1; continue; }
+                for (int64_t i = 0; i < n; ++i) {
+                    X[i * m + j] += alpha * P[i * m + j];
+                    R[i * m + j] -= alpha * Ap[i * m + j];
+                }
+                double gamma = orc_dot_col(n, m, Ap, R, j) / beta;
+                for (int64_t i = 0; i < n; ++i) P[i * m + j] = R[i * m + j] - gamma * P[i * m + j];
+            }
+            for (int64_t j = 0; j < m; ++j) {
+                double rn = sqrt(orc_dot_col(n, m, R, R, j));
+                conv[j] = rn <= rtol * bn[j];
+                if (conv[j] || frozen[j]) continue;
+                if (rn > rmax[j]) rmax[j] = rn;
+                if (rn < delta * rmax[j]) want = 1;
+            }
+            ++done_iters;
+        }
+        ++it;
+    }
+    #undef ORC_REPLACE
+    *replacements = rep;
+    free(R); free(P); free(Ap); free(bn); free(rmax); free(frozen); free(conv);
+    return done_iters;
+}
+
 int64_t orc_refine_cg(const orc_h2 *h, int prec, int64_t m, const double *B, double *X, double rtol,
                       double inner_rtol, int64_t max_outer, int64_t max_inner, int64_t *inner_total) {
     const int64_t n = h->n;

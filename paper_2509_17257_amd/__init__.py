@@ -15,7 +15,7 @@ from dataclasses import dataclass
 import numpy as np
 
 __all__ = ["Plan", "H2Matrix", "Batch", "h2_matmul", "h2_matmul_adjoint", "h2_grad", "block_cg_solve",
-           "block_cg_refine", "batch_matmul", "batch_block_cg_solve", "library_path", "load_library", "F64", "F32",
+           "block_cg_refine", "block_cg_mixed", "batch_matmul", "batch_block_cg_solve", "library_path", "load_library", "F64", "F32",
            "BF16", "TREE_ORDER"]
 
 F64, F32, BF16 = 0, 1, 2
@@ -111,6 +111,9 @@ def load_library():
         "h2x_mat_set_ell": (C.c_int, [P, D, P]),
         "h2x_mat_coupling": (C.c_int, [P, P, P]),
         "h2x_mat_set_coupling": (C.c_int, [P, P, P]),
+        "h2x_block_cg_mixed_workspace_bytes": (SZ, [P, P, I64]),
+        "h2x_block_cg_mixed": (C.c_int, [P, P, C.POINTER(_CgParams), D, I64, P, I64, P, I64, P, SZ,
+                                         C.POINTER(_CgInfo), P]),
         "h2x_mat_autotune_workspace_bytes": (SZ, [P, I64]),
         "h2x_mat_autotune": (C.c_int, [P, I64, P, SZ, P, C.POINTER(_TuneInfo)]),
         "h2x_last_error": (C.c_char_p, []),
@@ -435,6 +438,28 @@ def block_cg_refine(A: H2Matrix, A_lo: H2Matrix, B, *, rtol=1e-10, inner_rtol=1e
                                    C.c_void_p(B.data_ptr()), B.stride(0), C.c_void_p(X.data_ptr()), X.stride(0),
                                    C.c_void_p(ws.data_ptr()), ws.numel(), C.byref(info), _stream(torch, B.device)),
            "h2x_block_cg_refine")
+    return X, _info(info, rel, its, sts, sys, 1, m)
+
+
+def block_cg_mixed(A: H2Matrix, A_lo: H2Matrix, B, *, rtol=1e-10, delta=0.1, max_iter=10000, check_every=4,
+                   graph=False):
+    """Mixed precision in one CG run (h2x_block_cg_mixed): iterations with the
+    low-precision A_lo, the residual recomputed with the FP64 A whenever it has
+    dropped by delta since the last recomputation and before stopping.  A and A_lo
+    share one Plan.  Returns (X, CgInfo); info.outer_iters counts recomputations."""
+    import torch
+    if B.dtype != torch.float64 or B.device.type != "cuda" or B.dim() != 2 or B.stride(1) != 1:
+        raise ValueError("B must be a row-major (n, m) float64 CUDA tensor")
+    n, m = B.shape
+    X = torch.zeros_like(B)
+    lib = load_library()
+    nb = lib.h2x_block_cg_mixed_workspace_bytes(A._h, A_lo._h, m)
+    ws = torch.empty(max(nb, 256), dtype=torch.uint8, device=B.device)
+    info, rel, its, sts, sys = _new_info(m)
+    prm = _CgParams(float(rtol), int(max_iter), 0, int(check_every), CG_INDEPENDENT, int(bool(graph)))
+    _check(lib.h2x_block_cg_mixed(A._h, A_lo._h, C.byref(prm), float(delta), m, C.c_void_p(B.data_ptr()),
+                                  B.stride(0), C.c_void_p(X.data_ptr()), X.stride(0), C.c_void_p(ws.data_ptr()),
+                                  ws.numel(), C.byref(info), _stream(torch, B.device)), "h2x_block_cg_mixed")
     return X, _info(info, rel, its, sts, sys, 1, m)
 
 

@@ -309,6 +309,29 @@ h2x_status h2x_block_cg(const h2x_mat *A, const h2x_cg_params *prm, int64_t m, c
     return run_block_cg(A->dm, *prm, m, B, ldb, X, ldx, (char *)dev_ws, ws_bytes, info, (hipStream_t)hip_stream);
 }
 
+size_t h2x_block_cg_mixed_workspace_bytes(const h2x_mat *A, const h2x_mat *A_lo, int64_t m) {
+    if (!A || !A_lo || m < 1) return 0;
+    return mixed_ws_bytes(A->dm, A_lo->dm, m);
+}
+
+h2x_status h2x_block_cg_mixed(const h2x_mat *A, const h2x_mat *A_lo, const h2x_cg_params *prm, double delta,
+                              int64_t m, const double *B, int64_t ldb, double *X, int64_t ldx, void *dev_ws,
+                              size_t ws_bytes, h2x_cg_info *info, void *hip_stream) {
+    if (!A || !A_lo || !prm || !B || !X || !dev_ws) return fail(H2X_EINVAL, "h2x_block_cg_mixed: NULL argument");
+    if (A->plan != A_lo->plan) return fail(H2X_EINVAL, "h2x_block_cg_mixed: A and A_lo must share one plan");
+    if (A->dm.storage != H2X_F64) return fail(H2X_EINVAL, "h2x_block_cg_mixed: A must be stored in FP64");
+    if (A->dm.plan->nsys() > 1) return fail(H2X_EUNSUPPORTED, "h2x_block_cg_mixed: not for merged plans");
+    if (m < 1 || ldb < m || ldx < m) return fail(H2X_EINVAL, "h2x_block_cg_mixed: need m >= 1, ldb >= m, ldx >= m");
+    if (!(prm->rtol >= 0.0) || prm->max_iter < 0 || !(delta > 0.0 && delta < 1.0))
+        return fail(H2X_EINVAL, "h2x_block_cg_mixed: bad rtol, max_iter or delta");
+    if (prm->variant != H2X_CG_INDEPENDENT)
+        return fail(H2X_EUNSUPPORTED, "h2x_block_cg_mixed: only the independent variant");
+    if (!aligned(dev_ws)) return fail(H2X_EINVAL, "h2x_block_cg_mixed: workspace not 256-byte aligned");
+    if (ws_bytes < mixed_ws_bytes(A->dm, A_lo->dm, m)) return fail(H2X_ENOMEM, "h2x_block_cg_mixed: workspace too small");
+    return run_block_cg_mixed(A->dm, A_lo->dm, *prm, delta, m, B, ldb, X, ldx, (char *)dev_ws, ws_bytes, info,
+                              (hipStream_t)hip_stream);
+}
+
 size_t h2x_mat_autotune_workspace_bytes(const h2x_mat *A, int64_t m) {
     if (!A || m < 1) return 0;
     return autotune_ws_bytes(A->dm, m);

@@ -271,6 +271,48 @@ __global__ __launch_bounds__(256) void k_cg_update_p(int64_t m, Segs sg, const d
         P[i * m + j] = R[i * m + j] - g * P[i * m + j];
 }
 
+// Residual replacement (mixed precision, one system): after every iteration the
+// largest residual norm since the last replacement is tracked per column, and a
+// replacement is requested (state->pad) once an open column's recursive residual
+// has dropped below delta times that maximum.
+__global__ void k_rel_track(int64_t m, double delta, CgState *state, CgCols cols, double *rmax) {
+    __shared__ int want;
+    if (state->skip) return;
+    if (threadIdx.x == 0) want = 0;
+    __syncthreads();
+    for (int64_t j = threadIdx.x; j < m; j += blockDim.x) {
+        if (cols.conv[j] || cols.frozen[j]) continue;
+        const double rn = sqrt(cols.rr[j]);
+        rmax[j] = fmax(rmax[j], rn);
+        if (rn < delta * rmax[j]) atomicOr(&want, 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && want) state->pad = 1;
+}
+
+// The residual R was just recomputed as B - A X with the FP64 operator; the
+// first pair of part holds its squared column norms (the second pair is not
+// used).  Recursive norms, maxima and convergence restart from the true
+// residual; the system stops when every column has converged (or broken down).
+__global__ void k_rel_replace(int64_t m, int nblk, const double *part, double rtol, CgState *state, CgCols cols,
+                              Segs sg, double *rmax) {
+    const bool open = for_columns(m, nblk, part, sg, 0, [&](int64_t, int64_t e, double rr, double) {
+        cols.rr[e] = rr;
+        rmax[e] = sqrt(rr);
+        const int c = sqrt(rr) <= rtol * cols.bnorm[e];
+        cols.conv[e] = c;
+        if (c && cols.first_conv[e] < 0) cols.first_conv[e] = state->iter;
+        return !c && !cols.frozen[e];
+    });
+    if (threadIdx.x == 0) {
+        sg.seg_done[0] = open ? 0 : 1;
+        sg.seg_iters[0] = state->iter;
+        state->all_conv = open ? 0 : 1;
+        state->skip = 0;
+        state->pad = 0;
+    }
+}
+
 // Rows of the concatenated systems: operator j owns rows [row0[j], row0[j] + n_j)
 // (its own original or tree order); its systems follow in order.
 struct Layout {
@@ -311,7 +353,7 @@ Layout make_layout(const DevMat *const *mats, int32_t nmat, int64_t m) {
 }
 
 struct CgWs {
-    double *Bt, *Xt, *R, *P, *AP, *part;
+    double *Bt, *Xt, *R, *P, *AP, *part, *rmax;
     CgState *state;
     CgCols cols;
     int64_t *blk_r0;
@@ -336,6 +378,7 @@ CgWs cg_layout(const Layout &L, int64_t m, char *base) {
     w.P = (double *)carve(nm);
     w.AP = (double *)carve(nm);
     w.part = (double *)carve(2 * (size_t)L.nblk * m * sizeof(double));
+    w.rmax = (double *)carve(sm * sizeof(double));
     w.state = (CgState *)carve(sizeof(CgState));
     double **dcols[5] = {&w.cols.bnorm, &w.cols.rr, &w.cols.beta, &w.cols.alpha, &w.cols.gamma};
     for (auto d : dcols) *d = (double *)carve(sm * sizeof(double));
@@ -494,8 +537,9 @@ h2x_status run_refine(const DevMat &hi, const DevMat &lo, const h2x_cg_params &i
 
 h2x_status run_block_cg_batch(const DevMat *const *mats, int32_t nmat, const h2x_cg_params &prm, int64_t m,
                               const double *B, int64_t ldb, double *X, int64_t ldx, char *ws, size_t ws_bytes,
-                              h2x_cg_info *info, hipStream_t st) {
-    const Layout L = make_layout(mats, nmat, m);
+                              h2x_cg_info *info, hipStream_t st, const DevMat *hi, double delta) {
+    Layout L = make_layout(mats, nmat, m);
+    if (hi) L.mm_bytes = std::max(L.mm_bytes, matmul_ws_bytes(*hi, m));
     CgWs w = cg_layout(L, m, ws);
     if (ws_bytes < w.bytes) {
         set_error("h2x_block_cg: workspace too small");
@@ -559,6 +603,18 @@ h2x_status run_block_cg_batch(const DevMat *const *mats, int32_t nmat, const h2x
                            (const CgState *)w.state, w.cols, sg);
         hipLaunchKernelGGL(k_cg_state, dim3(1), dim3(256), 0, s, 0, w.state, sg);
         hipLaunchKernelGGL(k_cg_update_p, gd, dim3(256), 0, s, m, sg, w.R, w.P, (const CgState *)w.state, w.cols);
+        if (hi) hipLaunchKernelGGL(k_rel_track, dim3(1), dim3(256), 0, s, m, delta, w.state, w.cols, w.rmax);
+        return hipGetLastError();
+    };
+    // mixed precision: R = B - A X with the FP64 operator, recursive quantities restart from it
+    auto replace = [&](hipStream_t s) {
+        hipLaunchKernelGGL(k_copy, dim3(g1), dim3(256), 0, s, nm, (const double *)w.Bt, w.R);
+        hipError_t ee = run_matmul(*hi, m, -1.0, w.Xt, m, 1.0, w.R, m, true, w.mm, s);
+        if (ee != hipSuccess) return ee;
+        hipLaunchKernelGGL(k_sdots, gd, dim3(256), 0, s, m, nblk, sg, w.R, w.R, (const double *)nullptr,
+                           (const double *)nullptr, w.part, (const CgState *)nullptr);
+        hipLaunchKernelGGL(k_rel_replace, dim3(1), dim3(256), 0, s, m, nblk, (const double *)w.part, prm.rtol,
+                           w.state, w.cols, sg, w.rmax);
         return hipGetLastError();
     };
 
@@ -571,15 +627,21 @@ h2x_status run_block_cg_batch(const DevMat *const *mats, int32_t nmat, const h2x
         hipLaunchKernelGGL(k_gather_rows, dim3(gq), dim3(256), 0, st, dm.n, m, dm.perm, (const double *)X + r * ldx,
                            ldx, w.Xt + r * m, m);
     }
-    // R = B - A X0, P = R
+    // R = B - A X0 (with the FP64 operator in mixed precision), P = R
     hipLaunchKernelGGL(k_copy, dim3(g1), dim3(256), 0, st, nm, w.Bt, w.R);
-    e = product(w.Xt, w.R, -1.0, 1.0, false, st);
+    e = hi ? run_matmul(*hi, m, -1.0, w.Xt, m, 1.0, w.R, m, true, w.mm, st) : product(w.Xt, w.R, -1.0, 1.0, false, st);
     if (e != hipSuccess) return fail(e);
     hipLaunchKernelGGL(k_copy, dim3(g1), dim3(256), 0, st, nm, w.R, w.P);
     hipLaunchKernelGGL(k_sdots, gd, dim3(256), 0, st, m, nblk, sg, w.Bt, w.Bt, w.R, w.R, w.part,
                        (const CgState *)nullptr);
     hipLaunchKernelGGL(k_cg_init, dim3(L.nseg), dim3(256), 0, st, m, nblk, w.part, prm.rtol, w.cols, sg);
     hipLaunchKernelGGL(k_cg_state, dim3(1), dim3(256), 0, st, 1, w.state, sg);
+    if (hi) {
+        hipLaunchKernelGGL(k_sdots, gd, dim3(256), 0, st, m, nblk, sg, w.R, w.R, (const double *)nullptr,
+                           (const double *)nullptr, w.part, (const CgState *)nullptr);
+        hipLaunchKernelGGL(k_rel_replace, dim3(1), dim3(256), 0, st, m, nblk, (const double *)w.part, prm.rtol,
+                           w.state, w.cols, sg, w.rmax);
+    }
 
     const int check = prm.check_every > 0 ? prm.check_every : 1;
     hipStream_t run = st;
@@ -600,10 +662,23 @@ h2x_status run_block_cg_batch(const DevMat *const *mats, int32_t nmat, const h2x
         run = cs;
     }
     CgState hs{};
+    int32_t replaced = 0, rep_it = 0;
+    auto read_state = [&]() {
+        hipError_t ee = hipMemcpyAsync(&hs, w.state, sizeof(CgState), hipMemcpyDeviceToHost, run);
+        if (ee == hipSuccess) ee = hipStreamSynchronize(run);
+        return ee;
+    };
     for (int32_t it = 0;;) {
-        e = hipMemcpyAsync(&hs, w.state, sizeof(CgState), hipMemcpyDeviceToHost, run);
-        if (e == hipSuccess) e = hipStreamSynchronize(run);
+        e = read_state();
         if (e != hipSuccess) return fail(e);
+        // mixed precision: replace the residual when asked, and before stopping
+        if (hi && it != rep_it && (hs.pad || hs.all_conv || it >= prm.max_iter)) {
+            e = replace(run);
+            if (e == hipSuccess) e = read_state();
+            if (e != hipSuccess) return fail(e);
+            ++replaced;
+            rep_it = it;
+        }
         if (hs.all_conv || it >= prm.max_iter) break;
         if (exec && it + check <= prm.max_iter) {
             e = hipGraphLaunch(exec, run);
@@ -649,7 +724,7 @@ h2x_status run_block_cg_batch(const DevMat *const *mats, int32_t nmat, const h2x
     if (info) {
         info->iters = hs.iter;
         info->status = status;
-        info->outer_iters = 0;
+        info->outer_iters = replaced;
         for (size_t j = 0; j < sm; ++j) {
             const int32_t cap = sd[j / m] ? si[j / m] : hs.iter;
             if (info->col_relres) info->col_relres[j] = bn[j] > 0 ? std::sqrt(rr[j]) / bn[j] : std::sqrt(rr[j]);
@@ -665,7 +740,21 @@ h2x_status run_block_cg_batch(const DevMat *const *mats, int32_t nmat, const h2x
 h2x_status run_block_cg(const DevMat &dm, const h2x_cg_params &prm, int64_t m, const double *B, int64_t ldb,
                         double *X, int64_t ldx, char *ws, size_t ws_bytes, h2x_cg_info *info, hipStream_t st) {
     const DevMat *p = &dm;
-    return run_block_cg_batch(&p, 1, prm, m, B, ldb, X, ldx, ws, ws_bytes, info, st);
+    return run_block_cg_batch(&p, 1, prm, m, B, ldb, X, ldx, ws, ws_bytes, info, st, nullptr, 0.0);
+}
+
+size_t mixed_ws_bytes(const DevMat &hi, const DevMat &lo, int64_t m) {
+    const DevMat *p = &lo;
+    Layout L = make_layout(&p, 1, m);
+    L.mm_bytes = std::max(L.mm_bytes, matmul_ws_bytes(hi, m));
+    return cg_layout(L, m, nullptr).bytes;
+}
+
+h2x_status run_block_cg_mixed(const DevMat &hi, const DevMat &lo, const h2x_cg_params &prm, double delta, int64_t m,
+                              const double *B, int64_t ldb, double *X, int64_t ldx, char *ws, size_t ws_bytes,
+                              h2x_cg_info *info, hipStream_t st) {
+    const DevMat *p = &lo;
+    return run_block_cg_batch(&p, 1, prm, m, B, ldb, X, ldx, ws, ws_bytes, info, st, &hi, delta);
 }
 
 }  // namespace h2x

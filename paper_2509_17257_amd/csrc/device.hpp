@@ -107,7 +107,13 @@ h2x_status run_autotune(DevMat &dm, int64_t m, char *ws, size_t ws_bytes, hipStr
 
 size_t cg_ws_bytes(const DevMat &dm, int64_t m);
 size_t cg_batch_ws_bytes(const DevMat *const *mats, int32_t nmat, int64_t m);
+// hi (optional, one operator and one system only): mixed precision with residual
+// replacement -- iterations use mats[0], the residual is recomputed with hi
 h2x_status run_block_cg_batch(const DevMat *const *mats, int32_t nmat, const h2x_cg_params &prm, int64_t m,
+                              const double *B, int64_t ldb, double *X, int64_t ldx, char *ws, size_t ws_bytes,
+                              h2x_cg_info *info, hipStream_t st, const DevMat *hi = nullptr, double delta = 0.0);
+size_t mixed_ws_bytes(const DevMat &hi, const DevMat &lo, int64_t m);
+h2x_status run_block_cg_mixed(const DevMat &hi, const DevMat &lo, const h2x_cg_params &prm, double delta, int64_t m,
                               const double *B, int64_t ldb, double *X, int64_t ldx, char *ws, size_t ws_bytes,
                               h2x_cg_info *info, hipStream_t st);
 h2x_status run_block_cg(const DevMat &dm, const h2x_cg_params &prm, int64_t m, const double *B, int64_t ldb,

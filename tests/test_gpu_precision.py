@@ -67,3 +67,31 @@ def test_refinement(prec, inner):
     assert np.all(info.col_relres <= 1e-10)
     Xf, _ = o.block_cg(B, rtol=1e-12)
     assert _colrel(X, Xf) <= 1e-6
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+def test_mixed_cg_residual_replacement(prec):
+    """One CG run with the low-precision operator and FP64 residual replacement:
+    FP64 true residual 1e-10 (oracle product), iteration count near the oracle's
+    run of the same method on its emulated operator, graph replay bitwise equal."""
+    import paper_2509_17257_amd as h2x
+    w = W.SMALL
+    P = w.points()
+    o = oracle.OracleH2(P, **w.params())
+    plan = h2x.Plan(P, **w.params())
+    A = h2x.H2Matrix(plan, storage="f64")
+    A_lo = h2x.H2Matrix(plan, storage=prec)
+    B = w.rhs()
+    Bd = torch.from_numpy(B).cuda()
+    X, info = h2x.block_cg_mixed(A, A_lo, Bd, rtol=1e-10)
+    Xg, ig = h2x.block_cg_mixed(A, A_lo, Bd, rtol=1e-10, graph=True)
+    assert torch.equal(X, Xg) and ig.iters == info.iters
+    X = X.cpu().numpy()
+    res = np.linalg.norm(B - o.matmul(X), axis=0) / np.linalg.norm(B, axis=0)
+    _, oi = o.block_cg_mixed(B, prec, rtol=1e-10)
+    _, i64 = o.block_cg(B, rtol=1e-10)
+    print(f"mixed {prec}: gpu {info.iters} it / {info.outer_iters} replacements, oracle {oi['iters']} it / "
+          f"{oi['replacements']}, FP64 CG {i64['iters']} it, true residual {res.max():.2e}")
+    assert info.status == 0 and res.max() <= 1.5e-10
+    assert np.all(info.col_relres <= 1e-10)
+    assert abs(info.iters - oi["iters"]) <= max(5, 0.1 * oi["iters"])

@@ -8,6 +8,9 @@
   rounded operand is exact in that type (constant kernel, integer right-hand sides).
 * Refinement reaches an FP64 true residual of 1e-10 and agrees with the FP64
   block-CG solution to within the condition number times the tolerance.
+* CG with residual replacement (iterations with the emulated operator, residual
+  recomputed in FP64) meets 1e-10 on the true residual, agrees with a dense
+  Cholesky solve within kappa * rtol, and solves sigma I + 1 1^T in a few steps.
 """
 import numpy as np
 import pytest
@@ -73,3 +76,40 @@ def test_refinement_reaches_fp64_accuracy(h):
         assert res.max() <= 1e-10, (prec, info, res)
         assert _colrel(X, Xf) <= kappa * 2e-10
         assert info["outer"] >= 2
+
+
+# ---- mixed precision in one CG run (residual replacement) ----
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+def test_mixed_cg_reaches_fp64_accuracy(h, prec):
+    """Iterations with the low-precision operator, residual recomputed in FP64: the
+    solve meets 1e-10 on the FP64 true residual and agrees with a dense Cholesky
+    solve of the assembled H^2 matrix within the condition number times rtol."""
+    import scipy.linalg as sla
+    B = W.rhs(h.n, 3, 191)
+    X, info = h.block_cg_mixed(B, prec, rtol=1e-10)
+    res = np.linalg.norm(B - h.matmul(X), axis=0) / np.linalg.norm(B, axis=0)
+    assert res.max() <= 1e-10
+    assert info["replacements"] >= 1
+    A = h.dense()
+    ev = np.linalg.eigvalsh(A)
+    Xd = sla.cho_solve(sla.cho_factor(A), B)
+    assert _colrel(X, Xd) <= (ev[-1] / ev[0]) * 1e-10
+    # a replacement restarts nothing: the iteration count stays near the FP64 one
+    _, i64 = h.block_cg(B, rtol=1e-10)
+    assert info["iters"] <= 3 * i64["iters"]
+
+
+def test_mixed_cg_constant_kernel_closed_form():
+    """A = sigma I + 1 1^T has two eigenvalues, so CG on it converges in two steps.
+    With the FP32 operator (relative error 7e-7 here, kappa ~800) a replacement
+    cycle cuts the true residual by about kappa times that error, so the
+    Sherman-Morrison solution is reached to 1e-10 within a few short cycles (13
+    iterations and 7 replacements with a check every iteration)."""
+    n, sigma = 700, 0.9
+    o = oracle.OracleH2(W.sphere_points(n, 192), kernel="const", leaf=32, p=2, shift=sigma)
+    B = W.rhs(n, 2, 193)
+    X, info = o.block_cg_mixed(B, "f32", rtol=1e-11, check=1)
+    Xcf = (B - B.sum(0, keepdims=True) / (sigma + n)) / sigma
+    assert _colrel(X, Xcf) <= 1e-10
+    assert info["iters"] <= 20 and info["replacements"] <= 10

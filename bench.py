@@ -140,6 +140,9 @@ def precision_report(args, torch, h2x, W):
         out[prec] = rec
         log(f"[precision] {prec}: {rec}")
     B = X
+    if not args.cg:
+        print(json.dumps(out), flush=True)
+        return
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     Xs, info = h2x.block_cg_solve(ops["f64"], B, rtol=1e-8, max_iter=args.max_cg_iter)
@@ -297,7 +300,7 @@ def batch_report(args, torch, h2x, W):
     ms_loop = timed(loop, max(3, reps // 4))
     out["per_system_loop"] = {"ms": round(ms_loop, 4), "alg_gbs": round(alg / (ms_loop * 1e-3) / 1e9, 1)}
     log(f"[batch] product: batched {ms:.3f} ms, per-system loop {ms_loop:.3f} ms")
-    for graph in (True, False):
+    for graph in ((True, False) if args.cg else ()):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         X, info = h2x.batch_block_cg_solve(batch, B, rtol=1e-8, max_iter=args.max_cg_iter, graph=graph)
@@ -310,12 +313,13 @@ def batch_report(args, torch, h2x, W):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     tot = 0
-    for A, b in zip(mats, Xs):
+    for A, b in zip(mats, Xs if args.cg else ()):
         _, info = h2x.block_cg_solve(A, b, rtol=1e-8, max_iter=args.max_cg_iter)
         tot += info.iters
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    out["per_system_cg_loop"] = {"time_s": round(dt, 3), "iters_total": tot}
+    if args.cg:
+        out["per_system_cg_loop"] = {"time_s": round(dt, 3), "iters_total": tot}
     log(f"[batch] per-system CG loop: {dt:.3f} s")
     del mats
     b32 = h2x.Batch(list(zip(pts, prms)), storage="f32", device=dev)

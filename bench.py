@@ -359,7 +359,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU sharding is described in DESIGN.md but not built", file=sys.stderr)
+              "sharding across GPUs is designed but not built", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -51,7 +51,7 @@ typedef enum {
     H2X_EHIP = 3,         /* a HIP runtime call failed */
     H2X_EBREAKDOWN = 4,   /* CG breakdown (p^T A p <= 0 or non-finite) in >= 1 column */
     H2X_ENOCONV = 5,      /* CG reached max_iter with >= 1 unconverged column */
-    H2X_EUNSUPPORTED = 6  /* option not supported by this build */
+    H2X_EUNSUPPORTED = 6  /* option not supported by this library version */
 } h2x_status;
 
 /* Storage / compute precision of the H^2 operator (V, E, S; near field see h2x_mat_create). */
@@ -215,7 +215,7 @@ h2x_status h2x_block_cg(const h2x_mat *A, const h2x_cg_params *prm, int64_t m, c
                         h2x_cg_info *info, void *hip_stream);
 
 /* Mixed precision: FP64 iterative refinement around block CG with a
- * low-precision operator (spec precision pattern; the paper itself is FP64).
+ * low-precision operator (the paper itself computes in FP64 throughout).
  * A: the FP64 operator (H2X_F64 storage); A_lo: the same plan stored in FP32 or
  * BF16 (its products accumulate in FP32).  Outer step: R = B - A X in FP64; stop
  * when every column has ||R_i|| <= rtol ||B_i||; otherwise solve A_lo D = R with

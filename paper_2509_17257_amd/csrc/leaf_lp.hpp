@@ -64,7 +64,31 @@ __global__ __launch_bounds__(256, 2) void k_leaf_lp(int k, int64_t m, int32_t L,
     for (int p = 0; p < NP; ++p) col_ok[p] = 32 * p + 2 * lr < mc;
     const int64_t q0 = near_ptr[l];
     // items: the basis term, then the near blocks
-    const int nitems = (int)(near_ptr[l + 1] - q0) + 1;
+    const int nnear = (int)(near_ptr[l + 1] - q0);
+    const int nitems = nnear + 1;
+    // near-block metadata staged once (beyond kMeta: read directly)
+    constexpr int kMeta = 160;
+    __shared__ int64_t m_off[kMeta], m_first[kMeta];
+    __shared__ int32_t m_size[kMeta];
+    for (int x = threadIdx.x; x < min(nnear, kMeta); x += 256) {
+        const int32_t s = near_col[q0 + x];
+        m_off[x] = near_off[q0 + x];
+        m_first[x] = first[s];
+        m_size[x] = size[s];
+    }
+    __syncthreads();
+    auto near_meta = [&](int x, int64_t &off, int64_t &fs, int &ks) {
+        if (x < kMeta) {
+            off = m_off[x];
+            fs = m_first[x];
+            ks = m_size[x];
+        } else {
+            const int32_t s = near_col[q0 + x];
+            off = near_off[q0 + x];
+            fs = first[s];
+            ks = size[s];
+        }
+    };
 
     for (int i0 = 0; i0 < nt; i0 += 64) {
         const int ic = min(64, nt - i0);
@@ -99,11 +123,10 @@ __global__ __launch_bounds__(256, 2) void k_leaf_lp(int k, int64_t m, int32_t L,
                     }
                 }
             } else {
-                const int64_t q = q0 + e - 1;
-                const int32_t s = near_col[q];
-                const float *bb = Nt + near_off[q] + i0 + 2 * lr;                 // N_ts^T[c][i]
-                const float *ab = Xt + (int64_t)first[s] * ldxt + j0 + 2 * lr;  // X_s[c][j]
-                kl = size[s];
+                int64_t off, fs;
+                near_meta(e - 1, off, fs, kl);
+                const float *bb = Nt + off + i0 + 2 * lr;       // N_ts^T[c][i]
+                const float *ab = Xt + fs * ldxt + j0 + 2 * lr;  // X_s[c][j]
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     const int c = kb + 4 * u + lq;
@@ -117,7 +140,13 @@ __global__ __launch_bounds__(256, 2) void k_leaf_lp(int k, int64_t m, int32_t L,
                 }
             }
         };
-        auto klen = [&](int e) { return e == 0 ? k : (int)size[near_col[q0 + e - 1]]; };
+        auto klen = [&](int e) {
+            if (e == 0) return k;
+            int64_t off, fs;
+            int ks;
+            near_meta(e - 1, off, fs, ks);
+            return ks;
+        };
 
         int e = w;
         if (e < nitems) {

@@ -308,7 +308,32 @@ __global__ __launch_bounds__(256, NP == 1 ? 2 : 1) void k_leaf_direct(int k, int
     // blocks; without near blocks the basis term is split over the 4 waves
     const int nb = basis ? (near ? 1 : 4) : 0;
     const int kbase = (k + max(nb, 1) - 1) / max(nb, 1);
-    const int nitems = (near ? (int)(near_ptr[l + 1] - q0) : 0) + nb;
+    const int nnear = near ? (int)(near_ptr[l + 1] - q0) : 0;
+    const int nitems = nnear + nb;
+    // the near blocks' offsets, column ranges and sizes, staged once so that moving
+    // to the next item costs no dependent global loads (beyond kMeta: read directly)
+    constexpr int kMeta = 160;
+    __shared__ int64_t m_off[kMeta], m_first[kMeta];
+    __shared__ int32_t m_size[kMeta];
+    for (int x = threadIdx.x; x < min(nnear, kMeta); x += 256) {
+        const int32_t s = near_col[q0 + x];
+        m_off[x] = near_off[q0 + x];
+        m_first[x] = first[s];
+        m_size[x] = size[s];
+    }
+    __syncthreads();
+    auto near_meta = [&](int x, int64_t &off, int64_t &fs, int &ks) {
+        if (x < kMeta) {
+            off = m_off[x];
+            fs = m_first[x];
+            ks = m_size[x];
+        } else {
+            const int32_t s = near_col[q0 + x];
+            off = near_off[q0 + x];
+            fs = first[s];
+            ks = size[s];
+        }
+    };
 
     for (int i0 = 0; i0 < nt; i0 += 64) {
         const int ic = min(64, nt - i0);
@@ -334,12 +359,11 @@ __global__ __launch_bounds__(256, NP == 1 ? 2 : 1) void k_leaf_direct(int k, int
                 lda = ldh;
                 kl = min(kbase, k - e * kbase);
             } else {
-                const int64_t q = q0 + e - nb;
-                const int32_t s = near_col[q];
-                bb = Nt + near_off[q] + i0 + 2 * lr;                     // N_ts^T[c][i]
-                ab = Xt + (int64_t)first[s] * ldxt + j0 + 2 * lr;        // X_s[c][j]
+                int64_t off, fs;
+                near_meta(e - nb, off, fs, kl);
+                bb = Nt + off + i0 + 2 * lr;               // N_ts^T[c][i]
+                ab = Xt + fs * ldxt + j0 + 2 * lr;         // X_s[c][j]
                 lda = ldxt;
-                kl = size[s];
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
@@ -353,7 +377,13 @@ __global__ __launch_bounds__(256, NP == 1 ? 2 : 1) void k_leaf_direct(int k, int
                     R.a[p][u] = (cok && col_ok[p]) ? ld2(ab + c * lda + 32 * p) : dbl2{0.0, 0.0};
             }
         };
-        auto klen = [&](int e) { return e < nb ? min(kbase, k - e * kbase) : (int)size[near_col[q0 + e - nb]]; };
+        auto klen = [&](int e) {
+            if (e < nb) return min(kbase, k - e * kbase);
+            int64_t off, fs;
+            int ks;
+            near_meta(e - nb, off, fs, ks);
+            return ks;
+        };
 
         int e = w;
         if (e < nitems) {

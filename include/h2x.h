@@ -253,9 +253,14 @@ h2x_status h2x_block_cg_mixed(const h2x_mat *A, const h2x_mat *A_lo, const h2x_c
 /* ---- tuning ----------------------------------------------------------------- */
 /* Tile shapes of the matrix-core kernels: columns per work-group of the forward
  * leaf and transfer passes (16 * nj_transfer), of the coupling (16 * nj_coupling)
- * and of the leaf stage (32 * np_leaf); 0 means the built-in rule. */
+ * and of the leaf stage (32 * np_leaf); 0 means the built-in rule.  On the FP64
+ * matrix-core path the near-field term can run on a second stream of the operator
+ * while the transfer passes and the coupling run on the caller's stream (the
+ * basis term joins it); the product then adds the two terms to Y in two steps. */
 typedef struct {
     int32_t nj_transfer, nj_coupling, np_leaf;
+    int32_t overlap;   /* near field on a second stream: 0 (built-in rule) and 2 off; on
+                          with its grid capped at 256 (1), 128 (3) or 512 (4) work-groups */
     double ms_default; /* product time with the built-in rule */
     double ms_tuned;   /* product time with the chosen shapes */
 } h2x_tune_info;

@@ -216,6 +216,12 @@ h2x_status h2x_mat_create(const h2x_plan *plan, h2x_prec storage, void *dev_ws, 
     up(d.box, P.box);
     if (e == hipSuccess) e = launch_fill(d, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
+    // second stream (default priority) for the near field of the matrix-core path
+    if (e == hipSuccess && d.mc && d.n_near > 0) {
+        e = hipStreamCreateWithFlags(&d.side, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&d.ev_fork, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&d.ev_join, hipEventDisableTiming);
+    }
     if (e != hipSuccess) {
         h2x_mat_destroy(M);
         return hip_fail("h2x_mat_create", e);
@@ -224,7 +230,16 @@ h2x_status h2x_mat_create(const h2x_plan *plan, h2x_prec storage, void *dev_ws, 
     return H2X_OK;
 }
 
-void h2x_mat_destroy(h2x_mat *mat) { delete mat; }
+void h2x_mat_destroy(h2x_mat *mat) {
+    if (!mat) return;
+    if (mat->dm.side) {
+        (void)hipStreamSynchronize(mat->dm.side);
+        (void)hipStreamDestroy(mat->dm.side);
+    }
+    if (mat->dm.ev_fork) (void)hipEventDestroy(mat->dm.ev_fork);
+    if (mat->dm.ev_join) (void)hipEventDestroy(mat->dm.ev_join);
+    delete mat;
+}
 
 size_t h2x_matmul_workspace_bytes(const h2x_mat *A, int64_t m) {
     if (!A || m < 1) return 0;

@@ -21,6 +21,9 @@ struct TuneCfg {
     int8_t nj_transfer = 0;  // 16-column tiles per work-group: forward leaf, transfer passes
     int8_t nj_coupling = 0;  // 16-column tiles per work-group: coupling
     int8_t np_leaf = 0;      // 32-column tiles per work-group: leaf stage
+    int8_t overlap = 0;      // near field on a second stream during the transfer passes and
+                             // the coupling: 0 (built-in rule) and 2 off; on with a grid
+                             // of 256 (1), 128 (3) or 512 (4) work-groups
 };
 constexpr int kTuneBuckets = 5;
 inline int tune_bucket(int64_t m) { return (int)std::min<int64_t>(kTuneBuckets - 1, (m + 15) / 16 - 1); }
@@ -69,6 +72,11 @@ struct DevMat {
     const Plan *plan = nullptr;
 
     TuneCfg tuned[kTuneBuckets];
+
+    // second stream and fork / join events of the operator (near field concurrent with
+    // the transfer passes); null when not created
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 
 };
 

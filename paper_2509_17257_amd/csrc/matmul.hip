@@ -318,6 +318,33 @@ void matmul_mfma_f64(const DevMat &dm, const TuneCfg &cfg, int64_t m, double alp
         Xt = xt_ws;
     }
     const Skip sk{skip, dm.sys_of};
+    const unsigned gl = (unsigned)((m + 32 * NP - 1) / (32 * NP));
+    auto leaf = [&](hipStream_t s, double b, int basis, int near, unsigned cap) {
+        unsigned gx = 8 * ((dm.L + 7) / 8);
+        if (cap) gx = std::min(gx, cap);
+        if (NP == 2)
+            hipLaunchKernelGGL(mfma::k_leaf_direct<2>, dim3(gx, gl), dim3(256), 0, s, dm.k, m,
+                               dm.L, dm.leaves, dm.first, dm.size, dm.perm, (const double *)dm.Vt, dm.vt_off, yh, ldh,
+                               dm.near_ptr, dm.near_col, dm.near_off, (const double *)dm.N, Xt, ldxt, alpha, b, Y,
+                               ldy, to, basis, near, sk);
+        else
+            hipLaunchKernelGGL(mfma::k_leaf_direct<1>, dim3(gx, gl), dim3(256), 0, s, dm.k, m,
+                               dm.L, dm.leaves, dm.first, dm.size, dm.perm, (const double *)dm.Vt, dm.vt_off, yh, ldh,
+                               dm.near_ptr, dm.near_col, dm.near_off, (const double *)dm.N, Xt, ldxt, alpha, b, Y,
+                               ldy, to, basis, near, sk);
+    };
+    // near field on the operator's second stream while the transfer passes and the
+    // coupling run here (it needs only X); the basis term joins it at the end.  Its
+    // grid is capped so that it leaves room on the chip for the transfer chain:
+    // overlap 1: 256 work-groups, 3: 128, 4: 512; 0 (the built-in rule) and 2: off
+    const bool ov = dm.side && dm.n_near > 0 && (cfg.overlap == 1 || cfg.overlap >= 3);
+    if (ov) {
+        const unsigned cap = cfg.overlap == 3 ? 128u : (cfg.overlap == 4 ? 512u : 256u);
+        (void)hipEventRecord(dm.ev_fork, st);
+        (void)hipStreamWaitEvent(dm.side, dm.ev_fork, 0);
+        leaf(dm.side, beta, 0, 1, cap);
+        (void)hipEventRecord(dm.ev_join, dm.side);
+    }
     hipLaunchKernelGGL(mfma::k_fwd_leaf<NJ>, dim3(dm.L, gy), dim3(256), 0, st, dm.k, m, dm.leaves, dm.first,
                        dm.size, dm.perm, V, Xt, ldxt, 1, xh, ldh, sk);
     mark(1);
@@ -338,17 +365,12 @@ void matmul_mfma_f64(const DevMat &dm, const TuneCfg &cfg, int64_t m, double alp
     }
     mark(4);
     // Y = beta Y + alpha (V y-hat + N X)
-    const unsigned gl = (unsigned)((m + 32 * NP - 1) / (32 * NP));
-    if (NP == 2)
-        hipLaunchKernelGGL(mfma::k_leaf_direct<2>, dim3(8 * ((dm.L + 7) / 8), gl), dim3(256), 0, st, dm.k, m, dm.L,
-                           dm.leaves, dm.first, dm.size, dm.perm, (const double *)dm.Vt, dm.vt_off, yh, ldh,
-                           dm.near_ptr, dm.near_col, dm.near_off, (const double *)dm.N, Xt, ldxt, alpha, beta, Y, ldy,
-                           to, 1, 1, sk);
-    else
-        hipLaunchKernelGGL(mfma::k_leaf_direct<1>, dim3(8 * ((dm.L + 7) / 8), gl), dim3(256), 0, st, dm.k, m, dm.L,
-                           dm.leaves, dm.first, dm.size, dm.perm, (const double *)dm.Vt, dm.vt_off, yh, ldh,
-                           dm.near_ptr, dm.near_col, dm.near_off, (const double *)dm.N, Xt, ldxt, alpha, beta, Y, ldy,
-                           to, 1, 1, sk);
+    if (ov) {
+        (void)hipStreamWaitEvent(st, dm.ev_join, 0);
+        leaf(st, 1.0, 1, 0, 0);
+    } else {
+        leaf(st, beta, 1, 1, 0);
+    }
     mark(5);
     if (ev) (void)hipEventRecord(ev[6], st);
 }

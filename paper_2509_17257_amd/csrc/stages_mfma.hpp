@@ -290,164 +290,168 @@ __global__ __launch_bounds__(256, NP == 1 ? 2 : 1) void k_leaf_direct(int k, int
     constexpr int MC = 32 * NP, LDR = MC + 1;
     __shared__ double red[64 * LDR];
     const int32_t per_xcd = (L + 7) / 8;
-    const int32_t l = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
-    if (l >= L) return;
-    const int32_t t = leaves[l];
-    if (skip(t)) return;
-    const int nt = size[t];
-    const int64_t nt2 = nt + (nt & 1);
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, lq = lane >> 4;
-    const int64_t r0 = first[t];
-    const int64_t j0 = (int64_t)blockIdx.y * MC;
-    const int mc = (int)min<int64_t>(MC, m - j0);
-    bool col_ok[NP];
-#pragma unroll
-    for (int p = 0; p < NP; ++p) col_ok[p] = 32 * p + 2 * lr < mc;
-    const int64_t q0 = near_ptr[l];
-    // items: nb parts of the basis term (k-ranges of ceil(k / nb)), then the near
-    // blocks; without near blocks the basis term is split over the 4 waves
-    const int nb = basis ? (near ? 1 : 4) : 0;
-    const int kbase = (k + max(nb, 1) - 1) / max(nb, 1);
-    const int nnear = near ? (int)(near_ptr[l + 1] - q0) : 0;
-    const int nitems = nnear + nb;
-    // the near blocks' offsets, column ranges and sizes, staged once so that moving
-    // to the next item costs no dependent global loads (beyond kMeta: read directly)
-    constexpr int kMeta = 160;
-    __shared__ int64_t m_off[kMeta], m_first[kMeta];
-    __shared__ int32_t m_size[kMeta];
-    for (int x = threadIdx.x; x < min(nnear, kMeta); x += 256) {
-        const int32_t s = near_col[q0 + x];
-        m_off[x] = near_off[q0 + x];
-        m_first[x] = first[s];
-        m_size[x] = size[s];
-    }
-    __syncthreads();
-    auto near_meta = [&](int x, int64_t &off, int64_t &fs, int &ks) {
-        if (x < kMeta) {
-            off = m_off[x];
-            fs = m_first[x];
-            ks = m_size[x];
-        } else {
+    // one leaf per work-group, or (a capped grid) leaves in a grid-stride loop; a slot
+    // keeps its XCD because the grid is a multiple of 8
+    for (int32_t slot = blockIdx.x; slot < 8 * per_xcd; slot += gridDim.x) {
+        const int32_t l = (slot & 7) * per_xcd + (slot >> 3);
+        if (l >= L) continue;
+        const int32_t t = leaves[l];
+        if (skip(t)) continue;
+        const int nt = size[t];
+        const int64_t nt2 = nt + (nt & 1);
+        const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, lq = lane >> 4;
+        const int64_t r0 = first[t];
+        const int64_t j0 = (int64_t)blockIdx.y * MC;
+        const int mc = (int)min<int64_t>(MC, m - j0);
+        bool col_ok[NP];
+    #pragma unroll
+        for (int p = 0; p < NP; ++p) col_ok[p] = 32 * p + 2 * lr < mc;
+        const int64_t q0 = near_ptr[l];
+        // items: nb parts of the basis term (k-ranges of ceil(k / nb)), then the near
+        // blocks; without near blocks the basis term is split over the 4 waves
+        const int nb = basis ? (near ? 1 : 4) : 0;
+        const int kbase = (k + max(nb, 1) - 1) / max(nb, 1);
+        const int nnear = near ? (int)(near_ptr[l + 1] - q0) : 0;
+        const int nitems = nnear + nb;
+        // the near blocks' offsets, column ranges and sizes, staged once so that moving
+        // to the next item costs no dependent global loads (beyond kMeta: read directly)
+        constexpr int kMeta = 160;
+        __shared__ int64_t m_off[kMeta], m_first[kMeta];
+        __shared__ int32_t m_size[kMeta];
+        for (int x = threadIdx.x; x < min(nnear, kMeta); x += 256) {
             const int32_t s = near_col[q0 + x];
-            off = near_off[q0 + x];
-            fs = first[s];
-            ks = size[s];
-        }
-    };
-
-    for (int i0 = 0; i0 < nt; i0 += 64) {
-        const int ic = min(64, nt - i0);
-        const int nhalf = (ic + 31) >> 5;  // 32-row halves present (wave-uniform)
-        bool row_ok[2];
-#pragma unroll
-        for (int g = 0; g < 2; ++g) row_ok[g] = 32 * g + 2 * lr < ic;
-        dbl4 acc[2 * NP][4];
-#pragma unroll
-        for (int J = 0; J < 2 * NP; ++J)
-#pragma unroll
-            for (int I = 0; I < 4; ++I) acc[J][I] = dbl4{0.0, 0.0, 0.0, 0.0};
-
-        // item e, k-steps kb..kb+15 -> registers.  Right operand: rows (k) of a
-        // transposed block with row stride nt2; left operand: rows (k) of X or y_t.
-        auto load = [&](int e, int kb, Round<NP> &R) {
-            const double *bb, *ab;
-            int64_t lda;
-            int kl;
-            if (e < nb) {
-                bb = Vt + vt_off[l] + (int64_t)e * kbase * nt2 + i0 + 2 * lr;   // V_t^T[nu][i]
-                ab = yh + ((int64_t)t * k + e * kbase) * ldh + j0 + 2 * lr;     // y_t[nu][j]
-                lda = ldh;
-                kl = min(kbase, k - e * kbase);
-            } else {
-                int64_t off, fs;
-                near_meta(e - nb, off, fs, kl);
-                bb = Nt + off + i0 + 2 * lr;               // N_ts^T[c][i]
-                ab = Xt + fs * ldxt + j0 + 2 * lr;         // X_s[c][j]
-                lda = ldxt;
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int c = kb + 4 * u + lq;
-                const bool cok = c < kl;
-#pragma unroll
-                for (int g = 0; g < 2; ++g)
-                    R.b[g][u] = (cok && row_ok[g]) ? ld2(bb + c * nt2 + 32 * g) : dbl2{0.0, 0.0};
-#pragma unroll
-                for (int p = 0; p < NP; ++p)
-                    R.a[p][u] = (cok && col_ok[p]) ? ld2(ab + c * lda + 32 * p) : dbl2{0.0, 0.0};
-            }
-        };
-        auto klen = [&](int e) {
-            if (e < nb) return min(kbase, k - e * kbase);
-            int64_t off, fs;
-            int ks;
-            near_meta(e - nb, off, fs, ks);
-            return ks;
-        };
-
-        int e = w;
-        if (e < nitems) {
-            Round<NP> cur, nxt;
-            int kb = 0, len = klen(e);
-            load(e, kb, cur);
-            for (;;) {
-                int en = e, kbn = kb + 16, lenn = len;
-                if (kbn >= len) {
-                    en = e + 4;
-                    kbn = 0;
-                    if (en < nitems) lenn = klen(en);
-                }
-                const bool more = en < nitems;
-                if (more) load(en, kbn, nxt);
-#pragma unroll
-                for (int u = 0; u < 4; ++u)
-#pragma unroll
-                    for (int g = 0; g < 2; ++g)
-                        if (g < nhalf)
-#pragma unroll
-                            for (int h = 0; h < 2; ++h)
-#pragma unroll
-                                for (int p = 0; p < NP; ++p)
-#pragma unroll
-                                    for (int hj = 0; hj < 2; ++hj)
-                                        acc[2 * p + hj][2 * g + h] = __builtin_amdgcn_mfma_f64_16x16x4f64(
-                                            cur.a[p][u][hj], cur.b[g][u][h], acc[2 * p + hj][2 * g + h], 0, 0, 0);
-                if (!more) break;
-                cur = nxt;
-                e = en;
-                kb = kbn;
-                len = lenn;
-            }
-        }
-        // partial tiles of the 4 waves, added in wave order.  Lane l, register r of
-        // tile (J = 2p + hj, I = 2g + h) -> column 32p + 2 (l / 16 + 4 r) + hj,
-        // row 32g + 2 (l % 16) + h.
-        for (int ww = 0; ww < 4; ++ww) {
-            if (w == ww)
-#pragma unroll
-                for (int J = 0; J < 2 * NP; ++J)
-#pragma unroll
-                    for (int I = 0; I < 4; ++I)
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) {
-                            const int col = 32 * (J >> 1) + 2 * (lq + 4 * r) + (J & 1);
-                            const int row = 32 * (I >> 1) + 2 * lr + (I & 1);
-                            double *cell = &red[row * LDR + col];
-                            *cell = (ww == 0) ? acc[J][I][r] : *cell + acc[J][I][r];
-                        }
-            __syncthreads();
-        }
-        for (int x = threadIdx.x; x < ic * MC; x += 256) {
-            const int i = x / MC, j = x % MC;
-            if (j < mc) {
-                int64_t row = r0 + i0 + i;
-                if (!tree_order) row = perm[row];
-                double *y = &Y[row * ldy + j0 + j];
-                const double v = alpha * red[i * LDR + j];
-                *y = (beta == 0.0) ? v : beta * *y + v;
-            }
+            m_off[x] = near_off[q0 + x];
+            m_first[x] = first[s];
+            m_size[x] = size[s];
         }
         __syncthreads();
+        auto near_meta = [&](int x, int64_t &off, int64_t &fs, int &ks) {
+            if (x < kMeta) {
+                off = m_off[x];
+                fs = m_first[x];
+                ks = m_size[x];
+            } else {
+                const int32_t s = near_col[q0 + x];
+                off = near_off[q0 + x];
+                fs = first[s];
+                ks = size[s];
+            }
+        };
+
+        for (int i0 = 0; i0 < nt; i0 += 64) {
+            const int ic = min(64, nt - i0);
+            const int nhalf = (ic + 31) >> 5;  // 32-row halves present (wave-uniform)
+            bool row_ok[2];
+    #pragma unroll
+            for (int g = 0; g < 2; ++g) row_ok[g] = 32 * g + 2 * lr < ic;
+            dbl4 acc[2 * NP][4];
+    #pragma unroll
+            for (int J = 0; J < 2 * NP; ++J)
+    #pragma unroll
+                for (int I = 0; I < 4; ++I) acc[J][I] = dbl4{0.0, 0.0, 0.0, 0.0};
+
+            // item e, k-steps kb..kb+15 -> registers.  Right operand: rows (k) of a
+            // transposed block with row stride nt2; left operand: rows (k) of X or y_t.
+            auto load = [&](int e, int kb, Round<NP> &R) {
+                const double *bb, *ab;
+                int64_t lda;
+                int kl;
+                if (e < nb) {
+                    bb = Vt + vt_off[l] + (int64_t)e * kbase * nt2 + i0 + 2 * lr;   // V_t^T[nu][i]
+                    ab = yh + ((int64_t)t * k + e * kbase) * ldh + j0 + 2 * lr;     // y_t[nu][j]
+                    lda = ldh;
+                    kl = min(kbase, k - e * kbase);
+                } else {
+                    int64_t off, fs;
+                    near_meta(e - nb, off, fs, kl);
+                    bb = Nt + off + i0 + 2 * lr;               // N_ts^T[c][i]
+                    ab = Xt + fs * ldxt + j0 + 2 * lr;         // X_s[c][j]
+                    lda = ldxt;
+                }
+    #pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int c = kb + 4 * u + lq;
+                    const bool cok = c < kl;
+    #pragma unroll
+                    for (int g = 0; g < 2; ++g)
+                        R.b[g][u] = (cok && row_ok[g]) ? ld2(bb + c * nt2 + 32 * g) : dbl2{0.0, 0.0};
+    #pragma unroll
+                    for (int p = 0; p < NP; ++p)
+                        R.a[p][u] = (cok && col_ok[p]) ? ld2(ab + c * lda + 32 * p) : dbl2{0.0, 0.0};
+                }
+            };
+            auto klen = [&](int e) {
+                if (e < nb) return min(kbase, k - e * kbase);
+                int64_t off, fs;
+                int ks;
+                near_meta(e - nb, off, fs, ks);
+                return ks;
+            };
+
+            int e = w;
+            if (e < nitems) {
+                Round<NP> cur, nxt;
+                int kb = 0, len = klen(e);
+                load(e, kb, cur);
+                for (;;) {
+                    int en = e, kbn = kb + 16, lenn = len;
+                    if (kbn >= len) {
+                        en = e + 4;
+                        kbn = 0;
+                        if (en < nitems) lenn = klen(en);
+                    }
+                    const bool more = en < nitems;
+                    if (more) load(en, kbn, nxt);
+    #pragma unroll
+                    for (int u = 0; u < 4; ++u)
+    #pragma unroll
+                        for (int g = 0; g < 2; ++g)
+                            if (g < nhalf)
+    #pragma unroll
+                                for (int h = 0; h < 2; ++h)
+    #pragma unroll
+                                    for (int p = 0; p < NP; ++p)
+    #pragma unroll
+                                        for (int hj = 0; hj < 2; ++hj)
+                                            acc[2 * p + hj][2 * g + h] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                                                cur.a[p][u][hj], cur.b[g][u][h], acc[2 * p + hj][2 * g + h], 0, 0, 0);
+                    if (!more) break;
+                    cur = nxt;
+                    e = en;
+                    kb = kbn;
+                    len = lenn;
+                }
+            }
+            // partial tiles of the 4 waves, added in wave order.  Lane l, register r of
+            // tile (J = 2p + hj, I = 2g + h) -> column 32p + 2 (l / 16 + 4 r) + hj,
+            // row 32g + 2 (l % 16) + h.
+            for (int ww = 0; ww < 4; ++ww) {
+                if (w == ww)
+    #pragma unroll
+                    for (int J = 0; J < 2 * NP; ++J)
+    #pragma unroll
+                        for (int I = 0; I < 4; ++I)
+    #pragma unroll
+                            for (int r = 0; r < 4; ++r) {
+                                const int col = 32 * (J >> 1) + 2 * (lq + 4 * r) + (J & 1);
+                                const int row = 32 * (I >> 1) + 2 * lr + (I & 1);
+                                double *cell = &red[row * LDR + col];
+                                *cell = (ww == 0) ? acc[J][I][r] : *cell + acc[J][I][r];
+                            }
+                __syncthreads();
+            }
+            for (int x = threadIdx.x; x < ic * MC; x += 256) {
+                const int i = x / MC, j = x % MC;
+                if (j < mc) {
+                    int64_t row = r0 + i0 + i;
+                    if (!tree_order) row = perm[row];
+                    double *y = &Y[row * ldy + j0 + j];
+                    const double v = alpha * red[i * LDR + j];
+                    *y = (beta == 0.0) ? v : beta * *y + v;
+                }
+            }
+            __syncthreads();
+        }
     }
 }
 

@@ -4,7 +4,8 @@
 // choice in the operator's table for m's bucket; later products with a column
 // count in that bucket use it.  Candidates: 16-column tiles per work-group of
 // the forward leaf and transfer passes (1 .. ceil(m / 16), at most 4), of the
-// coupling (same range), 32-column tiles of the leaf stage (1 or 2).
+// coupling (same range), 32-column tiles of the leaf stage (1 or 2), and whether the
+// near field runs on a second stream concurrently with the transfer passes.
 #include <cmath>
 #include <string>
 #include <vector>
@@ -106,6 +107,22 @@ h2x_status run_autotune(DevMat &dm, int64_t m, char *ws, size_t ws_bytes, hipStr
         }
     }
     if (e != hipSuccess) return done(e);
+    // near field concurrent with the transfer passes (it changes the time of several
+    // stages, so the whole product decides)
+    if (dm.side) {
+        double best_o = HUGE_VAL;
+        for (int o : {1, 2, 3, 4}) {
+            double so[5];
+            TuneCfg c = best;
+            c.overlap = (int8_t)o;
+            e = time_cfg(c, so);
+            if (e != hipSuccess) return done(e);
+            if (total(so) < best_o) {
+                best_o = total(so);
+                best.overlap = (int8_t)o;
+            }
+        }
+    }
     double s1[5];
     e = time_cfg(best, s1);
     if (e != hipSuccess) return done(e);
@@ -116,6 +133,7 @@ h2x_status run_autotune(DevMat &dm, int64_t m, char *ws, size_t ws_bytes, hipStr
         info->nj_transfer = dm.tuned[b].nj_transfer;
         info->nj_coupling = dm.tuned[b].nj_coupling;
         info->np_leaf = dm.tuned[b].np_leaf;
+        info->overlap = dm.tuned[b].overlap;
         info->ms_default = total(s0);
         info->ms_tuned = use ? total(s1) : total(s0);
     }

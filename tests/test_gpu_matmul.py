@@ -152,8 +152,9 @@ def test_invalid_arguments_on_gpu():
 
 @pytest.mark.parametrize("storage,m", [("f64", 32), ("f64", 5), ("f64", 64), ("f32", 40), ("bf16", 20)])
 def test_autotune_keeps_results(storage, m):
-    """Autotuned tile shapes change only the work distribution: the product after
-    tuning is bitwise the product before (fixed summation order per element)."""
+    """Autotuned tile shapes change only the work distribution (fixed summation order
+    per element); turning the concurrent near field on or off changes only whether
+    the near and basis terms reach Y in one step or two."""
     h2x = _h2x()
     P = W.sphere_points(8000, 121)
     A = h2x.H2Matrix(P, storage=storage, ell=0.5, shift=1.0, eta=1.0, leaf=64, p=4)
@@ -164,4 +165,8 @@ def test_autotune_keeps_results(storage, m):
     torch.cuda.synchronize()
     print(f"{storage} m={m}: {info}")
     assert info["ms_tuned"] <= info["ms_default"] * 1.0001
-    assert torch.equal(before, after)
+    if info["overlap"] in (0, 2) or storage != "f64":
+        assert torch.equal(before, after)
+    else:
+        rel = ((after - before).norm(dim=0) / before.norm(dim=0)).max().item()
+        assert rel <= 1e-15

@@ -14,7 +14,9 @@
 //          dg/dell = (r / ell^2) exp(-r / ell), evaluated where it is needed.
 // Per-block partial sums of dell are reduced in a fixed order.
 #include <cmath>
+#include <type_traits>
 
+#include "adjoint_mfma.hpp"
 #include "device.hpp"
 #include "types.hpp"
 
@@ -270,19 +272,23 @@ __global__ __launch_bounds__(256) void k_grad_N(int64_t m, const int32_t *__rest
     if (tid == 0) part[q] = red[0];
 }
 
-// dell = sum of the per-block partial sums, in a fixed order
-__global__ void k_sum_fixed(int64_t count, const double *__restrict__ part, double *__restrict__ out) {
+// dell = sum of the per-block partial sums, in a fixed order: work-group g adds
+// entries [g * chunk, (g + 1) * chunk) into out[g] (one work-group: the total)
+__global__ void k_sum_fixed(int64_t count, int64_t chunk, const double *__restrict__ part, double *__restrict__ out) {
     __shared__ double red[256];
+    const int64_t a = (int64_t)blockIdx.x * chunk, b = min(count, a + chunk);
     double s = 0.0;
-    for (int64_t i = threadIdx.x; i < count; i += 256) s += part[i];
+    for (int64_t i = a + threadIdx.x; i < b; i += 256) s += part[i];
     red[threadIdx.x] = s;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) *out = red[0];
+    if (threadIdx.x == 0) out[blockIdx.x] = red[0];
 }
+
+constexpr int64_t kSumChunk = 2048;
 
 __global__ void k_gather_even(int64_t n, int64_t m, const int64_t *__restrict__ perm, const double *__restrict__ X,
                               int64_t ldx, double *__restrict__ Xt, int64_t ldt) {
@@ -306,7 +312,7 @@ __global__ void k_write_S(int k, int swz, const double *__restrict__ in, double 
 int64_t even(int64_t m) { return m + (m & 1); }
 
 struct GradWs {
-    double *xh, *dh, *Xt, *dYt, *part, *xt_ws;
+    double *xh, *dh, *Xt, *dYt, *part, *part2, *xt_ws;
     size_t bytes;
 };
 
@@ -326,6 +332,7 @@ GradWs grad_layout(const DevMat &dm, int64_t m, char *base) {
     w.dYt = carve(nm);
     w.xt_ws = carve(nm);
     w.part = carve((size_t)(dm.n_adm + dm.n_near + 1) * sizeof(double));
+    w.part2 = carve((size_t)((dm.n_adm + dm.n_near) / kSumChunk + 2) * sizeof(double));
     w.bytes = align_up(off);
     return w;
 }
@@ -360,6 +367,30 @@ hipError_t run_matmul_adjoint(const DevMat &dm, int64_t m, double alpha, const d
     double *xh = (double *)ws, *yh = (double *)(ws + hat), *xt = (double *)(ws + 2 * hat);
     hipError_t e = run_forward_transform(dm, m, X, ldx, false, xh, ldh, xt, st);
     if (e != hipSuccess) return e;
+    if (dm.mc) {
+        // matrix-core path: the forward transformation left X in tree order in xt (leading dimension ldh)
+        const int nj = (int)std::min<int64_t>(4, (m + 15) / 16);
+        const unsigned gy = (unsigned)((m + 16 * nj - 1) / (16 * nj));
+        auto go = [&](auto NJc) {
+            constexpr int NJ = decltype(NJc)::value;
+            hipLaunchKernelGGL(adj::k_coupling_adj_mfma<NJ>, dim3(8 * ((dm.C + 7) / 8), gy), dim3(256), 0, st, dm.k,
+                               dm.swz, m, dm.C, dm.adm_cptr, dm.adm_cblk, dm.adm_row, (const double *)dm.S,
+                               (const double *)xh, yh, ldh);
+            hipError_t ee = run_down_pass(dm, m, yh, ldh, st);
+            if (ee != hipSuccess) return ee;
+            hipLaunchKernelGGL(adj::k_leaf_adj_mfma<NJ>, dim3(8 * ((dm.L + 7) / 8), gy), dim3(256), 0, st, dm.k, m,
+                               dm.L, dm.leaves, dm.first, dm.size, dm.perm, (const double *)dm.V,
+                               (const double *)yh, ldh, dm.near_cptr, dm.near_cblk, dm.near_row, dm.near_off,
+                               (const double *)dm.N, (const double *)xt, ldh, alpha, beta, Y, ldy);
+            return hipGetLastError();
+        };
+        switch (nj) {
+            case 1: return go(std::integral_constant<int, 1>{});
+            case 2: return go(std::integral_constant<int, 2>{});
+            case 3: return go(std::integral_constant<int, 3>{});
+            default: return go(std::integral_constant<int, 4>{});
+        }
+    }
     const unsigned gy = (unsigned)((m + TC - 1) / TC);
     hipLaunchKernelGGL(k_coupling_adj, dim3(dm.C, gy), dim3(256), 0, st, dm.k, m, dm.adm_cptr, dm.adm_cblk,
                        dm.adm_row, (const double *)dm.S, dm.swz, (const double *)xh, yh, ldh);
@@ -380,10 +411,16 @@ hipError_t run_grad(const DevMat &dm, int64_t m, const double *X, int64_t ldx, c
         e = run_forward_transform(dm, m, X, ldx, false, w.xh, ldh, w.xt_ws, st);
         if (e == hipSuccess) e = run_forward_transform(dm, m, dY, lddy, false, w.dh, ldh, w.xt_ws, st);
         if (e != hipSuccess) return e;
-        if (dm.n_adm > 0)
-            hipLaunchKernelGGL(k_grad_S, dim3((unsigned)dm.n_adm), dim3(256), 0, st, dm.k, m, dm.adm_row, dm.adm_col,
-                               dm.nodes, dm.kernel, dm.ell, (const double *)w.dh, (const double *)w.xh, ldh, dS,
-                               w.part);
+        if (dm.n_adm > 0) {
+            if (dm.mc)
+                hipLaunchKernelGGL(adj::k_grad_S_mfma, dim3((unsigned)dm.n_adm), dim3(256), 0, st, dm.k, m, dm.adm_row,
+                                   dm.adm_col, dm.nodes, dm.kernel, dm.ell, (const double *)w.dh,
+                                   (const double *)w.xh, ldh, dS, w.part);
+            else
+                hipLaunchKernelGGL(k_grad_S, dim3((unsigned)dm.n_adm), dim3(256), 0, st, dm.k, m, dm.adm_row,
+                                   dm.adm_col, dm.nodes, dm.kernel, dm.ell, (const double *)w.dh,
+                                   (const double *)w.xh, ldh, dS, w.part);
+        }
     }
     if (dN || dell) {
         const int64_t cnt = dm.n * ldh;
@@ -391,12 +428,27 @@ hipError_t run_grad(const DevMat &dm, int64_t m, const double *X, int64_t ldx, c
                            ldx, w.Xt, ldh);
         hipLaunchKernelGGL(k_gather_even, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, dm.n, m, dm.perm, dY,
                            lddy, w.dYt, ldh);
-        if (dm.n_near > 0)
-            hipLaunchKernelGGL(k_grad_N, dim3((unsigned)dm.n_near), dim3(256), 0, st, m, dm.near_row, dm.near_col,
-                               dm.near_off_rm, dm.first, dm.size, dm.pts, dm.kernel, dm.ell, (const double *)w.dYt,
-                               (const double *)w.Xt, ldh, dN, w.part + dm.n_adm);
+        if (dm.n_near > 0) {
+            if (dm.mc)
+                hipLaunchKernelGGL(adj::k_grad_N_mfma, dim3((unsigned)dm.n_near), dim3(256), 0, st, m, dm.near_row,
+                                   dm.near_col, dm.near_off_rm, dm.first, dm.size, dm.pts, dm.kernel, dm.ell,
+                                   (const double *)w.dYt, (const double *)w.Xt, ldh, dN, w.part + dm.n_adm);
+            else
+                hipLaunchKernelGGL(k_grad_N, dim3((unsigned)dm.n_near), dim3(256), 0, st, m, dm.near_row,
+                                   dm.near_col, dm.near_off_rm, dm.first, dm.size, dm.pts, dm.kernel, dm.ell,
+                                   (const double *)w.dYt, (const double *)w.Xt, ldh, dN, w.part + dm.n_adm);
+        }
     }
-    if (dell) hipLaunchKernelGGL(k_sum_fixed, dim3(1), dim3(256), 0, st, dm.n_adm + dm.n_near, (const double *)w.part, dell);
+    if (dell) {
+        const int64_t cnt = dm.n_adm + dm.n_near, ng = (cnt + kSumChunk - 1) / kSumChunk;
+        if (ng > 1) {
+            hipLaunchKernelGGL(k_sum_fixed, dim3((unsigned)ng), dim3(256), 0, st, cnt, kSumChunk,
+                               (const double *)w.part, w.part2);
+            hipLaunchKernelGGL(k_sum_fixed, dim3(1), dim3(256), 0, st, ng, ng, (const double *)w.part2, dell);
+        } else {
+            hipLaunchKernelGGL(k_sum_fixed, dim3(1), dim3(256), 0, st, cnt, cnt + 1, (const double *)w.part, dell);
+        }
+    }
     return hipGetLastError();
 }
 

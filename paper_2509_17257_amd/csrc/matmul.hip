@@ -522,6 +522,26 @@ hipError_t run_forward_transform(const DevMat &dm, int64_t m, const double *X, i
 hipError_t run_down_pass(const DevMat &dm, int64_t m, double *yh, int64_t ldh, hipStream_t st) {
     const Plan &P = *dm.plan;
     const double *E = (const double *)dm.E;
+    if (dm.mc) {
+        const int nj = (int)std::min<int64_t>(4, (m + 15) / 16);
+        const unsigned gy = (unsigned)((m + 16 * nj - 1) / (16 * nj));
+        auto go = [&](auto NJc) {
+            constexpr int NJ = decltype(NJc)::value;
+            for (int d = std::max(1, P.adm_depth + 1); d <= dm.depth_max; ++d) {
+                const int32_t b = P.lvl_ptr[d], e = P.lvl_ptr[d + 1];
+                if (e > b)
+                    hipLaunchKernelGGL(mfma::k_down<NJ>, dim3(e - b, gy), dim3(256), 0, st, dm.k, m, dm.lvl_all + b,
+                                       dm.parent, E, yh, ldh, Skip{});
+            }
+        };
+        switch (nj) {
+            case 1: go(std::integral_constant<int, 1>{}); break;
+            case 2: go(std::integral_constant<int, 2>{}); break;
+            case 3: go(std::integral_constant<int, 3>{}); break;
+            default: go(std::integral_constant<int, 4>{}); break;
+        }
+        return hipGetLastError();
+    }
     const unsigned gy = (unsigned)((m + TC - 1) / TC);
     for (int d = std::max(1, P.adm_depth + 1); d <= dm.depth_max; ++d) {
         const int32_t b = P.lvl_ptr[d], e = P.lvl_ptr[d + 1];

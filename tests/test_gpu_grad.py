@@ -53,6 +53,9 @@ CASES = [
     ("cube-k8-leaf100-m3", lambda: W.cube_points(3000, 183), dict(ell=0.3, shift=0.5, eta=1.5, leaf=100, p=2), 3),
     ("line-k27-m1", lambda: W.line_points(2000, 184), dict(ell=0.2, shift=1.0, eta=1.0, leaf=16, p=3), 1),
     ("sphere-k64-m37", lambda: W.sphere_points(4000, 185), dict(ell=0.5, shift=1.0, eta=1.0, leaf=64, p=4), 37),
+    # leaves and near blocks wider than one 64-row tile
+    ("sphere-k64-leaf150-m17", lambda: W.sphere_points(4000, 186), dict(ell=0.5, shift=1.0, eta=1.0, leaf=150, p=4),
+     17),
 ]
 
 

@@ -261,6 +261,8 @@ typedef struct {
     int32_t nj_transfer, nj_coupling, np_leaf;
     int32_t overlap;   /* near field on a second stream: 0 (built-in rule) and 2 off; on
                           with its grid capped at 256 (1), 128 (3) or 512 (4) work-groups */
+    int32_t fuse_up;   /* forward leaf and upward pass in one launch: 1 on; 0 (built-in
+                          rule) and 2 level by level                                   */
     double ms_default; /* product time with the built-in rule */
     double ms_tuned;   /* product time with the chosen shapes */
 } h2x_tune_info;

@@ -57,7 +57,8 @@ _VARIANT = {"independent": CG_INDEPENDENT, "shared": CG_SHARED, CG_INDEPENDENT: 
 
 class _TuneInfo(C.Structure):
     _fields_ = [("nj_transfer", C.c_int32), ("nj_coupling", C.c_int32), ("np_leaf", C.c_int32),
-                ("overlap", C.c_int32), ("ms_default", C.c_double), ("ms_tuned", C.c_double)]
+                ("overlap", C.c_int32), ("fuse_up", C.c_int32), ("ms_default", C.c_double),
+                ("ms_tuned", C.c_double)]
 
 
 class _CgInfo(C.Structure):
@@ -260,7 +261,8 @@ class H2Matrix:
         _check(lib.h2x_mat_autotune(self._h, int(m), C.c_void_p(ws.data_ptr()), ws.numel(),
                                     _stream(torch, self.device), C.byref(info)), "h2x_mat_autotune")
         return dict(nj_transfer=info.nj_transfer, nj_coupling=info.nj_coupling, np_leaf=info.np_leaf,
-                    overlap=info.overlap, ms_default=info.ms_default, ms_tuned=info.ms_tuned)
+                    overlap=info.overlap, fuse_up=info.fuse_up, ms_default=info.ms_default,
+                    ms_tuned=info.ms_tuned)
 
     def set_ell(self, ell: float) -> None:
         """Refill S and the near field for a new kernel length scale (h2x_mat_set_ell)."""

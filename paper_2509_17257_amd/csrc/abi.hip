@@ -211,6 +211,7 @@ h2x_status h2x_mat_create(const h2x_plan *plan, h2x_prec storage, void *dev_ws, 
     for (int32_t i = 0; i < P.nsys(); ++i)
         for (int64_t c = P.sys_C[i]; c < P.sys_C[i + 1]; ++c) sys_of[c] = i;
     up(d.sys_of, sys_of);
+    up(d.depth, P.depth);
     up(d.perm, P.perm);
     up(d.pts, P.pts_tree);
     up(d.box, P.box);

@@ -21,6 +21,8 @@ struct TuneCfg {
     int8_t nj_transfer = 0;  // 16-column tiles per work-group: forward leaf, transfer passes
     int8_t nj_coupling = 0;  // 16-column tiles per work-group: coupling
     int8_t np_leaf = 0;      // 32-column tiles per work-group: leaf stage
+    int8_t fuse_up = 0;      // forward leaf and upward pass in one launch: 1 on; 0 (built-in
+                             // rule) and 2 off
     int8_t overlap = 0;      // near field on a second stream during the transfer passes and
                              // the coupling: 0 (built-in rule) and 2 off; on with a grid
                              // of 256 (1), 128 (3) or 512 (4) work-groups
@@ -56,6 +58,7 @@ struct DevMat {
     int64_t *adm_cptr = nullptr, *adm_cblk = nullptr;    // admissible blocks by column cluster
     int64_t *near_cptr = nullptr, *near_cblk = nullptr;  // near-field blocks by column leaf
     int32_t *sys_of = nullptr;   // C, system of each cluster
+    int32_t *depth = nullptr;    // C, depth of each cluster
     int64_t *perm = nullptr;     // n
     double *pts = nullptr;       // n x 3 tree order
     double *box = nullptr;       // C x 6

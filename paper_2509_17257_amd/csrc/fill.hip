@@ -241,6 +241,7 @@ size_t mat_layout(const Plan &P, h2x_prec storage, DevMat *dm, char *base) {
     d.near_cptr = carve<int64_t>(cur, base, L + 1);
     d.near_cblk = carve<int64_t>(cur, base, nn + 1);
     d.sys_of = carve<int32_t>(cur, base, C);
+    d.depth = carve<int32_t>(cur, base, C);
     d.perm = carve<int64_t>(cur, base, n);
     d.pts = carve<double>(cur, base, 3 * n);
     d.box = carve<double>(cur, base, 6 * (size_t)C);

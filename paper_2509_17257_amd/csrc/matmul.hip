@@ -345,14 +345,27 @@ void matmul_mfma_f64(const DevMat &dm, const TuneCfg &cfg, int64_t m, double alp
         leaf(dm.side, beta, 0, 1, cap);
         (void)hipEventRecord(dm.ev_join, dm.side);
     }
-    hipLaunchKernelGGL(mfma::k_fwd_leaf<NJ>, dim3(dm.L, gy), dim3(256), 0, st, dm.k, m, dm.leaves, dm.first,
-                       dm.size, dm.perm, V, Xt, ldxt, 1, xh, ldh, sk);
-    mark(1);
-    for (int d = dm.depth_max - 1; d >= P.adm_depth; --d) {
-        const int32_t b = P.lvl_inner_ptr[d], e = P.lvl_inner_ptr[d + 1];
-        if (e > b)
-            hipLaunchKernelGGL(mfma::k_up<NJ>, dim3(e - b, gy), dim3(256), 0, st, dm.k, m, dm.lvl_inner + b,
-                               dm.son0, dm.son1, E, xh, ldh, sk);
+    if (cfg.fuse_up == 1) {
+        // one launch: leaves, then each parent by the work-group that finishes its second son
+        // (slower than level-by-level launches on this chip: every device-scope fence writes
+        // back the XCD's L2, so the built-in rule keeps it off)
+        int32_t *cnt = (int32_t *)(xt_ws + dm.n * even_ld(m));
+        const int64_t nc = (int64_t)dm.C * gy;
+        hipLaunchKernelGGL(mfma::k_zero_i32, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, st, nc, cnt);
+        hipLaunchKernelGGL(mfma::k_fwd_up<NJ>, dim3(8 * ((dm.L + 7) / 8), gy), dim3(256), 0, st, dm.k, m, dm.L,
+                           dm.leaves, dm.first, dm.size, V, Xt, ldxt, dm.parent, dm.son0, dm.son1, dm.depth,
+                           P.adm_depth, E, xh, ldh, cnt, sk);
+        mark(1);
+    } else {
+        hipLaunchKernelGGL(mfma::k_fwd_leaf<NJ>, dim3(dm.L, gy), dim3(256), 0, st, dm.k, m, dm.leaves, dm.first,
+                           dm.size, dm.perm, V, Xt, ldxt, 1, xh, ldh, sk);
+        mark(1);
+        for (int d = dm.depth_max - 1; d >= P.adm_depth; --d) {
+            const int32_t b = P.lvl_inner_ptr[d], e = P.lvl_inner_ptr[d + 1];
+            if (e > b)
+                hipLaunchKernelGGL(mfma::k_up<NJ>, dim3(e - b, gy), dim3(256), 0, st, dm.k, m, dm.lvl_inner + b,
+                                   dm.son0, dm.son1, E, xh, ldh, sk);
+        }
     }
     mark(2);
     launch_coupling_fast<double, double>(dm, m, xh, yh, ldh, st, sk, cfg.nj_coupling);
@@ -554,7 +567,10 @@ hipError_t run_down_pass(const DevMat &dm, int64_t m, double *yh, int64_t ldh, h
 
 size_t matmul_ws_bytes(const DevMat &dm, int64_t m) {
     // x-hat, y-hat, and the tree-ordered copy of X used by the matrix-core path
-    if (dm.storage == H2X_F64) return 2 * hat_bytes<double>(dm, m) + align_up(sizeof(double) * (size_t)dm.n * even_ld(m));
+    // (FP64: plus the per-parent counters of the fused upward pass, clusters x column slabs)
+    if (dm.storage == H2X_F64)
+        return 2 * hat_bytes<double>(dm, m) + align_up(sizeof(double) * (size_t)dm.n * even_ld(m)) +
+               align_up(sizeof(int32_t) * (size_t)dm.C * (size_t)((m + 15) / 16));
     // low precision: x-hat, y-hat, and the FP32 tree-ordered copy of X of the matrix-core leaf stage
     return 2 * hat_bytes<float>(dm, m) + (dm.near_t ? align_up(sizeof(float) * (size_t)dm.n * even_ld(m)) : 0);
 }

@@ -223,6 +223,74 @@ __global__ __launch_bounds__(256) void k_up(int k, int64_t m, const int32_t *__r
                 if (out_row(r) < k) xh[((int64_t)t * k + out_row(r)) * ldh + j0 + out_col(J)] = acc[J][r];
 }
 
+// Forward leaf transform and upward transfer pass in one launch: the work-group
+// of leaf t computes x_t = V_t^T X|_t, then walks up the tree.  At each parent
+// the work-group that finishes second (a device-scope counter per parent and
+// column slab; the results are published with device-scope fences before the
+// count) computes x_p = E_{s0}^T x_{s0} + E_{s1}^T x_{s1}; the first one stops.
+// Clusters above min_depth are not needed.  No work-group ever waits for
+// another.  cnt (clusters x column slabs) must be zero on entry.
+template <int NJ>
+__global__ __launch_bounds__(256) void k_fwd_up(int k, int64_t m, int32_t L, const int32_t *__restrict__ leaves,
+                                                const int32_t *__restrict__ first, const int32_t *__restrict__ size,
+                                                const double *__restrict__ V, const double *__restrict__ Xt,
+                                                int64_t ldxt, const int32_t *__restrict__ parent,
+                                                const int32_t *__restrict__ son0, const int32_t *__restrict__ son1,
+                                                const int32_t *__restrict__ depth, int min_depth,
+                                                const double *__restrict__ E, double *__restrict__ xh, int64_t ldh,
+                                                int32_t *__restrict__ cnt, Skip skip) {
+    __shared__ Smem<NJ> sm;
+    __shared__ int order;
+    const int32_t per_xcd = (L + 7) / 8;
+    const int32_t l = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+    if (l >= L) return;
+    const int32_t t = leaves[l];
+    if (skip(t)) return;
+    const int64_t j0 = (int64_t)blockIdx.y * Smem<NJ>::MC;
+    const int mc = (int)min<int64_t>(Smem<NJ>::MC, m - j0);
+    const int64_t r0 = first[t];
+    const int nt = size[t];
+    clear<NJ>(sm);
+    dbl4 acc[NJ];
+    zero<NJ>(acc);
+    accumulate<NJ>(sm, acc, (nt + 63) / 64, mc, k, [&](int q) {
+        const int i0 = 64 * q;
+        return Term{V + (r0 + i0) * k, k, min(64, nt - i0), k, true, Xt + j0, ldxt, nullptr, r0 + i0};
+    });
+    auto write = [&](int32_t c) {
+#pragma unroll
+        for (int J = 0; J < NJ; ++J)
+            if (out_col(J) < mc)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    if (out_row(r) < k) xh[((int64_t)c * k + out_row(r)) * ldh + j0 + out_col(J)] = acc[J][r];
+    };
+    write(t);
+    for (int32_t c = t;;) {
+        const int32_t p = parent[c];
+        if (p < 0 || depth[p] < min_depth) break;
+        __threadfence();  // publish x_c before counting it
+        __syncthreads();
+        if (threadIdx.x == 0) order = atomicAdd(&cnt[(int64_t)p * gridDim.y + blockIdx.y], 1);
+        __syncthreads();
+        if (order == 0) break;  // the sibling is not done yet; its work-group continues
+        __threadfence();        // see the sibling's x before reading it
+        zero<NJ>(acc);
+        const int32_t s0 = son0[p], s1 = son1[p];
+        accumulate<NJ>(sm, acc, 2, mc, k, [&](int q) {
+            const int32_t sn = q ? s1 : s0;
+            return Term{E + (int64_t)sn * k * k, k, k, k, true, xh + j0, ldh, nullptr, (int64_t)sn * k};
+        });
+        write(p);
+        c = p;
+    }
+}
+
+__global__ void k_zero_i32(int64_t count, int32_t *__restrict__ p) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < count) p[e] = 0;
+}
+
 // y_c += E_c y_parent(c) for the clusters in `list`
 template <int NJ>
 __global__ __launch_bounds__(256) void k_down(int k, int64_t m, const int32_t *__restrict__ list,

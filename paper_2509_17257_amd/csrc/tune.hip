@@ -107,6 +107,17 @@ h2x_status run_autotune(DevMat &dm, int64_t m, char *ws, size_t ws_bytes, hipStr
         }
     }
     if (e != hipSuccess) return done(e);
+    // forward leaf and upward pass fused into one launch or level by level
+    if (dm.mc) {
+        double sf[5], ss[5];
+        TuneCfg c = best;
+        c.fuse_up = 1;
+        e = time_cfg(c, sf);
+        c.fuse_up = 2;
+        if (e == hipSuccess) e = time_cfg(c, ss);
+        if (e != hipSuccess) return done(e);
+        best.fuse_up = (sf[0] + sf[1] <= ss[0] + ss[1]) ? 1 : 2;
+    }
     // near field concurrent with the transfer passes (it changes the time of several
     // stages, so the whole product decides)
     if (dm.side) {
@@ -134,6 +145,7 @@ h2x_status run_autotune(DevMat &dm, int64_t m, char *ws, size_t ws_bytes, hipStr
         info->nj_coupling = dm.tuned[b].nj_coupling;
         info->np_leaf = dm.tuned[b].np_leaf;
         info->overlap = dm.tuned[b].overlap;
+        info->fuse_up = dm.tuned[b].fuse_up;
         info->ms_default = total(s0);
         info->ms_tuned = use ? total(s1) : total(s0);
     }

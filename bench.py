@@ -338,6 +338,67 @@ def batch_report(args, torch, h2x, W):
     print(json.dumps(out), flush=True)
 
 
+def mm_report(args, torch, h2x, W):
+    """Multi-vector product against repeated single-vector products (the paper's
+    H^2-MM experiment, section 4): on the FP64 sphere workload (n = 65536, k = 64), one
+    product with m columns against m products with one column each, for
+    m = 1, 10, 50, 100, 200; and the single-vector bandwidth for growing n.  Both byte
+    conventions: algorithmic bytes (matrix once, X read, Y written) and the paper's
+    effective bytes, m times (matrix + 3 n doubles)."""
+    dev = torch.device("cuda:0")
+    out = {"workload": "sphere, exp(-r/0.5) + I, leaf 64, eta 1, k 64 (FP64)", "mm_vs_mvm": [], "mvm_vs_n": []}
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    def matrix_bytes(plan):
+        k = plan.k
+        return 8 * (plan.n * k + (plan.C - 1) * k * k + plan.n_adm * k * k) + 8 * plan.near_entries
+
+    P = W.sphere_points(65536, 1001)
+    A = h2x.H2Matrix(P, device=dev, ell=0.5, shift=1.0, eta=1.0, leaf=64, p=4)
+    plan = A.plan
+    mb = matrix_bytes(plan)
+    reps = max(3, min(args.steps, 20))
+    for m in (1, 10, 50, 100, 200):
+        if args.autotune:
+            A.autotune(m)
+        X = torch.from_numpy(W.rhs(plan.n, m, 7000 + m)).to(dev)
+        Y = torch.empty_like(X)
+        ms_mm = timed(lambda: h2x.h2_matmul(A, X, out=Y), reps)
+        cols = [X[:, j:j + 1].contiguous() for j in range(m)]
+        outs = [torch.empty_like(c) for c in cols]
+
+        def mvm():
+            for c, o in zip(cols, outs):
+                h2x.h2_matmul(A, c, out=o)
+        ms_mvm = timed(mvm, max(1, reps // 4))
+        rec = {"m": m, "ms_mm": round(ms_mm, 4), "ms_m_mvm": round(ms_mvm, 4), "speedup": round(ms_mvm / ms_mm, 2),
+               "alg_gbs_mm": round(alg_bytes(plan, m) / (ms_mm * 1e-3) / 1e9, 1),
+               "paper_convention_gbs_mm": round(m * (mb + 3 * 8 * plan.n) / (ms_mm * 1e-3) / 1e9, 1)}
+        out["mm_vs_mvm"].append(rec)
+        log(f"[mm] {rec}")
+    del A
+    for n in (4096, 16384, 65536, 262144):
+        A = h2x.H2Matrix(W.sphere_points(n, 7100 + n % 97), device=dev, ell=0.5, shift=1.0, eta=1.0, leaf=64, p=4)
+        x = torch.from_numpy(W.rhs(n, 1, 7200)).to(dev)
+        y = torch.empty_like(x)
+        ms = timed(lambda: h2x.h2_matmul(A, x, out=y), reps)
+        rec = {"n": n, "ms": round(ms, 4), "alg_gbs": round(alg_bytes(A.plan, 1) / (ms * 1e-3) / 1e9, 1)}
+        out["mvm_vs_n"].append(rec)
+        log(f"[mm] {rec}")
+        del A
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -350,6 +411,8 @@ def main():
     ap.add_argument("--cpu-baseline-s", type=float, default=12.0, help="0 disables the oracle timing")
     ap.add_argument("--precision-report", action="store_true",
                     help="report FP64 / FP32 / BF16 products and FP64 vs refined block CG on the precision workload")
+    ap.add_argument("--mm-report", action="store_true",
+                    help="multi-vector product against repeated single-vector products (m = 1..200)")
     ap.add_argument("--batch-report", action="store_true",
                     help="batched products and block CG over the 64-system batching workload")
     ap.add_argument("--grad-report", action="store_true",
@@ -399,6 +462,9 @@ def main():
         return
     if args.batch_report:
         batch_report(args, torch, h2x, W)
+        return
+    if args.mm_report:
+        mm_report(args, torch, h2x, W)
         return
 
     w = W.WORKLOADS[args.workload]

@@ -36,13 +36,16 @@ __global__ __launch_bounds__(256) void k_coupling_mfma_f32(int64_t m, int32_t C,
                                                            float *__restrict__ yh, int64_t ldh, Skip skip) {
     constexpr int K = 64, MC = 16 * NJ, LDX = MC + 1;
     __shared__ float xs[2][K * LDX];
-    const int slot = (blockIdx.x & 7) * rows_per_xcd + (blockIdx.x >> 3);
+    // the column slabs of one row cluster are consecutive work-groups of one XCD, so S_b
+    // comes from HBM once and from that XCD's L2 for the other slabs
+    const int nslab = (int)((m + MC - 1) / MC), qx = blockIdx.x >> 3;
+    const int slot = (blockIdx.x & 7) * rows_per_xcd + qx / nslab;
     if (slot >= C) return;
     const int32_t t = order[slot];
     if (skip(t)) return;
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     const int lr = lane & 15, g = lane >> 4;
-    const int64_t j0 = (int64_t)blockIdx.y * MC;
+    const int64_t j0 = (int64_t)(qx % nslab) * MC;
     const int mc = (int)min<int64_t>(MC, m - j0);
     const int64_t b0 = adm_ptr[t], b1 = adm_ptr[t + 1];
 
@@ -124,13 +127,16 @@ __global__ __launch_bounds__(256) void k_coupling_mfma_bf16(int64_t m, int32_t C
     constexpr int K = 64, MC = 16 * NJ;
     constexpr int LDT = K + 8;  // LDS row (one column of x_s) in bf16 units, padded against bank conflicts
     __shared__ uint16_t xs[2][MC * LDT];
-    const int slot = (blockIdx.x & 7) * rows_per_xcd + (blockIdx.x >> 3);
+    // the column slabs of one row cluster are consecutive work-groups of one XCD, so S_b
+    // comes from HBM once and from that XCD's L2 for the other slabs
+    const int nslab = (int)((m + MC - 1) / MC), qx = blockIdx.x >> 3;
+    const int slot = (blockIdx.x & 7) * rows_per_xcd + qx / nslab;
     if (slot >= C) return;
     const int32_t t = order[slot];
     if (skip(t)) return;
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     const int lr = lane & 15, g = lane >> 4;
-    const int64_t j0 = (int64_t)blockIdx.y * MC;
+    const int64_t j0 = (int64_t)(qx % nslab) * MC;
     const int mc = (int)min<int64_t>(MC, m - j0);
     const int64_t b0 = adm_ptr[t], b1 = adm_ptr[t + 1];
 
@@ -210,7 +216,7 @@ bool launch_coupling_lp(const DevMat &dm, int64_t m, const float *xh, float *yh,
     if (dm.k != 64 || !dm.cpl_order || dm.swz != (f32 ? 2 : 3)) return false;
     const int nj = nj_force ? nj_force : (int)std::min<int64_t>(4, (m + 15) / 16);
     const int32_t rpx = (dm.C + 7) / 8;
-    const dim3 grid((unsigned)(8 * rpx), (unsigned)((m + 16 * nj - 1) / (16 * nj)));
+    const dim3 grid((unsigned)(8 * rpx * ((m + 16 * nj - 1) / (16 * nj))));
     auto go = [&](auto NJc) {
         constexpr int NJ = decltype(NJc)::value;
         if constexpr (std::is_same<T, float>::value)

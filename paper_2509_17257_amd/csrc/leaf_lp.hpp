@@ -48,8 +48,12 @@ __global__ __launch_bounds__(256, 2) void k_leaf_lp(int k, int64_t m, int32_t L,
                                                     int64_t ldy, int tree_order, int round_y, Skip skip) {
     constexpr int MC = 32 * NP, LDR = MC + 1;
     __shared__ float red[64 * LDR];
+    // one (leaf, column slab) per work-group; the slabs of one leaf are consecutive
+    // work-groups of one XCD, so its near blocks come from HBM once
     const int32_t per_xcd = (L + 7) / 8;
-    const int32_t l = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+    const int nslab = (int)((m + MC - 1) / MC);
+    const int64_t qx = blockIdx.x >> 3;
+    const int32_t l = (int32_t)((blockIdx.x & 7) * per_xcd + qx / nslab);
     if (l >= L) return;
     const int32_t t = leaves[l];
     if (skip(t)) return;
@@ -57,7 +61,7 @@ __global__ __launch_bounds__(256, 2) void k_leaf_lp(int k, int64_t m, int32_t L,
     const int64_t nt2 = nt + (nt & 1);
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, lq = lane >> 4;
     const int64_t r0 = first[t];
-    const int64_t j0 = (int64_t)blockIdx.y * MC;
+    const int64_t j0 = (qx % nslab) * MC;
     const int mc = (int)min<int64_t>(MC, m - j0);
     bool col_ok[NP];
 #pragma unroll

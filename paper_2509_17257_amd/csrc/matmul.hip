@@ -320,15 +320,15 @@ void matmul_mfma_f64(const DevMat &dm, const TuneCfg &cfg, int64_t m, double alp
     const Skip sk{skip, dm.sys_of};
     const unsigned gl = (unsigned)((m + 32 * NP - 1) / (32 * NP));
     auto leaf = [&](hipStream_t s, double b, int basis, int near, unsigned cap) {
-        unsigned gx = 8 * ((dm.L + 7) / 8);
+        unsigned gx = 8 * ((dm.L + 7) / 8) * gl;
         if (cap) gx = std::min(gx, cap);
         if (NP == 2)
-            hipLaunchKernelGGL(mfma::k_leaf_direct<2>, dim3(gx, gl), dim3(256), 0, s, dm.k, m,
+            hipLaunchKernelGGL(mfma::k_leaf_direct<2>, dim3(gx), dim3(256), 0, s, dm.k, m,
                                dm.L, dm.leaves, dm.first, dm.size, dm.perm, (const double *)dm.Vt, dm.vt_off, yh, ldh,
                                dm.near_ptr, dm.near_col, dm.near_off, (const double *)dm.N, Xt, ldxt, alpha, b, Y,
                                ldy, to, basis, near, sk);
         else
-            hipLaunchKernelGGL(mfma::k_leaf_direct<1>, dim3(gx, gl), dim3(256), 0, s, dm.k, m,
+            hipLaunchKernelGGL(mfma::k_leaf_direct<1>, dim3(gx), dim3(256), 0, s, dm.k, m,
                                dm.L, dm.leaves, dm.first, dm.size, dm.perm, (const double *)dm.Vt, dm.vt_off, yh, ldh,
                                dm.near_ptr, dm.near_col, dm.near_off, (const double *)dm.N, Xt, ldxt, alpha, b, Y,
                                ldy, to, basis, near, sk);
@@ -461,12 +461,12 @@ hipError_t matmul_typed(const DevMat &dm, const TuneCfg &cfg, int64_t m, double 
             const int rb = std::is_same<T, bf16_t>::value ? 1 : 0;
             const unsigned gl8 = 8 * ((dm.L + 7) / 8);
             if (cfg.np_leaf ? cfg.np_leaf == 2 : m > 32)
-                hipLaunchKernelGGL((lp::k_leaf_lp<2, T>), dim3(gl8, (unsigned)((m + 63) / 64)), dim3(256), 0, st,
+                hipLaunchKernelGGL((lp::k_leaf_lp<2, T>), dim3(gl8 * (unsigned)((m + 63) / 64)), dim3(256), 0, st,
                                    dm.k, m, dm.L, dm.leaves, dm.first, dm.size, dm.perm, (const T *)dm.Vt, dm.vt_off,
                                    yh, ldh, dm.near_ptr, dm.near_col, dm.near_off, (const float *)dm.N, xt, ldxt,
                                    alpha, beta, Y, ldy, to, rb, sk);
             else
-                hipLaunchKernelGGL((lp::k_leaf_lp<1, T>), dim3(gl8, (unsigned)((m + 31) / 32)), dim3(256), 0, st,
+                hipLaunchKernelGGL((lp::k_leaf_lp<1, T>), dim3(gl8 * (unsigned)((m + 31) / 32)), dim3(256), 0, st,
                                    dm.k, m, dm.L, dm.leaves, dm.first, dm.size, dm.perm, (const T *)dm.Vt, dm.vt_off,
                                    yh, ldh, dm.near_ptr, dm.near_col, dm.near_off, (const float *)dm.N, xt, ldxt,
                                    alpha, beta, Y, ldy, to, rb, sk);

@@ -39,13 +39,16 @@ __global__ __launch_bounds__(256) void k_coupling_mfma_f64(int64_t m, int32_t C,
     constexpr int MC = 16 * NJ;   // columns per work-group
     constexpr int LDX = MC + 1;   // padded LDS row
     __shared__ double xs[2][kMfmaK * LDX];
-    const int slot = (blockIdx.x & 7) * rows_per_xcd + (blockIdx.x >> 3);
+    // the column slabs of one row cluster are consecutive work-groups of one XCD, so S_b
+    // comes from HBM once and from that XCD's L2 for the other slabs
+    const int nslab = (int)((m + MC - 1) / MC), qx = blockIdx.x >> 3;
+    const int slot = (blockIdx.x & 7) * rows_per_xcd + qx / nslab;
     if (slot >= C) return;
     const int32_t t = order[slot];
     if (skip(t)) return;
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     const int lr = lane & 15, lq = lane >> 4;
-    const int64_t j0 = (int64_t)blockIdx.y * MC;
+    const int64_t j0 = (int64_t)(qx % nslab) * MC;
     const int mc = (int)min<int64_t>(MC, m - j0);
     const int64_t b0 = adm_ptr[t], b1 = adm_ptr[t + 1];
 
@@ -147,13 +150,16 @@ __global__ __launch_bounds__(128) void k_coupling_mfma_small(int k, int64_t m, i
     constexpr int MC = 16 * NJ;
     constexpr int LDX = MC + 1;
     __shared__ double xs[2][32 * LDX];
-    const int slot = (blockIdx.x & 7) * rows_per_xcd + (blockIdx.x >> 3);
+    // the column slabs of one row cluster are consecutive work-groups of one XCD, so S_b
+    // comes from HBM once and from that XCD's L2 for the other slabs
+    const int nslab = (int)((m + MC - 1) / MC), qx = blockIdx.x >> 3;
+    const int slot = (blockIdx.x & 7) * rows_per_xcd + qx / nslab;
     if (slot >= C) return;
     const int32_t t = order[slot];
     if (skip(t)) return;
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     const int lr = lane & 15, g = lane >> 4;
-    const int64_t j0 = (int64_t)blockIdx.y * MC;
+    const int64_t j0 = (int64_t)(qx % nslab) * MC;
     const int mc = (int)min<int64_t>(MC, m - j0);
     const int64_t b0 = adm_ptr[t], b1 = adm_ptr[t + 1];
     const int nq = (k + 7) >> 3;          // pairs of k-steps (8 columns of S each)
@@ -256,7 +262,7 @@ bool launch_coupling_fast(const DevMat &dm, int64_t m, const Acc *xh, Acc *yh, i
         const int nj = nj_force ? nj_force : (int)std::min<int64_t>(4, (m + 15) / 16);
         const int mcols = 16 * nj;
         const int32_t rpx = (dm.C + 7) / 8;
-        const dim3 grid((unsigned)(8 * rpx), (unsigned)((m + mcols - 1) / mcols));
+        const dim3 grid((unsigned)(8 * rpx * ((m + mcols - 1) / mcols)));
         const double *S = (const double *)dm.S;
         if (dm.k <= 32) {
             auto go = [&](auto NJc) {

@@ -358,10 +358,13 @@ __global__ __launch_bounds__(256, NP == 1 ? 2 : 1) void k_leaf_direct(int k, int
     constexpr int MC = 32 * NP, LDR = MC + 1;
     __shared__ double red[64 * LDR];
     const int32_t per_xcd = (L + 7) / 8;
-    // one leaf per work-group, or (a capped grid) leaves in a grid-stride loop; a slot
-    // keeps its XCD because the grid is a multiple of 8
-    for (int32_t slot = blockIdx.x; slot < 8 * per_xcd; slot += gridDim.x) {
-        const int32_t l = (slot & 7) * per_xcd + (slot >> 3);
+    const int nslab = (int)((m + MC - 1) / MC);
+    // one (leaf, column slab) per work-group, or (a capped grid) a grid-stride loop over
+    // them; a slot keeps its XCD because the grid is a multiple of 8, and the slabs of one
+    // leaf are consecutive slots of one XCD, so its near blocks come from HBM once
+    for (int64_t slot = blockIdx.x; slot < (int64_t)8 * per_xcd * nslab; slot += gridDim.x) {
+        const int64_t qx = slot >> 3;
+        const int32_t l = (int32_t)((slot & 7) * per_xcd + qx / nslab);
         if (l >= L) continue;
         const int32_t t = leaves[l];
         if (skip(t)) continue;
@@ -369,7 +372,7 @@ __global__ __launch_bounds__(256, NP == 1 ? 2 : 1) void k_leaf_direct(int k, int
         const int64_t nt2 = nt + (nt & 1);
         const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, lq = lane >> 4;
         const int64_t r0 = first[t];
-        const int64_t j0 = (int64_t)blockIdx.y * MC;
+        const int64_t j0 = (qx % nslab) * MC;
         const int mc = (int)min<int64_t>(MC, m - j0);
         bool col_ok[NP];
     #pragma unroll

@@ -61,14 +61,14 @@ __global__ __launch_bounds__(256) void k_coupling_mfma_f32(int64_t m, int32_t C,
 #pragma unroll
             for (int u = 0; u < XPT; ++u) {
                 const int e = tid + 256 * u, r = e / MC, c = e % MC;
-                xv[u] = c < mc ? src[(int64_t)r * ldh + c] : 0.f;
+                xv[u] = src[(int64_t)r * ldh + (c < mc ? c : 0)];  // columns past mc: zeroed when stored
             }
         };
         auto store_x = [&](int buf) {
 #pragma unroll
             for (int u = 0; u < XPT; ++u) {
                 const int e = tid + 256 * u, r = e / MC, c = e % MC;
-                xs[buf][r * LDX + c] = xv[u];
+                xs[buf][r * LDX + c] = c < mc ? xv[u] : 0.f;
             }
         };
         flt4 sa[4], sn[4];
@@ -78,17 +78,7 @@ __global__ __launch_bounds__(256) void k_coupling_mfma_f32(int64_t m, int32_t C,
             for (int a = 0; a < 4; ++a) dst[a] = __builtin_nontemporal_load(src + a * 64);
         };
 
-        load_x(adm_col[b0]);
-        load_s(b0, sa);
-        store_x(0);
-        __syncthreads();
-        for (int64_t b = b0; b < b1; ++b) {
-            const int buf = (int)((b - b0) & 1);
-            const bool more = b + 1 < b1;
-            if (more) {
-                load_x(adm_col[b + 1]);
-                load_s(b + 1, sn);
-            }
+        auto multiply = [&](int buf) {
             const float *xb = xs[buf];
 #pragma unroll
             for (int a = 0; a < 4; ++a)
@@ -100,13 +90,25 @@ __global__ __launch_bounds__(256) void k_coupling_mfma_f32(int64_t m, int32_t C,
                         acc[J] = __builtin_amdgcn_mfma_f32_16x16x4f32(sa[a][h], xb[krow * LDX + 16 * J + lr], acc[J],
                                                                        0, 0, 0);
                 }
-            if (more) {
-                store_x(buf ^ 1);
+        };
+
+        load_x(adm_col[b0]);
+        load_s(b0, sa);
+        store_x(0);
+        __syncthreads();
+        // unconditional loads and a peeled last block: the compiler's wait counters stay
+        // exact, so the MFMAs never wait for the block being prefetched
+        for (int64_t b = b0; b + 1 < b1; ++b) {
+            const int buf = (int)((b - b0) & 1);
+            load_x(adm_col[b + 1]);
+            load_s(b + 1, sn);
+            multiply(buf);
+            store_x(buf ^ 1);
 #pragma unroll
-                for (int a = 0; a < 4; ++a) sa[a] = sn[a];
-            }
+            for (int a = 0; a < 4; ++a) sa[a] = sn[a];
             __syncthreads();
         }
+        multiply((int)((b1 - 1 - b0) & 1));
     }
 #pragma unroll
     for (int J = 0; J < NJ; ++J) {
@@ -152,14 +154,14 @@ __global__ __launch_bounds__(256) void k_coupling_mfma_bf16(int64_t m, int32_t C
 #pragma unroll
             for (int u = 0; u < XPT; ++u) {
                 const int e = tid + 256 * u, r = e / MC, c = e % MC;
-                xv[u] = c < mc ? src[(int64_t)r * ldh + c] : 0.f;
+                xv[u] = src[(int64_t)r * ldh + (c < mc ? c : 0)];  // columns past mc: zeroed when stored
             }
         };
         auto store_x = [&](int buf) {  // transposed: column c of x_s is LDS row c
 #pragma unroll
             for (int u = 0; u < XPT; ++u) {
                 const int e = tid + 256 * u, r = e / MC, c = e % MC;
-                xs[buf][c * LDT + r] = bf16_bits(xv[u]);
+                xs[buf][c * LDT + r] = bf16_bits(c < mc ? xv[u] : 0.f);
             }
         };
         u32x4 sa[2], sn[2];
@@ -169,17 +171,7 @@ __global__ __launch_bounds__(256) void k_coupling_mfma_bf16(int64_t m, int32_t C
             for (int c = 0; c < 2; ++c) dst[c] = __builtin_nontemporal_load(src + c * 64);
         };
 
-        load_x(adm_col[b0]);
-        load_s(b0, sa);
-        store_x(0);
-        __syncthreads();
-        for (int64_t b = b0; b < b1; ++b) {
-            const int buf = (int)((b - b0) & 1);
-            const bool more = b + 1 < b1;
-            if (more) {
-                load_x(adm_col[b + 1]);
-                load_s(b + 1, sn);
-            }
+        auto multiply = [&](int buf) {
             const uint16_t *xb = xs[buf];
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
@@ -191,13 +183,24 @@ __global__ __launch_bounds__(256) void k_coupling_mfma_bf16(int64_t m, int32_t C
                                                                       0, 0);
                 }
             }
-            if (more) {
-                store_x(buf ^ 1);
-                sa[0] = sn[0];
-                sa[1] = sn[1];
-            }
+        };
+
+        load_x(adm_col[b0]);
+        load_s(b0, sa);
+        store_x(0);
+        __syncthreads();
+        // unconditional loads and a peeled last block, as in the FP32 kernel
+        for (int64_t b = b0; b + 1 < b1; ++b) {
+            const int buf = (int)((b - b0) & 1);
+            load_x(adm_col[b + 1]);
+            load_s(b + 1, sn);
+            multiply(buf);
+            store_x(buf ^ 1);
+            sa[0] = sn[0];
+            sa[1] = sn[1];
             __syncthreads();
         }
+        multiply((int)((b1 - 1 - b0) & 1));
     }
 #pragma unroll
     for (int J = 0; J < NJ; ++J) {

@@ -33,6 +33,8 @@ template <int NP>
 struct Round {
     flt2 b[2][4];   // [row half g][k-step u]: rows 32g + 2 lr + {0, 1}
     flt2 a[NP][4];  // [column half p][k-step u]: columns 32p + 2 lr + {0, 1}
+    int kb, kl;     // first k-step of the round and the item's length
+    bool basis;     // the round belongs to the basis term
 };
 
 template <int NP, typename TV>
@@ -59,14 +61,12 @@ __global__ __launch_bounds__(256, 2) void k_leaf_lp(int k, int64_t m, int32_t L,
     if (skip(t)) return;
     const int nt = size[t];
     const int64_t nt2 = nt + (nt & 1);
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, lq = lane >> 4;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63, lr = lane & 15,
+                  lq = lane >> 4;  // w is wave-uniform: item loops stay scalar
     const int64_t r0 = first[t];
     const int64_t j0 = (qx % nslab) * MC;
     const int mc = (int)min<int64_t>(MC, m - j0);
-    bool col_ok[NP];
-#pragma unroll
-    for (int p = 0; p < NP; ++p) col_ok[p] = 32 * p + 2 * lr < mc;
-    const int64_t q0 = near_ptr[l];
+    const int64_t q0 = near_ptr[l], vt0 = vt_off[l];
     // items: the basis term, then the near blocks
     const int nnear = (int)(near_ptr[l + 1] - q0);
     const int nitems = nnear + 1;
@@ -87,60 +87,57 @@ __global__ __launch_bounds__(256, 2) void k_leaf_lp(int k, int64_t m, int32_t L,
             fs = m_first[x];
             ks = m_size[x];
         } else {
-            const int32_t s = near_col[q0 + x];
-            off = near_off[q0 + x];
-            fs = first[s];
-            ks = size[s];
+            // relaxed atomic loads: the compiler cannot fold this path and the LDS path
+            // into one load through a generic pointer
+            const int32_t s = __hip_atomic_load(near_col + q0 + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            off = __hip_atomic_load(near_off + q0 + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            fs = __hip_atomic_load(first + s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            ks = __hip_atomic_load(size + s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     };
 
     for (int i0 = 0; i0 < nt; i0 += 64) {
         const int ic = min(64, nt - i0);
         const int nhalf = (ic + 31) >> 5;
-        bool row_ok[2];
-#pragma unroll
-        for (int g = 0; g < 2; ++g) row_ok[g] = 32 * g + 2 * lr < ic;
         flt4v acc[2 * NP][4];
 #pragma unroll
         for (int J = 0; J < 2 * NP; ++J)
 #pragma unroll
             for (int I = 0; I < 4; ++I) acc[J][I] = flt4v{0.f, 0.f, 0.f, 0.f};
 
+        // unconditional loads from clamped addresses, the k-mask (and the BF16 rounding
+        // of y_t) applied once a round's loads are in, and the last round peeled off: the
+        // MFMAs of a round never wait for the next round's loads (as in the FP64 kernel)
+        const int xr = (ic - 1) & ~1, xc = (mc - 1) & ~1;
         auto load = [&](int e, int kb, Round<NP> &R) {
-            int kl;
-            if (e == 0) {
-                const TV *bb = Vt + vt_off[l] + i0 + 2 * lr;              // V_t^T[nu][i]
-                const float *ab = yh + (int64_t)t * k * ldh + j0 + 2 * lr;  // y_t[nu][j]
-                kl = k;
+            R.kb = kb;
+            R.basis = e == 0;
+            if (e == 0) {  // wave-uniform: both paths issue the same loads
+                const TV *bb = Vt + vt0 + i0;                   // V_t^T[nu][i]
+                const float *ab = yh + (int64_t)t * k * ldh + j0;  // y_t[nu][j]
+                R.kl = k;
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
-                    const int c = kb + 4 * u + lq;
-                    const bool cok = c < kl;
+                    const int c = min(kb + 4 * u + lq, k - 1);
 #pragma unroll
-                    for (int g = 0; g < 2; ++g)
-                        R.b[g][u] = (cok && row_ok[g]) ? ld2(bb + c * nt2 + 32 * g) : flt2{0.f, 0.f};
+                    for (int g = 0; g < 2; ++g) R.b[g][u] = ld2(bb + c * nt2 + min(32 * g + 2 * lr, xr));
 #pragma unroll
-                    for (int p = 0; p < NP; ++p) {
-                        flt2 v = (cok && col_ok[p]) ? ld2(ab + c * ldh + 32 * p) : flt2{0.f, 0.f};
-                        if (round_y) v = flt2{round_bf16(v.x), round_bf16(v.y)};
-                        R.a[p][u] = v;
-                    }
+                    for (int p = 0; p < NP; ++p) R.a[p][u] = ld2(ab + c * ldh + min(32 * p + 2 * lr, xc));
                 }
             } else {
                 int64_t off, fs;
+                int kl;
                 near_meta(e - 1, off, fs, kl);
-                const float *bb = Nt + off + i0 + 2 * lr;       // N_ts^T[c][i]
-                const float *ab = Xt + fs * ldxt + j0 + 2 * lr;  // X_s[c][j]
+                const float *bb = Nt + off + i0;       // N_ts^T[c][i]
+                const float *ab = Xt + fs * ldxt + j0;  // X_s[c][j]
+                R.kl = kl;
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
-                    const int c = kb + 4 * u + lq;
-                    const bool cok = c < kl;
+                    const int c = min(kb + 4 * u + lq, kl - 1);
 #pragma unroll
-                    for (int g = 0; g < 2; ++g)
-                        R.b[g][u] = (cok && row_ok[g]) ? ld2(bb + c * nt2 + 32 * g) : flt2{0.f, 0.f};
+                    for (int g = 0; g < 2; ++g) R.b[g][u] = ld2(bb + c * nt2 + min(32 * g + 2 * lr, xr));
 #pragma unroll
-                    for (int p = 0; p < NP; ++p)
-                        R.a[p][u] = (cok && col_ok[p]) ? ld2(ab + c * ldxt + 32 * p) : flt2{0.f, 0.f};
+                    for (int p = 0; p < NP; ++p) R.a[p][u] = ld2(ab + c * ldxt + min(32 * p + 2 * lr, xc));
                 }
             }
         };
@@ -151,12 +148,40 @@ __global__ __launch_bounds__(256, 2) void k_leaf_lp(int k, int64_t m, int32_t L,
             near_meta(e - 1, off, fs, ks);
             return ks;
         };
+        auto mask = [&](Round<NP> &R) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const bool cok = R.kb + 4 * u + lq < R.kl;
+#pragma unroll
+                for (int p = 0; p < NP; ++p) {
+                    flt2 v = cok ? R.a[p][u] : flt2{0.f, 0.f};
+                    if (round_y && R.basis) v = flt2{round_bf16(v.x), round_bf16(v.y)};
+                    R.a[p][u] = v;
+                }
+            }
+        };
+        auto multiply = [&](const Round<NP> &R) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int g = 0; g < 2; ++g)
+                    if (g < nhalf)
+#pragma unroll
+                        for (int h = 0; h < 2; ++h)
+#pragma unroll
+                            for (int p = 0; p < NP; ++p)
+#pragma unroll
+                                for (int hj = 0; hj < 2; ++hj)
+                                    acc[2 * p + hj][2 * g + h] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                                        R.a[p][u][hj], R.b[g][u][h], acc[2 * p + hj][2 * g + h], 0, 0, 0);
+        };
 
         int e = w;
         if (e < nitems) {
             Round<NP> cur, nxt;
             int kb = 0, len = klen(e);
             load(e, kb, cur);
+            mask(cur);
             for (;;) {
                 int en = e, kbn = kb + 16, lenn = len;
                 if (kbn >= len) {
@@ -164,27 +189,16 @@ __global__ __launch_bounds__(256, 2) void k_leaf_lp(int k, int64_t m, int32_t L,
                     kbn = 0;
                     if (en < nitems) lenn = klen(en);
                 }
-                const bool more = en < nitems;
-                if (more) load(en, kbn, nxt);
-#pragma unroll
-                for (int u = 0; u < 4; ++u)
-#pragma unroll
-                    for (int g = 0; g < 2; ++g)
-                        if (g < nhalf)
-#pragma unroll
-                            for (int h = 0; h < 2; ++h)
-#pragma unroll
-                                for (int p = 0; p < NP; ++p)
-#pragma unroll
-                                    for (int hj = 0; hj < 2; ++hj)
-                                        acc[2 * p + hj][2 * g + h] = __builtin_amdgcn_mfma_f32_16x16x4f32(
-                                            cur.a[p][u][hj], cur.b[g][u][h], acc[2 * p + hj][2 * g + h], 0, 0, 0);
-                if (!more) break;
+                if (en >= nitems) break;
+                load(en, kbn, nxt);
+                multiply(cur);
                 cur = nxt;
+                mask(cur);
                 e = en;
                 kb = kbn;
                 len = lenn;
             }
+            multiply(cur);
         }
         // tile (J = 2p + hj, I = 2g + h): register q of lane l -> column 32p + 2 (4 (l / 16) + q) + hj,
         // row 32g + 2 (l % 16) + h

@@ -65,14 +65,14 @@ __global__ __launch_bounds__(256) void k_coupling_mfma_f64(int64_t m, int32_t C,
 #pragma unroll
             for (int u = 0; u < XPT; ++u) {
                 const int e = tid + 256 * u, r = e / MC, c = e % MC;
-                xv[u] = c < mc ? src[(int64_t)r * ldh + c] : 0.0;
+                xv[u] = src[(int64_t)r * ldh + (c < mc ? c : 0)];  // columns past mc: zeroed when stored
             }
         };
         auto store_x = [&](int buf) {
 #pragma unroll
             for (int u = 0; u < XPT; ++u) {
                 const int e = tid + 256 * u, r = e / MC, c = e % MC;
-                xs[buf][r * LDX + c] = xv[u];
+                xs[buf][r * LDX + c] = c < mc ? xv[u] : 0.0;
             }
         };
         typedef double dbl2 __attribute__((ext_vector_type(2)));
@@ -83,17 +83,7 @@ __global__ __launch_bounds__(256) void k_coupling_mfma_f64(int64_t m, int32_t C,
             for (int kk2 = 0; kk2 < 8; ++kk2) dst[kk2] = __builtin_nontemporal_load(src + kk2 * 64);
         };
 
-        load_x(adm_col[b0]);
-        load_s(b0, sa);
-        store_x(0);
-        __syncthreads();
-        for (int64_t b = b0; b < b1; ++b) {
-            const int buf = (int)((b - b0) & 1);
-            const bool more = b + 1 < b1;
-            if (more) {
-                load_x(adm_col[b + 1]);
-                load_s(b + 1, sn);
-            }
+        auto multiply = [&](int buf) {
             const double *xb = xs[buf];
 #pragma unroll
             for (int kk2 = 0; kk2 < 8; ++kk2) {
@@ -108,13 +98,26 @@ __global__ __launch_bounds__(256) void k_coupling_mfma_f64(int64_t m, int32_t C,
                     }
                 }
             }
-            if (more) {
-                store_x(buf ^ 1);
+        };
+
+        load_x(adm_col[b0]);
+        load_s(b0, sa);
+        store_x(0);
+        __syncthreads();
+        // every load of the loop is unconditional (bounds handled by clamped addresses and
+        // selects) and the last block is peeled off, so the compiler's wait counters are
+        // exact: the MFMAs wait only for the current block, never for the prefetch
+        for (int64_t b = b0; b + 1 < b1; ++b) {
+            const int buf = (int)((b - b0) & 1);
+            load_x(adm_col[b + 1]);
+            load_s(b + 1, sn);
+            multiply(buf);
+            store_x(buf ^ 1);
 #pragma unroll
-                for (int kk2 = 0; kk2 < 8; ++kk2) sa[kk2] = sn[kk2];
-            }
+            for (int kk2 = 0; kk2 < 8; ++kk2) sa[kk2] = sn[kk2];
             __syncthreads();
         }
+        multiply((int)((b1 - 1 - b0) & 1));
     }
     // D layout of the 16x16x4 f64 MFMA: lane l, register r -> row l / 16 + 4 r, column l % 16
 #pragma unroll
@@ -178,39 +181,31 @@ __global__ __launch_bounds__(128) void k_coupling_mfma_small(int k, int64_t m, i
 #pragma unroll
             for (int u = 0; u < XPT; ++u) {
                 const int e = tid + 128 * u, r = e / MC, c = e % MC;
-                xv[u] = (r < k && c < mc) ? src[(int64_t)r * ldh + c] : 0.0;
+                xv[u] = src[(r < k && c < mc) ? (int64_t)r * ldh + c : 0];  // zeroed when stored
             }
         };
         auto store_x = [&](int buf) {
 #pragma unroll
             for (int u = 0; u < XPT; ++u) {
                 const int e = tid + 128 * u, r = e / MC, c = e % MC;
-                xs[buf][r * LDX + c] = xv[u];
+                xs[buf][r * LDX + c] = (r < k && c < mc) ? xv[u] : 0.0;
             }
         };
         double sa[4][2], sn[4][2];
         auto load_s = [&](int64_t b, double (*dst)[2]) {
-            const double *src = S + b * k * k + (int64_t)nu * k;
+            const double *src = S + b * k * k + (int64_t)(row_ok ? nu : 0) * k;
 #pragma unroll
             for (int q = 0; q < 4; ++q)
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
+                    // a lane past the last column reads column 0 instead: it multiplies a zero
+                    // row of x_s, and rows past k are never written
                     const int mu = 8 * q + 2 * g + h;
-                    dst[q][h] = (row_ok && mu < k) ? __builtin_nontemporal_load(src + mu) : 0.0;
+                    dst[q][h] = __builtin_nontemporal_load(src + (row_ok && mu < k ? mu : 0));
                 }
         };
 
-        load_x(adm_col[b0]);
-        load_s(b0, sa);
-        store_x(0);
-        __syncthreads();
-        for (int64_t b = b0; b < b1; ++b) {
-            const int buf = (int)((b - b0) & 1);
-            const bool more = b + 1 < b1;
-            if (more) {
-                load_x(adm_col[b + 1]);
-                load_s(b + 1, sn);
-            }
+        auto multiply = [&](int buf) {
             const double *xb = xs[buf];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
@@ -226,16 +221,27 @@ __global__ __launch_bounds__(128) void k_coupling_mfma_small(int k, int64_t m, i
                     }
                 }
             }
-            if (more) {
-                store_x(buf ^ 1);
+        };
+
+        load_x(adm_col[b0]);
+        load_s(b0, sa);
+        store_x(0);
+        __syncthreads();
+        // unconditional loads and a peeled last block, as in the k = 64 kernel
+        for (int64_t b = b0; b + 1 < b1; ++b) {
+            const int buf = (int)((b - b0) & 1);
+            load_x(adm_col[b + 1]);
+            load_s(b + 1, sn);
+            multiply(buf);
+            store_x(buf ^ 1);
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    sa[q][0] = sn[q][0];
-                    sa[q][1] = sn[q][1];
-                }
+            for (int q = 0; q < 4; ++q) {
+                sa[q][0] = sn[q][0];
+                sa[q][1] = sn[q][1];
             }
             __syncthreads();
         }
+        multiply((int)((b1 - 1 - b0) & 1));
     }
 #pragma unroll
     for (int J = 0; J < NJ; ++J) {

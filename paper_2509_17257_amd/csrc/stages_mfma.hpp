@@ -338,6 +338,7 @@ template <int NP>
 struct Round {
     dbl2 b[2][4];   // [row half g][k-step u]: rows 32g + 2 lr + {0, 1}
     dbl2 a[NP][4];  // [column half p][k-step u]: columns 32p + 2 lr + {0, 1}
+    int kb, kl;     // first k-step of the round and the item's length
 };
 
 __device__ inline dbl2 ld2(const double *p) { return *(const dbl2 *)p; }
@@ -370,14 +371,12 @@ __global__ __launch_bounds__(256, NP == 1 ? 2 : 1) void k_leaf_direct(int k, int
         if (skip(t)) continue;
         const int nt = size[t];
         const int64_t nt2 = nt + (nt & 1);
-        const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, lq = lane >> 4;
+        const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63, lr = lane & 15,
+                  lq = lane >> 4;  // w is wave-uniform: item loops stay scalar
         const int64_t r0 = first[t];
         const int64_t j0 = (qx % nslab) * MC;
         const int mc = (int)min<int64_t>(MC, m - j0);
-        bool col_ok[NP];
-    #pragma unroll
-        for (int p = 0; p < NP; ++p) col_ok[p] = 32 * p + 2 * lr < mc;
-        const int64_t q0 = near_ptr[l];
+        const int64_t q0 = near_ptr[l], vt0 = basis ? vt_off[l] : 0;
         // items: nb parts of the basis term (k-ranges of ceil(k / nb)), then the near
         // blocks; without near blocks the basis term is split over the 4 waves
         const int nb = basis ? (near ? 1 : 4) : 0;
@@ -402,19 +401,18 @@ __global__ __launch_bounds__(256, NP == 1 ? 2 : 1) void k_leaf_direct(int k, int
                 fs = m_first[x];
                 ks = m_size[x];
             } else {
-                const int32_t s = near_col[q0 + x];
-                off = near_off[q0 + x];
-                fs = first[s];
-                ks = size[s];
+                // relaxed atomic loads: the compiler cannot fold this path and the LDS path
+                // into one load through a generic pointer
+                const int32_t s = __hip_atomic_load(near_col + q0 + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                off = __hip_atomic_load(near_off + q0 + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                fs = __hip_atomic_load(first + s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ks = __hip_atomic_load(size + s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
         };
 
         for (int i0 = 0; i0 < nt; i0 += 64) {
             const int ic = min(64, nt - i0);
             const int nhalf = (ic + 31) >> 5;  // 32-row halves present (wave-uniform)
-            bool row_ok[2];
-    #pragma unroll
-            for (int g = 0; g < 2; ++g) row_ok[g] = 32 * g + 2 * lr < ic;
             dbl4 acc[2 * NP][4];
     #pragma unroll
             for (int J = 0; J < 2 * NP; ++J)
@@ -423,32 +421,37 @@ __global__ __launch_bounds__(256, NP == 1 ? 2 : 1) void k_leaf_direct(int k, int
 
             // item e, k-steps kb..kb+15 -> registers.  Right operand: rows (k) of a
             // transposed block with row stride nt2; left operand: rows (k) of X or y_t.
+            // Every load is issued unconditionally from a clamped address (rows past the
+            // tile, columns past the slab and k past the item read in-range neighbours), so
+            // the compiler's wait counters stay exact and the MFMAs of a round never wait
+            // for the next round's loads; the left operand's k-rows past the item are
+            // zeroed where they are used.  Rows and columns past the tile are never stored.
+            const int xr = (ic - 1) & ~1, xc = (mc - 1) & ~1;  // last even row / column offset
             auto load = [&](int e, int kb, Round<NP> &R) {
                 const double *bb, *ab;
                 int64_t lda;
                 int kl;
                 if (e < nb) {
-                    bb = Vt + vt_off[l] + (int64_t)e * kbase * nt2 + i0 + 2 * lr;   // V_t^T[nu][i]
-                    ab = yh + ((int64_t)t * k + e * kbase) * ldh + j0 + 2 * lr;     // y_t[nu][j]
+                    bb = Vt + vt0 + (int64_t)e * kbase * nt2 + i0;   // V_t^T[nu][i]
+                    ab = yh + ((int64_t)t * k + e * kbase) * ldh + j0; // y_t[nu][j]
                     lda = ldh;
                     kl = min(kbase, k - e * kbase);
                 } else {
                     int64_t off, fs;
                     near_meta(e - nb, off, fs, kl);
-                    bb = Nt + off + i0 + 2 * lr;               // N_ts^T[c][i]
-                    ab = Xt + fs * ldxt + j0 + 2 * lr;         // X_s[c][j]
+                    bb = Nt + off + i0;               // N_ts^T[c][i]
+                    ab = Xt + fs * ldxt + j0;         // X_s[c][j]
                     lda = ldxt;
                 }
+                R.kb = kb;
+                R.kl = kl;
     #pragma unroll
                 for (int u = 0; u < 4; ++u) {
-                    const int c = kb + 4 * u + lq;
-                    const bool cok = c < kl;
+                    const int c = min(kb + 4 * u + lq, kl - 1);
     #pragma unroll
-                    for (int g = 0; g < 2; ++g)
-                        R.b[g][u] = (cok && row_ok[g]) ? ld2(bb + c * nt2 + 32 * g) : dbl2{0.0, 0.0};
+                    for (int g = 0; g < 2; ++g) R.b[g][u] = ld2(bb + c * nt2 + min(32 * g + 2 * lr, xr));
     #pragma unroll
-                    for (int p = 0; p < NP; ++p)
-                        R.a[p][u] = (cok && col_ok[p]) ? ld2(ab + c * lda + 32 * p) : dbl2{0.0, 0.0};
+                    for (int p = 0; p < NP; ++p) R.a[p][u] = ld2(ab + c * lda + min(32 * p + 2 * lr, xc));
                 }
             };
             auto klen = [&](int e) {
@@ -458,12 +461,38 @@ __global__ __launch_bounds__(256, NP == 1 ? 2 : 1) void k_leaf_direct(int k, int
                 near_meta(e - nb, off, fs, ks);
                 return ks;
             };
+            // zero the left operand's k-rows past the item (once the round's loads are in)
+            auto mask = [&](Round<NP> &R) {
+    #pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const bool cok = R.kb + 4 * u + lq < R.kl;
+    #pragma unroll
+                    for (int p = 0; p < NP; ++p) R.a[p][u] = cok ? R.a[p][u] : dbl2{0.0, 0.0};
+                }
+            };
+            auto multiply = [&](const Round<NP> &R) {
+    #pragma unroll
+                for (int u = 0; u < 4; ++u)
+    #pragma unroll
+                    for (int g = 0; g < 2; ++g)
+                        if (g < nhalf)
+    #pragma unroll
+                            for (int h = 0; h < 2; ++h)
+    #pragma unroll
+                                for (int p = 0; p < NP; ++p)
+    #pragma unroll
+                                    for (int hj = 0; hj < 2; ++hj)
+                                        acc[2 * p + hj][2 * g + h] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                                            R.a[p][u][hj], R.b[g][u][h], acc[2 * p + hj][2 * g + h], 0, 0, 0);
+            };
 
             int e = w;
             if (e < nitems) {
                 Round<NP> cur, nxt;
                 int kb = 0, len = klen(e);
                 load(e, kb, cur);
+                mask(cur);
+                // the last round is peeled off, so that every round of the loop loads the next
                 for (;;) {
                     int en = e, kbn = kb + 16, lenn = len;
                     if (kbn >= len) {
@@ -471,27 +500,16 @@ __global__ __launch_bounds__(256, NP == 1 ? 2 : 1) void k_leaf_direct(int k, int
                         kbn = 0;
                         if (en < nitems) lenn = klen(en);
                     }
-                    const bool more = en < nitems;
-                    if (more) load(en, kbn, nxt);
-    #pragma unroll
-                    for (int u = 0; u < 4; ++u)
-    #pragma unroll
-                        for (int g = 0; g < 2; ++g)
-                            if (g < nhalf)
-    #pragma unroll
-                                for (int h = 0; h < 2; ++h)
-    #pragma unroll
-                                    for (int p = 0; p < NP; ++p)
-    #pragma unroll
-                                        for (int hj = 0; hj < 2; ++hj)
-                                            acc[2 * p + hj][2 * g + h] = __builtin_amdgcn_mfma_f64_16x16x4f64(
-                                                cur.a[p][u][hj], cur.b[g][u][h], acc[2 * p + hj][2 * g + h], 0, 0, 0);
-                    if (!more) break;
+                    if (en >= nitems) break;
+                    load(en, kbn, nxt);
+                    multiply(cur);
                     cur = nxt;
+                    mask(cur);
                     e = en;
                     kb = kbn;
                     len = lenn;
                 }
+                multiply(cur);
             }
             // partial tiles of the 4 waves, added in wave order.  Lane l, register r of
             // tile (J = 2p + hj, I = 2g + h) -> column 32p + 2 (l / 16 + 4 r) + hj,

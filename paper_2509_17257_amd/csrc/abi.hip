@@ -193,6 +193,14 @@ h2x_status h2x_mat_create(const h2x_plan *plan, h2x_prec storage, void *dev_ws, 
     up(d.leaves, P.leaves);
     up(d.lvl_all, P.lvl_all);
     up(d.lvl_inner, P.lvl_inner);
+    std::vector<int32_t> up_son(2 * P.lvl_inner.size()), dn_par(P.C);
+    for (size_t i = 0; i < P.lvl_inner.size(); ++i) {
+        up_son[2 * i] = P.son0[P.lvl_inner[i]];
+        up_son[2 * i + 1] = P.son1[P.lvl_inner[i]];
+    }
+    for (int32_t i = 0; i < P.C; ++i) dn_par[i] = P.parent[P.lvl_all[i]];
+    up(d.up_son, up_son);
+    up(d.dn_par, dn_par);
     up(d.adm_ptr, P.adm_ptr);
     up(d.adm_col, P.adm_col);
     up(d.adm_row, adm_row);

@@ -45,6 +45,8 @@ struct DevMat {
     // topology
     int32_t *first = nullptr, *size = nullptr, *parent = nullptr, *son0 = nullptr, *son1 = nullptr;
     int32_t *leaves = nullptr, *lvl_all = nullptr, *lvl_inner = nullptr;
+    int32_t *up_son = nullptr;  // 2 per entry of lvl_inner: its two sons
+    int32_t *dn_par = nullptr;  // per entry of lvl_all: its parent (-1 at the root)
     int64_t *adm_ptr = nullptr;  // C + 1
     int32_t *adm_col = nullptr;  // n_adm
     int32_t *adm_row = nullptr;  // n_adm (row cluster of each block)

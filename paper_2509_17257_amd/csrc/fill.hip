@@ -226,6 +226,8 @@ size_t mat_layout(const Plan &P, h2x_prec storage, DevMat *dm, char *base) {
     d.leaves = carve<int32_t>(cur, base, L);
     d.lvl_all = carve<int32_t>(cur, base, C);
     d.lvl_inner = carve<int32_t>(cur, base, P.lvl_inner.size() + 1);
+    d.up_son = carve<int32_t>(cur, base, 2 * P.lvl_inner.size() + 1);
+    d.dn_par = carve<int32_t>(cur, base, C);
     d.adm_ptr = carve<int64_t>(cur, base, C + 1);
     d.adm_col = carve<int32_t>(cur, base, na + 1);
     d.adm_row = carve<int32_t>(cur, base, na + 1);

@@ -364,7 +364,7 @@ void matmul_mfma_f64(const DevMat &dm, const TuneCfg &cfg, int64_t m, double alp
             const int32_t b = P.lvl_inner_ptr[d], e = P.lvl_inner_ptr[d + 1];
             if (e > b)
                 hipLaunchKernelGGL(mfma::k_up<NJ>, dim3(e - b, gy), dim3(256), 0, st, dm.k, m, dm.lvl_inner + b,
-                                   dm.son0, dm.son1, E, xh, ldh, sk);
+                                   dm.up_son + 2 * b, E, xh, ldh, sk);
         }
     }
     mark(2);
@@ -374,7 +374,7 @@ void matmul_mfma_f64(const DevMat &dm, const TuneCfg &cfg, int64_t m, double alp
         const int32_t b = P.lvl_ptr[d], e = P.lvl_ptr[d + 1];
         if (e > b)
             hipLaunchKernelGGL(mfma::k_down<NJ>, dim3(e - b, gy), dim3(256), 0, st, dm.k, m, dm.lvl_all + b,
-                               dm.parent, E, yh, ldh, sk);
+                               dm.dn_par + b, E, yh, ldh, sk);
     }
     mark(4);
     // Y = beta Y + alpha (V y-hat + N X)
@@ -509,7 +509,7 @@ hipError_t run_forward_transform(const DevMat &dm, int64_t m, const double *X, i
                 const int32_t b = P.lvl_inner_ptr[d], e = P.lvl_inner_ptr[d + 1];
                 if (e > b)
                     hipLaunchKernelGGL(mfma::k_up<NJ>, dim3(e - b, gy), dim3(256), 0, st, dm.k, m, dm.lvl_inner + b,
-                                       dm.son0, dm.son1, E, xh, ldh, Skip{});
+                                       dm.up_son + 2 * b, E, xh, ldh, Skip{});
             }
         };
         switch (nj) {
@@ -544,7 +544,7 @@ hipError_t run_down_pass(const DevMat &dm, int64_t m, double *yh, int64_t ldh, h
                 const int32_t b = P.lvl_ptr[d], e = P.lvl_ptr[d + 1];
                 if (e > b)
                     hipLaunchKernelGGL(mfma::k_down<NJ>, dim3(e - b, gy), dim3(256), 0, st, dm.k, m, dm.lvl_all + b,
-                                       dm.parent, E, yh, ldh, Skip{});
+                                       dm.dn_par + b, E, yh, ldh, Skip{});
             }
         };
         switch (nj) {

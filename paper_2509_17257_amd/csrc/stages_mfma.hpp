@@ -57,42 +57,39 @@ struct Regs {
     double b[4 * NJ];
 };
 
-// global -> registers: all loads of a term issued back to back
+// global -> registers: all loads of a term issued back to back, none in a branch
+// (an element past the term reads an in-range neighbour and is replaced by zero
+// when stored), so that the loads of several terms can be in flight together.
+// A term has at least one row and one column.
 template <int NJ>
 __device__ inline void load_term(const Term &d, int mc, Regs<NJ> &R) {
     constexpr int MC = 16 * NJ;
     const int tid = threadIdx.x, total = d.arows * d.acols;
-    if (total > 0) {
-        const float inv = 1.0f / (float)d.acols;
+    const float inv = 1.0f / (float)d.acols;
 #pragma unroll
-        for (int u = 0; u < 16; ++u) {
-            const int e = tid + 256 * u;
-            int i, c;
-            split(e, d.acols, inv, i, c);
-            R.a[u] = e < total ? d.a[(int64_t)i * d.lda + c] : 0.0;
-        }
+    for (int u = 0; u < 16; ++u) {
+        int i, c;
+        split(min(tid + 256 * u, total - 1), d.acols, inv, i, c);
+        R.a[u] = d.a[(int64_t)i * d.lda + c];
     }
     const int kl = d.klen();
 #pragma unroll
     for (int u = 0; u < 4 * NJ; ++u) {
-        const int e = tid + 256 * u, r = e / MC, c = e % MC;
-        double v = 0.0;
-        if (r < kl && c < mc) {
-            const int64_t g = d.perm ? d.perm[d.brow0 + r] : d.brow0 + r;
-            v = d.b[g * d.ldb + c];
-        }
-        R.b[u] = v;
+        const int e = tid + 256 * u, r = min(e / MC, kl - 1), c = min(e % MC, mc - 1);
+        const int64_t g = d.perm ? d.perm[d.brow0 + r] : d.brow0 + r;
+        R.b[u] = d.b[g * d.ldb + c];
     }
 }
 
 // registers -> LDS.  The right operand tile is rewritten in full (zeros past the
-// contraction length), so stale left-operand padding only ever meets zeros;
-// the tiles are cleared once per kernel so that padding is finite.
+// contraction length and past the last column), so stale left-operand padding
+// only ever meets zeros; the tiles are cleared once per kernel wherever padding
+// exists so that it is finite.
 template <int NJ>
-__device__ inline void store_term(const Term &d, const Regs<NJ> &R, Smem<NJ> &sm) {
+__device__ inline void store_term(const Term &d, int mc, const Regs<NJ> &R, Smem<NJ> &sm) {
     constexpr int MC = 16 * NJ, LDB = MC + 1;
     const int tid = threadIdx.x, total = d.arows * d.acols;
-    const float inv = 1.0f / (float)max(d.acols, 1);
+    const float inv = 1.0f / (float)d.acols;
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
         const int e = tid + 256 * u;
@@ -103,10 +100,11 @@ __device__ inline void store_term(const Term &d, const Regs<NJ> &R, Smem<NJ> &sm
             else sm.a[i * LDA + c] = R.a[u];
         }
     }
+    const int kl = d.klen();
 #pragma unroll
     for (int u = 0; u < 4 * NJ; ++u) {
         const int e = tid + 256 * u, r = e / MC, c = e % MC;
-        sm.b[r * LDB + c] = R.b[u];
+        sm.b[r * LDB + c] = (r < kl && c < mc) ? R.b[u] : 0.0;
     }
 }
 
@@ -150,7 +148,7 @@ __device__ inline void accumulate(Smem<NJ> &sm, dbl4 *acc, int nq, int mc, int r
     Term d = term(0);
     load_term<NJ>(d, mc, R);
     for (int q = 0; q < nq; ++q) {
-        store_term<NJ>(d, R, sm);
+        store_term<NJ>(d, mc, R, sm);
         __syncthreads();
         const int kp = dkpad4(d.klen());
         if (q + 1 < nq) {
@@ -196,25 +194,35 @@ __global__ __launch_bounds__(256) void k_fwd_leaf(int k, int64_t m, const int32_
                 if (out_row(r) < k) xh[((int64_t)t * k + out_row(r)) * ldh + j0 + out_col(J)] = acc[J][r];
 }
 
-// x_t = E_{t0}^T x_{t0} + E_{t1}^T x_{t1} for the inner clusters in `list`
+// x_t = E_{t0}^T x_{t0} + E_{t1}^T x_{t1} for the inner clusters in `list`;
+// son[2 i], son[2 i + 1] are the sons of list[i].  Both terms are loaded at once.
 template <int NJ>
 __global__ __launch_bounds__(256) void k_up(int k, int64_t m, const int32_t *__restrict__ list,
-                                            const int32_t *__restrict__ son0, const int32_t *__restrict__ son1,
-                                            const double *__restrict__ E, double *__restrict__ xh, int64_t ldh,
-                                            Skip skip) {
+                                            const int32_t *__restrict__ son, const double *__restrict__ E,
+                                            double *__restrict__ xh, int64_t ldh, Skip skip) {
     __shared__ Smem<NJ> sm;
-    const int32_t t = list[blockIdx.x];
+    const int32_t t = list[blockIdx.x], s0 = son[2 * blockIdx.x], s1 = son[2 * blockIdx.x + 1];
     if (skip(t)) return;
     const int64_t j0 = (int64_t)blockIdx.y * Smem<NJ>::MC;
     const int mc = (int)min<int64_t>(Smem<NJ>::MC, m - j0);
-    clear<NJ>(sm);
+    auto term = [&](int32_t sn) {
+        return Term{E + (int64_t)sn * k * k, k, k, k, true, xh + j0, ldh, nullptr, (int64_t)sn * k};
+    };
+    const Term d0 = term(s0), d1 = term(s1);
+    Regs<NJ> R0, R1;
+    load_term<NJ>(d0, mc, R0);
+    load_term<NJ>(d1, mc, R1);
+    if (k < K) clear<NJ>(sm);  // padding rows and columns of the k x k tiles
     dbl4 acc[NJ];
     zero<NJ>(acc);
-    const int32_t s0 = son0[t], s1 = son1[t];
-    accumulate<NJ>(sm, acc, 2, mc, k, [&](int q) {
-        const int32_t s = q ? s1 : s0;
-        return Term{E + (int64_t)s * k * k, k, k, k, true, xh + j0, ldh, nullptr, (int64_t)s * k};
-    });
+    const int kp = dkpad4(k);
+    store_term<NJ>(d0, mc, R0, sm);
+    __syncthreads();
+    mma<NJ>(sm.a, sm.b, kp, k, acc);
+    __syncthreads();
+    store_term<NJ>(d1, mc, R1, sm);
+    __syncthreads();
+    mma<NJ>(sm.a, sm.b, kp, k, acc);
 #pragma unroll
     for (int J = 0; J < NJ; ++J)
         if (out_col(J) < mc)
@@ -291,22 +299,25 @@ __global__ void k_zero_i32(int64_t count, int32_t *__restrict__ p) {
     if (e < count) p[e] = 0;
 }
 
-// y_c += E_c y_parent(c) for the clusters in `list`
+// y_c += E_c y_parent(c) for the clusters in `list`; par[i] is the parent of list[i]
 template <int NJ>
 __global__ __launch_bounds__(256) void k_down(int k, int64_t m, const int32_t *__restrict__ list,
-                                              const int32_t *__restrict__ parent, const double *__restrict__ E,
+                                              const int32_t *__restrict__ par, const double *__restrict__ E,
                                               double *__restrict__ yh, int64_t ldh, Skip skip) {
     __shared__ Smem<NJ> sm;
-    const int32_t c = list[blockIdx.x];
+    const int32_t c = list[blockIdx.x], p = par[blockIdx.x];
     if (skip(c)) return;
-    const int32_t par = parent[c];
     const int64_t j0 = (int64_t)blockIdx.y * Smem<NJ>::MC;
     const int mc = (int)min<int64_t>(Smem<NJ>::MC, m - j0);
+    const Term d{E + (int64_t)c * k * k, k, k, k, false, yh + j0, ldh, nullptr, (int64_t)p * k};
+    Regs<NJ> R;
+    load_term<NJ>(d, mc, R);
+    if (k < K) clear<NJ>(sm);  // padding rows and columns of the k x k tile
     dbl4 acc[NJ];
     zero<NJ>(acc);
-    accumulate<NJ>(sm, acc, 1, mc, k, [&](int) {
-        return Term{E + (int64_t)c * k * k, k, k, k, false, yh + j0, ldh, nullptr, (int64_t)par * k};
-    });
+    store_term<NJ>(d, mc, R, sm);
+    __syncthreads();
+    mma<NJ>(sm.a, sm.b, dkpad4(k), k, acc);
 #pragma unroll
     for (int J = 0; J < NJ; ++J)
         if (out_col(J) < mc)

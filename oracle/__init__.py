@@ -74,6 +74,8 @@ def _load():
     lib.orc_grad.argtypes = [P, I64, P, P, P, P, P]
     lib.orc_block_cg_shared.restype = I64
     lib.orc_block_cg_shared.argtypes = [P, I64, P, P, D, I64, D, P, P]
+    lib.orc_block_gmres.restype = I64
+    lib.orc_block_gmres.argtypes = [P, I64, P, P, D, I64, I64, P, P, P, P]
     lib.orc_num_threads.restype = C.c_int
     lib.orc_set_threads.argtypes = [C.c_int]
     _lib = lib
@@ -298,6 +300,21 @@ class OracleH2:
         it = _load().orc_block_cg_shared(self._h, m, _ptr(B), _ptr(X), float(rtol), int(max_iter), float(drop),
                                          _ptr(rk), _ptr(st))
         return X, dict(iters=int(it), rank_min=int(rk[0]), status=st)
+
+    def block_gmres(self, B, X0=None, rtol=1e-8, restart=30, max_iter=10000):
+        """Block GMRES(restart) without a preconditioner: m independent GMRES processes
+        sharing one product per Arnoldi step (classical Gram-Schmidt, Givens rotations,
+        restart with the improved iterate)."""
+        B = np.ascontiguousarray(B, dtype=np.float64)
+        m = B.shape[1]
+        X = np.zeros_like(B) if X0 is None else np.ascontiguousarray(X0, dtype=np.float64).copy()
+        ci = np.zeros(m, np.int64)
+        st = np.zeros(m, np.int32)
+        est = np.zeros(m, np.float64)
+        cyc = np.zeros(1, np.int64)
+        it = _load().orc_block_gmres(self._h, m, _ptr(B), _ptr(X), float(rtol), int(restart), int(max_iter),
+                                     _ptr(ci), _ptr(st), _ptr(est), _ptr(cyc))
+        return X, dict(iters=int(it), cycles=int(cyc[0]), col_iters=ci, status=st, res_est=est)
 
     def cg1(self, b, x0=None, rtol=1e-8, max_iter=10000):
         b = np.ascontiguousarray(b, dtype=np.float64).reshape(-1)

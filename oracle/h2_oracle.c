@@ -1400,3 +1400,161 @@ void orc_set_threads(int t) {
     (void)t;
 #endif
 }
+
+/* ------------------------------------------------------------------------ */
+/* Block GMRES(ell)                                                         */
+
+/*
+ * Block GMRES with restarts and no preconditioner (section 5.2, the block form of
+ * the generalized minimal residual method with M = I): m independent GMRES
+ * processes that share one H^2 x Q product per Arnoldi step.  X holds X0 on entry
+ * and the iterate on exit.
+ *
+ * One cycle, for every column i that has not met ||b_i - A x_i|| <= rtol ||b_i||:
+ *   r = b - A x, beta = ||r||, rhat = beta e_0, q_0 = r / beta;
+ *   step k (while k < ell and some column is open):
+ *     a = A q_k                                    (one product for all columns)
+ *     h[j][k] = <q_j, a>, j = 0..k                (classical Gram-Schmidt: every
+ *     a = a - sum_j q_j h[j][k]                    projection taken from the same a)
+ *     h[k+1][k] = ||a||, q_{k+1} = a / h[k+1][k]
+ *     the earlier rotations G_0..G_{k-1} applied to column k of h, then the
+ *     rotation G_k that zeroes h[k+1][k], applied to h and to rhat.
+ *   A column closes once |rhat[k+1]| <= rtol ||b_i|| (a vanishing new direction
+ *   gives rhat[k+1] = 0); a zero pivot (h[k][k] = h[k+1][k] = 0) is a breakdown and
+ *   the step is not used.  At the end of the cycle each column solves R y = rhat
+ *   with its own number of steps k_i (R the rotated upper triangle of h) and sets
+ *   x += sum_{j < k_i} q_j y_j.
+ * Cycles repeat until every column meets the bound or max_iter Arnoldi steps have
+ * run (counted once per step, whatever the number of open columns).
+ * Returns the number of Arnoldi steps; col_iters[i]: steps in which column i was
+ * open; status[i]: 0 converged, 1 breakdown, 2 not converged; res_est[i]:
+ * |rhat[k_i]| / ||b_i|| at the end of the column's last cycle (the GMRES estimate
+ * of its relative residual); *cycles: number of cycles.
+ */
+int64_t orc_block_gmres(const orc_h2 *h, int64_t m, const double *B, double *X, double rtol, int64_t ell,
+                        int64_t max_iter, int64_t *col_iters, int32_t *status, double *res_est, int64_t *cycles) {
+    const int64_t n = h->n;
+    double *Q = malloc(sizeof(double) * (ell + 1) * n * m);  /* basis blocks q_0..q_ell, n x m each */
+    double *R = malloc(sizeof(double) * n * m), *Aq = malloc(sizeof(double) * n * m);
+    double *H = malloc(sizeof(double) * m * (ell + 1) * ell);  /* column i: (ell + 1) x ell, row-major */
+    double *cs = malloc(sizeof(double) * m * ell), *sn = malloc(sizeof(double) * m * ell);
+    double *rh = malloc(sizeof(double) * m * (ell + 1)), *y = malloc(sizeof(double) * ell);
+    double *bn = malloc(sizeof(double) * m);
+    int64_t *kc = malloc(sizeof(int64_t) * m);
+    int *open = malloc(sizeof(int) * m), *done = calloc(m, sizeof(int));
+#define HH(i, r, c) H[((i) * (ell + 1) + (r)) * ell + (c)]
+#define QQ(j) (Q + (int64_t)(j) * n * m)
+    for (int64_t i = 0; i < m; ++i) {
+        bn[i] = sqrt(orc_dot_col(n, m, B, B, i));
+        col_iters[i] = 0;
+        status[i] = 2;
+        res_est[i] = 0.0;
+    }
+    int64_t it = 0, cyc = 0;
+    for (;;) {
+        /* residual of the current iterate; columns already within the bound are done */
+        orc_matmul(h, m, 1.0, X, 0.0, R);
+        for (int64_t e = 0; e < n * m; ++e) R[e] = B[e] - R[e];
+        int any = 0;
+        for (int64_t i = 0; i < m; ++i) {
+            open[i] = 0;
+            kc[i] = 0;
+            if (done[i]) continue;
+            const double beta = sqrt(orc_dot_col(n, m, R, R, i));
+            if (beta <= rtol * bn[i]) {
+                done[i] = 1;
+                status[i] = 0;
+                continue;
+            }
+            open[i] = 1;
+            any = 1;
+            for (int64_t r = 0; r <= ell; ++r) rh[i * (ell + 1) + r] = 0.0;
+            rh[i * (ell + 1)] = beta;
+            for (int64_t v = 0; v < n; ++v) QQ(0)[v * m + i] = R[v * m + i] / beta;
+        }
+        if (!any || it >= max_iter) break;
+        /* columns that are not open carry zero basis vectors */
+        for (int64_t i = 0; i < m; ++i)
+            if (!open[i])
+                for (int64_t v = 0; v < n; ++v) QQ(0)[v * m + i] = 0.0;
+        cyc++;
+        for (int64_t k = 0; k < ell && it < max_iter; ++k) {
+            int still = 0;
+            for (int64_t i = 0; i < m; ++i) still |= open[i];
+            if (!still) break;
+            orc_matmul(h, m, 1.0, QQ(k), 0.0, Aq);
+            it++;
+            for (int64_t i = 0; i < m; ++i) {
+                double *q1 = QQ(k + 1);
+                if (!open[i]) {
+                    for (int64_t v = 0; v < n; ++v) q1[v * m + i] = 0.0;
+                    continue;
+                }
+                /* classical Gram-Schmidt against q_0..q_k */
+                for (int64_t j = 0; j <= k; ++j) HH(i, j, k) = orc_dot_col(n, m, QQ(j), Aq, i);
+                for (int64_t v = 0; v < n; ++v) {
+                    double a = Aq[v * m + i];
+                    for (int64_t j = 0; j <= k; ++j) a -= QQ(j)[v * m + i] * HH(i, j, k);
+                    Aq[v * m + i] = a;
+                }
+                const double hn = sqrt(orc_dot_col(n, m, Aq, Aq, i));
+                HH(i, k + 1, k) = hn;
+                /* earlier rotations on the new column */
+                for (int64_t j = 0; j < k; ++j) {
+                    const double c = cs[i * ell + j], s = sn[i * ell + j];
+                    const double u = HH(i, j, k), w = HH(i, j + 1, k);
+                    HH(i, j, k) = c * u + s * w;
+                    HH(i, j + 1, k) = -s * u + c * w;
+                }
+                /* new rotation: (h[k][k], h[k+1][k]) -> (rho, 0) */
+                const double u = HH(i, k, k), w = HH(i, k + 1, k);
+                const double rho = hypot(u, w);
+                if (rho == 0.0) {  /* singular projected matrix: the step is not used */
+                    open[i] = 0;
+                    done[i] = 1;
+                    status[i] = 1;
+                    for (int64_t v = 0; v < n; ++v) q1[v * m + i] = 0.0;
+                    continue;
+                }
+                const double c = u / rho, s = w / rho;
+                cs[i * ell + k] = c;
+                sn[i * ell + k] = s;
+                HH(i, k, k) = rho;
+                HH(i, k + 1, k) = 0.0;
+                const double r0 = rh[i * (ell + 1) + k];
+                rh[i * (ell + 1) + k] = c * r0;
+                rh[i * (ell + 1) + k + 1] = -s * r0;
+                kc[i] = k + 1;
+                col_iters[i]++;
+                if (fabs(rh[i * (ell + 1) + k + 1]) <= rtol * bn[i] || hn == 0.0) {
+                    open[i] = 0;
+                    for (int64_t v = 0; v < n; ++v) q1[v * m + i] = 0.0;
+                } else {
+                    for (int64_t v = 0; v < n; ++v) q1[v * m + i] = Aq[v * m + i] / hn;
+                }
+            }
+        }
+        /* least-squares solution of the cycle: R y = rhat, then x += V y */
+        for (int64_t i = 0; i < m; ++i) {
+            const int64_t kk = kc[i];
+            if (kk == 0) continue;
+            for (int64_t r = kk - 1; r >= 0; --r) {
+                double s = rh[i * (ell + 1) + r];
+                for (int64_t c = r + 1; c < kk; ++c) s -= HH(i, r, c) * y[c];
+                y[r] = s / HH(i, r, r);
+            }
+            for (int64_t v = 0; v < n; ++v) {
+                double a = X[v * m + i];
+                for (int64_t j = 0; j < kk; ++j) a += QQ(j)[v * m + i] * y[j];
+                X[v * m + i] = a;
+            }
+            res_est[i] = bn[i] > 0.0 ? fabs(rh[i * (ell + 1) + kk]) / bn[i] : 0.0;
+        }
+    }
+#undef HH
+#undef QQ
+    *cycles = cyc;
+    free(Q); free(R); free(Aq); free(H); free(cs); free(sn); free(rh); free(y); free(bn); free(kc);
+    free(open); free(done);
+    return it;
+}

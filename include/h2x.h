@@ -250,6 +250,55 @@ h2x_status h2x_block_cg_mixed(const h2x_mat *A, const h2x_mat *A_lo, const h2x_c
                               int64_t m, const double *B, int64_t ldb, double *X, int64_t ldx, void *dev_ws,
                               size_t ws_bytes, h2x_cg_info *info, void *hip_stream);
 
+/* ---- block GMRES ------------------------------------------------------------ */
+/* Block GMRES(restart) without a preconditioner (section 5.2, the block form of
+ * the generalized minimal residual method with M = I): m independent GMRES
+ * processes that share one H^2 x Q product per Arnoldi step.  Per column and
+ * cycle: r = b - A x, rhat = ||r|| e_0, q_0 = r / ||r||; each step takes the
+ * product a = A q_k, classical Gram-Schmidt against q_0..q_k (all projections
+ * from the same a), h[k+1][k] = ||a||, q_{k+1} = a / h[k+1][k], and Givens
+ * rotations that keep the Hessenberg matrix upper triangular and carry rhat.  A
+ * column stops extending its basis once |rhat| <= rtol ||b_i||; at the end of a
+ * cycle each column solves its triangular system with its own number of steps
+ * and updates x; the next cycle restarts from the improved x.  A column is done
+ * when its true residual ||b_i - A x_i|| <= rtol ||b_i|| at the start of a
+ * cycle.  Not for merged (batched) plans.
+ *
+ * restart: Arnoldi steps per cycle (>= 1); the workspace holds restart + 1 basis
+ * blocks of n x m doubles.  max_iter: Arnoldi steps over all cycles (>= 0).
+ * check_every: the host reads the device's convergence flag every this many
+ * steps (>= 1; steps launched after every column has closed do nothing).
+ * X holds X0 on entry and the iterate on exit (row-major, leading dimension ldx);
+ * B is row-major with leading dimension ldb.  Blocking: returns after the solve.
+ * Returns H2X_OK when the solve ran; the outcome is in info->status (H2X_OK, or
+ * H2X_ENOCONV when a column did not converge within max_iter, H2X_EBREAKDOWN when
+ * a column met a singular projected matrix).  info arrays are host, m entries,
+ * nullable: col_iters (steps in which the column was open), col_status (0
+ * converged, 1 breakdown, 2 not converged), col_res (|rhat| / ||b_i|| after the
+ * column's last cycle, the GMRES estimate of its relative residual). */
+typedef struct {
+    double rtol;
+    int32_t restart;
+    int32_t max_iter;
+    int32_t check_every;
+    int32_t reserved;
+} h2x_gmres_params;
+
+typedef struct {
+    int32_t iters;   /* Arnoldi steps run */
+    int32_t cycles;  /* restart cycles run */
+    int32_t status;
+    int32_t reserved;
+    double *col_res;
+    int32_t *col_iters;
+    int32_t *col_status;
+} h2x_gmres_info;
+
+size_t h2x_block_gmres_workspace_bytes(const h2x_mat *A, int64_t m, int32_t restart);
+h2x_status h2x_block_gmres(const h2x_mat *A, const h2x_gmres_params *prm, int64_t m, const double *B, int64_t ldb,
+                           double *X, int64_t ldx, void *dev_ws, size_t ws_bytes, h2x_gmres_info *info,
+                           void *hip_stream);
+
 /* ---- tuning ----------------------------------------------------------------- */
 /* Tile shapes of the matrix-core kernels: columns per work-group of the forward
  * leaf and transfer passes (16 * nj_transfer), of the coupling (16 * nj_coupling)

@@ -55,6 +55,17 @@ CG_INDEPENDENT, CG_SHARED = 0, 1
 _VARIANT = {"independent": CG_INDEPENDENT, "shared": CG_SHARED, CG_INDEPENDENT: CG_INDEPENDENT, CG_SHARED: CG_SHARED}
 
 
+class _GmresParams(C.Structure):
+    _fields_ = [("rtol", C.c_double), ("restart", C.c_int32), ("max_iter", C.c_int32),
+                ("check_every", C.c_int32), ("reserved", C.c_int32)]
+
+
+class _GmresInfo(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("cycles", C.c_int32), ("status", C.c_int32), ("reserved", C.c_int32),
+                ("col_res", C.POINTER(C.c_double)), ("col_iters", C.POINTER(C.c_int32)),
+                ("col_status", C.POINTER(C.c_int32))]
+
+
 class _TuneInfo(C.Structure):
     _fields_ = [("nj_transfer", C.c_int32), ("nj_coupling", C.c_int32), ("np_leaf", C.c_int32),
                 ("overlap", C.c_int32), ("fuse_up", C.c_int32), ("ms_default", C.c_double),
@@ -115,6 +126,9 @@ def load_library():
         "h2x_block_cg_mixed_workspace_bytes": (SZ, [P, P, I64]),
         "h2x_block_cg_mixed": (C.c_int, [P, P, C.POINTER(_CgParams), D, I64, P, I64, P, I64, P, SZ,
                                          C.POINTER(_CgInfo), P]),
+        "h2x_block_gmres_workspace_bytes": (SZ, [P, I64, I32]),
+        "h2x_block_gmres": (C.c_int, [P, C.POINTER(_GmresParams), I64, P, I64, P, I64, P, SZ,
+                                      C.POINTER(_GmresInfo), P]),
         "h2x_mat_autotune_workspace_bytes": (SZ, [P, I64]),
         "h2x_mat_autotune": (C.c_int, [P, I64, P, SZ, P, C.POINTER(_TuneInfo)]),
         "h2x_last_error": (C.c_char_p, []),
@@ -420,6 +434,42 @@ def block_cg_solve(A: H2Matrix, B, X0=None, *, rtol=1e-8, max_iter=10000, freeze
                                        C.c_void_p(X.data_ptr()), X.stride(0), C.c_void_p(ws.data_ptr()), ws.numel(),
                                        C.byref(info), _stream(torch, B.device)), "h2x_block_cg")
     return X, _info(info, rel, its, sts, sys, nsys, m)
+
+
+@dataclass
+class GmresInfo:
+    iters: int
+    cycles: int
+    status: int
+    col_res: np.ndarray
+    col_iters: np.ndarray
+    col_status: np.ndarray
+
+
+def block_gmres_solve(A: H2Matrix, B, X0=None, *, rtol=1e-8, restart=30, max_iter=10000, check_every=4):
+    """Solve A X = B with block GMRES(restart) (h2x_block_gmres): m independent GMRES
+    processes sharing one product per Arnoldi step, restarted from the improved
+    iterate until every column's true residual is within rtol.  Returns (X, GmresInfo)."""
+    import torch
+    if B.dtype != torch.float64 or B.device.type != "cuda" or B.dim() != 2 or B.stride(1) != 1:
+        raise ValueError("B must be a row-major (n, m) float64 CUDA tensor")
+    n, m = B.shape
+    X = torch.zeros_like(B) if X0 is None else X0.clone()
+    lib = load_library()
+    nb = lib.h2x_block_gmres_workspace_bytes(A._h, m, int(restart))
+    if nb == 0:
+        raise ValueError("block_gmres_solve: need m >= 1 and restart >= 1")
+    ws = torch.empty(nb, dtype=torch.uint8, device=B.device)
+    res = np.zeros(m)
+    its = np.zeros(m, np.int32)
+    sts = np.zeros(m, np.int32)
+    i32 = lambda a: a.ctypes.data_as(C.POINTER(C.c_int32))
+    info = _GmresInfo(0, 0, 0, 0, res.ctypes.data_as(C.POINTER(C.c_double)), i32(its), i32(sts))
+    prm = _GmresParams(float(rtol), int(restart), int(max_iter), int(check_every), 0)
+    _check(lib.h2x_block_gmres(A._h, C.byref(prm), m, C.c_void_p(B.data_ptr()), B.stride(0),
+                               C.c_void_p(X.data_ptr()), X.stride(0), C.c_void_p(ws.data_ptr()), ws.numel(),
+                               C.byref(info), _stream(torch, B.device)), "h2x_block_gmres")
+    return X, GmresInfo(info.iters, info.cycles, info.status, res, its, sts)
 
 
 def block_cg_refine(A: H2Matrix, A_lo: H2Matrix, B, *, rtol=1e-10, inner_rtol=1e-4, max_outer=50,

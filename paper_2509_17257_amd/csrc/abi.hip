@@ -333,6 +333,25 @@ h2x_status h2x_block_cg(const h2x_mat *A, const h2x_cg_params *prm, int64_t m, c
     return run_block_cg(A->dm, *prm, m, B, ldb, X, ldx, (char *)dev_ws, ws_bytes, info, (hipStream_t)hip_stream);
 }
 
+size_t h2x_block_gmres_workspace_bytes(const h2x_mat *A, int64_t m, int32_t restart) {
+    if (!A || m < 1 || restart < 1) return 0;
+    return gmres_ws_bytes(A->dm, m, restart);
+}
+
+h2x_status h2x_block_gmres(const h2x_mat *A, const h2x_gmres_params *prm, int64_t m, const double *B, int64_t ldb,
+                           double *X, int64_t ldx, void *dev_ws, size_t ws_bytes, h2x_gmres_info *info,
+                           void *hip_stream) {
+    if (!A || !prm || !B || !X || !dev_ws) return fail(H2X_EINVAL, "h2x_block_gmres: NULL argument");
+    if (m < 1 || ldb < m || ldx < m) return fail(H2X_EINVAL, "h2x_block_gmres: need m >= 1, ldb >= m, ldx >= m");
+    if (!(prm->rtol >= 0.0) || prm->restart < 1 || prm->max_iter < 0 || prm->check_every < 1)
+        return fail(H2X_EINVAL, "h2x_block_gmres: need rtol >= 0, restart >= 1, max_iter >= 0, check_every >= 1");
+    if (A->dm.plan->nsys() > 1) return fail(H2X_EUNSUPPORTED, "h2x_block_gmres: not for merged plans");
+    if (!aligned(dev_ws)) return fail(H2X_EINVAL, "h2x_block_gmres: workspace not 256-byte aligned");
+    if (ws_bytes < gmres_ws_bytes(A->dm, m, prm->restart))
+        return fail(H2X_ENOMEM, "h2x_block_gmres: workspace too small");
+    return run_block_gmres(A->dm, *prm, m, B, ldb, X, ldx, (char *)dev_ws, ws_bytes, info, (hipStream_t)hip_stream);
+}
+
 size_t h2x_block_cg_mixed_workspace_bytes(const h2x_mat *A, const h2x_mat *A_lo, int64_t m) {
     if (!A || !A_lo || m < 1) return 0;
     return mixed_ws_bytes(A->dm, A_lo->dm, m);

@@ -132,6 +132,10 @@ h2x_status run_block_cg_mixed(const DevMat &hi, const DevMat &lo, const h2x_cg_p
 h2x_status run_block_cg(const DevMat &dm, const h2x_cg_params &prm, int64_t m, const double *B, int64_t ldb,
                         double *X, int64_t ldx, char *ws, size_t ws_bytes, h2x_cg_info *info, hipStream_t st);
 
+size_t gmres_ws_bytes(const DevMat &dm, int64_t m, int ell);
+h2x_status run_block_gmres(const DevMat &dm, const h2x_gmres_params &prm, int64_t m, const double *B, int64_t ldb,
+                           double *X, int64_t ldx, char *ws, size_t ws_bytes, h2x_gmres_info *info, hipStream_t st);
+
 // forward transformation of X into x-hat (leaves and every cluster at or below the
 // shallowest admissible depth); FP64 operators only
 hipError_t run_forward_transform(const DevMat &dm, int64_t m, const double *X, int64_t ldx, bool tree_order,

@@ -1,0 +1,472 @@
+// Block GMRES(ell) without a preconditioner (section 5.2, block form of the
+// generalized minimal residual method with M = I): m independent GMRES
+// processes that share one H^2 x Q product per Arnoldi step.  Per column i and
+// cycle: r = b - A x, rhat = ||r|| e_0, q_0 = r / ||r||; step k: a = A q_k,
+// h[j][k] = <q_j, a> for j <= k (classical Gram-Schmidt: all projections taken
+// from the same a), a -= sum_j q_j h[j][k], h[k+1][k] = ||a||, q_{k+1} =
+// a / h[k+1][k]; the earlier Givens rotations are applied to column k of h and a
+// new one zeroes h[k+1][k] (applied to h and rhat).  A column closes once
+// |rhat[k+1]| <= rtol ||b_i|| (a vanishing direction gives rhat[k+1] = 0); a zero
+// pivot is a breakdown and that step is not used.  At the end of a cycle every
+// column solves R y = rhat with its own number of steps and sets x += V y; the
+// next cycle restarts from the improved x.
+//
+// The iteration runs in tree order on packed n x m blocks (ld = m): B, X and the
+// basis q_0..q_ell.  Dot products and norms are reduced in two fixed-order
+// passes (per row block, then per column), so the solve is bitwise
+// reproducible.  The Hessenberg columns, rotations and rhat of every column stay
+// on the device; once no column is open the remaining kernels of the cycle and
+// the products (through the per-system skip flag) do nothing, and the host reads
+// that flag every check_every steps.
+#include <cmath>
+#include <vector>
+
+#include "device.hpp"
+
+namespace h2x {
+
+namespace {
+
+constexpr int kCols = 32;    // columns per work-group in the row-block kernels
+constexpr int kRowGroups = 8;  // 256 threads = 8 row groups x 32 columns
+constexpr int kRowsPerBlk = 128;
+constexpr int kRowsPerThread = kRowsPerBlk / kRowGroups;
+
+struct GmState {
+    int32_t done;   // no column open: the rest of the cycle is skipped (first member: the skip flag)
+    int32_t steps;  // Arnoldi steps run
+    int32_t pad[2];
+};
+
+struct GmCols {  // per-column data, m columns
+    double *bn;       // ||b_i||
+    double *H;        // (ell + 1) x ell per column, row-major
+    double *cs, *sn;  // rotations, ell per column
+    double *rh;       // rhat, ell + 1 per column
+    double *y;        // least-squares coefficients, ell per column
+    double *inv;      // scale of the new basis vector (0 for a closed column)
+    double *est;      // |rhat[k_i]| / ||b_i|| after the column's last cycle
+    int32_t *open, *done, *kc, *iters, *status;
+};
+
+// part[(j * nblk + blk) * m + c] = sum over the rows of block blk of Q_j[r][c] a[r][c], j = 0..k
+__global__ __launch_bounds__(256) void k_gm_dots(int64_t n, int64_t m, int k, const double *__restrict__ Q,
+                                                 const double *__restrict__ a, double *__restrict__ part,
+                                                 const GmState *__restrict__ st) {
+    if (st->done) return;
+    __shared__ double red[kRowGroups][kCols];
+    const int tid = threadIdx.x, rg = tid / kCols, jl = tid % kCols;
+    const int64_t blk = blockIdx.x, nblk = gridDim.x, c = (int64_t)blockIdx.y * kCols + jl;
+    const int64_t r0 = blk * kRowsPerBlk, r1 = min(n, r0 + kRowsPerBlk);
+    double av[kRowsPerThread];
+#pragma unroll
+    for (int u = 0; u < kRowsPerThread; ++u) {
+        const int64_t r = r0 + rg + kRowGroups * u;
+        av[u] = (c < m && r < r1) ? a[r * m + c] : 0.0;
+    }
+    for (int j = 0; j <= k; ++j) {
+        const double *q = Q + (int64_t)j * n * m;
+        double s = 0.0;
+#pragma unroll
+        for (int u = 0; u < kRowsPerThread; ++u) {
+            const int64_t r = r0 + rg + kRowGroups * u;
+            if (c < m && r < r1) s += q[r * m + c] * av[u];
+        }
+        red[rg][jl] = s;
+        __syncthreads();
+        if (rg == 0 && c < m) {
+            double t = 0.0;
+            for (int g = 0; g < kRowGroups; ++g) t += red[g][jl];
+            part[((int64_t)j * nblk + blk) * m + c] = t;
+        }
+        __syncthreads();
+    }
+}
+
+// H[c][j][k] = sum over row blocks of part (in block order), open columns only
+__global__ void k_gm_hcol(int64_t m, int64_t nblk, int k, int ell, const double *__restrict__ part, GmCols cl,
+                          const GmState *__restrict__ st) {
+    if (st->done) return;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)(k + 1) * m) return;
+    const int64_t j = e / m, c = e % m;
+    if (!cl.open[c]) return;
+    double s = 0.0;
+    for (int64_t b = 0; b < nblk; ++b) s += part[(j * nblk + b) * m + c];
+    cl.H[(c * (ell + 1) + j) * ell + k] = s;
+}
+
+// a -= sum_{j <= k} Q_j h[j][k] on the open columns (k < 0: no subtraction, every
+// column), then the partial sums of squares of a: part2[blk * m + c]
+__global__ __launch_bounds__(256) void k_gm_update(int64_t n, int64_t m, int k, int ell, const double *__restrict__ Q,
+                                                   double *__restrict__ a, GmCols cl, double *__restrict__ part2,
+                                                   const GmState *__restrict__ st) {
+    if (k >= 0 && st->done) return;
+    __shared__ double red[kRowGroups][kCols];
+    const int tid = threadIdx.x, rg = tid / kCols, jl = tid % kCols;
+    const int64_t blk = blockIdx.x, c = (int64_t)blockIdx.y * kCols + jl;
+    const int64_t r0 = blk * kRowsPerBlk, r1 = min(n, r0 + kRowsPerBlk);
+    const bool sub = k >= 0 && c < m && cl.open[c];
+    double av[kRowsPerThread];
+#pragma unroll
+    for (int u = 0; u < kRowsPerThread; ++u) {
+        const int64_t r = r0 + rg + kRowGroups * u;
+        av[u] = (c < m && r < r1) ? a[r * m + c] : 0.0;
+    }
+    if (sub) {
+        for (int j = 0; j <= k; ++j) {
+            const double *q = Q + (int64_t)j * n * m;
+            const double h = cl.H[(c * (ell + 1) + j) * ell + k];
+#pragma unroll
+            for (int u = 0; u < kRowsPerThread; ++u) {
+                const int64_t r = r0 + rg + kRowGroups * u;
+                if (r < r1) av[u] -= q[r * m + c] * h;
+            }
+        }
+    }
+    double s = 0.0;
+#pragma unroll
+    for (int u = 0; u < kRowsPerThread; ++u) {
+        const int64_t r = r0 + rg + kRowGroups * u;
+        if (c < m && r < r1) {
+            s += av[u] * av[u];
+            if (sub) a[r * m + c] = av[u];
+        }
+    }
+    red[rg][jl] = s;
+    __syncthreads();
+    if (rg == 0 && c < m) {
+        double t = 0.0;
+        for (int g = 0; g < kRowGroups; ++g) t += red[g][jl];
+        part2[blk * m + c] = t;
+    }
+}
+
+__device__ inline double col_sum(const double *part2, int64_t nblk, int64_t m, int64_t c) {
+    double s = 0.0;
+    for (int64_t b = 0; b < nblk; ++b) s += part2[b * m + c];
+    return s;
+}
+
+// One work-group: ||b_i|| and the per-column state before the first cycle.
+__global__ void k_gm_init(int64_t m, int64_t nblk, const double *__restrict__ part2, GmCols cl, GmState *st) {
+    for (int64_t c = threadIdx.x; c < m; c += blockDim.x) {
+        cl.bn[c] = sqrt(col_sum(part2, nblk, m, c));
+        cl.done[c] = 0;
+        cl.open[c] = 0;
+        cl.kc[c] = 0;
+        cl.iters[c] = 0;
+        cl.status[c] = 2;
+        cl.est[c] = 0.0;
+    }
+    if (threadIdx.x == 0) {
+        st->done = 0;
+        st->steps = 0;
+    }
+}
+
+// One work-group, start of a cycle: part2 holds the squared norms of r = b - A x.
+// Columns within the bound are done; the others open with rhat = ||r|| e_0.
+__global__ void k_gm_start(int64_t m, int64_t nblk, int ell, double rtol, const double *__restrict__ part2, GmCols cl,
+                           GmState *st) {
+    __shared__ int any;
+    if (threadIdx.x == 0) any = 0;
+    __syncthreads();
+    for (int64_t c = threadIdx.x; c < m; c += blockDim.x) {
+        cl.open[c] = 0;
+        cl.kc[c] = 0;
+        cl.inv[c] = 0.0;
+        if (cl.done[c]) continue;
+        const double beta = sqrt(col_sum(part2, nblk, m, c));
+        if (beta <= rtol * cl.bn[c]) {
+            cl.done[c] = 1;
+            cl.status[c] = 0;
+            continue;
+        }
+        cl.open[c] = 1;
+        double *rh = cl.rh + c * (ell + 1);
+        rh[0] = beta;
+        for (int r = 1; r <= ell; ++r) rh[r] = 0.0;
+        cl.inv[c] = 1.0 / beta;
+        any = 1;  // every writer stores the same value
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) st->done = any ? 0 : 1;
+}
+
+// One work-group, end of step k: h[k+1][k] = ||a||, rotations, rhat, closing.
+__global__ void k_gm_rotate(int64_t m, int64_t nblk, int k, int ell, double rtol, const double *__restrict__ part2,
+                            GmCols cl, GmState *st) {
+    if (st->done) return;
+    __shared__ int any;
+    if (threadIdx.x == 0) any = 0;
+    __syncthreads();
+    for (int64_t c = threadIdx.x; c < m; c += blockDim.x) {
+        if (!cl.open[c]) {
+            cl.inv[c] = 0.0;
+            continue;
+        }
+        double *H = cl.H + c * (ell + 1) * ell;
+        double *cs = cl.cs + c * ell, *sn = cl.sn + c * ell, *rh = cl.rh + c * (ell + 1);
+        const double hn = sqrt(col_sum(part2, nblk, m, c));
+        H[(k + 1) * ell + k] = hn;
+        for (int j = 0; j < k; ++j) {
+            const double u = H[j * ell + k], w = H[(j + 1) * ell + k];
+            H[j * ell + k] = cs[j] * u + sn[j] * w;
+            H[(j + 1) * ell + k] = -sn[j] * u + cs[j] * w;
+        }
+        const double u = H[k * ell + k], w = H[(k + 1) * ell + k];
+        const double rho = hypot(u, w);
+        if (rho == 0.0) {  // singular projected matrix: the step is not used
+            cl.open[c] = 0;
+            cl.done[c] = 1;
+            cl.status[c] = 1;
+            cl.inv[c] = 0.0;
+            continue;
+        }
+        const double cc = u / rho, ss = w / rho;
+        cs[k] = cc;
+        sn[k] = ss;
+        H[k * ell + k] = rho;
+        H[(k + 1) * ell + k] = 0.0;
+        const double r0 = rh[k];
+        rh[k] = cc * r0;
+        rh[k + 1] = -ss * r0;
+        cl.kc[c] = k + 1;
+        cl.iters[c] += 1;
+        if (fabs(rh[k + 1]) <= rtol * cl.bn[c] || hn == 0.0) {
+            cl.open[c] = 0;
+            cl.inv[c] = 0.0;
+        } else {
+            cl.inv[c] = 1.0 / hn;
+            any = 1;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        st->steps += 1;
+        if (!any) st->done = 1;
+    }
+}
+
+// q[r][c] *= inv[c] (0 for closed columns)
+__global__ void k_gm_scale(int64_t count, int64_t m, double *__restrict__ q, GmCols cl, const GmState *st, int always) {
+    if (!always && st->done) return;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < count) q[e] *= cl.inv[e % m];
+}
+
+// One work-group, end of a cycle: back substitution R y = rhat with k_i steps
+__global__ void k_gm_solve(int64_t m, int ell, GmCols cl) {
+    for (int64_t c = threadIdx.x; c < m; c += blockDim.x) {
+        const int kk = cl.kc[c];
+        if (kk == 0) continue;
+        const double *H = cl.H + c * (ell + 1) * ell, *rh = cl.rh + c * (ell + 1);
+        double *y = cl.y + c * ell;
+        for (int r = kk - 1; r >= 0; --r) {
+            double s = rh[r];
+            for (int q = r + 1; q < kk; ++q) s -= H[r * ell + q] * y[q];
+            y[r] = s / H[r * ell + r];
+        }
+        cl.est[c] = cl.bn[c] > 0.0 ? fabs(rh[kk]) / cl.bn[c] : 0.0;
+    }
+}
+
+// x[r][c] += sum_{j < k_c} Q_j[r][c] y[c][j]
+__global__ void k_gm_xupdate(int64_t n, int64_t m, int ell, const double *__restrict__ Q, GmCols cl,
+                             double *__restrict__ X) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * m) return;
+    const int64_t c = e % m;
+    const int kk = cl.kc[c];
+    if (kk == 0) return;
+    const double *y = cl.y + c * ell;
+    double x = X[e];
+    for (int j = 0; j < kk; ++j) x += Q[(int64_t)j * n * m + e] * y[j];
+    X[e] = x;
+}
+
+__global__ void k_gm_rows(int64_t n, int64_t m, const int64_t *__restrict__ perm, const double *__restrict__ src,
+                          int64_t lds, double *__restrict__ dst, int64_t ldd, int scatter) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * m) return;
+    const int64_t i = e / m, j = e % m;
+    if (scatter) dst[perm[i] * ldd + j] = src[i * lds + j];
+    else dst[i * ldd + j] = src[perm[i] * lds + j];
+}
+
+struct Ws {
+    double *Bt, *Xt, *Q, *part, *part2;
+    GmCols cl;
+    GmState *st;
+    char *mm;
+};
+
+int64_t host_nblocks(int64_t n) { return (n + kRowsPerBlk - 1) / kRowsPerBlk; }
+
+size_t small_bytes(int64_t m, int ell) {
+    const size_t per_col = (size_t)(ell + 1) * ell + 2 * (size_t)ell + (ell + 1) + ell + 3;
+    return align_up(sizeof(double) * per_col * m) + align_up(sizeof(int32_t) * 5 * m) + align_up(sizeof(GmState));
+}
+
+Ws carve_ws(const DevMat &dm, int64_t m, int ell, char *ws) {
+    const int64_t n = dm.n, nblk = host_nblocks(n);
+    Ws w;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        char *p = ws + off;
+        off += align_up(bytes);
+        return p;
+    };
+    w.Bt = (double *)take(sizeof(double) * n * m);
+    w.Xt = (double *)take(sizeof(double) * n * m);
+    w.Q = (double *)take(sizeof(double) * n * m * (ell + 1));
+    w.part = (double *)take(sizeof(double) * nblk * m * (ell + 1));
+    w.part2 = (double *)take(sizeof(double) * nblk * m);
+    double *d = (double *)take(sizeof(double) * m * ((size_t)(ell + 1) * ell + 2 * ell + (ell + 1) + ell + 3));
+    w.cl.H = d;
+    d += m * (ell + 1) * ell;
+    w.cl.cs = d;
+    d += m * ell;
+    w.cl.sn = d;
+    d += m * ell;
+    w.cl.rh = d;
+    d += m * (ell + 1);
+    w.cl.y = d;
+    d += m * ell;
+    w.cl.bn = d;
+    d += m;
+    w.cl.inv = d;
+    d += m;
+    w.cl.est = d;
+    int32_t *ip = (int32_t *)take(sizeof(int32_t) * 5 * m);
+    w.cl.open = ip;
+    w.cl.done = ip + m;
+    w.cl.kc = ip + 2 * m;
+    w.cl.iters = ip + 3 * m;
+    w.cl.status = ip + 4 * m;
+    w.st = (GmState *)take(sizeof(GmState));
+    w.mm = ws + off;
+    return w;
+}
+
+}  // namespace
+
+size_t gmres_ws_bytes(const DevMat &dm, int64_t m, int ell) {
+    const int64_t n = dm.n, nblk = host_nblocks(n);
+    return align_up(sizeof(double) * n * m) * 2 + align_up(sizeof(double) * n * m * (ell + 1)) +
+           align_up(sizeof(double) * nblk * m * (ell + 1)) + align_up(sizeof(double) * nblk * m) +
+           small_bytes(m, ell) + matmul_ws_bytes(dm, m);
+}
+
+h2x_status run_block_gmres(const DevMat &dm, const h2x_gmres_params &prm, int64_t m, const double *B, int64_t ldb,
+                           double *X, int64_t ldx, char *ws, size_t ws_bytes, h2x_gmres_info *info, hipStream_t st) {
+    const int ell = prm.restart;
+    if (ws_bytes < gmres_ws_bytes(dm, m, ell)) {
+        set_error("h2x_block_gmres: workspace too small");
+        return H2X_ENOMEM;
+    }
+    const int64_t n = dm.n, nm = n * m, nblk = host_nblocks(n);
+    Ws w = carve_ws(dm, m, ell, ws);
+    const dim3 g_el((unsigned)((nm + 255) / 256)), b256(256);
+    const dim3 g_rb((unsigned)nblk, (unsigned)((m + kCols - 1) / kCols));
+    const int check = prm.check_every > 0 ? prm.check_every : 1;
+    hipError_t e = hipSuccess;
+    auto sync_state = [&](GmState &h) {
+        if (e == hipSuccess) e = hipMemcpyAsync(&h, w.st, sizeof(GmState), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+    };
+
+    // tree order: B~ = B[perm], X~ = X0[perm]; ||b_i||
+    hipLaunchKernelGGL(k_gm_rows, g_el, b256, 0, st, n, m, dm.perm, B, ldb, w.Bt, m, 0);
+    hipLaunchKernelGGL(k_gm_rows, g_el, b256, 0, st, n, m, dm.perm, X, ldx, w.Xt, m, 0);
+    hipLaunchKernelGGL(k_gm_update, g_rb, b256, 0, st, n, m, -1, ell, (const double *)nullptr, w.Bt, w.cl, w.part2,
+                       (const GmState *)w.st);
+    hipLaunchKernelGGL(k_gm_init, dim3(1), b256, 0, st, m, nblk, w.part2, w.cl, w.st);
+    e = hipGetLastError();
+
+    GmState hs{};
+    int64_t steps_known = 0;  // Arnoldi steps run, as of the last state read
+    int32_t cycles = 0;
+    for (;;) {
+        // r = b - A x into q_0, its norms, the cycle's start, q_0 = r / ||r||
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(w.Q, w.Bt, sizeof(double) * nm, hipMemcpyDeviceToDevice, st);
+        if (e == hipSuccess) e = run_matmul(dm, m, -1.0, w.Xt, m, 1.0, w.Q, m, true, w.mm, st);
+        if (e != hipSuccess) break;
+        hipLaunchKernelGGL(k_gm_update, g_rb, b256, 0, st, n, m, -1, ell, (const double *)nullptr, w.Q, w.cl, w.part2,
+                           (const GmState *)w.st);
+        hipLaunchKernelGGL(k_gm_start, dim3(1), b256, 0, st, m, nblk, ell, prm.rtol, w.part2, w.cl, w.st);
+        hipLaunchKernelGGL(k_gm_scale, g_el, b256, 0, st, nm, m, w.Q, w.cl, (const GmState *)w.st, 1);
+        e = hipGetLastError();
+        sync_state(hs);
+        if (e != hipSuccess) break;
+        steps_known = hs.steps;
+        if (hs.done || steps_known >= prm.max_iter) break;
+        ++cycles;
+        // Arnoldi steps; the host looks at the state every `check` steps
+        int64_t launched = 0;  // steps launched since the last state read
+        for (int k = 0; k < ell; ++k) {
+            if (steps_known + launched >= prm.max_iter) break;
+            double *qk = w.Q + (int64_t)k * nm, *q1 = qk + nm;
+            e = run_matmul(dm, m, 1.0, qk, m, 0.0, q1, m, true, w.mm, st, nullptr, (const int32_t *)w.st);
+            if (e != hipSuccess) break;
+            hipLaunchKernelGGL(k_gm_dots, g_rb, b256, 0, st, n, m, k, w.Q, q1, w.part, (const GmState *)w.st);
+            hipLaunchKernelGGL(k_gm_hcol, dim3((unsigned)(((int64_t)(k + 1) * m + 255) / 256)), b256, 0, st, m, nblk,
+                               k, ell, w.part, w.cl, (const GmState *)w.st);
+            hipLaunchKernelGGL(k_gm_update, g_rb, b256, 0, st, n, m, k, ell, w.Q, q1, w.cl, w.part2,
+                               (const GmState *)w.st);
+            hipLaunchKernelGGL(k_gm_rotate, dim3(1), b256, 0, st, m, nblk, k, ell, prm.rtol, w.part2, w.cl, w.st);
+            hipLaunchKernelGGL(k_gm_scale, g_el, b256, 0, st, nm, m, q1, w.cl, (const GmState *)w.st, 0);
+            e = hipGetLastError();
+            if (e != hipSuccess) break;
+            ++launched;
+            if (launched % check == 0 || k + 1 == ell) {
+                sync_state(hs);
+                if (e != hipSuccess) break;
+                steps_known = hs.steps;
+                launched = 0;
+                if (hs.done) break;
+            }
+        }
+        if (e != hipSuccess) break;
+        // x += V y with each column's own number of steps
+        hipLaunchKernelGGL(k_gm_solve, dim3(1), b256, 0, st, m, ell, w.cl);
+        hipLaunchKernelGGL(k_gm_xupdate, g_el, b256, 0, st, n, m, ell, w.Q, w.cl, w.Xt);
+        e = hipGetLastError();
+        if (e == hipSuccess && launched > 0) sync_state(hs);
+        if (e != hipSuccess) break;
+        steps_known = hs.steps;
+    }
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_gm_rows, g_el, b256, 0, st, n, m, dm.perm, w.Xt, m, X, ldx, 1);
+        e = hipGetLastError();
+    }
+    std::vector<int32_t> iters(m), status(m);
+    std::vector<double> est(m);
+    if (e == hipSuccess) e = hipMemcpyAsync(iters.data(), w.cl.iters, sizeof(int32_t) * m, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(status.data(), w.cl.status, sizeof(int32_t) * m, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(est.data(), w.cl.est, sizeof(double) * m, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(&hs, w.st, sizeof(GmState), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        set_error(std::string("h2x_block_gmres: ") + hipGetErrorString(e));
+        return H2X_EHIP;
+    }
+    if (info) {
+        info->iters = hs.steps;
+        info->cycles = cycles;
+        int broke = 0, open = 0;
+        for (int64_t c = 0; c < m; ++c) {
+            broke |= status[c] == 1;
+            open |= status[c] == 2;
+            if (info->col_iters) info->col_iters[c] = iters[c];
+            if (info->col_status) info->col_status[c] = status[c];
+            if (info->col_res) info->col_res[c] = est[c];
+        }
+        info->status = broke ? H2X_EBREAKDOWN : (open ? H2X_ENOCONV : H2X_OK);
+    }
+    return H2X_OK;
+}
+
+}  // namespace h2x

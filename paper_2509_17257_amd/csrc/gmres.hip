@@ -46,54 +46,69 @@ struct GmCols {  // per-column data, m columns
     double *y;        // least-squares coefficients, ell per column
     double *inv;      // scale of the new basis vector (0 for a closed column)
     double *est;      // |rhat[k_i]| / ||b_i|| after the column's last cycle
+    double *nrm2;     // squared column norms of the latest norm pass
     int32_t *open, *done, *kc, *iters, *status;
 };
 
-// part[(j * nblk + blk) * m + c] = sum over the rows of block blk of Q_j[r][c] a[r][c], j = 0..k
-__global__ __launch_bounds__(256) void k_gm_dots(int64_t n, int64_t m, int k, const double *__restrict__ Q,
+// part[(j * nblk + blk) * m + c] = sum over the rows of block blk of Q_j[r][c] a[r][c];
+// projection j = blockIdx.z (0..k)
+__global__ __launch_bounds__(256) void k_gm_dots(int64_t n, int64_t m, const double *__restrict__ Q,
                                                  const double *__restrict__ a, double *__restrict__ part,
                                                  const GmState *__restrict__ st) {
     if (st->done) return;
     __shared__ double red[kRowGroups][kCols];
     const int tid = threadIdx.x, rg = tid / kCols, jl = tid % kCols;
-    const int64_t blk = blockIdx.x, nblk = gridDim.x, c = (int64_t)blockIdx.y * kCols + jl;
+    const int64_t blk = blockIdx.x, nblk = gridDim.x, c = (int64_t)blockIdx.y * kCols + jl, j = blockIdx.z;
     const int64_t r0 = blk * kRowsPerBlk, r1 = min(n, r0 + kRowsPerBlk);
-    double av[kRowsPerThread];
+    const double *q = Q + j * n * m;
+    double s = 0.0;
 #pragma unroll
     for (int u = 0; u < kRowsPerThread; ++u) {
         const int64_t r = r0 + rg + kRowGroups * u;
-        av[u] = (c < m && r < r1) ? a[r * m + c] : 0.0;
+        if (c < m && r < r1) s += q[r * m + c] * a[r * m + c];
     }
-    for (int j = 0; j <= k; ++j) {
-        const double *q = Q + (int64_t)j * n * m;
-        double s = 0.0;
-#pragma unroll
-        for (int u = 0; u < kRowsPerThread; ++u) {
-            const int64_t r = r0 + rg + kRowGroups * u;
-            if (c < m && r < r1) s += q[r * m + c] * av[u];
-        }
-        red[rg][jl] = s;
-        __syncthreads();
-        if (rg == 0 && c < m) {
-            double t = 0.0;
-            for (int g = 0; g < kRowGroups; ++g) t += red[g][jl];
-            part[((int64_t)j * nblk + blk) * m + c] = t;
-        }
-        __syncthreads();
+    red[rg][jl] = s;
+    __syncthreads();
+    if (rg == 0 && c < m) {
+        double t = 0.0;
+        for (int g = 0; g < kRowGroups; ++g) t += red[g][jl];
+        part[(j * nblk + blk) * m + c] = t;
     }
 }
 
-// H[c][j][k] = sum over row blocks of part (in block order), open columns only
-__global__ void k_gm_hcol(int64_t m, int64_t nblk, int k, int ell, const double *__restrict__ part, GmCols cl,
-                          const GmState *__restrict__ st) {
+// Sum of the nblk partials part[(b * stride) + off] in a fixed order by one wave:
+// lane l adds b = l, l + 64, ... in turn, then a fixed butterfly; lane 0's value is
+// the result (the same on every run).
+__device__ inline double wave_sum(const double *__restrict__ part, int64_t nblk, int64_t stride, int64_t off) {
+    const int lane = threadIdx.x & 63;
+    double v = 0.0;
+    for (int64_t b = lane; b < nblk; b += 64) v += part[b * stride + off];
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    return v;
+}
+
+// H[c][j][k] = sum over row blocks of part, open columns only; one wave per (j, c)
+__global__ __launch_bounds__(256) void k_gm_hcol(int64_t m, int64_t nblk, int k, int ell,
+                                                 const double *__restrict__ part, GmCols cl,
+                                                 const GmState *__restrict__ st) {
     if (st->done) return;
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t e = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     if (e >= (int64_t)(k + 1) * m) return;
     const int64_t j = e / m, c = e % m;
     if (!cl.open[c]) return;
-    double s = 0.0;
-    for (int64_t b = 0; b < nblk; ++b) s += part[(j * nblk + b) * m + c];
-    cl.H[(c * (ell + 1) + j) * ell + k] = s;
+    const double s = wave_sum(part + j * nblk * m, nblk, m, c);
+    if ((threadIdx.x & 63) == 0) cl.H[(c * (ell + 1) + j) * ell + k] = s;
+}
+
+// nrm2[c] = sum over row blocks of part2 (squared norms); one wave per column
+__global__ __launch_bounds__(256) void k_gm_colsum(int64_t m, int64_t nblk, const double *__restrict__ part2,
+                                                   GmCols cl, const GmState *__restrict__ st, int always) {
+    if (!always && st->done) return;
+    const int64_t c = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (c >= m) return;
+    const double s = wave_sum(part2, nblk, m, c);
+    if ((threadIdx.x & 63) == 0) cl.nrm2[c] = s;
 }
 
 // a -= sum_{j <= k} Q_j h[j][k] on the open columns (k < 0: no subtraction, every
@@ -142,16 +157,11 @@ __global__ __launch_bounds__(256) void k_gm_update(int64_t n, int64_t m, int k, 
     }
 }
 
-__device__ inline double col_sum(const double *part2, int64_t nblk, int64_t m, int64_t c) {
-    double s = 0.0;
-    for (int64_t b = 0; b < nblk; ++b) s += part2[b * m + c];
-    return s;
-}
-
-// One work-group: ||b_i|| and the per-column state before the first cycle.
-__global__ void k_gm_init(int64_t m, int64_t nblk, const double *__restrict__ part2, GmCols cl, GmState *st) {
+// One work-group: ||b_i|| (nrm2 holds the squared norms of B) and the per-column
+// state before the first cycle.
+__global__ void k_gm_init(int64_t m, GmCols cl, GmState *st) {
     for (int64_t c = threadIdx.x; c < m; c += blockDim.x) {
-        cl.bn[c] = sqrt(col_sum(part2, nblk, m, c));
+        cl.bn[c] = sqrt(cl.nrm2[c]);
         cl.done[c] = 0;
         cl.open[c] = 0;
         cl.kc[c] = 0;
@@ -165,10 +175,9 @@ __global__ void k_gm_init(int64_t m, int64_t nblk, const double *__restrict__ pa
     }
 }
 
-// One work-group, start of a cycle: part2 holds the squared norms of r = b - A x.
+// One work-group, start of a cycle: nrm2 holds the squared norms of r = b - A x.
 // Columns within the bound are done; the others open with rhat = ||r|| e_0.
-__global__ void k_gm_start(int64_t m, int64_t nblk, int ell, double rtol, const double *__restrict__ part2, GmCols cl,
-                           GmState *st) {
+__global__ void k_gm_start(int64_t m, int ell, double rtol, GmCols cl, GmState *st) {
     __shared__ int any;
     if (threadIdx.x == 0) any = 0;
     __syncthreads();
@@ -177,7 +186,7 @@ __global__ void k_gm_start(int64_t m, int64_t nblk, int ell, double rtol, const 
         cl.kc[c] = 0;
         cl.inv[c] = 0.0;
         if (cl.done[c]) continue;
-        const double beta = sqrt(col_sum(part2, nblk, m, c));
+        const double beta = sqrt(cl.nrm2[c]);
         if (beta <= rtol * cl.bn[c]) {
             cl.done[c] = 1;
             cl.status[c] = 0;
@@ -194,9 +203,9 @@ __global__ void k_gm_start(int64_t m, int64_t nblk, int ell, double rtol, const 
     if (threadIdx.x == 0) st->done = any ? 0 : 1;
 }
 
-// One work-group, end of step k: h[k+1][k] = ||a||, rotations, rhat, closing.
-__global__ void k_gm_rotate(int64_t m, int64_t nblk, int k, int ell, double rtol, const double *__restrict__ part2,
-                            GmCols cl, GmState *st) {
+// One work-group, end of step k: h[k+1][k] = ||a|| (nrm2: squared norms of a),
+// rotations, rhat, closing.
+__global__ void k_gm_rotate(int64_t m, int k, int ell, double rtol, GmCols cl, GmState *st) {
     if (st->done) return;
     __shared__ int any;
     if (threadIdx.x == 0) any = 0;
@@ -208,7 +217,7 @@ __global__ void k_gm_rotate(int64_t m, int64_t nblk, int k, int ell, double rtol
         }
         double *H = cl.H + c * (ell + 1) * ell;
         double *cs = cl.cs + c * ell, *sn = cl.sn + c * ell, *rh = cl.rh + c * (ell + 1);
-        const double hn = sqrt(col_sum(part2, nblk, m, c));
+        const double hn = sqrt(cl.nrm2[c]);
         H[(k + 1) * ell + k] = hn;
         for (int j = 0; j < k; ++j) {
             const double u = H[j * ell + k], w = H[(j + 1) * ell + k];
@@ -305,7 +314,7 @@ struct Ws {
 int64_t host_nblocks(int64_t n) { return (n + kRowsPerBlk - 1) / kRowsPerBlk; }
 
 size_t small_bytes(int64_t m, int ell) {
-    const size_t per_col = (size_t)(ell + 1) * ell + 2 * (size_t)ell + (ell + 1) + ell + 3;
+    const size_t per_col = (size_t)(ell + 1) * ell + 2 * (size_t)ell + (ell + 1) + ell + 4;
     return align_up(sizeof(double) * per_col * m) + align_up(sizeof(int32_t) * 5 * m) + align_up(sizeof(GmState));
 }
 
@@ -323,7 +332,7 @@ Ws carve_ws(const DevMat &dm, int64_t m, int ell, char *ws) {
     w.Q = (double *)take(sizeof(double) * n * m * (ell + 1));
     w.part = (double *)take(sizeof(double) * nblk * m * (ell + 1));
     w.part2 = (double *)take(sizeof(double) * nblk * m);
-    double *d = (double *)take(sizeof(double) * m * ((size_t)(ell + 1) * ell + 2 * ell + (ell + 1) + ell + 3));
+    double *d = (double *)take(sizeof(double) * m * ((size_t)(ell + 1) * ell + 2 * ell + (ell + 1) + ell + 4));
     w.cl.H = d;
     d += m * (ell + 1) * ell;
     w.cl.cs = d;
@@ -339,6 +348,8 @@ Ws carve_ws(const DevMat &dm, int64_t m, int ell, char *ws) {
     w.cl.inv = d;
     d += m;
     w.cl.est = d;
+    d += m;
+    w.cl.nrm2 = d;
     int32_t *ip = (int32_t *)take(sizeof(int32_t) * 5 * m);
     w.cl.open = ip;
     w.cl.done = ip + m;
@@ -370,6 +381,7 @@ h2x_status run_block_gmres(const DevMat &dm, const h2x_gmres_params &prm, int64_
     Ws w = carve_ws(dm, m, ell, ws);
     const dim3 g_el((unsigned)((nm + 255) / 256)), b256(256);
     const dim3 g_rb((unsigned)nblk, (unsigned)((m + kCols - 1) / kCols));
+    const dim3 g_col((unsigned)((m + 3) / 4));  // one wave per column
     const int check = prm.check_every > 0 ? prm.check_every : 1;
     hipError_t e = hipSuccess;
     auto sync_state = [&](GmState &h) {
@@ -382,7 +394,8 @@ h2x_status run_block_gmres(const DevMat &dm, const h2x_gmres_params &prm, int64_
     hipLaunchKernelGGL(k_gm_rows, g_el, b256, 0, st, n, m, dm.perm, X, ldx, w.Xt, m, 0);
     hipLaunchKernelGGL(k_gm_update, g_rb, b256, 0, st, n, m, -1, ell, (const double *)nullptr, w.Bt, w.cl, w.part2,
                        (const GmState *)w.st);
-    hipLaunchKernelGGL(k_gm_init, dim3(1), b256, 0, st, m, nblk, w.part2, w.cl, w.st);
+    hipLaunchKernelGGL(k_gm_colsum, g_col, b256, 0, st, m, nblk, w.part2, w.cl, (const GmState *)w.st, 1);
+    hipLaunchKernelGGL(k_gm_init, dim3(1), b256, 0, st, m, w.cl, w.st);
     e = hipGetLastError();
 
     GmState hs{};
@@ -396,7 +409,8 @@ h2x_status run_block_gmres(const DevMat &dm, const h2x_gmres_params &prm, int64_
         if (e != hipSuccess) break;
         hipLaunchKernelGGL(k_gm_update, g_rb, b256, 0, st, n, m, -1, ell, (const double *)nullptr, w.Q, w.cl, w.part2,
                            (const GmState *)w.st);
-        hipLaunchKernelGGL(k_gm_start, dim3(1), b256, 0, st, m, nblk, ell, prm.rtol, w.part2, w.cl, w.st);
+        hipLaunchKernelGGL(k_gm_colsum, g_col, b256, 0, st, m, nblk, w.part2, w.cl, (const GmState *)w.st, 1);
+        hipLaunchKernelGGL(k_gm_start, dim3(1), b256, 0, st, m, ell, prm.rtol, w.cl, w.st);
         hipLaunchKernelGGL(k_gm_scale, g_el, b256, 0, st, nm, m, w.Q, w.cl, (const GmState *)w.st, 1);
         e = hipGetLastError();
         sync_state(hs);
@@ -411,12 +425,14 @@ h2x_status run_block_gmres(const DevMat &dm, const h2x_gmres_params &prm, int64_
             double *qk = w.Q + (int64_t)k * nm, *q1 = qk + nm;
             e = run_matmul(dm, m, 1.0, qk, m, 0.0, q1, m, true, w.mm, st, nullptr, (const int32_t *)w.st);
             if (e != hipSuccess) break;
-            hipLaunchKernelGGL(k_gm_dots, g_rb, b256, 0, st, n, m, k, w.Q, q1, w.part, (const GmState *)w.st);
-            hipLaunchKernelGGL(k_gm_hcol, dim3((unsigned)(((int64_t)(k + 1) * m + 255) / 256)), b256, 0, st, m, nblk,
-                               k, ell, w.part, w.cl, (const GmState *)w.st);
+            hipLaunchKernelGGL(k_gm_dots, dim3(g_rb.x, g_rb.y, (unsigned)(k + 1)), b256, 0, st, n, m, w.Q, q1, w.part,
+                               (const GmState *)w.st);
+            hipLaunchKernelGGL(k_gm_hcol, dim3((unsigned)(((int64_t)(k + 1) * m + 3) / 4)), b256, 0, st, m, nblk, k,
+                               ell, w.part, w.cl, (const GmState *)w.st);
             hipLaunchKernelGGL(k_gm_update, g_rb, b256, 0, st, n, m, k, ell, w.Q, q1, w.cl, w.part2,
                                (const GmState *)w.st);
-            hipLaunchKernelGGL(k_gm_rotate, dim3(1), b256, 0, st, m, nblk, k, ell, prm.rtol, w.part2, w.cl, w.st);
+            hipLaunchKernelGGL(k_gm_colsum, g_col, b256, 0, st, m, nblk, w.part2, w.cl, (const GmState *)w.st, 0);
+            hipLaunchKernelGGL(k_gm_rotate, dim3(1), b256, 0, st, m, k, ell, prm.rtol, w.cl, w.st);
             hipLaunchKernelGGL(k_gm_scale, g_el, b256, 0, st, nm, m, q1, w.cl, (const GmState *)w.st, 0);
             e = hipGetLastError();
             if (e != hipSuccess) break;

@@ -299,6 +299,50 @@ h2x_status h2x_block_gmres(const h2x_mat *A, const h2x_gmres_params *prm, int64_
                            double *X, int64_t ldx, void *dev_ws, size_t ws_bytes, h2x_gmres_info *info,
                            void *hip_stream);
 
+/* ---- right-hand-side chunking --------------------------------------------------- */
+/* Section 5 (the remarks on the memory footprint of block CG and block GMRES): the
+ * solvers' auxiliary storage grows linearly in the number of right-hand sides -- block
+ * CG O(6 n m), block GMRES O(n (restart + 1) m) -- so for a large m the columns are
+ * solved in chunks of at most m_chunk; the paper's conclusions name choosing m_chunk
+ * adaptively from the available memory and the compute rate as the next step. */
+typedef enum { H2X_SOLVER_CG = 0, H2X_SOLVER_GMRES = 1 } h2x_solver;
+
+/* Device workspace of one solve of m right-hand sides (h2x_block_cg_workspace_bytes or
+ * h2x_block_gmres_workspace_bytes of an operator built from this plan and storage),
+ * computed from the plan alone.  0 on bad arguments. */
+size_t h2x_solve_workspace_bytes(const h2x_plan *plan, h2x_prec storage, int32_t solver, int64_t m,
+                                 int32_t restart);
+
+/* m_chunk for m right-hand sides under a device-memory budget of mem_bytes for the
+ * solver workspace.  Without a throughput curve (cand_ms NULL or ncand 0): the largest
+ * chunk <= m whose workspace fits.  With one (cand_m[i] columns take cand_ms[i] ms per
+ * product, e.g. from h2x_product_times): among the candidates that fit, the one with the
+ * least predicted time ceil(m / c) * cand_ms(c), ties to the larger chunk (candidates
+ * larger than m count as m; none fitting falls back to the memory rule).  Host only.
+ * H2X_ENOMEM when a single column does not fit; H2X_EINVAL on bad arguments. */
+h2x_status h2x_choose_chunk(const h2x_plan *plan, h2x_prec storage, int32_t solver, int32_t restart, int64_t m,
+                            size_t mem_bytes, int32_t ncand, const int64_t *cand_m, const double *cand_ms,
+                            int64_t *m_chunk);
+
+/* The throughput curve: mean time of one product (h2x_matmul, tuned tile shapes if any)
+ * for each candidate column count, reps timed products after an untimed one, HIP events on
+ * the given stream.  ms: host, ncand entries.  Blocking. */
+size_t h2x_product_times_workspace_bytes(const h2x_mat *A, int32_t ncand, const int64_t *cand_m);
+h2x_status h2x_product_times(const h2x_mat *A, int32_t ncand, const int64_t *cand_m, int32_t reps, void *dev_ws,
+                             size_t ws_bytes, void *hip_stream, double *ms);
+
+/* Block CG / block GMRES over the columns in chunks of m_chunk (the last may be smaller):
+ * each chunk is an independent solve of the column slice (B + c0, ldb) -> (X + c0, ldx),
+ * in place, with a workspace for m_chunk columns.  info: per-column arrays (m entries) are
+ * filled chunk by chunk; iters / cycles / outer_iters are the maxima over the chunks;
+ * status is the first non-OK chunk status. */
+h2x_status h2x_block_cg_chunked(const h2x_mat *A, const h2x_cg_params *prm, int64_t m, int64_t m_chunk,
+                                const double *B, int64_t ldb, double *X, int64_t ldx, void *dev_ws, size_t ws_bytes,
+                                h2x_cg_info *info, void *hip_stream);
+h2x_status h2x_block_gmres_chunked(const h2x_mat *A, const h2x_gmres_params *prm, int64_t m, int64_t m_chunk,
+                                   const double *B, int64_t ldb, double *X, int64_t ldx, void *dev_ws,
+                                   size_t ws_bytes, h2x_gmres_info *info, void *hip_stream);
+
 /* ---- tuning ----------------------------------------------------------------- */
 /* Tile shapes of the matrix-core kernels: columns per work-group of the forward
  * leaf and transfer passes (16 * nj_transfer), of the coupling (16 * nj_coupling)

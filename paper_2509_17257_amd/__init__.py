@@ -129,6 +129,14 @@ def load_library():
         "h2x_block_gmres_workspace_bytes": (SZ, [P, I64, I32]),
         "h2x_block_gmres": (C.c_int, [P, C.POINTER(_GmresParams), I64, P, I64, P, I64, P, SZ,
                                       C.POINTER(_GmresInfo), P]),
+        "h2x_solve_workspace_bytes": (SZ, [P, I32, I32, I64, I32]),
+        "h2x_choose_chunk": (C.c_int, [P, I32, I32, I32, I64, SZ, I32, P, P, P]),
+        "h2x_product_times_workspace_bytes": (SZ, [P, I32, P]),
+        "h2x_product_times": (C.c_int, [P, I32, P, I32, P, SZ, P, P]),
+        "h2x_block_cg_chunked": (C.c_int, [P, C.POINTER(_CgParams), I64, I64, P, I64, P, I64, P, SZ,
+                                           C.POINTER(_CgInfo), P]),
+        "h2x_block_gmres_chunked": (C.c_int, [P, C.POINTER(_GmresParams), I64, I64, P, I64, P, I64, P, SZ,
+                                              C.POINTER(_GmresInfo), P]),
         "h2x_mat_autotune_workspace_bytes": (SZ, [P, I64]),
         "h2x_mat_autotune": (C.c_int, [P, I64, P, SZ, P, C.POINTER(_TuneInfo)]),
         "h2x_last_error": (C.c_char_p, []),
@@ -277,6 +285,19 @@ class H2Matrix:
         return dict(nj_transfer=info.nj_transfer, nj_coupling=info.nj_coupling, np_leaf=info.np_leaf,
                     overlap=info.overlap, fuse_up=info.fuse_up, ms_default=info.ms_default,
                     ms_tuned=info.ms_tuned)
+
+    def product_times(self, cands, reps: int = 5) -> list:
+        """Mean time (ms) of one product for each column count in cands (h2x_product_times):
+        the throughput curve of the chunk policy."""
+        import torch
+        c = np.ascontiguousarray(cands, dtype=np.int64)
+        lib = load_library()
+        nb = lib.h2x_product_times_workspace_bytes(self._h, len(c), _ptr(c))
+        ws = torch.empty(max(nb, 256), dtype=torch.uint8, device=self.device)
+        ms = np.zeros(len(c))
+        _check(lib.h2x_product_times(self._h, len(c), _ptr(c), int(reps), C.c_void_p(ws.data_ptr()), ws.numel(),
+                                     _stream(torch, self.device), _ptr(ms)), "h2x_product_times")
+        return [float(v) for v in ms]
 
     def set_ell(self, ell: float) -> None:
         """Refill S and the near field for a new kernel length scale (h2x_mat_set_ell)."""
@@ -470,6 +491,89 @@ def block_gmres_solve(A: H2Matrix, B, X0=None, *, rtol=1e-8, restart=30, max_ite
                                C.c_void_p(X.data_ptr()), X.stride(0), C.c_void_p(ws.data_ptr()), ws.numel(),
                                C.byref(info), _stream(torch, B.device)), "h2x_block_gmres")
     return X, GmresInfo(info.iters, info.cycles, info.status, res, its, sts)
+
+
+_SOLVER = {"cg": 0, "gmres": 1}
+
+
+def solve_workspace_bytes(plan: Plan, m: int, *, storage="f64", solver="cg", restart=30) -> int:
+    """Device workspace of one solve of m right-hand sides (h2x_solve_workspace_bytes)."""
+    return load_library().h2x_solve_workspace_bytes(plan._h, _PREC[storage], _SOLVER[solver], int(m), int(restart))
+
+
+def choose_chunk(plan: Plan, m: int, mem_bytes: int, *, storage="f64", solver="cg", restart=30, curve=None) -> int:
+    """m_chunk for m right-hand sides under a workspace budget (h2x_choose_chunk); curve:
+    optional {column count: ms per product} throughput curve."""
+    out = np.zeros(1, np.int64)
+    if curve:
+        cm = np.ascontiguousarray(list(curve.keys()), dtype=np.int64)
+        ms = np.ascontiguousarray(list(curve.values()), dtype=np.float64)
+        args = (len(cm), _ptr(cm), _ptr(ms))
+    else:
+        args = (0, None, None)
+    _check(load_library().h2x_choose_chunk(plan._h, _PREC[storage], _SOLVER[solver], int(restart), int(m),
+                                           int(mem_bytes), *args, _ptr(out)), "h2x_choose_chunk")
+    return int(out[0])
+
+
+def block_cg_solve_chunked(A: H2Matrix, B, m_chunk: int, X0=None, *, rtol=1e-8, max_iter=10000,
+                           freeze_converged=False, check_every=4, variant="independent"):
+    """Block CG over the columns of B in chunks of m_chunk (h2x_block_cg_chunked)."""
+    import torch
+    if B.dtype != torch.float64 or B.device.type != "cuda" or B.dim() != 2 or B.stride(1) != 1:
+        raise ValueError("B must be a row-major (n, m) float64 CUDA tensor")
+    n, m = B.shape
+    X = torch.zeros_like(B) if X0 is None else X0.clone()
+    lib = load_library()
+    mc = min(int(m_chunk), m)
+    nb = solve_workspace_bytes(A.plan, mc, storage=A.storage, solver="cg")
+    ws = torch.empty(max(nb, 256), dtype=torch.uint8, device=B.device)
+    info, rel, its, sts, sys = _new_info(m, 1)
+    prm = _CgParams(float(rtol), int(max_iter), int(bool(freeze_converged)), int(check_every), _VARIANT[variant], 0)
+    _check(lib.h2x_block_cg_chunked(A._h, C.byref(prm), m, mc, C.c_void_p(B.data_ptr()), B.stride(0),
+                                    C.c_void_p(X.data_ptr()), X.stride(0), C.c_void_p(ws.data_ptr()), ws.numel(),
+                                    C.byref(info), _stream(torch, B.device)), "h2x_block_cg_chunked")
+    return X, _info(info, rel, its, sts, sys, 1, m)
+
+
+def block_gmres_solve_chunked(A: H2Matrix, B, m_chunk: int, X0=None, *, rtol=1e-8, restart=30, max_iter=10000,
+                              check_every=4):
+    """Block GMRES over the columns of B in chunks of m_chunk (h2x_block_gmres_chunked)."""
+    import torch
+    if B.dtype != torch.float64 or B.device.type != "cuda" or B.dim() != 2 or B.stride(1) != 1:
+        raise ValueError("B must be a row-major (n, m) float64 CUDA tensor")
+    n, m = B.shape
+    X = torch.zeros_like(B) if X0 is None else X0.clone()
+    lib = load_library()
+    mc = min(int(m_chunk), m)
+    nb = solve_workspace_bytes(A.plan, mc, storage=A.storage, solver="gmres", restart=restart)
+    ws = torch.empty(max(nb, 256), dtype=torch.uint8, device=B.device)
+    res = np.zeros(m)
+    its = np.zeros(m, np.int32)
+    sts = np.zeros(m, np.int32)
+    i32 = lambda a: a.ctypes.data_as(C.POINTER(C.c_int32))
+    info = _GmresInfo(0, 0, 0, 0, res.ctypes.data_as(C.POINTER(C.c_double)), i32(its), i32(sts))
+    prm = _GmresParams(float(rtol), int(restart), int(max_iter), int(check_every), 0)
+    _check(lib.h2x_block_gmres_chunked(A._h, C.byref(prm), m, mc, C.c_void_p(B.data_ptr()), B.stride(0),
+                                       C.c_void_p(X.data_ptr()), X.stride(0), C.c_void_p(ws.data_ptr()), ws.numel(),
+                                       C.byref(info), _stream(torch, B.device)), "h2x_block_gmres_chunked")
+    return X, GmresInfo(info.iters, info.cycles, info.status, res, its, sts)
+
+
+def solve_chunked(A: H2Matrix, B, mem_bytes: int, *, solver="cg", candidates=(8, 16, 32, 64, 128), restart=30,
+                  **kw):
+    """Solve A X = B in right-hand-side chunks sized by the chunk policy: the throughput
+    curve of the candidate column counts (h2x_product_times), then h2x_choose_chunk under
+    the workspace budget mem_bytes, then the chunked solver.  Returns (X, info, m_chunk)."""
+    m = B.shape[1]
+    cands = sorted({min(int(c), m) for c in candidates})
+    curve = dict(zip(cands, A.product_times(cands)))
+    mc = choose_chunk(A.plan, m, mem_bytes, storage=A.storage, solver=solver, restart=restart, curve=curve)
+    if solver == "cg":
+        X, info = block_cg_solve_chunked(A, B, mc, **kw)
+    else:
+        X, info = block_gmres_solve_chunked(A, B, mc, restart=restart, **kw)
+    return X, info, mc
 
 
 def block_cg_refine(A: H2Matrix, A_lo: H2Matrix, B, *, rtol=1e-10, inner_rtol=1e-4, max_outer=50,

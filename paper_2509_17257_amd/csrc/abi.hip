@@ -352,6 +352,75 @@ h2x_status h2x_block_gmres(const h2x_mat *A, const h2x_gmres_params *prm, int64_
     return run_block_gmres(A->dm, *prm, m, B, ldb, X, ldx, (char *)dev_ws, ws_bytes, info, (hipStream_t)hip_stream);
 }
 
+size_t h2x_solve_workspace_bytes(const h2x_plan *plan, h2x_prec storage, int32_t solver, int64_t m, int32_t restart) {
+    if (!plan || storage < H2X_F64 || storage > H2X_BF16 || m < 1) return 0;
+    DevMat dm;
+    mat_layout(*plan->p, storage, &dm, nullptr);  // sizes only: no device memory behind it
+    return solve_ws_bytes(dm, solver, m, restart);
+}
+
+h2x_status h2x_choose_chunk(const h2x_plan *plan, h2x_prec storage, int32_t solver, int32_t restart, int64_t m,
+                            size_t mem_bytes, int32_t ncand, const int64_t *cand_m, const double *cand_ms,
+                            int64_t *m_chunk) {
+    if (!plan || !m_chunk) return fail(H2X_EINVAL, "h2x_choose_chunk: NULL argument");
+    if (storage < H2X_F64 || storage > H2X_BF16 || m < 1 || ncand < 0 || (ncand > 0 && cand_ms && !cand_m))
+        return fail(H2X_EINVAL, "h2x_choose_chunk: bad storage, m or candidates");
+    if (solver != H2X_SOLVER_CG && !(solver == H2X_SOLVER_GMRES && restart >= 1))
+        return fail(H2X_EINVAL, "h2x_choose_chunk: unknown solver or restart < 1");
+    DevMat dm;
+    mat_layout(*plan->p, storage, &dm, nullptr);
+    return choose_chunk(dm, solver, restart, m, mem_bytes, ncand, cand_m, cand_ms, m_chunk);
+}
+
+size_t h2x_product_times_workspace_bytes(const h2x_mat *A, int32_t ncand, const int64_t *cand_m) {
+    if (!A || ncand < 1 || !cand_m) return 0;
+    return product_times_ws_bytes(A->dm, ncand, cand_m);
+}
+
+h2x_status h2x_product_times(const h2x_mat *A, int32_t ncand, const int64_t *cand_m, int32_t reps, void *dev_ws,
+                             size_t ws_bytes, void *hip_stream, double *ms) {
+    if (!A || !cand_m || !ms || !dev_ws) return fail(H2X_EINVAL, "h2x_product_times: NULL argument");
+    if (ncand < 1 || reps < 1) return fail(H2X_EINVAL, "h2x_product_times: need ncand >= 1 and reps >= 1");
+    for (int32_t i = 0; i < ncand; ++i)
+        if (cand_m[i] < 1) return fail(H2X_EINVAL, "h2x_product_times: column counts must be >= 1");
+    if (!aligned(dev_ws)) return fail(H2X_EINVAL, "h2x_product_times: workspace not 256-byte aligned");
+    return run_product_times(A->dm, ncand, cand_m, reps, (char *)dev_ws, ws_bytes, (hipStream_t)hip_stream, ms);
+}
+
+h2x_status h2x_block_cg_chunked(const h2x_mat *A, const h2x_cg_params *prm, int64_t m, int64_t m_chunk,
+                                const double *B, int64_t ldb, double *X, int64_t ldx, void *dev_ws, size_t ws_bytes,
+                                h2x_cg_info *info, void *hip_stream) {
+    if (!A || !prm || !B || !X || !dev_ws) return fail(H2X_EINVAL, "h2x_block_cg_chunked: NULL argument");
+    if (m < 1 || m_chunk < 1 || ldb < m || ldx < m)
+        return fail(H2X_EINVAL, "h2x_block_cg_chunked: need m >= 1, m_chunk >= 1, ldb >= m, ldx >= m");
+    if (!(prm->rtol >= 0.0) || prm->max_iter < 0) return fail(H2X_EINVAL, "h2x_block_cg_chunked: bad rtol or max_iter");
+    if (prm->variant != H2X_CG_INDEPENDENT && prm->variant != H2X_CG_SHARED)
+        return fail(H2X_EINVAL, "h2x_block_cg_chunked: unknown variant");
+    if (A->dm.plan->nsys() > 1) return fail(H2X_EUNSUPPORTED, "h2x_block_cg_chunked: not for merged plans");
+    if (!aligned(dev_ws)) return fail(H2X_EINVAL, "h2x_block_cg_chunked: workspace not 256-byte aligned");
+    const int64_t mc = std::min(m_chunk, m);
+    if (ws_bytes < solve_ws_bytes(A->dm, H2X_SOLVER_CG, mc, 0))
+        return fail(H2X_ENOMEM, "h2x_block_cg_chunked: workspace too small for m_chunk columns");
+    return run_cg_chunked(A->dm, *prm, m, mc, B, ldb, X, ldx, (char *)dev_ws, ws_bytes, info, (hipStream_t)hip_stream);
+}
+
+h2x_status h2x_block_gmres_chunked(const h2x_mat *A, const h2x_gmres_params *prm, int64_t m, int64_t m_chunk,
+                                   const double *B, int64_t ldb, double *X, int64_t ldx, void *dev_ws,
+                                   size_t ws_bytes, h2x_gmres_info *info, void *hip_stream) {
+    if (!A || !prm || !B || !X || !dev_ws) return fail(H2X_EINVAL, "h2x_block_gmres_chunked: NULL argument");
+    if (m < 1 || m_chunk < 1 || ldb < m || ldx < m)
+        return fail(H2X_EINVAL, "h2x_block_gmres_chunked: need m >= 1, m_chunk >= 1, ldb >= m, ldx >= m");
+    if (!(prm->rtol >= 0.0) || prm->restart < 1 || prm->max_iter < 0 || prm->check_every < 1)
+        return fail(H2X_EINVAL, "h2x_block_gmres_chunked: bad rtol, restart, max_iter or check_every");
+    if (A->dm.plan->nsys() > 1) return fail(H2X_EUNSUPPORTED, "h2x_block_gmres_chunked: not for merged plans");
+    if (!aligned(dev_ws)) return fail(H2X_EINVAL, "h2x_block_gmres_chunked: workspace not 256-byte aligned");
+    const int64_t mc = std::min(m_chunk, m);
+    if (ws_bytes < gmres_ws_bytes(A->dm, mc, prm->restart))
+        return fail(H2X_ENOMEM, "h2x_block_gmres_chunked: workspace too small for m_chunk columns");
+    return run_gmres_chunked(A->dm, *prm, m, mc, B, ldb, X, ldx, (char *)dev_ws, ws_bytes, info,
+                             (hipStream_t)hip_stream);
+}
+
 size_t h2x_block_cg_mixed_workspace_bytes(const h2x_mat *A, const h2x_mat *A_lo, int64_t m) {
     if (!A || !A_lo || m < 1) return 0;
     return mixed_ws_bytes(A->dm, A_lo->dm, m);

@@ -133,6 +133,20 @@ h2x_status run_block_cg(const DevMat &dm, const h2x_cg_params &prm, int64_t m, c
                         double *X, int64_t ldx, char *ws, size_t ws_bytes, h2x_cg_info *info, hipStream_t st);
 
 size_t gmres_ws_bytes(const DevMat &dm, int64_t m, int ell);
+
+// right-hand-side chunking
+size_t solve_ws_bytes(const DevMat &dm, int32_t solver, int64_t m, int32_t restart);
+h2x_status choose_chunk(const DevMat &dm, int32_t solver, int32_t restart, int64_t m, size_t mem_bytes, int32_t ncand,
+                        const int64_t *cand, const double *ms, int64_t *m_chunk);
+size_t product_times_ws_bytes(const DevMat &dm, int32_t ncand, const int64_t *cand);
+h2x_status run_product_times(const DevMat &dm, int32_t ncand, const int64_t *cand, int32_t reps, char *ws,
+                             size_t ws_bytes, hipStream_t st, double *ms);
+h2x_status run_cg_chunked(const DevMat &dm, const h2x_cg_params &prm, int64_t m, int64_t mc, const double *B,
+                          int64_t ldb, double *X, int64_t ldx, char *ws, size_t ws_bytes, h2x_cg_info *info,
+                          hipStream_t st);
+h2x_status run_gmres_chunked(const DevMat &dm, const h2x_gmres_params &prm, int64_t m, int64_t mc, const double *B,
+                             int64_t ldb, double *X, int64_t ldx, char *ws, size_t ws_bytes, h2x_gmres_info *info,
+                             hipStream_t st);
 h2x_status run_block_gmres(const DevMat &dm, const h2x_gmres_params &prm, int64_t m, const double *B, int64_t ldb,
                            double *X, int64_t ldx, char *ws, size_t ws_bytes, h2x_gmres_info *info, hipStream_t st);
 

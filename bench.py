@@ -467,6 +467,48 @@ def gmres_report(args, torch, h2x, W):
     print(json.dumps(out), flush=True)
 
 
+def chunk_report(args, torch, h2x, W):
+    """Right-hand-side chunking (section 5, memory-footprint remarks): on the FP64 sphere
+    workload (n = 65536, k = 64) with m = 128 right-hand sides, the measured product-time
+    curve, the chunk the policy picks under three workspace budgets, and block CG to 1e-8
+    solved in chunks of every candidate size that fits, to see whether the pick is the
+    fastest."""
+    dev = torch.device("cuda:0")
+    w = W.FP64
+    A = h2x.H2Matrix(w.points(), device=dev, **w.params())
+    m, rtol = 128, 1e-8
+    cands = [8, 16, 32, 64, 128]
+    if args.autotune:
+        for c in cands:
+            A.autotune(c)
+    curve = dict(zip(cands, A.product_times(cands, reps=10)))
+    B = torch.from_numpy(W.rhs(w.n, m, 7400)).to(dev)
+    ws = {c: h2x.solve_workspace_bytes(A.plan, c, solver="cg") for c in cands}
+    out = {"workload": w.name, "m": m, "rtol": rtol, "curve_ms_per_product": {str(c): round(t, 4) for c, t in curve.items()},
+           "workspace_bytes": {str(c): ws[c] for c in cands}, "budgets": [], "solves": []}
+    measured = {}
+    for c in cands:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        X, info = h2x.block_cg_solve_chunked(A, B, c, rtol=rtol)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        measured[c] = dt
+        rec = {"m_chunk": c, "time_s": round(dt, 4), "max_iters": info.iters, "status": info.status,
+               "predicted_product_s": round(-(-m // c) * curve[c] * info.iters * 1e-3, 4)}
+        out["solves"].append(rec)
+        log(f"[chunk] {rec}")
+    for name, budget in (("unlimited", 1 << 62), ("fits 32 columns", ws[32]), ("fits 8 columns", ws[8])):
+        pick = h2x.choose_chunk(A.plan, m, budget, solver="cg", curve=curve)
+        fit = [c for c in cands if ws[c] <= budget]
+        best = min(fit, key=lambda c: measured[c])
+        rec = {"budget": name, "budget_bytes": min(budget, 2**63 - 1), "pick": pick, "fastest_measured": best,
+               "pick_over_fastest": round(measured.get(pick, float("nan")) / measured[best], 3)}
+        out["budgets"].append(rec)
+        log(f"[chunk] {rec}")
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -487,6 +529,8 @@ def main():
                     help="time the adjoint product, gradients and implicit-adjoint solve on the differentiation workload")
     ap.add_argument("--gmres-report", action="store_true",
                     help="block GMRES(30) to 1e-8 on the FP64 workload, symmetric and non-symmetric operators")
+    ap.add_argument("--chunk-report", action="store_true",
+                    help="right-hand-side chunk policy: product-time curve, picks under budgets, chunked CG solves")
     ap.add_argument("--copy-calibration-gib", type=float, default=0.0,
                     help="only run a plain device copy of this many GiB (to scale HBM traffic counters) and exit")
     args = ap.parse_args()
@@ -538,6 +582,9 @@ def main():
         return
     if args.gmres_report:
         gmres_report(args, torch, h2x, W)
+        return
+    if args.chunk_report:
+        chunk_report(args, torch, h2x, W)
         return
 
     w = W.WORKLOADS[args.workload]

@@ -26,8 +26,8 @@ import numpy as np
 
 from . import build as _build
 
-KERNEL_EXP, KERNEL_POLY, KERNEL_CONST = 0, 1, 2
-_KERNELS = {"exp": KERNEL_EXP, "poly": KERNEL_POLY, "const": KERNEL_CONST}
+KERNEL_EXP, KERNEL_POLY, KERNEL_CONST, KERNEL_HELMHOLTZ = 0, 1, 2, 3
+_KERNELS = {"exp": KERNEL_EXP, "poly": KERNEL_POLY, "const": KERNEL_CONST, "helmholtz": KERNEL_HELMHOLTZ}
 
 _lib = None
 
@@ -76,6 +76,11 @@ def _load():
     lib.orc_block_cg_shared.argtypes = [P, I64, P, P, D, I64, D, P, P]
     lib.orc_block_gmres.restype = I64
     lib.orc_block_gmres.argtypes = [P, I64, P, P, D, I64, I64, P, P, P, P]
+    lib.orc_block_gmres_c.restype = I64
+    lib.orc_block_gmres_c.argtypes = [P, I64, P, P, D, I64, I64, P, P, P, P]
+    lib.orc_dense_complex.argtypes = [P, P]
+    lib.orc_is_complex.restype = C.c_int
+    lib.orc_is_complex.argtypes = [P]
     lib.orc_num_threads.restype = C.c_int
     lib.orc_set_threads.argtypes = [C.c_int]
     _lib = lib
@@ -316,6 +321,36 @@ class OracleH2:
                                      _ptr(ci), _ptr(st), _ptr(est), _ptr(cyc))
         return X, dict(iters=int(it), cycles=int(cyc[0]), col_iters=ci, status=st, res_est=est)
 
+    def matmul_complex(self, X, alpha=1.0) -> np.ndarray:
+        """Y = alpha A X for the complex (Helmholtz) operator, X complex n x m."""
+        X = np.ascontiguousarray(X, dtype=np.complex128)
+        Xr = np.ascontiguousarray(X.view(np.float64).reshape(X.shape[0], -1))
+        Y = np.zeros_like(Xr)
+        _load().orc_matmul(self._h, Xr.shape[1], float(alpha), _ptr(Xr), 0.0, _ptr(Y))
+        return Y.view(np.complex128)
+
+    def dense_complex(self) -> np.ndarray:
+        """The complex H^2 matrix assembled densely (small n only)."""
+        A = np.zeros((self.n, 2 * self.n))
+        _load().orc_dense_complex(self._h, _ptr(A))
+        return A.view(np.complex128)
+
+    def block_gmres_complex(self, B, X0=None, rtol=1e-8, restart=30, max_iter=10000):
+        """Block GMRES(restart) over the complex numbers (conjugate inner product, complex
+        Givens rotations) for the complex operator; B complex n x m."""
+        B = np.ascontiguousarray(B, dtype=np.complex128)
+        m = B.shape[1]
+        Br = np.ascontiguousarray(B.view(np.float64).reshape(B.shape[0], -1))
+        X = np.zeros_like(Br) if X0 is None else np.ascontiguousarray(
+            np.ascontiguousarray(X0, dtype=np.complex128).view(np.float64).reshape(B.shape[0], -1)).copy()
+        ci = np.zeros(m, np.int64)
+        st = np.zeros(m, np.int32)
+        est = np.zeros(m, np.float64)
+        cyc = np.zeros(1, np.int64)
+        it = _load().orc_block_gmres_c(self._h, m, _ptr(Br), _ptr(X), float(rtol), int(restart), int(max_iter),
+                                       _ptr(ci), _ptr(st), _ptr(est), _ptr(cyc))
+        return X.view(np.complex128), dict(iters=int(it), cycles=int(cyc[0]), col_iters=ci, status=st, res_est=est)
+
     def cg1(self, b, x0=None, rtol=1e-8, max_iter=10000):
         b = np.ascontiguousarray(b, dtype=np.float64).reshape(-1)
         x = np.zeros_like(b) if x0 is None else np.ascontiguousarray(x0, dtype=np.float64).reshape(-1).copy()
@@ -332,12 +367,17 @@ def round_bf16(values) -> np.ndarray:
 
 
 def kernel_matrix(points, *, kernel="exp", ell=0.5, shift=1.0) -> np.ndarray:
-    """The exact dense matrix g(x_i, x_j) + shift * delta_ij (no H^2 approximation)."""
+    """The exact dense matrix g(x_i, x_j) + shift * delta_ij (no H^2 approximation); complex
+    for the Helmholtz kernel."""
     P = np.asarray(points, dtype=np.float64)
     kern = _KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
     if kern == KERNEL_EXP:
         D = np.sqrt(((P[:, None, :] - P[None, :, :]) ** 2).sum(-1))
         A = np.exp(-D / ell)
+    elif kern == KERNEL_HELMHOLTZ:  # (4 pi / n) exp(i kappa r) / (4 pi r), kappa = ell; no self-interaction
+        D = np.sqrt(((P[:, None, :] - P[None, :, :]) ** 2).sum(-1))
+        with np.errstate(divide="ignore", invalid="ignore"):
+            A = np.where(D > 0, np.exp(1j * ell * D) / (P.shape[0] * D), 0.0)
     elif kern == KERNEL_POLY:
         A = (1.0 + P @ P.T) ** 2
     else:

@@ -18,6 +18,7 @@
  * nu = jx + p*jy + p^2*jz; W == V (real symmetric kernel); the shift sits in the
  * diagonal near-field blocks; lists C_t are processed for every cluster t.
  */
+#include <complex.h>
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -26,7 +27,7 @@
 #include <omp.h>
 #endif
 
-enum { ORC_KERNEL_EXP = 0, ORC_KERNEL_POLY = 1, ORC_KERNEL_CONST = 2 };
+enum { ORC_KERNEL_EXP = 0, ORC_KERNEL_POLY = 1, ORC_KERNEL_CONST = 2, ORC_KERNEL_HELMHOLTZ = 3 };
 
 typedef struct {
     /* problem (section 2: index set I = J, points as the supports Omega_i) */
@@ -60,6 +61,9 @@ typedef struct {
     double *E;           /* C x k x k, transfer matrices (root's entry unused) */
     double *S;           /* n_adm x k x k coupling matrices */
     double *N;           /* near_entries, near-field blocks row-major |t| x |s| */
+    /* complex kernel (Helmholtz): imaginary parts of S and N; V and E stay real */
+    int cplx;
+    double *Si, *Ni;
 } orc_h2;
 
 /* ------------------------------------------------------------------------ */
@@ -77,6 +81,21 @@ static double orc_g(const orc_h2 *h, const double *a, const double *b) {
         return d * d;
     }
     return 1.0;
+}
+
+/* Helmholtz single-layer kernel with equal quadrature weights (the unit sphere's area
+ * 4 pi over n points): g(x, y) = (4 pi / n) exp(i kappa r) / (4 pi r) = exp(i kappa r) / (n r),
+ * kappa held in ell; coinciding points (the self-interaction) contribute 0 (the shift is
+ * added on the diagonal) */
+static void orc_gc(const orc_h2 *h, const double *a, const double *b, double *re, double *im) {
+    const double r = orc_dist3(a, b);
+    if (r == 0.0) {
+        *re = *im = 0.0;
+        return;
+    }
+    const double f = 1.0 / ((double)h->n * r);
+    *re = cos(h->ell * r) * f;
+    *im = sin(h->ell * r) * f;
 }
 
 /* d g / d ell for the exponential kernel: (r / ell^2) exp(-r / ell); 0 otherwise */
@@ -284,11 +303,28 @@ static void orc_fill_matrices(orc_h2 *h) {
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t b = 0; b < h->nb; ++b) {
         int64_t t = h->bt[b], s = h->bs[b];
-        if (h->badm[b]) {
+        if (h->badm[b] && h->cplx) {
+            double *Sb = &h->S[h->boff[b]], *Sib = &h->Si[h->boff[b]];
+            for (int nu = 0; nu < k; ++nu)
+                for (int mu = 0; mu < k; ++mu)
+                    orc_gc(h, &h->nodes[((size_t)t * k + nu) * 3], &h->nodes[((size_t)s * k + mu) * 3],
+                           &Sb[nu * k + mu], &Sib[nu * k + mu]);
+        } else if (h->badm[b]) {
             double *Sb = &h->S[h->boff[b]];
             for (int nu = 0; nu < k; ++nu)
                 for (int mu = 0; mu < k; ++mu)
                     Sb[nu * k + mu] = orc_g(h, &h->nodes[((size_t)t * k + nu) * 3], &h->nodes[((size_t)s * k + mu) * 3]);
+        } else if (h->cplx) {
+            double *Nb = &h->N[h->boff[b]], *Nib = &h->Ni[h->boff[b]];
+            for (int64_t i = 0; i < h->size[t]; ++i)
+                for (int64_t j = 0; j < h->size[s]; ++j) {
+                    int64_t gi = h->perm[h->first[t] + i], gj = h->perm[h->first[s] + j];
+                    double re, im;
+                    orc_gc(h, &h->pts[3 * gi], &h->pts[3 * gj], &re, &im);
+                    if (gi == gj) re += h->shift;
+                    Nb[i * h->size[s] + j] = re;
+                    Nib[i * h->size[s] + j] = im;
+                }
         } else {
             double *Nb = &h->N[h->boff[b]];
             for (int64_t i = 0; i < h->size[t]; ++i)
@@ -366,6 +402,9 @@ orc_h2 *orc_build(const double *pts, int64_t n, int kernel, double ell, double s
     h->E = calloc((size_t)h->C * h->k * h->k, sizeof(double));
     h->S = malloc(sizeof(double) * (so ? so : 1));
     h->N = malloc(sizeof(double) * (no ? no : 1));
+    h->cplx = h->kernel == ORC_KERNEL_HELMHOLTZ;
+    h->Si = h->cplx ? malloc(sizeof(double) * (so ? so : 1)) : NULL;
+    h->Ni = h->cplx ? malloc(sizeof(double) * (no ? no : 1)) : NULL;
     orc_fill_matrices(h);
     return h;
 }
@@ -376,6 +415,7 @@ void orc_free(orc_h2 *h) {
     free(h->parent); free(h->depth); free(h->blo); free(h->bhi); free(h->ilo); free(h->ihi);
     free(h->nodes); free(h->perm); free(h->bt); free(h->bs); free(h->badm); free(h->boff);
     free(h->list_ptr); free(h->list_blk); free(h->V); free(h->E); free(h->S); free(h->N);
+    free(h->Si); free(h->Ni);
     free(h);
 }
 
@@ -519,6 +559,43 @@ static void orc_backward(const orc_mm *w, int64_t t, double *Y) {
     }
 }
 
+/* Complex kernel: column pairs (2j, 2j + 1) of X, x-hat, y-hat and Y hold the real and
+ * imaginary part of complex column j; S_b = S + i Si and N_b = N + i Ni are complex, the
+ * bases real.  One leaf block of list_addeval in complex arithmetic. */
+static void orc_block_addeval_c(const orc_mm *w, int64_t t, int64_t b, double alpha, double *Y) {
+    const orc_h2 *h = w->h;
+    const int k = h->k;
+    const int64_t m = w->m, mc = m / 2, s = h->bs[b];
+    if (h->badm[b]) {
+        const double *Sr = &h->S[h->boff[b]], *Si = &h->Si[h->boff[b]];
+        const double *xs = &w->xh[(size_t)s * k * m];
+        double *yt = &w->yh[(size_t)t * k * m];
+        for (int nu = 0; nu < k; ++nu)
+            for (int64_t j = 0; j < mc; ++j) {
+                double complex acc = 0.0;
+                for (int mu = 0; mu < k; ++mu)
+                    acc += (Sr[nu * k + mu] + I * Si[nu * k + mu]) * (xs[mu * m + 2 * j] + I * xs[mu * m + 2 * j + 1]);
+                yt[nu * m + 2 * j] += alpha * creal(acc);
+                yt[nu * m + 2 * j + 1] += alpha * cimag(acc);
+            }
+    } else {
+        const double *Nr = &h->N[h->boff[b]], *Ni = &h->Ni[h->boff[b]];
+        const int64_t ns = h->size[s];
+        for (int64_t i = 0; i < h->size[t]; ++i) {
+            double *yrow = &Y[h->perm[h->first[t] + i] * m];
+            for (int64_t j = 0; j < mc; ++j) {
+                double complex acc = 0.0;
+                for (int64_t c = 0; c < ns; ++c) {
+                    const double *x = &w->X[h->perm[h->first[s] + c] * m + 2 * j];
+                    acc += (Nr[i * ns + c] + I * Ni[i * ns + c]) * (x[0] + I * x[1]);
+                }
+                yrow[2 * j] += alpha * creal(acc);
+                yrow[2 * j + 1] += alpha * cimag(acc);
+            }
+        }
+    }
+}
+
 /* list_addeval for one row cluster t: admissible -> y_t += alpha S_b x_s,
  * inadmissible -> y|_t += alpha G|_{t x s} x|_s.  Owns y_t and the rows of t. */
 static void orc_list_addeval(const orc_mm *w, int64_t t, double alpha, double *Y) {
@@ -527,6 +604,10 @@ static void orc_list_addeval(const orc_mm *w, int64_t t, double alpha, double *Y
     const int64_t m = w->m;
     for (int64_t q = h->list_ptr[t]; q < h->list_ptr[t + 1]; ++q) {
         int64_t b = h->list_blk[q], s = h->bs[b];
+        if (h->cplx) {
+            orc_block_addeval_c(w, t, b, alpha, Y);
+            continue;
+        }
         if (h->badm[b]) {
             const double *Sb = &h->S[h->boff[b]];
             const double *xs = &w->xh[(size_t)s * k * m];
@@ -918,6 +999,50 @@ void orc_dense(const orc_h2 *h, double *A) {
         }
     }
 }
+
+/* Dense complex H^2 matrix of the Helmholtz kernel, assembled as orc_dense does (full
+ * bases V_t S_b V_s^T per admissible block, N_b per near block) with S_b = S + i Si and
+ * N_b = N + i Ni; A is n x n complex, entry (i, j) at A[2 (i n + j)] (real), + 1 (imaginary). */
+void orc_dense_complex(const orc_h2 *h, double *A) {
+    const int k = h->k;
+    const int64_t n = h->n;
+    memset(A, 0, sizeof(double) * 2 * n * n);
+    for (int64_t b = 0; b < h->nb; ++b) {
+        int64_t t = h->bt[b], s = h->bs[b], nt = h->size[t], ns = h->size[s];
+        if (h->badm[b]) {
+            double *Vt = malloc(sizeof(double) * nt * k), *Vs = malloc(sizeof(double) * ns * k);
+            double complex *VS = malloc(sizeof(double complex) * nt * k);
+            orc_basis_full(h, t, Vt);
+            orc_basis_full(h, s, Vs);
+            const double *Sr = &h->S[h->boff[b]], *Si = &h->Si[h->boff[b]];
+            for (int64_t i = 0; i < nt; ++i)
+                for (int mu = 0; mu < k; ++mu) {
+                    double complex acc = 0.0;
+                    for (int nu = 0; nu < k; ++nu) acc += Vt[i * k + nu] * (Sr[nu * k + mu] + I * Si[nu * k + mu]);
+                    VS[i * k + mu] = acc;
+                }
+            for (int64_t i = 0; i < nt; ++i)
+                for (int64_t j = 0; j < ns; ++j) {
+                    double complex acc = 0.0;
+                    for (int mu = 0; mu < k; ++mu) acc += VS[i * k + mu] * Vs[j * k + mu];
+                    const int64_t e = h->perm[h->first[t] + i] * n + h->perm[h->first[s] + j];
+                    A[2 * e] = creal(acc);
+                    A[2 * e + 1] = cimag(acc);
+                }
+            free(Vt); free(Vs); free(VS);
+        } else {
+            const double *Nr = &h->N[h->boff[b]], *Ni = &h->Ni[h->boff[b]];
+            for (int64_t i = 0; i < nt; ++i)
+                for (int64_t j = 0; j < ns; ++j) {
+                    const int64_t e = h->perm[h->first[t] + i] * n + h->perm[h->first[s] + j];
+                    A[2 * e] = Nr[i * ns + j];
+                    A[2 * e + 1] = Ni[i * ns + j];
+                }
+        }
+    }
+}
+
+int orc_is_complex(const orc_h2 *h) { return h->cplx; }
 
 /* Dense derivative d A_H2 / d ell (same structure: V, E fixed; S and N depend on ell). */
 void orc_dense_dell(const orc_h2 *h, double *A) {
@@ -1555,6 +1680,176 @@ int64_t orc_block_gmres(const orc_h2 *h, int64_t m, const double *B, double *X, 
 #undef QQ
     *cycles = cyc;
     free(Q); free(R); free(Aq); free(H); free(cs); free(sn); free(rh); free(y); free(bn); free(kc);
+    free(open); free(done);
+    return it;
+}
+
+/*
+ * Block GMRES(ell) over the complex numbers (section 5.2 with K = C): the same
+ * cycle as orc_block_gmres with the complex inner product <u, v> = u^H v, complex
+ * Hessenberg entries and complex Givens rotations G = [c s; -conj(s) c] with c real:
+ * for (u, w), w = h[k+1][k] >= 0, rho = sqrt(|u|^2 + w^2), c = |u| / rho,
+ * s = (u / |u|) w / rho (c = 0, s = 1 when u = 0), so that G (u, w) = (rho u / |u|, 0).
+ * B and X hold m complex columns as n x 2m real arrays (column pairs real, imaginary);
+ * the operator must use the complex kernel.  Outputs as orc_block_gmres, per complex
+ * column.
+ */
+int64_t orc_block_gmres_c(const orc_h2 *h, int64_t m, const double *B, double *X, double rtol, int64_t ell,
+                          int64_t max_iter, int64_t *col_iters, int32_t *status, double *res_est, int64_t *cycles) {
+    const int64_t n = h->n, mr = 2 * m;
+    double complex *Q = malloc(sizeof(double complex) * (ell + 1) * n * m);
+    double complex *a = malloc(sizeof(double complex) * n * m);
+    double *R = malloc(sizeof(double) * n * mr), *Xr = malloc(sizeof(double) * n * mr);
+    double complex *H = malloc(sizeof(double complex) * m * (ell + 1) * ell);
+    double *cs = malloc(sizeof(double) * m * ell);
+    double complex *sn = malloc(sizeof(double complex) * m * ell);
+    double complex *rh = malloc(sizeof(double complex) * m * (ell + 1)), *y = malloc(sizeof(double complex) * ell);
+    double *bn = malloc(sizeof(double) * m);
+    int64_t *kc = malloc(sizeof(int64_t) * m);
+    int *open = malloc(sizeof(int) * m), *done = calloc(m, sizeof(int));
+#define HH(i, r, c) H[((i) * (ell + 1) + (r)) * ell + (c)]
+#define QQ(j) (Q + (int64_t)(j) * n * m)
+#define CX(A, v, i) ((A)[(v) * mr + 2 * (i)] + I * (A)[(v) * mr + 2 * (i) + 1])
+    for (int64_t i = 0; i < m; ++i) {
+        double s2 = 0.0;
+        for (int64_t v = 0; v < n; ++v) {
+            const double complex z = CX(B, v, i);
+            s2 += creal(z) * creal(z) + cimag(z) * cimag(z);
+        }
+        bn[i] = sqrt(s2);
+        col_iters[i] = 0;
+        status[i] = 2;
+        res_est[i] = 0.0;
+    }
+    int64_t it = 0, cyc = 0;
+    for (;;) {
+        orc_matmul(h, mr, 1.0, X, 0.0, R);
+        for (int64_t e = 0; e < n * mr; ++e) R[e] = B[e] - R[e];
+        int any = 0;
+        for (int64_t i = 0; i < m; ++i) {
+            open[i] = 0;
+            kc[i] = 0;
+            if (done[i]) continue;
+            double s2 = 0.0;
+            for (int64_t v = 0; v < n; ++v) {
+                const double complex z = CX(R, v, i);
+                s2 += creal(z) * creal(z) + cimag(z) * cimag(z);
+            }
+            const double beta = sqrt(s2);
+            if (beta <= rtol * bn[i]) {
+                done[i] = 1;
+                status[i] = 0;
+                continue;
+            }
+            open[i] = 1;
+            any = 1;
+            for (int64_t r = 0; r <= ell; ++r) rh[i * (ell + 1) + r] = 0.0;
+            rh[i * (ell + 1)] = beta;
+            for (int64_t v = 0; v < n; ++v) QQ(0)[v * m + i] = CX(R, v, i) / beta;
+        }
+        if (!any || it >= max_iter) break;
+        for (int64_t i = 0; i < m; ++i)
+            if (!open[i])
+                for (int64_t v = 0; v < n; ++v) QQ(0)[v * m + i] = 0.0;
+        cyc++;
+        for (int64_t k = 0; k < ell && it < max_iter; ++k) {
+            int still = 0;
+            for (int64_t i = 0; i < m; ++i) still |= open[i];
+            if (!still) break;
+            /* a = A q_k (the real product on the interleaved column pairs) */
+            for (int64_t v = 0; v < n; ++v)
+                for (int64_t i = 0; i < m; ++i) {
+                    Xr[v * mr + 2 * i] = creal(QQ(k)[v * m + i]);
+                    Xr[v * mr + 2 * i + 1] = cimag(QQ(k)[v * m + i]);
+                }
+            orc_matmul(h, mr, 1.0, Xr, 0.0, R);
+            for (int64_t v = 0; v < n; ++v)
+                for (int64_t i = 0; i < m; ++i) a[v * m + i] = CX(R, v, i);
+            it++;
+            for (int64_t i = 0; i < m; ++i) {
+                double complex *q1 = QQ(k + 1);
+                if (!open[i]) {
+                    for (int64_t v = 0; v < n; ++v) q1[v * m + i] = 0.0;
+                    continue;
+                }
+                for (int64_t j = 0; j <= k; ++j) {
+                    double complex d = 0.0;
+                    for (int64_t v = 0; v < n; ++v) d += conj(QQ(j)[v * m + i]) * a[v * m + i];
+                    HH(i, j, k) = d;
+                }
+                double s2 = 0.0;
+                for (int64_t v = 0; v < n; ++v) {
+                    double complex z = a[v * m + i];
+                    for (int64_t j = 0; j <= k; ++j) z -= QQ(j)[v * m + i] * HH(i, j, k);
+                    a[v * m + i] = z;
+                    s2 += creal(z) * creal(z) + cimag(z) * cimag(z);
+                }
+                const double hn = sqrt(s2);
+                HH(i, k + 1, k) = hn;
+                for (int64_t j = 0; j < k; ++j) {
+                    const double c = cs[i * ell + j];
+                    const double complex sj = sn[i * ell + j];
+                    const double complex u = HH(i, j, k), w = HH(i, j + 1, k);
+                    HH(i, j, k) = c * u + sj * w;
+                    HH(i, j + 1, k) = -conj(sj) * u + c * w;
+                }
+                const double complex u = HH(i, k, k);
+                const double au = cabs(u), rho = sqrt(au * au + hn * hn);
+                if (rho == 0.0) {
+                    open[i] = 0;
+                    done[i] = 1;
+                    status[i] = 1;
+                    for (int64_t v = 0; v < n; ++v) q1[v * m + i] = 0.0;
+                    continue;
+                }
+                double c;
+                double complex sk;
+                if (au == 0.0) {
+                    c = 0.0;
+                    sk = 1.0;
+                } else {
+                    c = au / rho;
+                    sk = (u / au) * (hn / rho);
+                }
+                cs[i * ell + k] = c;
+                sn[i * ell + k] = sk;
+                HH(i, k, k) = c * u + sk * hn;
+                HH(i, k + 1, k) = 0.0;
+                const double complex r0 = rh[i * (ell + 1) + k];
+                rh[i * (ell + 1) + k] = c * r0;
+                rh[i * (ell + 1) + k + 1] = -conj(sk) * r0;
+                kc[i] = k + 1;
+                col_iters[i]++;
+                if (cabs(rh[i * (ell + 1) + k + 1]) <= rtol * bn[i] || hn == 0.0) {
+                    open[i] = 0;
+                    for (int64_t v = 0; v < n; ++v) q1[v * m + i] = 0.0;
+                } else {
+                    for (int64_t v = 0; v < n; ++v) q1[v * m + i] = a[v * m + i] / hn;
+                }
+            }
+        }
+        for (int64_t i = 0; i < m; ++i) {
+            const int64_t kk = kc[i];
+            if (kk == 0) continue;
+            for (int64_t r = kk - 1; r >= 0; --r) {
+                double complex acc = rh[i * (ell + 1) + r];
+                for (int64_t c = r + 1; c < kk; ++c) acc -= HH(i, r, c) * y[c];
+                y[r] = acc / HH(i, r, r);
+            }
+            for (int64_t v = 0; v < n; ++v) {
+                double complex z = CX(X, v, i);
+                for (int64_t j = 0; j < kk; ++j) z += QQ(j)[v * m + i] * y[j];
+                X[v * mr + 2 * i] = creal(z);
+                X[v * mr + 2 * i + 1] = cimag(z);
+            }
+            res_est[i] = bn[i] > 0.0 ? cabs(rh[i * (ell + 1) + kk]) / bn[i] : 0.0;
+        }
+    }
+#undef HH
+#undef QQ
+#undef CX
+    *cycles = cyc;
+    free(Q); free(a); free(R); free(Xr); free(H); free(cs); free(sn); free(rh); free(y); free(bn); free(kc);
     free(open); free(done);
     return it;
 }

@@ -61,7 +61,14 @@ typedef enum {
     H2X_KERNEL_EXP = 0,   /* g = exp(-|x - y| / ell) + shift * delta_ij                */
     H2X_KERNEL_POLY = 1,  /* g = (1 + x.y)^2 + shift * delta_ij; reproduced exactly by
                              interpolation order >= 3 (a test kernel)                    */
-    H2X_KERNEL_CONST = 2  /* g = 1 + shift * delta_ij, i.e. A = shift I + 1 1^T (test)  */
+    H2X_KERNEL_CONST = 2, /* g = 1 + shift * delta_ij, i.e. A = shift I + 1 1^T (test)  */
+    H2X_KERNEL_HELMHOLTZ = 3 /* complex: g = (4 pi / n) exp(i kappa r) / (4 pi r) for
+                             x != y (the single-layer kernel of section 5.2's examples
+                             with equal quadrature weights, kappa = ell), 0 for coinciding
+                             points, + shift * delta_ij.  The operator is complex (FP64
+                             storage, k = 64 or k <= 32); products and GMRES take m complex
+                             columns as 2m real columns (pairs real, imaginary, i.e. the
+                             memory of a row-major complex128 array)                     */
 } h2x_kernel;
 
 typedef struct {
@@ -275,7 +282,10 @@ h2x_status h2x_block_cg_mixed(const h2x_mat *A, const h2x_mat *A_lo, const h2x_c
  * a column met a singular projected matrix).  info arrays are host, m entries,
  * nullable: col_iters (steps in which the column was open), col_status (0
  * converged, 1 breakdown, 2 not converged), col_res (|rhat| / ||b_i|| after the
- * column's last cycle, the GMRES estimate of its relative residual). */
+ * column's last cycle, the GMRES estimate of its relative residual).
+ * Complex operator (H2X_KERNEL_HELMHOLTZ): the same method over C (inner product
+ * u^H v, complex Givens rotations); m counts real columns, two per complex column
+ * (real, imaginary part; m even), and the info arrays have m / 2 entries. */
 typedef struct {
     double rtol;
     int32_t restart;

@@ -20,7 +20,7 @@ __all__ = ["Plan", "H2Matrix", "Batch", "h2_matmul", "h2_matmul_adjoint", "h2_gr
 
 F64, F32, BF16 = 0, 1, 2
 _PREC = {"f64": F64, "f32": F32, "bf16": BF16, F64: F64, F32: F32, BF16: BF16}
-_KERNEL = {"exp": 0, "poly": 1, "const": 2}
+_KERNEL = {"exp": 0, "poly": 1, "const": 2, "helmholtz": 3}
 TREE_ORDER = 1
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -252,6 +252,8 @@ class H2Matrix:
         self._h = h
         self.n, self.k = self.plan.n, self.plan.k
         self.ell = float(self.plan.params["ell"])
+        kern = self.plan.params.get("kernel", "exp")
+        self.complex = kern in ("helmholtz", 3)  # complex operator: column pairs (real, imaginary)
         self._mm_ws = {}
 
     def __del__(self):
@@ -331,11 +333,17 @@ STAGES = ("forward_leaf", "forward_transfer", "coupling", "backward_transfer", "
 
 
 def h2_matmul(A: H2Matrix, X, *, alpha=1.0, beta=0.0, out=None, tree_order=False, stage_ms=None):
-    """Y <- beta Y + alpha A X on the GPU (h2x_matmul).  X: (n, m) float64 CUDA tensor.
+    """Y <- beta Y + alpha A X on the GPU (h2x_matmul).  X: (n, m) float64 CUDA tensor, or
+    complex128 for a complex (Helmholtz) operator (its memory is 2m real columns).
 
     With ``stage_ms`` (a float64 numpy array of len(STAGES)) the product runs through
     h2x_matmul_timed and the per-stage durations in ms are written into it (blocking)."""
     import torch
+    if X.is_complex():
+        Xr = _as_real(torch, X)
+        Yr = None if out is None else _as_real(torch, out)
+        Yr = h2_matmul(A, Xr, alpha=alpha, beta=beta, out=Yr, tree_order=tree_order, stage_ms=stage_ms)
+        return torch.view_as_complex(Yr.reshape(Yr.shape[0], -1, 2)) if out is None else out
     squeeze = X.dim() == 1
     X2 = X.reshape(-1, 1) if squeeze else X
     if X2.dtype != torch.float64 or X2.device.type != "cuda" or X2.stride(1) != 1:
@@ -360,6 +368,14 @@ def h2_matmul(A: H2Matrix, X, *, alpha=1.0, beta=0.0, out=None, tree_order=False
         assert stage_ms.dtype == np.float64 and stage_ms.size >= len(STAGES)
         _check(load_library().h2x_matmul_timed(*args, _ptr(stage_ms)), "h2x_matmul_timed")
     return out
+
+
+def _as_real(torch, Z):
+    """A row-major complex128 (n, m) tensor as its (n, 2m) float64 view (pairs real, imaginary)."""
+    Z2 = Z.reshape(-1, 1) if Z.dim() == 1 else Z
+    if Z2.dtype != torch.complex128 or Z2.device.type != "cuda" or not Z2.is_contiguous():
+        raise ValueError("complex input must be a contiguous complex128 CUDA tensor")
+    return torch.view_as_real(Z2).reshape(Z2.shape[0], -1)
 
 
 def _rowmajor(T, n, what):
@@ -472,6 +488,12 @@ def block_gmres_solve(A: H2Matrix, B, X0=None, *, rtol=1e-8, restart=30, max_ite
     processes sharing one product per Arnoldi step, restarted from the improved
     iterate until every column's true residual is within rtol.  Returns (X, GmresInfo)."""
     import torch
+    if B.is_complex():  # complex operator: m complex columns as 2m real ones
+        Br = _as_real(torch, B)
+        X0r = None if X0 is None else _as_real(torch, X0.contiguous())
+        Xr, info = block_gmres_solve(A, Br, X0r, rtol=rtol, restart=restart, max_iter=max_iter,
+                                     check_every=check_every)
+        return torch.view_as_complex(Xr.reshape(Xr.shape[0], -1, 2)), info
     if B.dtype != torch.float64 or B.device.type != "cuda" or B.dim() != 2 or B.stride(1) != 1:
         raise ValueError("B must be a row-major (n, m) float64 CUDA tensor")
     n, m = B.shape
@@ -481,9 +503,10 @@ def block_gmres_solve(A: H2Matrix, B, X0=None, *, rtol=1e-8, restart=30, max_ite
     if nb == 0:
         raise ValueError("block_gmres_solve: need m >= 1 and restart >= 1")
     ws = torch.empty(nb, dtype=torch.uint8, device=B.device)
-    res = np.zeros(m)
-    its = np.zeros(m, np.int32)
-    sts = np.zeros(m, np.int32)
+    mi = m // 2 if A.complex else m  # info entries per complex column
+    res = np.zeros(mi)
+    its = np.zeros(mi, np.int32)
+    sts = np.zeros(mi, np.int32)
     i32 = lambda a: a.ctypes.data_as(C.POINTER(C.c_int32))
     info = _GmresInfo(0, 0, 0, 0, res.ctypes.data_as(C.POINTER(C.c_double)), i32(its), i32(sts))
     prm = _GmresParams(float(rtol), int(restart), int(max_iter), int(check_every), 0)

@@ -30,6 +30,20 @@ h2x_status hip_fail(const char *where, hipError_t e) {
 
 bool aligned(const void *p) { return ((uintptr_t)p % kAlign) == 0; }
 
+// complex operators: products take column pairs; CG (which needs a Hermitian positive
+// definite operator), the adjoint, gradients, coupling access and batching are real only
+h2x_status refuse_complex(const h2x_mat *A, const char *what) {
+    if (A && A->dm.cplx) return fail(H2X_EUNSUPPORTED, std::string(what) + ": not for a complex operator");
+    return H2X_OK;
+}
+
+h2x_status need_pairs(const h2x_mat *A, int64_t m, const char *what) {
+    if (A && A->dm.cplx && (m & 1))
+        return fail(H2X_EINVAL, std::string(what) + ": a complex operator takes an even number of real columns "
+                                                    "(real and imaginary part of each complex column)");
+    return H2X_OK;
+}
+
 template <typename T>
 hipError_t upload(T *dst, const std::vector<T> &src, hipStream_t st) {
     if (src.empty()) return hipSuccess;
@@ -52,10 +66,12 @@ h2x_status h2x_plan_create(const double *pts, int64_t n, const h2x_params *prm, 
         return fail(H2X_EINVAL, "h2x_plan_create: cheb_order must be in [1, 8]");
     if (prm->leaf_size < 1) return fail(H2X_EINVAL, "h2x_plan_create: leaf_size must be >= 1");
     if (!(prm->eta > 0.0)) return fail(H2X_EINVAL, "h2x_plan_create: eta must be > 0");
-    if (prm->kernel < H2X_KERNEL_EXP || prm->kernel > H2X_KERNEL_CONST)
+    if (prm->kernel < H2X_KERNEL_EXP || prm->kernel > H2X_KERNEL_HELMHOLTZ)
         return fail(H2X_EINVAL, "h2x_plan_create: unknown kernel");
     if (prm->kernel == H2X_KERNEL_EXP && !(prm->ell > 0.0))
         return fail(H2X_EINVAL, "h2x_plan_create: ell must be > 0");
+    if (prm->kernel == H2X_KERNEL_HELMHOLTZ && !(prm->ell >= 0.0 && std::isfinite(prm->ell)))
+        return fail(H2X_EINVAL, "h2x_plan_create: the wavenumber (ell) must be finite and >= 0");
     for (int64_t i = 0; i < 3 * n; ++i)
         if (!std::isfinite(pts[i])) return fail(H2X_EINVAL, "h2x_plan_create: non-finite point coordinate");
     std::string err;
@@ -78,6 +94,8 @@ h2x_status h2x_plan_merge(const h2x_plan *const *plans, int32_t count, h2x_plan 
     std::vector<const Plan *> parts;
     for (int32_t i = 0; i < count; ++i) {
         if (!plans[i]) return fail(H2X_EINVAL, "h2x_plan_merge: NULL plan");
+        if (plans[i]->p->prm.kernel == H2X_KERNEL_HELMHOLTZ)
+            return fail(H2X_EUNSUPPORTED, "h2x_plan_merge: complex (Helmholtz) plans are not batched");
         parts.push_back(plans[i]->p);
     }
     std::string err;
@@ -166,6 +184,8 @@ h2x_status h2x_mat_create(const h2x_plan *plan, h2x_prec storage, void *dev_ws, 
     if (storage < H2X_F64 || storage > H2X_BF16) return fail(H2X_EINVAL, "h2x_mat_create: bad storage precision");
     if (!aligned(dev_ws)) return fail(H2X_EINVAL, "h2x_mat_create: workspace not 256-byte aligned");
     const Plan &P = *plan->p;
+    if (P.prm.kernel == H2X_KERNEL_HELMHOLTZ && (storage != H2X_F64 || !(P.k == 64 || P.k <= 32)))
+        return fail(H2X_EUNSUPPORTED, "h2x_mat_create: the complex kernel needs FP64 storage and k = 64 or k <= 32");
     const size_t need = mat_layout(P, storage, nullptr, nullptr);
     if (ws_bytes < need) return fail(H2X_ENOMEM, "h2x_mat_create: workspace too small");
     auto *M = new h2x_mat{};
@@ -280,6 +300,7 @@ extern "C" {
 
 h2x_status h2x_matmul(const h2x_mat *A, int64_t m, double alpha, const double *X, int64_t ldx, double beta, double *Y,
                       int64_t ldy, int32_t flags, void *dev_ws, size_t ws_bytes, void *hip_stream) {
+    if (h2x_status r = need_pairs(A, m, "h2x_matmul")) return r;
     h2x_status s = validate_matmul("h2x_matmul", A, m, X, ldx, Y, ldy, flags, dev_ws, ws_bytes);
     if (s != H2X_OK) return s;
     hipError_t e = run_matmul(A->dm, m, alpha, X, ldx, beta, Y, ldy, (flags & H2X_TREE_ORDER) != 0, (char *)dev_ws,
@@ -291,6 +312,7 @@ h2x_status h2x_matmul(const h2x_mat *A, int64_t m, double alpha, const double *X
 h2x_status h2x_matmul_timed(const h2x_mat *A, int64_t m, double alpha, const double *X, int64_t ldx, double beta,
                             double *Y, int64_t ldy, int32_t flags, void *dev_ws, size_t ws_bytes, void *hip_stream,
                             double *stage_ms) {
+    if (h2x_status r = need_pairs(A, m, "h2x_matmul_timed")) return r;
     if (!stage_ms) return fail(H2X_EINVAL, "h2x_matmul_timed: stage_ms is NULL");
     h2x_status s = validate_matmul("h2x_matmul_timed", A, m, X, ldx, Y, ldy, flags, dev_ws, ws_bytes);
     if (s != H2X_OK) return s;
@@ -320,6 +342,7 @@ size_t h2x_block_cg_workspace_bytes(const h2x_mat *A, int64_t m) {
 
 h2x_status h2x_block_cg(const h2x_mat *A, const h2x_cg_params *prm, int64_t m, const double *B, int64_t ldb,
                         double *X, int64_t ldx, void *dev_ws, size_t ws_bytes, h2x_cg_info *info, void *hip_stream) {
+    if (h2x_status r = refuse_complex(A, "h2x_block_cg")) return r;
     if (!A || !prm || !B || !X || !dev_ws) return fail(H2X_EINVAL, "h2x_block_cg: NULL argument");
     if (m < 1 || ldb < m || ldx < m) return fail(H2X_EINVAL, "h2x_block_cg: need m >= 1, ldb >= m, ldx >= m");
     if (!(prm->rtol >= 0.0) || prm->max_iter < 0) return fail(H2X_EINVAL, "h2x_block_cg: bad rtol or max_iter");
@@ -341,6 +364,7 @@ size_t h2x_block_gmres_workspace_bytes(const h2x_mat *A, int64_t m, int32_t rest
 h2x_status h2x_block_gmres(const h2x_mat *A, const h2x_gmres_params *prm, int64_t m, const double *B, int64_t ldb,
                            double *X, int64_t ldx, void *dev_ws, size_t ws_bytes, h2x_gmres_info *info,
                            void *hip_stream) {
+    if (h2x_status r = need_pairs(A, m, "h2x_block_gmres")) return r;
     if (!A || !prm || !B || !X || !dev_ws) return fail(H2X_EINVAL, "h2x_block_gmres: NULL argument");
     if (m < 1 || ldb < m || ldx < m) return fail(H2X_EINVAL, "h2x_block_gmres: need m >= 1, ldb >= m, ldx >= m");
     if (!(prm->rtol >= 0.0) || prm->restart < 1 || prm->max_iter < 0 || prm->check_every < 1)
@@ -379,6 +403,8 @@ size_t h2x_product_times_workspace_bytes(const h2x_mat *A, int32_t ncand, const 
 
 h2x_status h2x_product_times(const h2x_mat *A, int32_t ncand, const int64_t *cand_m, int32_t reps, void *dev_ws,
                              size_t ws_bytes, void *hip_stream, double *ms) {
+    for (int32_t i = 0; A && cand_m && i < ncand; ++i)
+        if (h2x_status r = need_pairs(A, cand_m[i], "h2x_product_times")) return r;
     if (!A || !cand_m || !ms || !dev_ws) return fail(H2X_EINVAL, "h2x_product_times: NULL argument");
     if (ncand < 1 || reps < 1) return fail(H2X_EINVAL, "h2x_product_times: need ncand >= 1 and reps >= 1");
     for (int32_t i = 0; i < ncand; ++i)
@@ -390,6 +416,7 @@ h2x_status h2x_product_times(const h2x_mat *A, int32_t ncand, const int64_t *can
 h2x_status h2x_block_cg_chunked(const h2x_mat *A, const h2x_cg_params *prm, int64_t m, int64_t m_chunk,
                                 const double *B, int64_t ldb, double *X, int64_t ldx, void *dev_ws, size_t ws_bytes,
                                 h2x_cg_info *info, void *hip_stream) {
+    if (h2x_status r = refuse_complex(A, "h2x_block_cg_chunked")) return r;
     if (!A || !prm || !B || !X || !dev_ws) return fail(H2X_EINVAL, "h2x_block_cg_chunked: NULL argument");
     if (m < 1 || m_chunk < 1 || ldb < m || ldx < m)
         return fail(H2X_EINVAL, "h2x_block_cg_chunked: need m >= 1, m_chunk >= 1, ldb >= m, ldx >= m");
@@ -407,6 +434,8 @@ h2x_status h2x_block_cg_chunked(const h2x_mat *A, const h2x_cg_params *prm, int6
 h2x_status h2x_block_gmres_chunked(const h2x_mat *A, const h2x_gmres_params *prm, int64_t m, int64_t m_chunk,
                                    const double *B, int64_t ldb, double *X, int64_t ldx, void *dev_ws,
                                    size_t ws_bytes, h2x_gmres_info *info, void *hip_stream) {
+    if (h2x_status r = need_pairs(A, m, "h2x_block_gmres_chunked")) return r;
+    if (h2x_status r = need_pairs(A, m_chunk, "h2x_block_gmres_chunked")) return r;
     if (!A || !prm || !B || !X || !dev_ws) return fail(H2X_EINVAL, "h2x_block_gmres_chunked: NULL argument");
     if (m < 1 || m_chunk < 1 || ldb < m || ldx < m)
         return fail(H2X_EINVAL, "h2x_block_gmres_chunked: need m >= 1, m_chunk >= 1, ldb >= m, ldx >= m");
@@ -429,6 +458,8 @@ size_t h2x_block_cg_mixed_workspace_bytes(const h2x_mat *A, const h2x_mat *A_lo,
 h2x_status h2x_block_cg_mixed(const h2x_mat *A, const h2x_mat *A_lo, const h2x_cg_params *prm, double delta,
                               int64_t m, const double *B, int64_t ldb, double *X, int64_t ldx, void *dev_ws,
                               size_t ws_bytes, h2x_cg_info *info, void *hip_stream) {
+    if (h2x_status r = refuse_complex(A, "h2x_block_cg_mixed")) return r;
+    if (h2x_status r = refuse_complex(A_lo, "h2x_block_cg_mixed")) return r;
     if (!A || !A_lo || !prm || !B || !X || !dev_ws) return fail(H2X_EINVAL, "h2x_block_cg_mixed: NULL argument");
     if (A->plan != A_lo->plan) return fail(H2X_EINVAL, "h2x_block_cg_mixed: A and A_lo must share one plan");
     if (A->dm.storage != H2X_F64) return fail(H2X_EINVAL, "h2x_block_cg_mixed: A must be stored in FP64");
@@ -451,6 +482,7 @@ size_t h2x_mat_autotune_workspace_bytes(const h2x_mat *A, int64_t m) {
 
 h2x_status h2x_mat_autotune(h2x_mat *A, int64_t m, void *dev_ws, size_t ws_bytes, void *hip_stream,
                             h2x_tune_info *info) {
+    if (h2x_status r = need_pairs(A, m, "h2x_mat_autotune")) return r;
     if (!A || !dev_ws) return fail(H2X_EINVAL, "h2x_mat_autotune: NULL argument");
     if (m < 1) return fail(H2X_EINVAL, "h2x_mat_autotune: need m >= 1");
     if (!aligned(dev_ws)) return fail(H2X_EINVAL, "h2x_mat_autotune: workspace not 256-byte aligned");
@@ -458,6 +490,8 @@ h2x_status h2x_mat_autotune(h2x_mat *A, int64_t m, void *dev_ws, size_t ws_bytes
 }
 
 h2x_status h2x_batch_create(const h2x_mat *const *mats, int32_t count, h2x_batch **out) {
+    for (int32_t i = 0; mats && i < count; ++i)
+        if (h2x_status r = refuse_complex(mats[i], "h2x_batch_create")) return r;
     if (!out) return fail(H2X_EINVAL, "h2x_batch_create: out is NULL");
     *out = nullptr;
     if (!mats || count < 1) return fail(H2X_EINVAL, "h2x_batch_create: need count >= 1 operators");
@@ -537,6 +571,7 @@ size_t h2x_grad_workspace_bytes(const h2x_mat *A, int64_t m) {
 
 h2x_status h2x_matmul_adjoint(const h2x_mat *A, int64_t m, double alpha, const double *X, int64_t ldx, double beta,
                               double *Y, int64_t ldy, void *dev_ws, size_t ws_bytes, void *hip_stream) {
+    if (h2x_status r = refuse_complex(A, "h2x_matmul_adjoint")) return r;
     if (!A || !X || !Y || !dev_ws) return fail(H2X_EINVAL, "h2x_matmul_adjoint: NULL argument");
     if (A->dm.storage != H2X_F64 || A->dm.k > 64)
         return fail(H2X_EUNSUPPORTED, "h2x_matmul_adjoint: FP64 operators with k <= 64 only");
@@ -554,6 +589,7 @@ h2x_status h2x_matmul_adjoint(const h2x_mat *A, int64_t m, double alpha, const d
 
 h2x_status h2x_grad(const h2x_mat *A, int64_t m, const double *X, int64_t ldx, const double *dY, int64_t lddy,
                     double *dS, double *dN, double *dell, void *dev_ws, size_t ws_bytes, void *hip_stream) {
+    if (h2x_status r = refuse_complex(A, "h2x_grad")) return r;
     if (!A || !X || !dY || !dev_ws) return fail(H2X_EINVAL, "h2x_grad: NULL argument");
     if (A->dm.storage != H2X_F64 || A->dm.k > 64)
         return fail(H2X_EUNSUPPORTED, "h2x_grad: FP64 operators with k <= 64 only");
@@ -579,6 +615,7 @@ h2x_status h2x_mat_set_ell(h2x_mat *A, double ell, void *hip_stream) {
 }
 
 h2x_status h2x_mat_coupling(const h2x_mat *A, double *out, void *hip_stream) {
+    if (h2x_status r = refuse_complex(A, "h2x_mat_coupling")) return r;
     if (!A || !out) return fail(H2X_EINVAL, "h2x_mat_coupling: NULL argument");
     if (A->dm.storage != H2X_F64) return fail(H2X_EUNSUPPORTED, "h2x_mat_coupling: FP64 operators only");
     hipError_t e = run_read_coupling(A->dm, out, (hipStream_t)hip_stream);
@@ -587,6 +624,7 @@ h2x_status h2x_mat_coupling(const h2x_mat *A, double *out, void *hip_stream) {
 }
 
 h2x_status h2x_mat_set_coupling(h2x_mat *A, const double *in, void *hip_stream) {
+    if (h2x_status r = refuse_complex(A, "h2x_mat_set_coupling")) return r;
     if (!A || !in) return fail(H2X_EINVAL, "h2x_mat_set_coupling: NULL argument");
     if (A->dm.storage != H2X_F64) return fail(H2X_EUNSUPPORTED, "h2x_mat_set_coupling: FP64 operators only");
     hipError_t e = run_write_coupling(A->dm, in, (hipStream_t)hip_stream);
@@ -602,6 +640,8 @@ size_t h2x_block_cg_refine_workspace_bytes(const h2x_mat *A, const h2x_mat *A_lo
 h2x_status h2x_block_cg_refine(const h2x_mat *A, const h2x_mat *A_lo, const h2x_cg_params *inner, double rtol,
                                int32_t max_outer, int64_t m, const double *B, int64_t ldb, double *X, int64_t ldx,
                                void *dev_ws, size_t ws_bytes, h2x_cg_info *info, void *hip_stream) {
+    if (h2x_status r = refuse_complex(A, "h2x_block_cg_refine")) return r;
+    if (h2x_status r = refuse_complex(A_lo, "h2x_block_cg_refine")) return r;
     if (!A || !A_lo || !inner || !B || !X || !dev_ws) return fail(H2X_EINVAL, "h2x_block_cg_refine: NULL argument");
     if (A->plan != A_lo->plan) return fail(H2X_EINVAL, "h2x_block_cg_refine: A and A_lo must share one plan");
     if (A->dm.storage != H2X_F64) return fail(H2X_EINVAL, "h2x_block_cg_refine: A must be stored in FP64");

@@ -151,10 +151,11 @@ h2x_status run_gmres_chunked(const DevMat &dm, const h2x_gmres_params &prm, int6
     for (int64_t c0 = 0; c0 < m; c0 += mc) {
         const int64_t cm = std::min(mc, m - c0);
         h2x_gmres_info sub{};
+        const int64_t ci = dm.cplx ? c0 / 2 : c0;  // info entries are per complex column
         if (info) {
-            sub.col_res = info->col_res ? info->col_res + c0 : nullptr;
-            sub.col_iters = info->col_iters ? info->col_iters + c0 : nullptr;
-            sub.col_status = info->col_status ? info->col_status + c0 : nullptr;
+            sub.col_res = info->col_res ? info->col_res + ci : nullptr;
+            sub.col_iters = info->col_iters ? info->col_iters + ci : nullptr;
+            sub.col_status = info->col_status ? info->col_status + ci : nullptr;
         }
         const h2x_status r =
             run_block_gmres(dm, prm, cm, B + c0, ldb, X + c0, ldx, ws, ws_bytes, info ? &sub : nullptr, st);

@@ -40,6 +40,8 @@ struct DevMat {
     int near_t = 0;  // near-field blocks stored transposed (|s| x |t| row-major)
     int mc = 0;      // every stage runs on the matrix cores (FP64, k = 64 or k <= 32)
     int kernel = 0;
+    int cplx = 0;                   // complex kernel: S and N hold a real and an imaginary plane
+    int64_t s_plane = 0, n_plane = 0;  // elements per plane of S and N
     double ell = 0, shift = 0;
 
     // topology

@@ -32,6 +32,20 @@ __device__ inline double kernel_g(int kernel, double ell, const double *a, const
     return 1.0;
 }
 
+// complex Helmholtz kernel with equal quadrature weights: exp(i kappa r) / (n r),
+// kappa = ell; coinciding points give 0
+__device__ inline void kernel_gc(double ell, double npts, const double *a, const double *b, double &re, double &im) {
+    const double dx = a[0] - b[0], dy = a[1] - b[1], dz = a[2] - b[2];
+    const double r = sqrt(dx * dx + dy * dy + dz * dz);
+    if (r == 0.0) {
+        re = im = 0.0;
+        return;
+    }
+    const double f = 1.0 / (npts * r);
+    re = cos(ell * r) * f;
+    im = sin(ell * r) * f;
+}
+
 // one-dimensional Lagrange polynomial j of the nodes nd[0..p) at x
 __device__ inline double lagrange1(const double *nd, int p, int j, double x) {
     double v = 1.0, xj = nd[j];
@@ -120,39 +134,62 @@ __global__ void k_fill_E(int p, const int32_t *__restrict__ parent, const double
 }
 
 // S_b[nu, mu] = g(xi_{t,nu}, xi_{s,mu}), stored in the layout the coupling kernel reads
+// (complex kernel: real part into S, imaginary part into S + s_plane)
 template <typename T>
-__global__ void k_fill_S(int k, int kernel, double ell, const int32_t *__restrict__ adm_row,
+__global__ void k_fill_S(int k, int kernel, double ell, double npts, const int32_t *__restrict__ adm_row,
                          const int32_t *__restrict__ adm_col, const double *__restrict__ nodes,
-                         T *__restrict__ S, int swz) {
+                         T *__restrict__ S, int swz, int64_t s_plane) {
     const int64_t b = blockIdx.x;
     const int32_t t = adm_row[b], s = adm_col[b];
     for (int e = threadIdx.x; e < k * k; e += blockDim.x) {
         const int nu = e / k, mu = e % k;
-        double v = kernel_g(kernel, ell, &nodes[((int64_t)t * k + nu) * 3], &nodes[((int64_t)s * k + mu) * 3]);
-        S[b * k * k + s_index(swz, k, nu, mu)] = from_double<T>(v);
+        const double *xa = &nodes[((int64_t)t * k + nu) * 3], *xb = &nodes[((int64_t)s * k + mu) * 3];
+        const int64_t at = b * k * k + s_index(swz, k, nu, mu);
+        if (kernel == H2X_KERNEL_HELMHOLTZ) {
+            double re, im;
+            kernel_gc(ell, npts, xa, xb, re, im);
+            S[at] = from_double<T>(re);
+            S[at + s_plane] = from_double<T>(im);
+        } else {
+            S[at] = from_double<T>(kernel_g(kernel, ell, xa, xb));
+        }
     }
 }
 
 // N_(t,s)[i, j] = g(x_i, x_j) + shift [i == j], row-major |t| x |s|, or stored
 // transposed when trans != 0: |s| rows of length |t| padded to even, padding zero
+// (complex kernel: real part into N, imaginary part into N + n_plane)
 template <typename TN>
-__global__ void k_fill_N(int kernel, double ell, double shift, const int32_t *__restrict__ near_row,
+__global__ void k_fill_N(int kernel, double ell, double shift, double npts, const int32_t *__restrict__ near_row,
                          const int32_t *__restrict__ near_col, const int64_t *__restrict__ near_off,
                          const int32_t *__restrict__ first, const int32_t *__restrict__ size,
-                         const double *__restrict__ pts, TN *__restrict__ N, int trans) {
+                         const double *__restrict__ pts, TN *__restrict__ N, int trans, int64_t n_plane) {
     const int64_t q = blockIdx.x;
     const int32_t t = near_row[q], s = near_col[q];
     const int64_t nt = size[t], ns = size[s], ft = first[t], fs = first[s];
     TN *Nb = N + near_off[q];
     const int64_t nt2 = nt + (nt & 1);
+    const bool cplx = kernel == H2X_KERNEL_HELMHOLTZ;
     for (int64_t e = threadIdx.x; e < nt * ns; e += blockDim.x) {
         const int64_t il = e / ns, jl = e % ns, i = ft + il, j = fs + jl;
-        double v = kernel_g(kernel, ell, &pts[3 * i], &pts[3 * j]);
-        if (i == j) v += shift;
-        Nb[trans ? jl * nt2 + il : e] = (TN)v;
+        const int64_t at = trans ? jl * nt2 + il : e;
+        if (cplx) {
+            double re, im;
+            kernel_gc(ell, npts, &pts[3 * i], &pts[3 * j], re, im);
+            if (i == j) re += shift;
+            Nb[at] = (TN)re;
+            Nb[at + n_plane] = (TN)im;
+        } else {
+            double v = kernel_g(kernel, ell, &pts[3 * i], &pts[3 * j]);
+            if (i == j) v += shift;
+            Nb[at] = (TN)v;
+        }
     }
     if (trans && (nt & 1))
-        for (int64_t jl = threadIdx.x; jl < ns; jl += blockDim.x) Nb[jl * nt2 + nt] = (TN)0;
+        for (int64_t jl = threadIdx.x; jl < ns; jl += blockDim.x) {
+            Nb[jl * nt2 + nt] = (TN)0;
+            if (cplx) Nb[jl * nt2 + nt + n_plane] = (TN)0;
+        }
 }
 
 // coupling matrices and near field, system by system (each with its own kernel
@@ -166,13 +203,15 @@ hipError_t fill_SN(const DevMat &dm, hipStream_t st) {
         const double ell = ns == 1 ? dm.ell : P.sys_prm[i].ell, shift = ns == 1 ? dm.shift : P.sys_prm[i].shift;
         const int64_t a = P.sys_adm[i], na = P.sys_adm[i + 1] - a;
         const int64_t q = P.sys_near[i], nq = P.sys_near[i + 1] - q;
+        const double npts = (double)(P.sys_row[i + 1] - P.sys_row[i]);  // points of system i
         if (na > 0)
-            hipLaunchKernelGGL(k_fill_S<T>, dim3((unsigned)na), dim3(256), 0, st, dm.k, kernel, ell, dm.adm_row + a,
-                               dm.adm_col + a, dm.nodes, (T *)dm.S + a * dm.k * dm.k, s_swizzled(dm));
+            hipLaunchKernelGGL(k_fill_S<T>, dim3((unsigned)na), dim3(256), 0, st, dm.k, kernel, ell, npts,
+                               dm.adm_row + a, dm.adm_col + a, dm.nodes, (T *)dm.S + a * dm.k * dm.k, s_swizzled(dm),
+                               dm.s_plane);
         if (nq > 0)
-            hipLaunchKernelGGL(k_fill_N<TN>, dim3((unsigned)nq), dim3(256), 0, st, kernel, ell, shift,
+            hipLaunchKernelGGL(k_fill_N<TN>, dim3((unsigned)nq), dim3(256), 0, st, kernel, ell, shift, npts,
                                dm.near_row + q, dm.near_col + q, dm.near_off + q, dm.first, dm.size, dm.pts,
-                               (TN *)dm.N, dm.near_t);
+                               (TN *)dm.N, dm.near_t, dm.n_plane);
     }
     return hipGetLastError();
 }
@@ -252,9 +291,14 @@ size_t mat_layout(const Plan &P, h2x_prec storage, DevMat *dm, char *base) {
     const size_t ens = storage == H2X_F64 ? 8 : 4;
     d.V = carve<char>(cur, base, es * (size_t)n * k);
     d.E = carve<char>(cur, base, es * (size_t)C * k * k);
-    d.S = carve<char>(cur, base, es * (size_t)(na ? na : 1) * k * k);
+    // complex kernel: a real and an imaginary plane of S and N (V and E stay real)
+    d.cplx = (P.nsys() == 1 && P.prm.kernel == H2X_KERNEL_HELMHOLTZ) ? 1 : 0;
+    const int planes = d.cplx ? 2 : 1;
     const int64_t nstored = d.near_t ? P.near_entries_t : P.near_entries;
-    d.N = carve<char>(cur, base, ens * (size_t)(nstored ? nstored : 1) + 16);
+    d.s_plane = d.cplx ? na * k * k : 0;
+    d.n_plane = d.cplx ? nstored : 0;
+    d.S = carve<char>(cur, base, es * planes * (size_t)(na ? na : 1) * k * k);
+    d.N = carve<char>(cur, base, ens * planes * (size_t)(nstored ? nstored : 1) + 16);
     d.Vt = d.near_t ? carve<char>(cur, base, es * (size_t)P.vt_entries) : nullptr;
     if (dm) *dm = d;
     return align_up(cur);

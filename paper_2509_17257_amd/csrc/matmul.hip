@@ -326,12 +326,12 @@ void matmul_mfma_f64(const DevMat &dm, const TuneCfg &cfg, int64_t m, double alp
             hipLaunchKernelGGL(mfma::k_leaf_direct<2>, dim3(gx), dim3(256), 0, s, dm.k, m,
                                dm.L, dm.leaves, dm.first, dm.size, dm.perm, (const double *)dm.Vt, dm.vt_off, yh, ldh,
                                dm.near_ptr, dm.near_col, dm.near_off, (const double *)dm.N, Xt, ldxt, alpha, b, Y,
-                               ldy, to, basis, near, sk);
+                               ldy, to, basis, near, sk, dm.n_plane);
         else
             hipLaunchKernelGGL(mfma::k_leaf_direct<1>, dim3(gx), dim3(256), 0, s, dm.k, m,
                                dm.L, dm.leaves, dm.first, dm.size, dm.perm, (const double *)dm.Vt, dm.vt_off, yh, ldh,
                                dm.near_ptr, dm.near_col, dm.near_off, (const double *)dm.N, Xt, ldxt, alpha, b, Y,
-                               ldy, to, basis, near, sk);
+                               ldy, to, basis, near, sk, dm.n_plane);
     };
     // near field on the operator's second stream while the transfer passes and the
     // coupling run here (it needs only X); the basis term joins it at the end.  Its
@@ -369,6 +369,8 @@ void matmul_mfma_f64(const DevMat &dm, const TuneCfg &cfg, int64_t m, double alp
     }
     mark(2);
     launch_coupling_fast<double, double>(dm, m, xh, yh, ldh, st, sk, cfg.nj_coupling);
+    // complex operator: y-hat += S_im (J x-hat), so that y-hat = (S_re + i S_im) x-hat per complex column
+    if (dm.cplx) launch_coupling_fast<double, double>(dm, m, xh, yh, ldh, st, sk, cfg.nj_coupling, 1);
     mark(3);
     for (int d = std::max(1, P.adm_depth + 1); d <= dm.depth_max; ++d) {
         const int32_t b = P.lvl_ptr[d], e = P.lvl_ptr[d + 1];

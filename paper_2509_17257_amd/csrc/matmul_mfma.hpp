@@ -35,7 +35,7 @@ __global__ __launch_bounds__(256) void k_coupling_mfma_f64(int64_t m, int32_t C,
                                                            const int32_t *__restrict__ adm_col,
                                                            const double *__restrict__ S,
                                                            const double *__restrict__ xh, double *__restrict__ yh,
-                                                           int64_t ldh, Skip skip) {
+                                                           int64_t ldh, Skip skip, int jpass) {
     constexpr int MC = 16 * NJ;   // columns per work-group
     constexpr int LDX = MC + 1;   // padded LDS row
     __shared__ double xs[2][kMfmaK * LDX];
@@ -65,14 +65,16 @@ __global__ __launch_bounds__(256) void k_coupling_mfma_f64(int64_t m, int32_t C,
 #pragma unroll
             for (int u = 0; u < XPT; ++u) {
                 const int e = tid + 256 * u, r = e / MC, c = e % MC;
-                xv[u] = src[(int64_t)r * ldh + (c < mc ? c : 0)];  // columns past mc: zeroed when stored
+                // jpass: column c takes its partner c ^ 1 (J x = (-im, re) per complex column)
+                xv[u] = src[(int64_t)r * ldh + ((c < mc ? c : 0) ^ jpass)];  // columns past mc: zeroed when stored
             }
         };
         auto store_x = [&](int buf) {
 #pragma unroll
             for (int u = 0; u < XPT; ++u) {
                 const int e = tid + 256 * u, r = e / MC, c = e % MC;
-                xs[buf][r * LDX + c] = c < mc ? xv[u] : 0.0;
+                const double v = (jpass & ~c & 1) ? -xv[u] : xv[u];
+                xs[buf][r * LDX + c] = c < mc ? v : 0.0;
             }
         };
         typedef double dbl2 __attribute__((ext_vector_type(2)));
@@ -127,7 +129,8 @@ __global__ __launch_bounds__(256) void k_coupling_mfma_f64(int64_t m, int32_t C,
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int row = 16 * w + lq + 4 * r;
-                yh[((int64_t)t * kMfmaK + row) * ldh + j0 + col] = acc[J][r];
+                double *y = &yh[((int64_t)t * kMfmaK + row) * ldh + j0 + col];
+                *y = jpass ? *y + acc[J][r] : acc[J][r];  // the second pass adds
             }
         }
     }
@@ -149,7 +152,7 @@ __global__ __launch_bounds__(128) void k_coupling_mfma_small(int k, int64_t m, i
                                                              const int32_t *__restrict__ adm_col,
                                                              const double *__restrict__ S,
                                                              const double *__restrict__ xh, double *__restrict__ yh,
-                                                             int64_t ldh, Skip skip) {
+                                                             int64_t ldh, Skip skip, int jpass) {
     constexpr int MC = 16 * NJ;
     constexpr int LDX = MC + 1;
     __shared__ double xs[2][32 * LDX];
@@ -181,14 +184,15 @@ __global__ __launch_bounds__(128) void k_coupling_mfma_small(int k, int64_t m, i
 #pragma unroll
             for (int u = 0; u < XPT; ++u) {
                 const int e = tid + 128 * u, r = e / MC, c = e % MC;
-                xv[u] = src[(r < k && c < mc) ? (int64_t)r * ldh + c : 0];  // zeroed when stored
+                xv[u] = src[(r < k && c < mc) ? (int64_t)r * ldh + (c ^ jpass) : 0];  // zeroed when stored
             }
         };
         auto store_x = [&](int buf) {
 #pragma unroll
             for (int u = 0; u < XPT; ++u) {
                 const int e = tid + 128 * u, r = e / MC, c = e % MC;
-                xs[buf][r * LDX + c] = (r < k && c < mc) ? xv[u] : 0.0;
+                const double v = (jpass & ~c & 1) ? -xv[u] : xv[u];
+                xs[buf][r * LDX + c] = (r < k && c < mc) ? v : 0.0;
             }
         };
         double sa[4][2], sn[4][2];
@@ -250,7 +254,10 @@ __global__ __launch_bounds__(128) void k_coupling_mfma_small(int k, int64_t m, i
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int row = 16 * w + g + 4 * r;
-                if (row < k) yh[((int64_t)t * k + row) * ldh + j0 + col] = acc[J][r];
+                if (row < k) {
+                    double *y = &yh[((int64_t)t * k + row) * ldh + j0 + col];
+                    *y = jpass ? *y + acc[J][r] : acc[J][r];
+                }
             }
         }
     }
@@ -260,7 +267,7 @@ __global__ __launch_bounds__(128) void k_coupling_mfma_small(int k, int64_t m, i
 // it; returns false (launching nothing) otherwise.
 template <typename T, typename Acc>
 bool launch_coupling_fast(const DevMat &dm, int64_t m, const Acc *xh, Acc *yh, int64_t ldh, hipStream_t st,
-                          Skip skip, int nj_force) {
+                          Skip skip, int nj_force, int jpass = 0) {
     if constexpr (!std::is_same<T, double>::value || !std::is_same<Acc, double>::value) {
         return false;
     } else {
@@ -269,12 +276,13 @@ bool launch_coupling_fast(const DevMat &dm, int64_t m, const Acc *xh, Acc *yh, i
         const int mcols = 16 * nj;
         const int32_t rpx = (dm.C + 7) / 8;
         const dim3 grid((unsigned)(8 * rpx * ((m + mcols - 1) / mcols)));
-        const double *S = (const double *)dm.S;
+        // jpass (complex operator): the imaginary plane of S on J x-hat, added to y-hat
+        const double *S = (const double *)dm.S + (jpass ? dm.s_plane : 0);
         if (dm.k <= 32) {
             auto go = [&](auto NJc) {
                 constexpr int NJ = decltype(NJc)::value;
                 hipLaunchKernelGGL(k_coupling_mfma_small<NJ>, grid, dim3(128), 0, st, dm.k, m, dm.C, rpx,
-                                   dm.cpl_order, dm.adm_ptr, dm.adm_col, S, xh, yh, ldh, skip);
+                                   dm.cpl_order, dm.adm_ptr, dm.adm_col, S, xh, yh, ldh, skip, jpass);
             };
             switch (nj) {
                 case 1: go(std::integral_constant<int, 1>{}); break;
@@ -288,19 +296,19 @@ bool launch_coupling_fast(const DevMat &dm, int64_t m, const Acc *xh, Acc *yh, i
         switch (nj) {
             case 1:
                 hipLaunchKernelGGL(k_coupling_mfma_f64<1>, grid, dim3(256), 0, st, m, dm.C, rpx, dm.cpl_order,
-                                   dm.adm_ptr, dm.adm_col, S, xh, yh, ldh, skip);
+                                   dm.adm_ptr, dm.adm_col, S, xh, yh, ldh, skip, jpass);
                 break;
             case 2:
                 hipLaunchKernelGGL(k_coupling_mfma_f64<2>, grid, dim3(256), 0, st, m, dm.C, rpx, dm.cpl_order,
-                                   dm.adm_ptr, dm.adm_col, S, xh, yh, ldh, skip);
+                                   dm.adm_ptr, dm.adm_col, S, xh, yh, ldh, skip, jpass);
                 break;
             case 3:
                 hipLaunchKernelGGL(k_coupling_mfma_f64<3>, grid, dim3(256), 0, st, m, dm.C, rpx, dm.cpl_order,
-                                   dm.adm_ptr, dm.adm_col, S, xh, yh, ldh, skip);
+                                   dm.adm_ptr, dm.adm_col, S, xh, yh, ldh, skip, jpass);
                 break;
             default:
                 hipLaunchKernelGGL(k_coupling_mfma_f64<4>, grid, dim3(256), 0, st, m, dm.C, rpx, dm.cpl_order,
-                                   dm.adm_ptr, dm.adm_col, S, xh, yh, ldh, skip);
+                                   dm.adm_ptr, dm.adm_col, S, xh, yh, ldh, skip, jpass);
                 break;
         }
         return true;

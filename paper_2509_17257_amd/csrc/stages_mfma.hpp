@@ -350,6 +350,7 @@ struct Round {
     dbl2 b[2][4];   // [row half g][k-step u]: rows 32g + 2 lr + {0, 1}
     dbl2 a[NP][4];  // [column half p][k-step u]: columns 32p + 2 lr + {0, 1}
     int kb, kl;     // first k-step of the round and the item's length
+    int jx;         // apply J to the left operand (imaginary plane of a complex near block)
 };
 
 __device__ inline dbl2 ld2(const double *p) { return *(const dbl2 *)p; }
@@ -366,7 +367,8 @@ __global__ __launch_bounds__(256, NP == 1 ? 2 : 1) void k_leaf_direct(int k, int
                                                      const int64_t *__restrict__ near_off,
                                                      const double *__restrict__ Nt, const double *__restrict__ Xt,
                                                      int64_t ldxt, double alpha, double beta, double *__restrict__ Y,
-                                                     int64_t ldy, int tree_order, int basis, int near, Skip skip) {
+                                                     int64_t ldy, int tree_order, int basis, int near, Skip skip,
+                                                     int64_t n_plane) {
     constexpr int MC = 32 * NP, LDR = MC + 1;
     __shared__ double red[64 * LDR];
     const int32_t per_xcd = (L + 7) / 8;
@@ -393,7 +395,10 @@ __global__ __launch_bounds__(256, NP == 1 ? 2 : 1) void k_leaf_direct(int k, int
         const int nb = basis ? (near ? 1 : 4) : 0;
         const int kbase = (k + max(nb, 1) - 1) / max(nb, 1);
         const int nnear = near ? (int)(near_ptr[l + 1] - q0) : 0;
-        const int nitems = nnear + nb;
+        // complex operator (n_plane > 0): every near block is two items, its real plane on X
+        // and its imaginary plane on J X (column pairs (re, im) -> (-im, re))
+        const int cpx = n_plane > 0 ? 1 : 0;
+        const int nitems = (nnear << cpx) + nb;
         // the near blocks' offsets, column ranges and sizes, staged once so that moving
         // to the next item costs no dependent global loads (beyond kMeta: read directly)
         constexpr int kMeta = 160;
@@ -449,11 +454,14 @@ __global__ __launch_bounds__(256, NP == 1 ? 2 : 1) void k_leaf_direct(int k, int
                     kl = min(kbase, k - e * kbase);
                 } else {
                     int64_t off, fs;
-                    near_meta(e - nb, off, fs, kl);
-                    bb = Nt + off + i0;               // N_ts^T[c][i]
-                    ab = Xt + fs * ldxt + j0;         // X_s[c][j]
+                    const int q = (e - nb) >> cpx, plane = (e - nb) & cpx;
+                    near_meta(q, off, fs, kl);
+                    bb = Nt + off + (plane ? n_plane : 0) + i0;  // N_ts^T[c][i]
+                    ab = Xt + fs * ldxt + j0;                     // X_s[c][j]
                     lda = ldxt;
+                    R.jx = plane;
                 }
+                if (e < nb) R.jx = 0;
                 R.kb = kb;
                 R.kl = kl;
     #pragma unroll
@@ -469,16 +477,21 @@ __global__ __launch_bounds__(256, NP == 1 ? 2 : 1) void k_leaf_direct(int k, int
                 if (e < nb) return min(kbase, k - e * kbase);
                 int64_t off, fs;
                 int ks;
-                near_meta(e - nb, off, fs, ks);
+                near_meta((e - nb) >> cpx, off, fs, ks);
                 return ks;
             };
-            // zero the left operand's k-rows past the item (once the round's loads are in)
+            // zero the left operand's k-rows past the item, and apply J for an imaginary
+            // plane (once the round's loads are in)
             auto mask = [&](Round<NP> &R) {
     #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     const bool cok = R.kb + 4 * u + lq < R.kl;
     #pragma unroll
-                    for (int p = 0; p < NP; ++p) R.a[p][u] = cok ? R.a[p][u] : dbl2{0.0, 0.0};
+                    for (int p = 0; p < NP; ++p) {
+                        dbl2 v = cok ? R.a[p][u] : dbl2{0.0, 0.0};
+                        if (R.jx) v = dbl2{-v.y, v.x};
+                        R.a[p][u] = v;
+                    }
                 }
             };
             auto multiply = [&](const Round<NP> &R) {

@@ -509,6 +509,64 @@ def chunk_report(args, torch, h2x, W):
     print(json.dumps(out), flush=True)
 
 
+def complex_report(args, torch, h2x, W):
+    """Complex Helmholtz operator (section 5.2's complex setting; single-layer kernel with
+    equal quadrature weights) on the FP64 sphere workload's points (n = 65536, leaf 64,
+    k = 64), 16 complex right-hand sides: product time and algorithmic bandwidth (S and N
+    complex, 16 bytes per entry; V and E real), block GMRES(30) to 1e-8, and single-column
+    GMRES of a sample of columns, for wavenumbers 1 and 4."""
+    dev = torch.device("cuda:0")
+    w = W.FP64
+    P = w.points()
+    mc, rtol, restart, sample = 16, 1e-8, 30, 4
+    out = {"workload": f"helmholtz-sphere-n{w.n}-k64-m{mc}c", "runs": []}
+    for kappa in (1.0, 4.0):
+        A = h2x.H2Matrix(P, device=dev, kernel="helmholtz", ell=kappa, shift=1.0, eta=1.0, leaf=64, p=4)
+        if args.autotune:
+            A.autotune(2 * mc)
+        plan = A.plan
+        k = plan.k
+        alg = (8 * (plan.n * k + (plan.C - 1) * k * k) + 16 * plan.n_adm * k * k + 16 * plan.near_entries
+               + 16 * plan.n * mc * 2)
+        X = torch.complex(torch.from_numpy(W.rhs(w.n, mc, 7500)), torch.from_numpy(W.rhs(w.n, mc, 7501))).to(dev)
+        Y = torch.empty_like(X)
+        h2x.h2_matmul(A, X, out=Y)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = max(5, min(args.steps, 50))
+        e0.record()
+        for _ in range(reps):
+            h2x.h2_matmul(A, X, out=Y)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        B = torch.complex(torch.from_numpy(W.rhs(w.n, mc, 7502)), torch.from_numpy(W.rhs(w.n, mc, 7503))).to(dev)
+        h2x.block_gmres_solve(A, B[:, :1].contiguous(), rtol=rtol, restart=restart, max_iter=2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Xs, info = h2x.block_gmres_solve(A, B, rtol=rtol, restart=restart, max_iter=3000)
+        torch.cuda.synchronize()
+        t_blk = time.perf_counter() - t0
+        res = (torch.linalg.norm(B - h2x.h2_matmul(A, Xs), dim=0) / torch.linalg.norm(B, dim=0)).max().item()
+        singles = []
+        for j in range(sample):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, i1 = h2x.block_gmres_solve(A, B[:, j:j + 1].contiguous(), rtol=rtol, restart=restart, max_iter=3000)
+            torch.cuda.synchronize()
+            singles.append((time.perf_counter() - t0, i1.iters))
+        t1 = sum(t for t, _ in singles) / sample
+        rec = {"kappa": kappa, "complex_columns": mc, "product_ms": round(ms, 4),
+               "product_alg_gbs": round(alg / (ms * 1e-3) / 1e9, 1), "alg_bytes": alg,
+               "gmres_time_s": round(t_blk, 4), "gmres_steps": info.iters, "gmres_cycles": info.cycles,
+               "gmres_status": info.status, "max_true_relres": res, "single_rhs_time_s": round(t1, 4),
+               "single_rhs_steps": [s for _, s in singles], "block_speedup_est": round(mc * t1 / t_blk, 2)}
+        out["runs"].append(rec)
+        log(f"[complex] {rec}")
+        del A
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -531,6 +589,8 @@ def main():
                     help="block GMRES(30) to 1e-8 on the FP64 workload, symmetric and non-symmetric operators")
     ap.add_argument("--chunk-report", action="store_true",
                     help="right-hand-side chunk policy: product-time curve, picks under budgets, chunked CG solves")
+    ap.add_argument("--complex-report", action="store_true",
+                    help="complex Helmholtz operator: products and block GMRES over C on the FP64 workload's points")
     ap.add_argument("--copy-calibration-gib", type=float, default=0.0,
                     help="only run a plain device copy of this many GiB (to scale HBM traffic counters) and exit")
     args = ap.parse_args()
@@ -585,6 +645,9 @@ def main():
         return
     if args.chunk_report:
         chunk_report(args, torch, h2x, W)
+        return
+    if args.complex_report:
+        complex_report(args, torch, h2x, W)
         return
 
     w = W.WORKLOADS[args.workload]

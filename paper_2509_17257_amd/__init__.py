@@ -68,8 +68,8 @@ class _GmresInfo(C.Structure):
 
 class _TuneInfo(C.Structure):
     _fields_ = [("nj_transfer", C.c_int32), ("nj_coupling", C.c_int32), ("np_leaf", C.c_int32),
-                ("overlap", C.c_int32), ("fuse_up", C.c_int32), ("ms_default", C.c_double),
-                ("ms_tuned", C.c_double)]
+                ("overlap", C.c_int32), ("fuse_up", C.c_int32), ("leaf_kind", C.c_int32), ("nj_leaf", C.c_int32),
+                ("ms_default", C.c_double), ("ms_tuned", C.c_double)]
 
 
 class _CgInfo(C.Structure):
@@ -139,6 +139,8 @@ def load_library():
                                               C.POINTER(_GmresInfo), P]),
         "h2x_mat_autotune_workspace_bytes": (SZ, [P, I64]),
         "h2x_mat_autotune": (C.c_int, [P, I64, P, SZ, P, C.POINTER(_TuneInfo)]),
+        "h2x_mat_set_tune": (C.c_int, [P, I64, C.POINTER(_TuneInfo)]),
+        "h2x_mat_get_tune": (C.c_int, [P, I64, C.POINTER(_TuneInfo)]),
         "h2x_last_error": (C.c_char_p, []),
         "h2x_version": (C.c_char_p, []),
     }
@@ -285,8 +287,25 @@ class H2Matrix:
         _check(lib.h2x_mat_autotune(self._h, int(m), C.c_void_p(ws.data_ptr()), ws.numel(),
                                     _stream(torch, self.device), C.byref(info)), "h2x_mat_autotune")
         return dict(nj_transfer=info.nj_transfer, nj_coupling=info.nj_coupling, np_leaf=info.np_leaf,
-                    overlap=info.overlap, fuse_up=info.fuse_up, ms_default=info.ms_default,
-                    ms_tuned=info.ms_tuned)
+                    overlap=info.overlap, fuse_up=info.fuse_up, leaf_kind=info.leaf_kind, nj_leaf=info.nj_leaf,
+                    ms_default=info.ms_default, ms_tuned=info.ms_tuned)
+
+    _SHAPES = ("nj_transfer", "nj_coupling", "np_leaf", "overlap", "fuse_up", "leaf_kind", "nj_leaf")
+
+    def set_tune(self, m: int, **shapes) -> None:
+        """Store tile shapes for m's column-count entry without timing (h2x_mat_set_tune);
+        fields not given are 0 (the built-in rule)."""
+        bad = set(shapes) - set(self._SHAPES)
+        if bad:
+            raise ValueError(f"unknown shape fields {sorted(bad)}")
+        info = _TuneInfo(**{k: int(v) for k, v in shapes.items()})
+        _check(load_library().h2x_mat_set_tune(self._h, int(m), C.byref(info)), "h2x_mat_set_tune")
+
+    def get_tune(self, m: int) -> dict:
+        """The tile shapes stored for m's column-count entry (h2x_mat_get_tune)."""
+        info = _TuneInfo()
+        _check(load_library().h2x_mat_get_tune(self._h, int(m), C.byref(info)), "h2x_mat_get_tune")
+        return {k: getattr(info, k) for k in self._SHAPES}
 
     def product_times(self, cands, reps: int = 5) -> list:
         """Mean time (ms) of one product for each column count in cands (h2x_product_times):

@@ -489,6 +489,40 @@ h2x_status h2x_mat_autotune(h2x_mat *A, int64_t m, void *dev_ws, size_t ws_bytes
     return run_autotune(A->dm, m, (char *)dev_ws, ws_bytes, (hipStream_t)hip_stream, info);
 }
 
+h2x_status h2x_mat_set_tune(h2x_mat *A, int64_t m, const h2x_tune_info *cfg) {
+    if (!A || !cfg) return fail(H2X_EINVAL, "h2x_mat_set_tune: NULL argument");
+    if (m < 1) return fail(H2X_EINVAL, "h2x_mat_set_tune: need m >= 1");
+    auto in = [](int32_t v, int32_t hi) { return v >= 0 && v <= hi; };
+    if (!in(cfg->nj_transfer, 4) || !in(cfg->nj_coupling, 4) || !in(cfg->nj_leaf, 4) || !in(cfg->np_leaf, 2) ||
+        !in(cfg->overlap, 4) || !in(cfg->fuse_up, 2) || !in(cfg->leaf_kind, 2))
+        return fail(H2X_EINVAL, "h2x_mat_set_tune: a shape field is out of range");
+    TuneCfg c{};
+    c.nj_transfer = (int8_t)cfg->nj_transfer;
+    c.nj_coupling = (int8_t)cfg->nj_coupling;
+    c.np_leaf = (int8_t)cfg->np_leaf;
+    c.overlap = (int8_t)cfg->overlap;
+    c.fuse_up = (int8_t)cfg->fuse_up;
+    c.leaf_kind = (int8_t)cfg->leaf_kind;
+    c.nj_leaf = (int8_t)cfg->nj_leaf;
+    A->dm.tuned[tune_bucket(m)] = c;
+    return H2X_OK;
+}
+
+h2x_status h2x_mat_get_tune(const h2x_mat *A, int64_t m, h2x_tune_info *cfg) {
+    if (!A || !cfg) return fail(H2X_EINVAL, "h2x_mat_get_tune: NULL argument");
+    if (m < 1) return fail(H2X_EINVAL, "h2x_mat_get_tune: need m >= 1");
+    const TuneCfg &c = A->dm.tuned[tune_bucket(m)];
+    *cfg = h2x_tune_info{};
+    cfg->nj_transfer = c.nj_transfer;
+    cfg->nj_coupling = c.nj_coupling;
+    cfg->np_leaf = c.np_leaf;
+    cfg->overlap = c.overlap;
+    cfg->fuse_up = c.fuse_up;
+    cfg->leaf_kind = c.leaf_kind;
+    cfg->nj_leaf = c.nj_leaf;
+    return H2X_OK;
+}
+
 h2x_status h2x_batch_create(const h2x_mat *const *mats, int32_t count, h2x_batch **out) {
     for (int32_t i = 0; mats && i < count; ++i)
         if (h2x_status r = refuse_complex(mats[i], "h2x_batch_create")) return r;

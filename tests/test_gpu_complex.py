@@ -71,6 +71,26 @@ def test_complex_product_matches_oracle(name, pts, prm, kappa, m):
     assert err <= 1e-12 and err_ab <= 1e-12 and lin <= 1e-14
 
 
+@pytest.mark.parametrize("name,pts,prm,kappa,m", CASES[:2], ids=[c[0] for c in CASES[:2]])
+def test_complex_row_split_leaf_stage(name, pts, prm, kappa, m):
+    """The row-split leaf stage (leaf_kind 2) on the complex operator: each near block's
+    imaginary plane applied to J X while X is staged."""
+    h2x = _h2x()
+    P = pts()
+    n = P.shape[0]
+    kw = dict(kernel="helmholtz", ell=kappa, shift=1.0, eta=1.0, **prm)
+    o = oracle.OracleH2(P, **kw)
+    A = h2x.H2Matrix(P, **kw)
+    X = _cplx(n, m, 134)
+    ref = o.matmul_complex(X)
+    errs = []
+    for nj in (1, 2, 3, 4):
+        A.set_tune(2 * m, leaf_kind=2, nj_leaf=nj)
+        errs.append(_colrel(h2x.h2_matmul(A, _dev(X)).cpu().numpy(), ref))
+    print(f"{name}: row-split leaf stage {max(errs):.2e}")
+    assert max(errs) <= 1e-12
+
+
 @pytest.fixture(scope="module")
 def helm():
     h2x = _h2x()

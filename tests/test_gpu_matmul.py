@@ -73,6 +73,57 @@ def test_matmul_matches_oracle(name, pts, prm, m):
     assert err <= TOL
 
 
+ROWS = [c for c in CASES if c[0] in ("small-k27-m37", "sphere-k64-m32", "cube-k64-m5", "cube-k8-leaf100",
+                                      "line-k27", "cube-k64-m64", "sphere-k64-m100", "sphere-k64-leaf150-m17")]
+
+
+@pytest.mark.parametrize("name,pts,prm,m", ROWS, ids=[c[0] for c in ROWS])
+def test_row_split_leaf_stage_matches_oracle(name, pts, prm, m):
+    """The row-split leaf stage (leaf_kind 2, 16 * nj_leaf columns per work-group, leaves
+    above 64 points in 64-row chunks), alone and with the near field on the second
+    stream, against the oracle; alpha / beta in original and in tree order."""
+    h2x = _h2x()
+    P = pts()
+    o, A = _pair(P, **prm)
+    n = P.shape[0]
+    X = W.rhs(n, m, 190 + m)
+    ref = o.matmul(X)
+    errs = []
+    for nj in (1, 2, 3, 4):
+        for ov in (2, 1):
+            A.set_tune(m, leaf_kind=2, nj_leaf=nj, overlap=ov)
+            assert A.get_tune(m)["nj_leaf"] == nj
+            errs.append(_colrel(_gpu(A, X), ref))
+    Y0 = W.rhs(n, m, 191)
+    A.set_tune(m, leaf_kind=2, nj_leaf=2)
+    err_ab = _colrel(_gpu(A, X, alpha=0.75, beta=-1.5, out=Y0), 0.75 * ref - 1.5 * Y0)
+    perm = A.plan.perm()
+    got_t = _gpu(A, X[perm], alpha=2.0, tree_order=True)
+    err_t = _colrel(got_t, 2.0 * ref[perm])
+    A.set_tune(m)
+    print(f"{name}: row-split leaf stage max col rel err {max(errs):.3e}, alpha/beta {err_ab:.3e}, "
+          f"tree order {err_t:.3e}")
+    assert max(errs) <= TOL and err_ab <= TOL and err_t <= TOL
+
+
+def test_set_get_tune():
+    h2x = _h2x()
+    A = h2x.H2Matrix(W.sphere_points(2000, 192), ell=0.5, shift=1.0, eta=1.0, leaf=64, p=4)
+    assert all(v == 0 for v in A.get_tune(20).values())
+    A.set_tune(20, nj_coupling=2, leaf_kind=2, nj_leaf=3, overlap=1)
+    # one entry per ceil(m / 16): 17..32 share it, 16 and 33 do not
+    assert A.get_tune(17) == A.get_tune(32) == dict(nj_transfer=0, nj_coupling=2, np_leaf=0, overlap=1, fuse_up=0,
+                                                    leaf_kind=2, nj_leaf=3)
+    assert A.get_tune(16)["leaf_kind"] == 0 and A.get_tune(33)["leaf_kind"] == 0
+    for bad in (dict(nj_leaf=5), dict(leaf_kind=3), dict(np_leaf=-1), dict(overlap=5), dict(fuse_up=3)):
+        with pytest.raises(h2x.H2xError, match="out of range"):
+            A.set_tune(20, **bad)
+    with pytest.raises(ValueError):
+        A.set_tune(20, nj_foo=1)
+    A.set_tune(20)
+    assert all(v == 0 for v in A.get_tune(20).values())
+
+
 def test_polynomial_kernel_equals_dense():
     P = W.sphere_points(3000, 86)
     h2x = _h2x()
@@ -154,7 +205,10 @@ def test_invalid_arguments_on_gpu():
 def test_autotune_keeps_results(storage, m):
     """Autotuned tile shapes change only the work distribution (fixed summation order
     per element); turning the concurrent near field on or off changes only whether
-    the near and basis terms reach Y in one step or two."""
+    the near and basis terms reach Y in one step or two, and the leaf stage's
+    wave-per-term form (leaf_kind 1) sums each wave's share of the terms before
+    adding the shares, where the built-in row-split form sums the terms in order:
+    both are rounding-level changes."""
     h2x = _h2x()
     P = W.sphere_points(8000, 121)
     A = h2x.H2Matrix(P, storage=storage, ell=0.5, shift=1.0, eta=1.0, leaf=64, p=4)
@@ -165,8 +219,8 @@ def test_autotune_keeps_results(storage, m):
     torch.cuda.synchronize()
     print(f"{storage} m={m}: {info}")
     assert info["ms_tuned"] <= info["ms_default"] * 1.0001
-    if info["overlap"] in (0, 2) or storage != "f64":
+    if (info["overlap"] in (0, 2) and info["leaf_kind"] != 2) or storage != "f64":
         assert torch.equal(before, after)
     else:
         rel = ((after - before).norm(dim=0) / before.norm(dim=0)).max().item()
-        assert rel <= 1e-15
+        assert rel <= 1e-14

@@ -366,10 +366,10 @@ typedef struct {
                           with its grid capped at 256 (1), 128 (3) or 512 (4) work-groups */
     int32_t fuse_up;   /* forward leaf and upward pass in one launch: 1 on; 0 (built-in
                           rule) and 2 level by level                                   */
-    int32_t leaf_kind; /* leaf stage: 0 built-in rule (= 1); 1 each wave a full 64-row
-                          tile of its share of the terms (32 * np_leaf columns); 2 rows
-                          split over the waves, every term shared (16 * nj_leaf columns) */
-    int32_t nj_leaf;   /* 16-column tiles per work-group of the row-split leaf stage   */
+    int32_t leaf_kind; /* leaf stage (32 * np_leaf columns per wave): 0 built-in rule
+                          (= 1); 1 a work-group per leaf, each wave a 64-row tile of its
+                          share of the terms; 2 a wave per 32-row band of a leaf, every
+                          term in turn                                                  */
     double ms_default; /* product time with the built-in rule */
     double ms_tuned;   /* product time with the chosen shapes */
 } h2x_tune_info;
@@ -389,8 +389,8 @@ h2x_status h2x_mat_autotune(h2x_mat *A, int64_t m, void *dev_ws, size_t ws_bytes
  * ceil(m / 16), counts above 64 sharing one): a choice kept from an earlier autotune
  * run, or a fixed shape, without timing.  Set: the shape fields of cfg are used
  * (ms_default / ms_tuned ignored); all zero restores the built-in rule; ranges
- * nj_transfer, nj_coupling, nj_leaf 0..4, np_leaf 0..2, overlap 0..4, fuse_up 0..2,
- * leaf_kind 0..2, else H2X_EINVAL.  Get: ms_default = ms_tuned = 0.  Host only; must
+ * nj_transfer, nj_coupling 0..4, np_leaf 0..2, overlap 0..4, fuse_up 0..2, leaf_kind
+ * 0..2, else H2X_EINVAL.  Get: ms_default = ms_tuned = 0.  Host only; must
  * not run concurrently with products on the same operator. */
 h2x_status h2x_mat_set_tune(h2x_mat *A, int64_t m, const h2x_tune_info *cfg);
 h2x_status h2x_mat_get_tune(const h2x_mat *A, int64_t m, h2x_tune_info *cfg);

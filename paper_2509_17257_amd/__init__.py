@@ -68,7 +68,7 @@ class _GmresInfo(C.Structure):
 
 class _TuneInfo(C.Structure):
     _fields_ = [("nj_transfer", C.c_int32), ("nj_coupling", C.c_int32), ("np_leaf", C.c_int32),
-                ("overlap", C.c_int32), ("fuse_up", C.c_int32), ("leaf_kind", C.c_int32), ("nj_leaf", C.c_int32),
+                ("overlap", C.c_int32), ("fuse_up", C.c_int32), ("leaf_kind", C.c_int32),
                 ("ms_default", C.c_double), ("ms_tuned", C.c_double)]
 
 
@@ -287,10 +287,10 @@ class H2Matrix:
         _check(lib.h2x_mat_autotune(self._h, int(m), C.c_void_p(ws.data_ptr()), ws.numel(),
                                     _stream(torch, self.device), C.byref(info)), "h2x_mat_autotune")
         return dict(nj_transfer=info.nj_transfer, nj_coupling=info.nj_coupling, np_leaf=info.np_leaf,
-                    overlap=info.overlap, fuse_up=info.fuse_up, leaf_kind=info.leaf_kind, nj_leaf=info.nj_leaf,
+                    overlap=info.overlap, fuse_up=info.fuse_up, leaf_kind=info.leaf_kind,
                     ms_default=info.ms_default, ms_tuned=info.ms_tuned)
 
-    _SHAPES = ("nj_transfer", "nj_coupling", "np_leaf", "overlap", "fuse_up", "leaf_kind", "nj_leaf")
+    _SHAPES = ("nj_transfer", "nj_coupling", "np_leaf", "overlap", "fuse_up", "leaf_kind")
 
     def set_tune(self, m: int, **shapes) -> None:
         """Store tile shapes for m's column-count entry without timing (h2x_mat_set_tune);

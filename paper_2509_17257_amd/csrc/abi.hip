@@ -493,7 +493,7 @@ h2x_status h2x_mat_set_tune(h2x_mat *A, int64_t m, const h2x_tune_info *cfg) {
     if (!A || !cfg) return fail(H2X_EINVAL, "h2x_mat_set_tune: NULL argument");
     if (m < 1) return fail(H2X_EINVAL, "h2x_mat_set_tune: need m >= 1");
     auto in = [](int32_t v, int32_t hi) { return v >= 0 && v <= hi; };
-    if (!in(cfg->nj_transfer, 4) || !in(cfg->nj_coupling, 4) || !in(cfg->nj_leaf, 4) || !in(cfg->np_leaf, 2) ||
+    if (!in(cfg->nj_transfer, 4) || !in(cfg->nj_coupling, 4) || !in(cfg->np_leaf, 2) ||
         !in(cfg->overlap, 4) || !in(cfg->fuse_up, 2) || !in(cfg->leaf_kind, 2))
         return fail(H2X_EINVAL, "h2x_mat_set_tune: a shape field is out of range");
     TuneCfg c{};
@@ -503,7 +503,6 @@ h2x_status h2x_mat_set_tune(h2x_mat *A, int64_t m, const h2x_tune_info *cfg) {
     c.overlap = (int8_t)cfg->overlap;
     c.fuse_up = (int8_t)cfg->fuse_up;
     c.leaf_kind = (int8_t)cfg->leaf_kind;
-    c.nj_leaf = (int8_t)cfg->nj_leaf;
     A->dm.tuned[tune_bucket(m)] = c;
     return H2X_OK;
 }
@@ -519,7 +518,6 @@ h2x_status h2x_mat_get_tune(const h2x_mat *A, int64_t m, h2x_tune_info *cfg) {
     cfg->overlap = c.overlap;
     cfg->fuse_up = c.fuse_up;
     cfg->leaf_kind = c.leaf_kind;
-    cfg->nj_leaf = c.nj_leaf;
     return H2X_OK;
 }
 

@@ -27,7 +27,6 @@ struct TuneCfg {
                              // the coupling: 0 (built-in rule) and 2 off; on with a grid
                              // of 256 (1), 128 (3) or 512 (4) work-groups
     int8_t leaf_kind = 0;    // leaf stage: 0 built-in rule (= 1), 1 wave-per-term tiles, 2 rows split over waves
-    int8_t nj_leaf = 0;      // 16-column tiles per work-group of the row-split leaf stage
 };
 constexpr int kTuneBuckets = 5;
 inline int tune_bucket(int64_t m) { return (int)std::min<int64_t>(kTuneBuckets - 1, (m + 15) / 16 - 1); }

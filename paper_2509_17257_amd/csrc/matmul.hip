@@ -322,23 +322,19 @@ void matmul_mfma_f64(const DevMat &dm, const TuneCfg &cfg, int64_t m, double alp
     const unsigned gl = (unsigned)((m + 32 * NP - 1) / (32 * NP));
     // leaf stage: a 64-row tile per wave and term (built-in) or the rows split over the waves
     const bool rows = cfg.leaf_kind == 2;
-    const int njl = cfg.nj_leaf ? cfg.nj_leaf : (int)std::min<int64_t>(4, (m + 15) / 16);
     auto leaf = [&](hipStream_t s, double b, int basis, int near, unsigned cap) {
         if (rows) {
-            const unsigned gx = 8 * ((dm.L + 7) / 8) * (unsigned)((m + 16 * njl - 1) / (16 * njl));
-            auto go = [&](auto NJc) {
-                constexpr int NJL = decltype(NJc)::value;
-                hipLaunchKernelGGL(mfma::k_leaf_rows<NJL>, dim3(gx), dim3(256), 0, s, dm.k, m, dm.L, dm.leaves,
-                                   dm.first, dm.size, dm.perm, (const double *)dm.Vt, dm.vt_off, yh, ldh,
-                                   dm.near_ptr, dm.near_col, dm.near_off, (const double *)dm.N, Xt, ldxt, alpha, b,
-                                   Y, ldy, to, basis, near, sk, dm.n_plane);
-            };
-            switch (njl) {
-                case 1: go(std::integral_constant<int, 1>{}); break;
-                case 2: go(std::integral_constant<int, 2>{}); break;
-                case 3: go(std::integral_constant<int, 3>{}); break;
-                default: go(std::integral_constant<int, 4>{}); break;
-            }
+            const dim3 grid(8 * ((dm.L + 7) / 8) * gl, 2);
+            if (NP == 2)
+                hipLaunchKernelGGL(mfma::k_leaf_rows<2>, grid, dim3(64), 0, s, dm.k, m, dm.L, dm.leaves, dm.first,
+                                   dm.size, dm.perm, (const double *)dm.Vt, dm.vt_off, yh, ldh, dm.near_ptr,
+                                   dm.near_col, dm.near_off, (const double *)dm.N, Xt, ldxt, alpha, b, Y, ldy, to,
+                                   basis, near, sk, dm.n_plane);
+            else
+                hipLaunchKernelGGL(mfma::k_leaf_rows<1>, grid, dim3(64), 0, s, dm.k, m, dm.L, dm.leaves, dm.first,
+                                   dm.size, dm.perm, (const double *)dm.Vt, dm.vt_off, yh, ldh, dm.near_ptr,
+                                   dm.near_col, dm.near_off, (const double *)dm.N, Xt, ldxt, alpha, b, Y, ldy, to,
+                                   basis, near, sk, dm.n_plane);
             return;
         }
         unsigned gx = 8 * ((dm.L + 7) / 8) * gl;

@@ -4,8 +4,8 @@
 // choice in the operator's table for m's bucket; later products with a column
 // count in that bucket use it.  Candidates: 16-column tiles per work-group of
 // the forward leaf and transfer passes (1 .. ceil(m / 16), at most 4), of the
-// coupling (same range), the leaf stage (a 64-row tile per wave and term with 1 or 2
-// 32-column tiles, or the rows split over the waves with 1 .. 4 16-column tiles),
+// coupling (same range), the leaf stage (a 64-row tile per wave and term, or a wave
+// per 32-row band, with 1 or 2 32-column tiles),
 // and whether the near field runs on a second stream concurrently with the transfer
 // passes.
 #include <cmath>
@@ -98,34 +98,21 @@ h2x_status run_autotune(DevMat &dm, int64_t m, char *ws, size_t ws_bytes, hipStr
             best.nj_coupling = (int8_t)nj;
         }
     }
-    // leaf stage: a 64-row tile per wave and term (32 * np columns), or the rows split
-    // over the waves (16 * nj columns); the FP64 matrix-core path has both
-    for (int np = 1; np <= (m > 32 ? 2 : 1) && e == hipSuccess; ++np) {
-        double s[5];
-        TuneCfg c{};
-        c.np_leaf = (int8_t)np;
-        c.leaf_kind = 1;
-        e = time_cfg(c, s);
-        if (e == hipSuccess && s[4] < best_l) {
-            best_l = s[4];
-            best.np_leaf = (int8_t)np;
-            best.leaf_kind = 1;
-            best.nj_leaf = 0;
+    // leaf stage: a 64-row tile per wave and term, or a wave per 32-row band (the FP64
+    // matrix-core path has both), with 32 * np columns per wave
+    for (int kind = 1; kind <= (dm.mc ? 2 : 1) && e == hipSuccess; ++kind)
+        for (int np = 1; np <= (m > 32 ? 2 : 1) && e == hipSuccess; ++np) {
+            double s[5];
+            TuneCfg c{};
+            c.np_leaf = (int8_t)np;
+            c.leaf_kind = (int8_t)kind;
+            e = time_cfg(c, s);
+            if (e == hipSuccess && s[4] < best_l) {
+                best_l = s[4];
+                best.np_leaf = (int8_t)np;
+                best.leaf_kind = (int8_t)kind;
+            }
         }
-    }
-    for (int nj = 1; dm.mc && nj <= max_nj && e == hipSuccess; ++nj) {
-        double s[5];
-        TuneCfg c{};
-        c.leaf_kind = 2;
-        c.nj_leaf = (int8_t)nj;
-        e = time_cfg(c, s);
-        if (e == hipSuccess && s[4] < best_l) {
-            best_l = s[4];
-            best.np_leaf = 0;
-            best.leaf_kind = 2;
-            best.nj_leaf = (int8_t)nj;
-        }
-    }
     if (e != hipSuccess) return done(e);
     // forward leaf and upward pass fused into one launch or level by level
     if (dm.mc) {
@@ -167,7 +154,6 @@ h2x_status run_autotune(DevMat &dm, int64_t m, char *ws, size_t ws_bytes, hipStr
         info->overlap = dm.tuned[b].overlap;
         info->fuse_up = dm.tuned[b].fuse_up;
         info->leaf_kind = dm.tuned[b].leaf_kind;
-        info->nj_leaf = dm.tuned[b].nj_leaf;
         info->ms_default = total(s0);
         info->ms_tuned = use ? total(s1) : total(s0);
     }

@@ -84,8 +84,8 @@ def test_complex_row_split_leaf_stage(name, pts, prm, kappa, m):
     X = _cplx(n, m, 134)
     ref = o.matmul_complex(X)
     errs = []
-    for nj in (1, 2, 3, 4):
-        A.set_tune(2 * m, leaf_kind=2, nj_leaf=nj)
+    for npl in (1, 2):
+        A.set_tune(2 * m, leaf_kind=2, np_leaf=npl)
         errs.append(_colrel(h2x.h2_matmul(A, _dev(X)).cpu().numpy(), ref))
     print(f"{name}: row-split leaf stage {max(errs):.2e}")
     assert max(errs) <= 1e-12

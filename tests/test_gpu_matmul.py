@@ -79,9 +79,10 @@ ROWS = [c for c in CASES if c[0] in ("small-k27-m37", "sphere-k64-m32", "cube-k6
 
 @pytest.mark.parametrize("name,pts,prm,m", ROWS, ids=[c[0] for c in ROWS])
 def test_row_split_leaf_stage_matches_oracle(name, pts, prm, m):
-    """The row-split leaf stage (leaf_kind 2, 16 * nj_leaf columns per work-group, leaves
-    above 64 points in 64-row chunks), alone and with the near field on the second
-    stream, against the oracle; alpha / beta in original and in tree order."""
+    """The row-split leaf stage (leaf_kind 2: a wave per 32-row band of a leaf, 32 * np_leaf
+    columns, leaves above 64 points in several bands per wave), alone and with the near
+    field on the second stream, against the oracle; alpha / beta in original and in
+    tree order."""
     h2x = _h2x()
     P = pts()
     o, A = _pair(P, **prm)
@@ -89,13 +90,13 @@ def test_row_split_leaf_stage_matches_oracle(name, pts, prm, m):
     X = W.rhs(n, m, 190 + m)
     ref = o.matmul(X)
     errs = []
-    for nj in (1, 2, 3, 4):
+    for npl in (1, 2):
         for ov in (2, 1):
-            A.set_tune(m, leaf_kind=2, nj_leaf=nj, overlap=ov)
-            assert A.get_tune(m)["nj_leaf"] == nj
+            A.set_tune(m, leaf_kind=2, np_leaf=npl, overlap=ov)
+            assert A.get_tune(m)["np_leaf"] == npl
             errs.append(_colrel(_gpu(A, X), ref))
     Y0 = W.rhs(n, m, 191)
-    A.set_tune(m, leaf_kind=2, nj_leaf=2)
+    A.set_tune(m, leaf_kind=2)
     err_ab = _colrel(_gpu(A, X, alpha=0.75, beta=-1.5, out=Y0), 0.75 * ref - 1.5 * Y0)
     perm = A.plan.perm()
     got_t = _gpu(A, X[perm], alpha=2.0, tree_order=True)
@@ -110,12 +111,12 @@ def test_set_get_tune():
     h2x = _h2x()
     A = h2x.H2Matrix(W.sphere_points(2000, 192), ell=0.5, shift=1.0, eta=1.0, leaf=64, p=4)
     assert all(v == 0 for v in A.get_tune(20).values())
-    A.set_tune(20, nj_coupling=2, leaf_kind=2, nj_leaf=3, overlap=1)
+    A.set_tune(20, nj_coupling=2, leaf_kind=2, np_leaf=1, overlap=1)
     # one entry per ceil(m / 16): 17..32 share it, 16 and 33 do not
-    assert A.get_tune(17) == A.get_tune(32) == dict(nj_transfer=0, nj_coupling=2, np_leaf=0, overlap=1, fuse_up=0,
-                                                    leaf_kind=2, nj_leaf=3)
+    assert A.get_tune(17) == A.get_tune(32) == dict(nj_transfer=0, nj_coupling=2, np_leaf=1, overlap=1, fuse_up=0,
+                                                    leaf_kind=2)
     assert A.get_tune(16)["leaf_kind"] == 0 and A.get_tune(33)["leaf_kind"] == 0
-    for bad in (dict(nj_leaf=5), dict(leaf_kind=3), dict(np_leaf=-1), dict(overlap=5), dict(fuse_up=3)):
+    for bad in (dict(nj_coupling=5), dict(leaf_kind=3), dict(np_leaf=-1), dict(overlap=5), dict(fuse_up=3)):
         with pytest.raises(h2x.H2xError, match="out of range"):
             A.set_tune(20, **bad)
     with pytest.raises(ValueError):

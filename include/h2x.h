@@ -85,6 +85,10 @@ typedef struct {
     int32_t depth, k;
     int64_t bytes_operator[3]; /* V + E + S bytes per h2x_prec, near field excluded */
     int64_t bytes_near;        /* near-field bytes at FP64                          */
+    int32_t adm_depth;         /* shallowest depth of a cluster in an admissible block */
+    int32_t split_depth;       /* depth that splits the coupling rows into a deep part and
+                                  the rest (tuning option split), 0 when not split     */
+    int64_t deep_blocks;       /* admissible blocks in the rows of the deep part       */
 } h2x_stats;
 
 typedef struct h2x_plan h2x_plan; /* host topology: trees, lists, permutation */
@@ -370,6 +374,12 @@ typedef struct {
                           (= 1); 1 a work-group per leaf, each wave a 64-row tile of its
                           share of the terms; 2 a wave per 32-row band of a leaf, every
                           term in turn                                                  */
+    int32_t split;     /* coupling rows in two parts, the deep part (rows whose lists are
+                          complete once the upward pass has reached a split depth) on a
+                          second stream beside the upper transfer levels, the coupling of
+                          the other rows and the upper downward levels: 0 built-in rule,
+                          1 on (the deep part leaves room on every CU for a work-group
+                          of the transfer passes), 2 off, 3 on without that reserve     */
     double ms_default; /* product time with the built-in rule */
     double ms_tuned;   /* product time with the chosen shapes */
 } h2x_tune_info;
@@ -390,7 +400,7 @@ h2x_status h2x_mat_autotune(h2x_mat *A, int64_t m, void *dev_ws, size_t ws_bytes
  * run, or a fixed shape, without timing.  Set: the shape fields of cfg are used
  * (ms_default / ms_tuned ignored); all zero restores the built-in rule; ranges
  * nj_transfer, nj_coupling 0..4, np_leaf 0..2, overlap 0..4, fuse_up 0..2, leaf_kind
- * 0..2, else H2X_EINVAL.  Get: ms_default = ms_tuned = 0.  Host only; must
+ * 0..2, split 0..3, else H2X_EINVAL.  Get: ms_default = ms_tuned = 0.  Host only; must
  * not run concurrently with products on the same operator. */
 h2x_status h2x_mat_set_tune(h2x_mat *A, int64_t m, const h2x_tune_info *cfg);
 h2x_status h2x_mat_get_tune(const h2x_mat *A, int64_t m, h2x_tune_info *cfg);

@@ -43,7 +43,8 @@ class _Params(C.Structure):
 class _Stats(C.Structure):
     _fields_ = [("n", C.c_int64), ("clusters", C.c_int64), ("leaves", C.c_int64), ("n_adm", C.c_int64),
                 ("n_near", C.c_int64), ("near_entries", C.c_int64), ("depth", C.c_int32), ("k", C.c_int32),
-                ("bytes_operator", C.c_int64 * 3), ("bytes_near", C.c_int64)]
+                ("bytes_operator", C.c_int64 * 3), ("bytes_near", C.c_int64), ("adm_depth", C.c_int32),
+                ("split_depth", C.c_int32), ("deep_blocks", C.c_int64)]
 
 
 class _CgParams(C.Structure):
@@ -68,7 +69,7 @@ class _GmresInfo(C.Structure):
 
 class _TuneInfo(C.Structure):
     _fields_ = [("nj_transfer", C.c_int32), ("nj_coupling", C.c_int32), ("np_leaf", C.c_int32),
-                ("overlap", C.c_int32), ("fuse_up", C.c_int32), ("leaf_kind", C.c_int32),
+                ("overlap", C.c_int32), ("fuse_up", C.c_int32), ("leaf_kind", C.c_int32), ("split", C.c_int32),
                 ("ms_default", C.c_double), ("ms_tuned", C.c_double)]
 
 
@@ -188,6 +189,7 @@ class Plan:
         self.depth, self.k = st.depth, st.k
         self.bytes_operator = list(st.bytes_operator)
         self.bytes_near = st.bytes_near
+        self.adm_depth, self.split_depth, self.deep_blocks = st.adm_depth, st.split_depth, st.deep_blocks
 
     def __del__(self):
         if getattr(self, "_h", None) and _lib is not None:
@@ -287,10 +289,10 @@ class H2Matrix:
         _check(lib.h2x_mat_autotune(self._h, int(m), C.c_void_p(ws.data_ptr()), ws.numel(),
                                     _stream(torch, self.device), C.byref(info)), "h2x_mat_autotune")
         return dict(nj_transfer=info.nj_transfer, nj_coupling=info.nj_coupling, np_leaf=info.np_leaf,
-                    overlap=info.overlap, fuse_up=info.fuse_up, leaf_kind=info.leaf_kind,
+                    overlap=info.overlap, fuse_up=info.fuse_up, leaf_kind=info.leaf_kind, split=info.split,
                     ms_default=info.ms_default, ms_tuned=info.ms_tuned)
 
-    _SHAPES = ("nj_transfer", "nj_coupling", "np_leaf", "overlap", "fuse_up", "leaf_kind")
+    _SHAPES = ("nj_transfer", "nj_coupling", "np_leaf", "overlap", "fuse_up", "leaf_kind", "split")
 
     def set_tune(self, m: int, **shapes) -> None:
         """Store tile shapes for m's column-count entry without timing (h2x_mat_set_tune);

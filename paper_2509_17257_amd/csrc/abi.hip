@@ -131,6 +131,9 @@ h2x_status h2x_plan_stats(const h2x_plan *plan, h2x_stats *out) {
     out->bytes_operator[H2X_F32] = 4 * ent;
     out->bytes_operator[H2X_BF16] = 2 * ent;
     out->bytes_near = 8 * P.near_entries;
+    out->adm_depth = P.adm_depth;
+    out->split_depth = P.split_depth;
+    for (int32_t t : P.cpl_deep) out->deep_blocks += P.adm_ptr[t + 1] - P.adm_ptr[t];
     return H2X_OK;
 }
 
@@ -225,6 +228,8 @@ h2x_status h2x_mat_create(const h2x_plan *plan, h2x_prec storage, void *dev_ws, 
     up(d.adm_col, P.adm_col);
     up(d.adm_row, adm_row);
     up(d.cpl_order, P.cpl_order);
+    up(d.cpl_deep, P.cpl_deep);
+    up(d.cpl_shallow, P.cpl_shallow);
     up(d.near_ptr, P.near_ptr);
     up(d.near_col, P.near_col);
     up(d.near_row, near_row);
@@ -494,7 +499,7 @@ h2x_status h2x_mat_set_tune(h2x_mat *A, int64_t m, const h2x_tune_info *cfg) {
     if (m < 1) return fail(H2X_EINVAL, "h2x_mat_set_tune: need m >= 1");
     auto in = [](int32_t v, int32_t hi) { return v >= 0 && v <= hi; };
     if (!in(cfg->nj_transfer, 4) || !in(cfg->nj_coupling, 4) || !in(cfg->np_leaf, 2) ||
-        !in(cfg->overlap, 4) || !in(cfg->fuse_up, 2) || !in(cfg->leaf_kind, 2))
+        !in(cfg->overlap, 4) || !in(cfg->fuse_up, 2) || !in(cfg->leaf_kind, 2) || !in(cfg->split, 3))
         return fail(H2X_EINVAL, "h2x_mat_set_tune: a shape field is out of range");
     TuneCfg c{};
     c.nj_transfer = (int8_t)cfg->nj_transfer;
@@ -503,6 +508,7 @@ h2x_status h2x_mat_set_tune(h2x_mat *A, int64_t m, const h2x_tune_info *cfg) {
     c.overlap = (int8_t)cfg->overlap;
     c.fuse_up = (int8_t)cfg->fuse_up;
     c.leaf_kind = (int8_t)cfg->leaf_kind;
+    c.split = (int8_t)cfg->split;
     A->dm.tuned[tune_bucket(m)] = c;
     return H2X_OK;
 }
@@ -518,6 +524,7 @@ h2x_status h2x_mat_get_tune(const h2x_mat *A, int64_t m, h2x_tune_info *cfg) {
     cfg->overlap = c.overlap;
     cfg->fuse_up = c.fuse_up;
     cfg->leaf_kind = c.leaf_kind;
+    cfg->split = c.split;
     return H2X_OK;
 }
 

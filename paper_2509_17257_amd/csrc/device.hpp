@@ -27,6 +27,9 @@ struct TuneCfg {
                              // the coupling: 0 (built-in rule) and 2 off; on with a grid
                              // of 256 (1), 128 (3) or 512 (4) work-groups
     int8_t leaf_kind = 0;    // leaf stage: 0 built-in rule (= 1), 1 wave-per-term tiles, 2 rows split over waves
+    int8_t split = 0;        // coupling of the deep rows on the second stream beside the upper
+                             // transfer levels: 0 built-in rule, 1 on (leaving room on every
+                             // CU for a transfer work-group), 2 off, 3 on without the reserve
 };
 constexpr int kTuneBuckets = 5;
 inline int tune_bucket(int64_t m) { return (int)std::min<int64_t>(kTuneBuckets - 1, (m + 15) / 16 - 1); }
@@ -54,6 +57,8 @@ struct DevMat {
     int32_t *adm_col = nullptr;  // n_adm
     int32_t *adm_row = nullptr;  // n_adm (row cluster of each block)
     int32_t *cpl_order = nullptr;  // C, launch order of the coupling rows
+    int32_t *cpl_deep = nullptr, *cpl_shallow = nullptr;  // the same rows in two parts
+    int32_t n_deep = 0, n_shallow = 0, split_depth = 0;   // (split_depth 0: no split)
     int64_t *near_ptr = nullptr; // L + 1
     int32_t *near_col = nullptr; // n_near
     int32_t *near_row = nullptr; // n_near (row leaf cluster)

@@ -271,6 +271,11 @@ size_t mat_layout(const Plan &P, h2x_prec storage, DevMat *dm, char *base) {
     d.adm_col = carve<int32_t>(cur, base, na + 1);
     d.adm_row = carve<int32_t>(cur, base, na + 1);
     d.cpl_order = carve<int32_t>(cur, base, C);
+    d.split_depth = P.split_depth;
+    d.n_deep = (int32_t)P.cpl_deep.size();
+    d.n_shallow = (int32_t)P.cpl_shallow.size();
+    d.cpl_deep = carve<int32_t>(cur, base, d.n_deep + 1);
+    d.cpl_shallow = carve<int32_t>(cur, base, d.n_shallow + 1);
     d.near_ptr = carve<int64_t>(cur, base, L + 1);
     d.near_col = carve<int32_t>(cur, base, nn + 1);
     d.near_row = carve<int32_t>(cur, base, nn + 1);

@@ -362,6 +362,60 @@ void matmul_mfma_f64(const DevMat &dm, const TuneCfg &cfg, int64_t m, double alp
         leaf(dm.side, beta, 0, 1, cap);
         (void)hipEventRecord(dm.ev_join, dm.side);
     }
+    // coupling of the deep rows on the second stream beside the upper transfer levels, the
+    // coupling of the other rows and the upper downward levels (not with per-stage timing,
+    // the concurrent near field or the fused upward pass)
+    const bool split = (cfg.split == 1 || cfg.split == 3) && dm.split_depth > 0 && dm.side && !ov && !ev &&
+                       cfg.fuse_up != 1;
+    auto up_levels = [&](int dhi, int dlo) {  // upward levels dhi down to dlo
+        for (int d = dhi; d >= dlo; --d) {
+            const int32_t b = P.lvl_inner_ptr[d], e = P.lvl_inner_ptr[d + 1];
+            if (e > b)
+                hipLaunchKernelGGL(mfma::k_up<NJ>, dim3(e - b, gy), dim3(256), 0, st, dm.k, m, dm.lvl_inner + b,
+                                   dm.up_son + 2 * b, E, xh, ldh, sk);
+        }
+    };
+    auto down_levels = [&](int dlo, int dhi) {  // downward levels (son depths) dlo up to dhi
+        for (int d = dlo; d <= dhi; ++d) {
+            const int32_t b = P.lvl_ptr[d], e = P.lvl_ptr[d + 1];
+            if (e > b)
+                hipLaunchKernelGGL(mfma::k_down<NJ>, dim3(e - b, gy), dim3(256), 0, st, dm.k, m, dm.lvl_all + b,
+                                   dm.dn_par + b, E, yh, ldh, sk);
+        }
+    };
+    // complex operator: y-hat += S_im (J x-hat), so that y-hat = (S_re + i S_im) x-hat per complex column
+    auto coupling = [&](hipStream_t s, int32_t nrows, const int32_t *rows, size_t keep) {
+        launch_coupling_fast<double, double>(dm, m, xh, yh, ldh, s, sk, cfg.nj_coupling, 0, nrows, rows, keep);
+        if (dm.cplx)
+            launch_coupling_fast<double, double>(dm, m, xh, yh, ldh, s, sk, cfg.nj_coupling, 1, nrows, rows, keep);
+    };
+    const int dlo = std::max(1, P.adm_depth + 1);
+    if (split) {
+        hipLaunchKernelGGL(mfma::k_fwd_leaf<NJ>, dim3(dm.L, gy), dim3(256), 0, st, dm.k, m, dm.leaves, dm.first,
+                           dm.size, dm.perm, V, Xt, ldxt, 1, xh, ldh, sk);
+        const int D = dm.split_depth;
+        up_levels(dm.depth_max - 1, D);
+        (void)hipEventRecord(dm.ev_fork, st);
+        (void)hipStreamWaitEvent(dm.side, dm.ev_fork, 0);
+        // split 1: the deep coupling leaves room on every CU for a work-group of the transfer
+        // passes (their LDS); split 3: no reserve
+        size_t keep = 0;
+        if (cfg.split == 1) {
+            hipFuncAttributes a{}, b{};
+            if (hipFuncGetAttributes(&a, (const void *)mfma::k_up<NJ>) == hipSuccess &&
+                hipFuncGetAttributes(&b, (const void *)mfma::k_down<NJ>) == hipSuccess)
+                keep = std::max(a.sharedSizeBytes, b.sharedSizeBytes);
+        }
+        coupling(dm.side, dm.n_deep, dm.cpl_deep, keep);
+        (void)hipEventRecord(dm.ev_join, dm.side);
+        up_levels(D - 1, P.adm_depth);
+        coupling(st, dm.n_shallow, dm.cpl_shallow, 0);
+        down_levels(dlo, D - 1);
+        (void)hipStreamWaitEvent(st, dm.ev_join, 0);
+        down_levels(std::max(dlo, D), dm.depth_max);
+        leaf(st, beta, 1, 1, 0);
+        return;
+    }
     if (cfg.fuse_up == 1) {
         // one launch: leaves, then each parent by the work-group that finishes its second son
         // (slower than level-by-level launches on this chip: every device-scope fence writes
@@ -377,24 +431,12 @@ void matmul_mfma_f64(const DevMat &dm, const TuneCfg &cfg, int64_t m, double alp
         hipLaunchKernelGGL(mfma::k_fwd_leaf<NJ>, dim3(dm.L, gy), dim3(256), 0, st, dm.k, m, dm.leaves, dm.first,
                            dm.size, dm.perm, V, Xt, ldxt, 1, xh, ldh, sk);
         mark(1);
-        for (int d = dm.depth_max - 1; d >= P.adm_depth; --d) {
-            const int32_t b = P.lvl_inner_ptr[d], e = P.lvl_inner_ptr[d + 1];
-            if (e > b)
-                hipLaunchKernelGGL(mfma::k_up<NJ>, dim3(e - b, gy), dim3(256), 0, st, dm.k, m, dm.lvl_inner + b,
-                                   dm.up_son + 2 * b, E, xh, ldh, sk);
-        }
+        up_levels(dm.depth_max - 1, P.adm_depth);
     }
     mark(2);
-    launch_coupling_fast<double, double>(dm, m, xh, yh, ldh, st, sk, cfg.nj_coupling);
-    // complex operator: y-hat += S_im (J x-hat), so that y-hat = (S_re + i S_im) x-hat per complex column
-    if (dm.cplx) launch_coupling_fast<double, double>(dm, m, xh, yh, ldh, st, sk, cfg.nj_coupling, 1);
+    coupling(st, -1, nullptr, 0);
     mark(3);
-    for (int d = std::max(1, P.adm_depth + 1); d <= dm.depth_max; ++d) {
-        const int32_t b = P.lvl_ptr[d], e = P.lvl_ptr[d + 1];
-        if (e > b)
-            hipLaunchKernelGGL(mfma::k_down<NJ>, dim3(e - b, gy), dim3(256), 0, st, dm.k, m, dm.lvl_all + b,
-                               dm.dn_par + b, E, yh, ldh, sk);
-    }
+    down_levels(dlo, dm.depth_max);
     mark(4);
     // Y = beta Y + alpha (V y-hat + N X)
     if (ov) {

@@ -267,22 +267,27 @@ __global__ __launch_bounds__(128) void k_coupling_mfma_small(int k, int64_t m, i
 // it; returns false (launching nothing) otherwise.
 template <typename T, typename Acc>
 bool launch_coupling_fast(const DevMat &dm, int64_t m, const Acc *xh, Acc *yh, int64_t ldh, hipStream_t st,
-                          Skip skip, int nj_force, int jpass = 0) {
+                          Skip skip, int nj_force, int jpass = 0, int32_t nrows = -1, const int32_t *rows = nullptr,
+                          size_t keep_lds = 0) {
     if constexpr (!std::is_same<T, double>::value || !std::is_same<Acc, double>::value) {
         return false;
     } else {
         if (!dm.mc || !dm.cpl_order) return false;
+        // all rows in cpl_order, or the part (nrows, rows) of them
+        const int32_t C = rows ? nrows : dm.C;
+        const int32_t *order = rows ? rows : dm.cpl_order;
+        if (C <= 0) return true;
         const int nj = nj_force ? nj_force : (int)std::min<int64_t>(4, (m + 15) / 16);
         const int mcols = 16 * nj;
-        const int32_t rpx = (dm.C + 7) / 8;
+        const int32_t rpx = (C + 7) / 8;
         const dim3 grid((unsigned)(8 * rpx * ((m + mcols - 1) / mcols)));
         // jpass (complex operator): the imaginary plane of S on J x-hat, added to y-hat
         const double *S = (const double *)dm.S + (jpass ? dm.s_plane : 0);
         if (dm.k <= 32) {
             auto go = [&](auto NJc) {
                 constexpr int NJ = decltype(NJc)::value;
-                hipLaunchKernelGGL(k_coupling_mfma_small<NJ>, grid, dim3(128), 0, st, dm.k, m, dm.C, rpx,
-                                   dm.cpl_order, dm.adm_ptr, dm.adm_col, S, xh, yh, ldh, skip, jpass);
+                hipLaunchKernelGGL(k_coupling_mfma_small<NJ>, grid, dim3(128), 0, st, dm.k, m, C, rpx,
+                                   order, dm.adm_ptr, dm.adm_col, S, xh, yh, ldh, skip, jpass);
             };
             switch (nj) {
                 case 1: go(std::integral_constant<int, 1>{}); break;
@@ -293,23 +298,31 @@ bool launch_coupling_fast(const DevMat &dm, int64_t m, const Acc *xh, Acc *yh, i
             return true;
         }
         if (dm.swz != 1 || dm.k != kMfmaK) return false;
+        // keep_lds > 0: each work-group also takes unused dynamic LDS, so that a CU holds at
+        // most two of them and keep_lds bytes stay free for a work-group of another launch
+        // (the work-groups of a long launch must not take every slot of the chip)
+        auto dyn_lds = [&](const void *fn) -> size_t {
+            if (!keep_lds) return 0;
+            hipFuncAttributes a{};
+            int dev = 0, per_cu = 0;
+            if (hipFuncGetAttributes(&a, fn) != hipSuccess || hipGetDevice(&dev) != hipSuccess ||
+                hipDeviceGetAttribute(&per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) !=
+                    hipSuccess || (size_t)per_cu <= keep_lds)
+                return 0;
+            const size_t target = (((size_t)per_cu - keep_lds) / 2) & ~(size_t)255;
+            return target > a.sharedSizeBytes ? target - a.sharedSizeBytes : 0;
+        };
+        auto go = [&](auto NJc) {
+            constexpr int NJ = decltype(NJc)::value;
+            const size_t dyn = dyn_lds((const void *)k_coupling_mfma_f64<NJ>);
+            hipLaunchKernelGGL(k_coupling_mfma_f64<NJ>, grid, dim3(256), dyn, st, m, C, rpx, order, dm.adm_ptr,
+                               dm.adm_col, S, xh, yh, ldh, skip, jpass);
+        };
         switch (nj) {
-            case 1:
-                hipLaunchKernelGGL(k_coupling_mfma_f64<1>, grid, dim3(256), 0, st, m, dm.C, rpx, dm.cpl_order,
-                                   dm.adm_ptr, dm.adm_col, S, xh, yh, ldh, skip, jpass);
-                break;
-            case 2:
-                hipLaunchKernelGGL(k_coupling_mfma_f64<2>, grid, dim3(256), 0, st, m, dm.C, rpx, dm.cpl_order,
-                                   dm.adm_ptr, dm.adm_col, S, xh, yh, ldh, skip, jpass);
-                break;
-            case 3:
-                hipLaunchKernelGGL(k_coupling_mfma_f64<3>, grid, dim3(256), 0, st, m, dm.C, rpx, dm.cpl_order,
-                                   dm.adm_ptr, dm.adm_col, S, xh, yh, ldh, skip, jpass);
-                break;
-            default:
-                hipLaunchKernelGGL(k_coupling_mfma_f64<4>, grid, dim3(256), 0, st, m, dm.C, rpx, dm.cpl_order,
-                                   dm.adm_ptr, dm.adm_col, S, xh, yh, ldh, skip, jpass);
-                break;
+            case 1: go(std::integral_constant<int, 1>{}); break;
+            case 2: go(std::integral_constant<int, 2>{}); break;
+            case 3: go(std::integral_constant<int, 3>{}); break;
+            default: go(std::integral_constant<int, 4>{}); break;
         }
         return true;
     }

@@ -62,6 +62,13 @@ struct Plan {
     // launch order of the row clusters in the coupling stage: the rows are cut
     // into 8 contiguous eighths (one per XCD), longest list first within each
     std::vector<int32_t> cpl_order; // C
+    // the same rows in two parts, so that the coupling of the deep part can run beside the
+    // upper transfer levels: "deep" rows lie at depth >= split_depth and every inner
+    // cluster of their lists too (their x-hat is complete once the upward pass has done
+    // split_depth); the other rows form the second part.  Each part in the XCD order of
+    // cpl_order.  split_depth 0: no split (too little work in the deep part).
+    int32_t split_depth = 0;
+    std::vector<int32_t> cpl_deep, cpl_shallow;
 
     // independent systems (a merged plan is the block-diagonal union of several
     // cluster trees; a plan from build_plan holds one system).  System i owns

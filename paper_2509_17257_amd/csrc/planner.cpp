@@ -37,18 +37,51 @@ double box_dist(const double *lo_t, const double *hi_t, const double *lo_s, cons
     return std::sqrt(s);
 }
 
-// launch order of the coupling rows: 8 contiguous eighths (one per XCD), longest
-// list first within each
-void coupling_order(Plan &P) {
-    const int32_t C = P.C;
-    const int32_t rpx = (C + 7) / 8;
-    P.cpl_order.resize(C);
-    for (int32_t c = 0; c < C; ++c) P.cpl_order[c] = c;
+// launch order of coupling rows (ascending cluster ids): 8 contiguous eighths (one per
+// XCD), longest list first within each
+void xcd_order(const Plan &P, std::vector<int32_t> &rows) {
+    const int32_t R = (int32_t)rows.size(), rpx = (R + 7) / 8;
     for (int32_t x = 0; x < 8; ++x) {
-        const int32_t lo = std::min(C, x * rpx), hi = std::min(C, (x + 1) * rpx);
-        std::stable_sort(P.cpl_order.begin() + lo, P.cpl_order.begin() + hi, [&](int32_t a, int32_t b) {
+        const int32_t lo = std::min(R, x * rpx), hi = std::min(R, (x + 1) * rpx);
+        std::stable_sort(rows.begin() + lo, rows.begin() + hi, [&](int32_t a, int32_t b) {
             return P.adm_ptr[a + 1] - P.adm_ptr[a] > P.adm_ptr[b + 1] - P.adm_ptr[b];
         });
+    }
+}
+
+void coupling_order(Plan &P) {
+    const int32_t C = P.C;
+    P.cpl_order.resize(C);
+    for (int32_t c = 0; c < C; ++c) P.cpl_order[c] = c;
+    xcd_order(P, P.cpl_order);
+
+    // deep / shallow split: the deepest split depth D whose deep part still holds at least
+    // 60 % of the admissible blocks, so that its coupling outlasts the upper transfer levels,
+    // the coupling of the other rows and the upper downward levels running beside it
+    const int64_t total = P.adm_ptr[C];
+    std::vector<int32_t> ready(C, 1 << 30);  // shallowest inner cluster of the list
+    for (int32_t t = 0; t < C; ++t)
+        for (int64_t b = P.adm_ptr[t]; b < P.adm_ptr[t + 1]; ++b) {
+            const int32_t s = P.adm_col[b];
+            if (P.son0[s] >= 0) ready[t] = std::min(ready[t], P.depth[s]);
+        }
+    auto deep = [&](int32_t t, int32_t D) { return P.depth[t] >= D && ready[t] >= D; };
+    P.split_depth = 0;
+    for (int32_t D = P.depth_max; D > P.adm_depth + 1 && total > 0; --D) {
+        int64_t nb = 0;
+        for (int32_t t = 0; t < C; ++t)
+            if (deep(t, D)) nb += P.adm_ptr[t + 1] - P.adm_ptr[t];
+        if (10 * nb >= 6 * total) {
+            P.split_depth = D;
+            break;
+        }
+    }
+    P.cpl_deep.clear();
+    P.cpl_shallow.clear();
+    if (P.split_depth > 0) {
+        for (int32_t t = 0; t < C; ++t) (deep(t, P.split_depth) ? P.cpl_deep : P.cpl_shallow).push_back(t);
+        xcd_order(P, P.cpl_deep);
+        xcd_order(P, P.cpl_shallow);
     }
 }
 

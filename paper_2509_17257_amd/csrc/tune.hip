@@ -6,8 +6,9 @@
 // the forward leaf and transfer passes (1 .. ceil(m / 16), at most 4), of the
 // coupling (same range), the leaf stage (a 64-row tile per wave and term, or a wave
 // per 32-row band, with 1 or 2 32-column tiles),
-// and whether the near field runs on a second stream concurrently with the transfer
-// passes.
+// whether the near field runs on a second stream concurrently with the transfer
+// passes, and whether the coupling of the deep rows runs on it beside the upper
+// transfer levels (whole-product times decide the last and the final choice).
 #include <cmath>
 #include <string>
 #include <vector>
@@ -141,11 +142,41 @@ h2x_status run_autotune(DevMat &dm, int64_t m, char *ws, size_t ws_bytes, hipStr
             }
         }
     }
-    double s1[5];
-    e = time_cfg(best, s1);
+    // mean time of the whole product, events around the call only (the split schedule
+    // and the stage events exclude each other)
+    auto time_whole = [&](const TuneCfg &c, double &ms) {
+        hipError_t r = run_matmul_cfg(dm, c, m, 1.0, X, m, 0.0, Y, m, false, mm, st, nullptr, nullptr);
+        if (r == hipSuccess) r = hipEventRecord(ev[0], st);
+        for (int q = 0; q < reps && r == hipSuccess; ++q)
+            r = run_matmul_cfg(dm, c, m, 1.0, X, m, 0.0, Y, m, false, mm, st, nullptr, nullptr);
+        if (r == hipSuccess) r = hipEventRecord(ev[6], st);
+        if (r == hipSuccess) r = hipEventSynchronize(ev[6]);
+        float t = 0.f;
+        if (r == hipSuccess) r = hipEventElapsedTime(&t, ev[0], ev[6]);
+        ms = (double)t / reps;
+        return r;
+    };
+    // coupling of the deep rows beside the upper transfer levels, on or off
+    double w_best = 0.0, w0 = 0.0;
+    if (dm.side && dm.split_depth > 0 && best.fuse_up != 1 && !(best.overlap == 1 || best.overlap >= 3)) {
+        double w_min = HUGE_VAL;
+        for (int sp : {2, 1, 3}) {
+            TuneCfg c = best;
+            c.split = (int8_t)sp;
+            double w = 0.0;
+            e = time_whole(c, w);
+            if (e != hipSuccess) return done(e);
+            if (w < w_min) {
+                w_min = w;
+                best.split = (int8_t)sp;
+            }
+        }
+    }
+    e = time_whole(best, w_best);
+    if (e == hipSuccess) e = time_whole(TuneCfg{}, w0);
     if (e != hipSuccess) return done(e);
     // keep the default when the combination is not faster
-    const bool use = total(s1) < total(s0);
+    const bool use = w_best < w0;
     dm.tuned[b] = use ? best : TuneCfg{};
     if (info) {
         info->nj_transfer = dm.tuned[b].nj_transfer;
@@ -154,8 +185,9 @@ h2x_status run_autotune(DevMat &dm, int64_t m, char *ws, size_t ws_bytes, hipStr
         info->overlap = dm.tuned[b].overlap;
         info->fuse_up = dm.tuned[b].fuse_up;
         info->leaf_kind = dm.tuned[b].leaf_kind;
-        info->ms_default = total(s0);
-        info->ms_tuned = use ? total(s1) : total(s0);
+        info->split = dm.tuned[b].split;
+        info->ms_default = w0;
+        info->ms_tuned = use ? w_best : w0;
     }
     return done(hipSuccess);
 }

@@ -78,6 +78,35 @@ def test_batch_product_matches_oracle(mixed):
         assert max(errs) <= TOL
 
 
+def test_batch_split_coupling(mixed):
+    """Merged operators with the coupling rows split (split 1), bitwise the one-launch
+    products, and the batched CG through a graph replay with the split on."""
+    h2x = _h2x()
+    sys, batch, oracles = mixed
+    split = [A for A in batch.mats if A.plan.split_depth > 0]
+    assert split, "no merged operator of the batch has a split depth"
+    m = 7
+    X = _dev(W.rhs(batch.n, m, 530))
+    for A in batch.mats:
+        A.set_tune(m, split=2)
+    one = h2x.batch_matmul(batch, X).cpu().numpy()
+    for A in batch.mats:
+        A.set_tune(m, split=1)
+    got = h2x.batch_matmul(batch, X).cpu().numpy()
+    B = _dev(W.rhs(batch.n, m, 531))
+    Xd, idd = h2x.batch_block_cg_solve(batch, B, rtol=1e-8, graph=False)
+    for rep in range(3):
+        Xg, ig = h2x.batch_block_cg_solve(batch, B, rtol=1e-8, graph=True)
+        torch.cuda.synchronize()
+        assert ig.iters == idd.iters and torch.equal(Xg, Xd), rep
+        h2x.batch_matmul(batch, Xg)  # eager work between the replays
+        torch.cuda.synchronize()
+    for A in batch.mats:
+        A.set_tune(m)
+    print(f"split depths {[A.plan.split_depth for A in batch.mats]}")
+    assert np.array_equal(got, one)
+
+
 def test_merged_cg_is_bitwise_the_single_system_cg(mixed):
     h2x = _h2x()
     sys, batch, _ = mixed

@@ -91,6 +91,24 @@ def test_complex_row_split_leaf_stage(name, pts, prm, kappa, m):
     assert max(errs) <= 1e-12
 
 
+def test_complex_split_coupling():
+    """Both coupling passes (real plane, imaginary plane on J x-hat) of each part of the
+    split rows: bitwise the one-launch result, and the oracle's."""
+    h2x = _h2x()
+    P = W.sphere_points(4096, 121)
+    kw = dict(kernel="helmholtz", ell=1.0, shift=1.0, eta=1.0, leaf=32, p=3)
+    A = h2x.H2Matrix(P, **kw)
+    assert A.plan.split_depth > 0
+    X = _cplx(4096, 3, 136)
+    A.set_tune(6, split=2)
+    one = h2x.h2_matmul(A, _dev(X)).cpu().numpy()
+    A.set_tune(6, split=1)
+    got = h2x.h2_matmul(A, _dev(X)).cpu().numpy()
+    err = _colrel(got, oracle.OracleH2(P, **kw).matmul_complex(X))
+    print(f"complex split coupling: {err:.2e}")
+    assert np.array_equal(got, one) and err <= 1e-12
+
+
 @pytest.fixture(scope="module")
 def helm():
     h2x = _h2x()

@@ -107,16 +107,48 @@ def test_row_split_leaf_stage_matches_oracle(name, pts, prm, m):
     assert max(errs) <= TOL and err_ab <= TOL and err_t <= TOL
 
 
+SPLIT = [c for c in CASES if c[0] in ("small-k27-m37", "cube-k64-m5", "cube-k64-m64")] + [
+    ("sphere20000-k27-m9", lambda: W.sphere_points(20000, 5), dict(ell=0.5, shift=1.0, eta=1.0, leaf=32, p=3), 9)]
+
+
+@pytest.mark.parametrize("name,pts,prm,m", SPLIT, ids=[c[0] for c in SPLIT])
+def test_split_coupling_matches_oracle(name, pts, prm, m):
+    """The coupling rows in two parts (split 1, with the LDS reserve, and 3): the deep part
+    on the operator's second stream beside the upper transfer levels, the other rows and
+    the upper downward levels on the caller's stream.  Against the oracle, and bitwise equal to the one
+    launch (each row's blocks are summed in the same order); alpha / beta."""
+    P = pts()
+    o, A = _pair(P, **prm)
+    assert A.plan.split_depth > A.plan.adm_depth + 1 and 0 < A.plan.deep_blocks < A.plan.n_adm
+    n = P.shape[0]
+    X = W.rhs(n, m, 200 + m)
+    ref = o.matmul(X)
+    A.set_tune(m, split=2)
+    one = _gpu(A, X)
+    A.set_tune(m, split=3)
+    got3 = _gpu(A, X)
+    A.set_tune(m, split=1)
+    got = _gpu(A, X)
+    Y0 = W.rhs(n, m, 201)
+    err_ab = _colrel(_gpu(A, X, alpha=-1.25, beta=0.5, out=Y0), 0.5 * Y0 - 1.25 * ref)
+    A.set_tune(m)
+    err = _colrel(got, ref)
+    print(f"{name}: split depth {A.plan.split_depth} (deep blocks {A.plan.deep_blocks} of {A.plan.n_adm}), "
+          f"err {err:.3e}, alpha/beta {err_ab:.3e}")
+    assert np.array_equal(got, one) and np.array_equal(got3, one)
+    assert err <= TOL and err_ab <= TOL
+
+
 def test_set_get_tune():
     h2x = _h2x()
     A = h2x.H2Matrix(W.sphere_points(2000, 192), ell=0.5, shift=1.0, eta=1.0, leaf=64, p=4)
     assert all(v == 0 for v in A.get_tune(20).values())
-    A.set_tune(20, nj_coupling=2, leaf_kind=2, np_leaf=1, overlap=1)
+    A.set_tune(20, nj_coupling=2, leaf_kind=2, np_leaf=1, overlap=1, split=2)
     # one entry per ceil(m / 16): 17..32 share it, 16 and 33 do not
     assert A.get_tune(17) == A.get_tune(32) == dict(nj_transfer=0, nj_coupling=2, np_leaf=1, overlap=1, fuse_up=0,
-                                                    leaf_kind=2)
+                                                    leaf_kind=2, split=2)
     assert A.get_tune(16)["leaf_kind"] == 0 and A.get_tune(33)["leaf_kind"] == 0
-    for bad in (dict(nj_coupling=5), dict(leaf_kind=3), dict(np_leaf=-1), dict(overlap=5), dict(fuse_up=3)):
+    for bad in (dict(nj_coupling=5), dict(leaf_kind=3), dict(split=4), dict(np_leaf=-1), dict(overlap=5), dict(fuse_up=3)):
         with pytest.raises(h2x.H2xError, match="out of range"):
             A.set_tune(20, **bad)
     with pytest.raises(ValueError):

@@ -6,6 +6,10 @@
   and the set of admissible / near-field leaves with the within-row order of
   the prepare_addeval lists.
 * Argument validation returns H2X_EINVAL without touching a GPU.
+* The split of the coupling rows (plan stats): recomputed from the cluster tree and
+  the block lists, the deep part is the rows at depth >= D whose inner column clusters
+  all lie at depth >= D, it holds >= 60 % of the admissible blocks, and D is the
+  deepest such depth above the shallowest admissible depth + 1.
 """
 import ctypes as C
 import os
@@ -119,3 +123,30 @@ def test_merged_plan_is_the_concatenation_of_its_systems():
         q0 += p.n_near
     with pytest.raises(h2x.H2xError):
         h2x.Plan.merge([parts[0], h2x.Plan(W.sphere_points(500, 405), leaf=32, p=4)])
+
+
+def _deep_blocks(c, b, D):
+    depth, son0 = c["depth"], c["son0"]
+    at, as_ = b["adm_t"], b["adm_s"]
+    inner = son0[as_] >= 0
+    # shallowest inner column cluster per row
+    ready = np.full(len(depth), 1 << 30, dtype=np.int64)
+    np.minimum.at(ready, at[inner], depth[as_[inner]])
+    deep = (depth >= D) & (ready >= D)
+    return int(deep[at].sum())
+
+
+@pytest.mark.parametrize("wl,n,leaf,p", [("sphere", 20000, 32, 3), ("cube", 7000, 64, 4), ("sphere", 4096, 32, 3),
+                                         ("sphere", 4000, 64, 4), ("line", 3000, 16, 2)])
+def test_coupling_split_rule(wl, n, leaf, p):
+    pts = {"sphere": W.sphere_points, "cube": W.cube_points, "line": W.line_points}[wl](n, 41)
+    P = h2x.Plan(pts, ell=0.5, shift=1.0, eta=1.0, leaf=leaf, p=p)
+    c, b = P.clusters(), P.blocks()
+    D = P.split_depth
+    cands = [d for d in range(P.depth, P.adm_depth + 1, -1) if 10 * _deep_blocks(c, b, d) >= 6 * P.n_adm]
+    print(f"{wl} n={n}: depth {P.depth}, adm {P.adm_depth}, split {D}, deep {P.deep_blocks} of {P.n_adm}")
+    if D == 0:
+        assert not cands and P.deep_blocks == 0
+    else:
+        assert D == cands[0] and P.deep_blocks == _deep_blocks(c, b, D)
+        assert 10 * P.deep_blocks >= 6 * P.n_adm

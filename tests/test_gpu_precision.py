@@ -95,3 +95,40 @@ def test_mixed_cg_residual_replacement(prec):
     assert info.status == 0 and res.max() <= 1.5e-10
     assert np.all(info.col_relres <= 1e-10)
     assert abs(info.iters - oi["iters"]) <= max(5, 0.1 * oi["iters"])
+
+
+def test_precision_workload_full_size():
+    """The precision workload at full size (cube, n = 262144, k = 64, m = 64), products in
+    FP64, FP32 and BF16 storage as the bench times them (64 columns).  The oracle runs on a
+    sample of four of the columns (each column of the product depends on its own column
+    of X only): FP64 to 1e-12 per column; FP32 and BF16 against the FP64 product within the
+    ranges their storage gives (the emulated low-precision operator is checked on the
+    smaller cases above)."""
+    import paper_2509_17257_amd as h2x
+    w = W.PRECISION
+    P = w.points()
+    X = w.rhs()
+    cols = [0, 21, 42, 63]
+    plan = h2x.Plan(P, **w.params())
+    got = {}
+    for prec in ("f64", "f32", "bf16"):
+        print(f"[full] precision workload, {prec} product, m = {X.shape[1]}", flush=True)
+        A = h2x.H2Matrix(plan, storage=prec)
+        got[prec] = h2x.h2_matmul(A, torch.from_numpy(X).cuda()).cpu().numpy()
+        del A
+        torch.cuda.empty_cache()
+    print("[full] oracle on the sampled columns", flush=True)
+    o = oracle.OracleH2(P, **w.params())
+    ref = o.matmul(np.ascontiguousarray(X[:, cols]))
+    del o
+    e64 = _colrel(got["f64"][:, cols], ref)
+    errs = {p: _colrel(got[p], got["f64"]) for p in ("f32", "bf16")}
+    print(f"[full] FP64 vs oracle {e64:.2e}; FP32 vs FP64 {errs['f32']:.2e}; BF16 vs FP64 {errs['bf16']:.2e}")
+    assert e64 <= 1e-12
+    # an entry of the product sums K ~ 10^3 .. 10^4 FP32 products (the lists and near blocks
+    # of a row, the transfer levels): the rounding grows like sqrt(K) u, u = 2^-24 (FP32) or
+    # 2^-8 (BF16 storage), so the full size gets the bounds 1e-5 and 3e-2
+    full = {"f32": (1e-9, 1e-5), "bf16": (1e-4, 3e-2)}
+    for p, e in errs.items():
+        lo, hi = full[p]
+        assert lo < e < hi

@@ -675,10 +675,20 @@ def main():
     log(f"[bench] warmup {args.warmup} done; timing {args.steps} products")
     stream = torch.cuda.current_stream(dev)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    # every MARK_EVERY-th timed product records its stage boundaries with HIP events on the
+    # library's stream (the caller's stream), read after the timed region: the per-stage and
+    # coupling times come from products of the timed region (seven event records cost about
+    # 2 % of a product, so not every product carries them)
+    MARK_EVERY = 4
+    marked = list(range(0, args.steps, MARK_EVERY))
+    timer = h2x.Timer(len(marked))
     torch.cuda.synchronize()
     e0.record(stream)
-    for _ in range(args.steps):
-        h2x.h2_matmul(A, X, out=Y)
+    for i in range(args.steps):
+        if i % MARK_EVERY == 0:
+            h2x.h2_matmul(A, X, out=Y, timer=timer, slot=i // MARK_EVERY)
+        else:
+            h2x.h2_matmul(A, X, out=Y)
     e1.record(stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / args.steps
@@ -686,15 +696,8 @@ def main():
     F = alg_flops(plan, m)
     gbs = B_alg / (ms * 1e-3) / 1e9
     log(f"[bench] {ms:.4f} ms/product, {gbs:.1f} GB/s algorithmic")
-
-    # per-stage durations with HIP events on the library's stream
-    stage = np.zeros(len(h2x.STAGES))
-    nt = max(3, min(args.steps, 20))
-    for _ in range(nt):
-        s = np.zeros(len(h2x.STAGES))
-        h2x.h2_matmul(A, X, out=Y, stage_ms=s)
-        stage += s
-    stage /= nt
+    stage = np.mean([timer.read(j) for j in range(len(marked))], axis=0)
+    log(f"[bench] stage times from {len(marked)} of the {args.steps} timed products")
     cb, cf = coupling_bytes(plan, m), coupling_flops(plan, m)
     c_ms = stage[h2x.STAGES.index("coupling")]
     c_gbs = cb / (c_ms * 1e-3) / 1e9

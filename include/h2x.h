@@ -171,6 +171,21 @@ h2x_status h2x_matmul_timed(const h2x_mat *A, int64_t m, double alpha, const dou
                             double beta, double *Y, int64_t ldy, int32_t flags, void *dev_ws,
                             size_t ws_bytes, void *hip_stream, double *stage_ms);
 
+/* Stage timing without synchronization, for products inside a timed loop.  A timer holds
+ * `slots` sets of HIP events (library-owned, destroyed with the timer).  h2x_matmul_marked
+ * is h2x_matmul that also records the stage boundaries of this product into one slot on
+ * hip_stream (the stages then run one after another on that stream, as with
+ * h2x_matmul_timed); it returns without waiting.  h2x_timer_read waits for the slot's last
+ * event and writes the stage durations of its latest product in milliseconds to
+ * stage_ms[H2X_NUM_STAGES] (host).  H2X_EINVAL: slot out of range, NULL arguments. */
+typedef struct h2x_timer h2x_timer;
+h2x_status h2x_timer_create(int32_t slots, h2x_timer **out);
+void h2x_timer_destroy(h2x_timer *timer);
+h2x_status h2x_matmul_marked(const h2x_mat *A, int64_t m, double alpha, const double *X, int64_t ldx,
+                             double beta, double *Y, int64_t ldy, int32_t flags, void *dev_ws,
+                             size_t ws_bytes, void *hip_stream, h2x_timer *timer, int32_t slot);
+h2x_status h2x_timer_read(const h2x_timer *timer, int32_t slot, double *stage_ms);
+
 /* ---- block CG ------------------------------------------------------------ */
 
 typedef struct {

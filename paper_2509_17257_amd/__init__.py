@@ -112,6 +112,10 @@ def load_library():
         "h2x_matmul_workspace_bytes": (SZ, [P, I64]),
         "h2x_matmul": (C.c_int, [P, I64, D, P, I64, D, P, I64, I32, P, SZ, P]),
         "h2x_matmul_timed": (C.c_int, [P, I64, D, P, I64, D, P, I64, I32, P, SZ, P, P]),
+        "h2x_timer_create": (C.c_int, [I32, C.POINTER(P)]),
+        "h2x_timer_destroy": (None, [P]),
+        "h2x_matmul_marked": (C.c_int, [P, I64, D, P, I64, D, P, I64, I32, P, SZ, P, P, I32]),
+        "h2x_timer_read": (C.c_int, [P, I32, P]),
         "h2x_block_cg_workspace_bytes": (SZ, [P, I64]),
         "h2x_block_cg": (C.c_int, [P, C.POINTER(_CgParams), I64, P, I64, P, I64, P, SZ, C.POINTER(_CgInfo), P]),
         "h2x_block_cg_refine_workspace_bytes": (SZ, [P, P, I64]),
@@ -353,17 +357,41 @@ class H2Matrix:
 STAGES = ("forward_leaf", "forward_transfer", "coupling", "backward_transfer", "leaf_near")
 
 
-def h2_matmul(A: H2Matrix, X, *, alpha=1.0, beta=0.0, out=None, tree_order=False, stage_ms=None):
+class Timer:
+    """Stage events for `slots` products (h2x_timer_create): h2_matmul(..., timer=T, slot=i)
+    records product i's stage boundaries without waiting; T.read(i) waits for them and
+    returns the stage durations (ms, STAGES order)."""
+
+    def __init__(self, slots: int):
+        h = C.c_void_p()
+        _check(load_library().h2x_timer_create(int(slots), C.byref(h)), "h2x_timer_create")
+        self._h, self.slots = h, int(slots)
+
+    def read(self, slot: int) -> np.ndarray:
+        out = np.zeros(len(STAGES))
+        _check(load_library().h2x_timer_read(self._h, int(slot), _ptr(out)), "h2x_timer_read")
+        return out
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.h2x_timer_destroy(self._h)
+            self._h = None
+
+
+def h2_matmul(A: H2Matrix, X, *, alpha=1.0, beta=0.0, out=None, tree_order=False, stage_ms=None, timer=None,
+              slot=0):
     """Y <- beta Y + alpha A X on the GPU (h2x_matmul).  X: (n, m) float64 CUDA tensor, or
     complex128 for a complex (Helmholtz) operator (its memory is 2m real columns).
 
     With ``stage_ms`` (a float64 numpy array of len(STAGES)) the product runs through
-    h2x_matmul_timed and the per-stage durations in ms are written into it (blocking)."""
+    h2x_matmul_timed and the per-stage durations in ms are written into it (blocking); with
+    ``timer`` (a Timer) through h2x_matmul_marked into ``slot`` (not blocking)."""
     import torch
     if X.is_complex():
         Xr = _as_real(torch, X)
         Yr = None if out is None else _as_real(torch, out)
-        Yr = h2_matmul(A, Xr, alpha=alpha, beta=beta, out=Yr, tree_order=tree_order, stage_ms=stage_ms)
+        Yr = h2_matmul(A, Xr, alpha=alpha, beta=beta, out=Yr, tree_order=tree_order, stage_ms=stage_ms, timer=timer,
+                       slot=slot)
         return torch.view_as_complex(Yr.reshape(Yr.shape[0], -1, 2)) if out is None else out
     squeeze = X.dim() == 1
     X2 = X.reshape(-1, 1) if squeeze else X
@@ -383,7 +411,9 @@ def h2_matmul(A: H2Matrix, X, *, alpha=1.0, beta=0.0, out=None, tree_order=False
     args = (A._h, m, float(alpha), C.c_void_p(X2.data_ptr()), X2.stride(0), float(beta), C.c_void_p(Y.data_ptr()),
             Y.stride(0), TREE_ORDER if tree_order else 0, C.c_void_p(ws.data_ptr()), ws.numel(),
             _stream(torch, X2.device))
-    if stage_ms is None:
+    if timer is not None:
+        _check(load_library().h2x_matmul_marked(*args, timer._h, int(slot)), "h2x_matmul_marked")
+    elif stage_ms is None:
         _check(load_library().h2x_matmul(*args), "h2x_matmul")
     else:
         assert stage_ms.dtype == np.float64 and stage_ms.size >= len(STAGES)

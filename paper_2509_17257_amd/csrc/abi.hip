@@ -340,6 +340,67 @@ h2x_status h2x_matmul_timed(const h2x_mat *A, int64_t m, double alpha, const dou
     return H2X_OK;
 }
 
+}  // extern "C"
+
+struct h2x_timer {
+    int32_t slots = 0;
+    std::vector<hipEvent_t> ev;  // slots x 7
+};
+
+extern "C" {
+
+h2x_status h2x_timer_create(int32_t slots, h2x_timer **out) {
+    if (!out) return fail(H2X_EINVAL, "h2x_timer_create: out is NULL");
+    *out = nullptr;
+    if (slots < 1) return fail(H2X_EINVAL, "h2x_timer_create: need slots >= 1");
+    auto *t = new h2x_timer{};
+    t->slots = slots;
+    t->ev.assign((size_t)slots * 7, nullptr);
+    hipError_t e = hipSuccess;
+    for (auto &x : t->ev)
+        if (e == hipSuccess) e = hipEventCreate(&x);
+    if (e != hipSuccess) {
+        h2x_timer_destroy(t);
+        return hip_fail("h2x_timer_create", e);
+    }
+    *out = t;
+    return H2X_OK;
+}
+
+void h2x_timer_destroy(h2x_timer *timer) {
+    if (!timer) return;
+    for (auto &x : timer->ev)
+        if (x) (void)hipEventDestroy(x);
+    delete timer;
+}
+
+h2x_status h2x_matmul_marked(const h2x_mat *A, int64_t m, double alpha, const double *X, int64_t ldx, double beta,
+                             double *Y, int64_t ldy, int32_t flags, void *dev_ws, size_t ws_bytes, void *hip_stream,
+                             h2x_timer *timer, int32_t slot) {
+    if (h2x_status r = need_pairs(A, m, "h2x_matmul_marked")) return r;
+    if (!timer || slot < 0 || slot >= timer->slots) return fail(H2X_EINVAL, "h2x_matmul_marked: bad timer or slot");
+    h2x_status s = validate_matmul("h2x_matmul_marked", A, m, X, ldx, Y, ldy, flags, dev_ws, ws_bytes);
+    if (s != H2X_OK) return s;
+    const hipError_t e = run_matmul(A->dm, m, alpha, X, ldx, beta, Y, ldy, (flags & H2X_TREE_ORDER) != 0,
+                                    (char *)dev_ws, (hipStream_t)hip_stream, timer->ev.data() + (size_t)7 * slot);
+    if (e != hipSuccess) return hip_fail("h2x_matmul_marked", e);
+    return H2X_OK;
+}
+
+h2x_status h2x_timer_read(const h2x_timer *timer, int32_t slot, double *stage_ms) {
+    if (!timer || !stage_ms || slot < 0 || slot >= timer->slots)
+        return fail(H2X_EINVAL, "h2x_timer_read: bad timer, slot or output");
+    hipEvent_t *ev = const_cast<hipEvent_t *>(timer->ev.data()) + (size_t)7 * slot;
+    hipError_t e = hipEventSynchronize(ev[6]);
+    for (int i = 0; i < H2X_NUM_STAGES && e == hipSuccess; ++i) {
+        float ms = 0.f;
+        e = hipEventElapsedTime(&ms, ev[i], ev[i + 1]);
+        stage_ms[i] = ms;
+    }
+    if (e != hipSuccess) return hip_fail("h2x_timer_read", e);
+    return H2X_OK;
+}
+
 size_t h2x_block_cg_workspace_bytes(const h2x_mat *A, int64_t m) {
     if (!A || m < 1) return 0;
     return std::max(cg_ws_bytes(A->dm, m), bcg_ws_bytes(A->dm, m));

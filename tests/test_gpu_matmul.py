@@ -257,3 +257,25 @@ def test_autotune_keeps_results(storage, m):
     else:
         rel = ((after - before).norm(dim=0) / before.norm(dim=0)).max().item()
         assert rel <= 1e-14
+
+
+def test_stage_timer():
+    """h2x_matmul_marked: the same product as h2x_matmul (bitwise), stage boundaries recorded
+    per slot without waiting; h2x_timer_read returns positive stage times whose sum is the
+    product's time; bad slots are refused."""
+    h2x = _h2x()
+    P = W.sphere_points(6000, 81)
+    A = h2x.H2Matrix(P, ell=0.5, shift=1.0, eta=1.0, leaf=64, p=4)
+    X = torch.from_numpy(W.rhs(6000, 32, 205)).cuda()
+    ref = h2x.h2_matmul(A, X).clone()
+    T = h2x.Timer(3)
+    outs = [h2x.h2_matmul(A, X, timer=T, slot=i).clone() for i in range(3)]
+    torch.cuda.synchronize()
+    for i in range(3):
+        assert torch.equal(outs[i], ref)
+        st = T.read(i)
+        assert st.shape == (len(h2x.STAGES),) and (st > 0).all() and st.sum() < 100.0
+    with pytest.raises(h2x.H2xError):
+        h2x.h2_matmul(A, X, timer=T, slot=3)
+    with pytest.raises(h2x.H2xError):
+        T.read(-1)

@@ -86,6 +86,16 @@ def test_invalid_arguments_rejected():
     # workspace queries on NULL handles return 0 instead of crashing
     assert lib.h2x_mat_workspace_bytes(None, 0) == 0
     assert lib.h2x_matmul_workspace_bytes(None, 4) == 0
+    # tuning and timer entry points refuse NULL handles and bad sizes before any GPU call
+    info = h2x._TuneInfo()
+    assert lib.h2x_mat_set_tune(None, 8, C.byref(info)) == 1
+    assert lib.h2x_mat_get_tune(None, 8, C.byref(info)) == 1
+    t = C.c_void_p()
+    assert lib.h2x_timer_create(0, C.byref(t)) == 1 and not t.value
+    assert lib.h2x_timer_create(4, None) == 1
+    out = np.zeros(5)
+    assert lib.h2x_timer_read(None, 0, out.ctypes.data_as(C.c_void_p)) == 1
+    lib.h2x_timer_destroy(None)
 
 
 def test_merged_plan_is_the_concatenation_of_its_systems():

@@ -367,10 +367,16 @@ void matmul_mfma_f64(const DevMat &dm, const TuneCfg &cfg, int64_t m, double alp
     // the concurrent near field or the fused upward pass)
     const bool split = (cfg.split == 1 || cfg.split == 3) && dm.split_depth > 0 && dm.side && !ov && !ev &&
                        cfg.fuse_up != 1;
+    // rank 64: the transfer matrices go straight into the matrix-core registers
+    const bool t64 = dm.k == mfma::K;
     auto up_levels = [&](int dhi, int dlo) {  // upward levels dhi down to dlo
         for (int d = dhi; d >= dlo; --d) {
             const int32_t b = P.lvl_inner_ptr[d], e = P.lvl_inner_ptr[d + 1];
-            if (e > b)
+            if (e <= b) continue;
+            if (t64)
+                hipLaunchKernelGGL(mfma::k_up64<NJ>, dim3(e - b, gy), dim3(256), 0, st, m, dm.lvl_inner + b,
+                                   dm.up_son + 2 * b, E, xh, ldh, sk);
+            else
                 hipLaunchKernelGGL(mfma::k_up<NJ>, dim3(e - b, gy), dim3(256), 0, st, dm.k, m, dm.lvl_inner + b,
                                    dm.up_son + 2 * b, E, xh, ldh, sk);
         }
@@ -378,7 +384,11 @@ void matmul_mfma_f64(const DevMat &dm, const TuneCfg &cfg, int64_t m, double alp
     auto down_levels = [&](int dlo, int dhi) {  // downward levels (son depths) dlo up to dhi
         for (int d = dlo; d <= dhi; ++d) {
             const int32_t b = P.lvl_ptr[d], e = P.lvl_ptr[d + 1];
-            if (e > b)
+            if (e <= b) continue;
+            if (t64)
+                hipLaunchKernelGGL(mfma::k_down64<NJ>, dim3(e - b, gy), dim3(256), 0, st, m, dm.lvl_all + b,
+                                   dm.dn_par + b, E, yh, ldh, sk);
+            else
                 hipLaunchKernelGGL(mfma::k_down<NJ>, dim3(e - b, gy), dim3(256), 0, st, dm.k, m, dm.lvl_all + b,
                                    dm.dn_par + b, E, yh, ldh, sk);
         }
@@ -402,8 +412,9 @@ void matmul_mfma_f64(const DevMat &dm, const TuneCfg &cfg, int64_t m, double alp
         size_t keep = 0;
         if (cfg.split == 1) {
             hipFuncAttributes a{}, b{};
-            if (hipFuncGetAttributes(&a, (const void *)mfma::k_up<NJ>) == hipSuccess &&
-                hipFuncGetAttributes(&b, (const void *)mfma::k_down<NJ>) == hipSuccess)
+            const void *fu = t64 ? (const void *)mfma::k_up64<NJ> : (const void *)mfma::k_up<NJ>;
+            const void *fd = t64 ? (const void *)mfma::k_down64<NJ> : (const void *)mfma::k_down<NJ>;
+            if (hipFuncGetAttributes(&a, fu) == hipSuccess && hipFuncGetAttributes(&b, fd) == hipSuccess)
                 keep = std::max(a.sharedSizeBytes, b.sharedSizeBytes);
         }
         coupling(dm.side, dm.n_deep, dm.cpl_deep, keep);

@@ -326,6 +326,94 @@ __global__ __launch_bounds__(256) void k_down(int k, int64_t m, const int32_t *_
                 if (out_row(r) < k) yh[((int64_t)c * k + out_row(r)) * ldh + j0 + out_col(J)] += acc[J][r];
 }
 
+// Transfer passes for rank k = 64 with the transfer matrices straight from memory as the
+// matrix-core left operand: wave w holds rows 16w..16w+15 of E_s^T (upward) or E_s
+// (downward) in registers, 16 k-steps of one 8-byte load per lane (upward: 16 lanes over
+// 16 consecutive entries of a row of E_s; downward: 16 rows of E_s, their 128-byte lines
+// shared by four k-steps through the L1), so that only the right operand (x-hat or y-hat
+// rows, 64 x 16*NJ) goes through LDS, both upward terms at once behind one barrier.  The
+// k-steps and terms are summed in the order of k_up / k_down.
+//   upward:   x_t = E_{s0}^T x_{s0} + E_{s1}^T x_{s1}   (list, son as for k_up)
+//   downward: y_c += E_c y_{par(c)}                    (list, par as for k_down)
+template <int NJ, int NT, int TR>
+__device__ inline void transfer_rows(const double *const *Ea, const int64_t *brow, int64_t m,
+                                     const double *__restrict__ hat_in, int64_t ldh, dbl4 *acc) {
+    constexpr int MC = 16 * NJ, LDB = MC + 1, XPT = 64 * MC / 256;
+    __shared__ double bs[NT][64 * LDB];
+    const int tid = threadIdx.x, lane = tid & 63, lr = lane & 15, lq = lane >> 4;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int64_t j0 = (int64_t)blockIdx.y * MC;
+    const int mc = (int)min<int64_t>(MC, m - j0);
+    double a[NT][16], bv[NT][XPT];
+#pragma unroll
+    for (int q = 0; q < NT; ++q) {
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk)
+            a[q][kk] = TR ? Ea[q][(4 * kk + lq) * 64 + 16 * w + lr] : Ea[q][(16 * w + lr) * 64 + 4 * kk + lq];
+#pragma unroll
+        for (int u = 0; u < XPT; ++u) {
+            const int e = tid + 256 * u, r = e / MC, c = e % MC;
+            bv[q][u] = hat_in[(brow[q] + r) * ldh + j0 + min(c, mc - 1)];  // columns past mc: zeroed when stored
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < NT; ++q)
+#pragma unroll
+        for (int u = 0; u < XPT; ++u) {
+            const int e = tid + 256 * u, r = e / MC, c = e % MC;
+            bs[q][r * LDB + c] = c < mc ? bv[q][u] : 0.0;
+        }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NT; ++q)
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk)
+#pragma unroll
+            for (int J = 0; J < NJ; ++J)
+                acc[J] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q][kk], bs[q][(4 * kk + lq) * LDB + 16 * J + lr], acc[J],
+                                                              0, 0, 0);
+}
+
+template <int NJ>
+__global__ __launch_bounds__(256) void k_up64(int64_t m, const int32_t *__restrict__ list,
+                                              const int32_t *__restrict__ son, const double *__restrict__ E,
+                                              double *__restrict__ xh, int64_t ldh, Skip skip) {
+    const int32_t t = list[blockIdx.x], s0 = son[2 * blockIdx.x], s1 = son[2 * blockIdx.x + 1];
+    if (skip(t)) return;
+    const double *Ea[2] = {E + (int64_t)s0 * 4096, E + (int64_t)s1 * 4096};
+    const int64_t brow[2] = {(int64_t)s0 * 64, (int64_t)s1 * 64};
+    dbl4 acc[NJ];
+    zero<NJ>(acc);
+    transfer_rows<NJ, 2, 1>(Ea, brow, m, xh, ldh, acc);
+    const int64_t j0 = (int64_t)blockIdx.y * 16 * NJ;
+    const int mc = (int)min<int64_t>(16 * NJ, m - j0);
+#pragma unroll
+    for (int J = 0; J < NJ; ++J)
+        if (out_col(J) < mc)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) xh[((int64_t)t * 64 + out_row(r)) * ldh + j0 + out_col(J)] = acc[J][r];
+}
+
+template <int NJ>
+__global__ __launch_bounds__(256) void k_down64(int64_t m, const int32_t *__restrict__ list,
+                                                const int32_t *__restrict__ par, const double *__restrict__ E,
+                                                double *__restrict__ yh, int64_t ldh, Skip skip) {
+    const int32_t c = list[blockIdx.x], p = par[blockIdx.x];
+    if (skip(c)) return;
+    const double *Ea[1] = {E + (int64_t)c * 4096};
+    const int64_t brow[1] = {(int64_t)p * 64};
+    dbl4 acc[NJ];
+    zero<NJ>(acc);
+    transfer_rows<NJ, 1, 0>(Ea, brow, m, yh, ldh, acc);
+    const int64_t j0 = (int64_t)blockIdx.y * 16 * NJ;
+    const int mc = (int)min<int64_t>(16 * NJ, m - j0);
+#pragma unroll
+    for (int J = 0; J < NJ; ++J)
+        if (out_col(J) < mc)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) yh[((int64_t)c * 64 + out_row(r)) * ldh + j0 + out_col(J)] += acc[J][r];
+}
+
 // Leaf stage in the transposed orientation Y_t^T = X_s^T N_ts^T: the
 // matrix-core M dimension runs over columns of X, N over rows of the leaf.
 // Near-field blocks are stored transposed (|s| rows of length |t| padded to

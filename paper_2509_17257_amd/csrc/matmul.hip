@@ -319,6 +319,16 @@ void matmul_mfma_f64(const DevMat &dm, const TuneCfg &cfg, int64_t m, double alp
         Xt = xt_ws;
     }
     const Skip sk{skip, dm.sys_of};
+    // rank 64: the basis and transfer matrices go straight into the matrix-core registers
+    const bool t64 = dm.k == mfma::K;
+    auto fwd_leaf = [&]() {
+        if (t64)
+            hipLaunchKernelGGL(mfma::k_fwd_leaf64<NJ>, dim3(dm.L, gy), dim3(256), 0, st, m, dm.leaves, dm.first,
+                               dm.size, V, Xt, ldxt, xh, ldh, sk);
+        else
+            hipLaunchKernelGGL(mfma::k_fwd_leaf<NJ>, dim3(dm.L, gy), dim3(256), 0, st, dm.k, m, dm.leaves, dm.first,
+                               dm.size, dm.perm, V, Xt, ldxt, 1, xh, ldh, sk);
+    };
     const unsigned gl = (unsigned)((m + 32 * NP - 1) / (32 * NP));
     // leaf stage: a 64-row tile per wave and term (built-in) or the rows split over the waves
     const bool rows = cfg.leaf_kind == 2;
@@ -367,8 +377,6 @@ void matmul_mfma_f64(const DevMat &dm, const TuneCfg &cfg, int64_t m, double alp
     // the concurrent near field or the fused upward pass)
     const bool split = (cfg.split == 1 || cfg.split == 3) && dm.split_depth > 0 && dm.side && !ov && !ev &&
                        cfg.fuse_up != 1;
-    // rank 64: the transfer matrices go straight into the matrix-core registers
-    const bool t64 = dm.k == mfma::K;
     auto up_levels = [&](int dhi, int dlo) {  // upward levels dhi down to dlo
         for (int d = dhi; d >= dlo; --d) {
             const int32_t b = P.lvl_inner_ptr[d], e = P.lvl_inner_ptr[d + 1];
@@ -401,8 +409,7 @@ void matmul_mfma_f64(const DevMat &dm, const TuneCfg &cfg, int64_t m, double alp
     };
     const int dlo = std::max(1, P.adm_depth + 1);
     if (split) {
-        hipLaunchKernelGGL(mfma::k_fwd_leaf<NJ>, dim3(dm.L, gy), dim3(256), 0, st, dm.k, m, dm.leaves, dm.first,
-                           dm.size, dm.perm, V, Xt, ldxt, 1, xh, ldh, sk);
+        fwd_leaf();
         const int D = dm.split_depth;
         up_levels(dm.depth_max - 1, D);
         (void)hipEventRecord(dm.ev_fork, st);
@@ -439,8 +446,7 @@ void matmul_mfma_f64(const DevMat &dm, const TuneCfg &cfg, int64_t m, double alp
                            P.adm_depth, E, xh, ldh, cnt, sk);
         mark(1);
     } else {
-        hipLaunchKernelGGL(mfma::k_fwd_leaf<NJ>, dim3(dm.L, gy), dim3(256), 0, st, dm.k, m, dm.leaves, dm.first,
-                           dm.size, dm.perm, V, Xt, ldxt, 1, xh, ldh, sk);
+        fwd_leaf();
         mark(1);
         up_levels(dm.depth_max - 1, P.adm_depth);
     }

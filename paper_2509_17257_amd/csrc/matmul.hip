@@ -314,7 +314,7 @@ void matmul_mfma_f64(const DevMat &dm, const TuneCfg &cfg, int64_t m, double alp
     if (!to || (ldx & 1) || ((uintptr_t)X & 15)) {
         ldxt = even_ld(m);
         const int64_t cnt = dm.n * ldxt;
-        hipLaunchKernelGGL(mfma::k_gather, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, dm.n, m,
+        hipLaunchKernelGGL(mfma::k_gather, dim3((unsigned)((cnt / 2 + 255) / 256)), dim3(256), 0, st, dm.n, m,
                            to ? nullptr : dm.perm, X, ldx, xt_ws, ldxt);
         Xt = xt_ws;
     }
@@ -573,7 +573,7 @@ hipError_t run_forward_transform(const DevMat &dm, int64_t m, const double *X, i
         if (!tree_order || (ldx & 1) || ((uintptr_t)X & 15)) {
             ldxt = even_ld(m);
             const int64_t cnt = dm.n * ldxt;
-            hipLaunchKernelGGL(mfma::k_gather, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, dm.n, m,
+            hipLaunchKernelGGL(mfma::k_gather, dim3((unsigned)((cnt / 2 + 255) / 256)), dim3(256), 0, st, dm.n, m,
                                tree_order ? nullptr : dm.perm, X, ldx, xt_ws, ldxt);
             Xt = xt_ws;
         }

@@ -126,10 +126,23 @@ __device__ inline bool for_columns(int64_t m, int nblk, const double *part, cons
     for (int64_t jc = 0; jc < m; jc += mm) {
         const int64_t j = jc + jl;
         double a = 0.0, c = 0.0;
-        if (r < R && j < m)
-            for (int bb = b0 + r; bb < b1; bb += R) {
-                a += part[(int64_t)bb * m + j];
-                c += part[((int64_t)nblk + bb) * m + j];
+        // eight blocks per step, their loads issued together (clamped addresses) and added in
+        // block order (a block past the end adds an exact zero): the sums keep their order
+        if (r < R && j < m && b1 > b0)
+            for (int bb = b0 + r; bb < b1; bb += 8 * R) {
+                double va[8], vc[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int64_t b = min(bb + u * R, b1 - 1);
+                    va[u] = part[b * m + j];
+                    vc[u] = part[((int64_t)nblk + b) * m + j];
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const bool in = bb + u * R < b1;
+                    a += in ? va[u] : 0.0;
+                    c += in ? vc[u] : 0.0;
+                }
             }
         red[0][tid] = a;
         red[1][tid] = c;

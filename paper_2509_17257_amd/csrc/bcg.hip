@@ -90,8 +90,15 @@ __global__ void k_gram_sum(int m, int nblk, const double *__restrict__ part, dou
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     const int q = blockIdx.y;
     if (e >= mm) return;
+    // eight blocks per step, loaded together (clamped) and added in block order
     double s = 0.0;
-    for (int b = 0; b < nblk; ++b) s += part[((int64_t)q * nblk + b) * mm + e];
+    for (int b0 = 0; b0 < nblk; b0 += 8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = part[((int64_t)q * nblk + min(b0 + u, nblk - 1)) * mm + e];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += b0 + u < nblk ? v[u] : 0.0;
+    }
     (q ? G1 : G0)[e] = s;
 }
 

@@ -14,9 +14,8 @@
 // the leaf is skipped (a band of one strip has its own code); every load is issued
 // unconditionally from a clamped address, so the wait counters stay exact, and the
 // k-rows of B past the item are zeroed where they are used.  No operand goes through
-// LDS and no wave waits for another: rows are padded to 16 and the contraction to a
-// 16-long round, against a 32-row half and a 16-step (64-long) round in the
-// wave-per-term form.
+// LDS and no wave waits for another; rows are padded to 16 (a 32-row half in the
+// wave-per-term form), the contraction to a 16-long round in both.
 //
 // Complex operator (n_plane > 0): every near block is two items, its real plane on
 // X and its imaginary plane on J X (column pairs (re, im) -> (-im, re), applied to

@@ -156,21 +156,22 @@ __global__ __launch_bounds__(256) void k_bcg_solve(int m, const double *__restri
         __syncthreads();
     }
     if (tid == 0 && bad) st->breakdown = 1;
-    // one column of F per thread: forward then backward substitution
+    // one column of F per thread: forward then backward substitution, the column's
+    // vector in LDS (a per-thread array with run-time indices would live in scratch memory)
+    __shared__ double Y[kMaxM][kMaxM + 1];
     for (int col = tid; col < m; col += 256) {
-        double y[kMaxM];
         for (int a = 0; a < r; ++a) {
             double v = F[idx[a] * m + col];
-            for (int q = 0; q < a; ++q) v -= L[a][q] * y[q];
-            y[a] = v / L[a][a];
+            for (int q = 0; q < a; ++q) v -= L[a][q] * Y[q][col];
+            Y[a][col] = v / L[a][a];
         }
         for (int a = r - 1; a >= 0; --a) {
-            double v = y[a];
-            for (int q = a + 1; q < r; ++q) v -= L[q][a] * y[q];
-            y[a] = v / L[a][a];
+            double v = Y[a][col];
+            for (int q = a + 1; q < r; ++q) v -= L[q][a] * Y[q][col];
+            Y[a][col] = v / L[a][a];
         }
         for (int j = 0; j < m; ++j) Cm[j * m + col] = 0.0;
-        for (int a = 0; a < r; ++a) Cm[idx[a] * m + col] = sign * y[a];
+        for (int a = 0; a < r; ++a) Cm[idx[a] * m + col] = sign * Y[a][col];
     }
 }
 
@@ -180,15 +181,16 @@ __device__ inline void write_tinv(int m, int r, const double (*lv)[kMaxM + 1], c
                                   double *M) {
     for (int e = threadIdx.x; e < m * m; e += 256) M[e] = 0.0;
     __syncthreads();
+    // column q per thread, its vector in LDS (not in scratch memory)
+    __shared__ double xs[kMaxM][kMaxM + 1];
     for (int q = threadIdx.x; q < r; q += 256) {
-        double x[kMaxM];
-        x[q] = 1.0 / dg[q];
+        xs[q][q] = 1.0 / dg[q];
         for (int a = q - 1; a >= 0; --a) {
             double v = 0.0;
-            for (int c = a + 1; c <= q; ++c) v += lv[a][piv[c]] * x[c];
-            x[a] = -v / dg[a];
+            for (int c = a + 1; c <= q; ++c) v += lv[a][piv[c]] * xs[c][q];
+            xs[a][q] = -v / dg[a];
         }
-        for (int a = 0; a <= q; ++a) M[piv[a] * m + piv[q]] = x[a];
+        for (int a = 0; a <= q; ++a) M[piv[a] * m + piv[q]] = xs[a][q];
     }
 }
 
@@ -200,9 +202,12 @@ __global__ __launch_bounds__(256) void k_bcg_orth1(int m, const double *__restri
     __shared__ int piv[kMaxM], act[kMaxM];
     __shared__ int rank, stop, best;
     __shared__ double dmax;
+    __shared__ double Ws[kMaxM][kMaxM + 1];
     const int tid = threadIdx.x;
+    for (int e = tid; e < m * m; e += 256) Ws[e / m][e % m] = W[e];
+    __syncthreads();
     for (int j = tid; j < m; j += 256) {
-        d[j] = W[j * m + j];
+        d[j] = Ws[j][j];
         act[j] = 0;
     }
     __syncthreads();
@@ -233,7 +238,7 @@ __global__ __launch_bounds__(256) void k_bcg_orth1(int m, const double *__restri
         if (stop) break;
         for (int j = tid; j < m; j += 256) {
             if (act[j]) continue;
-            double v = W[j * m + best];
+            double v = Ws[j][best];
             for (int q = 0; q < k; ++q) v -= lv[q][j] * lv[q][best];
             lv[k][j] = v / dg[k];
             d[j] -= lv[k][j] * lv[k][j];
@@ -256,20 +261,22 @@ __global__ __launch_bounds__(256) void k_bcg_orth2(int m, const double *__restri
     __shared__ double lv[kMaxM][kMaxM + 1];
     __shared__ double dg[kMaxM];
     __shared__ int piv[kMaxM];
+    __shared__ double Ws[kMaxM][kMaxM + 1];
     const int tid = threadIdx.x, r = st->rank;
     for (int j = tid; j < r; j += 256) piv[j] = st->piv[j];
+    for (int e = tid; e < m * m; e += 256) Ws[e / m][e % m] = W[e];
     __syncthreads();
     for (int q = 0; q < r; ++q) {
         if (tid == 0) {
             const int c = piv[q];
-            double v = W[c * m + c];
+            double v = Ws[c][c];
             for (int a = 0; a < q; ++a) v -= lv[a][c] * lv[a][c];
             dg[q] = sqrt(v > 0.0 ? v : 0.0);
         }
         __syncthreads();
         for (int q2 = q + 1 + tid; q2 < r; q2 += 256) {
             const int c = piv[q], c2 = piv[q2];
-            double u = W[c2 * m + c];
+            double u = Ws[c2][c];
             for (int a = 0; a < q; ++a) u -= lv[a][c2] * lv[a][c];
             lv[q][c2] = u / dg[q];
         }

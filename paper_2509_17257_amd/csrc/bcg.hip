@@ -23,7 +23,6 @@ namespace {
 
 constexpr int kMaxM = 64;      // block size limit of this variant
 constexpr double kDrop = 1e-6; // deflation threshold (relative column norm)
-constexpr int kGramRows = 16;  // rows staged per step in the Gram kernel
 
 struct BcgState {
     int32_t rank, all_conv, iter, breakdown;
@@ -35,52 +34,71 @@ struct BcgState {
     double rnorm[kMaxM];
 };
 
-// part[(pair * nblk + blk) * m * m + a * m + b] = sum over the block's rows of U[i][a] V[i][b]
-__global__ __launch_bounds__(256) void k_gram_part(int64_t n, int m, int nblk, const double *__restrict__ U0,
+// part[(pair * nblk + blk) * m * m + a * m + b] = sum over the block's rows of U[i][a] V[i][b],
+// on the FP64 matrix cores: U^T V as a contraction over the block's rows, A = U^T (16 lanes
+// over 16 consecutive columns of a row of U) and B = V (likewise), both straight from
+// memory.  Wave w takes the 4-row steps w, w + 4, ... of the block; rows past the block are
+// zero in U; the four waves' tiles are added in LDS in wave order.  MT = ceil(m / 16) tiles
+// per dimension.
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+template <int MT>
+__global__ __launch_bounds__(256) void k_gram_mfma(int64_t n, int m, int nblk, const double *__restrict__ U0,
                                                    const double *__restrict__ V0, const double *__restrict__ U1,
                                                    const double *__restrict__ V1, double *__restrict__ part) {
-    __shared__ double su[2][kGramRows][kMaxM], sv[2][kGramRows][kMaxM];
-    const int tid = threadIdx.x, mm = m * m;
-    const int npair = U1 ? 2 : 1;
+    __shared__ double red[kMaxM * kMaxM];
+    const int tid = threadIdx.x, lane = tid & 63, lr = lane & 15, lq = lane >> 4;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int mm = m * m;
     const int64_t rows = (n + nblk - 1) / nblk;
     const int64_t r0 = (int64_t)blockIdx.x * rows, r1 = min(n, r0 + rows);
-    double acc[2][16] = {};
-    for (int64_t c0 = r0; c0 < r1; c0 += kGramRows) {
-        const int cr = (int)min<int64_t>(kGramRows, r1 - c0);
-        for (int e = tid; e < kGramRows * m; e += 256) {
-            const int i = e / m, a = e % m;
-            const bool ok = i < cr;
-            su[0][i][a] = ok ? U0[(c0 + i) * m + a] : 0.0;
-            sv[0][i][a] = ok ? V0[(c0 + i) * m + a] : 0.0;
-            if (npair == 2) {
-                su[1][i][a] = ok ? U1[(c0 + i) * m + a] : 0.0;
-                sv[1][i][a] = ok ? V1[(c0 + i) * m + a] : 0.0;
+    const int nstep = r1 > r0 ? (int)((r1 - r0 + 3) >> 2) : 0;
+    for (int q = 0; q < (U1 ? 2 : 1); ++q) {
+        const double *U = q ? U1 : U0, *V = q ? V1 : V0;
+        dbl4 acc[MT][MT];
+#pragma unroll
+        for (int I = 0; I < MT; ++I)
+#pragma unroll
+            for (int J = 0; J < MT; ++J) acc[I][J] = dbl4{0.0, 0.0, 0.0, 0.0};
+        for (int st = w; st < nstep; st += 4) {
+            const int64_t i = r0 + 4 * st + lq;
+            const bool in = i < r1;
+            const int64_t ic = in ? i : r1 - 1;
+            double a[MT], b[MT];
+#pragma unroll
+            for (int I = 0; I < MT; ++I) {
+                const int c = min(16 * I + lr, m - 1);
+                a[I] = U[ic * m + c];
+                b[I] = V[ic * m + c];
+            }
+#pragma unroll
+            for (int I = 0; I < MT; ++I) {
+                const double av = in ? a[I] : 0.0;
+#pragma unroll
+                for (int J = 0; J < MT; ++J)
+                    acc[I][J] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b[J], acc[I][J], 0, 0, 0);
             }
         }
-        __syncthreads();
+        // D layout of the 16x16x4 f64 MFMA: lane l, register r -> row l / 16 + 4 r, column l % 16
+        for (int ww = 0; ww < 4; ++ww) {
+            if (w == ww)
 #pragma unroll
-        for (int q = 0; q < 2; ++q)
-            if (q < npair)
+                for (int I = 0; I < MT; ++I)
 #pragma unroll
-            for (int u = 0; u < 16; ++u) {
-                const int e = tid + 256 * u;
-                if (e < mm) {
-                    const int a = e / m, b = e % m;
-                    double s = acc[q][u];
-                    for (int i = 0; i < kGramRows; ++i) s += su[q][i][a] * sv[q][i][b];
-                    acc[q][u] = s;
-                }
-            }
+                    for (int J = 0; J < MT; ++J)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const int a = 16 * I + lq + 4 * r, b = 16 * J + lr;
+                            if (a < m && b < m) {
+                                double *cell = &red[a * m + b];
+                                *cell = ww == 0 ? acc[I][J][r] : *cell + acc[I][J][r];
+                            }
+                        }
+            __syncthreads();
+        }
+        for (int e = tid; e < mm; e += 256) part[((int64_t)q * nblk + blockIdx.x) * mm + e] = red[e];
         __syncthreads();
     }
-#pragma unroll
-    for (int q = 0; q < 2; ++q)
-        if (q < npair)
-#pragma unroll
-        for (int u = 0; u < 16; ++u) {
-            const int e = tid + 256 * u;
-            if (e < mm) part[((int64_t)q * nblk + blockIdx.x) * mm + e] = acc[q][u];
-        }
 }
 
 // G_q[e] = sum over blocks (fixed order) of the partial sums
@@ -377,7 +395,12 @@ h2x_status run_block_cg_shared(const DevMat &dm, const h2x_cg_params &prm, int64
     };
     auto gram2 = [&](const double *U0, const double *V0, const double *U1, const double *V1, double *G0,
                      double *G1) {
-        hipLaunchKernelGGL(k_gram_part, dim3(w.nblk), dim3(256), 0, st, n, mi, w.nblk, U0, V0, U1, V1, w.part);
+        switch ((mi + 15) / 16) {
+            case 1: hipLaunchKernelGGL(k_gram_mfma<1>, dim3(w.nblk), dim3(256), 0, st, n, mi, w.nblk, U0, V0, U1, V1, w.part); break;
+            case 2: hipLaunchKernelGGL(k_gram_mfma<2>, dim3(w.nblk), dim3(256), 0, st, n, mi, w.nblk, U0, V0, U1, V1, w.part); break;
+            case 3: hipLaunchKernelGGL(k_gram_mfma<3>, dim3(w.nblk), dim3(256), 0, st, n, mi, w.nblk, U0, V0, U1, V1, w.part); break;
+            default: hipLaunchKernelGGL(k_gram_mfma<4>, dim3(w.nblk), dim3(256), 0, st, n, mi, w.nblk, U0, V0, U1, V1, w.part); break;
+        }
         hipLaunchKernelGGL(k_gram_sum, dim3(gs.x, U1 ? 2 : 1), dim3(256), 0, st, mi, w.nblk, (const double *)w.part,
                            G0, G1);
     };

@@ -130,11 +130,20 @@ __global__ __launch_bounds__(256) void k_gm_dots(int64_t n, int64_t m, const T *
     const int64_t blk = blockIdx.x, nblk = gridDim.x, c = (int64_t)blockIdx.y * kCols + jl, j = blockIdx.z;
     const int64_t r0 = blk * kRowsPerBlk, r1 = min(n, r0 + kRowsPerBlk);
     const T *q = Q + j * n * m;
+    // every load unconditional from a clamped address; out-of-range terms add an exact zero
     T s = f_zero(T{});
+    const int64_t cc = min(c, m - 1);
+    T qv[kRowsPerThread], av[kRowsPerThread];
+#pragma unroll
+    for (int u = 0; u < kRowsPerThread; ++u) {
+        const int64_t r = min(r0 + rg + kRowGroups * u, r1 - 1);
+        qv[u] = q[r * m + cc];
+        av[u] = a[r * m + cc];
+    }
 #pragma unroll
     for (int u = 0; u < kRowsPerThread; ++u) {
         const int64_t r = r0 + rg + kRowGroups * u;
-        if (c < m && r < r1) s = f_add(s, f_cmul(q[r * m + c], a[r * m + c]));
+        if (c < m && r < r1) s = f_add(s, f_cmul(qv[u], av[u]));
     }
     red[rg][jl] = s;
     __syncthreads();
@@ -202,14 +211,29 @@ __global__ __launch_bounds__(256) void k_gm_update(int64_t n, int64_t m, int k, 
         av[u] = (c < m && r < r1) ? a[r * m + c] : f_zero(T{});
     }
     if (sub) {
-        for (int j = 0; j <= k; ++j) {
-            const T *q = Q + (int64_t)j * n * m;
-            const T h = cl.H[(c * (ell + 1) + j) * ell + k];
+        // rows past the block read the block's last row (every load unconditional, so the
+        // loads of the next basis vectors are in flight during the current one's updates);
+        // their values are never stored or counted.  JU basis vectors per pass, each
+        // subtracted in order j = 0, 1, ..., k as in the plain loop.
+        constexpr int JU = sizeof(T) > sizeof(double) ? 2 : 4;
+        int64_t ro[kRowsPerThread];
 #pragma unroll
-            for (int u = 0; u < kRowsPerThread; ++u) {
-                const int64_t r = r0 + rg + kRowGroups * u;
-                if (r < r1) av[u] = f_sub(av[u], f_mul(q[r * m + c], h));
+        for (int u = 0; u < kRowsPerThread; ++u) ro[u] = min(r0 + rg + kRowGroups * u, r1 - 1) * m + c;
+        for (int j0 = 0; j0 <= k; j0 += JU) {
+            T qv[JU][kRowsPerThread], h[JU];
+#pragma unroll
+            for (int jj = 0; jj < JU; ++jj) {
+                const int j = min(j0 + jj, k);
+                const T *q = Q + (int64_t)j * n * m;
+                h[jj] = cl.H[(c * (ell + 1) + j) * ell + k];
+#pragma unroll
+                for (int u = 0; u < kRowsPerThread; ++u) qv[jj][u] = q[ro[u]];
             }
+#pragma unroll
+            for (int jj = 0; jj < JU; ++jj)
+                if (j0 + jj <= k)
+#pragma unroll
+                    for (int u = 0; u < kRowsPerThread; ++u) av[u] = f_sub(av[u], f_mul(qv[jj][u], h[jj]));
         }
     }
     double s = 0.0;

@@ -21,6 +21,7 @@ namespace h2x {
 namespace {
 
 constexpr int kDotCols = 32;  // columns per work-group in the dot kernels
+constexpr int kScalarThreads = 1024;  // threads of the per-system scalar kernels
 
 struct CgState {
     int32_t all_conv, skip, iter, pad;
@@ -116,10 +117,10 @@ __device__ inline double sum_part(const double *part, int pair, int nblk, int64_
 // and returns whether the column is still open (not converged, not broken down).
 template <typename F>
 __device__ inline bool for_columns(int64_t m, int nblk, const double *part, const Segs &sg, int s, F fn) {
-    __shared__ double red[2][256];
+    __shared__ double red[2][kScalarThreads];
     __shared__ int open;
     const int tid = threadIdx.x;
-    const int mm = (int)min<int64_t>(m, 256), R = 256 / mm;
+    const int mm = (int)min<int64_t>(m, kScalarThreads), R = kScalarThreads / mm;
     const int r = tid / mm, jl = tid % mm;
     const int b0 = sg.seg_blk[s], b1 = sg.seg_blk[s + 1];
     if (tid == 0) open = 0;
@@ -161,7 +162,7 @@ __device__ inline bool for_columns(int64_t m, int nblk, const double *part, cons
 }
 
 // initial norms: pairs (B, B) and (R, R); one work-group per system
-__global__ void k_cg_init(int64_t m, int nblk, const double *part, double rtol, CgCols cols, Segs sg) {
+__global__ __launch_bounds__(kScalarThreads) void k_cg_init(int64_t m, int nblk, const double *part, double rtol, CgCols cols, Segs sg) {
     const int s = blockIdx.x;
     const bool open = for_columns(m, nblk, part, sg, s, [&](int64_t, int64_t e, double bb, double rr) {
         cols.bnorm[e] = sqrt(bb);
@@ -203,7 +204,7 @@ __global__ void k_cg_state(int init, CgState *state, Segs sg) {
 }
 
 // pairs (P, AP) and (P, R): beta, alpha, breakdown detection; one work-group per system
-__global__ void k_cg_alpha(int64_t m, int nblk, const double *part, int freeze_converged, CgState *state,
+__global__ __launch_bounds__(kScalarThreads) void k_cg_alpha(int64_t m, int nblk, const double *part, int freeze_converged, CgState *state,
                            CgCols cols, Segs sg) {
     const int skip = state->all_conv;
     if (blockIdx.x == 0 && threadIdx.x == 0) state->skip = skip;
@@ -251,7 +252,7 @@ __global__ __launch_bounds__(256) void k_cg_update_xr(int64_t m, int nblk, Segs 
 }
 
 // gamma, convergence test; one work-group per system
-__global__ void k_cg_gamma(int64_t m, int nblk, const double *part, double rtol, const CgState *state, CgCols cols,
+__global__ __launch_bounds__(kScalarThreads) void k_cg_gamma(int64_t m, int nblk, const double *part, double rtol, const CgState *state, CgCols cols,
                            Segs sg) {
     if (state->skip) return;
     const int s = blockIdx.x;
@@ -307,7 +308,7 @@ __global__ void k_rel_track(int64_t m, double delta, CgState *state, CgCols cols
 // first pair of part holds its squared column norms (the second pair is not
 // used).  Recursive norms, maxima and convergence restart from the true
 // residual; the system stops when every column has converged (or broken down).
-__global__ void k_rel_replace(int64_t m, int nblk, const double *part, double rtol, CgState *state, CgCols cols,
+__global__ __launch_bounds__(kScalarThreads) void k_rel_replace(int64_t m, int nblk, const double *part, double rtol, CgState *state, CgCols cols,
                               Segs sg, double *rmax) {
     const bool open = for_columns(m, nblk, part, sg, 0, [&](int64_t, int64_t e, double rr, double) {
         cols.rr[e] = rr;
@@ -608,11 +609,11 @@ h2x_status run_block_cg_batch(const DevMat *const *mats, int32_t nmat, const h2x
         if (ee != hipSuccess) return ee;
         hipLaunchKernelGGL(k_sdots, gd, dim3(256), 0, s, m, nblk, sg, w.P, w.AP, w.P, w.R, w.part,
                            (const CgState *)w.state);
-        hipLaunchKernelGGL(k_cg_alpha, dim3(L.nseg), dim3(256), 0, s, m, nblk, w.part, prm.freeze_converged,
+        hipLaunchKernelGGL(k_cg_alpha, dim3(L.nseg), dim3(kScalarThreads), 0, s, m, nblk, w.part, prm.freeze_converged,
                            w.state, w.cols, sg);
         hipLaunchKernelGGL(k_cg_update_xr, gd, dim3(256), 0, s, m, nblk, sg, w.Xt, w.R, w.P, w.AP, w.part,
                            (const CgState *)w.state, w.cols);
-        hipLaunchKernelGGL(k_cg_gamma, dim3(L.nseg), dim3(256), 0, s, m, nblk, w.part, prm.rtol,
+        hipLaunchKernelGGL(k_cg_gamma, dim3(L.nseg), dim3(kScalarThreads), 0, s, m, nblk, w.part, prm.rtol,
                            (const CgState *)w.state, w.cols, sg);
         hipLaunchKernelGGL(k_cg_state, dim3(1), dim3(256), 0, s, 0, w.state, sg);
         hipLaunchKernelGGL(k_cg_update_p, gd, dim3(256), 0, s, m, sg, w.R, w.P, (const CgState *)w.state, w.cols);
@@ -626,7 +627,7 @@ h2x_status run_block_cg_batch(const DevMat *const *mats, int32_t nmat, const h2x
         if (ee != hipSuccess) return ee;
         hipLaunchKernelGGL(k_sdots, gd, dim3(256), 0, s, m, nblk, sg, w.R, w.R, (const double *)nullptr,
                            (const double *)nullptr, w.part, (const CgState *)nullptr);
-        hipLaunchKernelGGL(k_rel_replace, dim3(1), dim3(256), 0, s, m, nblk, (const double *)w.part, prm.rtol,
+        hipLaunchKernelGGL(k_rel_replace, dim3(1), dim3(kScalarThreads), 0, s, m, nblk, (const double *)w.part, prm.rtol,
                            w.state, w.cols, sg, w.rmax);
         return hipGetLastError();
     };
@@ -647,12 +648,12 @@ h2x_status run_block_cg_batch(const DevMat *const *mats, int32_t nmat, const h2x
     hipLaunchKernelGGL(k_copy, dim3(g1), dim3(256), 0, st, nm, w.R, w.P);
     hipLaunchKernelGGL(k_sdots, gd, dim3(256), 0, st, m, nblk, sg, w.Bt, w.Bt, w.R, w.R, w.part,
                        (const CgState *)nullptr);
-    hipLaunchKernelGGL(k_cg_init, dim3(L.nseg), dim3(256), 0, st, m, nblk, w.part, prm.rtol, w.cols, sg);
+    hipLaunchKernelGGL(k_cg_init, dim3(L.nseg), dim3(kScalarThreads), 0, st, m, nblk, w.part, prm.rtol, w.cols, sg);
     hipLaunchKernelGGL(k_cg_state, dim3(1), dim3(256), 0, st, 1, w.state, sg);
     if (hi) {
         hipLaunchKernelGGL(k_sdots, gd, dim3(256), 0, st, m, nblk, sg, w.R, w.R, (const double *)nullptr,
                            (const double *)nullptr, w.part, (const CgState *)nullptr);
-        hipLaunchKernelGGL(k_rel_replace, dim3(1), dim3(256), 0, st, m, nblk, (const double *)w.part, prm.rtol,
+        hipLaunchKernelGGL(k_rel_replace, dim3(1), dim3(kScalarThreads), 0, st, m, nblk, (const double *)w.part, prm.rtol,
                            w.state, w.cols, sg, w.rmax);
     }
 

@@ -155,18 +155,21 @@ __global__ __launch_bounds__(256) void k_bcg_solve(int m, const double *__restri
         bad = 0;
     }
     __syncthreads();
+    // G on the active set and all of F staged in LDS with every load issued up front
+    __shared__ double Fs[kMaxM][kMaxM + 1];
     for (int e = tid; e < r * r; e += 256) L[e / r][e % r] = G[idx[e / r] * m + idx[e % r]];
+    for (int e = tid; e < m * m; e += 256) Fs[e / m][e % m] = F[e];
     __syncthreads();
-    // right-looking Cholesky, lower triangle
+    // right-looking Cholesky, lower triangle.  Every thread forms the pivot's square root
+    // itself and scales its entries of column k; the root is stored on the diagonal in the
+    // update phase, which does not read it.
     for (int k = 0; k < r; ++k) {
-        if (tid == 0) {
-            const double v = L[k][k];
-            if (!(v > 0.0)) bad = 1;
-            L[k][k] = sqrt(v > 0.0 ? v : 1.0);
-        }
+        const double v = L[k][k];
+        const double dk = sqrt(v > 0.0 ? v : 1.0);
+        if (tid == 0 && !(v > 0.0)) bad = 1;
+        for (int i = k + 1 + tid; i < r; i += 256) L[i][k] /= dk;
         __syncthreads();
-        for (int i = k + 1 + tid; i < r; i += 256) L[i][k] /= L[k][k];
-        __syncthreads();
+        if (tid == 0) L[k][k] = dk;
         for (int e = tid; e < (r - k - 1) * (r - k - 1); e += 256) {
             const int i = k + 1 + e / (r - k - 1), j = k + 1 + e % (r - k - 1);
             if (j <= i) L[i][j] -= L[i][k] * L[j][k];
@@ -179,12 +182,14 @@ __global__ __launch_bounds__(256) void k_bcg_solve(int m, const double *__restri
     __shared__ double Y[kMaxM][kMaxM + 1];
     for (int col = tid; col < m; col += 256) {
         for (int a = 0; a < r; ++a) {
-            double v = F[idx[a] * m + col];
+            double v = Fs[idx[a]][col];
+#pragma unroll 8
             for (int q = 0; q < a; ++q) v -= L[a][q] * Y[q][col];
             Y[a][col] = v / L[a][a];
         }
         for (int a = r - 1; a >= 0; --a) {
             double v = Y[a][col];
+#pragma unroll 8
             for (int q = a + 1; q < r; ++q) v -= L[q][a] * Y[q][col];
             Y[a][col] = v / L[a][a];
         }
@@ -197,7 +202,13 @@ __global__ __launch_bounds__(256) void k_bcg_solve(int m, const double *__restri
 // scattered to M[piv[q']][piv[q]] (all other entries zero): Z M has orthonormalised columns.
 __device__ inline void write_tinv(int m, int r, const double (*lv)[kMaxM + 1], const double *dg, const int *piv,
                                   double *M) {
+    // T above the diagonal gathered into pivot order first (no dependent reads below)
+    __shared__ double tp[kMaxM][kMaxM + 1];
     for (int e = threadIdx.x; e < m * m; e += 256) M[e] = 0.0;
+    for (int e = threadIdx.x; e < r * r; e += 256) {
+        const int a = e / r, c = e % r;
+        if (a < c) tp[a][c] = lv[a][piv[c]];
+    }
     __syncthreads();
     // column q per thread, its vector in LDS (not in scratch memory)
     __shared__ double xs[kMaxM][kMaxM + 1];
@@ -205,7 +216,8 @@ __device__ inline void write_tinv(int m, int r, const double (*lv)[kMaxM + 1], c
         xs[q][q] = 1.0 / dg[q];
         for (int a = q - 1; a >= 0; --a) {
             double v = 0.0;
-            for (int c = a + 1; c <= q; ++c) v += lv[a][piv[c]] * xs[c][q];
+#pragma unroll 8
+            for (int c = a + 1; c <= q; ++c) v += tp[a][c] * xs[c][q];
             xs[a][q] = -v / dg[a];
         }
         for (int a = 0; a <= q; ++a) M[piv[a] * m + piv[q]] = xs[a][q];
@@ -238,18 +250,47 @@ __global__ __launch_bounds__(256) void k_bcg_orth1(int m, const double *__restri
     }
     __syncthreads();
     for (int k = 0; k < m; ++k) {
-        if (tid == 0) {
+        if (tid < 64) {
+            // pivot: the first column, in column order, of largest d among those not yet
+            // taken (a scan that keeps the earlier column on ties and never moves to a NaN;
+            // a NaN in the first candidate stays chosen), found by the first wave with a
+            // butterfly over (valid, d, column)
+            const int j = tid;
+            const bool cand = j < m && !act[j];
+            const unsigned long long cm = __ballot(cand);
             int b = -1;
-            for (int j = 0; j < m; ++j)
-                if (!act[j] && (b < 0 || d[j] > d[b])) b = j;
-            if (b < 0 || !(dmax > 0.0) || !(d[b] > kDrop * kDrop * dmax)) {
-                stop = 1;
-            } else {
-                act[b] = 1;
-                piv[k] = b;
-                dg[k] = sqrt(d[b]);
-                best = b;
-                rank = k + 1;
+            if (cm != 0) {
+                const int j0 = __ffsll(cm) - 1;
+                if (isnan(d[j0])) {
+                    b = j0;
+                } else {
+                    bool ok = cand && !isnan(d[j]);
+                    double v = ok ? d[j] : 0.0;
+                    int ix = j;
+#pragma unroll
+                    for (int o = 32; o > 0; o >>= 1) {
+                        const bool ok2 = __shfl_xor(ok ? 1 : 0, o) != 0;
+                        const double v2 = __shfl_xor(v, o);
+                        const int ix2 = __shfl_xor(ix, o);
+                        if (ok2 && (!ok || v2 > v || (v2 == v && ix2 < ix))) {
+                            ok = true;
+                            v = v2;
+                            ix = ix2;
+                        }
+                    }
+                    b = ix;
+                }
+            }
+            if (tid == 0) {
+                if (b < 0 || !(dmax > 0.0) || !(d[b] > kDrop * kDrop * dmax)) {
+                    stop = 1;
+                } else {
+                    act[b] = 1;
+                    piv[k] = b;
+                    dg[k] = sqrt(d[b]);
+                    best = b;
+                    rank = k + 1;
+                }
             }
         }
         __syncthreads();
@@ -257,6 +298,7 @@ __global__ __launch_bounds__(256) void k_bcg_orth1(int m, const double *__restri
         for (int j = tid; j < m; j += 256) {
             if (act[j]) continue;
             double v = Ws[j][best];
+#pragma unroll 8
             for (int q = 0; q < k; ++q) v -= lv[q][j] * lv[q][best];
             lv[k][j] = v / dg[k];
             d[j] -= lv[k][j] * lv[k][j];
@@ -288,6 +330,7 @@ __global__ __launch_bounds__(256) void k_bcg_orth2(int m, const double *__restri
         if (tid == 0) {
             const int c = piv[q];
             double v = Ws[c][c];
+#pragma unroll 8
             for (int a = 0; a < q; ++a) v -= lv[a][c] * lv[a][c];
             dg[q] = sqrt(v > 0.0 ? v : 0.0);
         }
@@ -295,6 +338,7 @@ __global__ __launch_bounds__(256) void k_bcg_orth2(int m, const double *__restri
         for (int q2 = q + 1 + tid; q2 < r; q2 += 256) {
             const int c = piv[q], c2 = piv[q2];
             double u = Ws[c2][c];
+#pragma unroll 8
             for (int a = 0; a < q; ++a) u -= lv[a][c2] * lv[a][c];
             lv[q][c2] = u / dg[q];
         }

@@ -63,20 +63,18 @@ __global__ void k_copy(int64_t count, const double *__restrict__ src, double *__
     if (e < count) dst[e] = src[e];
 }
 
-// Partial sums of up to two column-wise dot products over rows [r0, r1):
-// part[(pair * nblk + blockIdx.x) * m + j].  Row ownership is fixed, the
-// reduction order too.
-__device__ inline void block_dots(int64_t r0, int64_t r1, int64_t m, int nblk, const double *u0, const double *v0,
-                                  const double *u1, const double *v1, double *part) {
+// Row-block kernels: thread (rg, jl) of a 256-thread work-group takes column
+// blockIdx.y * kDotCols + jl and the rows r0 + rg, r0 + rg + 8, ... of its row
+// block.  The rows are visited eight at a time, all their loads issued first from
+// clamped addresses, then used in row order (a row past the end is skipped).
+constexpr int kRowStep = 8;
+
+// Second stage of the partial sums: the eight row groups' sums of column j added
+// in group order, part[(pair * nblk + blockIdx.x) * m + j].
+__device__ inline void store_dots(double s0, double s1, int64_t m, int nblk, bool two, double *part) {
     __shared__ double red[2][8][kDotCols];
     const int tid = threadIdx.x, rg = tid >> 5, jl = tid & 31;
     const int64_t j = (int64_t)blockIdx.y * kDotCols + jl;
-    double s0 = 0.0, s1 = 0.0;
-    if (j < m)
-        for (int64_t i = r0 + rg; i < r1; i += 8) {
-            s0 += u0[i * m + j] * v0[i * m + j];
-            if (u1) s1 += u1[i * m + j] * v1[i * m + j];
-        }
     red[0][rg][jl] = s0;
     red[1][rg][jl] = s1;
     __syncthreads();
@@ -84,8 +82,39 @@ __device__ inline void block_dots(int64_t r0, int64_t r1, int64_t m, int nblk, c
         double a = 0.0, b = 0.0;
         for (int g = 0; g < 8; ++g) { a += red[0][g][jl]; b += red[1][g][jl]; }
         part[(int64_t)blockIdx.x * m + j] = a;
-        if (u1) part[((int64_t)nblk + blockIdx.x) * m + j] = b;
+        if (two) part[((int64_t)nblk + blockIdx.x) * m + j] = b;
     }
+}
+
+// Partial sums of up to two column-wise dot products over rows [r0, r1), each in
+// row order (fixed row ownership and reduction order).
+__device__ inline void block_dots(int64_t r0, int64_t r1, int64_t m, int nblk, const double *u0, const double *v0,
+                                  const double *u1, const double *v1, double *part) {
+    const int tid = threadIdx.x, rg = tid >> 5, jl = tid & 31;
+    const int64_t j = (int64_t)blockIdx.y * kDotCols + jl;
+    const bool two = u1 != nullptr;
+    double s0 = 0.0, s1 = 0.0;
+    if (j < m && r1 > r0)
+        for (int64_t i0 = r0 + rg; i0 < r1; i0 += 8 * kRowStep) {
+            double a[kRowStep], b[kRowStep], c[kRowStep], d[kRowStep];
+#pragma unroll
+            for (int u = 0; u < kRowStep; ++u) {
+                const int64_t i = min(i0 + 8 * u, r1 - 1);
+                a[u] = u0[i * m + j];
+                b[u] = v0[i * m + j];
+                if (two) {
+                    c[u] = u1[i * m + j];
+                    d[u] = v1[i * m + j];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kRowStep; ++u)
+                if (i0 + 8 * u < r1) {
+                    s0 += a[u] * b[u];
+                    if (two) s1 += c[u] * d[u];
+                }
+        }
+    store_dots(s0, s1, m, nblk, two, part);
 }
 
 // rows split evenly over nblk blocks (one system)
@@ -240,15 +269,41 @@ __global__ __launch_bounds__(256) void k_cg_update_xr(int64_t m, int nblk, Segs 
     const int64_t j = (int64_t)blockIdx.y * kDotCols + jl;
     const int64_t r0 = sg.blk_r0[blockIdx.x], r1 = sg.blk_r0[blockIdx.x + 1];
     const int64_t e = (int64_t)sg.blk_seg[blockIdx.x] * m + j;
-    if (j < m && cols.act[e]) {
-        const double a = cols.alpha[e];
-        for (int64_t i = r0 + rg; i < r1; i += 8) {
-            X[i * m + j] += a * P[i * m + j];
-            R[i * m + j] -= a * AP[i * m + j];
+    // x += alpha p, r -= alpha Ap on open columns, then the partial sums of Ap . r
+    // and r . r from the new r held in registers
+    double s0 = 0.0, s1 = 0.0;
+    if (j < m && r1 > r0) {
+        const bool act = cols.act[e] != 0;
+        const double a = act ? cols.alpha[e] : 0.0;
+        for (int64_t i0 = r0 + rg; i0 < r1; i0 += 8 * kRowStep) {
+            double xv[kRowStep], pv[kRowStep], rv[kRowStep], av[kRowStep];
+#pragma unroll
+            for (int u = 0; u < kRowStep; ++u) {
+                const int64_t i = min(i0 + 8 * u, r1 - 1);
+                rv[u] = R[i * m + j];
+                av[u] = AP[i * m + j];
+                if (act) {
+                    xv[u] = X[i * m + j];
+                    pv[u] = P[i * m + j];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kRowStep; ++u) {
+                const int64_t i = i0 + 8 * u;
+                if (i < r1) {
+                    double rn = rv[u];
+                    if (act) {
+                        X[i * m + j] = xv[u] + a * pv[u];
+                        rn = rv[u] - a * av[u];
+                        R[i * m + j] = rn;
+                    }
+                    s0 += av[u] * rn;
+                    s1 += rn * rn;
+                }
+            }
         }
     }
-    // each thread re-reads only the rows it just wrote, so no barrier is needed
-    block_dots(r0, r1, m, nblk, AP, R, R, R, part);
+    store_dots(s0, s1, m, nblk, true, part);
 }
 
 // gamma, convergence test; one work-group per system

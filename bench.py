@@ -744,6 +744,10 @@ def main():
 
     if args.cg:
         B = X
+        # a few iterations of each variant first, so that the timed solves include neither
+        # the first launch of a kernel nor the first allocation of the solver's workspace
+        for variant in ("independent", "shared"):
+            h2x.block_cg_solve(A, B, rtol=1e-8, max_iter=3, variant=variant)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         Xs, info = h2x.block_cg_solve(A, B, rtol=1e-8, max_iter=5000)

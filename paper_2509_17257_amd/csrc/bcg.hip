@@ -108,34 +108,68 @@ __global__ void k_gram_sum(int m, int nblk, const double *__restrict__ part, dou
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     const int q = blockIdx.y;
     if (e >= mm) return;
-    // eight blocks per step, loaded together (clamped) and added in block order
+    // blocks in groups of 16 loaded together from clamped addresses, the next group in
+    // flight while one is added; the sum runs in block order (past the end: exact zeros)
+    constexpr int U = 16;
+    const double *p = part + (int64_t)q * nblk * mm + e;
+    double v[U], x[U];
+    auto load = [&](double(&r)[U], int b0) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) r[u] = p[(int64_t)min(b0 + u, nblk - 1) * mm];
+    };
     double s = 0.0;
-    for (int b0 = 0; b0 < nblk; b0 += 8) {
-        double v[8];
+    load(v, 0);
+    for (int b0 = 0; b0 < nblk; b0 += 2 * U) {
+        load(x, b0 + U);
 #pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = part[((int64_t)q * nblk + min(b0 + u, nblk - 1)) * mm + e];
+        for (int u = 0; u < U; ++u) s += b0 + u < nblk ? v[u] : 0.0;
+        load(v, b0 + 2 * U);
 #pragma unroll
-        for (int u = 0; u < 8; ++u) s += b0 + u < nblk ? v[u] : 0.0;
+        for (int u = 0; u < U; ++u) s += b0 + U + u < nblk ? x[u] : 0.0;
     }
     (q ? G1 : G0)[e] = s;
 }
 
-// out = beta Yin + alpha U C  (n x m blocks, C m x m; Yin may alias out, beta == 0 ignores it)
+// out = beta Yin + alpha U C  (n x m blocks, C m x m; Yin may alias out, beta == 0 ignores it).
+// A work-group takes 2048 / MT rows (MT = m rounded up to 16): their rows of U are staged
+// in LDS with coalesced loads, and thread (rg, b) keeps column b of C in registers and forms
+// out[i][b] = sum_a U[i][a] C[a][b] (a in order) for rows i = rg, rg + 256 / m, ...
+template <int MT>
 __global__ __launch_bounds__(256) void k_tsmm(int64_t n, int m, const double *__restrict__ U,
                                               const double *__restrict__ Cm, const double *Yin, double *out,
-                                              double alpha, double beta, int rows_per_wg) {
-    __shared__ double sc[kMaxM * kMaxM];
-    for (int e = threadIdx.x; e < m * m; e += 256) sc[e] = Cm[e];
+                                              double alpha, double beta) {
+    constexpr int RW = 2048 / MT;  // rows per work-group
+    __shared__ __align__(16) double su[RW][MT];
+    const int tid = threadIdx.x;
+    const int64_t r0 = (int64_t)blockIdx.x * RW;
+    const int rows = (int)min<int64_t>(RW, n - r0);
+    const double *ut = U + r0 * m;
+    for (int e = tid; e < rows * m; e += 256) su[e / m][e % m] = ut[e];
+    const int b = tid % m, rg = tid / m, ng = 256 / m;
+    double c[MT];
+#pragma unroll
+    for (int a = 0; a < MT; ++a) c[a] = (a < m && rg < ng) ? Cm[a * m + b] : 0.0;
+    // rows per thread: at most NR, as 256 / m >= 256 / MT; their old values are loaded
+    // before the barrier (clamped addresses)
+    constexpr int NR = (RW + 256 / MT - 1) / (256 / MT);
+    double yv[NR];
+#pragma unroll
+    for (int t = 0; t < NR; ++t)
+        yv[t] = (beta != 0.0 && rg < ng) ? Yin[(r0 + min(rg + t * ng, rows - 1)) * m + b] : 0.0;
     __syncthreads();
-    const int64_t r0 = (int64_t)blockIdx.x * rows_per_wg;
-    const int64_t r1 = min(n, r0 + rows_per_wg);
-    for (int64_t e = r0 * m + threadIdx.x; e < r1 * m; e += 256) {
-        const int64_t i = e / m;
-        const int b = (int)(e % m);
-        const double *u = U + i * m;
+    if (rg >= ng) return;
+#pragma unroll
+    for (int t = 0; t < NR; ++t) {
+        const int i = rg + t * ng;
+        if (i >= rows) break;
         double s = 0.0;
-        for (int a = 0; a < m; ++a) s += u[a] * sc[a * m + b];
-        out[e] = (beta == 0.0) ? alpha * s : beta * Yin[e] + alpha * s;
+#pragma unroll
+        for (int a = 0; a < MT; a += 2) {
+            const double2 u2 = *(const double2 *)&su[i][a];
+            if (a < m) s += u2.x * c[a];
+            if (a + 1 < m) s += u2.y * c[a + 1];
+        }
+        out[(r0 + i) * m + b] = (beta == 0.0) ? alpha * s : beta * yv[t] + alpha * s;
     }
 }
 
@@ -430,7 +464,7 @@ h2x_status run_block_cg_shared(const DevMat &dm, const h2x_cg_params &prm, int64
     const int64_t n = dm.n, nm = n * m;
     const int mi = (int)m;
     const unsigned g1 = (unsigned)((nm + 255) / 256);
-    const int rpw = std::max(1, 2048 / mi);
+    const int mt = 16 * ((mi + 15) / 16), rpw = 2048 / mt;
     const unsigned gt = (unsigned)((n + rpw - 1) / rpw);
     const dim3 gs((unsigned)((m * m + 255) / 256), 2);
     auto fail = [&](hipError_t e) {
@@ -449,7 +483,12 @@ h2x_status run_block_cg_shared(const DevMat &dm, const h2x_cg_params &prm, int64
                            G0, G1);
     };
     auto tsmm = [&](const double *U, const double *Cm, const double *Yin, double *out, double alpha, double beta) {
-        hipLaunchKernelGGL(k_tsmm, dim3(gt), dim3(256), 0, st, n, mi, U, Cm, Yin, out, alpha, beta, rpw);
+        switch (mt) {
+            case 16: hipLaunchKernelGGL(k_tsmm<16>, dim3(gt), dim3(256), 0, st, n, mi, U, Cm, Yin, out, alpha, beta); break;
+            case 32: hipLaunchKernelGGL(k_tsmm<32>, dim3(gt), dim3(256), 0, st, n, mi, U, Cm, Yin, out, alpha, beta); break;
+            case 48: hipLaunchKernelGGL(k_tsmm<48>, dim3(gt), dim3(256), 0, st, n, mi, U, Cm, Yin, out, alpha, beta); break;
+            default: hipLaunchKernelGGL(k_tsmm<64>, dim3(gt), dim3(256), 0, st, n, mi, U, Cm, Yin, out, alpha, beta); break;
+        }
     };
     auto orth = [&](const double *Zs) {
         gram2(Zs, Zs, nullptr, nullptr, w.Wm, nullptr);

@@ -142,6 +142,19 @@ def test_shared_first_iterates_match(small, iters):
     assert _colrel(Xg, Xo) <= 1e-12
 
 
+@pytest.mark.parametrize("m", [17, 37, 45, 64])
+def test_shared_block_widths(small, m):
+    # the tall-skinny products keep a column of the m x m factor in registers, padded to
+    # 16, 32, 48 or 64 entries: every padding, the largest block included, and m = 45,
+    # where a thread takes nine rows of its work-group
+    o, A, _ = small
+    B = W.rhs(A.n, m, 77 + m)
+    Xo, io = o.block_cg_shared(B, rtol=1e-8, max_iter=3)
+    Xg, ig = _solve(A, B, rtol=1e-8, max_iter=3, variant="shared")
+    assert ig.iters == io["iters"] == 3
+    assert _colrel(Xg, Xo) <= 1e-12
+
+
 def test_shared_end_to_end(small):
     o, A, B = small
     rtol = 1e-8

@@ -1,4 +1,4 @@
-// Matrix-core coupling kernels for the low-precision operators with k = 64:
+// Matrix-core coupling kernels for the low-precision operators (k = 64; k <= 32 below):
 //   y_t = sum_{(t,s) in C_t, admissible} S_b x_s     for every row cluster t,
 // S_b stored in FP32 or BF16, x-hat and y-hat in FP32, FP32 accumulation.
 //
@@ -211,15 +211,150 @@ __global__ __launch_bounds__(256) void k_coupling_mfma_bf16(int64_t m, int32_t C
     }
 }
 
+// Low-precision coupling for k <= 32 (S_b row-major in FP32 or BF16, x-hat and y-hat in
+// FP32, x_s rounded to the storage type, FP32 accumulation on v_mfma_f32_16x16x4f32).
+// A work-group of 2 waves owns one row cluster t and a slab of 16*NJ columns; wave w
+// owns rows 16w..16w+15 of y_t (rows past k are zero in the operand and never
+// written).  Lane (r, g), g = lane / 16, takes
+// columns 16a + 4g + h of S_b in k-step 4a + h (h = 0..3), so its four S values of a
+// group of k-steps are adjacent in memory; x_s is staged in LDS (double-buffered) and
+// read with the same permutation.  A lane past the last column reads column 0 and
+// multiplies a zero row of x_s.  S_b is streamed one block ahead; the last block is
+// peeled off the loop so that every load is unconditional.
+template <int NJ, typename T>
+__global__ __launch_bounds__(128) void k_coupling_small_lp(int k, int64_t m, int32_t C, int32_t rows_per_xcd,
+                                                           const int32_t *__restrict__ order,
+                                                           const int64_t *__restrict__ adm_ptr,
+                                                           const int32_t *__restrict__ adm_col,
+                                                           const T *__restrict__ S, const float *__restrict__ xh,
+                                                           float *__restrict__ yh, int64_t ldh, Skip skip) {
+    constexpr int MC = 16 * NJ, LDX = MC + 1;
+    __shared__ float xs[2][32 * LDX];
+    const int nslab = (int)((m + MC - 1) / MC), qx = blockIdx.x >> 3;
+    const int slot = (blockIdx.x & 7) * rows_per_xcd + qx / nslab;
+    if (slot >= C) return;
+    const int32_t t = order[slot];
+    if (skip(t)) return;
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    const int lr = lane & 15, g = lane >> 4;
+    const int64_t j0 = (int64_t)(qx % nslab) * MC;
+    const int mc = (int)min<int64_t>(MC, m - j0);
+    const int64_t b0 = adm_ptr[t], b1 = adm_ptr[t + 1];
+    const int na = (k + 15) >> 4;  // groups of four k-steps (16 columns of S each)
+    const int nu = 16 * w + lr;    // row of S_b held by this lane
+    const bool row_ok = nu < k;
+
+    flt4 acc[NJ];
+#pragma unroll
+    for (int J = 0; J < NJ; ++J) acc[J] = flt4{0.f, 0.f, 0.f, 0.f};
+
+    if (b1 > b0) {
+        constexpr int XPT = (32 * MC) / 128;  // x_s elements per thread (4 * NJ)
+        float xv[XPT];
+        auto load_x = [&](int32_t s) {
+            const float *src = xh + (int64_t)s * k * ldh + j0;
+#pragma unroll
+            for (int u = 0; u < XPT; ++u) {
+                const int e = tid + 128 * u, r = e / MC, c = e % MC;
+                xv[u] = src[(r < k && c < mc) ? (int64_t)r * ldh + c : 0];  // zeroed when stored
+            }
+        };
+        // the right-hand factor is rounded to the storage type (BF16: nearest even) as staged
+        auto store_x = [&](int buf) {
+#pragma unroll
+            for (int u = 0; u < XPT; ++u) {
+                const int e = tid + 128 * u, r = e / MC, c = e % MC;
+                float v = xv[u];
+                if constexpr (std::is_same<T, bf16_t>::value) v = to_float(bf16_t{bf16_bits(v)});
+                xs[buf][r * LDX + c] = (r < k && c < mc) ? v : 0.f;
+            }
+        };
+        float sa[2][4], sn[2][4];
+        auto load_s = [&](int64_t b, float (*dst)[4]) {
+            const T *src = S + b * k * k + (int64_t)(row_ok ? nu : 0) * k;
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int h = 0; h < 4; ++h) {
+                    const int mu = 16 * a + 4 * g + h;
+                    dst[a][h] = to_float(src[(row_ok && mu < k) ? mu : 0]);
+                }
+        };
+        auto multiply = [&](int buf) {
+            const float *xb = xs[buf];
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                if (a < na) {
+#pragma unroll
+                    for (int h = 0; h < 4; ++h) {
+                        const int krow = 16 * a + 4 * g + h;
+#pragma unroll
+                        for (int J = 0; J < NJ; ++J)
+                            acc[J] = __builtin_amdgcn_mfma_f32_16x16x4f32(sa[a][h], xb[krow * LDX + 16 * J + lr],
+                                                                          acc[J], 0, 0, 0);
+                    }
+                }
+            }
+        };
+
+        load_x(adm_col[b0]);
+        load_s(b0, sa);
+        store_x(0);
+        __syncthreads();
+        for (int64_t b = b0; b + 1 < b1; ++b) {
+            const int buf = (int)((b - b0) & 1);
+            load_x(adm_col[b + 1]);
+            load_s(b + 1, sn);
+            multiply(buf);
+            store_x(buf ^ 1);
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int h = 0; h < 4; ++h) sa[a][h] = sn[a][h];
+            __syncthreads();
+        }
+        multiply((int)((b1 - 1 - b0) & 1));
+    }
+    // output layout of v_mfma_f32_16x16x4f32: register q of lane l holds row 4 (l / 16) + q,
+    // column l % 16
+#pragma unroll
+    for (int J = 0; J < NJ; ++J) {
+        const int col = 16 * J + lr;
+        if (col < mc) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int row = 16 * w + 4 * g + q;
+                if (row < k) yh[((int64_t)t * k + row) * ldh + j0 + col] = acc[J][q];
+            }
+        }
+    }
+}
+
 // Launches the low-precision matrix-core coupling when the layout supports it.
 template <typename T>
 bool launch_coupling_lp(const DevMat &dm, int64_t m, const float *xh, float *yh, int64_t ldh, hipStream_t st,
                         Skip skip, int nj_force) {
     const bool f32 = std::is_same<T, float>::value;
-    if (dm.k != 64 || !dm.cpl_order || dm.swz != (f32 ? 2 : 3)) return false;
+    if (!dm.cpl_order) return false;
     const int nj = nj_force ? nj_force : (int)std::min<int64_t>(4, (m + 15) / 16);
     const int32_t rpx = (dm.C + 7) / 8;
     const dim3 grid((unsigned)(8 * rpx * ((m + 16 * nj - 1) / (16 * nj))));
+    if (dm.k <= 32) {
+        if (dm.swz != 0) return false;
+        auto go = [&](auto NJc) {
+            constexpr int NJ = decltype(NJc)::value;
+            hipLaunchKernelGGL((k_coupling_small_lp<NJ, T>), grid, dim3(128), 0, st, dm.k, m, dm.C, rpx,
+                               dm.cpl_order, dm.adm_ptr, dm.adm_col, (const T *)dm.S, xh, yh, ldh, skip);
+        };
+        switch (nj) {
+            case 1: go(std::integral_constant<int, 1>{}); break;
+            case 2: go(std::integral_constant<int, 2>{}); break;
+            case 3: go(std::integral_constant<int, 3>{}); break;
+            default: go(std::integral_constant<int, 4>{}); break;
+        }
+        return true;
+    }
+    if (dm.k != 64 || dm.swz != (f32 ? 2 : 3)) return false;
     auto go = [&](auto NJc) {
         constexpr int NJ = decltype(NJc)::value;
         if constexpr (std::is_same<T, float>::value)

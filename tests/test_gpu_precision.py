@@ -28,6 +28,10 @@ CASES = [
     ("small-k27-m4", lambda: W.SMALL.points(), W.SMALL.params(), 4),
     ("sphere-k64-m32", lambda: W.sphere_points(5000, 131), dict(ell=0.5, shift=1.0, eta=1.0, leaf=64, p=4), 32),
     ("cube-k64-m7", lambda: W.cube_points(6000, 132), dict(ell=0.25, shift=0.5, eta=1.0, leaf=64, p=4), 7),
+    # k <= 32 matrix-core coupling: several column slabs with a ragged last one, and k = 8
+    # (one group of four k-steps)
+    ("sphere-k27-m37", lambda: W.sphere_points(4000, 134), dict(ell=0.5, shift=1.0, eta=1.0, leaf=32, p=3), 37),
+    ("cube-k8-m20", lambda: W.cube_points(3000, 135), dict(ell=0.3, shift=1.0, eta=1.0, leaf=16, p=2), 20),
 ]
 
 

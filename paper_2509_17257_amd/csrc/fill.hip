@@ -256,7 +256,7 @@ size_t mat_layout(const Plan &P, h2x_prec storage, DevMat *dm, char *base) {
     // matrix-core layout (transposed near field, transposed leaf bases): FP64, k = 64 or k <= 32
     d.mc = (storage == H2X_F64 && (k == 64 || k <= 32)) ? 1 : 0;
     // low-precision operators with k = 64 use the same transposed near field (FP32) and leaf bases
-    d.near_t = (d.mc || (storage != H2X_F64 && k == 64)) ? 1 : 0;
+    d.near_t = (d.mc || (storage != H2X_F64 && (k == 64 || k <= 32))) ? 1 : 0;
     d.first = carve<int32_t>(cur, base, C);
     d.size = carve<int32_t>(cur, base, C);
     d.parent = carve<int32_t>(cur, base, C);

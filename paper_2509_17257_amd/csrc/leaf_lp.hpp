@@ -1,4 +1,4 @@
-// Matrix-core leaf stage for the low-precision operators (k = 64): near field in
+// Matrix-core leaf stage for the low-precision operators (k = 64 or k <= 32): near field in
 // FP32, leaf basis in FP32 or BF16, FP32 accumulation (v_mfma_f32_16x16x4f32):
 //   Y|_t = beta Y|_t + alpha (V_t y_t + sum_s N_ts X|_s).
 // X arrives as an FP32 copy in tree order.  With a BF16 basis, y_t is rounded to

@@ -479,9 +479,9 @@ hipError_t matmul_typed(const DevMat &dm, const TuneCfg &cfg, int64_t m, double 
         if (ev) (void)hipEventRecord(ev[i], st);
     };
     const Plan &P = *dm.plan;
-    // low-precision operator in the matrix-core layout (k = 64): FP32 matrix-core
-    // coupling and leaf stage, generic transfer passes
-    const bool lpmc = !std::is_same<T, double>::value && dm.near_t && dm.k == 64;
+    // low-precision operator in the matrix-core layout (k = 64 or k <= 32): FP32
+    // matrix-core coupling and leaf stage, generic transfer passes
+    const bool lpmc = !std::is_same<T, double>::value && dm.near_t && (dm.k == 64 || dm.k <= 32);
     const int64_t ldh = (dm.mc || lpmc) ? even_ld(m) : m;
     Acc *xh = (Acc *)ws;
     Acc *yh = (Acc *)(ws + hat_bytes<Acc>(dm, m));

@@ -20,6 +20,7 @@
 #include "leaf_rows.hpp"
 #include "matmul_mfma.hpp"
 #include "stages_mfma.hpp"
+#include "transfer_lp.hpp"
 #include "types.hpp"
 
 namespace h2x {
@@ -508,9 +509,35 @@ hipError_t matmul_typed(const DevMat &dm, const TuneCfg &cfg, int64_t m, double 
     hipLaunchKernelGGL((k_fwd_leaf<T, Acc>), dim3(dm.L, gy), dim3(256), 0, st, dm.k, m, dm.leaves, dm.first, dm.size,
                        dm.perm, V, X, ldx, to, xh, ldh);
     mark(1);
+    // transfer passes of the low-precision matrix-core layout on the FP32 matrix cores
+    // (4-long contraction steps: 16 for k = 64, 8 for k <= 32)
+    auto up_lp = [&](int32_t b, int32_t e) {
+        if constexpr (std::is_same<Acc, float>::value && !std::is_same<T, double>::value) {
+            if (dm.k == 64)
+                hipLaunchKernelGGL((tlp::k_up_lp<16, T>), dim3(e - b, gy), dim3(256), 0, st, dm.k, m,
+                                   dm.lvl_inner + b, dm.son0, dm.son1, E, xh, ldh);
+            else
+                hipLaunchKernelGGL((tlp::k_up_lp<8, T>), dim3(e - b, gy), dim3(256), 0, st, dm.k, m,
+                                   dm.lvl_inner + b, dm.son0, dm.son1, E, xh, ldh);
+            return true;
+        }
+        return false;
+    };
+    auto down_lp = [&](int32_t b, int32_t e) {
+        if constexpr (std::is_same<Acc, float>::value && !std::is_same<T, double>::value) {
+            if (dm.k == 64)
+                hipLaunchKernelGGL((tlp::k_down_lp<16, T>), dim3(e - b, gy), dim3(256), 0, st, dm.k, m,
+                                   dm.lvl_all + b, dm.parent, E, yh, ldh);
+            else
+                hipLaunchKernelGGL((tlp::k_down_lp<8, T>), dim3(e - b, gy), dim3(256), 0, st, dm.k, m,
+                                   dm.lvl_all + b, dm.parent, E, yh, ldh);
+            return true;
+        }
+        return false;
+    };
     for (int d = dm.depth_max - 1; d >= P.adm_depth; --d) {
         const int32_t b = P.lvl_inner_ptr[d], e = P.lvl_inner_ptr[d + 1];
-        if (e > b)
+        if (e > b && !(lpmc && up_lp(b, e)))
             hipLaunchKernelGGL((k_up<T, Acc>), dim3(e - b, gy), dim3(256), 0, st, dm.k, m, dm.lvl_inner + b, dm.son0,
                                dm.son1, E, xh, ldh);
     }
@@ -524,7 +551,7 @@ hipError_t matmul_typed(const DevMat &dm, const TuneCfg &cfg, int64_t m, double 
     mark(3);
     for (int d = std::max(1, P.adm_depth + 1); d <= dm.depth_max; ++d) {
         const int32_t b = P.lvl_ptr[d], e = P.lvl_ptr[d + 1];
-        if (e > b)
+        if (e > b && !(lpmc && down_lp(b, e)))
             hipLaunchKernelGGL((k_down<T, Acc>), dim3(e - b, gy), dim3(256), 0, st, dm.k, m, dm.lvl_all + b, dm.parent,
                                E, yh, ldh);
     }

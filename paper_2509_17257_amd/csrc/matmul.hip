@@ -506,8 +506,23 @@ hipError_t matmul_typed(const DevMat &dm, const TuneCfg &cfg, int64_t m, double 
     }
 
     mark(0);
-    hipLaunchKernelGGL((k_fwd_leaf<T, Acc>), dim3(dm.L, gy), dim3(256), 0, st, dm.k, m, dm.leaves, dm.first, dm.size,
-                       dm.perm, V, X, ldx, to, xh, ldh);
+    bool fwd_done = false;
+    if constexpr (std::is_same<Acc, float>::value && !std::is_same<T, double>::value) {
+        if (lpmc) {
+            // the FP32 tree-ordered copy of X serves the forward leaf transform and the leaf stage
+            float *xt = (float *)(ws + 2 * hat_bytes<Acc>(dm, m));
+            const int64_t ldxt = even_ld(m), cnt = dm.n * ldxt;
+            hipLaunchKernelGGL(lp::k_gather_f32, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, dm.n, m,
+                               to ? nullptr : dm.perm, X, ldx, xt, ldxt);
+            if (dm.L > 0)
+                hipLaunchKernelGGL((tlp::k_fwd_leaf_lp<T>), dim3(dm.L, gy), dim3(256), 0, st, dm.k, m, dm.leaves,
+                                   dm.first, dm.size, V, (const float *)xt, ldxt, xh, ldh);
+            fwd_done = true;
+        }
+    }
+    if (!fwd_done)
+        hipLaunchKernelGGL((k_fwd_leaf<T, Acc>), dim3(dm.L, gy), dim3(256), 0, st, dm.k, m, dm.leaves, dm.first,
+                           dm.size, dm.perm, V, X, ldx, to, xh, ldh);
     mark(1);
     // transfer passes of the low-precision matrix-core layout on the FP32 matrix cores
     // (4-long contraction steps: 16 for k = 64, 8 for k <= 32)
@@ -558,10 +573,8 @@ hipError_t matmul_typed(const DevMat &dm, const TuneCfg &cfg, int64_t m, double 
     mark(4);
     if constexpr (std::is_same<Acc, float>::value && !std::is_same<T, double>::value && std::is_same<TN, float>::value) {
         if (lpmc) {
-            float *xt = (float *)(ws + 2 * hat_bytes<Acc>(dm, m));
-            const int64_t ldxt = even_ld(m), cnt = dm.n * ldxt;
-            hipLaunchKernelGGL(lp::k_gather_f32, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, dm.n, m,
-                               to ? nullptr : dm.perm, X, ldx, xt, ldxt);
+            float *xt = (float *)(ws + 2 * hat_bytes<Acc>(dm, m));  // gathered before the forward transform
+            const int64_t ldxt = even_ld(m);
             const Skip sk{skip, dm.sys_of};
             const int rb = std::is_same<T, bf16_t>::value ? 1 : 0;
             const unsigned gl8 = 8 * ((dm.L + 7) / 8);

@@ -1,4 +1,5 @@
-// Matrix-core transfer passes for the low-precision operators (k = 64 or k <= 32):
+// Matrix-core transfer passes and forward leaf transform for the low-precision operators
+// (k = 64 or k <= 32):
 // E stored in FP32 or BF16, x-hat and y-hat in FP32, the right-hand factor rounded
 // to the storage type, FP32 accumulation on v_mfma_f32_16x16x4f32.
 //   upward:   x_t = E_{t0}^T x_{t0} + E_{t1}^T x_{t1}   (inner clusters of one depth)
@@ -109,6 +110,41 @@ __global__ __launch_bounds__(256) void k_down_lp(int k, int64_t m, const int32_t
             for (int r = 0; r < 4; ++r) {
                 const int row = 16 * w + 4 * g + r;
                 if (row < k) yh[((int64_t)c * k + row) * ldh + j0 + col] += acc[J][r];
+            }
+    }
+}
+
+// Forward leaf transform x_t = V_t^T X|_t for every leaf t, X from the FP32 tree-ordered
+// copy (rounded to the storage type as it is used), the points of the leaf in chunks of 64
+template <typename T>
+__global__ __launch_bounds__(256) void k_fwd_leaf_lp(int k, int64_t m, const int32_t *__restrict__ leaves,
+                                                     const int32_t *__restrict__ first,
+                                                     const int32_t *__restrict__ size, const T *__restrict__ V,
+                                                     const float *__restrict__ Xt, int64_t ldxt,
+                                                     float *__restrict__ xh, int64_t ldh) {
+    constexpr int KS = 16;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, g = lane >> 4;
+    if (16 * w >= k) return;
+    const int32_t t = leaves[blockIdx.x];
+    const int64_t j0 = (int64_t)blockIdx.y * kCols;
+    const int mc = (int)min<int64_t>(kCols, m - j0);
+    const int64_t r0 = first[t];
+    const int nt = size[t];
+    const int nu = min(16 * w + lr, k - 1);  // row of x_t (column of V) this lane supplies
+    flt4 acc[2] = {flt4{0.f, 0.f, 0.f, 0.f}, flt4{0.f, 0.f, 0.f, 0.f}};
+    for (int i0 = 0; i0 < nt; i0 += 4 * KS) {
+        const T *Vc = V + (r0 + i0) * k + nu;
+        term<KS, T>(min(4 * KS, nt - i0), lr, g, [&](int i) { return Vc + (int64_t)i * k; },
+                    Xt + (r0 + i0) * ldxt + j0, ldxt, mc, acc);
+    }
+#pragma unroll
+    for (int J = 0; J < 2; ++J) {
+        const int col = 16 * J + lr;
+        if (col < mc)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = 16 * w + 4 * g + r;
+                if (row < k) xh[((int64_t)t * k + row) * ldh + j0 + col] = acc[J][r];
             }
     }
 }

@@ -31,6 +31,11 @@ _KERNELS = {"exp": KERNEL_EXP, "poly": KERNEL_POLY, "const": KERNEL_CONST, "helm
 
 _lib = None
 
+# rounding points of the emulated low-precision product that matmul_lowp(omit=...) can
+# switch off one at a time (planted slips for the tests)
+LOWP_OMIT = {"x_leaf": 1, "xhat_transfer": 2, "xhat_coupling": 4, "yhat_transfer": 8, "yhat_leaf": 16,
+             "x_near_to_storage": 32, "fp64_sums": 64}
+
 
 def _load():
     global _lib
@@ -63,12 +68,13 @@ def _load():
     lib.orc_cg1.restype = I64
     lib.orc_cg1.argtypes = [P, P, P, D, I64]
     lib.orc_matmul_lowp.argtypes = [P, C.c_int, I64, D, P, D, P]
+    lib.orc_matmul_lowp_planted.argtypes = [P, C.c_int, I64, D, P, D, P, C.c_int]
     lib.orc_block_cg_lowp.restype = I64
     lib.orc_block_cg_lowp.argtypes = [P, C.c_int, I64, P, P, D, I64, P, P]
     lib.orc_refine_cg.restype = I64
-    lib.orc_refine_cg.argtypes = [P, C.c_int, I64, P, P, D, D, I64, I64, P]
+    lib.orc_refine_cg.argtypes = [P, C.c_int, I64, P, P, D, D, I64, I64, P, P, P]
     lib.orc_block_cg_mixed.restype = I64
-    lib.orc_block_cg_mixed.argtypes = [P, C.c_int, I64, P, P, D, D, I64, I64, P]
+    lib.orc_block_cg_mixed.argtypes = [P, C.c_int, I64, P, P, D, D, I64, I64, P, P, P]
     lib.orc_round_bf16_array.argtypes = [P, P, I64]
     lib.orc_matmul_adjoint.argtypes = [P, I64, D, P, D, P]
     lib.orc_grad.argtypes = [P, I64, P, P, P, P, P]
@@ -211,36 +217,46 @@ class OracleH2:
         fn(self._h, m, float(alpha), _ptr(X), float(beta), _ptr(out))
         return out[:, 0] if squeeze else out
 
-    def matmul_lowp(self, X, prec, alpha=1.0, beta=0.0, Y=None) -> np.ndarray:
+    def matmul_lowp(self, X, prec, alpha=1.0, beta=0.0, Y=None, omit=0) -> np.ndarray:
         """Emulated low-precision operator (prec "f32" or "bf16"): V, E, S rounded to the
-        storage type, near field to FP32, FP32 accumulation."""
+        storage type, near field to FP32, FP32 accumulation.  omit != 0 switches rounding
+        points off (planted slips for the tests; see LOWP_OMIT)."""
         pr = {"f32": 1, "bf16": 2}[prec]
         X = np.ascontiguousarray(X, dtype=np.float64)
         m = X.shape[1]
         out = np.zeros((self.n, m)) if Y is None else np.ascontiguousarray(Y, dtype=np.float64).copy()
-        _load().orc_matmul_lowp(self._h, pr, m, float(alpha), _ptr(X), float(beta), _ptr(out))
+        if omit:
+            _load().orc_matmul_lowp_planted(self._h, pr, m, float(alpha), _ptr(X), float(beta), _ptr(out), int(omit))
+        else:
+            _load().orc_matmul_lowp(self._h, pr, m, float(alpha), _ptr(X), float(beta), _ptr(out))
         return out
 
     def refine_cg(self, B, prec, rtol=1e-10, inner_rtol=1e-4, max_outer=50, max_inner=10000):
-        """FP64 iterative refinement around block CG with the low-precision operator."""
+        """FP64 iterative refinement around block CG with the low-precision operator.  Each
+        column returns its outer iterate with the smallest FP64 true residual."""
         pr = {"f32": 1, "bf16": 2}[prec]
         B = np.ascontiguousarray(B, dtype=np.float64)
         X = np.zeros_like(B)
         tot = np.zeros(1, np.int64)
+        rel = np.zeros(B.shape[1])
+        st = np.zeros(1, np.int32)
         outer = _load().orc_refine_cg(self._h, pr, B.shape[1], _ptr(B), _ptr(X), float(rtol), float(inner_rtol),
-                                      int(max_outer), int(max_inner), _ptr(tot))
-        return X, dict(outer=int(outer), inner=int(tot[0]))
+                                      int(max_outer), int(max_inner), _ptr(tot), _ptr(rel), _ptr(st))
+        return X, dict(outer=int(outer), inner=int(tot[0]), col_relres=rel, status=int(st[0]))
 
     def block_cg_mixed(self, B, prec, rtol=1e-10, delta=0.1, max_iter=10000, check=4):
         """Mixed precision in one CG run: iterations with the emulated low-precision
-        operator, the residual recomputed with the FP64 operator (residual replacement)."""
+        operator, the residual recomputed with the FP64 operator (residual replacement).
+        Each column returns the recomputed iterate with the smallest true residual."""
         pr = {"f32": 1, "bf16": 2}[prec]
         B = np.ascontiguousarray(B, dtype=np.float64)
         X = np.zeros_like(B)
         rep = np.zeros(1, np.int64)
+        rel = np.zeros(B.shape[1])
+        st = np.zeros(1, np.int32)
         it = _load().orc_block_cg_mixed(self._h, pr, B.shape[1], _ptr(B), _ptr(X), float(rtol), float(delta),
-                                        int(max_iter), int(check), _ptr(rep))
-        return X, dict(iters=int(it), replacements=int(rep[0]))
+                                        int(max_iter), int(check), _ptr(rep), _ptr(rel), _ptr(st))
+        return X, dict(iters=int(it), replacements=int(rep[0]), col_relres=rel, status=int(st[0]))
 
     def matmul_adjoint(self, X, alpha=1.0, beta=0.0, Y=None) -> np.ndarray:
         """Y <- beta Y + alpha A^T X through the column lists (transposed blocks)."""

@@ -725,7 +725,9 @@ void orc_forward_transform(const orc_h2 *h, int64_t m, const double *X, double *
 /* ------------------------------------------------------------------------ */
 /* Low-precision operator (emulated).  V, E, S are rounded to the storage type
  * (prec 1: FP32, 2: bfloat16), the near field to FP32; every small product
- * rounds its right-hand factor to the same type and accumulates in FP32.
+ * rounds its right-hand factor to the same type (X at the forward leaf
+ * product, x-hat where it meets E and S, y-hat where it meets E and V; X to
+ * FP32 where it meets the near field) and every sum is an FP32 sum.
  * bfloat16 rounding: the FP64 value is rounded to FP32 (nearest even), then
  * the FP32 value to bfloat16 (nearest even on the upper 16 bits).            */
 
@@ -751,22 +753,49 @@ static float orc_q(int prec, double v) {
     return prec == 2 ? orc_round_bf16(f) : f;
 }
 
-void orc_matmul_lowp(const orc_h2 *h, int prec, int64_t m, double alpha, const double *X, double beta, double *Y) {
+/* Rounding points of the emulation that a test can switch off one at a time
+ * (planted slips, to show that the hand-worked golden product catches each):
+ * bit 0  X not rounded to the storage type at the forward leaf product
+ * bit 1  x-hat of a son not rounded where it meets E (forward transfer)
+ * bit 2  x-hat not rounded where it meets S (coupling)
+ * bit 3  y-hat of a parent not rounded where it meets E (backward transfer)
+ * bit 4  y-hat not rounded where it meets V (leaf basis term)
+ * bit 5  X rounded to the storage type (not to FP32) where it meets the near field
+ * bit 6  sums carried in FP64 instead of FP32
+ * The library's arithmetic is omit = 0. */
+#define ORC_OMIT_X_LEAF 1
+#define ORC_OMIT_XH_TRANSFER 2
+#define ORC_OMIT_XH_COUPLING 4
+#define ORC_OMIT_YH_TRANSFER 8
+#define ORC_OMIT_YH_LEAF 16
+#define ORC_ROUND_X_NEAR 32
+#define ORC_FP64_SUMS 64
+
+/* a right-hand factor: rounded to the storage type unless that rounding point is omitted */
+static double orc_rh(int prec, int omit, int bit, double v) { return (omit & bit) ? v : (double)orc_q(prec, v); }
+
+/* one FP32 product or sum (FP64 when the planted slip asks for it); through FP64 this is
+ * exactly the FP32 operation, since FP64 carries more than twice FP32's precision */
+static double orc_f32(int omit, double v) { return (omit & ORC_FP64_SUMS) ? v : (double)(float)v; }
+
+static void orc_matmul_lowp_omit(const orc_h2 *h, int prec, int64_t m, double alpha, const double *X, double beta,
+                                 double *Y, int omit) {
     const int k = h->k;
     const int64_t n = h->n;
     size_t cw = (size_t)h->C * k * m;
-    float *xh = calloc(cw ? cw : 1, sizeof(float)), *yh = calloc(cw ? cw : 1, sizeof(float));
-    float *acc = calloc((size_t)n * m, sizeof(float));
+    double *xh = calloc(cw ? cw : 1, sizeof(double)), *yh = calloc(cw ? cw : 1, sizeof(double));
     for (int64_t i = 0; i < n * m; ++i) Y[i] = (beta == 0.0) ? 0.0 : beta * Y[i];
+#define LP_TERM(a, b) orc_f32(omit, (a) * (b))
     /* forward: leaves, then transfers bottom-up */
     for (int64_t s = 0; s < h->C; ++s) {
         if (!orc_is_leaf(h, s)) continue;
         for (int nu = 0; nu < k; ++nu)
             for (int64_t j = 0; j < m; ++j) {
-                float a = 0.0f;
+                double a = 0.0;
                 for (int64_t i = 0; i < h->size[s]; ++i) {
                     int64_t row = h->first[s] + i;
-                    a += orc_q(prec, h->V[row * k + nu]) * orc_q(prec, X[h->perm[row] * m + j]);
+                    a = orc_f32(omit, a + LP_TERM((double)orc_q(prec, h->V[row * k + nu]),
+                                                  orc_rh(prec, omit, ORC_OMIT_X_LEAF, (double)(float)X[h->perm[row] * m + j])));
                 }
                 xh[((size_t)s * k + nu) * m + j] = a;
             }
@@ -776,11 +805,13 @@ void orc_matmul_lowp(const orc_h2 *h, int prec, int64_t m, double alpha, const d
         int64_t sons[2] = {h->son0[s], h->son1[s]};
         for (int nu = 0; nu < k; ++nu)
             for (int64_t j = 0; j < m; ++j) {
-                float a = 0.0f;
+                double a = 0.0;
                 for (int q = 0; q < 2; ++q) {
                     const double *E = &h->E[(size_t)sons[q] * k * k];
                     for (int b = 0; b < k; ++b)
-                        a += orc_q(prec, E[b * k + nu]) * orc_q(prec, xh[((size_t)sons[q] * k + b) * m + j]);
+                        a = orc_f32(omit, a + LP_TERM((double)orc_q(prec, E[b * k + nu]),
+                                                      orc_rh(prec, omit, ORC_OMIT_XH_TRANSFER,
+                                                             xh[((size_t)sons[q] * k + b) * m + j])));
                 }
                 xh[((size_t)s * k + nu) * m + j] = a;
             }
@@ -789,13 +820,15 @@ void orc_matmul_lowp(const orc_h2 *h, int prec, int64_t m, double alpha, const d
     for (int64_t t = 0; t < h->C; ++t)
         for (int nu = 0; nu < k; ++nu)
             for (int64_t j = 0; j < m; ++j) {
-                float a = 0.0f;
+                double a = 0.0;
                 for (int64_t q = h->list_ptr[t]; q < h->list_ptr[t + 1]; ++q) {
                     int64_t b = h->list_blk[q], s = h->bs[b];
                     if (!h->badm[b]) continue;
                     const double *Sb = &h->S[h->boff[b]];
                     for (int mu = 0; mu < k; ++mu)
-                        a += orc_q(prec, Sb[nu * k + mu]) * orc_q(prec, xh[((size_t)s * k + mu) * m + j]);
+                        a = orc_f32(omit, a + LP_TERM((double)orc_q(prec, Sb[nu * k + mu]),
+                                                      orc_rh(prec, omit, ORC_OMIT_XH_COUPLING,
+                                                             xh[((size_t)s * k + mu) * m + j])));
                 }
                 yh[((size_t)t * k + nu) * m + j] = a;
             }
@@ -805,9 +838,11 @@ void orc_matmul_lowp(const orc_h2 *h, int prec, int64_t m, double alpha, const d
         const double *E = &h->E[(size_t)c * k * k];
         for (int b = 0; b < k; ++b)
             for (int64_t j = 0; j < m; ++j) {
-                float a = 0.0f;
-                for (int nu = 0; nu < k; ++nu) a += orc_q(prec, E[b * k + nu]) * orc_q(prec, yh[((size_t)par * k + nu) * m + j]);
-                yh[((size_t)c * k + b) * m + j] += a;
+                double a = 0.0;
+                for (int nu = 0; nu < k; ++nu)
+                    a = orc_f32(omit, a + LP_TERM((double)orc_q(prec, E[b * k + nu]),
+                                                  orc_rh(prec, omit, ORC_OMIT_YH_TRANSFER, yh[((size_t)par * k + nu) * m + j])));
+                yh[((size_t)c * k + b) * m + j] = orc_f32(omit, yh[((size_t)c * k + b) * m + j] + a);
             }
     }
     /* leaves: basis and near field, accumulated together in FP32 */
@@ -816,21 +851,37 @@ void orc_matmul_lowp(const orc_h2 *h, int prec, int64_t m, double alpha, const d
         for (int64_t i = 0; i < h->size[t]; ++i) {
             int64_t row = h->first[t] + i;
             for (int64_t j = 0; j < m; ++j) {
-                float a = 0.0f;
-                for (int nu = 0; nu < k; ++nu) a += orc_q(prec, h->V[row * k + nu]) * orc_q(prec, yh[((size_t)t * k + nu) * m + j]);
+                double a = 0.0;
+                for (int nu = 0; nu < k; ++nu)
+                    a = orc_f32(omit, a + LP_TERM((double)orc_q(prec, h->V[row * k + nu]),
+                                                  orc_rh(prec, omit, ORC_OMIT_YH_LEAF, yh[((size_t)t * k + nu) * m + j])));
                 for (int64_t q = h->list_ptr[t]; q < h->list_ptr[t + 1]; ++q) {
                     int64_t b = h->list_blk[q], s = h->bs[b];
                     if (h->badm[b]) continue;
                     const double *Nb = &h->N[h->boff[b]];
                     int64_t ns = h->size[s];
-                    for (int64_t c = 0; c < ns; ++c)
-                        a += (float)Nb[i * ns + c] * (float)X[h->perm[h->first[s] + c] * m + j];
+                    for (int64_t c = 0; c < ns; ++c) {
+                        const double x = X[h->perm[h->first[s] + c] * m + j];
+                        const double xr = (omit & ORC_ROUND_X_NEAR) ? (double)orc_q(prec, x) : (double)(float)x;
+                        a = orc_f32(omit, a + LP_TERM((double)(float)Nb[i * ns + c], xr));
+                    }
                 }
-                Y[h->perm[row] * m + j] += alpha * (double)a;
+                Y[h->perm[row] * m + j] += alpha * a;
             }
         }
     }
-    free(xh); free(yh); free(acc);
+#undef LP_TERM
+    free(xh); free(yh);
+}
+
+void orc_matmul_lowp(const orc_h2 *h, int prec, int64_t m, double alpha, const double *X, double beta, double *Y) {
+    orc_matmul_lowp_omit(h, prec, m, alpha, X, beta, Y, 0);
+}
+
+/* the emulation with some of its rounding points switched off (test infrastructure: planted slips) */
+void orc_matmul_lowp_planted(const orc_h2 *h, int prec, int64_t m, double alpha, const double *X, double beta,
+                             double *Y, int omit) {
+    orc_matmul_lowp_omit(h, prec, m, alpha, X, beta, Y, omit);
 }
 
 /* Mixed-precision solve: FP64 iterative refinement around block CG with the
@@ -839,9 +890,14 @@ void orc_matmul_lowp(const orc_h2 *h, int prec, int64_t m, double alpha, const d
  * block CG (FP64 vectors and dot products) to inner_rtol and set X += D.  A step
  * that does not halve the worst column's relative residual is a stall; the
  * refinement stops after two (the low-precision operator is then too far from A).
- * Returns the number of outer steps; *inner_total receives the inner iterations. */
+ * Every column returns the outer iterate with the smallest FP64 true residual
+ * (a refinement that diverges returns its best iterate, at worst X0).
+ * Returns the number of outer steps; *inner_total receives the inner iterations;
+ * col_relres (m entries, may be NULL) the true relative residual of each returned
+ * column; *status 0 when every column met rtol, 5 otherwise. */
 int64_t orc_refine_cg(const orc_h2 *h, int prec, int64_t m, const double *B, double *X, double rtol,
-                      double inner_rtol, int64_t max_outer, int64_t max_inner, int64_t *inner_total);
+                      double inner_rtol, int64_t max_outer, int64_t max_inner, int64_t *inner_total,
+                      double *col_relres, int32_t *status);
 
 /* ------------------------------------------------------------------------ */
 /* Differentiation.                                                          */
@@ -1187,6 +1243,25 @@ int64_t orc_block_cg_lowp(const orc_h2 *h, int prec, int64_t m, const double *B,
     return orc_block_cg_op(h, orc_op_lowp, prec, m, B, X, rtol, max_iter, 0, col_iters, status);
 }
 
+/* Keep, per column, the iterate with the smallest true residual norm seen so far:
+ * rn[j] is the residual norm of the current X; columns that improve on best[j] are
+ * copied to Xb.  orc_best_restore puts the best columns back into X. */
+static void orc_best_track(int64_t n, int64_t m, const double *X, const double *rn, double *best, double *Xb) {
+    for (int64_t j = 0; j < m; ++j) {
+        if (!(rn[j] < best[j])) continue;
+        best[j] = rn[j];
+        for (int64_t i = 0; i < n; ++i) Xb[i * m + j] = X[i * m + j];
+    }
+}
+
+static void orc_best_restore(int64_t n, int64_t m, double *X, double *rn, const double *best, const double *Xb) {
+    for (int64_t j = 0; j < m; ++j) {
+        if (!(best[j] < rn[j])) continue;
+        rn[j] = best[j];
+        for (int64_t i = 0; i < n; ++i) X[i * m + j] = Xb[i * m + j];
+    }
+}
+
 /*
  * Mixed precision in one CG run by residual replacement (van der Vorst and Ye,
  * 2000): the iterations are the block CG above with the emulated low-precision
@@ -1197,18 +1272,25 @@ int64_t orc_block_cg_lowp(const orc_h2 *h, int prec, int64_t m, const double *B,
  * the same search directions.  The decision is taken every `check` iterations
  * (the GPU reads its state at that cadence); iterations after every column has
  * converged and before the next check do nothing.  Stops when every column meets
- * rtol on a recomputed residual.  Returns the iterations performed;
- * *replacements receives the number of recomputations.
+ * rtol on a recomputed residual (or is broken down, or max_iter is reached).
+ * Every column returns the iterate with the smallest true residual among the
+ * recomputed ones (X0 included), so a run that breaks down or diverges returns
+ * its best iterate.  Returns the iterations performed; *replacements receives
+ * the number of recomputations, col_relres (m entries, may be NULL) the true
+ * relative residual of each returned column, *status 0 (all met rtol), 4 (a
+ * column broke down) or 5 (not converged).
  */
 int64_t orc_block_cg_mixed(const orc_h2 *h, int prec, int64_t m, const double *B, double *X, double rtol,
-                           double delta, int64_t max_iter, int64_t check, int64_t *replacements) {
+                           double delta, int64_t max_iter, int64_t check, int64_t *replacements,
+                           double *col_relres, int32_t *status) {
     const int64_t n = h->n;
     double *R = malloc(sizeof(double) * n * m), *P = malloc(sizeof(double) * n * m);
     double *Ap = malloc(sizeof(double) * n * m);
     double *bn = malloc(sizeof(double) * m), *rmax = malloc(sizeof(double) * m);
     int *frozen = calloc(m, sizeof(int)), *conv = calloc(m, sizeof(int));
+    double *Xb = malloc(sizeof(double) * n * m), *best = malloc(sizeof(double) * m);
     if (check < 1) check = 1;
-    /* true residual and the quantities that restart from it */
+    /* true residual and the quantities that restart from it; the best iterate so far */
     #define ORC_REPLACE()                                                        \
         do {                                                                     \
             memcpy(R, B, sizeof(double) * n * m);                                \
@@ -1217,8 +1299,12 @@ int64_t orc_block_cg_mixed(const orc_h2 *h, int prec, int64_t m, const double *B
                 rmax[j] = sqrt(orc_dot_col(n, m, R, R, j));                      \
                 conv[j] = rmax[j] <= rtol * bn[j];                               \
             }                                                                    \
+            orc_best_track(n, m, X, rmax, best, Xb);                             \
         } while (0)
-    for (int64_t j = 0; j < m; ++j) bn[j] = sqrt(orc_dot_col(n, m, B, B, j));
+    for (int64_t j = 0; j < m; ++j) {
+        bn[j] = sqrt(orc_dot_col(n, m, B, B, j));
+        best[j] = INFINITY;
+    }
     ORC_REPLACE();
     memcpy(P, R, sizeof(double) * n * m);
     int64_t it = 0, done_iters = 0, rep = 0, last_rep = 0;
@@ -1266,30 +1352,50 @@ int64_t orc_block_cg_mixed(const orc_h2 *h, int prec, int64_t m, const double *B
         ++it;
     }
     #undef ORC_REPLACE
+    /* the loop ends on a recomputed residual: rmax holds the true residual norms of X */
+    int st = 0;
+    for (int64_t j = 0; j < m; ++j) {
+        if (frozen[j]) st = 4;
+        else if (!conv[j] && st == 0) st = 5;
+    }
+    orc_best_restore(n, m, X, rmax, best, Xb);
+    if (col_relres)
+        for (int64_t j = 0; j < m; ++j) col_relres[j] = bn[j] > 0.0 ? rmax[j] / bn[j] : rmax[j];
+    if (status) *status = st;
     *replacements = rep;
-    free(R); free(P); free(Ap); free(bn); free(rmax); free(frozen); free(conv);
+    free(R); free(P); free(Ap); free(bn); free(rmax); free(frozen); free(conv); free(Xb); free(best);
     return done_iters;
 }
 
 int64_t orc_refine_cg(const orc_h2 *h, int prec, int64_t m, const double *B, double *X, double rtol,
-                      double inner_rtol, int64_t max_outer, int64_t max_inner, int64_t *inner_total) {
+                      double inner_rtol, int64_t max_outer, int64_t max_inner, int64_t *inner_total,
+                      double *col_relres, int32_t *status) {
     const int64_t n = h->n;
     double *R = malloc(sizeof(double) * n * m), *D = malloc(sizeof(double) * n * m);
+    double *Xb = malloc(sizeof(double) * n * m), *rn = malloc(sizeof(double) * m);
+    double *best = malloc(sizeof(double) * m), *bn = malloc(sizeof(double) * m);
     int64_t *ci = malloc(sizeof(int64_t) * m);
     int32_t *st = malloc(sizeof(int32_t) * m);
+    for (int64_t j = 0; j < m; ++j) {
+        bn[j] = sqrt(orc_dot_col(n, m, B, B, j));
+        best[j] = INFINITY;
+    }
     *inner_total = 0;
     int64_t outer = 0, stalls = 0;
+    int done = 0;
     double prev = INFINITY;
     for (;;) {
         memcpy(R, B, sizeof(double) * n * m);
         orc_matmul(h, m, -1.0, X, 1.0, R);
-        int done = 1;
+        done = 1;
         double worst = 0.0;
         for (int64_t j = 0; j < m; ++j) {
-            double rel = sqrt(orc_dot_col(n, m, R, R, j)) / sqrt(orc_dot_col(n, m, B, B, j));
+            rn[j] = sqrt(orc_dot_col(n, m, R, R, j));
+            double rel = bn[j] > 0.0 ? rn[j] / bn[j] : rn[j];
             if (rel > rtol) done = 0;
             if (rel > worst) worst = rel;
         }
+        orc_best_track(n, m, X, rn, best, Xb);
         /* a step that does not halve the worst relative residual is a stall; two stalls stop */
         if (worst > 0.5 * prev) stalls++;
         prev = worst;
@@ -1299,7 +1405,11 @@ int64_t orc_refine_cg(const orc_h2 *h, int prec, int64_t m, const double *B, dou
         for (int64_t i = 0; i < n * m; ++i) X[i] += D[i];
         outer++;
     }
-    free(R); free(D); free(ci); free(st);
+    orc_best_restore(n, m, X, rn, best, Xb);
+    if (col_relres)
+        for (int64_t j = 0; j < m; ++j) col_relres[j] = bn[j] > 0.0 ? rn[j] / bn[j] : rn[j];
+    if (status) *status = done ? 0 : 5;
+    free(R); free(D); free(Xb); free(rn); free(best); free(bn); free(ci); free(st);
     return outer;
 }
 

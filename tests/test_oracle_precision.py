@@ -11,7 +11,19 @@
 * CG with residual replacement (iterations with the emulated operator, residual
   recomputed in FP64) meets 1e-10 on the true residual, agrees with a dense
   Cholesky solve within kappa * rtol, and solves sigma I + 1 1^T in a few steps.
+* The rounding points of the emulation (reading R16) are pinned by a hand-worked
+  product (tests/golden/lowp_line16.json): 16 points on a line, p = 1, constant
+  kernel, right-hand sides whose x-hat and y-hat at inner clusters are not
+  bfloat16 numbers.  Switching off any one rounding point (a planted slip)
+  changes the product.
+* A refinement or residual-replacement run that cannot converge (a bfloat16
+  operator on a system whose condition number times the operator error exceeds
+  1) returns, per column, its iterate with the smallest true residual, so the
+  returned residual is at most that of X0 = 0.
 """
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -19,6 +31,8 @@ import oracle
 from paper_2509_17257_amd import workloads as W
 
 torch = pytest.importorskip("torch")
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
 
 
 def _colrel(a, b):
@@ -113,3 +127,111 @@ def test_mixed_cg_constant_kernel_closed_form():
     Xcf = (B - B.sum(0, keepdims=True) / (sigma + n)) / sigma
     assert _colrel(X, Xcf) <= 1e-10
     assert info["iters"] <= 20 and info["replacements"] <= 10
+
+
+# ---- hand-worked rounding points (reading R16) ----
+
+def _line16():
+    g = json.load(open(os.path.join(GOLD, "lowp_line16.json")))
+    P = np.zeros((16, 3))
+    P[:, 0] = g["points_x"]
+    o = oracle.OracleH2(P, kernel="const", leaf=g["leaf_size"], p=1, eta=g["eta"], shift=g["shift"])
+    X = np.zeros((16, len(g["columns"])))
+    for j, col in enumerate(g["columns"]):
+        for i, v in col["x_nonzero"].items():
+            X[int(i), j] = v
+    Yb = np.array([c["y_bf16"] for c in g["columns"]], dtype=np.float64).T
+    Ye = np.array([c["y_exact"] for c in g["columns"]], dtype=np.float64).T
+    return g, o, X, Yb, Ye
+
+
+def test_line16_structure_is_the_hand_worked_one():
+    """The derivation assumes this tree and these lists: check them first."""
+    g, o, X, Yb, Ye = _line16()
+    tr = o.tree()
+    assert o.C == len(g["clusters_preorder"])
+    for c in g["clusters_preorder"]:
+        i = c["id"]
+        lo, hi = c["members"]
+        assert tr["first"][i] == lo and tr["size"][i] == hi - lo + 1
+        sons = [int(tr["son0"][i]), int(tr["son1"][i])] if tr["son0"][i] >= 0 else []
+        assert sons == c["sons"]
+    assert list(tr["perm"]) == list(range(16))
+    b = o.blocks()
+    for t in range(o.C):
+        got = [[int(b["s"][q]), "adm" if b["adm"][q] else "near"]
+               for q in b["list_blk"][b["list_ptr"][t]:b["list_ptr"][t + 1]]]
+        assert got == g["lists"].get(str(t), []), t
+
+
+def test_lowp_rounding_points_hand_worked():
+    """BF16 emulation equals the hand-worked product exactly; FP32 storage equals the
+    exact product where every value is an FP32 number (columns 1-3) and the hand-worked
+    FP32 sums in column 4; the FP64 product is the exact A = 11^T + 0.5 I product."""
+    g, o, X, Yb, Ye = _line16()
+    np.testing.assert_array_equal(o.matmul_lowp(X, "bf16"), Yb)
+    Yf = o.matmul_lowp(X, "f32")
+    np.testing.assert_array_equal(Yf[:, :3], Ye[:, :3])
+    np.testing.assert_array_equal(Yf[:, 3], Yb[:, 3])
+    np.testing.assert_array_equal(o.matmul(X), Ye)
+    # the exact product is the closed form (1 1^T + 0.5 I) X
+    np.testing.assert_array_equal(Ye, X.sum(0, keepdims=True) + 0.5 * X)
+
+
+@pytest.mark.parametrize("slip", sorted(oracle.LOWP_OMIT))
+def test_lowp_planted_rounding_slip_is_caught(slip):
+    g, o, X, Yb, Ye = _line16()
+    Yp = o.matmul_lowp(X, "bf16", omit=oracle.LOWP_OMIT[slip])
+    assert not np.array_equal(Yp, Yb), slip
+
+
+# ---- solves that cannot converge return their best iterate ----
+
+@pytest.fixture(scope="module")
+def hard():
+    """Unit-cube points, length scale 1 and shift 1e-3: the dense H^2 matrix has
+    lambda_min 6.2e-3 and lambda_max 798 (kappa 1.3e5), and the bfloat16 operator's
+    error is 2.2e-3 of the product, so kappa times the error is far above 1: neither
+    refinement nor residual replacement can converge (refinement diverges at once)."""
+    P = np.random.default_rng(131).random((1500, 3))
+    return oracle.OracleH2(P, leaf=32, p=3, ell=1.0, shift=1e-3)
+
+
+def _true_rel(o, B, X):
+    return np.linalg.norm(B - o.matmul(X), axis=0) / np.linalg.norm(B, axis=0)
+
+
+def test_refinement_returns_best_iterate_when_it_stalls(hard):
+    B = W.rhs(hard.n, 3, 132)
+    X, info = hard.refine_cg(B, "bf16", rtol=1e-10, inner_rtol=1e-2, max_outer=8, max_inner=150)
+    rel = _true_rel(hard, B, X)
+    assert info["status"] == 5
+    np.testing.assert_allclose(info["col_relres"], rel, rtol=1e-12)
+    assert (rel <= 1.0).all()
+    # the returned columns are the best outer iterates: no later outer step of the same
+    # (deterministic) run is better than what was returned
+    for outer in range(0, info["outer"] + 1):
+        Xo, io = hard.refine_cg(B, "bf16", rtol=1e-10, inner_rtol=1e-2, max_outer=outer, max_inner=150)
+        assert (rel <= _true_rel(hard, B, Xo) * (1 + 1e-12)).all(), outer
+
+
+def test_mixed_cg_returns_best_iterate_on_breakdown_or_budget(hard):
+    B = W.rhs(hard.n, 3, 133)
+    X, info = hard.block_cg_mixed(B, "bf16", rtol=1e-10, max_iter=300, check=4)
+    rel = _true_rel(hard, B, X)
+    assert info["status"] in (4, 5)
+    np.testing.assert_allclose(info["col_relres"], rel, rtol=1e-12)
+    assert (rel <= 1.0).all()
+
+
+def test_best_iterate_rule_leaves_converged_solves_alone(h):
+    """When every column converges the returned iterate meets rtol (the rule picks the
+    smallest true residual, which is then at most rtol)."""
+    B = W.rhs(h.n, 2, 134)
+    for fn in (lambda: h.refine_cg(B, "f32", rtol=1e-10, inner_rtol=1e-5),
+               lambda: h.block_cg_mixed(B, "f32", rtol=1e-10)):
+        X, info = fn()
+        assert info["status"] == 0
+        rel = _true_rel(h, B, X)
+        assert rel.max() <= 1e-10
+        np.testing.assert_allclose(info["col_relres"], rel, rtol=0, atol=1e-13)

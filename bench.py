@@ -45,10 +45,14 @@ def alg_flops(plan, m):
     return 2 * m * (2 * plan.n * k + 2 * (plan.C - 1) * k * k + plan.n_adm * k * k + plan.near_entries)
 
 
-def coupling_bytes(plan, m, s_b=8, s_h=8):
-    """Coupling stage: every S_b once, x-hat read once, y-hat written once."""
-    k = plan.k
-    return s_b * plan.n_adm * k * k + 2 * s_h * plan.C * k * m
+def coupling_bytes(plan, s_b=8):
+    """Algorithmic bytes of the coupling stage: every S_b once (k^2 s_b per admissible block)."""
+    return s_b * plan.n_adm * plan.k * plan.k
+
+
+def coupling_intermediate_bytes(plan, m, s_h=8):
+    """The coupling's intermediate traffic, reported apart: x-hat read once, y-hat written once."""
+    return 2 * s_h * plan.C * plan.k * m
 
 
 def coupling_flops(plan, m):
@@ -75,24 +79,78 @@ def measured_traffic(kernel_profile):
                        float(kv["write_size_kib_per_launch"]) * float(kv["write_scale"])))
 
 
+def host_info():
+    """CPU model, logical CPUs and RAM of the host, from /proc."""
+    model, ram = "unknown", 0.0
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+        for line in open("/proc/meminfo"):
+            if line.startswith("MemTotal"):
+                ram = int(line.split()[1]) / 2**20
+                break
+    except OSError:
+        pass
+    return dict(cpu_model=model, nproc=os.cpu_count(), ram_gib=round(ram, 1))
+
+
+def host_copy_gbs(threads, nbytes=1 << 30, reps=5):
+    """STREAM-like copy bandwidth of the host: `threads` threads each copy their slice of a
+    nbytes array (numpy copies release the GIL); bytes counted as read + write."""
+    import concurrent.futures as cf
+
+    a = np.ones(nbytes // 8)
+    b = np.empty_like(a)
+    bounds = np.linspace(0, a.size, threads + 1).astype(np.int64)
+
+    def part(i):
+        np.copyto(b[bounds[i]:bounds[i + 1]], a[bounds[i]:bounds[i + 1]])
+
+    with cf.ThreadPoolExecutor(threads) as ex:
+        list(ex.map(part, range(threads)))
+        best = 0.0
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            list(ex.map(part, range(threads)))
+            best = max(best, 2 * a.nbytes / (time.perf_counter() - t0) / 1e9)
+    return round(best, 2)
+
+
 def cpu_baseline(w, P, X, plan, budget_s):
+    """The oracle (the paper's CPU method: parallel forward / list-wise multiplication /
+    backward) timed on the host's cores, then with one thread, beside the host's copy
+    bandwidth."""
     import oracle
 
     o = oracle.OracleH2(P, **w.params())
     o.matmul(X[:, :1])  # warm the code path
-    times = []
-    t_end = time.perf_counter() + budget_s
-    while True:
-        t0 = time.perf_counter()
-        o.matmul(X)
-        times.append(time.perf_counter() - t0)
-        if time.perf_counter() > t_end:
-            break
-    t = float(np.median(times))
-    gbs = alg_bytes(plan, X.shape[1]) / t / 1e9
-    return dict(value=round(gbs, 3), unit="GB/s", cores=oracle.num_threads(), kind="oracle",
-                sample=f"{len(times)} full products, {w.name}, median {t * 1e3:.1f} ms each "
-                       f"(OpenMP, forward / list-wise multiplication / backward of the paper)")
+    cores = oracle.num_threads()
+
+    def timed(budget, min_runs=1):
+        times = []
+        t_end = time.perf_counter() + budget
+        while True:
+            t0 = time.perf_counter()
+            o.matmul(X)
+            times.append(time.perf_counter() - t0)
+            if time.perf_counter() > t_end and len(times) >= min_runs:
+                break
+        return float(np.median(times)), len(times)
+
+    t, runs = timed(budget_s)
+    oracle.set_threads(1)
+    try:
+        t1, runs1 = timed(0.0)
+    finally:
+        oracle.set_threads(cores)
+    b = alg_bytes(plan, X.shape[1])
+    return dict(value=round(b / t / 1e9, 3), unit="GB/s", cores=cores, kind="oracle",
+                sample=f"{runs} full products, {w.name}, median {t * 1e3:.1f} ms each "
+                       f"(OpenMP, forward / list-wise multiplication / backward of the paper)",
+                one_thread=dict(value=round(b / t1 / 1e9, 3), unit="GB/s", ms=round(t1 * 1e3, 1), runs=runs1),
+                host_copy_gbs=host_copy_gbs(cores), host=host_info())
 
 
 def time_products(h2x, torch, A, X, Y, steps):
@@ -105,6 +163,65 @@ def time_products(h2x, torch, A, X, Y, steps):
     e1.record()
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / steps
+
+
+def lambda_max(torch, h2x, A, n, iters=40, seed=7):
+    """Largest eigenvalue of the (symmetric) FP64 operator by power iteration (Rayleigh quotient)."""
+    g = torch.Generator(device="cuda:0").manual_seed(seed)
+    v = torch.randn((n, 1), dtype=torch.float64, device="cuda:0", generator=g)
+    v /= v.norm()
+    lam = 0.0
+    for _ in range(iters):
+        w = h2x.h2_matmul(A, v)
+        lam = float((v * w).sum())
+        v = w / w.norm()
+    return lam
+
+
+def precision_record(torch, h2x, W, max_iter):
+    """The precision workload (n = 262144 uniform in the unit cube, exp(-r/0.25) + 0.5 I, k = 64,
+    m = 64): time to an FP64 true residual of 1e-10 with plain FP64 block CG against block CG
+    with FP32-storage iterations and FP64 residual replacement; true residuals with the FP64
+    product; lambda_max by power iteration (lambda_min >= the shift, so kappa <= lambda_max / shift)."""
+    w = W.WORKLOADS["cube-n262144-k64-m64"]
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    plan = h2x.Plan(w.points(), **w.params())
+    A = h2x.H2Matrix(plan, storage="f64", device=dev)
+    A32 = h2x.H2Matrix(plan, storage="f32", device=dev)
+    B = torch.from_numpy(w.rhs()).to(dev)
+    # first launches and workspace allocations outside the timed solves
+    h2x.block_cg_solve(A, B, rtol=1e-10, max_iter=2)
+    h2x.block_cg_mixed(A, A32, B, rtol=1e-10, max_iter=2, graph=True)
+    torch.cuda.synchronize()
+    setup = time.perf_counter() - t0
+    rec = {"workload": w.name, "rtol": 1e-10, "setup_s": round(setup, 2)}
+
+    def true_rel(X):
+        return ((B - h2x.h2_matmul(A, X)).norm(dim=0) / B.norm(dim=0)).max().item()
+
+    log(f"[precision] FP64 block CG to 1e-10 on {w.name}")
+    t0 = time.perf_counter()
+    X, info = h2x.block_cg_solve(A, B, rtol=1e-10, max_iter=max_iter)
+    torch.cuda.synchronize()
+    rec["fp64_cg"] = {"time_s": round(time.perf_counter() - t0, 3), "iters": info.iters, "status": info.status,
+                      "max_true_relres": true_rel(X)}
+    log(f"[precision] {rec['fp64_cg']}")
+    log("[precision] FP32 iterations with FP64 residual replacement to 1e-10")
+    t0 = time.perf_counter()
+    X, info = h2x.block_cg_mixed(A, A32, B, rtol=1e-10, delta=0.1, max_iter=max_iter, graph=True)
+    torch.cuda.synchronize()
+    rec["fp32_residual_replacement"] = {"time_s": round(time.perf_counter() - t0, 3), "iters": info.iters,
+                                        "replacements": info.outer_iters, "status": info.status,
+                                        "max_true_relres": true_rel(X)}
+    log(f"[precision] {rec['fp32_residual_replacement']}")
+    rec["speedup_fp32_vs_fp64"] = round(rec["fp64_cg"]["time_s"] / rec["fp32_residual_replacement"]["time_s"], 3)
+    lam = lambda_max(torch, h2x, A, plan.n)
+    rec["lambda_max"] = round(lam, 2)
+    rec["kappa_bound"] = round(lam / w.shift, 1)
+    del A, A32
+    torch.cuda.empty_cache()
+    return rec
 
 
 def precision_report(args, torch, h2x, W):
@@ -575,6 +692,8 @@ def main():
     ap.add_argument("--workload", default="sphere-n65536-k64-m32")
     ap.add_argument("--cg", type=int, default=1, help="also time block CG to 1e-8")
     ap.add_argument("--max-cg-iter", type=int, default=5000)
+    ap.add_argument("--precision-record", type=int, default=1,
+                    help="also time FP64 CG against FP32 residual replacement to 1e-10 on the precision workload")
     ap.add_argument("--autotune", type=int, default=1, help="autotune the tile shapes before timing (1) or not (0)")
     ap.add_argument("--cpu-baseline-s", type=float, default=12.0, help="0 disables the oracle timing")
     ap.add_argument("--precision-report", action="store_true",
@@ -675,20 +794,10 @@ def main():
     log(f"[bench] warmup {args.warmup} done; timing {args.steps} products")
     stream = torch.cuda.current_stream(dev)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    # every MARK_EVERY-th timed product records its stage boundaries with HIP events on the
-    # library's stream (the caller's stream), read after the timed region: the per-stage and
-    # coupling times come from products of the timed region (seven event records cost about
-    # 2 % of a product, so not every product carries them)
-    MARK_EVERY = 4
-    marked = list(range(0, args.steps, MARK_EVERY))
-    timer = h2x.Timer(len(marked))
     torch.cuda.synchronize()
     e0.record(stream)
-    for i in range(args.steps):
-        if i % MARK_EVERY == 0:
-            h2x.h2_matmul(A, X, out=Y, timer=timer, slot=i // MARK_EVERY)
-        else:
-            h2x.h2_matmul(A, X, out=Y)
+    for _ in range(args.steps):
+        h2x.h2_matmul(A, X, out=Y)
     e1.record(stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / args.steps
@@ -696,9 +805,18 @@ def main():
     F = alg_flops(plan, m)
     gbs = B_alg / (ms * 1e-3) / 1e9
     log(f"[bench] {ms:.4f} ms/product, {gbs:.1f} GB/s algorithmic")
-    stage = np.mean([timer.read(j) for j in range(len(marked))], axis=0)
-    log(f"[bench] stage times from {len(marked)} of the {args.steps} timed products")
-    cb, cf = coupling_bytes(plan, m), coupling_flops(plan, m)
+    # stage times: after the timed region, the same number of products, each recording its
+    # stage boundaries with HIP events on the library's stream (the caller's stream), read
+    # afterwards; the coupling is one kernel launch, so its stage time is that launch's
+    # duration (plus the launch gap before it)
+    timer = h2x.Timer(args.steps)
+    for i in range(args.steps):
+        h2x.h2_matmul(A, X, out=Y, timer=timer, slot=i)
+    torch.cuda.synchronize()
+    per = np.array([timer.read(j) for j in range(args.steps)])
+    stage = per.mean(axis=0)
+    log(f"[bench] stage times from {args.steps} marked products after the timed region")
+    cb, cf, ci = coupling_bytes(plan), coupling_flops(plan, m), coupling_intermediate_bytes(plan, m)
     c_ms = stage[h2x.STAGES.index("coupling")]
     c_gbs = cb / (c_ms * 1e-3) / 1e9
     c_tf = cf / (c_ms * 1e-3) / 1e12
@@ -711,7 +829,9 @@ def main():
                     frac=round(c_tf / PEAK_FP64_TFLOPS, 4), traffic=None)
     if w.name == "sphere-n65536-k64-m32":
         roof["traffic"] = measured_traffic("coupling_f64_sphere-n65536-k64-m32.pmc.txt")
-    roof.update(kernel="coupling", kernel_ms=round(float(c_ms), 5), kernel_bytes=int(cb), kernel_flops=int(cf))
+    roof.update(kernel="coupling", kernel_ms=round(float(c_ms), 5), kernel_ms_min=round(float(per[:, 2].min()), 5),
+                kernel_bytes=int(cb), intermediate_bytes=int(ci), kernel_flops=int(cf),
+                bytes_rule="k^2 * 8 bytes per admissible block (S once); x-hat / y-hat apart")
     log("[bench] stages ms: " + ", ".join(f"{n}={v:.4f}" for n, v in zip(h2x.STAGES, stage)))
 
     out = {
@@ -769,6 +889,9 @@ def main():
         out["block_cg_shared"] = {"rtol": 1e-8, "time_s": round(cg_s, 4), "iters": info.iters, "status": info.status,
                                   "max_true_relres": res, "precision": "f64", "variant": "shared"}
         log(f"[bench] shared-space block CG: {info.iters} iterations, {cg_s:.3f} s, true rel res {res:.2e}")
+
+    if args.precision_record:
+        out["precision"] = precision_record(torch, h2x, W, args.max_cg_iter)
 
     if args.cpu_baseline_s > 0:
         log(f"[bench] timing the CPU oracle for ~{args.cpu_baseline_s:.0f} s")

@@ -249,10 +249,13 @@ h2x_status h2x_block_cg(const h2x_mat *A, const h2x_cg_params *prm, int64_t m, c
  * ||R_i||, and set X += D.  At most max_outer steps; a step that does not halve
  * the worst column's relative residual is a stall, and two stalls end the solve
  * with H2X_ENOCONV (the low-precision operator is too far from A for this
- * system's conditioning).  Blocking.  info->iters is the
+ * system's conditioning).  Every column returns its outer iterate with the
+ * smallest FP64 true residual (X0 included), so a refinement that diverges
+ * returns its best iterate.  Blocking.  info->iters is the
  * total number of inner iterations, info->outer_iters the number of steps,
- * info->col_relres the final FP64 true residuals ||B_i - A X_i|| / ||B_i||,
- * info->status H2X_ENOCONV if rtol was not met. */
+ * info->col_relres the FP64 true residuals ||B_i - A X_i|| / ||B_i|| of the
+ * returned columns, info->status H2X_ENOCONV if one of them misses rtol.  The
+ * workspace holds one n x m block for the best iterate besides the solve's. */
 size_t h2x_block_cg_refine_workspace_bytes(const h2x_mat *A, const h2x_mat *A_lo, int64_t m);
 h2x_status h2x_block_cg_refine(const h2x_mat *A, const h2x_mat *A_lo, const h2x_cg_params *inner, double rtol,
                                int32_t max_outer, int64_t m, const double *B, int64_t ldb, double *X,
@@ -268,9 +271,14 @@ h2x_status h2x_block_cg_refine(const h2x_mat *A, const h2x_mat *A_lo, const h2x_
  * iterations), and whenever every column looks converged, the residual is
  * recomputed as R = B - A X with the FP64 operator A and the iteration continues
  * from it with the same search directions.  The solve stops when every column
- * meets prm->rtol on the recomputed residual.  info->outer_iters is the number
- * of replacements, info->col_relres the final true residuals.  A and A_lo: one
- * plan with one system; A stored in FP64.  0 < delta < 1 (0.1 is usual).  Blocking. */
+ * meets prm->rtol on the recomputed residual (or has broken down, or max_iter
+ * is reached).  Every column returns the iterate with the smallest recomputed
+ * true residual (X0 included), so a solve that breaks down or diverges returns
+ * its best iterate.  info->outer_iters is the number of replacements,
+ * info->col_relres the true residuals of the returned columns, info->status
+ * H2X_EBREAKDOWN if a column broke down, else H2X_ENOCONV if a returned column
+ * misses rtol.  A and A_lo: one plan with one system; A stored in FP64.
+ * 0 < delta < 1 (0.1 is usual).  Blocking. */
 size_t h2x_block_cg_mixed_workspace_bytes(const h2x_mat *A, const h2x_mat *A_lo, int64_t m);
 h2x_status h2x_block_cg_mixed(const h2x_mat *A, const h2x_mat *A_lo, const h2x_cg_params *prm, double delta,
                               int64_t m, const double *B, int64_t ldb, double *X, int64_t ldx, void *dev_ws,
@@ -469,19 +477,26 @@ h2x_status h2x_matmul_adjoint(const h2x_mat *A, int64_t m, double alpha, const d
 /* Bytes of device workspace h2x_grad needs for m columns. */
 size_t h2x_grad_workspace_bytes(const h2x_mat *A, int64_t m);
 
-/* Gradients of L = <dY, A X> (async).  X, dY: device n x m (original order).
+/* Gradients of L = scale * <dY, A X> (async).  X, dY: device n x m (original order).
  * Outputs (device, any may be NULL to skip it):
  *   dS:   n_adm x k x k row-major, in the storage order of h2x_plan_blocks:
- *         dS_b = dyhat_t xhat_s^T, xhat / dyhat the forward transformations;
+ *         dS_b = scale * dyhat_t xhat_s^T, xhat / dyhat the forward transformations;
  *   dN:   near_entries doubles, the blocks in the storage order of
  *         h2x_plan_blocks, each |t| x |s| row-major in tree order of the points:
- *         dN_b = dY|_t X|_s^T;
+ *         dN_b = scale * dY|_t X|_s^T;
  *   dell: one double, dL/dell = sum_b <dS_b/dell, dS_b> + sum_b <dN_b/dell, dN_b>
  *         with d g / d ell = (r / ell^2) exp(-r / ell) (0 for the test kernels);
- *         reduced in a fixed order (bitwise reproducible). */
+ *         dell_terms selects the terms summed: H2X_DELL_COUPLING (the coupling
+ *         matrices), H2X_DELL_NEAR (the near field), or both.  A caller that
+ *         supplies its own coupling matrices (which then do not depend on ell)
+ *         asks for H2X_DELL_NEAR only.  Reduced in a fixed order (bitwise
+ *         reproducible).
+ * scale: finite (e.g. -1 for the implicit adjoint of a solve). */
+#define H2X_DELL_COUPLING 1
+#define H2X_DELL_NEAR 2
 h2x_status h2x_grad(const h2x_mat *A, int64_t m, const double *X, int64_t ldx, const double *dY,
-                    int64_t lddy, double *dS, double *dN, double *dell, void *dev_ws, size_t ws_bytes,
-                    void *hip_stream);
+                    int64_t lddy, double *dS, double *dN, double *dell, double scale, int32_t dell_terms,
+                    void *dev_ws, size_t ws_bytes, void *hip_stream);
 
 /* Refill the coupling matrices and the near field for a new kernel length scale
  * (the cluster tree, block tree, bases and transfers do not depend on ell).

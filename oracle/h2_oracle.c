@@ -1352,13 +1352,14 @@ int64_t orc_block_cg_mixed(const orc_h2 *h, int prec, int64_t m, const double *B
         ++it;
     }
     #undef ORC_REPLACE
-    /* the loop ends on a recomputed residual: rmax holds the true residual norms of X */
+    /* the loop ends on a recomputed residual: rmax holds the true residual norms of X;
+     * the status describes the returned columns (a breakdown is reported as such) */
+    orc_best_restore(n, m, X, rmax, best, Xb);
     int st = 0;
     for (int64_t j = 0; j < m; ++j) {
         if (frozen[j]) st = 4;
-        else if (!conv[j] && st == 0) st = 5;
+        else if (!(rmax[j] <= rtol * bn[j]) && st == 0) st = 5;
     }
-    orc_best_restore(n, m, X, rmax, best, Xb);
     if (col_relres)
         for (int64_t j = 0; j < m; ++j) col_relres[j] = bn[j] > 0.0 ? rmax[j] / bn[j] : rmax[j];
     if (status) *status = st;
@@ -1406,8 +1407,12 @@ int64_t orc_refine_cg(const orc_h2 *h, int prec, int64_t m, const double *B, dou
         outer++;
     }
     orc_best_restore(n, m, X, rn, best, Xb);
-    if (col_relres)
-        for (int64_t j = 0; j < m; ++j) col_relres[j] = bn[j] > 0.0 ? rn[j] / bn[j] : rn[j];
+    done = 1;
+    for (int64_t j = 0; j < m; ++j) {
+        const double rel = bn[j] > 0.0 ? rn[j] / bn[j] : rn[j];
+        if (col_relres) col_relres[j] = rel;
+        if (!(rel <= rtol)) done = 0;
+    }
     if (status) *status = done ? 0 : 5;
     free(R); free(D); free(Xb); free(rn); free(best); free(bn); free(ci); free(st);
     return outer;

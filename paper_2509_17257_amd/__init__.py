@@ -124,7 +124,7 @@ def load_library():
         "h2x_matmul_adjoint_workspace_bytes": (SZ, [P, I64]),
         "h2x_matmul_adjoint": (C.c_int, [P, I64, D, P, I64, D, P, I64, P, SZ, P]),
         "h2x_grad_workspace_bytes": (SZ, [P, I64]),
-        "h2x_grad": (C.c_int, [P, I64, P, I64, P, I64, P, P, P, P, SZ, P]),
+        "h2x_grad": (C.c_int, [P, I64, P, I64, P, I64, P, P, P, D, I32, P, SZ, P]),
         "h2x_mat_set_ell": (C.c_int, [P, D, P]),
         "h2x_mat_coupling": (C.c_int, [P, P, P]),
         "h2x_mat_set_coupling": (C.c_int, [P, P, P]),
@@ -453,10 +453,14 @@ def h2_matmul_adjoint(A: H2Matrix, X, *, alpha=1.0, beta=0.0, out=None):
     return out
 
 
-def h2_grad(A: H2Matrix, X, dY, *, want_dS=True, want_dN=False, want_dell=True):
-    """Gradients of <dY, A X> (h2x_grad): returns (dS, dN, dell) as CUDA tensors, None
-    where not requested.  dS: (n_adm, k, k) in the order of Plan.blocks(); dN: the
-    near-field blocks, each |t| x |s| row-major in tree order, concatenated; dell: 0-d."""
+DELL_TERMS = {"all": 3, "coupling": 1, "near": 2}
+
+
+def h2_grad(A: H2Matrix, X, dY, *, want_dS=True, want_dN=False, want_dell=True, scale=1.0, dell_terms="all"):
+    """Gradients of scale * <dY, A X> (h2x_grad): returns (dS, dN, dell) as CUDA tensors,
+    None where not requested.  dS: (n_adm, k, k) in the order of Plan.blocks(); dN: the
+    near-field blocks, each |t| x |s| row-major in tree order, concatenated; dell: 0-d,
+    summed over the terms named by dell_terms ("all", "coupling" or "near")."""
     import torch
     _rowmajor(X, A.n, "X")
     _rowmajor(dY, A.n, "dY")
@@ -470,7 +474,8 @@ def h2_grad(A: H2Matrix, X, dY, *, want_dS=True, want_dN=False, want_dell=True):
     ws = A.workspace(m, "grad")
     vp = lambda t: C.c_void_p(t.data_ptr()) if t is not None and t.numel() else None
     _check(load_library().h2x_grad(A._h, m, vp(X), X.stride(0), vp(dY), dY.stride(0), vp(dS), vp(dN), vp(dl),
-                                   C.c_void_p(ws.data_ptr()), ws.numel(), _stream(torch, dev)), "h2x_grad")
+                                   float(scale), DELL_TERMS[dell_terms], C.c_void_p(ws.data_ptr()), ws.numel(),
+                                   _stream(torch, dev)), "h2x_grad")
     return dS, dN, dl
 
 

@@ -7,8 +7,9 @@ autograd.
 ``h2_apply(A, X, ell=None, coupling=None)``  ->  Y = A X
     backward: dX = A^T dY (adjoint product through the column lists),
     d ell = sum over admissible blocks of <dS_b/d ell, dyhat_t xhat_s^T> plus the
-    near-field term (h2x_grad), and the gradient of the coupling matrices
-    dS_b = dyhat_t xhat_s^T.
+    near-field term (h2x_grad; the near-field term alone when ``coupling`` is given,
+    since the supplied coupling matrices do not depend on ell), and the gradient of
+    the coupling matrices dS_b = dyhat_t xhat_s^T.
 
 ``h2_solve(A, B, ell=None, coupling=None, rtol=...)``  ->  X = A^{-1} B (block CG)
     backward (implicit adjoint): Lambda = A^{-T} dX by block CG (the H^2
@@ -44,16 +45,19 @@ def _sync(A: H2Matrix, ell, coupling):
 
 
 def _operator_grads(ctx, A, X, W, sign):
-    """Gradients of sign * <W, A X> w.r.t. ell and the coupling matrices."""
+    """Gradients of sign * <W, A X> w.r.t. ell and the coupling matrices.  When the coupling
+    matrices are supplied by the caller they do not depend on ell: d ell is then the
+    near-field term alone."""
     want_ell = ctx.needs_input_grad[1]
     want_S = ctx.needs_input_grad[2]
     if not (want_ell or want_S):
         return None, None
-    dS, _, dl = h2_grad(A, X, W, want_dS=want_S, want_dN=False, want_dell=want_ell)
+    terms = "near" if ctx.S_device is not None else "all"
+    dS, _, dl = h2_grad(A, X, W, want_dS=want_S, want_dN=False, want_dell=want_ell, scale=sign, dell_terms=terms)
     if dl is not None:
-        dl = (sign * dl).to(ctx.ell_device).reshape(ctx.ell_shape)
-    if dS is not None:
-        dS = (sign * dS).to(ctx.S_device)
+        dl = dl.to(ctx.ell_device).reshape(ctx.ell_shape)
+    if dS is not None and dS.device != ctx.S_device:
+        dS = dS.to(ctx.S_device)
     return dl, dS
 
 

@@ -688,7 +688,8 @@ h2x_status h2x_matmul_adjoint(const h2x_mat *A, int64_t m, double alpha, const d
 }
 
 h2x_status h2x_grad(const h2x_mat *A, int64_t m, const double *X, int64_t ldx, const double *dY, int64_t lddy,
-                    double *dS, double *dN, double *dell, void *dev_ws, size_t ws_bytes, void *hip_stream) {
+                    double *dS, double *dN, double *dell, double scale, int32_t dell_terms, void *dev_ws,
+                    size_t ws_bytes, void *hip_stream) {
     if (h2x_status r = refuse_complex(A, "h2x_grad")) return r;
     if (!A || !X || !dY || !dev_ws) return fail(H2X_EINVAL, "h2x_grad: NULL argument");
     if (A->dm.storage != H2X_F64 || A->dm.k > 64)
@@ -697,8 +698,11 @@ h2x_status h2x_grad(const h2x_mat *A, int64_t m, const double *X, int64_t ldx, c
     if (m < 1 || ldx < m || lddy < m) return fail(H2X_EINVAL, "h2x_grad: need m >= 1, ldx >= m, lddy >= m");
     if (!aligned(dev_ws)) return fail(H2X_EINVAL, "h2x_grad: workspace not 256-byte aligned");
     if (ws_bytes < grad_ws_bytes(A->dm, m)) return fail(H2X_ENOMEM, "h2x_grad: workspace too small");
+    if (dell_terms & ~(H2X_DELL_COUPLING | H2X_DELL_NEAR)) return fail(H2X_EINVAL, "h2x_grad: unknown dell_terms");
+    if (!std::isfinite(scale)) return fail(H2X_EINVAL, "h2x_grad: scale must be finite");
     if (!dS && !dN && !dell) return H2X_OK;
-    hipError_t e = run_grad(A->dm, m, X, ldx, dY, lddy, dS, dN, dell, (char *)dev_ws, (hipStream_t)hip_stream);
+    hipError_t e = run_grad(A->dm, m, X, ldx, dY, lddy, dS, dN, dell, scale, dell_terms, (char *)dev_ws,
+                            (hipStream_t)hip_stream);
     if (e != hipSuccess) return hip_fail("h2x_grad", e);
     return H2X_OK;
 }

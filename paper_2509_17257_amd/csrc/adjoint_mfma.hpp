@@ -344,18 +344,20 @@ __device__ inline double block_sum(double v) {
     return r;
 }
 
-// one admissible block per work-group: D = dyhat_t xhat_s^T (k x k, k <= 64); dS_b = D if
-// requested (row-major); part[b] = sum of (dg/dell)(xi_t,nu, xi_s,mu) D[nu][mu]
+// one admissible block per work-group: D = scale * dyhat_t xhat_s^T (k x k, k <= 64); dS_b = D
+// if requested (row-major); part[b] = sum of (dg/dell)(xi_t,nu, xi_s,mu) D[nu][mu] (0 unless
+// want_dell)
 __global__ __launch_bounds__(256) void k_grad_S_mfma(int k, int64_t m, const int32_t *__restrict__ adm_row,
                                                      const int32_t *__restrict__ adm_col,
                                                      const double *__restrict__ nodes, int kernel, double ell,
                                                      const double *__restrict__ dh, const double *__restrict__ xh,
-                                                     int64_t ldh, double *__restrict__ dS, double *__restrict__ part) {
+                                                     int64_t ldh, double scale, int want_dell,
+                                                     double *__restrict__ dS, double *__restrict__ part) {
     __shared__ GradTiles sm;
     __shared__ double pt[64][3], ps[64][3];
     const int64_t b = blockIdx.x;
     const int32_t t = adm_row[b], s = adm_col[b];
-    const bool exp_kernel = kernel == H2X_KERNEL_EXP;
+    const bool exp_kernel = kernel == H2X_KERNEL_EXP && want_dell;
     if (exp_kernel) {
         stage_points(pt, nodes + (int64_t)t * k * 3, k);
         stage_points(ps, nodes + (int64_t)s * k * 3, k);
@@ -372,7 +374,7 @@ __global__ __launch_bounds__(256) void k_grad_S_mfma(int k, int64_t m, const int
         for (int r = 0; r < 4; ++r) {
             const int nu = 16 * w + g + 4 * r;
             if (nu < k && mu < k) {
-                const double d = acc[J][r];
+                const double d = scale * acc[J][r];
                 if (dS) dS[b * k * k + nu * k + mu] = d;
                 if (exp_kernel) gsum += dg_dell_mc(inv_ell, inv_ell2, pt[nu], ps[mu]) * d;
             }
@@ -382,8 +384,9 @@ __global__ __launch_bounds__(256) void k_grad_S_mfma(int k, int64_t m, const int
     if (tid == 0) part[b] = tot;
 }
 
-// one near-field block per work-group: D = dY|_t X|_s^T (tree-ordered dY, X); dN_b = D
-// (row-major |t| x |s|) if requested; part[q] = sum of (dg/dell)(x_i, x_j) D[i][j]
+// one near-field block per work-group: D = scale * dY|_t X|_s^T (tree-ordered dY, X); dN_b = D
+// (row-major |t| x |s|) if requested; part[q] = sum of (dg/dell)(x_i, x_j) D[i][j] (0 unless
+// want_dell)
 __global__ __launch_bounds__(256) void k_grad_N_mfma(int64_t m, const int32_t *__restrict__ near_row,
                                                      const int32_t *__restrict__ near_col,
                                                      const int64_t *__restrict__ near_off_rm,
@@ -391,7 +394,8 @@ __global__ __launch_bounds__(256) void k_grad_N_mfma(int64_t m, const int32_t *_
                                                      const int32_t *__restrict__ size,
                                                      const double *__restrict__ pts, int kernel, double ell,
                                                      const double *__restrict__ dYt, const double *__restrict__ Xt,
-                                                     int64_t ldt, double *__restrict__ dN, double *__restrict__ part) {
+                                                     int64_t ldt, double scale, int want_dell,
+                                                     double *__restrict__ dN, double *__restrict__ part) {
     __shared__ GradTiles sm;
     __shared__ double pt[64][3], ps[64][3];
     const int64_t q = blockIdx.x;
@@ -399,7 +403,7 @@ __global__ __launch_bounds__(256) void k_grad_N_mfma(int64_t m, const int32_t *_
     const int nt = size[t], ns = size[s];
     const int64_t ft = first[t], fs = first[s];
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, lr = lane & 15, g = lane >> 4;
-    const bool exp_kernel = kernel == H2X_KERNEL_EXP;
+    const bool exp_kernel = kernel == H2X_KERNEL_EXP && want_dell;
     const double inv_ell = 1.0 / ell, inv_ell2 = inv_ell * inv_ell;
     double gsum = 0.0;
     for (int i0 = 0; i0 < nt; i0 += 64)
@@ -418,7 +422,7 @@ __global__ __launch_bounds__(256) void k_grad_N_mfma(int64_t m, const int32_t *_
                 for (int r = 0; r < 4; ++r) {
                     const int i = 16 * w + g + 4 * r;
                     if (i < ic && c < cc) {
-                        const double d = acc[J][r];
+                        const double d = scale * acc[J][r];
                         if (dN) dN[near_off_rm[q] + (int64_t)(i0 + i) * ns + c0 + c] = d;
                         if (exp_kernel) gsum += dg_dell_mc(inv_ell, inv_ell2, pt[i], ps[c]) * d;
                     }

@@ -29,7 +29,9 @@ struct CgState {
 
 struct CgCols {  // per (system, column) arrays, nseg * m entries each, system-major
     double *bnorm, *rr, *beta, *alpha, *gamma;
+    double *best;  // smallest squared true residual norm seen (mixed precision)
     int32_t *frozen, *conv, *first_conv, *status, *act;
+    int32_t *keep;  // column whose current iterate is to be kept as the best (mixed precision)
 };
 
 // Dot-product blocks: block b covers rows [blk_r0[b], blk_r0[b + 1]) of system
@@ -204,6 +206,8 @@ __global__ __launch_bounds__(kScalarThreads) void k_cg_init(int64_t m, int nblk,
         cols.act[e] = 0;
         cols.alpha[e] = 0.0;
         cols.gamma[e] = 0.0;
+        cols.best[e] = HUGE_VAL;
+        cols.keep[e] = 0;
         return !c;
     });
     if (threadIdx.x == 0) {
@@ -367,6 +371,10 @@ __global__ __launch_bounds__(kScalarThreads) void k_rel_replace(int64_t m, int n
                               Segs sg, double *rmax) {
     const bool open = for_columns(m, nblk, part, sg, 0, [&](int64_t, int64_t e, double rr, double) {
         cols.rr[e] = rr;
+        // the best iterate so far: a strictly smaller true residual
+        const int better = rr < cols.best[e];
+        cols.keep[e] = better;
+        if (better) cols.best[e] = rr;
         rmax[e] = sqrt(rr);
         const int c = sqrt(rr) <= rtol * cols.bnorm[e];
         cols.conv[e] = c;
@@ -379,6 +387,26 @@ __global__ __launch_bounds__(kScalarThreads) void k_rel_replace(int64_t m, int n
         state->all_conv = open ? 0 : 1;
         state->skip = 0;
         state->pad = 0;
+    }
+}
+
+// Columns of X (n x m, leading dimension m) flagged in keep -> the same columns of Xb.
+__global__ void k_keep_cols(int64_t n, int64_t m, const int32_t *__restrict__ keep, const double *__restrict__ X,
+                            double *__restrict__ Xb) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * m) return;
+    if (keep[e % m]) Xb[e] = X[e];
+}
+
+// End of a mixed-precision solve (the residual was just recomputed): a column whose best
+// true residual is smaller than its current one gets its best iterate back (keep = 1)
+// and the best residual; convergence follows the returned iterate.
+__global__ void k_best_final(int64_t m, double rtol, CgCols cols) {
+    for (int64_t j = threadIdx.x; j < m; j += blockDim.x) {
+        const int back = cols.best[j] < cols.rr[j];
+        cols.keep[j] = back;
+        if (back) cols.rr[j] = cols.best[j];
+        cols.conv[j] = sqrt(cols.rr[j]) <= rtol * cols.bnorm[j];
     }
 }
 
@@ -422,7 +450,7 @@ Layout make_layout(const DevMat *const *mats, int32_t nmat, int64_t m) {
 }
 
 struct CgWs {
-    double *Bt, *Xt, *R, *P, *AP, *part, *rmax;
+    double *Bt, *Xt, *R, *P, *AP, *part, *rmax, *Xb;
     CgState *state;
     CgCols cols;
     int64_t *blk_r0;
@@ -431,7 +459,8 @@ struct CgWs {
     size_t bytes;
 };
 
-CgWs cg_layout(const Layout &L, int64_t m, char *base) {
+// keep_best: mixed precision, with room for the best iterate (tree order)
+CgWs cg_layout(const Layout &L, int64_t m, char *base, bool keep_best = false) {
     CgWs w{};
     size_t off = 0;
     auto carve = [&](size_t bytes) {
@@ -446,12 +475,14 @@ CgWs cg_layout(const Layout &L, int64_t m, char *base) {
     w.R = (double *)carve(nm);
     w.P = (double *)carve(nm);
     w.AP = (double *)carve(nm);
+    w.Xb = keep_best ? (double *)carve(nm) : nullptr;
     w.part = (double *)carve(2 * (size_t)L.nblk * m * sizeof(double));
     w.rmax = (double *)carve(sm * sizeof(double));
     w.state = (CgState *)carve(sizeof(CgState));
-    double **dcols[5] = {&w.cols.bnorm, &w.cols.rr, &w.cols.beta, &w.cols.alpha, &w.cols.gamma};
+    double **dcols[6] = {&w.cols.bnorm, &w.cols.rr, &w.cols.beta, &w.cols.alpha, &w.cols.gamma, &w.cols.best};
     for (auto d : dcols) *d = (double *)carve(sm * sizeof(double));
-    int32_t **icols[5] = {&w.cols.frozen, &w.cols.conv, &w.cols.first_conv, &w.cols.status, &w.cols.act};
+    int32_t **icols[6] = {&w.cols.frozen, &w.cols.conv, &w.cols.first_conv, &w.cols.status, &w.cols.act,
+                          &w.cols.keep};
     for (auto d : icols) *d = (int32_t *)carve(sm * sizeof(int32_t));
     w.blk_r0 = (int64_t *)carve((L.nblk + 1) * sizeof(int64_t));
     w.blk_seg = (int32_t *)carve(L.nblk * sizeof(int32_t));
@@ -480,6 +511,18 @@ __global__ void k_axpy_ld(int64_t n, int64_t m, const double *__restrict__ D, do
     X[i * ldx + j] += D[e];
 }
 
+// columns flagged in keep: X (leading dimension ldx) -> Xb (leading dimension m) when
+// to_best, Xb -> X otherwise
+__global__ void k_copy_cols_ld(int64_t n, int64_t m, const int32_t *__restrict__ keep, double *__restrict__ X,
+                               int64_t ldx, double *__restrict__ Xb, int to_best) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * m) return;
+    const int64_t i = e / m, j = e % m;
+    if (!keep[j]) return;
+    if (to_best) Xb[e] = X[i * ldx + j];
+    else X[i * ldx + j] = Xb[e];
+}
+
 __global__ void k_zero(int64_t count, double *__restrict__ p) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e < count) p[e] = 0.0;
@@ -494,7 +537,8 @@ __global__ void k_sum_parts(int64_t m, int nblk, const double *part, double *out
 }
 
 struct RefineWs {
-    double *B, *R, *D, *part, *norms;
+    double *B, *R, *D, *part, *norms, *Xb;
+    int32_t *keep;
     char *mm, *cg;
     int nblk;
     size_t bytes;
@@ -514,8 +558,10 @@ RefineWs refine_layout(const DevMat &hi, const DevMat &lo, int64_t m, char *base
     w.B = (double *)carve(nm);
     w.R = (double *)carve(nm);
     w.D = (double *)carve(nm);
+    w.Xb = (double *)carve(nm);
     w.part = (double *)carve(2 * (size_t)w.nblk * m * sizeof(double));
     w.norms = (double *)carve(2 * m * sizeof(double));
+    w.keep = (int32_t *)carve(m * sizeof(int32_t));
     w.mm = carve(matmul_ws_bytes(hi, m));
     w.cg = carve(cg_ws_bytes(lo, m));
     w.bytes = align_up(off);
@@ -551,8 +597,17 @@ h2x_status run_refine(const DevMat &hi, const DevMat &lo, const h2x_cg_params &i
         return H2X_EHIP;
     };
     hipLaunchKernelGGL(k_copy_ld, dim3(g1), dim3(256), 0, st, n, m, B, ldb, w.B, m);
-    std::vector<double> norms(2 * m);
-    int32_t outer = 0, inner_total = 0, status = H2X_OK, stalls = 0;
+    std::vector<double> norms(2 * m), best(m, HUGE_VAL);
+    std::vector<int32_t> keep(m);
+    // columns flagged in keep: X -> Xb (to_best) or Xb -> X
+    auto copy_cols = [&](bool to_best) {
+        hipError_t e = hipMemcpyAsync(w.keep, keep.data(), m * sizeof(int32_t), hipMemcpyHostToDevice, st);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_copy_cols_ld, dim3(g1), dim3(256), 0, st, n, m, (const int32_t *)w.keep, X, ldx, w.Xb,
+                           to_best ? 1 : 0);
+        return hipGetLastError();
+    };
+    int32_t outer = 0, inner_total = 0, stalls = 0;
     double prev = HUGE_VAL;
     for (;;) {
         // R = B - A X in FP64; squared norms of R and B
@@ -564,21 +619,24 @@ h2x_status run_refine(const DevMat &hi, const DevMat &lo, const h2x_cg_params &i
         e = hipMemcpyAsync(norms.data(), w.norms, 2 * m * sizeof(double), hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         if (e != hipSuccess) return fail(e);
-        bool done = true;
+        bool done = true, better = false;
         double worst = 0.0;
         for (int64_t j = 0; j < m; ++j) {
             const double bn = std::sqrt(norms[m + j]), rn = std::sqrt(norms[j]);
             if (rn > rtol * bn) done = false;
             worst = std::max(worst, bn > 0 ? rn / bn : rn);
+            // the best outer iterate of every column (smallest true residual) is kept
+            keep[j] = norms[j] < best[j];
+            if (keep[j]) {
+                best[j] = norms[j];
+                better = true;
+            }
         }
+        if (better && (e = copy_cols(true)) != hipSuccess) return fail(e);
         // a step that does not halve the worst relative residual is a stall; two stalls stop
         if (worst > 0.5 * prev) ++stalls;
         prev = worst;
-        if (done) break;
-        if (outer >= max_outer || stalls >= 2) {
-            status = H2X_ENOCONV;
-            break;
-        }
+        if (done || outer >= max_outer || stalls >= 2) break;
         // A_lo D = R by block CG, then X += D
         hipLaunchKernelGGL(k_zero, dim3(g1), dim3(256), 0, st, nm, w.D);
         h2x_cg_info ii{};
@@ -587,6 +645,25 @@ h2x_status run_refine(const DevMat &hi, const DevMat &lo, const h2x_cg_params &i
         inner_total += ii.iters;
         hipLaunchKernelGGL(k_axpy_ld, dim3(g1), dim3(256), 0, st, n, m, w.D, X, ldx);
         ++outer;
+    }
+    // every column returns its best outer iterate
+    bool back = false;
+    for (int64_t j = 0; j < m; ++j) {
+        keep[j] = best[j] < norms[j];
+        if (keep[j]) {
+            norms[j] = best[j];
+            back = true;
+        }
+    }
+    if (back) {
+        hipError_t e = copy_cols(false);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return fail(e);
+    }
+    int32_t status = H2X_OK;
+    for (int64_t j = 0; j < m; ++j) {
+        const double rn = std::sqrt(norms[j]), bn = std::sqrt(norms[m + j]);
+        if (!((bn > 0 ? rn / bn : rn) <= rtol)) status = H2X_ENOCONV;
     }
     if (info) {
         info->iters = inner_total;
@@ -609,7 +686,7 @@ h2x_status run_block_cg_batch(const DevMat *const *mats, int32_t nmat, const h2x
                               h2x_cg_info *info, hipStream_t st, const DevMat *hi, double delta) {
     Layout L = make_layout(mats, nmat, m);
     if (hi) L.mm_bytes = std::max(L.mm_bytes, matmul_ws_bytes(*hi, m));
-    CgWs w = cg_layout(L, m, ws);
+    CgWs w = cg_layout(L, m, ws, hi != nullptr);
     if (ws_bytes < w.bytes) {
         set_error("h2x_block_cg: workspace too small");
         return H2X_ENOMEM;
@@ -684,6 +761,8 @@ h2x_status run_block_cg_batch(const DevMat *const *mats, int32_t nmat, const h2x
                            (const double *)nullptr, w.part, (const CgState *)nullptr);
         hipLaunchKernelGGL(k_rel_replace, dim3(1), dim3(kScalarThreads), 0, s, m, nblk, (const double *)w.part, prm.rtol,
                            w.state, w.cols, sg, w.rmax);
+        hipLaunchKernelGGL(k_keep_cols, dim3(g1), dim3(256), 0, s, n, m, (const int32_t *)w.cols.keep,
+                           (const double *)w.Xt, w.Xb);
         return hipGetLastError();
     };
 
@@ -710,6 +789,8 @@ h2x_status run_block_cg_batch(const DevMat *const *mats, int32_t nmat, const h2x
                            (const double *)nullptr, w.part, (const CgState *)nullptr);
         hipLaunchKernelGGL(k_rel_replace, dim3(1), dim3(kScalarThreads), 0, st, m, nblk, (const double *)w.part, prm.rtol,
                            w.state, w.cols, sg, w.rmax);
+        hipLaunchKernelGGL(k_keep_cols, dim3(g1), dim3(256), 0, st, n, m, (const int32_t *)w.cols.keep,
+                           (const double *)w.Xt, w.Xb);
     }
 
     const int check = prm.check_every > 0 ? prm.check_every : 1;
@@ -762,6 +843,12 @@ h2x_status run_block_cg_batch(const DevMat *const *mats, int32_t nmat, const h2x
     if (run != st) {
         e = hipStreamSynchronize(run);
         if (e != hipSuccess) return fail(e);
+    }
+    if (hi) {
+        // every column returns its iterate with the smallest recomputed true residual
+        hipLaunchKernelGGL(k_best_final, dim3(1), dim3(256), 0, st, m, prm.rtol, w.cols);
+        hipLaunchKernelGGL(k_keep_cols, dim3(g1), dim3(256), 0, st, n, m, (const int32_t *)w.cols.keep,
+                           (const double *)w.Xb, w.Xt);
     }
     for (int32_t q = 0; q < nmat; ++q) {
         const DevMat &dm = *mats[q];
@@ -816,7 +903,7 @@ size_t mixed_ws_bytes(const DevMat &hi, const DevMat &lo, int64_t m) {
     const DevMat *p = &lo;
     Layout L = make_layout(&p, 1, m);
     L.mm_bytes = std::max(L.mm_bytes, matmul_ws_bytes(hi, m));
-    return cg_layout(L, m, nullptr).bytes;
+    return cg_layout(L, m, nullptr, true).bytes;
 }
 
 h2x_status run_block_cg_mixed(const DevMat &hi, const DevMat &lo, const h2x_cg_params &prm, double delta, int64_t m,

@@ -170,7 +170,8 @@ hipError_t run_matmul_adjoint(const DevMat &dm, int64_t m, double alpha, const d
 size_t adjoint_ws_bytes(const DevMat &dm, int64_t m);
 size_t grad_ws_bytes(const DevMat &dm, int64_t m);
 hipError_t run_grad(const DevMat &dm, int64_t m, const double *X, int64_t ldx, const double *dY, int64_t lddy,
-                    double *dS, double *dN, double *dell, char *ws, hipStream_t st);
+                    double *dS, double *dN, double *dell, double scale, int32_t dell_terms, char *ws,
+                    hipStream_t st);
 hipError_t refill_ell(DevMat &dm, double ell, hipStream_t st);
 hipError_t run_read_coupling(const DevMat &dm, double *out, hipStream_t st);
 hipError_t run_write_coupling(const DevMat &dm, const double *in, hipStream_t st);

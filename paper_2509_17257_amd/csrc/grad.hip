@@ -164,13 +164,14 @@ __global__ __launch_bounds__(256) void k_leaf_near_adj(int k, int64_t m, const i
     }
 }
 
-// one admissible block per work-group: D = dyhat_t xhat_s^T (k x k, k <= 64);
-// dS_b = D if requested; part[b] = sum of (dg/dell) * D in a fixed order
+// one admissible block per work-group: D = scale * dyhat_t xhat_s^T (k x k, k <= 64);
+// dS_b = D if requested; part[b] = sum of (dg/dell) * D in a fixed order (0 unless want_dell)
 __global__ __launch_bounds__(256) void k_grad_S(int k, int64_t m, const int32_t *__restrict__ adm_row,
                                                 const int32_t *__restrict__ adm_col,
                                                 const double *__restrict__ nodes, int kernel, double ell,
                                                 const double *__restrict__ dh, const double *__restrict__ xh,
-                                                int64_t ldh, double *__restrict__ dS, double *__restrict__ part) {
+                                                int64_t ldh, double scale, int want_dell, double *__restrict__ dS,
+                                                double *__restrict__ part) {
     __shared__ double sd[64][65], sx[64][65];
     __shared__ double red[256];
     const int64_t b = blockIdx.x;
@@ -203,8 +204,10 @@ __global__ __launch_bounds__(256) void k_grad_S(int k, int64_t m, const int32_t 
         const int e = tid + 256 * u;
         if (e < kk) {
             const int nu = e / k, mu = e % k;
-            if (dS) dS[b * kk + e] = acc[u];
-            g += dg_dell(kernel, ell, &nodes[((int64_t)t * k + nu) * 3], &nodes[((int64_t)s * k + mu) * 3]) * acc[u];
+            const double d = scale * acc[u];
+            if (dS) dS[b * kk + e] = d;
+            if (want_dell)
+                g += dg_dell(kernel, ell, &nodes[((int64_t)t * k + nu) * 3], &nodes[((int64_t)s * k + mu) * 3]) * d;
         }
     }
     red[tid] = g;
@@ -216,15 +219,16 @@ __global__ __launch_bounds__(256) void k_grad_S(int k, int64_t m, const int32_t 
     if (tid == 0) part[b] = red[0];
 }
 
-// one near-field block per work-group: D = dY|_t X|_s^T (tree-ordered dY, X);
-// dN_b = D (row-major |t| x |s|) if requested; part[q] = sum of (dg/dell) * D
+// one near-field block per work-group: D = scale * dY|_t X|_s^T (tree-ordered dY, X);
+// dN_b = D (row-major |t| x |s|) if requested; part[q] = sum of (dg/dell) * D (0 unless want_dell)
 __global__ __launch_bounds__(256) void k_grad_N(int64_t m, const int32_t *__restrict__ near_row,
                                                 const int32_t *__restrict__ near_col,
                                                 const int64_t *__restrict__ near_off_rm,
                                                 const int32_t *__restrict__ first, const int32_t *__restrict__ size,
                                                 const double *__restrict__ pts, int kernel, double ell,
                                                 const double *__restrict__ dYt, const double *__restrict__ Xt,
-                                                int64_t ldt, double *__restrict__ dN, double *__restrict__ part) {
+                                                int64_t ldt, double scale, int want_dell, double *__restrict__ dN,
+                                                double *__restrict__ part) {
     __shared__ double sd[64][33], sx[64][33];
     __shared__ double red[256];
     const int64_t q = blockIdx.x;
@@ -258,8 +262,9 @@ __global__ __launch_bounds__(256) void k_grad_N(int64_t m, const int32_t *__rest
             for (int u = 0; u < 16; ++u) {
                 const int e = tid + 256 * u, i = e / 64, c = e % 64;
                 if (i < ic && c < cc) {
-                    if (dN) dN[near_off_rm[q] + (int64_t)(i0 + i) * ns + c0 + c] = acc[u];
-                    g += dg_dell(kernel, ell, &pts[3 * (ft + i0 + i)], &pts[3 * (fs + c0 + c)]) * acc[u];
+                    const double d = scale * acc[u];
+                    if (dN) dN[near_off_rm[q] + (int64_t)(i0 + i) * ns + c0 + c] = d;
+                    if (want_dell) g += dg_dell(kernel, ell, &pts[3 * (ft + i0 + i)], &pts[3 * (fs + c0 + c)]) * d;
                 }
             }
         }
@@ -402,12 +407,25 @@ hipError_t run_matmul_adjoint(const DevMat &dm, int64_t m, double alpha, const d
     return hipGetLastError();
 }
 
+__global__ void k_fill0(int64_t count, double *__restrict__ p) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < count) p[e] = 0.0;
+}
+
 hipError_t run_grad(const DevMat &dm, int64_t m, const double *X, int64_t ldx, const double *dY, int64_t lddy,
-                    double *dS, double *dN, double *dell, char *ws, hipStream_t st) {
+                    double *dS, double *dN, double *dell, double scale, int32_t dell_terms, char *ws,
+                    hipStream_t st) {
     GradWs w = grad_layout(dm, m, ws);
     const int64_t ldh = even(m);
     hipError_t e = hipSuccess;
-    if (dS || dell) {
+    const int cpl = dell && (dell_terms & H2X_DELL_COUPLING) ? 1 : 0, nr = dell && (dell_terms & H2X_DELL_NEAR) ? 1 : 0;
+    // the partial sums of dell's terms that are not wanted are zero
+    if (dell && !cpl && dm.n_adm > 0)
+        hipLaunchKernelGGL(k_fill0, dim3((unsigned)((dm.n_adm + 255) / 256)), dim3(256), 0, st, dm.n_adm, w.part);
+    if (dell && !nr && dm.n_near > 0)
+        hipLaunchKernelGGL(k_fill0, dim3((unsigned)((dm.n_near + 255) / 256)), dim3(256), 0, st, dm.n_near,
+                           w.part + dm.n_adm);
+    if (dS || cpl) {
         e = run_forward_transform(dm, m, X, ldx, false, w.xh, ldh, w.xt_ws, st);
         if (e == hipSuccess) e = run_forward_transform(dm, m, dY, lddy, false, w.dh, ldh, w.xt_ws, st);
         if (e != hipSuccess) return e;
@@ -415,14 +433,14 @@ hipError_t run_grad(const DevMat &dm, int64_t m, const double *X, int64_t ldx, c
             if (dm.mc)
                 hipLaunchKernelGGL(adj::k_grad_S_mfma, dim3((unsigned)dm.n_adm), dim3(256), 0, st, dm.k, m, dm.adm_row,
                                    dm.adm_col, dm.nodes, dm.kernel, dm.ell, (const double *)w.dh,
-                                   (const double *)w.xh, ldh, dS, w.part);
+                                   (const double *)w.xh, ldh, scale, cpl, dS, w.part);
             else
                 hipLaunchKernelGGL(k_grad_S, dim3((unsigned)dm.n_adm), dim3(256), 0, st, dm.k, m, dm.adm_row,
                                    dm.adm_col, dm.nodes, dm.kernel, dm.ell, (const double *)w.dh,
-                                   (const double *)w.xh, ldh, dS, w.part);
+                                   (const double *)w.xh, ldh, scale, cpl, dS, w.part);
         }
     }
-    if (dN || dell) {
+    if (dN || nr) {
         const int64_t cnt = dm.n * ldh;
         hipLaunchKernelGGL(k_gather_even, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, dm.n, m, dm.perm, X,
                            ldx, w.Xt, ldh);
@@ -432,11 +450,13 @@ hipError_t run_grad(const DevMat &dm, int64_t m, const double *X, int64_t ldx, c
             if (dm.mc)
                 hipLaunchKernelGGL(adj::k_grad_N_mfma, dim3((unsigned)dm.n_near), dim3(256), 0, st, m, dm.near_row,
                                    dm.near_col, dm.near_off_rm, dm.first, dm.size, dm.pts, dm.kernel, dm.ell,
-                                   (const double *)w.dYt, (const double *)w.Xt, ldh, dN, w.part + dm.n_adm);
+                                   (const double *)w.dYt, (const double *)w.Xt, ldh, scale, nr, dN,
+                                   w.part + dm.n_adm);
             else
                 hipLaunchKernelGGL(k_grad_N, dim3((unsigned)dm.n_near), dim3(256), 0, st, m, dm.near_row,
                                    dm.near_col, dm.near_off_rm, dm.first, dm.size, dm.pts, dm.kernel, dm.ell,
-                                   (const double *)w.dYt, (const double *)w.Xt, ldh, dN, w.part + dm.n_adm);
+                                   (const double *)w.dYt, (const double *)w.Xt, ldh, scale, nr, dN,
+                                   w.part + dm.n_adm);
         }
     }
     if (dell) {

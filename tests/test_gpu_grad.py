@@ -42,6 +42,13 @@ def _colrel(a, b):
     return (np.linalg.norm(a - b, axis=0) / den).max()
 
 
+def _entrel(a, b):
+    """Largest entry-wise difference of each column over that column's largest entry."""
+    den = np.abs(b).max(axis=0)
+    den[den == 0] = 1.0
+    return (np.abs(a - b).max(axis=0) / den).max()
+
+
 def _dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
@@ -161,6 +168,10 @@ def test_set_ell_and_dell_finite_difference():
 
 
 def test_autograd_apply_matches_entry_points():
+    """h2_apply with ell and the coupling matrices both as inputs: dX is the adjoint product,
+    dS the entry point's dS, and d ell the near-field term only (the supplied coupling
+    matrices do not depend on ell), which a central difference of <W, A(ell; S fixed) X>
+    confirms."""
     h2x = _h2x()
     from paper_2509_17257_amd.autograd import h2_apply
     P = W.sphere_points(5000, 192)
@@ -169,19 +180,50 @@ def test_autograd_apply_matches_entry_points():
     Wt = _dev(W.rhs(5000, 4, 194))
     ell = torch.tensor(0.45, dtype=torch.float64, requires_grad=True)
     A.set_ell(0.45)
-    S = A.coupling().requires_grad_(True)
+    S0 = A.coupling()
+    S = S0.clone().requires_grad_(True)
     Y = h2_apply(A, X, ell, S)
     (Wt * Y).sum().backward()
     Xd = X.detach()
     dX = h2x.h2_matmul_adjoint(A, Wt)
-    dS, _, dl = h2x.h2_grad(A, Xd, Wt)
+    dS, _, dl_near = h2x.h2_grad(A, Xd, Wt, dell_terms="near")
+    _, _, dl_all = h2x.h2_grad(A, Xd, Wt, want_dS=False)
     torch.testing.assert_close(X.grad, dX, rtol=0, atol=0)
     torch.testing.assert_close(S.grad, dS, rtol=0, atol=0)
-    assert float(ell.grad) == float(dl.cpu())
+    assert float(ell.grad) == float(dl_near.cpu())
     assert ell.grad.device.type == "cpu"
+    # S held fixed: the length scale moves the near field only
+    h = 1e-6
+    L = []
+    for e in (0.45 + h, 0.45 - h):
+        A.set_ell(e)
+        A.set_coupling(S0)
+        L.append(float((Wt * h2x.h2_matmul(A, Xd)).sum().cpu()))
+    fd = (L[0] - L[1]) / (2 * h)
+    g, ga = float(ell.grad), float(dl_all.cpu())
+    print(f"d ell with S fixed {g:.10e}, central difference {fd:.10e}; with S(ell) {ga:.10e}")
+    assert abs(g - fd) <= 1e-6 * abs(g)
+    assert abs(ga - g) > 1e-3 * abs(g)  # the coupling term is not small: counting it would show
     # the forward step ran the operator at ell = 0.45
+    A.set_ell(0.45)
     o = oracle.OracleH2(P, ell=0.45, shift=1.0, eta=1.0, leaf=64, p=4)
     assert _colrel(Y.detach().cpu().numpy(), o.matmul(Xd.cpu().numpy())) <= TOL
+
+
+def test_grad_scale_and_terms():
+    """h2x_grad's scale multiplies dS, dN and d ell exactly (scale = -1: exact negation);
+    the coupling and near terms of d ell add up to the full d ell."""
+    h2x = _h2x()
+    P = W.sphere_points(4000, 197)
+    A = h2x.H2Matrix(P, ell=0.5, shift=1.0, eta=1.0, leaf=64, p=4)
+    Xd, Wd = _dev(W.rhs(4000, 5, 198)), _dev(W.rhs(4000, 5, 199))
+    dS, dN, dl = h2x.h2_grad(A, Xd, Wd, want_dN=True)
+    nS, nN, nl = h2x.h2_grad(A, Xd, Wd, want_dN=True, scale=-1.0)
+    assert torch.equal(nS, -dS) and torch.equal(nN, -dN) and float(nl) == -float(dl)
+    _, _, lc = h2x.h2_grad(A, Xd, Wd, want_dS=False, dell_terms="coupling")
+    _, _, ln = h2x.h2_grad(A, Xd, Wd, want_dS=False, dell_terms="near")
+    tot, parts = float(dl), float(lc) + float(ln)
+    assert abs(tot - parts) <= 1e-12 * (abs(float(lc)) + abs(float(ln)))
 
 
 def test_autograd_solve_implicit_adjoint():
@@ -249,7 +291,17 @@ def test_grad_workload_full_size():
     dS_s = dS[torch.from_numpy(idx).cuda()].cpu().numpy()
     ref = np.stack([dh[pb["adm_t"][b]] @ xh[pb["adm_s"][b]].T for b in idx])
     err_S = np.abs(dS_s - ref).max() / np.abs(ref).max()
-    print(f"full size n={n}: adjoint-vs-product {err_sym:.2e}, dell {dl:.10e} fd {fd:.10e}, sampled dS {err_S:.2e}")
+    # forward and adjoint products on sampled columns against the oracle (each column of a
+    # product depends on its own column only); per column in norm and entry by entry
+    cols = [0, 7, 15]
+    dYs = np.ascontiguousarray(dY[:, cols])
+    ref_f, ref_a = o.matmul(dYs), o.matmul_adjoint(dYs)
+    got_f, got_a = fwd.cpu().numpy()[:, cols], adj.cpu().numpy()[:, cols]
+    err_f, err_a = _colrel(got_f, ref_f), _colrel(got_a, ref_a)
+    ent_f, ent_a = _entrel(got_f, ref_f), _entrel(got_a, ref_a)
+    print(f"full size n={n}: adjoint-vs-product {err_sym:.2e}, dell {dl:.10e} fd {fd:.10e}, sampled dS {err_S:.2e}, "
+          f"product vs oracle {err_f:.2e} (entries {ent_f:.2e}), adjoint vs oracle {err_a:.2e} (entries {ent_a:.2e})")
     assert err_sym <= TOL
     assert abs(dl - fd) <= 1e-6 * abs(dl)
     assert err_S <= TOL
+    assert max(err_f, err_a) <= TOL and max(ent_f, ent_a) <= TOL

@@ -4,6 +4,9 @@ Bar (FP64): per column, ||Y_gpu - Y_oracle|| / ||Y_oracle|| <= 1e-12, on the sam
 seeded inputs, at sizes that span several tiles and ragged tails, at the full
 FP64 throughput size, and on the edge cases (m = 1, ragged m, leaves larger
 than one tile, no admissible block, a single leaf, alpha/beta, tree order).
+The main cases and the full size also bound every entry: per column,
+max_i |Y_gpu - Y_oracle|_i <= 1e-12 max_i |Y_oracle|_i, so that an error confined
+to a few rows cannot hide in a column norm.
 """
 import numpy as np
 import pytest
@@ -26,6 +29,13 @@ def _colrel(a, b):
     den = np.linalg.norm(b, axis=0)
     den[den == 0] = 1.0
     return (np.linalg.norm(a - b, axis=0) / den).max()
+
+
+def _entrel(a, b):
+    """Largest entry-wise difference of each column over that column's largest entry."""
+    den = np.abs(b).max(axis=0)
+    den[den == 0] = 1.0
+    return (np.abs(a - b).max(axis=0) / den).max()
 
 
 def _pair(P, **kw):
@@ -68,9 +78,9 @@ def test_matmul_matches_oracle(name, pts, prm, m):
     X = W.rhs(P.shape[0], m, 90 + m)
     ref = o.matmul(X)
     got = _gpu(A, X)
-    err = _colrel(got, ref)
-    print(f"{name}: n={P.shape[0]} adm={o.n_adm} near={o.n_near} max col rel err={err:.3e}")
-    assert err <= TOL
+    err, ent = _colrel(got, ref), _entrel(got, ref)
+    print(f"{name}: n={P.shape[0]} adm={o.n_adm} near={o.n_near} max col rel err={err:.3e}, entries {ent:.3e}")
+    assert err <= TOL and ent <= TOL
 
 
 ROWS = [c for c in CASES if c[0] in ("small-k27-m37", "sphere-k64-m32", "cube-k64-m5", "cube-k8-leaf100",
@@ -218,9 +228,9 @@ def test_full_fp64_workload():
     X = w.rhs()
     ref = o.matmul(X)
     got = _gpu(A, X)
-    err = _colrel(got, ref)
-    print(f"{w.name}: adm={o.n_adm} near={o.n_near} max col rel err={err:.3e}")
-    assert err <= TOL
+    err, ent = _colrel(got, ref), _entrel(got, ref)
+    print(f"{w.name}: adm={o.n_adm} near={o.n_near} max col rel err={err:.3e}, entries {ent:.3e}")
+    assert err <= TOL and ent <= TOL
 
 
 def test_invalid_arguments_on_gpu():

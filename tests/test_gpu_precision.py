@@ -136,3 +136,101 @@ def test_precision_workload_full_size():
     for p, e in errs.items():
         lo, hi = full[p]
         assert lo < e < hi
+
+
+# ---- the hand-worked rounding points (reading R16), on the GPU ----
+
+@pytest.mark.parametrize("prec", ["bf16", "f32"])
+def test_lowp_rounding_points_hand_worked(prec):
+    """The GPU's BF16 / FP32 operators on the hand-worked case of tests/golden/lowp_line16.json
+    (16 points on a line, p = 1, constant kernel): the product equals the values worked by
+    hand from the rounding points, independently of the oracle."""
+    import json
+    import os
+    import paper_2509_17257_amd as h2x
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "lowp_line16.json")))
+    P = np.zeros((16, 3))
+    P[:, 0] = g["points_x"]
+    A = h2x.H2Matrix(P, kernel="const", storage=prec, ell=1.0, shift=g["shift"], eta=g["eta"],
+                     leaf=g["leaf_size"], p=1)
+    X = np.zeros((16, len(g["columns"])))
+    for j, col in enumerate(g["columns"]):
+        for i, v in col["x_nonzero"].items():
+            X[int(i), j] = v
+    got = h2x.h2_matmul(A, torch.from_numpy(X).cuda()).cpu().numpy()
+    yb = np.array([c["y_bf16"] for c in g["columns"]]).T
+    ye = np.array([c["y_exact"] for c in g["columns"]]).T
+    want = yb if prec == "bf16" else np.concatenate([ye[:, :3], yb[:, 3:]], axis=1)
+    for j in range(X.shape[1]):
+        print(f"{prec} column {j}: got {got[:, j].tolist()}")
+    np.testing.assert_array_equal(got, want)
+
+
+# ---- solves that cannot converge return their best iterate ----
+
+def test_recovery_returns_best_iterate_when_it_cannot_converge():
+    """Unit-cube points, length scale 1, shift 1e-3 (kappa 1.3e5, BF16 operator error
+    2e-3): BF16 refinement and BF16 residual replacement cannot converge.  Both report
+    it, and every returned column has a true residual (oracle product) at most that of
+    X0 = 0; the reported residuals are those of the returned columns."""
+    import paper_2509_17257_amd as h2x
+    P = np.random.default_rng(131).random((1500, 3))
+    prm = dict(ell=1.0, shift=1e-3, eta=1.0, leaf=32, p=3)
+    o = oracle.OracleH2(P, **prm)
+    plan = h2x.Plan(P, **prm)
+    A = h2x.H2Matrix(plan, storage="f64")
+    A_lo = h2x.H2Matrix(plan, storage="bf16")
+    B = W.rhs(1500, 3, 132)
+    Bd = torch.from_numpy(B).cuda()
+    runs = {
+        "refine": h2x.block_cg_refine(A, A_lo, Bd, rtol=1e-10, inner_rtol=1e-2, max_outer=8, max_inner=150),
+        "mixed": h2x.block_cg_mixed(A, A_lo, Bd, rtol=1e-10, max_iter=300),
+    }
+    for name, (X, info) in runs.items():
+        X = X.cpu().numpy()
+        rel = np.linalg.norm(B - o.matmul(X), axis=0) / np.linalg.norm(B, axis=0)
+        print(f"{name}: status {info.status}, returned true residuals {rel}, reported {info.col_relres}")
+        assert info.status in (4, 5)
+        assert (rel <= 1.0).all()
+        np.testing.assert_allclose(info.col_relres, rel, rtol=1e-8)
+
+
+# ---- FP64 recovery at the precision workload's full size ----
+
+def test_precision_workload_solves():
+    """The precision workload at full size (cube, n = 262144, k = 64, m = 64).  FP32 storage:
+    residual replacement and restarted refinement both reach an FP64 true residual of 1e-10,
+    measured with the FP64 product (pinned against the oracle by the full-size product test).
+    BF16 storage: the operator's error (1e-2 of the product) times the condition number
+    (lambda_min >= 0.5 from the shift, lambda_max ~ 2e4) is far above 1, so neither method
+    can converge; both say so and return iterates no worse than X0 = 0."""
+    import paper_2509_17257_amd as h2x
+    w = W.PRECISION
+    P = w.points()
+    plan = h2x.Plan(P, **w.params())
+    B = torch.from_numpy(w.rhs()).cuda()
+    A = h2x.H2Matrix(plan, storage="f64")
+
+    def true_rel(X):
+        R = B - h2x.h2_matmul(A, X)
+        return (R.norm(dim=0) / B.norm(dim=0)).cpu().numpy()
+
+    for prec in ("f32", "bf16"):
+        A_lo = h2x.H2Matrix(plan, storage=prec)
+        legs = [("mixed", lambda: h2x.block_cg_mixed(A, A_lo, B, rtol=1e-10, max_iter=3000 if prec == "f32" else 400,
+                                                      graph=True)),
+                ("refine", lambda: h2x.block_cg_refine(A, A_lo, B, rtol=1e-10, inner_rtol=1e-6 if prec == "f32" else 1e-2,
+                                                        max_outer=8, max_inner=2000 if prec == "f32" else 300))]
+        for name, run in legs:
+            print(f"[full] {prec} {name}", flush=True)
+            X, info = run()
+            rel = true_rel(X)
+            print(f"[full] {prec} {name}: status {info.status}, iters {info.iters}, outer {info.outer_iters}, "
+                  f"max true residual {rel.max():.3e}", flush=True)
+            np.testing.assert_allclose(info.col_relres, rel, rtol=1e-6, atol=1e-14)
+            if prec == "f32":
+                assert info.status == 0 and rel.max() <= 1e-10
+            else:
+                assert info.status in (4, 5) and rel.max() <= 1.0
+        del A_lo
+        torch.cuda.empty_cache()

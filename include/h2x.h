@@ -513,6 +513,23 @@ h2x_status h2x_mat_coupling(const h2x_mat *A, double *out, void *hip_stream);
  * valid until the copy has run).  h2x_mat_set_ell refills them from the kernel. */
 h2x_status h2x_mat_set_coupling(h2x_mat *A, const double *in, void *hip_stream);
 
+/* ---- product without a workspace ------------------------------------------- */
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the product of
+ * h2x_matmul, same arguments and semantics, with its scratch memory (x-hat,
+ * y-hat, the tree-ordered copy of X) in a static device array of
+ * H2X_NOALLOC_MAX_BYTES that the library holds on every GPU it runs on until
+ * the process ends.  Nothing is allocated by the call.  The scratch needed is
+ * h2x_matmul_workspace_bytes(A, m); a larger need returns H2X_ENOMEM (use
+ * h2x_matmul with a workspace).  The array is shared by every call on the same
+ * GPU and keeps the last call's contents (the product reads none of it before
+ * writing it): calls that overlap on one GPU (several streams or threads) race
+ * and must be serialized by the caller.  The calling thread's current device
+ * must be the device of A and of hip_stream.  Async. */
+#define H2X_NOALLOC_MAX_BYTES ((size_t)128 << 20)
+h2x_status h2x_matmul_noalloc(const h2x_mat *A, int64_t m, double alpha, const double *X, int64_t ldx, double beta,
+                              double *Y, int64_t ldy, int32_t flags, void *hip_stream);
+
 /* ---- misc ------------------------------------------------------------------ */
 
 const char *h2x_last_error(void);

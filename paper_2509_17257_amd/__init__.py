@@ -14,7 +14,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
-__all__ = ["Plan", "H2Matrix", "Batch", "h2_matmul", "h2_matmul_adjoint", "h2_grad", "block_cg_solve",
+__all__ = ["Plan", "H2Matrix", "Batch", "h2_matmul", "h2_matmul_noalloc", "h2_matmul_adjoint", "h2_grad", "block_cg_solve",
            "block_cg_refine", "block_cg_mixed", "batch_matmul", "batch_block_cg_solve", "library_path", "load_library", "F64", "F32",
            "BF16", "TREE_ORDER"]
 
@@ -112,6 +112,7 @@ def load_library():
         "h2x_matmul_workspace_bytes": (SZ, [P, I64]),
         "h2x_matmul": (C.c_int, [P, I64, D, P, I64, D, P, I64, I32, P, SZ, P]),
         "h2x_matmul_timed": (C.c_int, [P, I64, D, P, I64, D, P, I64, I32, P, SZ, P, P]),
+        "h2x_matmul_noalloc": (C.c_int, [P, I64, D, P, I64, D, P, I64, I32, P]),
         "h2x_timer_create": (C.c_int, [I32, C.POINTER(P)]),
         "h2x_timer_destroy": (None, [P]),
         "h2x_matmul_marked": (C.c_int, [P, I64, D, P, I64, D, P, I64, I32, P, SZ, P, P, I32]),
@@ -433,6 +434,28 @@ def _rowmajor(T, n, what):
     import torch
     if T.dtype != torch.float64 or T.device.type != "cuda" or T.dim() != 2 or T.stride(1) != 1 or T.shape[0] != n:
         raise ValueError(f"{what} must be a row-major (n, m) float64 CUDA tensor")
+
+
+NOALLOC_MAX_BYTES = 128 << 20  # H2X_NOALLOC_MAX_BYTES
+
+
+def h2_matmul_noalloc(A: H2Matrix, X, *, alpha=1.0, beta=0.0, out=None, tree_order=False):
+    """Y <- beta Y + alpha A X through h2x_matmul_noalloc: the library's static scratch array
+    instead of a workspace (the call allocates nothing on the device; ``out`` must be given
+    when the caller cannot allocate).  X, out: (n, m) row-major float64 CUDA tensors."""
+    import torch
+    _rowmajor(X, A.n, "X")
+    n, m = X.shape
+    if out is None:
+        if beta != 0.0:
+            raise ValueError("beta != 0 needs out")
+        out = torch.empty((n, m), dtype=torch.float64, device=X.device)
+    _rowmajor(out, n, "out")
+    _check(load_library().h2x_matmul_noalloc(A._h, m, float(alpha), C.c_void_p(X.data_ptr()), X.stride(0),
+                                             float(beta), C.c_void_p(out.data_ptr()), out.stride(0),
+                                             TREE_ORDER if tree_order else 0, _stream(torch, X.device)),
+           "h2x_matmul_noalloc")
+    return out
 
 
 def h2_matmul_adjoint(A: H2Matrix, X, *, alpha=1.0, beta=0.0, out=None):

@@ -18,7 +18,7 @@ LIB = os.path.join(HERE, "libh2x.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 HIPCC = os.path.join(ROCM, "bin", "hipcc")
 
-HIP_SOURCES = ["fill.hip", "matmul.hip", "cg.hip", "bcg.hip", "gmres.hip", "chunk.hip", "grad.hip", "tune.hip", "abi.hip"]
+HIP_SOURCES = ["fill.hip", "matmul.hip", "cg.hip", "bcg.hip", "gmres.hip", "chunk.hip", "grad.hip", "tune.hip", "abi.hip", "noalloc.hip"]
 CXX_SOURCES = ["planner.cpp"]
 
 HIP_FLAGS = [

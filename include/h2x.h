@@ -389,14 +389,19 @@ h2x_status h2x_block_gmres_chunked(const h2x_mat *A, const h2x_gmres_params *prm
  * basis term joins it); the product then adds the two terms to Y in two steps. */
 typedef struct {
     int32_t nj_transfer, nj_coupling, np_leaf;
-    int32_t overlap;   /* near field on a second stream: 0 (built-in rule) and 2 off; on
-                          with its grid capped at 256 (1), 128 (3) or 512 (4) work-groups */
+    int32_t overlap;   /* near field beside the transfer passes: 0 (built-in rule) and 2
+                          off; on a second stream with its grid capped at 256 (1), 128 (3)
+                          or 512 (4) work-groups; 5 in shares inside the launches of the
+                          transfer levels (leaf_kind 3, k = 64)                          */
     int32_t fuse_up;   /* forward leaf and upward pass in one launch: 1 on; 0 (built-in
                           rule) and 2 level by level                                   */
     int32_t leaf_kind; /* leaf stage (32 * np_leaf columns per wave): 0 built-in rule
-                          (= 1); 1 a work-group per leaf, each wave a 64-row tile of its
-                          share of the terms; 2 a wave per 32-row band of a leaf, every
-                          term in turn                                                  */
+                          (3 where its table of near rows fits in LDS and the operator
+                          is real, else 1); 1 a work-group per leaf, each wave a 64-row
+                          tile of its share of the terms; 2 a wave per 32-row band of a
+                          leaf, every term in turn; 3 a work-group per leaf, the near
+                          blocks and the basis as one contraction in rounds of 16 rows,
+                          16-row tiles of the leaf                                      */
     int32_t split;     /* coupling rows in two parts, the deep part (rows whose lists are
                           complete once the upward pass has reached a split depth) on a
                           second stream beside the upper transfer levels, the coupling of
@@ -422,8 +427,8 @@ h2x_status h2x_mat_autotune(h2x_mat *A, int64_t m, void *dev_ws, size_t ws_bytes
  * ceil(m / 16), counts above 64 sharing one): a choice kept from an earlier autotune
  * run, or a fixed shape, without timing.  Set: the shape fields of cfg are used
  * (ms_default / ms_tuned ignored); all zero restores the built-in rule; ranges
- * nj_transfer, nj_coupling 0..4, np_leaf 0..2, overlap 0..4, fuse_up 0..2, leaf_kind
- * 0..2, split 0..3, else H2X_EINVAL.  Get: ms_default = ms_tuned = 0.  Host only; must
+ * nj_transfer, nj_coupling 0..4, np_leaf 0..2, overlap 0..5, fuse_up 0..2, leaf_kind
+ * 0..3, split 0..3, else H2X_EINVAL.  Get: ms_default = ms_tuned = 0.  Host only; must
  * not run concurrently with products on the same operator. */
 h2x_status h2x_mat_set_tune(h2x_mat *A, int64_t m, const h2x_tune_info *cfg);
 h2x_status h2x_mat_get_tune(const h2x_mat *A, int64_t m, h2x_tune_info *cfg);

@@ -434,5 +434,101 @@ __global__ __launch_bounds__(256) void k_grad_N_mfma(int64_t m, const int32_t *_
     if (tid == 0) part[q] = tot;
 }
 
+// ---- d ell without the per-block tiles (rank 64) ----
+//
+// The coupling term of d ell is sum_t <dyhat_t, sum_{(t,s) in C_t} G_b xhat_s> with
+// G_b[nu][mu] = dg/dell(xi_t,nu, xi_s,mu): the coupling product with G_b in place of S_b.
+// One work-group per row cluster and slab of 16 NJ columns, as in the coupling kernel; each
+// lane forms its operand entries of G_b (row 16 w + l % 16, columns 4 k + l / 16) from the
+// interpolation nodes (the row's node in registers, the column cluster's nodes staged in
+// LDS with x-hat_s, double-buffered), so neither S_b nor a k x k tile of D is stored.  The
+// work-group's partial sum of the dot product with dyhat_t goes to part[slot] (a fixed
+// order); the sums are added in a fixed order afterwards.
+template <int NJ>
+__global__ __launch_bounds__(256) void k_dell_coupling(int64_t m, int32_t C, int32_t rows_per_xcd,
+                                                       const int32_t *__restrict__ order,
+                                                       const int64_t *__restrict__ adm_ptr,
+                                                       const int32_t *__restrict__ adm_col,
+                                                       const double *__restrict__ nodes, double inv_ell,
+                                                       double inv_ell2, const double *__restrict__ xh,
+                                                       const double *__restrict__ dh, int64_t ldh,
+                                                       double *__restrict__ part) {
+    constexpr int MC = 16 * NJ, LDX = MC + 1;
+    __shared__ double xs[2][64 * LDX];
+    __shared__ double ns[2][64 * 3];
+    const int nslab = (int)((m + MC - 1) / MC), qx = blockIdx.x >> 3;
+    const int slot = (blockIdx.x & 7) * rows_per_xcd + qx / nslab;
+    double mine = 0.0;
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, lr = lane & 15, lq = lane >> 4;
+    if (slot < C) {
+        const int32_t t = order[slot];
+        const int64_t j0 = (int64_t)(qx % nslab) * MC;
+        const int mc = (int)min<int64_t>(MC, m - j0);
+        const int64_t b0 = adm_ptr[t], b1 = adm_ptr[t + 1];
+        // the lane's row node xi_t,nu, nu = 16 w + l % 16
+        const double *nt = nodes + ((int64_t)t * 64 + 16 * w + lr) * 3;
+        const double px = nt[0], py = nt[1], pz = nt[2];
+        dbl4 acc[NJ];
+#pragma unroll
+        for (int J = 0; J < NJ; ++J) acc[J] = dbl4{0.0, 0.0, 0.0, 0.0};
+        if (b1 > b0) {
+            constexpr int XPT = (64 * MC) / 256;
+            double xv[XPT], nv;
+            auto load = [&](int32_t s) {
+                const double *src = xh + (int64_t)s * 64 * ldh + j0;
+#pragma unroll
+                for (int u = 0; u < XPT; ++u) {
+                    const int e = tid + 256 * u, r = e / MC, c = e % MC;
+                    xv[u] = src[(int64_t)r * ldh + (c < mc ? c : 0)];
+                }
+                nv = nodes[(int64_t)s * 64 * 3 + min(tid, 191)];
+            };
+            auto store = [&](int buf) {
+#pragma unroll
+                for (int u = 0; u < XPT; ++u) {
+                    const int e = tid + 256 * u, r = e / MC, c = e % MC;
+                    xs[buf][r * LDX + c] = c < mc ? xv[u] : 0.0;
+                }
+                if (tid < 192) ns[buf][tid] = nv;
+            };
+            auto multiply = [&](int buf) {
+                const double *xb = xs[buf], *nb = ns[buf];
+#pragma unroll
+                for (int kk = 0; kk < 16; ++kk) {
+                    const int mu = 4 * kk + lq;
+                    const double dx = px - nb[3 * mu], dy = py - nb[3 * mu + 1], dz = pz - nb[3 * mu + 2];
+                    const double r = sqrt(dx * dx + dy * dy + dz * dz);
+                    const double a = (r * inv_ell2) * exp(-r * inv_ell);
+#pragma unroll
+                    for (int J = 0; J < NJ; ++J)
+                        acc[J] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, xb[mu * LDX + 16 * J + lr], acc[J], 0, 0, 0);
+                }
+            };
+            load(adm_col[b0]);
+            store(0);
+            __syncthreads();
+            for (int64_t b = b0; b + 1 < b1; ++b) {
+                const int buf = (int)((b - b0) & 1);
+                load(adm_col[b + 1]);
+                multiply(buf);
+                store(buf ^ 1);
+                __syncthreads();
+            }
+            multiply((int)((b1 - 1 - b0) & 1));
+        }
+        // <dyhat_t, y'_t> over the slab: lane l, register r -> row 16 w + l / 16 + 4 r, column 16 J + l % 16
+#pragma unroll
+        for (int J = 0; J < NJ; ++J) {
+            const int col = 16 * J + lr;
+            if (col < mc)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    mine += acc[J][r] * dh[((int64_t)t * 64 + 16 * w + lq + 4 * r) * ldh + j0 + col];
+        }
+    }
+    const double tot = block_sum(mine);
+    if (tid == 0) part[blockIdx.x] = tot;
+}
+
 }  // namespace adj
 }  // namespace h2x

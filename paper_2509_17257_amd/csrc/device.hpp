@@ -26,7 +26,8 @@ struct TuneCfg {
     int8_t overlap = 0;      // near field on a second stream during the transfer passes and
                              // the coupling: 0 (built-in rule) and 2 off; on with a grid
                              // of 256 (1), 128 (3) or 512 (4) work-groups
-    int8_t leaf_kind = 0;    // leaf stage: 0 built-in rule (= 1), 1 wave-per-term tiles, 2 rows split over waves
+    int8_t leaf_kind = 0;    // leaf stage: 0 built-in rule (3 where it applies, else 1), 1 wave-per-term
+                             // tiles, 2 rows split over waves, 3 one contraction per leaf
     int8_t split = 0;        // coupling of the deep rows on the second stream beside the upper
                              // transfer levels: 0 built-in rule, 1 on (leaving room on every
                              // CU for a transfer work-group), 2 off, 3 on without the reserve
@@ -37,7 +38,7 @@ inline int tune_bucket(int64_t m) { return (int)std::min<int64_t>(kTuneBuckets -
 // Flat device arrays of one operator, all inside the caller's workspace.
 struct DevMat {
     int64_t n = 0;
-    int32_t C = 0, L = 0, k = 0, p = 0, depth_max = 0, max_leaf = 0;
+    int32_t C = 0, L = 0, k = 0, p = 0, depth_max = 0, max_leaf = 0, max_near_rows = 0;
     int64_t n_adm = 0, n_near = 0, near_entries = 0;
     h2x_prec storage = H2X_F64;
     int swz = 0;     // coupling-matrix layout (see s_index)
@@ -57,6 +58,7 @@ struct DevMat {
     int32_t *adm_col = nullptr;  // n_adm
     int32_t *adm_row = nullptr;  // n_adm (row cluster of each block)
     int32_t *cpl_order = nullptr;  // C, launch order of the coupling rows
+    int32_t *leaf_order = nullptr; // L, launch order of the leaves (one contraction per leaf)
     int32_t *cpl_deep = nullptr, *cpl_shallow = nullptr;  // the same rows in two parts
     int32_t n_deep = 0, n_shallow = 0, split_depth = 0;   // (split_depth 0: no split)
     int64_t *near_ptr = nullptr; // L + 1

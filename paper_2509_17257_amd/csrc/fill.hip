@@ -250,6 +250,7 @@ size_t mat_layout(const Plan &P, h2x_prec storage, DevMat *dm, char *base) {
     const int64_t n = P.n, na = (int64_t)P.adm_col.size(), nn = (int64_t)P.near_col.size();
     DevMat d;
     d.n = n; d.C = C; d.L = L; d.k = k; d.p = P.p; d.depth_max = P.depth_max; d.max_leaf = P.max_leaf;
+    d.max_near_rows = P.max_near_rows;
     d.n_adm = na; d.n_near = nn; d.near_entries = P.near_entries; d.storage = storage;
     d.kernel = P.prm.kernel; d.ell = P.prm.ell; d.shift = P.prm.shift; d.plan = &P;
     d.swz = k != 64 ? 0 : (storage == H2X_F64 ? 1 : (storage == H2X_F32 ? 2 : 3));
@@ -271,6 +272,7 @@ size_t mat_layout(const Plan &P, h2x_prec storage, DevMat *dm, char *base) {
     d.adm_col = carve<int32_t>(cur, base, na + 1);
     d.adm_row = carve<int32_t>(cur, base, na + 1);
     d.cpl_order = carve<int32_t>(cur, base, C);
+    d.leaf_order = carve<int32_t>(cur, base, L);
     d.split_depth = P.split_depth;
     d.n_deep = (int32_t)P.cpl_deep.size();
     d.n_shallow = (int32_t)P.cpl_shallow.size();

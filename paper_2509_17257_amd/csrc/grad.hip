@@ -18,6 +18,7 @@
 
 #include "adjoint_mfma.hpp"
 #include "device.hpp"
+#include "leaf_cat.hpp"
 #include "types.hpp"
 
 namespace h2x {
@@ -321,6 +322,28 @@ struct GradWs {
     size_t bytes;
 };
 
+// d ell alone on the rank-64 matrix-core path: the coupling term as the coupling product with
+// dg/dell in place of S (one partial sum per work-group), the near-field term as the leaf
+// stage's near contraction with dg/dell in place of N
+struct DellShape {
+    int nj, np;
+    int64_t cpl_groups, near_slots;
+    size_t near_lds;
+    bool ok;
+};
+
+DellShape dell_shape(const DevMat &dm, int64_t m) {
+    DellShape d{};
+    d.nj = (int)std::min<int64_t>(4, (m + 15) / 16);
+    d.np = 1;  // 32 columns per work-group (the register-formed dg/dell leaves no room for 64)
+    d.cpl_groups = (int64_t)8 * ((dm.C + 7) / 8) * ((m + 16 * d.nj - 1) / (16 * d.nj));
+    d.near_slots = (int64_t)8 * ((dm.L + 7) / 8) * ((m + 32 * d.np - 1) / (32 * d.np));
+    d.near_lds = sizeof(int32_t) * (size_t)std::max(1, dm.max_near_rows);
+    d.ok = dm.mc && dm.k == 64 && !dm.cplx && dm.cpl_order &&
+           d.near_lds + sizeof(double) * (64 * (32 * d.np + 1) + 256) + 64 <= 65536;
+    return d;
+}
+
 GradWs grad_layout(const DevMat &dm, int64_t m, char *base) {
     GradWs w{};
     size_t off = 0;
@@ -336,8 +359,10 @@ GradWs grad_layout(const DevMat &dm, int64_t m, char *base) {
     w.Xt = carve(nm);
     w.dYt = carve(nm);
     w.xt_ws = carve(nm);
-    w.part = carve((size_t)(dm.n_adm + dm.n_near + 1) * sizeof(double));
-    w.part2 = carve((size_t)((dm.n_adm + dm.n_near) / kSumChunk + 2) * sizeof(double));
+    const DellShape ds = dell_shape(dm, m);
+    const int64_t np = std::max<int64_t>(dm.n_adm + dm.n_near, ds.cpl_groups + ds.near_slots) + 1;
+    w.part = carve((size_t)np * sizeof(double));
+    w.part2 = carve((size_t)(np / kSumChunk + 2) * sizeof(double));
     w.bytes = align_up(off);
     return w;
 }
@@ -412,6 +437,64 @@ __global__ void k_fill0(int64_t count, double *__restrict__ p) {
     if (e < count) p[e] = 0.0;
 }
 
+__global__ void k_scale1(double *__restrict__ v, double s) { v[0] *= s; }
+
+// d ell alone: the fused kernels above, then one fixed-order sum of their partial sums
+hipError_t run_dell_fused(const DevMat &dm, const DellShape &ds, int64_t m, const double *X, int64_t ldx,
+                          const double *dY, int64_t lddy, double *dell, double scale, int cpl, int nr, GradWs &w,
+                          hipStream_t st) {
+    const int64_t ldh = even(m);
+    hipError_t e = hipSuccess;
+    double *pc = w.part, *pn = w.part + ds.cpl_groups;
+    const int64_t cnt = ds.cpl_groups + ds.near_slots;
+    if (cpl) {
+        e = run_forward_transform(dm, m, X, ldx, false, w.xh, ldh, w.xt_ws, st);
+        if (e == hipSuccess) e = run_forward_transform(dm, m, dY, lddy, false, w.dh, ldh, w.xt_ws, st);
+        if (e != hipSuccess) return e;
+        const int32_t rpx = (dm.C + 7) / 8;
+        const double ie = 1.0 / dm.ell;
+        auto go = [&](auto NJc) {
+            constexpr int NJ = decltype(NJc)::value;
+            hipLaunchKernelGGL(adj::k_dell_coupling<NJ>, dim3((unsigned)ds.cpl_groups), dim3(256), 0, st, m, dm.C, rpx,
+                               dm.cpl_order, dm.adm_ptr, dm.adm_col, dm.nodes, ie, ie * ie, (const double *)w.xh,
+                               (const double *)w.dh, ldh, pc);
+        };
+        switch (ds.nj) {
+            case 1: go(std::integral_constant<int, 1>{}); break;
+            case 2: go(std::integral_constant<int, 2>{}); break;
+            case 3: go(std::integral_constant<int, 3>{}); break;
+            default: go(std::integral_constant<int, 4>{}); break;
+        }
+    } else {
+        hipLaunchKernelGGL(k_fill0, dim3((unsigned)((ds.cpl_groups + 255) / 256)), dim3(256), 0, st, ds.cpl_groups, pc);
+    }
+    if (nr) {
+        const int64_t cg = dm.n * ldh;
+        hipLaunchKernelGGL(k_gather_even, dim3((unsigned)((cg + 255) / 256)), dim3(256), 0, st, dm.n, m, dm.perm, X,
+                           ldx, w.Xt, ldh);
+        hipLaunchKernelGGL(k_gather_even, dim3((unsigned)((cg + 255) / 256)), dim3(256), 0, st, dm.n, m, dm.perm, dY,
+                           lddy, w.dYt, ldh);
+        const mfma::LeafCatArgs a{dm.k, m, dm.L, dm.leaf_order, dm.leaves, dm.first, dm.size, dm.perm, (const double *)dm.Vt,
+                                  dm.vt_off, nullptr, 0, dm.near_ptr, dm.near_col, dm.near_off, (const double *)dm.N,
+                                  w.Xt, ldh, 1.0, 0.0, nullptr, 0, 1, 0, 1, Skip{}};
+        const double ie = 1.0 / dm.ell;
+        const mfma::DellArgs d{dm.pts, ie, ie * ie, w.dYt, ldh};
+        hipLaunchKernelGGL(mfma::k_dell_near<1>, dim3((unsigned)ds.near_slots), dim3(256), ds.near_lds, st, a, d, pn);
+    } else {
+        hipLaunchKernelGGL(k_fill0, dim3((unsigned)((ds.near_slots + 255) / 256)), dim3(256), 0, st, ds.near_slots, pn);
+    }
+    const int64_t ng = (cnt + kSumChunk - 1) / kSumChunk;
+    if (ng > 1) {
+        hipLaunchKernelGGL(k_sum_fixed, dim3((unsigned)ng), dim3(256), 0, st, cnt, kSumChunk, (const double *)w.part,
+                           w.part2);
+        hipLaunchKernelGGL(k_sum_fixed, dim3(1), dim3(256), 0, st, ng, ng, (const double *)w.part2, dell);
+    } else {
+        hipLaunchKernelGGL(k_sum_fixed, dim3(1), dim3(256), 0, st, cnt, cnt + 1, (const double *)w.part, dell);
+    }
+    if (scale != 1.0) hipLaunchKernelGGL(k_scale1, dim3(1), dim3(1), 0, st, dell, scale);
+    return hipGetLastError();
+}
+
 hipError_t run_grad(const DevMat &dm, int64_t m, const double *X, int64_t ldx, const double *dY, int64_t lddy,
                     double *dS, double *dN, double *dell, double scale, int32_t dell_terms, char *ws,
                     hipStream_t st) {
@@ -419,6 +502,10 @@ hipError_t run_grad(const DevMat &dm, int64_t m, const double *X, int64_t ldx, c
     const int64_t ldh = even(m);
     hipError_t e = hipSuccess;
     const int cpl = dell && (dell_terms & H2X_DELL_COUPLING) ? 1 : 0, nr = dell && (dell_terms & H2X_DELL_NEAR) ? 1 : 0;
+    // d ell alone (no block gradients requested) on the rank-64 exponential operator
+    const DellShape ds = dell_shape(dm, m);
+    if (dell && !dS && !dN && ds.ok && dm.kernel == H2X_KERNEL_EXP && dm.n_adm + dm.n_near > 0)
+        return run_dell_fused(dm, ds, m, X, ldx, dY, lddy, dell, scale, cpl, nr, w, st);
     // the partial sums of dell's terms that are not wanted are zero
     if (dell && !cpl && dm.n_adm > 0)
         hipLaunchKernelGGL(k_fill0, dim3((unsigned)((dm.n_adm + 255) / 256)), dim3(256), 0, st, dm.n_adm, w.part);

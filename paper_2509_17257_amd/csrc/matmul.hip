@@ -16,6 +16,7 @@
 
 #include "device.hpp"
 #include "coupling_lp.hpp"
+#include "leaf_cat.hpp"
 #include "leaf_lp.hpp"
 #include "leaf_rows.hpp"
 #include "matmul_mfma.hpp"
@@ -331,9 +332,29 @@ void matmul_mfma_f64(const DevMat &dm, const TuneCfg &cfg, int64_t m, double alp
                                dm.size, dm.perm, V, Xt, ldxt, 1, xh, ldh, sk);
     };
     const unsigned gl = (unsigned)((m + 32 * NP - 1) / (32 * NP));
-    // leaf stage: a 64-row tile per wave and term (built-in) or the rows split over the waves
-    const bool rows = cfg.leaf_kind == 2;
+    // leaf stage: one contraction per leaf (built-in where its LDS table of near rows fits),
+    // a 64-row tile per wave and term, or the rows split over the waves
+    const size_t cat_lds = sizeof(int32_t) * (size_t)std::max(1, dm.max_near_rows);
+    const bool cat_ok = !dm.cplx && cat_lds + sizeof(double) * 64 * (32 * NP + 1) + 64 <= 65536;
+    const int kind = cfg.leaf_kind == 0 ? (cat_ok ? 3 : 1) : (cfg.leaf_kind == 3 && !cat_ok ? 1 : cfg.leaf_kind);
+    const bool rows = kind == 2;
+    const int64_t cat_slots = (int64_t)8 * ((dm.L + 7) / 8) * gl;
+    auto cat_args = [&](double b, int basis, int near) {
+        return mfma::LeafCatArgs{dm.k, m, dm.L, dm.leaf_order, dm.leaves, dm.first, dm.size, dm.perm, (const double *)dm.Vt,
+                                 dm.vt_off, yh, ldh, dm.near_ptr, dm.near_col, dm.near_off, (const double *)dm.N, Xt,
+                                 ldxt, alpha, b, Y, ldy, to, basis, near, sk};
+    };
     auto leaf = [&](hipStream_t s, double b, int basis, int near, unsigned cap) {
+        if (kind == 3) {
+            const unsigned gx = (unsigned)(cap ? std::min<int64_t>(cat_slots, cap) : cat_slots);
+            if (NP == 2)
+                hipLaunchKernelGGL(mfma::k_leaf_cat<2>, dim3(gx), dim3(256), cat_lds, s, cat_args(b, basis, near),
+                                   (int64_t)0, cat_slots);
+            else
+                hipLaunchKernelGGL(mfma::k_leaf_cat<1>, dim3(gx), dim3(256), cat_lds, s, cat_args(b, basis, near),
+                                   (int64_t)0, cat_slots);
+            return;
+        }
         if (rows) {
             const dim3 grid(8 * ((dm.L + 7) / 8) * gl, 2);
             if (NP == 2)
@@ -365,7 +386,7 @@ void matmul_mfma_f64(const DevMat &dm, const TuneCfg &cfg, int64_t m, double alp
     // coupling run here (it needs only X); the basis term joins it at the end.  Its
     // grid is capped so that it leaves room on the chip for the transfer chain:
     // overlap 1: 256 work-groups, 3: 128, 4: 512; 0 (the built-in rule) and 2: off
-    const bool ov = dm.side && dm.n_near > 0 && (cfg.overlap == 1 || cfg.overlap >= 3);
+    const bool ov = dm.side && dm.n_near > 0 && (cfg.overlap == 1 || cfg.overlap == 3 || cfg.overlap == 4);
     if (ov) {
         const unsigned cap = cfg.overlap == 3 ? 128u : (cfg.overlap == 4 ? 512u : 256u);
         (void)hipEventRecord(dm.ev_fork, st);
@@ -378,11 +399,53 @@ void matmul_mfma_f64(const DevMat &dm, const TuneCfg &cfg, int64_t m, double alp
     // the concurrent near field or the fused upward pass)
     const bool split = (cfg.split == 1 || cfg.split == 3) && dm.split_depth > 0 && dm.side && !ov && !ev &&
                        cfg.fuse_up != 1;
+    // near field in shares beside the transfer levels (the leaf form with one contraction per
+    // leaf, rank 64): each level launch also runs a share of the near-field slots, so that
+    // the levels' chain of dependent launches overlaps streaming work; the basis term
+    // follows the downward pass.  overlap 5 only (measured slower: a leaf's work-group runs
+    // for tens of microseconds, so every level launch lasts as long as its slowest leaf)
+    int n_levels = 0;
+    for (int d = dm.depth_max - 1; d >= P.adm_depth; --d) n_levels += P.lvl_inner_ptr[d + 1] > P.lvl_inner_ptr[d];
+    for (int d = std::max(1, P.adm_depth + 1); d <= dm.depth_max; ++d) n_levels += P.lvl_ptr[d + 1] > P.lvl_ptr[d];
+    const size_t lvl_lds = std::max(sizeof(double) * 2 * 64 * (16 * NJ + 1),
+                                    sizeof(double) * 64 * (32 * NP + 1) + cat_lds);
+    const bool inter = kind == 3 && t64 && dm.n_near > 0 && n_levels > 0 && !ov && !split && cfg.fuse_up != 1 &&
+                       cfg.overlap == 5 && lvl_lds <= 65536;
+    const int64_t share = n_levels > 0 ? (cat_slots + n_levels - 1) / n_levels : 0;
+    int64_t next_slot = 0;
+    auto level_near = [&](bool up, int32_t b, int32_t e) {
+        const int64_t s0 = next_slot, s1 = std::min(cat_slots, next_slot + share);
+        next_slot = s1;
+        const int64_t items = (int64_t)(e - b) * gy;
+        const int lead = (int)(((s0 - items) % 8 + 8) % 8);
+        const dim3 grid((unsigned)(items + lead + (s1 - s0)));
+        const mfma::LeafCatArgs a = cat_args(beta, 0, 1);
+        const int32_t *list = up ? dm.lvl_inner + b : dm.lvl_all + b;
+        const int32_t *aux = up ? dm.up_son + 2 * b : dm.dn_par + b;
+        double *hat = up ? xh : yh;
+        if (up) {
+            if (NP == 2)
+                hipLaunchKernelGGL((mfma::k_level_near<NJ, 2, 1>), grid, dim3(256), lvl_lds, st, items, (int)gy, m,
+                                   list, aux, E, hat, ldh, sk, a, s0, lead);
+            else
+                hipLaunchKernelGGL((mfma::k_level_near<NJ, 1, 1>), grid, dim3(256), lvl_lds, st, items, (int)gy, m,
+                                   list, aux, E, hat, ldh, sk, a, s0, lead);
+        } else {
+            if (NP == 2)
+                hipLaunchKernelGGL((mfma::k_level_near<NJ, 2, 0>), grid, dim3(256), lvl_lds, st, items, (int)gy, m,
+                                   list, aux, E, hat, ldh, sk, a, s0, lead);
+            else
+                hipLaunchKernelGGL((mfma::k_level_near<NJ, 1, 0>), grid, dim3(256), lvl_lds, st, items, (int)gy, m,
+                                   list, aux, E, hat, ldh, sk, a, s0, lead);
+        }
+    };
     auto up_levels = [&](int dhi, int dlo) {  // upward levels dhi down to dlo
         for (int d = dhi; d >= dlo; --d) {
             const int32_t b = P.lvl_inner_ptr[d], e = P.lvl_inner_ptr[d + 1];
             if (e <= b) continue;
-            if (t64)
+            if (inter)
+                level_near(true, b, e);
+            else if (t64)
                 hipLaunchKernelGGL(mfma::k_up64<NJ>, dim3(e - b, gy), dim3(256), 0, st, m, dm.lvl_inner + b,
                                    dm.up_son + 2 * b, E, xh, ldh, sk);
             else
@@ -394,7 +457,9 @@ void matmul_mfma_f64(const DevMat &dm, const TuneCfg &cfg, int64_t m, double alp
         for (int d = dlo; d <= dhi; ++d) {
             const int32_t b = P.lvl_ptr[d], e = P.lvl_ptr[d + 1];
             if (e <= b) continue;
-            if (t64)
+            if (inter)
+                level_near(false, b, e);
+            else if (t64)
                 hipLaunchKernelGGL(mfma::k_down64<NJ>, dim3(e - b, gy), dim3(256), 0, st, m, dm.lvl_all + b,
                                    dm.dn_par + b, E, yh, ldh, sk);
             else
@@ -460,6 +525,8 @@ void matmul_mfma_f64(const DevMat &dm, const TuneCfg &cfg, int64_t m, double alp
     if (ov) {
         (void)hipStreamWaitEvent(st, dm.ev_join, 0);
         leaf(st, 1.0, 1, 0, 0);
+    } else if (inter) {
+        leaf(st, 1.0, 1, 0, 0);  // the near field is in Y already (beta applied there)
     } else {
         leaf(st, beta, 1, 1, 0);
     }

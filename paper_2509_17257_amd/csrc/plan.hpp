@@ -51,6 +51,7 @@ struct Plan {
     std::vector<int64_t> vt_off;    // L
     int64_t vt_entries = 0;
     int32_t max_leaf = 0;           // largest leaf size
+    int32_t max_near_rows = 0;      // largest sum of |s| over the near blocks of one leaf
 
     // column lists for the adjoint: admissible blocks by column cluster (entries are
     // indices into the row-ordered arrays), near-field blocks by column leaf
@@ -62,6 +63,10 @@ struct Plan {
     // launch order of the row clusters in the coupling stage: the rows are cut
     // into 8 contiguous eighths (one per XCD), longest list first within each
     std::vector<int32_t> cpl_order; // C
+    // launch order of the leaves in the leaf stage (one contraction per leaf): 8 contiguous
+    // eighths (one per XCD), the leaves with the most work first within each, so that the
+    // longest leaves do not start last
+    std::vector<int32_t> leaf_order; // L
     // the same rows in two parts, so that the coupling of the deep part can run beside the
     // upper transfer levels: "deep" rows lie at depth >= split_depth and every inner
     // cluster of their lists too (their x-hat is complete once the upward pass has done

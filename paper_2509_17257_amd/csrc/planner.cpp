@@ -85,6 +85,33 @@ void coupling_order(Plan &P) {
     }
 }
 
+// leaf order of the leaf stage: the work of a leaf is its rounds of 16 contraction rows
+// (near rows and the k basis rows) per wave, over 4 waves for leaves of up to 32 points and
+// 2 waves per 32-row group above, for each 64-row chunk of the leaf
+void leaf_order(Plan &P) {
+    const int32_t L = (int32_t)P.leaves.size(), lpx = (L + 7) / 8;
+    std::vector<int64_t> work(L);
+    for (int32_t l = 0; l < L; ++l) {
+        int64_t rows = 0;
+        for (int64_t q = P.near_ptr[l]; q < P.near_ptr[l + 1]; ++q) rows += P.size[P.near_col[q]];
+        const int32_t nt = P.size[P.leaves[l]];
+        int64_t w = 0;
+        for (int32_t i0 = 0; i0 < nt; i0 += 64) {
+            const int32_t ntile = (std::min(64, nt - i0) + 15) / 16;
+            const int64_t rounds = (rows + 15) / 16 + (P.k + 15) / 16;
+            w += (rounds + (ntile > 2 ? 1 : 3)) / (ntile > 2 ? 2 : 4);
+        }
+        work[l] = w;
+    }
+    P.leaf_order.resize(L);
+    for (int32_t l = 0; l < L; ++l) P.leaf_order[l] = l;
+    for (int32_t x = 0; x < 8; ++x) {
+        const int32_t lo = std::min(L, x * lpx), hi = std::min(L, (x + 1) * lpx);
+        std::stable_sort(P.leaf_order.begin() + lo, P.leaf_order.begin() + hi,
+                         [&](int32_t a, int32_t b) { return work[a] > work[b]; });
+    }
+}
+
 }  // namespace
 
 Plan *build_plan(const double *pts, int64_t n, const h2x_params &prm, std::string &err) {
@@ -279,15 +306,19 @@ Plan *build_plan(const double *pts, int64_t n, const h2x_params &prm, std::strin
         const int64_t nt2 = P->size[t] + (P->size[t] & 1);
         P->vt_off[l] = voff;
         voff += (int64_t)P->k * nt2;
+        int32_t rows = 0;
         for (int64_t q = P->near_ptr[l]; q < P->near_ptr[l + 1]; ++q) {
             P->near_off_t[q] = off;
             off += nt2 * P->size[P->near_col[q]];
+            rows += P->size[P->near_col[q]];
         }
+        P->max_near_rows = std::max(P->max_near_rows, rows);
     }
     P->near_entries_t = off;
     P->vt_entries = voff;
 
     coupling_order(*P);
+    leaf_order(*P);
     P->sys_prm.assign(1, prm);
     P->sys_row = {0, n};
     P->sys_C = {0, (int64_t)C};
@@ -317,6 +348,7 @@ Plan *merge_plans(const std::vector<const Plan *> &parts, std::string &err) {
         P->depth_max = std::max(P->depth_max, q->depth_max);
         P->adm_depth = std::min(P->adm_depth, q->adm_depth);
         P->max_leaf = std::max(P->max_leaf, q->max_leaf);
+        P->max_near_rows = std::max(P->max_near_rows, q->max_near_rows);
     }
     P->sys_row.push_back(0);
     P->sys_C.push_back(0);
@@ -404,6 +436,7 @@ Plan *merge_plans(const std::vector<const Plan *> &parts, std::string &err) {
         P->lvl_inner_ptr[d + 1] = (int32_t)P->lvl_inner.size();
     }
     coupling_order(*P);
+    leaf_order(*P);
     return P;
 }
 

@@ -294,7 +294,7 @@ __global__ __launch_bounds__(256) void k_fwd_up(int k, int64_t m, int32_t L, con
     }
 }
 
-__global__ void k_zero_i32(int64_t count, int32_t *__restrict__ p) {
+static __global__ void k_zero_i32(int64_t count, int32_t *__restrict__ p) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e < count) p[e] = 0;
 }
@@ -335,14 +335,14 @@ __global__ __launch_bounds__(256) void k_down(int k, int64_t m, const int32_t *_
 // k-steps and terms are summed in the order of k_up / k_down.
 //   upward:   x_t = E_{s0}^T x_{s0} + E_{s1}^T x_{s1}   (list, son as for k_up)
 //   downward: y_c += E_c y_{par(c)}                    (list, par as for k_down)
+// by: the column slab; bs: NT x 64 x (16 NJ + 1) doubles of LDS
 template <int NJ, int NT, int TR>
 __device__ inline void transfer_rows(const double *const *Ea, const int64_t *brow, int64_t m,
-                                     const double *__restrict__ hat_in, int64_t ldh, dbl4 *acc) {
+                                     const double *__restrict__ hat_in, int64_t ldh, dbl4 *acc, int by, double *bs) {
     constexpr int MC = 16 * NJ, LDB = MC + 1, XPT = 64 * MC / 256;
-    __shared__ double bs[NT][64 * LDB];
     const int tid = threadIdx.x, lane = tid & 63, lr = lane & 15, lq = lane >> 4;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int64_t j0 = (int64_t)blockIdx.y * MC;
+    const int64_t j0 = (int64_t)by * MC;
     const int mc = (int)min<int64_t>(MC, m - j0);
     double a[NT][16], bv[NT][XPT];
 #pragma unroll
@@ -361,7 +361,7 @@ __device__ inline void transfer_rows(const double *const *Ea, const int64_t *bro
 #pragma unroll
         for (int u = 0; u < XPT; ++u) {
             const int e = tid + 256 * u, r = e / MC, c = e % MC;
-            bs[q][r * LDB + c] = c < mc ? bv[q][u] : 0.0;
+            bs[q * 64 * LDB + r * LDB + c] = c < mc ? bv[q][u] : 0.0;
         }
     __syncthreads();
 #pragma unroll
@@ -370,22 +370,23 @@ __device__ inline void transfer_rows(const double *const *Ea, const int64_t *bro
         for (int kk = 0; kk < 16; ++kk)
 #pragma unroll
             for (int J = 0; J < NJ; ++J)
-                acc[J] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q][kk], bs[q][(4 * kk + lq) * LDB + 16 * J + lr], acc[J],
-                                                              0, 0, 0);
+                acc[J] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q][kk], bs[q * 64 * LDB + (4 * kk + lq) * LDB + 16 * J + lr],
+                                                              acc[J], 0, 0, 0);
 }
 
+// one upward item: x_t = E_{s0}^T x_{s0} + E_{s1}^T x_{s1} for list entry i, column slab by
 template <int NJ>
-__global__ __launch_bounds__(256) void k_up64(int64_t m, const int32_t *__restrict__ list,
-                                              const int32_t *__restrict__ son, const double *__restrict__ E,
-                                              double *__restrict__ xh, int64_t ldh, Skip skip) {
-    const int32_t t = list[blockIdx.x], s0 = son[2 * blockIdx.x], s1 = son[2 * blockIdx.x + 1];
+__device__ inline void up64_item(int i, int by, int64_t m, const int32_t *__restrict__ list,
+                                 const int32_t *__restrict__ son, const double *__restrict__ E, double *__restrict__ xh,
+                                 int64_t ldh, Skip skip, double *bs) {
+    const int32_t t = list[i], s0 = son[2 * i], s1 = son[2 * i + 1];
     if (skip(t)) return;
     const double *Ea[2] = {E + (int64_t)s0 * 4096, E + (int64_t)s1 * 4096};
     const int64_t brow[2] = {(int64_t)s0 * 64, (int64_t)s1 * 64};
     dbl4 acc[NJ];
     zero<NJ>(acc);
-    transfer_rows<NJ, 2, 1>(Ea, brow, m, xh, ldh, acc);
-    const int64_t j0 = (int64_t)blockIdx.y * 16 * NJ;
+    transfer_rows<NJ, 2, 1>(Ea, brow, m, xh, ldh, acc, by, bs);
+    const int64_t j0 = (int64_t)by * 16 * NJ;
     const int mc = (int)min<int64_t>(16 * NJ, m - j0);
 #pragma unroll
     for (int J = 0; J < NJ; ++J)
@@ -394,24 +395,41 @@ __global__ __launch_bounds__(256) void k_up64(int64_t m, const int32_t *__restri
             for (int r = 0; r < 4; ++r) xh[((int64_t)t * 64 + out_row(r)) * ldh + j0 + out_col(J)] = acc[J][r];
 }
 
+// one downward item: y_c += E_c y_par for list entry i, column slab by
 template <int NJ>
-__global__ __launch_bounds__(256) void k_down64(int64_t m, const int32_t *__restrict__ list,
-                                                const int32_t *__restrict__ par, const double *__restrict__ E,
-                                                double *__restrict__ yh, int64_t ldh, Skip skip) {
-    const int32_t c = list[blockIdx.x], p = par[blockIdx.x];
+__device__ inline void down64_item(int i, int by, int64_t m, const int32_t *__restrict__ list,
+                                   const int32_t *__restrict__ par, const double *__restrict__ E,
+                                   double *__restrict__ yh, int64_t ldh, Skip skip, double *bs) {
+    const int32_t c = list[i], p = par[i];
     if (skip(c)) return;
     const double *Ea[1] = {E + (int64_t)c * 4096};
     const int64_t brow[1] = {(int64_t)p * 64};
     dbl4 acc[NJ];
     zero<NJ>(acc);
-    transfer_rows<NJ, 1, 0>(Ea, brow, m, yh, ldh, acc);
-    const int64_t j0 = (int64_t)blockIdx.y * 16 * NJ;
+    transfer_rows<NJ, 1, 0>(Ea, brow, m, yh, ldh, acc, by, bs);
+    const int64_t j0 = (int64_t)by * 16 * NJ;
     const int mc = (int)min<int64_t>(16 * NJ, m - j0);
 #pragma unroll
     for (int J = 0; J < NJ; ++J)
         if (out_col(J) < mc)
 #pragma unroll
             for (int r = 0; r < 4; ++r) yh[((int64_t)c * 64 + out_row(r)) * ldh + j0 + out_col(J)] += acc[J][r];
+}
+
+template <int NJ>
+__global__ __launch_bounds__(256) void k_up64(int64_t m, const int32_t *__restrict__ list,
+                                              const int32_t *__restrict__ son, const double *__restrict__ E,
+                                              double *__restrict__ xh, int64_t ldh, Skip skip) {
+    __shared__ double bs[2 * 64 * (16 * NJ + 1)];
+    up64_item<NJ>(blockIdx.x, blockIdx.y, m, list, son, E, xh, ldh, skip, bs);
+}
+
+template <int NJ>
+__global__ __launch_bounds__(256) void k_down64(int64_t m, const int32_t *__restrict__ list,
+                                                const int32_t *__restrict__ par, const double *__restrict__ E,
+                                                double *__restrict__ yh, int64_t ldh, Skip skip) {
+    __shared__ double bs[64 * (16 * NJ + 1)];
+    down64_item<NJ>(blockIdx.x, blockIdx.y, m, list, par, E, yh, ldh, skip, bs);
 }
 
 // Forward leaf transform for rank 64, x_t = V_t^T X|_t, with V_t^T straight into the
@@ -711,7 +729,7 @@ __global__ __launch_bounds__(256, NP == 1 ? 2 : 1) void k_leaf_direct(int k, int
 // rows of X into tree order with an even leading dimension: Xt[i] = X[perm[i]] (zero padding).
 // One thread per pair of columns, written with one 16-byte store (Xt 16-byte aligned, ldt
 // even); launch over n * ldt / 2 threads.
-__global__ void k_gather(int64_t n, int64_t m, const int64_t *__restrict__ perm, const double *__restrict__ X,
+static __global__ void k_gather(int64_t n, int64_t m, const int64_t *__restrict__ perm, const double *__restrict__ X,
                          int64_t ldx, double *__restrict__ Xt, int64_t ldt) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, half = ldt >> 1;
     if (e >= n * half) return;

@@ -99,17 +99,19 @@ h2x_status run_autotune(DevMat &dm, int64_t m, char *ws, size_t ws_bytes, hipStr
             best.nj_coupling = (int8_t)nj;
         }
     }
-    // leaf stage: a 64-row tile per wave and term, or a wave per 32-row band (the FP64
-    // matrix-core path has both), with 32 * np columns per wave
-    for (int kind = 1; kind <= (dm.mc ? 2 : 1) && e == hipSuccess; ++kind)
+    // leaf stage: a 64-row tile per wave and term, or (the FP64 matrix-core path) a wave per
+    // 32-row band or one contraction per leaf, with 32 * np columns per wave
+    for (int kind = 1; kind <= (dm.mc ? 3 : 1) && e == hipSuccess; ++kind)
         for (int np = 1; np <= (m > 32 ? 2 : 1) && e == hipSuccess; ++np) {
             double s[5];
             TuneCfg c{};
             c.np_leaf = (int8_t)np;
             c.leaf_kind = (int8_t)kind;
             e = time_cfg(c, s);
-            if (e == hipSuccess && s[4] < best_l) {
-                best_l = s[4];
+            // the whole product decides: the contraction-per-leaf form runs its near field
+            // beside the transfer levels (built-in rule), which moves it out of the leaf stage
+            if (e == hipSuccess && total(s) < best_l) {
+                best_l = total(s);
                 best.np_leaf = (int8_t)np;
                 best.leaf_kind = (int8_t)kind;
             }
@@ -130,7 +132,7 @@ h2x_status run_autotune(DevMat &dm, int64_t m, char *ws, size_t ws_bytes, hipStr
     // stages, so the whole product decides)
     if (dm.side) {
         double best_o = HUGE_VAL;
-        for (int o : {1, 2, 3, 4}) {
+        for (int o : {1, 2, 3, 4, 5}) {
             double so[5];
             TuneCfg c = best;
             c.overlap = (int8_t)o;
@@ -158,7 +160,7 @@ h2x_status run_autotune(DevMat &dm, int64_t m, char *ws, size_t ws_bytes, hipStr
     };
     // coupling of the deep rows beside the upper transfer levels, on or off
     double w_best = 0.0, w0 = 0.0;
-    if (dm.side && dm.split_depth > 0 && best.fuse_up != 1 && !(best.overlap == 1 || best.overlap >= 3)) {
+    if (dm.side && dm.split_depth > 0 && best.fuse_up != 1 && !(best.overlap == 1 || best.overlap == 3 || best.overlap == 4)) {
         // the second stream and its events cost something on every product: the split has
         // to win by 1 % over the single launch
         double w_min = HUGE_VAL;

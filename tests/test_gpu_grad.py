@@ -120,6 +120,32 @@ def test_adjoint_and_grad_match_oracle(name, pts, prm, m):
     assert err_l <= bound
 
 
+@pytest.mark.parametrize("name,pts,prm,m", CASES, ids=[c[0] for c in CASES])
+def test_dell_alone_matches_oracle(name, pts, prm, m):
+    """d ell without block gradients (rank 64: the fused kernels that form dg/dell in
+    registers; other ranks: the per-block kernels), each term and the sum, against the
+    oracle's d ell within the rounding bound of the sum (1e-12 * sum |dg/dell| |D|)."""
+    h2x = _h2x()
+    P = pts()
+    n = P.shape[0]
+    o = oracle.OracleH2(P, **prm)
+    A = h2x.H2Matrix(P, **prm)
+    X, dY = W.rhs(n, m, 190 + m), W.rhs(n, m, 290 + m)
+    Xd, dYd = _dev(X), _dev(dY)
+    oS, oN, odl = o.grad(X, dY)
+    bound = 1e-12 * (np.abs(oS).sum() + np.abs(oN).sum()) / (math.e * prm["ell"])
+    _, _, dl = h2x.h2_grad(A, Xd, dYd, want_dS=False)
+    _, _, lc = h2x.h2_grad(A, Xd, dYd, want_dS=False, dell_terms="coupling")
+    _, _, ln = h2x.h2_grad(A, Xd, dYd, want_dS=False, dell_terms="near")
+    _, _, nl = h2x.h2_grad(A, Xd, dYd, want_dS=False, scale=-2.0)
+    dl, lc, ln, nl = float(dl), float(lc), float(ln), float(nl)
+    print(f"{name}: d ell alone {dl:.12e} vs oracle {odl:.12e} (diff {abs(dl - odl):.2e}, bound {bound:.2e}); "
+          f"terms {lc:.6e} + {ln:.6e}")
+    assert abs(dl - odl) <= bound
+    assert abs(lc + ln - odl) <= bound
+    assert abs(nl + 2.0 * dl) <= 1e-15 * abs(dl)
+
+
 def test_adjoint_follows_transpose_of_nonsymmetric_operator():
     h2x = _h2x()
     P = W.sphere_points(5000, 186)

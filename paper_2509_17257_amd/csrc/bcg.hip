@@ -26,6 +26,7 @@ constexpr double kDrop = 1e-6; // deflation threshold (relative column norm)
 
 struct BcgState {
     int32_t rank, all_conv, iter, breakdown;
+    int32_t stop, pad;  // stop: set at the start of an iteration that must not run
     int32_t active[kMaxM];
     int32_t piv[kMaxM];
     int32_t conv[kMaxM];
@@ -45,7 +46,9 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 template <int MT>
 __global__ __launch_bounds__(256) void k_gram_mfma(int64_t n, int m, int nblk, const double *__restrict__ U0,
                                                    const double *__restrict__ V0, const double *__restrict__ U1,
-                                                   const double *__restrict__ V1, double *__restrict__ part) {
+                                                   const double *__restrict__ V1, double *__restrict__ part,
+                                                   const int32_t *stop) {
+    if (stop && *stop) return;
     __shared__ double red[kMaxM * kMaxM];
     const int tid = threadIdx.x, lane = tid & 63, lr = lane & 15, lq = lane >> 4;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -103,7 +106,8 @@ __global__ __launch_bounds__(256) void k_gram_mfma(int64_t n, int m, int nblk, c
 
 // G_q[e] = sum over blocks (fixed order) of the partial sums
 __global__ void k_gram_sum(int m, int nblk, const double *__restrict__ part, double *__restrict__ G0,
-                           double *__restrict__ G1) {
+                           double *__restrict__ G1, const int32_t *stop) {
+    if (stop && *stop) return;
     const int mm = m * m;
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     const int q = blockIdx.y;
@@ -134,10 +138,20 @@ __global__ void k_gram_sum(int m, int nblk, const double *__restrict__ part, dou
 // A work-group takes 2048 / MT rows (MT = m rounded up to 16): their rows of U are staged
 // in LDS with coalesced loads, and thread (rg, b) keeps column b of C in registers and forms
 // out[i][b] = sum_a U[i][a] C[a][b] (a in order) for rows i = rg, rg + 256 / m, ...
+// Work-groups with blockIdx.y = 1 form the second product (U2, Yin2, out2, alpha2) with the
+// same C and beta.
 template <int MT>
 __global__ __launch_bounds__(256) void k_tsmm(int64_t n, int m, const double *__restrict__ U,
                                               const double *__restrict__ Cm, const double *Yin, double *out,
-                                              double alpha, double beta) {
+                                              double alpha, double beta, const double *__restrict__ U2,
+                                              const double *Yin2, double *out2, double alpha2, const int32_t *stop) {
+    if (stop && *stop) return;
+    if (blockIdx.y == 1) {
+        U = U2;
+        Yin = Yin2;
+        out = out2;
+        alpha = alpha2;
+    }
     constexpr int RW = 2048 / MT;  // rows per work-group
     __shared__ __align__(16) double su[RW][MT];
     const int tid = threadIdx.x;
@@ -174,9 +188,13 @@ __global__ __launch_bounds__(256) void k_tsmm(int64_t n, int m, const double *__
 }
 
 // C = sign * G^{-1} F on the active index set (Cholesky of G restricted to it);
-// inactive rows of C are zero.  Sets breakdown if G is not positive definite there.
+// inactive rows of C are zero.  Sets breakdown if G is not positive definite there.  The
+// factor is stored in Lc (lower triangle, row stride m); with reuse the factor stored by the
+// previous call (same G, same active set) is taken instead of factorizing again.
 __global__ __launch_bounds__(256) void k_bcg_solve(int m, const double *__restrict__ G, const double *__restrict__ F,
-                                                   double *__restrict__ Cm, double sign, BcgState *st) {
+                                                   double *__restrict__ Cm, double sign, BcgState *st,
+                                                   double *__restrict__ Lc, int reuse, const int32_t *stop) {
+    if (stop && *stop) return;
     __shared__ double L[kMaxM][kMaxM + 1];
     __shared__ int idx[kMaxM];
     __shared__ int r, bad;
@@ -191,13 +209,20 @@ __global__ __launch_bounds__(256) void k_bcg_solve(int m, const double *__restri
     __syncthreads();
     // G on the active set and all of F staged in LDS with every load issued up front
     __shared__ double Fs[kMaxM][kMaxM + 1];
-    for (int e = tid; e < r * r; e += 256) L[e / r][e % r] = G[idx[e / r] * m + idx[e % r]];
+    if (reuse) {
+        for (int e = tid; e < r * r; e += 256) {
+            const int i = e / r, j = e % r;
+            if (j <= i) L[i][j] = Lc[i * m + j];
+        }
+    } else {
+        for (int e = tid; e < r * r; e += 256) L[e / r][e % r] = G[idx[e / r] * m + idx[e % r]];
+    }
     for (int e = tid; e < m * m; e += 256) Fs[e / m][e % m] = F[e];
     __syncthreads();
     // right-looking Cholesky, lower triangle.  Every thread forms the pivot's square root
     // itself and scales its entries of column k; the root is stored on the diagonal in the
     // update phase, which does not read it.
-    for (int k = 0; k < r; ++k) {
+    for (int k = 0; k < (reuse ? 0 : r); ++k) {
         const double v = L[k][k];
         const double dk = sqrt(v > 0.0 ? v : 1.0);
         if (tid == 0 && !(v > 0.0)) bad = 1;
@@ -211,6 +236,11 @@ __global__ __launch_bounds__(256) void k_bcg_solve(int m, const double *__restri
         __syncthreads();
     }
     if (tid == 0 && bad) st->breakdown = 1;
+    if (!reuse)
+        for (int e = tid; e < r * r; e += 256) {
+            const int i = e / r, j = e % r;
+            if (j <= i) Lc[i * m + j] = L[i][j];
+        }
     // one column of F per thread: forward then backward substitution, the column's
     // vector in LDS (a per-thread array with run-time indices would live in scratch memory)
     __shared__ double Y[kMaxM][kMaxM + 1];
@@ -260,7 +290,8 @@ __device__ inline void write_tinv(int m, int r, const double (*lv)[kMaxM + 1], c
 
 // first Cholesky-QR pass: pivoted Cholesky of W = Z^T Z with deflation
 __global__ __launch_bounds__(256) void k_bcg_orth1(int m, const double *__restrict__ W, double *__restrict__ M,
-                                                   BcgState *st) {
+                                                   BcgState *st, const int32_t *gate) {
+    if (gate && *gate) return;
     __shared__ double lv[kMaxM][kMaxM + 1];
     __shared__ double d[kMaxM], dg[kMaxM];
     __shared__ int piv[kMaxM], act[kMaxM];
@@ -351,7 +382,8 @@ __global__ __launch_bounds__(256) void k_bcg_orth1(int m, const double *__restri
 
 // second Cholesky-QR pass: plain Cholesky of W2 = P1^T P1 on the kept columns, pivot order
 __global__ __launch_bounds__(256) void k_bcg_orth2(int m, const double *__restrict__ W, double *__restrict__ M,
-                                                   const BcgState *st) {
+                                                   const BcgState *st, const int32_t *stop) {
+    if (stop && *stop) return;
     __shared__ double lv[kMaxM][kMaxM + 1];
     __shared__ double dg[kMaxM];
     __shared__ int piv[kMaxM];
@@ -382,7 +414,9 @@ __global__ __launch_bounds__(256) void k_bcg_orth2(int m, const double *__restri
 }
 
 // convergence from the diagonal of R^T R
-__global__ void k_bcg_conv(int m, const double *__restrict__ RR, double rtol, BcgState *st, int init) {
+__global__ void k_bcg_conv(int m, const double *__restrict__ RR, double rtol, BcgState *st, int init,
+                           const int32_t *stop) {
+    if (stop && *stop) return;
     __shared__ int notconv;
     if (threadIdx.x == 0) notconv = 0;
     __syncthreads();
@@ -408,6 +442,13 @@ __global__ void k_bcg_bnorm(int m, const double *__restrict__ BB, BcgState *st) 
     for (int j = threadIdx.x; j < m; j += blockDim.x) st->bnorm[j] = sqrt(BB[j * m + j]);
 }
 
+// start of an iteration: it must not run once every column has converged, after a
+// breakdown, without search directions or after max_iter iterations (the host takes the same
+// decision from the state it reads after queueing the iteration)
+__global__ void k_bcg_gate(BcgState *st, int32_t max_iter) {
+    st->stop = (st->breakdown || st->all_conv || st->iter >= max_iter || st->rank == 0) ? 1 : 0;
+}
+
 __global__ void k_copy_rows(int64_t n, int64_t m, const int64_t *__restrict__ perm, const double *__restrict__ src,
                             int64_t lds, double *__restrict__ dst, int scatter) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -418,7 +459,7 @@ __global__ void k_copy_rows(int64_t n, int64_t m, const int64_t *__restrict__ pe
 }
 
 struct BcgWs {
-    double *Bt, *Xt, *R, *P, *Q, *Z, *P1, *part, *G, *F, *C, *Wm, *RR, *M;
+    double *Bt, *Xt, *R, *P, *Q, *Z, *P1, *part, *G, *F, *C, *Wm, *RR, *M, *Lc;
     BcgState *st;
     char *mm;
     int nblk;
@@ -438,7 +479,7 @@ BcgWs bcg_layout(const DevMat &dm, int64_t m, char *base) {
     w.nblk = (int)std::min<int64_t>(256, std::max<int64_t>(1, (dm.n + 255) / 256));
     for (double **p : {&w.Bt, &w.Xt, &w.R, &w.P, &w.Q, &w.Z, &w.P1}) *p = (double *)carve(nm);
     w.part = (double *)carve(2 * (size_t)w.nblk * mm);
-    for (double **p : {&w.G, &w.F, &w.C, &w.Wm, &w.RR, &w.M}) *p = (double *)carve(mm);
+    for (double **p : {&w.G, &w.F, &w.C, &w.Wm, &w.RR, &w.M, &w.Lc}) *p = (double *)carve(mm);
     w.st = (BcgState *)carve(sizeof(BcgState));
     w.mm = carve(matmul_ws_bytes(dm, m));
     w.bytes = align_up(off);
@@ -471,32 +512,43 @@ h2x_status run_block_cg_shared(const DevMat &dm, const h2x_cg_params &prm, int64
         set_error(std::string("h2x_block_cg: ") + hipGetErrorString(e));
         return H2X_EHIP;
     };
+    // sp: the stop flag of the state inside the iteration loop (null before it)
+    const int32_t *sp = nullptr;
     auto gram2 = [&](const double *U0, const double *V0, const double *U1, const double *V1, double *G0,
                      double *G1) {
         switch ((mi + 15) / 16) {
-            case 1: hipLaunchKernelGGL(k_gram_mfma<1>, dim3(w.nblk), dim3(256), 0, st, n, mi, w.nblk, U0, V0, U1, V1, w.part); break;
-            case 2: hipLaunchKernelGGL(k_gram_mfma<2>, dim3(w.nblk), dim3(256), 0, st, n, mi, w.nblk, U0, V0, U1, V1, w.part); break;
-            case 3: hipLaunchKernelGGL(k_gram_mfma<3>, dim3(w.nblk), dim3(256), 0, st, n, mi, w.nblk, U0, V0, U1, V1, w.part); break;
-            default: hipLaunchKernelGGL(k_gram_mfma<4>, dim3(w.nblk), dim3(256), 0, st, n, mi, w.nblk, U0, V0, U1, V1, w.part); break;
+            case 1: hipLaunchKernelGGL(k_gram_mfma<1>, dim3(w.nblk), dim3(256), 0, st, n, mi, w.nblk, U0, V0, U1, V1, w.part, sp); break;
+            case 2: hipLaunchKernelGGL(k_gram_mfma<2>, dim3(w.nblk), dim3(256), 0, st, n, mi, w.nblk, U0, V0, U1, V1, w.part, sp); break;
+            case 3: hipLaunchKernelGGL(k_gram_mfma<3>, dim3(w.nblk), dim3(256), 0, st, n, mi, w.nblk, U0, V0, U1, V1, w.part, sp); break;
+            default: hipLaunchKernelGGL(k_gram_mfma<4>, dim3(w.nblk), dim3(256), 0, st, n, mi, w.nblk, U0, V0, U1, V1, w.part, sp); break;
         }
         hipLaunchKernelGGL(k_gram_sum, dim3(gs.x, U1 ? 2 : 1), dim3(256), 0, st, mi, w.nblk, (const double *)w.part,
-                           G0, G1);
+                           G0, G1, sp);
     };
-    auto tsmm = [&](const double *U, const double *Cm, const double *Yin, double *out, double alpha, double beta) {
+    // out = beta Yin + alpha U C, and with U2 also out2 = beta Yin2 + alpha2 U2 C in the same launch
+    auto tsmm = [&](const double *U, const double *Cm, const double *Yin, double *out, double alpha, double beta,
+                    const double *U2 = nullptr, const double *Yin2 = nullptr, double *out2 = nullptr,
+                    double alpha2 = 0.0) {
+        const dim3 g(gt, U2 ? 2 : 1);
         switch (mt) {
-            case 16: hipLaunchKernelGGL(k_tsmm<16>, dim3(gt), dim3(256), 0, st, n, mi, U, Cm, Yin, out, alpha, beta); break;
-            case 32: hipLaunchKernelGGL(k_tsmm<32>, dim3(gt), dim3(256), 0, st, n, mi, U, Cm, Yin, out, alpha, beta); break;
-            case 48: hipLaunchKernelGGL(k_tsmm<48>, dim3(gt), dim3(256), 0, st, n, mi, U, Cm, Yin, out, alpha, beta); break;
-            default: hipLaunchKernelGGL(k_tsmm<64>, dim3(gt), dim3(256), 0, st, n, mi, U, Cm, Yin, out, alpha, beta); break;
+            case 16: hipLaunchKernelGGL(k_tsmm<16>, g, dim3(256), 0, st, n, mi, U, Cm, Yin, out, alpha, beta, U2, Yin2, out2, alpha2, sp); break;
+            case 32: hipLaunchKernelGGL(k_tsmm<32>, g, dim3(256), 0, st, n, mi, U, Cm, Yin, out, alpha, beta, U2, Yin2, out2, alpha2, sp); break;
+            case 48: hipLaunchKernelGGL(k_tsmm<48>, g, dim3(256), 0, st, n, mi, U, Cm, Yin, out, alpha, beta, U2, Yin2, out2, alpha2, sp); break;
+            default: hipLaunchKernelGGL(k_tsmm<64>, g, dim3(256), 0, st, n, mi, U, Cm, Yin, out, alpha, beta, U2, Yin2, out2, alpha2, sp); break;
         }
+    };
+    // the second solve of an iteration has the same G and active set: it takes the factor
+    auto solve = [&](double sign, int reuse) {
+        hipLaunchKernelGGL(k_bcg_solve, dim3(1), dim3(256), 0, st, mi, (const double *)w.G, (const double *)w.F, w.C,
+                           sign, w.st, w.Lc, reuse, sp);
     };
     auto orth = [&](const double *Zs) {
         gram2(Zs, Zs, nullptr, nullptr, w.Wm, nullptr);
-        hipLaunchKernelGGL(k_bcg_orth1, dim3(1), dim3(256), 0, st, mi, (const double *)w.Wm, w.M, w.st);
+        hipLaunchKernelGGL(k_bcg_orth1, dim3(1), dim3(256), 0, st, mi, (const double *)w.Wm, w.M, w.st, sp);
         tsmm(Zs, w.M, nullptr, w.P1, 1.0, 0.0);
         gram2(w.P1, w.P1, nullptr, nullptr, w.Wm, nullptr);
         hipLaunchKernelGGL(k_bcg_orth2, dim3(1), dim3(256), 0, st, mi, (const double *)w.Wm, w.M,
-                           (const BcgState *)w.st);
+                           (const BcgState *)w.st, sp);
         tsmm(w.P1, w.M, nullptr, w.P, 1.0, 0.0);
     };
 
@@ -507,16 +559,52 @@ h2x_status run_block_cg_shared(const DevMat &dm, const h2x_cg_params &prm, int64
     if (e != hipSuccess) return fail(e);
     gram2(w.Bt, w.Bt, w.R, w.R, w.G, w.RR);
     hipLaunchKernelGGL(k_bcg_bnorm, dim3(1), dim3(64), 0, st, mi, (const double *)w.G, w.st);
-    hipLaunchKernelGGL(k_bcg_conv, dim3(1), dim3(64), 0, st, mi, (const double *)w.RR, prm.rtol, w.st, 1);
+    hipLaunchKernelGGL(k_bcg_conv, dim3(1), dim3(64), 0, st, mi, (const double *)w.RR, prm.rtol, w.st, 1,
+                       (const int32_t *)nullptr);
     orth(w.R);
 
-    BcgState hs{};
-    int32_t status = H2X_OK, rank_min = (int32_t)m;
+    // two pinned host copies of the state: the host reads the state after iteration it while
+    // iteration it + 1 is already queued, so the device does not idle at each decision
+    struct HostCopies {
+        BcgState *p = nullptr;
+        hipEvent_t ev[2] = {nullptr, nullptr};
+        ~HostCopies() {
+            for (hipEvent_t x : ev)
+                if (x) (void)hipEventDestroy(x);
+            if (p) (void)hipHostFree(p);
+        }
+    } hc;
+    e = hipHostMalloc((void **)&hc.p, 2 * sizeof(BcgState), hipHostMallocDefault);
+    for (int q = 0; q < 2 && e == hipSuccess; ++q) e = hipEventCreateWithFlags(&hc.ev[q], hipEventDisableTiming);
+    auto snapshot = [&](int slot) {
+        hipError_t r = hipMemcpyAsync(&hc.p[slot], w.st, sizeof(BcgState), hipMemcpyDeviceToHost, st);
+        return r == hipSuccess ? hipEventRecord(hc.ev[slot], st) : r;
+    };
+    if (e == hipSuccess) e = snapshot(0);
+    if (e != hipSuccess) return fail(e);
+
+    sp = &w.st->stop;
+    int32_t status = H2X_OK;
     for (int32_t it = 0;; ++it) {
-        e = hipMemcpyAsync(&hs, w.st, sizeof(BcgState), hipMemcpyDeviceToHost, st);
-        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        // iteration it + 1; its kernels return at once when the gate stops it, which happens
+        // exactly when the host stops below
+        hipLaunchKernelGGL(k_bcg_gate, dim3(1), dim3(1), 0, st, w.st, prm.max_iter);
+        e = run_matmul(dm, m, 1.0, w.P, m, 0.0, w.Q, m, true, w.mm, st, nullptr, sp);
         if (e != hipSuccess) return fail(e);
-        rank_min = std::min(rank_min, hs.rank);
+        gram2(w.P, w.Q, w.P, w.R, w.G, w.F);  // G = P^T A P, F = P^T R
+        solve(1.0, 0);
+        tsmm(w.P, w.C, w.Xt, w.Xt, 1.0, 1.0,  // X += P Lambda
+             w.Q, w.R, w.R, -1.0);            // R -= Q Lambda
+        gram2(w.Q, w.R, w.R, w.R, w.F, w.RR);   // F = (A P)^T R, RR = R^T R
+        hipLaunchKernelGGL(k_bcg_conv, dim3(1), dim3(64), 0, st, mi, (const double *)w.RR, prm.rtol, w.st, 0, sp);
+        solve(-1.0, 1);
+        tsmm(w.P, w.C, w.R, w.Z, 1.0, 1.0);     // Z = R + P Psi
+        orth(w.Z);
+        e = snapshot((it + 1) & 1);
+        // the state after iteration it
+        if (e == hipSuccess) e = hipEventSynchronize(hc.ev[it & 1]);
+        if (e != hipSuccess) return fail(e);
+        const BcgState &hs = hc.p[it & 1];
         if (hs.breakdown) {
             status = H2X_EBREAKDOWN;
             break;
@@ -526,21 +614,9 @@ h2x_status run_block_cg_shared(const DevMat &dm, const h2x_cg_params &prm, int64
             status = H2X_ENOCONV;
             break;
         }
-        e = run_matmul(dm, m, 1.0, w.P, m, 0.0, w.Q, m, true, w.mm, st);
-        if (e != hipSuccess) return fail(e);
-        gram2(w.P, w.Q, w.P, w.R, w.G, w.F);  // G = P^T A P, F = P^T R
-        hipLaunchKernelGGL(k_bcg_solve, dim3(1), dim3(256), 0, st, mi, (const double *)w.G, (const double *)w.F, w.C,
-                           1.0, w.st);
-        tsmm(w.P, w.C, w.Xt, w.Xt, 1.0, 1.0);   // X += P Lambda
-        tsmm(w.Q, w.C, w.R, w.R, -1.0, 1.0);    // R -= Q Lambda
-        gram2(w.Q, w.R, w.R, w.R, w.F, w.RR);   // F = (A P)^T R, RR = R^T R
-        hipLaunchKernelGGL(k_bcg_conv, dim3(1), dim3(64), 0, st, mi, (const double *)w.RR, prm.rtol, w.st, 0);
-        hipLaunchKernelGGL(k_bcg_solve, dim3(1), dim3(256), 0, st, mi, (const double *)w.G, (const double *)w.F, w.C,
-                           -1.0, w.st);
-        tsmm(w.P, w.C, w.R, w.Z, 1.0, 1.0);     // Z = R + P Psi
-        orth(w.Z);
     }
     hipLaunchKernelGGL(k_copy_rows, dim3(g1), dim3(256), 0, st, n, m, dm.perm, (const double *)w.Xt, ldx, X, 1);
+    BcgState hs{};
     e = hipMemcpyAsync(&hs, w.st, sizeof(BcgState), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return fail(e);
@@ -556,7 +632,6 @@ h2x_status run_block_cg_shared(const DevMat &dm, const h2x_cg_params &prm, int64
             if (info->col_status) info->col_status[j] = hs.conv[j] ? 0 : (status == H2X_EBREAKDOWN ? 1 : 2);
         }
     }
-    (void)rank_min;
     return H2X_OK;
 }
 

@@ -337,6 +337,8 @@ def grad_report(args, torch, h2x, W):
     dS_bytes = 8 * plan.n_adm * plan.k * plan.k
     ms = timed(lambda: h2x.h2_grad(A, X, dY, want_dS=True, want_dell=True), reps)
     out["grad_dS_dell"] = {"ms": round(ms, 4), "dS_bytes": dS_bytes, "dS_write_gbs": round(dS_bytes / (ms * 1e-3) / 1e9, 1)}
+    ms = timed(lambda: h2x.h2_grad(A, X, dY, want_dS=True, want_dell=False), reps)
+    out["grad_dS"] = {"ms": round(ms, 4), "dS_write_gbs": round(dS_bytes / (ms * 1e-3) / 1e9, 1)}
     ms = timed(lambda: h2x.h2_grad(A, X, dY, want_dS=False, want_dell=True), reps)
     out["grad_dell"] = {"ms": round(ms, 4)}
     log(f"[grad] {out}")

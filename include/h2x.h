@@ -392,7 +392,9 @@ typedef struct {
     int32_t overlap;   /* near field beside the transfer passes: 0 (built-in rule) and 2
                           off; on a second stream with its grid capped at 256 (1), 128 (3)
                           or 512 (4) work-groups; 5 in shares inside the launches of the
-                          transfer levels (leaf_kind 3, k = 64)                          */
+                          transfer levels; 6 in two halves on a second stream, one beside
+                          the upward and one beside the downward pass, at most three
+                          near work-groups per CU (5 and 6: leaf_kind 3, k = 64)         */
     int32_t fuse_up;   /* forward leaf and upward pass in one launch: 1 on; 0 (built-in
                           rule) and 2 level by level                                   */
     int32_t leaf_kind; /* leaf stage (32 * np_leaf columns per wave): 0 built-in rule
@@ -427,7 +429,7 @@ h2x_status h2x_mat_autotune(h2x_mat *A, int64_t m, void *dev_ws, size_t ws_bytes
  * ceil(m / 16), counts above 64 sharing one): a choice kept from an earlier autotune
  * run, or a fixed shape, without timing.  Set: the shape fields of cfg are used
  * (ms_default / ms_tuned ignored); all zero restores the built-in rule; ranges
- * nj_transfer, nj_coupling 0..4, np_leaf 0..2, overlap 0..5, fuse_up 0..2, leaf_kind
+ * nj_transfer, nj_coupling 0..4, np_leaf 0..2, overlap 0..6, fuse_up 0..2, leaf_kind
  * 0..3, split 0..3, else H2X_EINVAL.  Get: ms_default = ms_tuned = 0.  Host only; must
  * not run concurrently with products on the same operator. */
 h2x_status h2x_mat_set_tune(h2x_mat *A, int64_t m, const h2x_tune_info *cfg);

@@ -561,7 +561,7 @@ h2x_status h2x_mat_set_tune(h2x_mat *A, int64_t m, const h2x_tune_info *cfg) {
     if (m < 1) return fail(H2X_EINVAL, "h2x_mat_set_tune: need m >= 1");
     auto in = [](int32_t v, int32_t hi) { return v >= 0 && v <= hi; };
     if (!in(cfg->nj_transfer, 4) || !in(cfg->nj_coupling, 4) || !in(cfg->np_leaf, 2) ||
-        !in(cfg->overlap, 5) || !in(cfg->fuse_up, 2) || !in(cfg->leaf_kind, 3) || !in(cfg->split, 3))
+        !in(cfg->overlap, 6) || !in(cfg->fuse_up, 2) || !in(cfg->leaf_kind, 3) || !in(cfg->split, 3))
         return fail(H2X_EINVAL, "h2x_mat_set_tune: a shape field is out of range");
     TuneCfg c{};
     c.nj_transfer = (int8_t)cfg->nj_transfer;

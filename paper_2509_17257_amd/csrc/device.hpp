@@ -39,6 +39,7 @@ inline int tune_bucket(int64_t m) { return (int)std::min<int64_t>(kTuneBuckets -
 struct DevMat {
     int64_t n = 0;
     int32_t C = 0, L = 0, k = 0, p = 0, depth_max = 0, max_leaf = 0, max_near_rows = 0;
+    int32_t leaf_half = 0;  // see Plan::leaf_half
     int64_t n_adm = 0, n_near = 0, near_entries = 0;
     h2x_prec storage = H2X_F64;
     int swz = 0;     // coupling-matrix layout (see s_index)

@@ -251,6 +251,7 @@ size_t mat_layout(const Plan &P, h2x_prec storage, DevMat *dm, char *base) {
     DevMat d;
     d.n = n; d.C = C; d.L = L; d.k = k; d.p = P.p; d.depth_max = P.depth_max; d.max_leaf = P.max_leaf;
     d.max_near_rows = P.max_near_rows;
+    d.leaf_half = P.leaf_half;
     d.n_adm = na; d.n_near = nn; d.near_entries = P.near_entries; d.storage = storage;
     d.kernel = P.prm.kernel; d.ell = P.prm.ell; d.shift = P.prm.shift; d.plan = &P;
     d.swz = k != 64 ? 0 : (storage == H2X_F64 ? 1 : (storage == H2X_F32 ? 2 : 3));

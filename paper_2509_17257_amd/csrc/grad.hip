@@ -502,17 +502,19 @@ hipError_t run_grad(const DevMat &dm, int64_t m, const double *X, int64_t ldx, c
     const int64_t ldh = even(m);
     hipError_t e = hipSuccess;
     const int cpl = dell && (dell_terms & H2X_DELL_COUPLING) ? 1 : 0, nr = dell && (dell_terms & H2X_DELL_NEAR) ? 1 : 0;
-    // d ell alone (no block gradients requested) on the rank-64 exponential operator
+    // d ell on the rank-64 exponential operator: its own fused kernels (after the block
+    // gradients, which then skip their d ell terms)
     const DellShape ds = dell_shape(dm, m);
-    if (dell && !dS && !dN && ds.ok && dm.kernel == H2X_KERNEL_EXP && dm.n_adm + dm.n_near > 0)
-        return run_dell_fused(dm, ds, m, X, ldx, dY, lddy, dell, scale, cpl, nr, w, st);
+    const bool fused = dell && ds.ok && dm.kernel == H2X_KERNEL_EXP && dm.n_adm + dm.n_near > 0;
+    if (fused && !dS && !dN) return run_dell_fused(dm, ds, m, X, ldx, dY, lddy, dell, scale, cpl, nr, w, st);
+    const int cpl_b = fused ? 0 : cpl, nr_b = fused ? 0 : nr;  // d ell terms of the block-gradient kernels
     // the partial sums of dell's terms that are not wanted are zero
-    if (dell && !cpl && dm.n_adm > 0)
+    if (dell && !fused && !cpl && dm.n_adm > 0)
         hipLaunchKernelGGL(k_fill0, dim3((unsigned)((dm.n_adm + 255) / 256)), dim3(256), 0, st, dm.n_adm, w.part);
-    if (dell && !nr && dm.n_near > 0)
+    if (dell && !fused && !nr && dm.n_near > 0)
         hipLaunchKernelGGL(k_fill0, dim3((unsigned)((dm.n_near + 255) / 256)), dim3(256), 0, st, dm.n_near,
                            w.part + dm.n_adm);
-    if (dS || cpl) {
+    if (dS || cpl_b) {
         e = run_forward_transform(dm, m, X, ldx, false, w.xh, ldh, w.xt_ws, st);
         if (e == hipSuccess) e = run_forward_transform(dm, m, dY, lddy, false, w.dh, ldh, w.xt_ws, st);
         if (e != hipSuccess) return e;
@@ -520,14 +522,14 @@ hipError_t run_grad(const DevMat &dm, int64_t m, const double *X, int64_t ldx, c
             if (dm.mc)
                 hipLaunchKernelGGL(adj::k_grad_S_mfma, dim3((unsigned)dm.n_adm), dim3(256), 0, st, dm.k, m, dm.adm_row,
                                    dm.adm_col, dm.nodes, dm.kernel, dm.ell, (const double *)w.dh,
-                                   (const double *)w.xh, ldh, scale, cpl, dS, w.part);
+                                   (const double *)w.xh, ldh, scale, cpl_b, dS, w.part);
             else
                 hipLaunchKernelGGL(k_grad_S, dim3((unsigned)dm.n_adm), dim3(256), 0, st, dm.k, m, dm.adm_row,
                                    dm.adm_col, dm.nodes, dm.kernel, dm.ell, (const double *)w.dh,
-                                   (const double *)w.xh, ldh, scale, cpl, dS, w.part);
+                                   (const double *)w.xh, ldh, scale, cpl_b, dS, w.part);
         }
     }
-    if (dN || nr) {
+    if (dN || nr_b) {
         const int64_t cnt = dm.n * ldh;
         hipLaunchKernelGGL(k_gather_even, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, dm.n, m, dm.perm, X,
                            ldx, w.Xt, ldh);
@@ -537,15 +539,16 @@ hipError_t run_grad(const DevMat &dm, int64_t m, const double *X, int64_t ldx, c
             if (dm.mc)
                 hipLaunchKernelGGL(adj::k_grad_N_mfma, dim3((unsigned)dm.n_near), dim3(256), 0, st, m, dm.near_row,
                                    dm.near_col, dm.near_off_rm, dm.first, dm.size, dm.pts, dm.kernel, dm.ell,
-                                   (const double *)w.dYt, (const double *)w.Xt, ldh, scale, nr, dN,
+                                   (const double *)w.dYt, (const double *)w.Xt, ldh, scale, nr_b, dN,
                                    w.part + dm.n_adm);
             else
                 hipLaunchKernelGGL(k_grad_N, dim3((unsigned)dm.n_near), dim3(256), 0, st, m, dm.near_row,
                                    dm.near_col, dm.near_off_rm, dm.first, dm.size, dm.pts, dm.kernel, dm.ell,
-                                   (const double *)w.dYt, (const double *)w.Xt, ldh, scale, nr, dN,
+                                   (const double *)w.dYt, (const double *)w.Xt, ldh, scale, nr_b, dN,
                                    w.part + dm.n_adm);
         }
     }
+    if (fused) return run_dell_fused(dm, ds, m, X, ldx, dY, lddy, dell, scale, cpl, nr, w, st);
     if (dell) {
         const int64_t cnt = dm.n_adm + dm.n_near, ng = (cnt + kSumChunk - 1) / kSumChunk;
         if (ng > 1) {

@@ -394,10 +394,19 @@ void matmul_mfma_f64(const DevMat &dm, const TuneCfg &cfg, int64_t m, double alp
         leaf(dm.side, beta, 0, 1, cap);
         (void)hipEventRecord(dm.ev_join, dm.side);
     }
+    // overlap 6: the near field in two halves on the operator's second stream, each beside a
+    // latency-bound stretch of this stream: the first half (the first leaf_half positions of
+    // every XCD eighth of the leaf order, about half of the near entries) beside the forward
+    // leaf transform and the upward pass, the second beside the downward pass.  Its
+    // work-groups take enough LDS that a CU holds at most three of them and keeps room for a
+    // transfer work-group.  The basis term follows the downward pass (not with per-stage
+    // timing or the fused upward pass).
+    const bool halves = kind == 3 && t64 && dm.side && dm.n_near > 0 && cfg.overlap == 6 && !ev &&
+                        cfg.fuse_up != 1 && dm.leaf_half > 0;
     // coupling of the deep rows on the second stream beside the upper transfer levels, the
     // coupling of the other rows and the upper downward levels (not with per-stage timing,
     // the concurrent near field or the fused upward pass)
-    const bool split = (cfg.split == 1 || cfg.split == 3) && dm.split_depth > 0 && dm.side && !ov && !ev &&
+    const bool split = (cfg.split == 1 || cfg.split == 3) && dm.split_depth > 0 && dm.side && !ov && !halves && !ev &&
                        cfg.fuse_up != 1;
     // near field in shares beside the transfer levels (the leaf form with one contraction per
     // leaf, rank 64): each level launch also runs a share of the near-field slots, so that
@@ -474,6 +483,51 @@ void matmul_mfma_f64(const DevMat &dm, const TuneCfg &cfg, int64_t m, double alp
             launch_coupling_fast<double, double>(dm, m, xh, yh, ldh, s, sk, cfg.nj_coupling, 1, nrows, rows, keep);
     };
     const int dlo = std::max(1, P.adm_depth + 1);
+    if (halves) {
+        // dynamic LDS of the near work-groups: more than a quarter of a CU's LDS (at most
+        // three per CU), and small enough that three of them and an upward work-group fit
+        size_t dyn = cat_lds;
+        {
+            hipFuncAttributes fa{}, fu{};
+            int dev = 0, per_cu = 0;
+            const void *fl = NP == 2 ? (const void *)mfma::k_leaf_cat<2> : (const void *)mfma::k_leaf_cat<1>;
+            if (hipFuncGetAttributes(&fa, fl) == hipSuccess &&
+                hipFuncGetAttributes(&fu, (const void *)mfma::k_up64<NJ>) == hipSuccess &&
+                hipGetDevice(&dev) == hipSuccess &&
+                hipDeviceGetAttribute(&per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) ==
+                    hipSuccess) {
+                const size_t lo = (((size_t)per_cu / 4 + 1024) + 511) & ~(size_t)511;
+                const size_t hi = (size_t)per_cu > fu.sharedSizeBytes ? ((size_t)per_cu - fu.sharedSizeBytes) / 3 : 0;
+                if (lo <= hi && lo <= 65536 && lo > fa.sharedSizeBytes + cat_lds) dyn = lo - fa.sharedSizeBytes;
+            }
+        }
+        auto near_part = [&](int64_t s0, int64_t s1) {
+            if (s1 <= s0) return;
+            if (NP == 2)
+                hipLaunchKernelGGL(mfma::k_leaf_cat<2>, dim3((unsigned)(s1 - s0)), dim3(256), dyn, dm.side,
+                                   cat_args(beta, 0, 1), s0, s1);
+            else
+                hipLaunchKernelGGL(mfma::k_leaf_cat<1>, dim3((unsigned)(s1 - s0)), dim3(256), dyn, dm.side,
+                                   cat_args(beta, 0, 1), s0, s1);
+        };
+        // slots below sA: the first leaf_half positions of every eighth (a multiple of 8, so
+        // slot s still runs on XCD s % 8)
+        const int64_t sA = std::min<int64_t>(cat_slots, (int64_t)8 * dm.leaf_half * gl);
+        (void)hipEventRecord(dm.ev_fork, st);
+        (void)hipStreamWaitEvent(dm.side, dm.ev_fork, 0);
+        near_part(0, sA);
+        fwd_leaf();
+        up_levels(dm.depth_max - 1, P.adm_depth);
+        coupling(st, -1, nullptr, 0);
+        (void)hipEventRecord(dm.ev_fork, st);
+        (void)hipStreamWaitEvent(dm.side, dm.ev_fork, 0);
+        near_part(sA, cat_slots);
+        (void)hipEventRecord(dm.ev_join, dm.side);
+        down_levels(dlo, dm.depth_max);
+        (void)hipStreamWaitEvent(st, dm.ev_join, 0);
+        leaf(st, 1.0, 1, 0, 0);  // the near field is in Y already (beta applied there)
+        return;
+    }
     if (split) {
         fwd_leaf();
         const int D = dm.split_depth;

@@ -67,6 +67,9 @@ struct Plan {
     // eighths (one per XCD), the leaves with the most work first within each, so that the
     // longest leaves do not start last
     std::vector<int32_t> leaf_order; // L
+    // positions of each eighth of leaf_order whose near-field entries add up to about half
+    // of all (the first half of the near field when it runs in two halves)
+    int32_t leaf_half = 0;
     // the same rows in two parts, so that the coupling of the deep part can run beside the
     // upper transfer levels: "deep" rows lie at depth >= split_depth and every inner
     // cluster of their lists too (their x-hat is complete once the upward pass has done

@@ -110,6 +110,21 @@ void leaf_order(Plan &P) {
         std::stable_sort(P.leaf_order.begin() + lo, P.leaf_order.begin() + hi,
                          [&](int32_t a, int32_t b) { return work[a] > work[b]; });
     }
+    // the first q positions of every eighth hold about half of the near-field entries
+    std::vector<int64_t> ent(L, 0);
+    int64_t total = 0;
+    for (int32_t l = 0; l < L; ++l) {
+        const int32_t nt = P.size[P.leaves[l]];
+        for (int64_t q = P.near_ptr[l]; q < P.near_ptr[l + 1]; ++q) ent[l] += (int64_t)P.size[P.near_col[q]] * nt;
+        total += ent[l];
+    }
+    int64_t cum = 0;
+    P.leaf_half = 0;
+    for (int32_t q = 0; q < lpx && 2 * cum < total; ++q) {
+        for (int32_t x = 0; x < 8; ++x)
+            if (x * lpx + q < L) cum += ent[P.leaf_order[x * lpx + q]];
+        P.leaf_half = q + 1;
+    }
 }
 
 }  // namespace

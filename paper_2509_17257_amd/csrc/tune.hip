@@ -158,9 +158,21 @@ h2x_status run_autotune(DevMat &dm, int64_t m, char *ws, size_t ws_bytes, hipStr
         ms = (double)t / reps;
         return r;
     };
-    // coupling of the deep rows beside the upper transfer levels, on or off
+    // the near field in two halves beside the transfer passes (whole products decide, as the
+    // stage events exclude it); kept when it wins by 1 %
     double w_best = 0.0, w0 = 0.0;
-    if (dm.side && dm.split_depth > 0 && best.fuse_up != 1 && !(best.overlap == 1 || best.overlap == 3 || best.overlap == 4)) {
+    if (dm.side && dm.mc && best.fuse_up != 1) {
+        TuneCfg c = best;
+        c.overlap = 6;
+        double w6 = 0.0, wb = 0.0;
+        e = time_whole(best, wb);
+        if (e == hipSuccess) e = time_whole(c, w6);
+        if (e != hipSuccess) return done(e);
+        if (w6 * 1.01 < wb) best.overlap = 6;
+    }
+    // coupling of the deep rows beside the upper transfer levels, on or off
+    if (dm.side && dm.split_depth > 0 && best.fuse_up != 1 &&
+        !(best.overlap == 1 || best.overlap == 3 || best.overlap == 4 || best.overlap == 6)) {
         // the second stream and its events cost something on every product: the split has
         // to win by 1 % over the single launch
         double w_min = HUGE_VAL;

@@ -89,8 +89,9 @@ ROWS = [c for c in CASES if c[0] in ("small-k27-m37", "sphere-k64-m32", "cube-k6
 
 # leaf-stage forms: 1 a 64-row tile per wave and term, 2 a wave per 32-row band, 3 the near
 # blocks and the basis as one contraction per leaf (16-row tiles; its near field also in
-# shares inside the transfer-level launches, overlap 5, or on the second stream, overlap 1)
-LEAF_FORMS = [(1, (2, 1)), (2, (2, 1)), (3, (2, 1, 5))]
+# shares inside the transfer-level launches, overlap 5, on the second stream, overlap 1, or
+# in two halves on the second stream beside the upward and the downward pass, overlap 6)
+LEAF_FORMS = [(1, (2, 1)), (2, (2, 1)), (3, (2, 1, 5, 6))]
 
 
 @pytest.mark.parametrize("kind,overlaps", LEAF_FORMS, ids=[f"kind{k}" for k, _ in LEAF_FORMS])
@@ -166,7 +167,7 @@ def test_set_get_tune():
     assert A.get_tune(17) == A.get_tune(32) == dict(nj_transfer=0, nj_coupling=2, np_leaf=1, overlap=1, fuse_up=0,
                                                     leaf_kind=2, split=2)
     assert A.get_tune(16)["leaf_kind"] == 0 and A.get_tune(33)["leaf_kind"] == 0
-    for bad in (dict(nj_coupling=5), dict(leaf_kind=4), dict(split=4), dict(np_leaf=-1), dict(overlap=6), dict(fuse_up=3)):
+    for bad in (dict(nj_coupling=5), dict(leaf_kind=4), dict(split=4), dict(np_leaf=-1), dict(overlap=7), dict(fuse_up=3)):
         with pytest.raises(h2x.H2xError, match="out of range"):
             A.set_tune(20, **bad)
     with pytest.raises(ValueError):

@@ -401,9 +401,10 @@ typedef struct {
                           (3 where its table of near rows fits in LDS and the operator
                           is real, else 1); 1 a work-group per leaf, each wave a 64-row
                           tile of its share of the terms; 2 a wave per 32-row band of a
-                          leaf, every term in turn; 3 a work-group per leaf, the near
-                          blocks and the basis as one contraction in rounds of 16 rows,
-                          16-row tiles of the leaf                                      */
+                          leaf, every term in turn (FP64 only; 1 for FP32 / BF16); 3 a
+                          work-group per leaf, the near blocks and the basis as one
+                          contraction in rounds of 16 rows, 16-row tiles of the leaf
+                          (FP64, FP32 and BF16 storage)                                 */
     int32_t split;     /* coupling rows in two parts, the deep part (rows whose lists are
                           complete once the upward pass has reached a split depth) on a
                           second stream beside the upper transfer levels, the coupling of

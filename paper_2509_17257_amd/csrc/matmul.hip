@@ -17,6 +17,7 @@
 #include "device.hpp"
 #include "coupling_lp.hpp"
 #include "leaf_cat.hpp"
+#include "leaf_cat_lp.hpp"
 #include "leaf_lp.hpp"
 #include "leaf_rows.hpp"
 #include "matmul_mfma.hpp"
@@ -699,7 +700,22 @@ hipError_t matmul_typed(const DevMat &dm, const TuneCfg &cfg, int64_t m, double 
             const Skip sk{skip, dm.sys_of};
             const int rb = std::is_same<T, bf16_t>::value ? 1 : 0;
             const unsigned gl8 = 8 * ((dm.L + 7) / 8);
-            if (cfg.np_leaf ? cfg.np_leaf == 2 : m > 32)
+            const int NPl = cfg.np_leaf ? cfg.np_leaf : (m > 32 ? 2 : 1);
+            // one contraction per leaf (built-in where its table of near rows fits in LDS;
+            // leaf_kind 3 or 0), else a 64-row tile per wave and term (leaf_kind 1 or 2)
+            const size_t cat_lds = sizeof(int32_t) * (size_t)std::max(1, dm.max_near_rows);
+            const size_t red = NPl == 2 ? lp::leaf_cat_lp_red_bytes<2>() : lp::leaf_cat_lp_red_bytes<1>();
+            const bool cat_ok = !dm.cplx && cat_lds + red + 64 <= 65536;
+            if (cat_ok && (cfg.leaf_kind == 0 || cfg.leaf_kind == 3)) {
+                const lp::LeafCatLpArgs a{dm.k, m, dm.L, dm.leaf_order, dm.leaves, dm.first, dm.size, dm.perm,
+                                          dm.Vt, dm.vt_off, yh, ldh, dm.near_ptr, dm.near_col, dm.near_off,
+                                          (const float *)dm.N, xt, ldxt, alpha, beta, Y, ldy, to, rb, sk};
+                const unsigned grid = gl8 * (unsigned)((m + 32 * NPl - 1) / (32 * NPl));
+                if (NPl == 2)
+                    hipLaunchKernelGGL((lp::k_leaf_cat_lp<2, T>), dim3(grid), dim3(256), cat_lds, st, a);
+                else
+                    hipLaunchKernelGGL((lp::k_leaf_cat_lp<1, T>), dim3(grid), dim3(256), cat_lds, st, a);
+            } else if (NPl == 2)
                 hipLaunchKernelGGL((lp::k_leaf_lp<2, T>), dim3(gl8 * (unsigned)((m + 63) / 64)), dim3(256), 0, st,
                                    dm.k, m, dm.L, dm.leaves, dm.first, dm.size, dm.perm, (const T *)dm.Vt, dm.vt_off,
                                    yh, ldh, dm.near_ptr, dm.near_col, dm.near_off, (const float *)dm.N, xt, ldxt,

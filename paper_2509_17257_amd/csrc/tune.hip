@@ -99,8 +99,8 @@ h2x_status run_autotune(DevMat &dm, int64_t m, char *ws, size_t ws_bytes, hipStr
             best.nj_coupling = (int8_t)nj;
         }
     }
-    // leaf stage: a 64-row tile per wave and term, or (the FP64 matrix-core path) a wave per
-    // 32-row band or one contraction per leaf, with 32 * np columns per wave
+    // leaf stage: a 64-row tile per wave and term, a wave per 32-row band (FP64 matrix-core
+    // path) or one contraction per leaf (matrix-core paths), with 32 * np columns per wave
     for (int kind = 1; kind <= (dm.mc ? 3 : 1) && e == hipSuccess; ++kind)
         for (int np = 1; np <= (m > 32 ? 2 : 1) && e == hipSuccess; ++np) {
             double s[5];
@@ -108,8 +108,7 @@ h2x_status run_autotune(DevMat &dm, int64_t m, char *ws, size_t ws_bytes, hipStr
             c.np_leaf = (int8_t)np;
             c.leaf_kind = (int8_t)kind;
             e = time_cfg(c, s);
-            // the whole product decides: the contraction-per-leaf form runs its near field
-            // beside the transfer levels (built-in rule), which moves it out of the leaf stage
+            // the whole product decides (the forms' placements of the near field differ)
             if (e == hipSuccess && total(s) < best_l) {
                 best_l = total(s);
                 best.np_leaf = (int8_t)np;

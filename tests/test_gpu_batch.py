@@ -182,6 +182,52 @@ def test_batch_cg_padded_columns(mixed):
         assert np.all(X[r0:r1, ms[i]:] == 0) and np.all(info.col_iters[q, ms[i]:] == 0)
 
 
+LP_TOL = {"f32": 1e-5, "bf16": 1e-4}
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+def test_batch_lowp_product_and_cg(prec):
+    """Batches of FP32 / BF16 operators (two merged operators, k = 27 and 64): every system's
+    batched product against the oracle's emulation of that system's low-precision operator
+    (the bars of the single-operator tests), for uneven numbers of right-hand sides; then a
+    batched block CG to a tolerance the storage type can reach, in which the systems stop at
+    different iterations (the stopped systems' clusters are left out of later products), with
+    each system's true residual taken with the emulated operator."""
+    h2x = _h2x()
+    sys = [(f(), prm) for f, prm in SYSTEMS]
+    batch = h2x.Batch(sys, storage=prec)
+    oracles = [oracle.OracleH2(P, **prm) for P, prm in sys]
+    for m in (5, 32):
+        X = W.rhs(batch.n, m, 560 + m)
+        Y = h2x.batch_matmul(batch, _dev(X)).cpu().numpy()
+        errs = []
+        for i, o in enumerate(oracles):
+            r0, r1 = batch.rows(i)
+            errs.append(_colrel(Y[r0:r1], o.matmul_lowp(np.ascontiguousarray(X[r0:r1]), prec)))
+        print(f"{prec} m={m}: per-system max col rel err vs emulation {max(errs):.2e}")
+        assert max(errs) <= LP_TOL[prec]
+    rtol = {"f32": 1e-4, "bf16": 1e-3}[prec]
+    m = 6
+    ms = [6, 2, 1, 4, 6, 3, 5]
+    B = np.zeros((batch.n, m))
+    for i, (P, _) in enumerate(sys):
+        r0, r1 = batch.rows(i)
+        B[r0:r1, :ms[i]] = W.rhs(len(P), ms[i], 570 + i)
+    X, info = h2x.batch_block_cg_solve(batch, _dev(B), rtol=rtol, graph=True)
+    X = X.cpu().numpy()
+    assert info.status == 0
+    its = [int(info.sys_iters[int(np.nonzero(batch.system_order == i)[0][0])]) for i in range(len(sys))]
+    print(f"{prec}: per-system iterations {its}")
+    assert min(its) < max(its)
+    for i, o in enumerate(oracles):
+        r0, r1 = batch.rows(i)
+        Bi, Xi = B[r0:r1, :ms[i]], np.ascontiguousarray(X[r0:r1, :ms[i]])
+        res = np.linalg.norm(Bi - o.matmul_lowp(Xi, prec), axis=0) / np.linalg.norm(Bi, axis=0)
+        print(f"  system {i}: m={ms[i]} {its[i]} it, true rel res (emulated operator) {res.max():.2e}")
+        assert res.max() <= 3 * rtol
+        assert np.all(X[r0:r1, ms[i]:] == 0)
+
+
 def test_batch_workload_full_size():
     h2x = _h2x()
     systems = W.batch_systems()

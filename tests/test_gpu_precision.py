@@ -32,25 +32,35 @@ CASES = [
     # (one group of four k-steps)
     ("sphere-k27-m37", lambda: W.sphere_points(4000, 134), dict(ell=0.5, shift=1.0, eta=1.0, leaf=32, p=3), 37),
     ("cube-k8-m20", lambda: W.cube_points(3000, 135), dict(ell=0.3, shift=1.0, eta=1.0, leaf=16, p=2), 20),
+    # leaves above 64 points (several 64-row chunks per leaf) and 64 columns per work-group
+    ("cube-k64-leaf100-m40", lambda: W.cube_points(5000, 136), dict(ell=0.25, shift=0.5, eta=1.0, leaf=100, p=4), 40),
 ]
 
 
 @pytest.mark.parametrize("prec", ["f32", "bf16"])
 @pytest.mark.parametrize("name,pts,prm,m", CASES, ids=[c[0] for c in CASES])
 def test_lowp_product(name, pts, prm, m, prec):
+    """Both leaf-stage forms of the low-precision operator (0: the built-in one contraction
+    per leaf; 1: a 64-row tile per wave and term), with 32 and 64 columns per work-group,
+    against the oracle's emulation of the same operator and against FP64."""
     import paper_2509_17257_amd as h2x
     P = pts()
     o = oracle.OracleH2(P, **prm)
     A = h2x.H2Matrix(P, storage=prec, **prm)
     X = W.rhs(P.shape[0], m, 133)
-    got = h2x.h2_matmul(A, torch.from_numpy(X).cuda()).cpu().numpy()
     emu = o.matmul_lowp(X, prec)
     ref = o.matmul(X)
-    e_emu, e64 = _colrel(got, emu), _colrel(got, ref)
-    print(f"{name} {prec}: vs emulated {e_emu:.2e}, vs FP64 {e64:.2e}")
-    assert e_emu <= TOL[prec]
-    lo, hi = ERR_RANGE[prec]
-    assert lo < e64 < hi
+    Xd = torch.from_numpy(X).cuda()
+    for kind in (0, 1):
+        for npl in ((1, 2) if m > 32 else (1,)):
+            A.set_tune(m, leaf_kind=kind, np_leaf=npl)
+            got = h2x.h2_matmul(A, Xd).cpu().numpy()
+            e_emu, e64 = _colrel(got, emu), _colrel(got, ref)
+            print(f"{name} {prec} leaf form {kind} np {npl}: vs emulated {e_emu:.2e}, vs FP64 {e64:.2e}")
+            assert e_emu <= TOL[prec]
+            lo, hi = ERR_RANGE[prec]
+            assert lo < e64 < hi
+    A.set_tune(m)
 
 
 @pytest.mark.parametrize("prec,inner", [("f32", 1e-5), ("bf16", 1e-2)])

@@ -182,17 +182,30 @@ def test_batch_cg_padded_columns(mixed):
         assert np.all(X[r0:r1, ms[i]:] == 0) and np.all(info.col_iters[q, ms[i]:] == 0)
 
 
-LP_TOL = {"f32": 1e-5, "bf16": 1e-4}
+def _colrel_all(a, b):
+    den = np.linalg.norm(b, axis=0)
+    den[den == 0] = 1.0
+    return np.linalg.norm(a - b, axis=0) / den
 
 
 @pytest.mark.parametrize("prec", ["f32", "bf16"])
 def test_batch_lowp_product_and_cg(prec):
     """Batches of FP32 / BF16 operators (two merged operators, k = 27 and 64): every system's
-    batched product against the oracle's emulation of that system's low-precision operator
-    (the bars of the single-operator tests), for uneven numbers of right-hand sides; then a
-    batched block CG to a tolerance the storage type can reach, in which the systems stop at
-    different iterations (the stopped systems' clusters are left out of later products), with
-    each system's true residual taken with the emulated operator."""
+    batched product against the oracle's emulation of that system's low-precision operator,
+    for uneven numbers of right-hand sides; then (FP32) a batched block CG in which the systems
+    stop at different iterations (the stopped systems' clusters are left out of later
+    products), with each system's true residual taken with the emulated operator.  The BF16
+    operator rounds its intermediates to BF16, so it is linear only to about its own 1e-2
+    error: a CG run with it cannot bring a true residual below that level, whatever the
+    recursive residual says, and the solve is not checked here (the FP32 solve runs the same
+    batched CG code).
+
+    Bars per column: FP32, 1e-5 (two FP32 summation orders). BF16: 1e-5 plus a tenth of the
+    BF16 operator's own error against FP64 in that column.  The two sides form every FP32
+    intermediate in a different order before rounding it to BF16 where it meets a stored
+    factor; where the two FP32 values straddle a BF16 rounding boundary the roundings differ
+    by one BF16 unit, so the difference is a small fraction of the error the BF16 roundings
+    themselves make (measured at most 0.04 of it on these systems), not a fixed number."""
     h2x = _h2x()
     sys = [(f(), prm) for f, prm in SYSTEMS]
     batch = h2x.Batch(sys, storage=prec)
@@ -200,13 +213,21 @@ def test_batch_lowp_product_and_cg(prec):
     for m in (5, 32):
         X = W.rhs(batch.n, m, 560 + m)
         Y = h2x.batch_matmul(batch, _dev(X)).cpu().numpy()
-        errs = []
+        worst = 0.0
         for i, o in enumerate(oracles):
             r0, r1 = batch.rows(i)
-            errs.append(_colrel(Y[r0:r1], o.matmul_lowp(np.ascontiguousarray(X[r0:r1]), prec)))
-        print(f"{prec} m={m}: per-system max col rel err vs emulation {max(errs):.2e}")
-        assert max(errs) <= LP_TOL[prec]
-    rtol = {"f32": 1e-4, "bf16": 1e-3}[prec]
+            Xi = np.ascontiguousarray(X[r0:r1])
+            emu = o.matmul_lowp(Xi, prec)
+            e = _colrel_all(Y[r0:r1], emu)
+            bar = np.full(m, 1e-5)
+            if prec == "bf16":
+                bar = bar + 0.1 * _colrel_all(emu, o.matmul(Xi))
+            worst = max(worst, float((e / bar).max()))
+            assert np.all(e <= bar), (i, e.max())
+        print(f"{prec} m={m}: largest error / bar over systems and columns {worst:.2f}")
+    if prec != "f32":
+        return
+    rtol = 1e-4
     m = 6
     ms = [6, 2, 1, 4, 6, 3, 5]
     B = np.zeros((batch.n, m))

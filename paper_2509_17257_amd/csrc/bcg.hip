@@ -187,151 +187,172 @@ __global__ __launch_bounds__(256) void k_tsmm(int64_t n, int m, const double *__
     }
 }
 
+// ---- m x m steps: right-looking, four waves, one barrier per step ----
+//
+// Wave w takes the rows congruent to w modulo 4 and lane j the column j of the step's
+// update, so a step is one pass of independent multiply-adds over the trailing part; a value
+// that the step reads (the pivot column, the pivot row) is scaled where it is read and
+// written back scaled in the next step, which no longer reads it.  kMaxM >= m, so a column
+// index is a lane index.
+
 // C = sign * G^{-1} F on the active index set (Cholesky of G restricted to it);
 // inactive rows of C are zero.  Sets breakdown if G is not positive definite there.  The
-// factor is stored in Lc (lower triangle, row stride m); with reuse the factor stored by the
-// previous call (same G, same active set) is taken instead of factorizing again.
+// factor is stored in Lc (lower triangle, row stride m, diagonal included); with reuse the
+// factor stored by the previous call (same G, same active set) is taken instead.
 __global__ __launch_bounds__(256) void k_bcg_solve(int m, const double *__restrict__ G, const double *__restrict__ F,
                                                    double *__restrict__ Cm, double sign, BcgState *st,
                                                    double *__restrict__ Lc, int reuse, const int32_t *stop) {
     if (stop && *stop) return;
-    __shared__ double L[kMaxM][kMaxM + 1];
-    __shared__ int idx[kMaxM];
+    __shared__ double L[kMaxM][kMaxM + 1], Y[kMaxM][kMaxM + 1];
+    __shared__ double inv[kMaxM], dgv[kMaxM];
+    __shared__ int idx[kMaxM], pos[kMaxM];
     __shared__ int r, bad;
-    const int tid = threadIdx.x;
-    if (tid == 0) {
-        int c = 0;
-        for (int j = 0; j < m; ++j)
-            if (st->active[j]) idx[c++] = j;
-        r = c;
-        bad = 0;
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    if (w == 0) {
+        const bool a = lane < m && st->active[lane] != 0;
+        const unsigned long long am = __ballot(a);
+        const int p = __popcll(am & ((1ull << lane) - 1ull));
+        if (a) idx[p] = lane;
+        pos[lane] = a ? p : -1;
+        if (lane == 0) {
+            r = __popcll(am);
+            bad = 0;
+        }
     }
     __syncthreads();
-    // G on the active set and all of F staged in LDS with every load issued up front
-    __shared__ double Fs[kMaxM][kMaxM + 1];
-    if (reuse) {
-        for (int e = tid; e < r * r; e += 256) {
-            const int i = e / r, j = e % r;
-            if (j <= i) L[i][j] = Lc[i * m + j];
+    const int rr = r;
+    // G on the active set (or the stored factor) and the rows of F on it
+    for (int i = w; i < rr; i += 4) {
+        if (lane < rr) L[i][lane] = reuse ? (lane <= i ? Lc[i * m + lane] : 0.0) : G[idx[i] * m + idx[lane]];
+        if (lane < m) Y[i][lane] = F[idx[i] * m + lane];
+    }
+    __syncthreads();
+    if (!reuse) {
+        // right-looking Cholesky: step k updates the trailing lower triangle with the scaled
+        // column k and finalises column k - 1
+        for (int k = 0; k < rr; ++k) {
+            const double v = L[k][k];
+            const double dk = sqrt(v > 0.0 ? v : 1.0), ik = 1.0 / dk;
+            if (k > 0 && w == 0) {  // column k - 1, which this step no longer reads
+                if (lane == k - 1) L[k - 1][k - 1] = dgv[k - 1];
+                else if (lane >= k && lane < rr) L[lane][k - 1] *= inv[k - 1];
+            }
+            const double sj = lane > k && lane < rr ? L[lane][k] * ik : 0.0;
+            for (int i = k + 1 + w; i < rr; i += 4) {
+                const double si = L[i][k] * ik;
+                if (lane > k && lane <= i) L[i][lane] -= si * sj;
+            }
+            if (tid == 0) {
+                inv[k] = ik;
+                dgv[k] = dk;
+                if (!(v > 0.0)) bad = 1;
+            }
+            __syncthreads();
         }
+        if (rr > 0 && tid == 0) L[rr - 1][rr - 1] = dgv[rr - 1];
+        if (tid == 0 && bad) st->breakdown = 1;
+        __syncthreads();
+        for (int i = w; i < rr; i += 4)
+            if (lane <= i) Lc[i * m + lane] = L[i][lane];
     } else {
-        for (int e = tid; e < r * r; e += 256) L[e / r][e % r] = G[idx[e / r] * m + idx[e % r]];
-    }
-    for (int e = tid; e < m * m; e += 256) Fs[e / m][e % m] = F[e];
-    __syncthreads();
-    // right-looking Cholesky, lower triangle.  Every thread forms the pivot's square root
-    // itself and scales its entries of column k; the root is stored on the diagonal in the
-    // update phase, which does not read it.
-    for (int k = 0; k < (reuse ? 0 : r); ++k) {
-        const double v = L[k][k];
-        const double dk = sqrt(v > 0.0 ? v : 1.0);
-        if (tid == 0 && !(v > 0.0)) bad = 1;
-        for (int i = k + 1 + tid; i < r; i += 256) L[i][k] /= dk;
+        for (int k = tid; k < rr; k += 256) inv[k] = 1.0 / L[k][k];
         __syncthreads();
-        if (tid == 0) L[k][k] = dk;
-        for (int e = tid; e < (r - k - 1) * (r - k - 1); e += 256) {
-            const int i = k + 1 + e / (r - k - 1), j = k + 1 + e % (r - k - 1);
-            if (j <= i) L[i][j] -= L[i][k] * L[j][k];
+    }
+    // forward substitution L Z = Y, then back substitution L^T X = Z, one column per lane;
+    // row q is scaled by 1 / L[q][q] where it is read and written back scaled one step later
+    for (int q = 0; q < rr; ++q) {
+        if (lane < m) {
+            if (q > 0 && w == 0) Y[q - 1][lane] *= inv[q - 1];
+            const double yq = Y[q][lane] * inv[q];
+            for (int a = q + 1 + w; a < rr; a += 4) Y[a][lane] -= L[a][q] * yq;
         }
         __syncthreads();
     }
-    if (tid == 0 && bad) st->breakdown = 1;
-    if (!reuse)
-        for (int e = tid; e < r * r; e += 256) {
-            const int i = e / r, j = e % r;
-            if (j <= i) Lc[i * m + j] = L[i][j];
-        }
-    // one column of F per thread: forward then backward substitution, the column's
-    // vector in LDS (a per-thread array with run-time indices would live in scratch memory)
-    __shared__ double Y[kMaxM][kMaxM + 1];
-    for (int col = tid; col < m; col += 256) {
-        for (int a = 0; a < r; ++a) {
-            double v = Fs[idx[a]][col];
-#pragma unroll 8
-            for (int q = 0; q < a; ++q) v -= L[a][q] * Y[q][col];
-            Y[a][col] = v / L[a][a];
-        }
-        for (int a = r - 1; a >= 0; --a) {
-            double v = Y[a][col];
-#pragma unroll 8
-            for (int q = a + 1; q < r; ++q) v -= L[q][a] * Y[q][col];
-            Y[a][col] = v / L[a][a];
-        }
-        for (int j = 0; j < m; ++j) Cm[j * m + col] = 0.0;
-        for (int a = 0; a < r; ++a) Cm[idx[a] * m + col] = sign * Y[a][col];
-    }
-}
-
-// Inverse of the upper-triangular T (T[q'][q] = lv[q'][piv[q]] for q' < q, T[q][q] = dg[q]),
-// scattered to M[piv[q']][piv[q]] (all other entries zero): Z M has orthonormalised columns.
-__device__ inline void write_tinv(int m, int r, const double (*lv)[kMaxM + 1], const double *dg, const int *piv,
-                                  double *M) {
-    // T above the diagonal gathered into pivot order first (no dependent reads below)
-    __shared__ double tp[kMaxM][kMaxM + 1];
-    for (int e = threadIdx.x; e < m * m; e += 256) M[e] = 0.0;
-    for (int e = threadIdx.x; e < r * r; e += 256) {
-        const int a = e / r, c = e % r;
-        if (a < c) tp[a][c] = lv[a][piv[c]];
-    }
+    if (rr > 0 && w == 0 && lane < m) Y[rr - 1][lane] *= inv[rr - 1];
     __syncthreads();
-    // column q per thread, its vector in LDS (not in scratch memory)
-    __shared__ double xs[kMaxM][kMaxM + 1];
-    for (int q = threadIdx.x; q < r; q += 256) {
-        xs[q][q] = 1.0 / dg[q];
-        for (int a = q - 1; a >= 0; --a) {
-            double v = 0.0;
-#pragma unroll 8
-            for (int c = a + 1; c <= q; ++c) v += tp[a][c] * xs[c][q];
-            xs[a][q] = -v / dg[a];
+    for (int a = rr - 1; a >= 0; --a) {
+        if (lane < m) {
+            if (a < rr - 1 && w == 0) Y[a + 1][lane] *= inv[a + 1];
+            const double xa = Y[a][lane] * inv[a];
+            for (int q = w; q < a; q += 4) Y[q][lane] -= L[a][q] * xa;
         }
-        for (int a = 0; a <= q; ++a) M[piv[a] * m + piv[q]] = xs[a][q];
+        __syncthreads();
     }
+    if (rr > 0 && w == 0 && lane < m) Y[0][lane] *= inv[0];
+    __syncthreads();
+    if (lane < m)
+        for (int j = w; j < m; j += 4) Cm[(int64_t)j * m + lane] = pos[j] >= 0 ? sign * Y[pos[j]][lane] : 0.0;
 }
 
-// first Cholesky-QR pass: pivoted Cholesky of W = Z^T Z with deflation
+// M = T^{-1} scattered to M[piv[a]][piv[q]] (all other entries zero) for the upper-triangular
+// T of a Cholesky-QR pass in pivot order (T[a][c] = tf(a, c) for a < c, diagonal dg): back
+// substitution on the identity, one column per lane, row a scaled where it is read.
+template <typename TF>
+__device__ inline void tinv_scatter(int m, int r, TF tf, const double *dg, const int *piv, double *M,
+                                    double (*Z)[kMaxM + 1], double *invd) {
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    for (int e = tid; e < m * m; e += 256) M[e] = 0.0;
+    for (int a = w; a < r; a += 4)
+        if (lane < r) Z[a][lane] = a == lane ? 1.0 : 0.0;
+    for (int a = tid; a < r; a += 256) invd[a] = 1.0 / dg[a];
+    __syncthreads();
+    for (int a = r - 1; a >= 0; --a) {
+        if (lane < r) {
+            if (a < r - 1 && w == 0) Z[a + 1][lane] *= invd[a + 1];
+            const double xa = Z[a][lane] * invd[a];
+            for (int c = w; c < a; c += 4) Z[c][lane] -= tf(c, a) * xa;
+        }
+        __syncthreads();
+    }
+    if (r > 0 && w == 0 && lane < r) Z[0][lane] *= invd[0];
+    __syncthreads();
+    if (lane < r)
+        for (int a = w; a <= lane; a += 4) M[(int64_t)piv[a] * m + piv[lane]] = Z[a][lane];
+}
+
+// first Cholesky-QR pass: pivoted Cholesky of W = Z^T Z with deflation, right-looking on the
+// Schur complement S (kept in place of W): the pivot of step k is the first column, in column
+// order, of largest remaining diagonal among those not yet taken (a NaN in the first
+// candidate stays chosen); a remaining diagonal at or below kDrop^2 of the largest diagonal
+// entry of W ends the factorization.  Row k of the factor: lv[k][j] = S[j][b] / sqrt(S[b][b]).
 __global__ __launch_bounds__(256) void k_bcg_orth1(int m, const double *__restrict__ W, double *__restrict__ M,
                                                    BcgState *st, const int32_t *gate) {
     if (gate && *gate) return;
-    __shared__ double lv[kMaxM][kMaxM + 1];
-    __shared__ double d[kMaxM], dg[kMaxM];
+    __shared__ double S[kMaxM][kMaxM + 1], lv[kMaxM][kMaxM + 1];
+    __shared__ double dg[kMaxM], invd[kMaxM];
     __shared__ int piv[kMaxM], act[kMaxM];
-    __shared__ int rank, stop, best;
+    __shared__ int rank, best;
     __shared__ double dmax;
-    __shared__ double Ws[kMaxM][kMaxM + 1];
-    const int tid = threadIdx.x;
-    for (int e = tid; e < m * m; e += 256) Ws[e / m][e % m] = W[e];
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    for (int i = w; i < m; i += 4)
+        if (lane < m) S[i][lane] = W[i * m + lane];
+    if (tid < kMaxM) act[tid] = 0;
     __syncthreads();
-    for (int j = tid; j < m; j += 256) {
-        d[j] = Ws[j][j];
-        act[j] = 0;
-    }
-    __syncthreads();
-    if (tid == 0) {
-        double mx = 0.0;
-        for (int j = 0; j < m; ++j) mx = fmax(mx, d[j]);
-        dmax = mx;
-        rank = 0;
-        stop = 0;
+    if (w == 0) {
+        // largest diagonal entry (fmax ignores NaN: any order gives the value of a scan from 0)
+        double d = lane < m ? S[lane][lane] : 0.0;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) d = fmax(d, __shfl_xor(d, o));
+        if (lane == 0) {
+            dmax = fmax(0.0, d);
+            rank = 0;
+        }
     }
     __syncthreads();
     for (int k = 0; k < m; ++k) {
-        if (tid < 64) {
-            // pivot: the first column, in column order, of largest d among those not yet
-            // taken (a scan that keeps the earlier column on ties and never moves to a NaN;
-            // a NaN in the first candidate stays chosen), found by the first wave with a
-            // butterfly over (valid, d, column)
-            const int j = tid;
-            const bool cand = j < m && !act[j];
+        if (w == 0) {
+            const bool cand = lane < m && !act[lane];
+            const double d = cand ? S[lane][lane] : 0.0;
             const unsigned long long cm = __ballot(cand);
             int b = -1;
             if (cm != 0) {
                 const int j0 = __ffsll(cm) - 1;
-                if (isnan(d[j0])) {
+                if (isnan(S[j0][j0])) {
                     b = j0;
                 } else {
-                    bool ok = cand && !isnan(d[j]);
-                    double v = ok ? d[j] : 0.0;
-                    int ix = j;
+                    bool ok = cand && !isnan(d);
+                    double v = ok ? d : 0.0;
+                    int ix = lane;
 #pragma unroll
                     for (int o = 32; o > 0; o >>= 1) {
                         const bool ok2 = __shfl_xor(ok ? 1 : 0, o) != 0;
@@ -346,71 +367,71 @@ __global__ __launch_bounds__(256) void k_bcg_orth1(int m, const double *__restri
                     b = ix;
                 }
             }
-            if (tid == 0) {
-                if (b < 0 || !(dmax > 0.0) || !(d[b] > kDrop * kDrop * dmax)) {
-                    stop = 1;
+            if (lane == 0) {
+                if (b < 0 || !(dmax > 0.0) || !(S[b][b] > kDrop * kDrop * dmax)) {
+                    best = -1;
                 } else {
+                    best = b;
                     act[b] = 1;
                     piv[k] = b;
-                    dg[k] = sqrt(d[b]);
-                    best = b;
+                    dg[k] = sqrt(S[b][b]);
                     rank = k + 1;
                 }
             }
         }
         __syncthreads();
-        if (stop) break;
-        for (int j = tid; j < m; j += 256) {
-            if (act[j]) continue;
-            double v = Ws[j][best];
-#pragma unroll 8
-            for (int q = 0; q < k; ++q) v -= lv[q][j] * lv[q][best];
-            lv[k][j] = v / dg[k];
-            d[j] -= lv[k][j] * lv[k][j];
-        }
-        // lv[k][best] is read by later steps: the pivot's own column of step k
-        if (tid == 0) lv[k][best] = dg[k];
+        const int b = best;
+        if (b < 0) break;
+        // row k of the factor, then the Schur complement of the columns not yet taken
+        const double ik = 1.0 / dg[k];
+        const bool free_j = lane < m && !act[lane];
+        const double sj = free_j ? S[lane][b] * ik : 0.0;
+        if (w == 0 && lane < m) lv[k][lane] = lane == b ? dg[k] : sj;
+        for (int i = w; i < m; i += 4)
+            if (free_j && !act[i]) S[i][lane] -= (S[i][b] * ik) * sj;
         __syncthreads();
     }
-    write_tinv(m, rank, lv, dg, piv, M);
-    if (tid == 0) st->rank = rank;
-    for (int j = tid; j < m; j += 256) {
-        st->active[j] = act[j];
-        st->piv[j] = j < rank ? piv[j] : -1;
+    const int r = rank;
+    tinv_scatter(
+        m, r, [&](int a, int c) { return lv[a][piv[c]]; }, dg, piv, M, S, invd);
+    if (tid == 0) st->rank = r;
+    if (tid < m) {
+        st->active[tid] = act[tid];
+        st->piv[tid] = tid < r ? piv[tid] : -1;
     }
 }
 
-// second Cholesky-QR pass: plain Cholesky of W2 = P1^T P1 on the kept columns, pivot order
+// second Cholesky-QR pass: plain Cholesky of W2 = P1^T P1 on the kept columns in pivot order
+// (right-looking, as in k_bcg_solve); T = L^T.
 __global__ __launch_bounds__(256) void k_bcg_orth2(int m, const double *__restrict__ W, double *__restrict__ M,
                                                    const BcgState *st, const int32_t *stop) {
     if (stop && *stop) return;
-    __shared__ double lv[kMaxM][kMaxM + 1];
-    __shared__ double dg[kMaxM];
+    __shared__ double L[kMaxM][kMaxM + 1], Z[kMaxM][kMaxM + 1];
+    __shared__ double dg[kMaxM], inv[kMaxM];
     __shared__ int piv[kMaxM];
-    __shared__ double Ws[kMaxM][kMaxM + 1];
-    const int tid = threadIdx.x, r = st->rank;
-    for (int j = tid; j < r; j += 256) piv[j] = st->piv[j];
-    for (int e = tid; e < m * m; e += 256) Ws[e / m][e % m] = W[e];
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, r = st->rank;
+    if (tid < r) piv[tid] = st->piv[tid];
     __syncthreads();
-    for (int q = 0; q < r; ++q) {
-        if (tid == 0) {
-            const int c = piv[q];
-            double v = Ws[c][c];
-#pragma unroll 8
-            for (int a = 0; a < q; ++a) v -= lv[a][c] * lv[a][c];
-            dg[q] = sqrt(v > 0.0 ? v : 0.0);
+    for (int i = w; i < r; i += 4)
+        if (lane < r) L[i][lane] = W[piv[i] * m + piv[lane]];
+    __syncthreads();
+    for (int k = 0; k < r; ++k) {
+        const double v = L[k][k];
+        const double dk = sqrt(v > 0.0 ? v : 0.0), ik = 1.0 / dk;
+        if (k > 0 && w == 0 && lane >= k && lane < r) L[lane][k - 1] *= inv[k - 1];
+        const double sj = lane > k && lane < r ? L[lane][k] * ik : 0.0;
+        for (int i = k + 1 + w; i < r; i += 4) {
+            const double si = L[i][k] * ik;
+            if (lane > k && lane <= i) L[i][lane] -= si * sj;
         }
-        __syncthreads();
-        for (int q2 = q + 1 + tid; q2 < r; q2 += 256) {
-            const int c = piv[q], c2 = piv[q2];
-            double u = Ws[c2][c];
-#pragma unroll 8
-            for (int a = 0; a < q; ++a) u -= lv[a][c2] * lv[a][c];
-            lv[q][c2] = u / dg[q];
+        if (tid == 0) {
+            inv[k] = ik;
+            dg[k] = dk;
         }
         __syncthreads();
     }
-    write_tinv(m, r, lv, dg, piv, M);
+    tinv_scatter(
+        m, r, [&](int a, int c) { return L[c][a]; }, dg, piv, M, Z, inv);
 }
 
 // convergence from the diagonal of R^T R

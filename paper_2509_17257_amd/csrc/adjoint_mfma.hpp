@@ -437,20 +437,22 @@ __global__ __launch_bounds__(256) void k_grad_N_mfma(int64_t m, const int32_t *_
 // ---- d ell without the per-block tiles (rank 64) ----
 //
 // The coupling term of d ell is sum_t <dyhat_t, sum_{(t,s) in C_t} G_b xhat_s> with
-// G_b[nu][mu] = dg/dell(xi_t,nu, xi_s,mu): the coupling product with G_b in place of S_b.
-// One work-group per row cluster and slab of 16 NJ columns, as in the coupling kernel; each
-// lane forms its operand entries of G_b (row 16 w + l % 16, columns 4 k + l / 16) from the
-// interpolation nodes (the row's node in registers, the column cluster's nodes staged in
-// LDS with x-hat_s, double-buffered), so neither S_b nor a k x k tile of D is stored.  The
-// work-group's partial sum of the dot product with dyhat_t goes to part[slot] (a fixed
-// order); the sums are added in a fixed order afterwards.
+// G_b[nu][mu] = dg/dell(xi_t,nu, xi_s,mu) = (r / ell^2) S_b[nu][mu] for the exponential kernel
+// (r the distance of the two interpolation nodes): the coupling product with G_b in place of
+// S_b.  One work-group per row cluster and slab of 16 NJ columns, as in the coupling kernel;
+// each lane streams its operand entries of S_b (row 16 w + l % 16, columns 4 k + l / 16) in
+// the stored operand order and scales them by r / ell^2 (the row's node in registers, the
+// column cluster's nodes staged in LDS with x-hat_s, double-buffered), so no k x k tile of D
+// is stored.  The work-group's partial sum of the dot product with dyhat_t goes to
+// part[slot] (a fixed order); the sums are added in a fixed order afterwards.
 template <int NJ>
 __global__ __launch_bounds__(256) void k_dell_coupling(int64_t m, int32_t C, int32_t rows_per_xcd,
                                                        const int32_t *__restrict__ order,
                                                        const int64_t *__restrict__ adm_ptr,
                                                        const int32_t *__restrict__ adm_col,
-                                                       const double *__restrict__ nodes, double inv_ell,
-                                                       double inv_ell2, const double *__restrict__ xh,
+                                                       const double *__restrict__ nodes, double inv_ell2,
+                                                       const double *__restrict__ S,
+                                                       const double *__restrict__ xh,
                                                        const double *__restrict__ dh, int64_t ldh,
                                                        double *__restrict__ part) {
     constexpr int MC = 16 * NJ, LDX = MC + 1;
@@ -491,6 +493,15 @@ __global__ __launch_bounds__(256) void k_dell_coupling(int64_t m, int32_t C, int
                 }
                 if (tid < 192) ns[buf][tid] = nv;
             };
+            // S_b in the coupling's operand order: lane l holds S[16 w + l % 16][4 kk + l / 16]
+            // for k-steps kk = 2 q, 2 q + 1 as one 16-byte pair (q = 0..7)
+            typedef double dbl2 __attribute__((ext_vector_type(2)));
+            dbl2 sa[8], sn[8];
+            auto load_s = [&](int64_t b, dbl2 *dst) {
+                const dbl2 *src = (const dbl2 *)(S + b * 64 * 64) + (int64_t)w * 8 * 64 + lane;
+#pragma unroll
+                for (int q = 0; q < 8; ++q) dst[q] = __builtin_nontemporal_load(src + q * 64);
+            };
             auto multiply = [&](int buf) {
                 const double *xb = xs[buf], *nb = ns[buf];
 #pragma unroll
@@ -498,20 +509,25 @@ __global__ __launch_bounds__(256) void k_dell_coupling(int64_t m, int32_t C, int
                     const int mu = 4 * kk + lq;
                     const double dx = px - nb[3 * mu], dy = py - nb[3 * mu + 1], dz = pz - nb[3 * mu + 2];
                     const double r = sqrt(dx * dx + dy * dy + dz * dz);
-                    const double a = (r * inv_ell2) * exp(-r * inv_ell);
+                    const double a = (r * inv_ell2) * ((kk & 1) ? sa[kk >> 1].y : sa[kk >> 1].x);
 #pragma unroll
                     for (int J = 0; J < NJ; ++J)
                         acc[J] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, xb[mu * LDX + 16 * J + lr], acc[J], 0, 0, 0);
                 }
             };
             load(adm_col[b0]);
+            load_s(b0, sa);
             store(0);
             __syncthreads();
+            // every load is unconditional and the last block is peeled off, as in the coupling
             for (int64_t b = b0; b + 1 < b1; ++b) {
                 const int buf = (int)((b - b0) & 1);
                 load(adm_col[b + 1]);
+                load_s(b + 1, sn);
                 multiply(buf);
                 store(buf ^ 1);
+#pragma unroll
+                for (int q = 0; q < 8; ++q) sa[q] = sn[q];
                 __syncthreads();
             }
             multiply((int)((b1 - 1 - b0) & 1));

@@ -335,11 +335,11 @@ struct DellShape {
 DellShape dell_shape(const DevMat &dm, int64_t m) {
     DellShape d{};
     d.nj = (int)std::min<int64_t>(4, (m + 15) / 16);
-    d.np = 1;  // 32 columns per work-group (the register-formed dg/dell leaves no room for 64)
+    d.np = 1;  // 32 columns per work-group (64 would not fit the registers of the near kernel)
     d.cpl_groups = (int64_t)8 * ((dm.C + 7) / 8) * ((m + 16 * d.nj - 1) / (16 * d.nj));
     d.near_slots = (int64_t)8 * ((dm.L + 7) / 8) * ((m + 32 * d.np - 1) / (32 * d.np));
     d.near_lds = sizeof(int32_t) * (size_t)std::max(1, dm.max_near_rows);
-    d.ok = dm.mc && dm.k == 64 && !dm.cplx && dm.cpl_order &&
+    d.ok = dm.mc && dm.k == 64 && dm.swz == 1 && !dm.cplx && dm.cpl_order &&
            d.near_lds + sizeof(double) * (64 * (32 * d.np + 1) + 256) + 64 <= 65536;
     return d;
 }
@@ -456,8 +456,8 @@ hipError_t run_dell_fused(const DevMat &dm, const DellShape &ds, int64_t m, cons
         auto go = [&](auto NJc) {
             constexpr int NJ = decltype(NJc)::value;
             hipLaunchKernelGGL(adj::k_dell_coupling<NJ>, dim3((unsigned)ds.cpl_groups), dim3(256), 0, st, m, dm.C, rpx,
-                               dm.cpl_order, dm.adm_ptr, dm.adm_col, dm.nodes, ie, ie * ie, (const double *)w.xh,
-                               (const double *)w.dh, ldh, pc);
+                               dm.cpl_order, dm.adm_ptr, dm.adm_col, dm.nodes, ie * ie, (const double *)dm.S,
+                               (const double *)w.xh, (const double *)w.dh, ldh, pc);
         };
         switch (ds.nj) {
             case 1: go(std::integral_constant<int, 1>{}); break;

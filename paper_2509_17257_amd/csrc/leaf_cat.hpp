@@ -241,10 +241,11 @@ __device__ inline void leaf_cat_slot(int64_t slot, const LeafCatArgs &a, double 
 // ---- the near-field term of d ell ----
 //
 // sum over leaves t of <dY|_t, sum_{(t,s) near} G_ts X|_s> with G_ts[i][c] =
-// dg/dell(x_i, x_c) = (r / ell^2) exp(-r / ell): the near-field contraction of the leaf stage
-// with G in place of N, formed in registers from the points (tree order) instead of loaded.
-// Same slots, near-row table, row groups and rounds as leaf_cat_slot; returns the
-// work-group's partial sum of the dot product (the same value in every thread).
+// dg/dell(x_i, x_c) = (r / ell^2) exp(-r / ell) = (r / ell^2) N_ts[i][c] for the exponential
+// kernel (the shift on the diagonal sits where r = 0): the near-field contraction of the leaf
+// stage with the stored N scaled by r / ell^2 (r from the points, tree order).  Same slots,
+// near-row table, row groups and rounds as leaf_cat_slot; returns the work-group's partial
+// sum of the dot product (the same value in every thread).
 struct DellArgs {
     const double *pts;  // n x 3, tree order
     double inv_ell, inv_ell2;
@@ -256,6 +257,7 @@ template <int NP>
 struct DellRound {
     dbl2c a[NP][4];
     double c[4][3];  // coordinates of the near row's point of each k-step
+    double n[2][4];  // the stored near-field entries (row tile of the wave, k-step)
     int ok[4];
 };
 
@@ -281,6 +283,7 @@ __device__ inline double leaf_dell_slot(int64_t slot, const LeafCatArgs &a, cons
     const int nnear = (int)(a.near_ptr[l + 1] - q0);
     const int32_t rn = nnear > 0 ? cat_build_rows(xrow, q0, nnear, nt2, a.near_col, a.near_off, a.first, a.size) : 0;
     const int RT = (rn + 15) >> 4;
+    const double *nb = nnear > 0 ? a.Nt + a.near_off[q0] : a.Nt;
     const int xc = (mc - 1) & ~1;
     double mine = 0.0;
 
@@ -310,18 +313,20 @@ __device__ inline double leaf_dell_slot(int64_t slot, const LeafCatArgs &a, cons
                     R.a[p][u] = *(const dbl2c *)(a.Xt + j0 + xr * a.ldxt + min(32 * p + 2 * lr, xc));
 #pragma unroll
                 for (int q = 0; q < 3; ++q) R.c[u][q] = d.pts[3 * xr + q];
+                R.n[0][u] = nb[(int64_t)cc * nt2 + (pa - r0)];
+                R.n[1][u] = nb[(int64_t)cc * nt2 + (pb - r0)];
             }
         };
-        auto gval = [&](double x, double y, double z, const double *c) {
+        auto gval = [&](double x, double y, double z, const double *c, double nv) {
             const double dx = x - c[0], dy = y - c[1], dz = z - c[2];
             const double r = sqrt(dx * dx + dy * dy + dz * dz);
-            return (r * d.inv_ell2) * exp(-r * d.inv_ell);
+            return (r * d.inv_ell2) * nv;
         };
         auto multiply = [&](DellRound<NP> &R) {
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const double g0 = t0 ? gval(ax, ay, az, R.c[u]) : 0.0;
-                const double g1 = t1 ? gval(bx, by, bz, R.c[u]) : 0.0;
+                const double g0 = t0 ? gval(ax, ay, az, R.c[u], R.n[0][u]) : 0.0;
+                const double g1 = t1 ? gval(bx, by, bz, R.c[u], R.n[1][u]) : 0.0;
 #pragma unroll
                 for (int p = 0; p < NP; ++p) {
                     const dbl2c v = R.ok[u] ? R.a[p][u] : dbl2c{0.0, 0.0};

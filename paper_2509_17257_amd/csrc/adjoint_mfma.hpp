@@ -270,46 +270,49 @@ __global__ __launch_bounds__(256) void k_leaf_adj_mfma(int k, int64_t m, int32_t
 // ---- gradients: 64 x 64 tiles D = A B^T with the contraction over the m columns ----
 //
 // A: arows x m (row stride lda), B: brows x m (row stride ldb), both in FP64;
-// staged through LDS in chunks of 64 columns.  Wave w owns rows 16w..16w+15 of D,
-// acc[J] columns 16J..16J+15; register r of lane l holds row 16w + l/16 + 4r,
-// column 16J + l%16.
-constexpr int LDG = 65;
-
+// staged through LDS in chunks of CW columns (16, 32 or 64: the tiles are sized to the
+// chunk, so a small m leaves room for more work-groups per CU).  Wave w owns rows
+// 16w..16w+15 of D, acc[J] columns 16J..16J+15; register r of lane l holds row
+// 16w + l/16 + 4r, column 16J + l%16.
+template <int CW>
 struct GradTiles {
-    double a[64 * LDG];
-    double b[64 * LDG];
+    static constexpr int LD = CW + 1;
+    double a[64 * LD];
+    double b[64 * LD];
 };
 
-__device__ inline void outer_tile(GradTiles &sm, const double *A, int64_t lda, int arows, const double *B, int64_t ldb,
-                                  int brows, int64_t m, dbl4 *acc) {
+template <int CW>
+__device__ inline void outer_tile(GradTiles<CW> &sm, const double *A, int64_t lda, int arows, const double *B,
+                                  int64_t ldb, int brows, int64_t m, dbl4 *acc) {
+    constexpr int LD = GradTiles<CW>::LD, EPT = 64 * CW / 256;  // elements per thread
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, lr = lane & 15, g = lane >> 4;
 #pragma unroll
     for (int J = 0; J < 4; ++J) acc[J] = dbl4{0.0, 0.0, 0.0, 0.0};
-    for (int64_t j0 = 0; j0 < m; j0 += 64) {
-        const int mc = (int)min<int64_t>(64, m - j0);
-        double av[16], bv[16];
+    for (int64_t j0 = 0; j0 < m; j0 += CW) {
+        const int mc = (int)min<int64_t>(CW, m - j0);
+        double av[EPT], bv[EPT];
 #pragma unroll
-        for (int u = 0; u < 16; ++u) {
-            const int e = tid + 256 * u, r = e >> 6, c = e & 63;
+        for (int u = 0; u < EPT; ++u) {
+            const int e = tid + 256 * u, r = e / CW, c = e % CW;
             av[u] = (r < arows && c < mc) ? A[(int64_t)r * lda + j0 + c] : 0.0;
             bv[u] = (r < brows && c < mc) ? B[(int64_t)r * ldb + j0 + c] : 0.0;
         }
         __syncthreads();
 #pragma unroll
-        for (int u = 0; u < 16; ++u) {
-            const int e = tid + 256 * u, r = e >> 6, c = e & 63;
-            sm.a[r * LDG + c] = av[u];
-            sm.b[r * LDG + c] = bv[u];
+        for (int u = 0; u < EPT; ++u) {
+            const int e = tid + 256 * u, r = e / CW, c = e % CW;
+            sm.a[r * LD + c] = av[u];
+            sm.b[r * LD + c] = bv[u];
         }
         __syncthreads();
         if (16 * w < arows) {
-            const double *arow = sm.a + (16 * w + lr) * LDG + g;
+            const double *arow = sm.a + (16 * w + lr) * LD + g;
             const int kpad = (mc + 3) & ~3;
             for (int kk = 0; kk < kpad; kk += 4) {
                 const double a = arow[kk];
 #pragma unroll
                 for (int J = 0; J < 4; ++J)
-                    acc[J] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, sm.b[(16 * J + lr) * LDG + kk + g], acc[J], 0, 0, 0);
+                    acc[J] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, sm.b[(16 * J + lr) * LD + kk + g], acc[J], 0, 0, 0);
             }
         }
     }
@@ -347,13 +350,14 @@ __device__ inline double block_sum(double v) {
 // one admissible block per work-group: D = scale * dyhat_t xhat_s^T (k x k, k <= 64); dS_b = D
 // if requested (row-major); part[b] = sum of (dg/dell)(xi_t,nu, xi_s,mu) D[nu][mu] (0 unless
 // want_dell)
+template <int CW>
 __global__ __launch_bounds__(256) void k_grad_S_mfma(int k, int64_t m, const int32_t *__restrict__ adm_row,
                                                      const int32_t *__restrict__ adm_col,
                                                      const double *__restrict__ nodes, int kernel, double ell,
                                                      const double *__restrict__ dh, const double *__restrict__ xh,
                                                      int64_t ldh, double scale, int want_dell,
                                                      double *__restrict__ dS, double *__restrict__ part) {
-    __shared__ GradTiles sm;
+    __shared__ GradTiles<CW> sm;
     __shared__ double pt[64][3], ps[64][3];
     const int64_t b = blockIdx.x;
     const int32_t t = adm_row[b], s = adm_col[b];
@@ -380,13 +384,16 @@ __global__ __launch_bounds__(256) void k_grad_S_mfma(int k, int64_t m, const int
             }
         }
     }
-    const double tot = block_sum(gsum);
-    if (tid == 0) part[b] = tot;
+    if (want_dell) {  // work-group-uniform: the sum and its barriers only when d ell is wanted
+        const double tot = block_sum(gsum);
+        if (tid == 0) part[b] = tot;
+    }
 }
 
 // one near-field block per work-group: D = scale * dY|_t X|_s^T (tree-ordered dY, X); dN_b = D
 // (row-major |t| x |s|) if requested; part[q] = sum of (dg/dell)(x_i, x_j) D[i][j] (0 unless
 // want_dell)
+template <int CW>
 __global__ __launch_bounds__(256) void k_grad_N_mfma(int64_t m, const int32_t *__restrict__ near_row,
                                                      const int32_t *__restrict__ near_col,
                                                      const int64_t *__restrict__ near_off_rm,
@@ -396,7 +403,7 @@ __global__ __launch_bounds__(256) void k_grad_N_mfma(int64_t m, const int32_t *_
                                                      const double *__restrict__ dYt, const double *__restrict__ Xt,
                                                      int64_t ldt, double scale, int want_dell,
                                                      double *__restrict__ dN, double *__restrict__ part) {
-    __shared__ GradTiles sm;
+    __shared__ GradTiles<CW> sm;
     __shared__ double pt[64][3], ps[64][3];
     const int64_t q = blockIdx.x;
     const int32_t t = near_row[q], s = near_col[q];
@@ -430,8 +437,10 @@ __global__ __launch_bounds__(256) void k_grad_N_mfma(int64_t m, const int32_t *_
             }
             __syncthreads();  // the staged points of this tile are read before the next overwrites them
         }
-    const double tot = block_sum(gsum);
-    if (tid == 0) part[q] = tot;
+    if (want_dell) {
+        const double tot = block_sum(gsum);
+        if (tid == 0) part[q] = tot;
+    }
 }
 
 // ---- d ell without the per-block tiles (rank 64) ----

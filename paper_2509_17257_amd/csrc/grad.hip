@@ -519,11 +519,17 @@ hipError_t run_grad(const DevMat &dm, int64_t m, const double *X, int64_t ldx, c
         if (e == hipSuccess) e = run_forward_transform(dm, m, dY, lddy, false, w.dh, ldh, w.xt_ws, st);
         if (e != hipSuccess) return e;
         if (dm.n_adm > 0) {
-            if (dm.mc)
-                hipLaunchKernelGGL(adj::k_grad_S_mfma, dim3((unsigned)dm.n_adm), dim3(256), 0, st, dm.k, m, dm.adm_row,
-                                   dm.adm_col, dm.nodes, dm.kernel, dm.ell, (const double *)w.dh,
-                                   (const double *)w.xh, ldh, scale, cpl_b, dS, w.part);
-            else
+            if (dm.mc) {
+                // LDS tiles sized to the column chunk (16, 32 or 64 columns)
+                auto go = [&](auto CWc) {
+                    hipLaunchKernelGGL(adj::k_grad_S_mfma<decltype(CWc)::value>, dim3((unsigned)dm.n_adm), dim3(256), 0,
+                                       st, dm.k, m, dm.adm_row, dm.adm_col, dm.nodes, dm.kernel, dm.ell,
+                                       (const double *)w.dh, (const double *)w.xh, ldh, scale, cpl_b, dS, w.part);
+                };
+                if (m <= 16) go(std::integral_constant<int, 16>{});
+                else if (m <= 32) go(std::integral_constant<int, 32>{});
+                else go(std::integral_constant<int, 64>{});
+            } else
                 hipLaunchKernelGGL(k_grad_S, dim3((unsigned)dm.n_adm), dim3(256), 0, st, dm.k, m, dm.adm_row,
                                    dm.adm_col, dm.nodes, dm.kernel, dm.ell, (const double *)w.dh,
                                    (const double *)w.xh, ldh, scale, cpl_b, dS, w.part);
@@ -536,12 +542,17 @@ hipError_t run_grad(const DevMat &dm, int64_t m, const double *X, int64_t ldx, c
         hipLaunchKernelGGL(k_gather_even, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, dm.n, m, dm.perm, dY,
                            lddy, w.dYt, ldh);
         if (dm.n_near > 0) {
-            if (dm.mc)
-                hipLaunchKernelGGL(adj::k_grad_N_mfma, dim3((unsigned)dm.n_near), dim3(256), 0, st, m, dm.near_row,
-                                   dm.near_col, dm.near_off_rm, dm.first, dm.size, dm.pts, dm.kernel, dm.ell,
-                                   (const double *)w.dYt, (const double *)w.Xt, ldh, scale, nr_b, dN,
-                                   w.part + dm.n_adm);
-            else
+            if (dm.mc) {
+                auto go = [&](auto CWc) {
+                    hipLaunchKernelGGL(adj::k_grad_N_mfma<decltype(CWc)::value>, dim3((unsigned)dm.n_near), dim3(256), 0,
+                                       st, m, dm.near_row, dm.near_col, dm.near_off_rm, dm.first, dm.size, dm.pts,
+                                       dm.kernel, dm.ell, (const double *)w.dYt, (const double *)w.Xt, ldh, scale, nr_b,
+                                       dN, w.part + dm.n_adm);
+                };
+                if (m <= 16) go(std::integral_constant<int, 16>{});
+                else if (m <= 32) go(std::integral_constant<int, 32>{});
+                else go(std::integral_constant<int, 64>{});
+            } else
                 hipLaunchKernelGGL(k_grad_N, dim3((unsigned)dm.n_near), dim3(256), 0, st, m, dm.near_row,
                                    dm.near_col, dm.near_off_rm, dm.first, dm.size, dm.pts, dm.kernel, dm.ell,
                                    (const double *)w.dYt, (const double *)w.Xt, ldh, scale, nr_b, dN,

@@ -270,11 +270,15 @@ def test_autotune_keeps_results(storage, m):
     torch.cuda.synchronize()
     print(f"{storage} m={m}: {info}")
     assert info["ms_tuned"] <= info["ms_default"] * 1.0001
-    if (info["overlap"] in (0, 5) and info["leaf_kind"] in (0, 3)) or storage != "f64":
+    builtin_form = info["leaf_kind"] in (0, 3) and (storage != "f64" or info["overlap"] in (0, 5))
+    if builtin_form:
         assert torch.equal(before, after)
     else:
+        # another leaf-stage form or near-field placement: the same terms summed in another
+        # order (FP64 sums; FP32 sums for the low-precision operators, whose last stage is the
+        # leaf stage, so no rounding to BF16 follows the changed sums)
         rel = ((after - before).norm(dim=0) / before.norm(dim=0)).max().item()
-        assert rel <= 1e-14
+        assert rel <= (1e-14 if storage == "f64" else 1e-5)
 
 
 def test_stage_timer():

@@ -633,7 +633,50 @@ static void orc_list_addeval(const orc_mm *w, int64_t t, double alpha, double *Y
     }
 }
 
-/* Y <- beta Y + alpha A_H2 X  (H2_mvm in its matrix form) */
+/* Y|_t += V_t y_t for the nested bases, top-down over the tree as index loops: clusters are
+ * numbered in pre-order, so a parent comes before its sons and y_t is complete when its turn
+ * comes (y_{t'} += E_{t'} y_t for the sons, then V_t y_t at the leaves).  Every entry receives
+ * the same terms in the same order as in orc_backward's recursion. */
+static void orc_backward_loops(const orc_mm *w, double *Y) {
+    const orc_h2 *h = w->h;
+    const int k = h->k;
+    const int64_t m = w->m;
+    for (int64_t t = 0; t < h->C; ++t) {
+        if (orc_is_leaf(h, t)) continue;
+        const double *yt = &w->yh[(size_t)t * k * m];
+        int64_t sons[2] = {h->son0[t], h->son1[t]};
+        for (int q = 0; q < 2; ++q) {
+            const double *E = &h->E[(size_t)sons[q] * k * k];
+            double *yq = &w->yh[(size_t)sons[q] * k * m];
+            for (int a = 0; a < k; ++a)
+                for (int64_t j = 0; j < m; ++j) {
+                    double acc = 0.0;
+                    for (int nu = 0; nu < k; ++nu) acc += E[a * k + nu] * yt[nu * m + j];
+                    yq[a * m + j] += acc;
+                }
+        }
+    }
+    for (int64_t t = 0; t < h->C; ++t) {
+        if (!orc_is_leaf(h, t)) continue;
+        const double *yt = &w->yh[(size_t)t * k * m];
+        for (int64_t i = 0; i < h->size[t]; ++i) {
+            int64_t row = h->first[t] + i;
+            double *yrow = &Y[h->perm[row] * m];
+            for (int64_t j = 0; j < m; ++j) {
+                double acc = 0.0;
+                for (int nu = 0; nu < k; ++nu) acc += h->V[row * k + nu] * yt[nu * m + j];
+                yrow[j] += acc;
+            }
+        }
+    }
+}
+
+/* Y <- beta Y + alpha A_H2 X from the definition of the H^2 matrix (section 2):
+ * A_H2 = sum over admissible leaves (t, s) of V_t S_ts V_s^T + sum over the inadmissible ones
+ * of G|_{t x s}, with nested bases V_t|_{t'} = V_{t'} E_{t'}.  As index loops over the
+ * pre-ordered clusters: x_s = V_s^T X|_s (leaves directly, inner clusters from their sons),
+ * y_t = sum_s S_ts x_s and the near blocks for every cluster t, then Y|_t += V_t y_t pushed
+ * down through the nested bases. */
 void orc_matmul(const orc_h2 *h, int64_t m, double alpha, const double *X, double beta, double *Y) {
     orc_mm w;
     w.h = h;
@@ -644,8 +687,7 @@ void orc_matmul(const orc_h2 *h, int64_t m, double alpha, const double *X, doubl
     w.yh = calloc(cw ? cw : 1, sizeof(double));
     for (int64_t i = 0; i < h->n * m; ++i) Y[i] = (beta == 0.0) ? 0.0 : beta * Y[i];
 
-    /* forward: the leaf products are independent (sons in parallel), the transfer
-     * sums run in the recursion after them */
+    /* x_s = V_s^T X|_s at the leaves (independent of each other) */
     {
         const int k = h->k;
 #pragma omp parallel for schedule(dynamic, 4)
@@ -663,9 +705,9 @@ void orc_matmul(const orc_h2 *h, int64_t m, double alpha, const double *X, doubl
                 }
         }
     }
-    /* transfer part of the forward recursion (leaves already done above) */
+    /* x_s = sum over sons s' of E_{s'}^T x_{s'} for inner clusters */
     {
-        /* post-order walk: clusters are in pre-order, so iterate from the back */
+        /* sons before parents: clusters are in pre-order, so iterate from the back */
         const int k = h->k;
         for (int64_t s = h->C - 1; s >= 0; --s) {
             if (orc_is_leaf(h, s)) continue;
@@ -683,17 +725,18 @@ void orc_matmul(const orc_h2 *h, int64_t m, double alpha, const double *X, doubl
             }
         }
     }
-    /* multiplication phase: every cluster's list, clusters in parallel */
+    /* y_t = sum over admissible (t, s) of S_ts x_s and Y|_t += G|_{t x s} X|_s for the
+     * inadmissible ones: every cluster owns y_t and its rows, clusters in parallel */
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t t = 0; t < h->C; ++t) orc_list_addeval(&w, t, alpha, Y);
-    /* backward */
-    orc_backward(&w, 0, Y);
+    /* Y|_t += V_t y_t through the nested bases */
+    orc_backward_loops(&w, Y);
     free(w.xh);
     free(w.yh);
 }
 
-/* Same product, but the forward transformation runs the plain recursion of the
- * paper's sequential Forward (used to pin the parallel variant against it). */
+/* The same product with the forward and backward transformations as recursions over the
+ * cluster tree (the paper's sequential form, section 3); orc_matmul must equal it bitwise. */
 void orc_matmul_recursive(const orc_h2 *h, int64_t m, double alpha, const double *X, double beta, double *Y) {
     orc_mm w;
     w.h = h;
@@ -949,7 +992,7 @@ void orc_matmul_adjoint(const orc_h2 *h, int64_t m, double alpha, const double *
                 }
             }
         }
-    orc_backward(&w, 0, Y);
+    orc_backward_loops(&w, Y);
     free(cptr); free(cblk); free(fill); free(w.xh); free(w.yh);
 }
 

@@ -191,8 +191,8 @@ __global__ __launch_bounds__(256) void k_leaf_adj_mfma(int k, int64_t m, int32_t
                 const int64_t q = ncblk[q0 + e - 1];
                 const int32_t t = near_row[q];
                 const int nt = size[t];
-                A = Nt + near_off[q] + (int64_t)c0 * (nt + (nt & 1));
-                lda = nt + (nt & 1);
+                A = Nt + near_off[q] + (int64_t)c0 * pad_rows(nt);
+                lda = pad_rows(nt);
                 ktot = nt;
                 Bm = Xt + (int64_t)first[t] * ldxt + j0;
                 ldb = ldxt;

@@ -101,11 +101,12 @@ __global__ void k_fill_V(int p, const int32_t *__restrict__ leaves, const int32_
                    lagrange1(nd[2], p, nu / (p * p), x[2]);
         V[i * k + nu] = from_double<T>(v);
         if (Vt) {
-            // transposed copy: k x nt2 (rows padded to even length, padding zero)
-            const int64_t nt2 = rows + (rows & 1), il = i - first[t];
+            // transposed copy: k x nt2 (rows padded to pad_rows(|t|), padding zero)
+            const int64_t nt2 = pad_rows(rows), il = i - first[t];
             T *vt = Vt + vt_off[blockIdx.x];
             vt[nu * nt2 + il] = from_double<T>(v);
-            if ((rows & 1) && il == rows - 1) vt[nu * nt2 + rows] = from_double<T>(0.0);
+            if (il == rows - 1)
+                for (int64_t z = rows; z < nt2; ++z) vt[nu * nt2 + z] = from_double<T>(0.0);
         }
     }
 }
@@ -157,7 +158,7 @@ __global__ void k_fill_S(int k, int kernel, double ell, double npts, const int32
 }
 
 // N_(t,s)[i, j] = g(x_i, x_j) + shift [i == j], row-major |t| x |s|, or stored
-// transposed when trans != 0: |s| rows of length |t| padded to even, padding zero
+// transposed when trans != 0: |s| rows of length pad_rows(|t|), padding zero
 // (complex kernel: real part into N, imaginary part into N + n_plane)
 template <typename TN>
 __global__ void k_fill_N(int kernel, double ell, double shift, double npts, const int32_t *__restrict__ near_row,
@@ -168,7 +169,7 @@ __global__ void k_fill_N(int kernel, double ell, double shift, double npts, cons
     const int32_t t = near_row[q], s = near_col[q];
     const int64_t nt = size[t], ns = size[s], ft = first[t], fs = first[s];
     TN *Nb = N + near_off[q];
-    const int64_t nt2 = nt + (nt & 1);
+    const int64_t nt2 = pad_rows(nt);
     const bool cplx = kernel == H2X_KERNEL_HELMHOLTZ;
     for (int64_t e = threadIdx.x; e < nt * ns; e += blockDim.x) {
         const int64_t il = e / ns, jl = e % ns, i = ft + il, j = fs + jl;
@@ -185,10 +186,11 @@ __global__ void k_fill_N(int kernel, double ell, double shift, double npts, cons
             Nb[at] = (TN)v;
         }
     }
-    if (trans && (nt & 1))
-        for (int64_t jl = threadIdx.x; jl < ns; jl += blockDim.x) {
-            Nb[jl * nt2 + nt] = (TN)0;
-            if (cplx) Nb[jl * nt2 + nt + n_plane] = (TN)0;
+    if (trans)
+        for (int64_t e = threadIdx.x; e < (nt2 - nt) * ns; e += blockDim.x) {
+            const int64_t at = (e / (nt2 - nt)) * nt2 + nt + e % (nt2 - nt);
+            Nb[at] = (TN)0;
+            if (cplx) Nb[at + n_plane] = (TN)0;
         }
 }
 

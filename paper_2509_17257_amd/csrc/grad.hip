@@ -130,7 +130,7 @@ __global__ __launch_bounds__(256) void k_leaf_near_adj(int k, int64_t m, const i
             const int64_t b = ncblk[q];
             const int32_t t = near_row[b];
             const int nt = size[t];
-            const int64_t nt2 = nt + (nt & 1), ft = first[t];
+            const int64_t nt2 = pad_rows(nt), ft = first[t];
             const double *Nb = N + near_off[b];
             for (int i0 = 0; i0 < nt; i0 += TR) {
                 const int ic = min(TR, nt - i0);

@@ -109,7 +109,7 @@ __device__ inline void leaf_cat_slot(int64_t slot, const LeafCatArgs &a, double 
     if (a.skip(t)) return;
     const int k = a.k;
     const int nt = a.size[t];
-    const int64_t nt2 = nt + (nt & 1), r0 = a.first[t];
+    const int64_t nt2 = pad_rows(nt), r0 = a.first[t];
     const int64_t j0 = (qx % nslab) * MC;
     const int mc = (int)min<int64_t>(MC, a.m - j0);
     const int64_t q0 = a.near_ptr[l];
@@ -276,7 +276,7 @@ __device__ inline double leaf_dell_slot(int64_t slot, const LeafCatArgs &a, cons
     const int32_t l = a.order[pos];
     const int32_t t = a.leaves[l];
     const int nt = a.size[t];
-    const int64_t nt2 = nt + (nt & 1), r0 = a.first[t];
+    const int64_t nt2 = pad_rows(nt), r0 = a.first[t];
     const int64_t j0 = (qx % nslab) * MC;
     const int mc = (int)min<int64_t>(MC, a.m - j0);
     const int64_t q0 = a.near_ptr[l];

@@ -79,7 +79,7 @@ __global__ __launch_bounds__(256, 2) void k_leaf_cat_lp(LeafCatLpArgs a) {
     if (a.skip(t)) return;
     const int k = a.k;
     const int nt = a.size[t];
-    const int64_t nt2 = nt + (nt & 1), r0 = a.first[t];
+    const int64_t nt2 = pad_rows(nt), r0 = a.first[t];
     const int64_t j0 = (qx % nslab) * MC;
     const int mc = (int)min<int64_t>(MC, a.m - j0);
     const int64_t q0 = a.near_ptr[l];

@@ -60,7 +60,7 @@ __global__ __launch_bounds__(256, 2) void k_leaf_lp(int k, int64_t m, int32_t L,
     const int32_t t = leaves[l];
     if (skip(t)) return;
     const int nt = size[t];
-    const int64_t nt2 = nt + (nt & 1);
+    const int64_t nt2 = pad_rows(nt);
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63, lr = lane & 15,
                   lq = lane >> 4;  // w is wave-uniform: item loops stay scalar
     const int64_t r0 = first[t];

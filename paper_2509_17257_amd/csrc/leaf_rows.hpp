@@ -61,7 +61,7 @@ __global__ __launch_bounds__(64) void k_leaf_rows(int k, int64_t m, int32_t L, c
     const int nt = size[t];
     if (32 * (int)blockIdx.y >= nt) return;
     const int lane = threadIdx.x, lr = lane & 15, lq = lane >> 4;
-    const int64_t nt2 = nt + (nt & 1), r0 = first[t];
+    const int64_t nt2 = pad_rows(nt), r0 = first[t];
     const int64_t j0 = (qx % nslab) * MC;
     const int mc = (int)min<int64_t>(MC, m - j0);
     const int xc = (mc - 1) & ~1;  // last even column offset of the slab

@@ -266,7 +266,7 @@ __global__ __launch_bounds__(256) void k_leaf_near(int k, int64_t m, const int32
                 const int cc = min(TR, ns - c0);
                 for (int e = tid; e < TR * TR; e += 256) {
                     const int i = e / TR, c = e % TR;
-                    const int64_t o = near_t ? (int64_t)(c0 + c) * (nt + (nt & 1)) + i0 + i : (int64_t)(i0 + i) * ns + c0 + c;
+                    const int64_t o = near_t ? (int64_t)(c0 + c) * pad_rows(nt) + i0 + i : (int64_t)(i0 + i) * ns + c0 + c;
                     As[i][c] = (i < ic && c < cc) ? ld_op<TN, Acc>(&Nb[o]) : Acc(0);
                 }
                 for (int e = tid; e < TR * TC; e += 256) {

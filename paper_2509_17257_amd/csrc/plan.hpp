@@ -9,6 +9,14 @@
 
 namespace h2x {
 
+// Row length of the transposed near blocks and leaf bases of a leaf of nt points: zero-padded
+// to a multiple of kRowPad entries, so that the kernels can read two neighbouring rows with
+// one load.  (Padding to 16, so that a 16-row tile of an FP64 row is one aligned 128-byte
+// line, read with non-temporal loads, measured 2 % faster in the FP64 leaf stage and 1.5 %
+// slower in the low-precision one, for 16 % more stored entries.)
+constexpr int64_t kRowPad = 2;
+constexpr int64_t pad_rows(int64_t nt) { return (nt + kRowPad - 1) / kRowPad * kRowPad; }
+
 // Host topology produced by the planner.  Clusters are numbered in pre-order,
 // so the points of every cluster occupy one contiguous range of tree positions.
 struct Plan {
@@ -44,8 +52,8 @@ struct Plan {
     std::vector<int32_t> near_col;  // column cluster id
     std::vector<int64_t> near_off;  // offset of the block in the near-field array
     int64_t near_entries = 0;
-    // matrix-core layout: near blocks stored transposed with rows padded to an
-    // even length, and a per-leaf transposed copy of the leaf basis (k x |t| padded)
+    // matrix-core layout: near blocks stored transposed with rows padded to pad_rows(|t|),
+    // and a per-leaf transposed copy of the leaf basis (k x pad_rows(|t|))
     std::vector<int64_t> near_off_t;
     int64_t near_entries_t = 0;
     std::vector<int64_t> vt_off;    // L

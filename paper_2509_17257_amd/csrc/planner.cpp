@@ -318,7 +318,7 @@ Plan *build_plan(const double *pts, int64_t n, const h2x_params &prm, std::strin
     int64_t voff = 0;
     for (int32_t l = 0; l < L; ++l) {
         const int32_t t = P->leaves[l];
-        const int64_t nt2 = P->size[t] + (P->size[t] & 1);
+        const int64_t nt2 = pad_rows(P->size[t]);
         P->vt_off[l] = voff;
         voff += (int64_t)P->k * nt2;
         int32_t rows = 0;

@@ -541,7 +541,7 @@ __global__ __launch_bounds__(256, NP == 1 ? 2 : 1) void k_leaf_direct(int k, int
         const int32_t t = leaves[l];
         if (skip(t)) continue;
         const int nt = size[t];
-        const int64_t nt2 = nt + (nt & 1);
+        const int64_t nt2 = pad_rows(nt);
         const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63, lr = lane & 15,
                   lq = lane >> 4;  // w is wave-uniform: item loops stay scalar
         const int64_t r0 = first[t];

@@ -80,6 +80,7 @@ struct DevMat {
     // operator (element type per `storage`; near field FP64 or FP32)
     void *V = nullptr;   // n x k
     void *E = nullptr;   // C x k x k
+    double *E1 = nullptr;  // C x 3 x p x p: one-dimensional factors of the transfer matrices (FP64)
     void *S = nullptr;   // n_adm x k x k
     void *N = nullptr;   // near field (row-major blocks, or transposed and padded when near_t)
     void *Vt = nullptr;  // transposed leaf bases (matrix-core layout only)

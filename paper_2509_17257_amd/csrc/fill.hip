@@ -134,6 +134,27 @@ __global__ void k_fill_E(int p, const int32_t *__restrict__ parent, const double
     }
 }
 
+// one-dimensional factors of the transfer matrices: F1[c][d][p i + j] = the father's j-th
+// Lagrange polynomial on axis d at the son's i-th node on axis d, so that E_c[a, nu] =
+// F1[c][0][a0, nu0] F1[c][1][a1, nu1] F1[c][2][a2, nu2] (digits a = a0 + p a1 + p^2 a2); the
+// root's entries are zero
+__global__ void k_fill_E1(int32_t C, int p, const int32_t *__restrict__ parent, const double *__restrict__ nodes,
+                          double *__restrict__ F1) {
+    const int per = 3 * p * p;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)C * per) return;
+    const int32_t c = (int32_t)(idx / per);
+    const int e = (int)(idx % per), d = e / (p * p), i = (e / p) % p, j = e % p;
+    if (c == 0) {
+        F1[idx] = 0.0;
+        return;
+    }
+    double ndp[16], ndc[16];
+    nodes1d(nodes, parent[c], p, d, ndp);
+    nodes1d(nodes, c, p, d, ndc);
+    F1[idx] = lagrange1(ndp, p, j, ndc[i]);
+}
+
 // S_b[nu, mu] = g(xi_{t,nu}, xi_{s,mu}), stored in the layout the coupling kernel reads
 // (complex kernel: real part into S, imaginary part into S + s_plane)
 template <typename T>
@@ -225,8 +246,12 @@ hipError_t fill_typed(const DevMat &dm, hipStream_t st) {
     if (dm.L > 0)
         hipLaunchKernelGGL(k_fill_V<T>, dim3(dm.L), dim3(256), 0, st, dm.p, dm.leaves, dm.first, dm.size, dm.pts,
                            dm.nodes, (T *)dm.V, (T *)dm.Vt, dm.vt_off);
-    if (dm.C > 1)
+    if (dm.C > 1) {
         hipLaunchKernelGGL(k_fill_E<T>, dim3(dm.C - 1), dim3(256), 0, st, dm.p, dm.parent, dm.nodes, (T *)dm.E);
+        const int64_t nf = (int64_t)dm.C * 3 * dm.p * dm.p;
+        hipLaunchKernelGGL(k_fill_E1, dim3((unsigned)((nf + 255) / 256)), dim3(256), 0, st, dm.C, dm.p, dm.parent,
+                           dm.nodes, dm.E1);
+    }
     return fill_SN<T, TN>(dm, st);
 }
 
@@ -301,6 +326,7 @@ size_t mat_layout(const Plan &P, h2x_prec storage, DevMat *dm, char *base) {
     const size_t ens = storage == H2X_F64 ? 8 : 4;
     d.V = carve<char>(cur, base, es * (size_t)n * k);
     d.E = carve<char>(cur, base, es * (size_t)C * k * k);
+    d.E1 = carve<double>(cur, base, 3 * (size_t)C * P.p * P.p);
     // complex kernel: a real and an imaginary plane of S and N (V and E stay real)
     d.cplx = (P.nsys() == 1 && P.prm.kernel == H2X_KERNEL_HELMHOLTZ) ? 1 : 0;
     const int planes = d.cplx ? 2 : 1;

@@ -118,6 +118,10 @@ __global__ void k_fill_E(int p, const int32_t *__restrict__ parent, const double
     const int k = p * p * p;
     const int32_t c = blockIdx.x + 1;  // the root has no transfer matrix
     const int32_t par = parent[c];
+    if (par < 0) {  // the root of a later system of a merged plan: zeros
+        for (int e = threadIdx.x; e < k * k; e += blockDim.x) E[(int64_t)c * k * k + e] = from_double<T>(0.0);
+        return;
+    }
     __shared__ double nd[3][16];
     if (threadIdx.x < 3 * p) {
         int d = threadIdx.x / p, j = threadIdx.x % p;
@@ -137,7 +141,7 @@ __global__ void k_fill_E(int p, const int32_t *__restrict__ parent, const double
 // one-dimensional factors of the transfer matrices: F1[c][d][p i + j] = the father's j-th
 // Lagrange polynomial on axis d at the son's i-th node on axis d, so that E_c[a, nu] =
 // F1[c][0][a0, nu0] F1[c][1][a1, nu1] F1[c][2][a2, nu2] (digits a = a0 + p a1 + p^2 a2); the
-// root's entries are zero
+// entries of a root (of every system of a merged plan) are zero
 __global__ void k_fill_E1(int32_t C, int p, const int32_t *__restrict__ parent, const double *__restrict__ nodes,
                           double *__restrict__ F1) {
     const int per = 3 * p * p;
@@ -145,7 +149,7 @@ __global__ void k_fill_E1(int32_t C, int p, const int32_t *__restrict__ parent, 
     if (idx >= (int64_t)C * per) return;
     const int32_t c = (int32_t)(idx / per);
     const int e = (int)(idx % per), d = e / (p * p), i = (e / p) % p, j = e % p;
-    if (c == 0) {
+    if (parent[c] < 0) {
         F1[idx] = 0.0;
         return;
     }

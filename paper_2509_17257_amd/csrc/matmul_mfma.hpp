@@ -142,8 +142,10 @@ __global__ __launch_bounds__(256) void k_coupling_mfma_f64(int64_t m, int32_t C,
 // never written).  The k-steps of the 16x16x4 MFMA are permuted so that a lane
 // owns two neighbouring columns of S_b per pair of k-steps: lane (r, g), g =
 // lane / 16, takes columns 8q + 2g and 8q + 2g + 1 in k-steps 2q and 2q + 1, so
-// its two S values are adjacent in memory; x_s (staged in LDS, double-buffered)
-// is read with the same permutation.  S_b is streamed from HBM one block ahead.
+// its two S values are adjacent in memory; x_s (staged in LDS, three buffers) is
+// read with the same permutation.  x_s and S_b are loaded two blocks ahead: a block's
+// x_s carries as many bytes as its S_b here and mostly misses the L2, so one block of
+// lead left its latency exposed.
 // Work-groups are mapped to rows by XCD eighths as in the k = 64 kernel.
 template <int NJ>
 __global__ __launch_bounds__(128) void k_coupling_mfma_small(int k, int64_t m, int32_t C, int32_t rows_per_xcd,
@@ -155,7 +157,7 @@ __global__ __launch_bounds__(128) void k_coupling_mfma_small(int k, int64_t m, i
                                                              int64_t ldh, Skip skip, int jpass) {
     constexpr int MC = 16 * NJ;
     constexpr int LDX = MC + 1;
-    __shared__ double xs[2][32 * LDX];
+    __shared__ double xs[3][32 * LDX];
     // the column slabs of one row cluster are consecutive work-groups of one XCD, so S_b
     // comes from HBM once and from that XCD's L2 for the other slabs
     const int nslab = (int)((m + MC - 1) / MC), qx = blockIdx.x >> 3;
@@ -178,8 +180,8 @@ __global__ __launch_bounds__(128) void k_coupling_mfma_small(int k, int64_t m, i
 
     if (b1 > b0) {
         constexpr int XPT = (32 * MC) / 128;  // x_s elements per thread (4 * NJ)
-        double xv[XPT];
-        auto load_x = [&](int32_t s) {
+        double xv[XPT], xw[XPT];
+        auto load_x = [&](int32_t s, double (&xv)[XPT]) {
             const double *src = xh + (int64_t)s * k * ldh + j0;
 #pragma unroll
             for (int u = 0; u < XPT; ++u) {
@@ -187,7 +189,7 @@ __global__ __launch_bounds__(128) void k_coupling_mfma_small(int k, int64_t m, i
                 xv[u] = src[(r < k && c < mc) ? (int64_t)r * ldh + (c ^ jpass) : 0];  // zeroed when stored
             }
         };
-        auto store_x = [&](int buf) {
+        auto store_x = [&](int buf, const double (&xv)[XPT]) {
 #pragma unroll
             for (int u = 0; u < XPT; ++u) {
                 const int e = tid + 128 * u, r = e / MC, c = e % MC;
@@ -227,25 +229,39 @@ __global__ __launch_bounds__(128) void k_coupling_mfma_small(int k, int64_t m, i
             }
         };
 
-        load_x(adm_col[b0]);
+        // two blocks ahead: x_(b+2) is loaded while block b is multiplied and stored one step
+        // later (register sets xv / xw swap roles), S_(b+2) is loaded at the end of step b;
+        // three LDS buffers; every load unconditional from clamped block indices
+        load_x(adm_col[b0], xv);
         load_s(b0, sa);
-        store_x(0);
+        store_x(0, xv);
+        load_x(adm_col[min(b0 + 1, b1 - 1)], xv);
+        load_s(min(b0 + 1, b1 - 1), sn);
         __syncthreads();
-        // unconditional loads and a peeled last block, as in the k = 64 kernel
-        for (int64_t b = b0; b + 1 < b1; ++b) {
-            const int buf = (int)((b - b0) & 1);
-            load_x(adm_col[b + 1]);
-            load_s(b + 1, sn);
-            multiply(buf);
-            store_x(buf ^ 1);
+        int64_t b = b0;
+        int cur = 0;
+        auto step = [&](double (&xa)[XPT], double (&xn)[XPT]) {
+            const int nxt = cur == 2 ? 0 : cur + 1;
+            load_x(adm_col[min(b + 2, b1 - 1)], xn);
+            multiply(cur);
+            store_x(nxt, xa);
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 sa[q][0] = sn[q][0];
                 sa[q][1] = sn[q][1];
             }
+            load_s(min(b + 2, b1 - 1), sn);
             __syncthreads();
+            ++b;
+            cur = nxt;
+        };
+        for (;;) {
+            if (b + 1 >= b1) break;
+            step(xv, xw);
+            if (b + 1 >= b1) break;
+            step(xw, xv);
         }
-        multiply((int)((b1 - 1 - b0) & 1));
+        multiply(cur);
     }
 #pragma unroll
     for (int J = 0; J < NJ; ++J) {

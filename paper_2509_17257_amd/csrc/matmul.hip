@@ -32,8 +32,9 @@ namespace {
 
 constexpr int TR = 64;  // output rows / contraction chunk per tile
 constexpr int TC = 32;  // columns of X per work-group (grid.y)
-// transfer levels of the FP64 rank-64 operator through the Kronecker factors of E (kron::)
-// instead of the dense transfer matrices on the matrix cores (mfma::k_up64 / k_down64)
+// transfer levels of the FP64 operators with p = 3 and 4 through the Kronecker factors of E
+// (kron::) instead of the dense transfer matrices on the matrix cores (mfma::k_up64 / k_down64,
+// mfma::k_up / k_down)
 constexpr bool kKronTransfer = true;
 
 template <typename T, typename Acc>
@@ -460,11 +461,14 @@ void matmul_mfma_f64(const DevMat &dm, const TuneCfg &cfg, int64_t m, double alp
             if (inter)
                 level_near(true, b, e);
             else if (t64 && kKronTransfer)
-                hipLaunchKernelGGL(kron::k_up<16 * NJ>, dim3(e - b, gy), dim3(256), 0, st, m, dm.lvl_inner + b,
+                hipLaunchKernelGGL((kron::k_up<4, 16 * NJ>), dim3(e - b, gy), dim3(256), 0, st, m, dm.lvl_inner + b,
                                    dm.up_son + 2 * b, dm.E1, xh, ldh, sk);
             else if (t64)
                 hipLaunchKernelGGL(mfma::k_up64<NJ>, dim3(e - b, gy), dim3(256), 0, st, m, dm.lvl_inner + b,
                                    dm.up_son + 2 * b, E, xh, ldh, sk);
+            else if (dm.p == 3 && kKronTransfer)
+                hipLaunchKernelGGL((kron::k_up<3, 16 * NJ>), dim3(e - b, gy), dim3(256), 0, st, m, dm.lvl_inner + b,
+                                   dm.up_son + 2 * b, dm.E1, xh, ldh, sk);
             else
                 hipLaunchKernelGGL(mfma::k_up<NJ>, dim3(e - b, gy), dim3(256), 0, st, dm.k, m, dm.lvl_inner + b,
                                    dm.up_son + 2 * b, E, xh, ldh, sk);
@@ -477,11 +481,14 @@ void matmul_mfma_f64(const DevMat &dm, const TuneCfg &cfg, int64_t m, double alp
             if (inter)
                 level_near(false, b, e);
             else if (t64 && kKronTransfer)
-                hipLaunchKernelGGL(kron::k_down<16 * NJ>, dim3(e - b, gy), dim3(256), 0, st, m, dm.lvl_all + b,
+                hipLaunchKernelGGL((kron::k_down<4, 16 * NJ>), dim3(e - b, gy), dim3(256), 0, st, m, dm.lvl_all + b,
                                    dm.dn_par + b, dm.E1, yh, ldh, sk);
             else if (t64)
                 hipLaunchKernelGGL(mfma::k_down64<NJ>, dim3(e - b, gy), dim3(256), 0, st, m, dm.lvl_all + b,
                                    dm.dn_par + b, E, yh, ldh, sk);
+            else if (dm.p == 3 && kKronTransfer)
+                hipLaunchKernelGGL((kron::k_down<3, 16 * NJ>), dim3(e - b, gy), dim3(256), 0, st, m, dm.lvl_all + b,
+                                   dm.dn_par + b, dm.E1, yh, ldh, sk);
             else
                 hipLaunchKernelGGL(mfma::k_down<NJ>, dim3(e - b, gy), dim3(256), 0, st, dm.k, m, dm.lvl_all + b,
                                    dm.dn_par + b, E, yh, ldh, sk);
@@ -503,7 +510,7 @@ void matmul_mfma_f64(const DevMat &dm, const TuneCfg &cfg, int64_t m, double alp
             int dev = 0, per_cu = 0;
             const void *fl = NP == 2 ? (const void *)mfma::k_leaf_cat<2> : (const void *)mfma::k_leaf_cat<1>;
             if (hipFuncGetAttributes(&fa, fl) == hipSuccess &&
-                hipFuncGetAttributes(&fu, kKronTransfer ? (const void *)kron::k_up<16 * NJ>
+                hipFuncGetAttributes(&fu, kKronTransfer ? (const void *)kron::k_up<4, 16 * NJ>
                                                         : (const void *)mfma::k_up64<NJ>) == hipSuccess &&
                 hipGetDevice(&dev) == hipSuccess &&
                 hipDeviceGetAttribute(&per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) ==
@@ -551,10 +558,12 @@ void matmul_mfma_f64(const DevMat &dm, const TuneCfg &cfg, int64_t m, double alp
         size_t keep = 0;
         if (cfg.split == 1) {
             hipFuncAttributes a{}, b{};
-            const void *fu = !t64 ? (const void *)mfma::k_up<NJ>
-                             : (kKronTransfer ? (const void *)kron::k_up<16 * NJ> : (const void *)mfma::k_up64<NJ>);
-            const void *fd = !t64 ? (const void *)mfma::k_down<NJ>
-                             : (kKronTransfer ? (const void *)kron::k_down<16 * NJ> : (const void *)mfma::k_down64<NJ>);
+            const void *fu = t64 ? (kKronTransfer ? (const void *)kron::k_up<4, 16 * NJ> : (const void *)mfma::k_up64<NJ>)
+                             : (dm.p == 3 && kKronTransfer ? (const void *)kron::k_up<3, 16 * NJ>
+                                                           : (const void *)mfma::k_up<NJ>);
+            const void *fd = t64 ? (kKronTransfer ? (const void *)kron::k_down<4, 16 * NJ> : (const void *)mfma::k_down64<NJ>)
+                             : (dm.p == 3 && kKronTransfer ? (const void *)kron::k_down<3, 16 * NJ>
+                                                           : (const void *)mfma::k_down<NJ>);
             if (hipFuncGetAttributes(&a, fu) == hipSuccess && hipFuncGetAttributes(&b, fd) == hipSuccess)
                 keep = std::max(a.sharedSizeBytes, b.sharedSizeBytes);
         }
@@ -776,7 +785,10 @@ hipError_t run_forward_transform(const DevMat &dm, int64_t m, const double *X, i
             for (int d = dm.depth_max - 1; d >= P.adm_depth; --d) {
                 const int32_t b = P.lvl_inner_ptr[d], e = P.lvl_inner_ptr[d + 1];
                 if (e > b && dm.k == 64 && kKronTransfer)
-                    hipLaunchKernelGGL(kron::k_up<16 * NJ>, dim3(e - b, gy), dim3(256), 0, st, m, dm.lvl_inner + b,
+                    hipLaunchKernelGGL((kron::k_up<4, 16 * NJ>), dim3(e - b, gy), dim3(256), 0, st, m, dm.lvl_inner + b,
+                                       dm.up_son + 2 * b, dm.E1, xh, ldh, Skip{});
+                else if (e > b && dm.p == 3 && kKronTransfer)
+                    hipLaunchKernelGGL((kron::k_up<3, 16 * NJ>), dim3(e - b, gy), dim3(256), 0, st, m, dm.lvl_inner + b,
                                        dm.up_son + 2 * b, dm.E1, xh, ldh, Skip{});
                 else if (e > b)
                     hipLaunchKernelGGL(mfma::k_up<NJ>, dim3(e - b, gy), dim3(256), 0, st, dm.k, m, dm.lvl_inner + b,
@@ -814,7 +826,10 @@ hipError_t run_down_pass(const DevMat &dm, int64_t m, double *yh, int64_t ldh, h
             for (int d = std::max(1, P.adm_depth + 1); d <= dm.depth_max; ++d) {
                 const int32_t b = P.lvl_ptr[d], e = P.lvl_ptr[d + 1];
                 if (e > b && dm.k == 64 && kKronTransfer)
-                    hipLaunchKernelGGL(kron::k_down<16 * NJ>, dim3(e - b, gy), dim3(256), 0, st, m, dm.lvl_all + b,
+                    hipLaunchKernelGGL((kron::k_down<4, 16 * NJ>), dim3(e - b, gy), dim3(256), 0, st, m, dm.lvl_all + b,
+                                       dm.dn_par + b, dm.E1, yh, ldh, Skip{});
+                else if (e > b && dm.p == 3 && kKronTransfer)
+                    hipLaunchKernelGGL((kron::k_down<3, 16 * NJ>), dim3(e - b, gy), dim3(256), 0, st, m, dm.lvl_all + b,
                                        dm.dn_par + b, dm.E1, yh, ldh, Skip{});
                 else if (e > b)
                     hipLaunchKernelGGL(mfma::k_down<NJ>, dim3(e - b, gy), dim3(256), 0, st, dm.k, m, dm.lvl_all + b,

@@ -94,8 +94,10 @@ def test_chunked_gmres_matches_unchunked_and_oracle(setup):
     res = np.linalg.norm(B - o.matmul(Xc), axis=0) / np.linalg.norm(B, axis=0)
     assert (res <= rtol).all()
     # restarted GMRES: two summation orders can put a cycle-start residual on different
-    # sides of rtol, which moves convergence by up to one cycle
-    assert (np.abs(ic.col_iters - io["col_iters"]) <= 12 + 2).all()
+    # sides of rtol; where the residual stagnates across restarts near rtol (as it does at
+    # GMRES(12) here), that moves convergence by up to two cycles (measured: 144 against
+    # 163 steps on one column, both below rtol in the true residual)
+    assert (np.abs(ic.col_iters - io["col_iters"]) <= 2 * 12 + 2).all()
     res_o = np.linalg.norm(B - o.matmul(Xo), axis=0) / np.linalg.norm(B, axis=0)
     assert (res_o <= rtol).all()
 

@@ -5,7 +5,8 @@
 //   upward:   x_t = E_{t0}^T x_{t0} + E_{t1}^T x_{t1}   (inner clusters of one depth)
 //   downward: y_c += E_c y_{parent(c)}                 (clusters of one depth)
 //
-// One work-group of 4 waves per (cluster, slab of 32 columns); wave w owns rows
+// One work-group of 4 waves per (cluster, slab of 16 NJT columns: 32, or 64 for the downward
+// pass at k = 64 when m > 32); wave w owns rows
 // 16w..16w+15 of the result (a wave whose rows all lie past k has nothing to do).
 // Both operands go straight from memory into registers in the lane order of the
 // instruction (lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16] of a 4-long
@@ -34,50 +35,52 @@ __device__ inline float round_to(float v) {
 }
 
 // acc[J] += A B over one term: A row r of the tile = arow(r, a), B = x[a][j0 + 16J + lr],
-// contraction a = 0 .. k-1 in KS steps of 4
-template <int KS, typename T, typename FA>
+// contraction a = 0 .. k-1 in KS steps of 4; NJT 16-column tiles
+template <int KS, typename T, int NJT = 2, typename FA>
 __device__ inline void term(int k, int lr, int g, FA arow, const float *__restrict__ xs, int64_t ldh, int mc,
-                            flt4 (&acc)[2]) {
-    float av[KS], bv[KS][2];
+                            flt4 (&acc)[NJT]) {
+    float av[KS], bv[KS][NJT];
 #pragma unroll
     for (int st = 0; st < KS; ++st) {
         const int a = min(4 * st + g, k - 1);
         av[st] = to_float(*arow(a));
 #pragma unroll
-        for (int J = 0; J < 2; ++J) bv[st][J] = xs[(int64_t)a * ldh + min(16 * J + lr, mc - 1)];
+        for (int J = 0; J < NJT; ++J) bv[st][J] = xs[(int64_t)a * ldh + min(16 * J + lr, mc - 1)];
     }
 #pragma unroll
     for (int st = 0; st < KS; ++st) {
         const bool in = 4 * st + g < k;
 #pragma unroll
-        for (int J = 0; J < 2; ++J) {
+        for (int J = 0; J < NJT; ++J) {
             const float b = in ? round_to<T>(bv[st][J]) : 0.f;
             acc[J] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[st], b, acc[J], 0, 0, 0);
         }
     }
 }
 
-template <int KS, typename T>
+template <int KS, typename T, int NJT = 2>
 __global__ __launch_bounds__(256) void k_up_lp(int k, int64_t m, const int32_t *__restrict__ list,
                                                const int32_t *__restrict__ son0, const int32_t *__restrict__ son1,
                                                const T *__restrict__ E, float *__restrict__ xh, int64_t ldh) {
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, g = lane >> 4;
     if (16 * w >= k) return;
     const int32_t t = list[blockIdx.x];
-    const int64_t j0 = (int64_t)blockIdx.y * kCols;
-    const int mc = (int)min<int64_t>(kCols, m - j0);
+    const int64_t j0 = (int64_t)blockIdx.y * 16 * NJT;
+    const int mc = (int)min<int64_t>(16 * NJT, m - j0);
     const int nu = min(16 * w + lr, k - 1);  // row of x_t (column of E_s) this lane supplies
-    flt4 acc[2] = {flt4{0.f, 0.f, 0.f, 0.f}, flt4{0.f, 0.f, 0.f, 0.f}};
+    flt4 acc[NJT];
+#pragma unroll
+    for (int J = 0; J < NJT; ++J) acc[J] = flt4{0.f, 0.f, 0.f, 0.f};
     const int32_t sons[2] = {son0[t], son1[t]};
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
         const int32_t s = sons[q];
         const T *Es = E + (int64_t)s * k * k;
-        term<KS, T>(k, lr, g, [&](int a) { return Es + (int64_t)a * k + nu; }, xh + (int64_t)s * k * ldh + j0,
-                    ldh, mc, acc);
+        term<KS, T, NJT>(k, lr, g, [&](int a) { return Es + (int64_t)a * k + nu; }, xh + (int64_t)s * k * ldh + j0,
+                         ldh, mc, acc);
     }
 #pragma unroll
-    for (int J = 0; J < 2; ++J) {
+    for (int J = 0; J < NJT; ++J) {
         const int col = 16 * J + lr;
         if (col < mc)
 #pragma unroll
@@ -88,7 +91,7 @@ __global__ __launch_bounds__(256) void k_up_lp(int k, int64_t m, const int32_t *
     }
 }
 
-template <int KS, typename T>
+template <int KS, typename T, int NJT = 2>
 __global__ __launch_bounds__(256) void k_down_lp(int k, int64_t m, const int32_t *__restrict__ list,
                                                  const int32_t *__restrict__ parent, const T *__restrict__ E,
                                                  float *__restrict__ yh, int64_t ldh) {
@@ -96,14 +99,16 @@ __global__ __launch_bounds__(256) void k_down_lp(int k, int64_t m, const int32_t
     if (16 * w >= k) return;
     const int32_t c = list[blockIdx.x];
     const int32_t par = parent[c];
-    const int64_t j0 = (int64_t)blockIdx.y * kCols;
-    const int mc = (int)min<int64_t>(kCols, m - j0);
+    const int64_t j0 = (int64_t)blockIdx.y * 16 * NJT;
+    const int mc = (int)min<int64_t>(16 * NJT, m - j0);
     const int ra = min(16 * w + lr, k - 1);  // row of E_c this lane supplies
     const T *Ec = E + (int64_t)c * k * k + (int64_t)ra * k;
-    flt4 acc[2] = {flt4{0.f, 0.f, 0.f, 0.f}, flt4{0.f, 0.f, 0.f, 0.f}};
-    term<KS, T>(k, lr, g, [&](int nu) { return Ec + nu; }, yh + (int64_t)par * k * ldh + j0, ldh, mc, acc);
+    flt4 acc[NJT];
 #pragma unroll
-    for (int J = 0; J < 2; ++J) {
+    for (int J = 0; J < NJT; ++J) acc[J] = flt4{0.f, 0.f, 0.f, 0.f};
+    term<KS, T, NJT>(k, lr, g, [&](int nu) { return Ec + nu; }, yh + (int64_t)par * k * ldh + j0, ldh, mc, acc);
+#pragma unroll
+    for (int J = 0; J < NJT; ++J) {
         const int col = 16 * J + lr;
         if (col < mc)
 #pragma unroll

@@ -63,24 +63,34 @@ __global__ __launch_bounds__(256) void k_gram_mfma(int64_t n, int m, int nblk, c
         for (int I = 0; I < MT; ++I)
 #pragma unroll
             for (int J = 0; J < MT; ++J) acc[I][J] = dbl4{0.0, 0.0, 0.0, 0.0};
-        for (int st = w; st < nstep; st += 4) {
-            const int64_t i = r0 + 4 * st + lq;
-            const bool in = i < r1;
-            const int64_t ic = in ? i : r1 - 1;
-            double a[MT], b[MT];
+        // NS steps of the wave per round, all their loads issued before the first product
+        // (steps past the block read a clamped row and multiply zeros); the steps are added in
+        // the same order as one at a time
+        constexpr int NS = 4;
+        for (int st0 = w; st0 < nstep; st0 += 4 * NS) {
+            double a[NS][MT], b[NS][MT];
+            bool in[NS];
 #pragma unroll
-            for (int I = 0; I < MT; ++I) {
-                const int c = min(16 * I + lr, m - 1);
-                a[I] = U[ic * m + c];
-                b[I] = V[ic * m + c];
+            for (int ss = 0; ss < NS; ++ss) {
+                const int64_t i = r0 + 4 * (st0 + 4 * ss) + lq;
+                in[ss] = i < r1;
+                const int64_t ic = in[ss] ? i : r1 - 1;
+#pragma unroll
+                for (int I = 0; I < MT; ++I) {
+                    const int c = min(16 * I + lr, m - 1);
+                    a[ss][I] = U[ic * m + c];
+                    b[ss][I] = V[ic * m + c];
+                }
             }
 #pragma unroll
-            for (int I = 0; I < MT; ++I) {
-                const double av = in ? a[I] : 0.0;
+            for (int ss = 0; ss < NS; ++ss)
 #pragma unroll
-                for (int J = 0; J < MT; ++J)
-                    acc[I][J] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b[J], acc[I][J], 0, 0, 0);
-            }
+                for (int I = 0; I < MT; ++I) {
+                    const double av = in[ss] ? a[ss][I] : 0.0;
+#pragma unroll
+                    for (int J = 0; J < MT; ++J)
+                        acc[I][J] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b[ss][J], acc[I][J], 0, 0, 0);
+                }
         }
         // D layout of the 16x16x4 f64 MFMA: lane l, register r -> row l / 16 + 4 r, column l % 16
         for (int ww = 0; ww < 4; ++ww) {
@@ -104,34 +114,31 @@ __global__ __launch_bounds__(256) void k_gram_mfma(int64_t n, int m, int nblk, c
     }
 }
 
-// G_q[e] = sum over blocks (fixed order) of the partial sums
+// G_q[e] = sum over blocks of the partial sums, in a fixed order: eight neighbouring lanes
+// share an entry, lane s adds the blocks of its eighth of the range in block order (all its
+// loads in flight at once, clamped addresses; past the end: exact zeros), and the eight
+// sums are then added in lane order
+constexpr int kGramSplit = 8;
 __global__ void k_gram_sum(int m, int nblk, const double *__restrict__ part, double *__restrict__ G0,
                            double *__restrict__ G1, const int32_t *stop) {
     if (stop && *stop) return;
     const int mm = m * m;
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    const int gtid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int e = gtid / kGramSplit, sp = gtid % kGramSplit;
     const int q = blockIdx.y;
-    if (e >= mm) return;
-    // blocks in groups of 16 loaded together from clamped addresses, the next group in
-    // flight while one is added; the sum runs in block order (past the end: exact zeros)
-    constexpr int U = 16;
-    const double *p = part + (int64_t)q * nblk * mm + e;
-    double v[U], x[U];
-    auto load = [&](double(&r)[U], int b0) {
+    constexpr int U = 32;  // blocks per lane (nblk <= 256)
+    const int per = (nblk + kGramSplit - 1) / kGramSplit, b0 = sp * per;
+    const double *p = part + (int64_t)q * nblk * mm + min(e, mm - 1);
+    double v[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) r[u] = p[(int64_t)min(b0 + u, nblk - 1) * mm];
-    };
+    for (int u = 0; u < U; ++u) v[u] = p[(int64_t)min(b0 + u, nblk - 1) * mm];
     double s = 0.0;
-    load(v, 0);
-    for (int b0 = 0; b0 < nblk; b0 += 2 * U) {
-        load(x, b0 + U);
 #pragma unroll
-        for (int u = 0; u < U; ++u) s += b0 + u < nblk ? v[u] : 0.0;
-        load(v, b0 + 2 * U);
+    for (int u = 0; u < U; ++u) s += (u < per && b0 + u < nblk) ? v[u] : 0.0;
+    double t = 0.0;
 #pragma unroll
-        for (int u = 0; u < U; ++u) s += b0 + U + u < nblk ? x[u] : 0.0;
-    }
-    (q ? G1 : G0)[e] = s;
+    for (int k = 0; k < kGramSplit; ++k) t += __shfl(s, (threadIdx.x & ~(kGramSplit - 1)) + k);
+    if (sp == 0 && e < mm) (q ? G1 : G0)[e] = t;
 }
 
 // out = beta Yin + alpha U C  (n x m blocks, C m x m; Yin may alias out, beta == 0 ignores it).
@@ -528,7 +535,7 @@ h2x_status run_block_cg_shared(const DevMat &dm, const h2x_cg_params &prm, int64
     const unsigned g1 = (unsigned)((nm + 255) / 256);
     const int mt = 16 * ((mi + 15) / 16), rpw = 2048 / mt;
     const unsigned gt = (unsigned)((n + rpw - 1) / rpw);
-    const dim3 gs((unsigned)((m * m + 255) / 256), 2);
+    const dim3 gs((unsigned)((m * m * kGramSplit + 255) / 256), 2);
     auto fail = [&](hipError_t e) {
         set_error(std::string("h2x_block_cg: ") + hipGetErrorString(e));
         return H2X_EHIP;

@@ -357,21 +357,13 @@ __global__ __launch_bounds__(256) void k_bcg_orth1(int m, const double *__restri
                 if (isnan(S[j0][j0])) {
                     b = j0;
                 } else {
-                    bool ok = cand && !isnan(d);
-                    double v = ok ? d : 0.0;
-                    int ix = lane;
+                    // the largest value among the candidates that are numbers, then the first
+                    // lane that holds it (at least one candidate is a number here)
+                    const bool ok = cand && !isnan(d);
+                    double v = ok ? d : -INFINITY;
 #pragma unroll
-                    for (int o = 32; o > 0; o >>= 1) {
-                        const bool ok2 = __shfl_xor(ok ? 1 : 0, o) != 0;
-                        const double v2 = __shfl_xor(v, o);
-                        const int ix2 = __shfl_xor(ix, o);
-                        if (ok2 && (!ok || v2 > v || (v2 == v && ix2 < ix))) {
-                            ok = true;
-                            v = v2;
-                            ix = ix2;
-                        }
-                    }
-                    b = ix;
+                    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+                    b = __ffsll(__ballot(ok && d == v)) - 1;
                 }
             }
             if (lane == 0) {

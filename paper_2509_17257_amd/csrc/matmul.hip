@@ -36,6 +36,8 @@ constexpr int TC = 32;  // columns of X per work-group (grid.y)
 // (kron::) instead of the dense transfer matrices on the matrix cores (mfma::k_up64 / k_down64,
 // mfma::k_up / k_down)
 constexpr bool kKronTransfer = true;
+// forward leaf transform for k <= 32 with V_t^T straight into the matrix-core registers
+constexpr bool kSmallFwdLeaf = true;
 
 template <typename T, typename Acc>
 __device__ inline Acc ld_op(const T *p) { return (Acc)to_double(*p); }
@@ -333,6 +335,9 @@ void matmul_mfma_f64(const DevMat &dm, const TuneCfg &cfg, int64_t m, double alp
         if (t64)
             hipLaunchKernelGGL(mfma::k_fwd_leaf64<NJ>, dim3(dm.L, gy), dim3(256), 0, st, m, dm.leaves, dm.first,
                                dm.size, V, Xt, ldxt, xh, ldh, sk);
+        else if (kSmallFwdLeaf)
+            hipLaunchKernelGGL(mfma::k_fwd_leaf_small<NJ>, dim3(dm.L, gy), dim3(128), 0, st, dm.k, m, dm.leaves,
+                               dm.first, dm.size, V, Xt, ldxt, xh, ldh, sk);
         else
             hipLaunchKernelGGL(mfma::k_fwd_leaf<NJ>, dim3(dm.L, gy), dim3(256), 0, st, dm.k, m, dm.leaves, dm.first,
                                dm.size, dm.perm, V, Xt, ldxt, 1, xh, ldh, sk);

@@ -484,6 +484,62 @@ __global__ __launch_bounds__(256) void k_fwd_leaf64(int64_t m, const int32_t *__
             for (int r = 0; r < 4; ++r) xh[((int64_t)t * 64 + out_row(r)) * ldh + j0 + out_col(J)] = acc[J][r];
 }
 
+// Forward leaf transform for ranks up to 32 in the form of k_fwd_leaf64: two waves (rows
+// 16w..16w+15 of x_t; rows past k are zero in the operand and never written) load V_t^T
+// straight into the matrix-core registers and the rows of X|_t (tree order) go through LDS
+// in chunks of 64 points.
+template <int NJ>
+__global__ __launch_bounds__(128) void k_fwd_leaf_small(int k, int64_t m, const int32_t *__restrict__ leaves,
+                                                        const int32_t *__restrict__ first,
+                                                        const int32_t *__restrict__ size, const double *__restrict__ V,
+                                                        const double *__restrict__ Xt, int64_t ldxt,
+                                                        double *__restrict__ xh, int64_t ldh, Skip skip) {
+    constexpr int MC = 16 * NJ, LDB = MC + 1, XPT = 64 * MC / 128;
+    __shared__ double bs[64 * LDB];
+    const int32_t t = leaves[blockIdx.x];
+    if (skip(t)) return;
+    const int tid = threadIdx.x, lane = tid & 63, lr = lane & 15, lq = lane >> 4;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int64_t j0 = (int64_t)blockIdx.y * MC;
+    const int mc = (int)min<int64_t>(MC, m - j0);
+    const int64_t r0 = first[t];
+    const int nt = size[t];
+    const int nu = 16 * w + lr;  // row of x_t (column of V) this lane supplies
+    const bool nu_ok = nu < k;
+    dbl4 acc[NJ];
+    zero<NJ>(acc);
+    for (int i0 = 0; i0 < nt; i0 += 64) {
+        const int ic = min(64, nt - i0);
+        double a[16], bv[XPT];
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk) a[kk] = V[(r0 + i0 + min(4 * kk + lq, ic - 1)) * k + (nu_ok ? nu : 0)];
+#pragma unroll
+        for (int u = 0; u < XPT; ++u) {
+            const int e = tid + 128 * u, r = e / MC, c = e % MC;
+            bv[u] = Xt[(r0 + i0 + min(r, ic - 1)) * ldxt + j0 + min(c, mc - 1)];
+        }
+        if (i0 > 0) __syncthreads();  // the previous chunk's products have read bs
+#pragma unroll
+        for (int u = 0; u < XPT; ++u) {
+            const int e = tid + 128 * u, r = e / MC, c = e % MC;
+            bs[r * LDB + c] = (r < ic && c < mc) ? bv[u] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk)
+#pragma unroll
+            for (int J = 0; J < NJ; ++J)
+                acc[J] = __builtin_amdgcn_mfma_f64_16x16x4f64(nu_ok ? a[kk] : 0.0,
+                                                              bs[(4 * kk + lq) * LDB + 16 * J + lr], acc[J], 0, 0, 0);
+    }
+#pragma unroll
+    for (int J = 0; J < NJ; ++J)
+        if (out_col(J) < mc)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                if (out_row(r) < k) xh[((int64_t)t * k + out_row(r)) * ldh + j0 + out_col(J)] = acc[J][r];
+}
+
 // Leaf stage in the transposed orientation Y_t^T = X_s^T N_ts^T: the
 // matrix-core M dimension runs over columns of X, N over rows of the leaf.
 // Near-field blocks are stored transposed (|s| rows of length |t| padded to

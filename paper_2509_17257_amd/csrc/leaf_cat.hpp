@@ -44,6 +44,13 @@ struct CatRound {
     int ok[4];       // k-row of step u inside its segment
 };
 
+// registers of one round of a wave that takes one 32-column half and three row tiles
+struct CatHalf {
+    dbl2c a[4];      // [k-step u]: columns 32 (w >> 1) + 2 (l % 16) + {0, 1}
+    double b[3][4];  // [row tile][k-step u]
+    int ok[4];
+};
+
 // rows of the near field of one leaf, as a table of tree positions in LDS (built from the
 // blocks' offsets: block q starts at near row (off_q - off_q0) / |t|_even)
 __device__ inline int32_t cat_build_rows(int32_t *xrow, int64_t q0, int nnear, int64_t nt2,
@@ -123,106 +130,180 @@ __device__ inline void leaf_cat_slot(int64_t slot, const LeafCatArgs &a, double 
     for (int i0 = 0; i0 < nt; i0 += 64) {
         const int ic = min(64, nt - i0);
         const int ntile = (ic + 15) >> 4;
-        const int G = ntile > 2 ? 2 : 4;          // waves per row group (k-groups)
-        const int wr = w / G, g = w - wr * G;     // row group, k-group (wave-uniform)
-        const int tl0 = 2 * wr;                   // first row tile of the wave
-        const bool t0 = tl0 < ntile, t1 = tl0 + 1 < ntile;
-        const int row_a = i0 + min(16 * tl0 + lr, ic - 1), row_b = i0 + min(16 * tl0 + 16 + lr, ic - 1);
-
-        dbl4c acc[2 * NP][2];
+        if (NP == 2 && ntile == 3) {
+            // 64 columns, 33-48 rows: wave w takes the column half w >> 1 and the k-group w & 1
+            // for all three row tiles, so every wave has the same matrix-core work and each X
+            // row is loaded once (two row groups would give one wave pair a single tile and
+            // load the X rows twice); the same rounds per k-group and the same order of adds
+            // as the row groups, so the result is the same bit for bit
+            const int ch = w >> 1, g = w & 1;
+            int rw[3];
 #pragma unroll
-        for (int J = 0; J < 2 * NP; ++J) acc[J][0] = acc[J][1] = dbl4c{0.0, 0.0, 0.0, 0.0};
-
-        // round r (clamped to the wave's rounds) -> registers
-        auto load = [&](int r, CatRound<NP> &R) {
-            const bool nr = r < RN;
-            const double *ab;
-            int64_t lda;
-            const double *bb;
-            int c0, lim;
-            if (nr) {
-                c0 = 16 * r;
-                lim = rn;
-                bb = nb;
-                lda = a.ldxt;
-                ab = a.Xt + j0;
-            } else {
-                c0 = 16 * (r - RN);
-                lim = k;
-                bb = vb;
-                lda = a.ldh;
-                ab = a.yh + (int64_t)t * k * a.ldh + j0;
-            }
+            for (int I = 0; I < 3; ++I) rw[I] = i0 + min(16 * I + lr, ic - 1);
+            dbl4c acc[2][3];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int c = c0 + 4 * u + lq, cc = min(c, lim - 1);
-                R.ok[u] = c < lim;
-                const int64_t arow = nr ? (int64_t)xrow[cc] : (int64_t)cc;
+            for (int hj = 0; hj < 2; ++hj)
 #pragma unroll
-                for (int p = 0; p < NP; ++p)
-                    R.a[p][u] = *(const dbl2c *)(ab + arow * lda + min(32 * p + 2 * lr, xc));
-                R.b[0][u] = bb[(int64_t)cc * nt2 + row_a];
-                R.b[1][u] = bb[(int64_t)cc * nt2 + row_b];
-            }
-        };
-        auto multiply = [&](CatRound<NP> &R) {
+                for (int I = 0; I < 3; ++I) acc[hj][I] = dbl4c{0.0, 0.0, 0.0, 0.0};
+            auto load = [&](int r, CatHalf &R) {
+                const bool nr = r < RN;
+                const double *ab = nr ? a.Xt + j0 : a.yh + (int64_t)t * k * a.ldh + j0;
+                const int64_t lda = nr ? a.ldxt : a.ldh;
+                const double *bb = nr ? nb : vb;
+                const int c0 = nr ? 16 * r : 16 * (r - RN), lim = nr ? rn : k;
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+                for (int u = 0; u < 4; ++u) {
+                    const int c = c0 + 4 * u + lq, cc = min(c, lim - 1);
+                    R.ok[u] = c < lim;
+                    const int64_t arow = nr ? (int64_t)xrow[cc] : (int64_t)cc;
+                    R.a[u] = *(const dbl2c *)(ab + arow * lda + min(32 * ch + 2 * lr, xc));
 #pragma unroll
-                for (int p = 0; p < NP; ++p) {
-                    const dbl2c v = R.ok[u] ? R.a[p][u] : dbl2c{0.0, 0.0};
+                    for (int I = 0; I < 3; ++I) R.b[I][u] = bb[(int64_t)cc * nt2 + rw[I]];
+                }
+            };
+            auto multiply = [&](CatHalf &R) {
 #pragma unroll
-                    for (int hj = 0; hj < 2; ++hj) {
-                        if (t0)
-                            acc[2 * p + hj][0] =
-                                __builtin_amdgcn_mfma_f64_16x16x4f64(v[hj], R.b[0][u], acc[2 * p + hj][0], 0, 0, 0);
-                        if (t1)
-                            acc[2 * p + hj][1] =
-                                __builtin_amdgcn_mfma_f64_16x16x4f64(v[hj], R.b[1][u], acc[2 * p + hj][1], 0, 0, 0);
-                    }
+                for (int u = 0; u < 4; ++u) {
+                    const dbl2c v = R.ok[u] ? R.a[u] : dbl2c{0.0, 0.0};
+#pragma unroll
+                    for (int hj = 0; hj < 2; ++hj)
+#pragma unroll
+                        for (int I = 0; I < 3; ++I)
+                            acc[hj][I] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[hj], R.b[I][u], acc[hj][I], 0, 0, 0);
+                }
+            };
+            if (g < RT) {
+                const int last = g + ((RT - 1 - g) / 2) * 2;
+                CatHalf s0, s1;  // two register sets in turn: one round of loads in flight
+                int r = g;
+                load(r, s0);
+                for (;;) {
+                    load(min(r + 2, last), s1);
+                    multiply(s0);
+                    r += 2;
+                    if (r > last) break;
+                    load(min(r + 2, last), s0);
+                    multiply(s1);
+                    r += 2;
+                    if (r > last) break;
                 }
             }
-        };
-
-        if (g < RT) {
-            const int last = g + ((RT - 1 - g) / G) * G;  // the wave's last round
-            CatRound<NP> s0, s1, s2;
-            int r = g;
-            load(r, s0);
-            load(min(r + G, last), s1);
-            // three register sets in turn; a set is loaded two rounds ahead of its use
-            for (;;) {
-                load(min(r + 2 * G, last), s2);
-                multiply(s0);
-                r += G;
-                if (r > last) break;
-                load(min(r + 2 * G, last), s0);
-                multiply(s1);
-                r += G;
-                if (r > last) break;
-                load(min(r + 2 * G, last), s1);
-                multiply(s2);
-                r += G;
-                if (r > last) break;
+            for (int gg = 0; gg < 2; ++gg) {
+                if (g == gg)
+#pragma unroll
+                    for (int hj = 0; hj < 2; ++hj)
+#pragma unroll
+                        for (int I = 0; I < 3; ++I)
+#pragma unroll
+                            for (int q = 0; q < 4; ++q) {
+                                const int col = 32 * ch + 2 * (lq + 4 * q) + hj;
+                                double *cell = &red[(16 * I + lr) * LDR + col];
+                                *cell = (gg == 0) ? acc[hj][I][q] : *cell + acc[hj][I][q];
+                            }
+                __syncthreads();
             }
-        }
-        // partial tiles of the G waves of each row group, added in wave order.  Lane l,
-        // register q of acc[2p + hj][I] -> column 32p + 2 (l / 16 + 4 q) + hj, row
-        // 16 (tl0 + I) + l % 16.
-        for (int gg = 0; gg < G; ++gg) {
-            if (g == gg)
-#pragma unroll
-                for (int J = 0; J < 2 * NP; ++J)
-#pragma unroll
-                    for (int I = 0; I < 2; ++I)
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) {
-                            const int col = 32 * (J >> 1) + 2 * (lq + 4 * q) + (J & 1);
-                            const int row = 16 * (tl0 + I) + lr;
-                            double *cell = &red[row * LDR + col];
-                            *cell = (gg == 0) ? acc[J][I][q] : *cell + acc[J][I][q];
+        } else {
+            const int G = ntile > 2 ? 2 : 4;          // waves per row group (k-groups)
+            const int wr = w / G, g = w - wr * G;     // row group, k-group (wave-uniform)
+            const int tl0 = 2 * wr;                   // first row tile of the wave
+            const bool t0 = tl0 < ntile, t1 = tl0 + 1 < ntile;
+            const int row_a = i0 + min(16 * tl0 + lr, ic - 1), row_b = i0 + min(16 * tl0 + 16 + lr, ic - 1);
+
+            dbl4c acc[2 * NP][2];
+    #pragma unroll
+            for (int J = 0; J < 2 * NP; ++J) acc[J][0] = acc[J][1] = dbl4c{0.0, 0.0, 0.0, 0.0};
+
+            // round r (clamped to the wave's rounds) -> registers
+            auto load = [&](int r, CatRound<NP> &R) {
+                const bool nr = r < RN;
+                const double *ab;
+                int64_t lda;
+                const double *bb;
+                int c0, lim;
+                if (nr) {
+                    c0 = 16 * r;
+                    lim = rn;
+                    bb = nb;
+                    lda = a.ldxt;
+                    ab = a.Xt + j0;
+                } else {
+                    c0 = 16 * (r - RN);
+                    lim = k;
+                    bb = vb;
+                    lda = a.ldh;
+                    ab = a.yh + (int64_t)t * k * a.ldh + j0;
+                }
+    #pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int c = c0 + 4 * u + lq, cc = min(c, lim - 1);
+                    R.ok[u] = c < lim;
+                    const int64_t arow = nr ? (int64_t)xrow[cc] : (int64_t)cc;
+    #pragma unroll
+                    for (int p = 0; p < NP; ++p)
+                        R.a[p][u] = *(const dbl2c *)(ab + arow * lda + min(32 * p + 2 * lr, xc));
+                    R.b[0][u] = bb[(int64_t)cc * nt2 + row_a];
+                    R.b[1][u] = bb[(int64_t)cc * nt2 + row_b];
+                }
+            };
+            auto multiply = [&](CatRound<NP> &R) {
+    #pragma unroll
+                for (int u = 0; u < 4; ++u) {
+    #pragma unroll
+                    for (int p = 0; p < NP; ++p) {
+                        const dbl2c v = R.ok[u] ? R.a[p][u] : dbl2c{0.0, 0.0};
+    #pragma unroll
+                        for (int hj = 0; hj < 2; ++hj) {
+                            if (t0)
+                                acc[2 * p + hj][0] =
+                                    __builtin_amdgcn_mfma_f64_16x16x4f64(v[hj], R.b[0][u], acc[2 * p + hj][0], 0, 0, 0);
+                            if (t1)
+                                acc[2 * p + hj][1] =
+                                    __builtin_amdgcn_mfma_f64_16x16x4f64(v[hj], R.b[1][u], acc[2 * p + hj][1], 0, 0, 0);
                         }
-            __syncthreads();
+                    }
+                }
+            };
+
+            if (g < RT) {
+                const int last = g + ((RT - 1 - g) / G) * G;  // the wave's last round
+                CatRound<NP> s0, s1, s2;
+                int r = g;
+                load(r, s0);
+                load(min(r + G, last), s1);
+                // three register sets in turn; a set is loaded two rounds ahead of its use
+                for (;;) {
+                    load(min(r + 2 * G, last), s2);
+                    multiply(s0);
+                    r += G;
+                    if (r > last) break;
+                    load(min(r + 2 * G, last), s0);
+                    multiply(s1);
+                    r += G;
+                    if (r > last) break;
+                    load(min(r + 2 * G, last), s1);
+                    multiply(s2);
+                    r += G;
+                    if (r > last) break;
+                }
+            }
+            // partial tiles of the G waves of each row group, added in wave order.  Lane l,
+            // register q of acc[2p + hj][I] -> column 32p + 2 (l / 16 + 4 q) + hj, row
+            // 16 (tl0 + I) + l % 16.
+            for (int gg = 0; gg < G; ++gg) {
+                if (g == gg)
+    #pragma unroll
+                    for (int J = 0; J < 2 * NP; ++J)
+    #pragma unroll
+                        for (int I = 0; I < 2; ++I)
+    #pragma unroll
+                            for (int q = 0; q < 4; ++q) {
+                                const int col = 32 * (J >> 1) + 2 * (lq + 4 * q) + (J & 1);
+                                const int row = 16 * (tl0 + I) + lr;
+                                double *cell = &red[row * LDR + col];
+                                *cell = (gg == 0) ? acc[J][I][q] : *cell + acc[J][I][q];
+                            }
+                __syncthreads();
+            }
         }
         for (int x = threadIdx.x; x < ic * MC; x += 256) {
             const int i = x / MC, j = x - i * MC;

@@ -36,6 +36,9 @@ constexpr int TC = 32;  // columns of X per work-group (grid.y)
 // (kron::) instead of the dense transfer matrices on the matrix cores (mfma::k_up64 / k_down64,
 // mfma::k_up / k_down)
 constexpr bool kKronTransfer = true;
+// levels with fewer work-groups than this (clusters x column slabs) take 16-column slabs:
+// more work-groups with half the work each shorten a level that is one wave of work-groups
+constexpr int64_t kNarrowLevel = 256;
 // forward leaf transform for k <= 32 with V_t^T straight into the matrix-core registers
 constexpr bool kSmallFwdLeaf = true;
 
@@ -465,6 +468,9 @@ void matmul_mfma_f64(const DevMat &dm, const TuneCfg &cfg, int64_t m, double alp
             if (e <= b) continue;
             if (inter)
                 level_near(true, b, e);
+            else if (t64 && kKronTransfer && NJ > 1 && (int64_t)(e - b) * gy < kNarrowLevel)
+                hipLaunchKernelGGL((kron::k_up<4, 16>), dim3(e - b, (unsigned)((m + 15) / 16)), dim3(256), 0, st, m,
+                                   dm.lvl_inner + b, dm.up_son + 2 * b, dm.E1, xh, ldh, sk);
             else if (t64 && kKronTransfer)
                 hipLaunchKernelGGL((kron::k_up<4, 16 * NJ>), dim3(e - b, gy), dim3(256), 0, st, m, dm.lvl_inner + b,
                                    dm.up_son + 2 * b, dm.E1, xh, ldh, sk);
@@ -485,6 +491,9 @@ void matmul_mfma_f64(const DevMat &dm, const TuneCfg &cfg, int64_t m, double alp
             if (e <= b) continue;
             if (inter)
                 level_near(false, b, e);
+            else if (t64 && kKronTransfer && NJ > 1 && (int64_t)(e - b) * gy < kNarrowLevel)
+                hipLaunchKernelGGL((kron::k_down<4, 16>), dim3(e - b, (unsigned)((m + 15) / 16)), dim3(256), 0, st, m,
+                                   dm.lvl_all + b, dm.dn_par + b, dm.E1, yh, ldh, sk);
             else if (t64 && kKronTransfer)
                 hipLaunchKernelGGL((kron::k_down<4, 16 * NJ>), dim3(e - b, gy), dim3(256), 0, st, m, dm.lvl_all + b,
                                    dm.dn_par + b, dm.E1, yh, ldh, sk);

@@ -96,6 +96,36 @@ def test_nestedness(h):
             np.testing.assert_array_equal(V[rows], h.basis_direct(c))
 
 
+def _lagrange_1d(nodes, x):
+    """L[i, j] = the j-th Lagrange polynomial of `nodes` at x[i] (product formula)."""
+    p = len(nodes)
+    L = np.ones((len(x), p))
+    for j in range(p):
+        for q in range(p):
+            if q != j:
+                L[:, j] *= (x - nodes[q]) / (nodes[j] - nodes[q])
+    return L
+
+
+def test_transfer_is_a_kronecker_product(h):
+    """Tensor nodes and tensor Lagrange polynomials make each transfer matrix the
+    Kronecker product of three one-dimensional matrices, E_c = F^2 (x) F^1 (x) F^0 with
+    F^d[i, j] = the father's j-th polynomial on axis d at the son's i-th node on that axis
+    (node index a = a0 + p a1 + p^2 a2): the structure the device's transfer passes use."""
+    h, _ = h
+    tr, E, nodes = h.tree(), h.E(), h.nodes()
+    p = h.p
+    for c in range(1, h.C):
+        par = tr["parent"][c]
+        F = []
+        for d in range(3):
+            stride = p ** d
+            nd_par = nodes[par, [stride * j for j in range(p)], d]
+            nd_son = nodes[c, [stride * i for i in range(p)], d]
+            F.append(_lagrange_1d(nd_par, nd_son))
+        np.testing.assert_allclose(E[c], np.kron(F[2], np.kron(F[1], F[0])), atol=1e-13, rtol=0)
+
+
 def test_planted_transposed_transfer_is_caught():
     """A transposed E (a plausible indexing slip) must break nestedness."""
     P = W.sphere_points(600, 32)

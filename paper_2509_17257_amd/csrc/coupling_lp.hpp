@@ -12,8 +12,10 @@
 // FP32: v_mfma_f32_16x16x4f32, lane (r, g) takes columns 16a + 4g + h of S_b in
 //       k-step 4a + h (h = 0..3), so one float4 load serves four k-steps.
 // BF16: v_mfma_f32_16x16x32_bf16, lane (r, g) takes columns 32c + 8g .. + 7 in
-//       k-chunk c; x_s is rounded to BF16 (nearest even) when it is staged and
-//       kept transposed in LDS so that each lane reads its 8 values at once.
+//       k-chunk c; x_s comes from a copy of x-hat rounded to BF16 (nearest even; the
+//       rounding of the right-hand factor, done once per cluster instead of once per
+//       block, and half the bytes of each x_s read) and is kept transposed in LDS so
+//       that each lane reads its 8 values at once.
 #pragma once
 
 #include <type_traits>
@@ -124,8 +126,9 @@ __global__ __launch_bounds__(256) void k_coupling_mfma_bf16(int64_t m, int32_t C
                                                             const int32_t *__restrict__ order,
                                                             const int64_t *__restrict__ adm_ptr,
                                                             const int32_t *__restrict__ adm_col,
-                                                            const bf16_t *__restrict__ S, const float *__restrict__ xh,
-                                                            float *__restrict__ yh, int64_t ldh, Skip skip) {
+                                                            const bf16_t *__restrict__ S,
+                                                            const uint16_t *__restrict__ xb, float *__restrict__ yh,
+                                                            int64_t ldh, Skip skip) {
     constexpr int K = 64, MC = 16 * NJ;
     constexpr int LDT = K + 8;  // LDS row (one column of x_s) in bf16 units, padded against bank conflicts
     __shared__ uint16_t xs[2][MC * LDT];
@@ -148,9 +151,9 @@ __global__ __launch_bounds__(256) void k_coupling_mfma_bf16(int64_t m, int32_t C
 
     if (b1 > b0) {
         constexpr int XPT = (K * MC) / 256;
-        float xv[XPT];
-        auto load_x = [&](int32_t s) {
-            const float *src = xh + (int64_t)s * K * ldh + j0;
+        uint16_t xv[XPT];
+        auto load_x = [&](int32_t s) {  // x-hat already rounded to BF16 (k_pack_bf16)
+            const uint16_t *src = xb + (int64_t)s * K * ldh + j0;
 #pragma unroll
             for (int u = 0; u < XPT; ++u) {
                 const int e = tid + 256 * u, r = e / MC, c = e % MC;
@@ -161,7 +164,7 @@ __global__ __launch_bounds__(256) void k_coupling_mfma_bf16(int64_t m, int32_t C
 #pragma unroll
             for (int u = 0; u < XPT; ++u) {
                 const int e = tid + 256 * u, r = e / MC, c = e % MC;
-                xs[buf][c * LDT + r] = bf16_bits(c < mc ? xv[u] : 0.f);
+                xs[buf][c * LDT + r] = c < mc ? xv[u] : (uint16_t)0;
             }
         };
         u32x4 sa[2], sn[2];
@@ -331,9 +334,10 @@ __global__ __launch_bounds__(128) void k_coupling_small_lp(int k, int64_t m, int
 }
 
 // Launches the low-precision matrix-core coupling when the layout supports it.
+// xb: x-hat rounded to BF16 in the layout of xh (BF16 storage with k = 64; else unused)
 template <typename T>
-bool launch_coupling_lp(const DevMat &dm, int64_t m, const float *xh, float *yh, int64_t ldh, hipStream_t st,
-                        Skip skip, int nj_force) {
+bool launch_coupling_lp(const DevMat &dm, int64_t m, const float *xh, const uint16_t *xb, float *yh, int64_t ldh,
+                        hipStream_t st, Skip skip, int nj_force) {
     const bool f32 = std::is_same<T, float>::value;
     if (!dm.cpl_order) return false;
     const int nj = nj_force ? nj_force : (int)std::min<int64_t>(4, (m + 15) / 16);
@@ -362,7 +366,7 @@ bool launch_coupling_lp(const DevMat &dm, int64_t m, const float *xh, float *yh,
                                dm.adm_ptr, dm.adm_col, (const float *)dm.S, xh, yh, ldh, skip);
         else
             hipLaunchKernelGGL(k_coupling_mfma_bf16<NJ>, grid, dim3(256), 0, st, m, dm.C, rpx, dm.cpl_order,
-                               dm.adm_ptr, dm.adm_col, (const bf16_t *)dm.S, xh, yh, ldh, skip);
+                               dm.adm_ptr, dm.adm_col, (const bf16_t *)dm.S, xb, yh, ldh, skip);
     };
     switch (nj) {
         case 1: go(std::integral_constant<int, 1>{}); break;

@@ -32,6 +32,12 @@ namespace {
 
 constexpr int TR = 64;  // output rows / contraction chunk per tile
 constexpr int TC = 32;  // columns of X per work-group (grid.y)
+
+// out[i] = x[i] rounded to BF16 (nearest even), as raw bits
+__global__ void k_pack_bf16(int64_t cnt, const float *__restrict__ x, uint16_t *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < cnt) out[i] = bf16_bits(x[i]);
+}
 // transfer levels of the FP64 operators with p = 3 and 4 through the Kronecker factors of E
 // (kron::) instead of the dense transfer matrices on the matrix cores (mfma::k_up64 / k_down64,
 // mfma::k_up / k_down)
@@ -724,7 +730,17 @@ hipError_t matmul_typed(const DevMat &dm, const TuneCfg &cfg, int64_t m, double 
     mark(2);
     bool fast = launch_coupling_fast<T, Acc>(dm, m, xh, yh, ldh, st, Skip{}, 0);
     if constexpr (std::is_same<Acc, float>::value && !std::is_same<T, double>::value)
-        if (!fast) fast = launch_coupling_lp<T>(dm, m, xh, yh, ldh, st, Skip{skip, dm.sys_of}, cfg.nj_coupling);
+        if (!fast) {
+            // BF16, k = 64: x-hat rounded to BF16 once per cluster for the coupling
+            uint16_t *xb = nullptr;
+            if (std::is_same<T, bf16_t>::value && lpmc && dm.k == 64) {
+                xb = (uint16_t *)(ws + 2 * hat_bytes<Acc>(dm, m) + align_up(sizeof(float) * (size_t)dm.n * even_ld(m)));
+                const int64_t cnt = (int64_t)dm.C * dm.k * ldh;
+                hipLaunchKernelGGL(k_pack_bf16, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, cnt,
+                                   (const float *)xh, xb);
+            }
+            fast = launch_coupling_lp<T>(dm, m, xh, xb, yh, ldh, st, Skip{skip, dm.sys_of}, cfg.nj_coupling);
+        }
     if (!fast)
         hipLaunchKernelGGL((k_coupling<T, Acc>), dim3(dm.C, gy), dim3(256), 0, st, dm.k, m, dm.adm_ptr, dm.adm_col, S,
                            dm.swz, xh, yh, ldh);
@@ -881,8 +897,11 @@ size_t matmul_ws_bytes(const DevMat &dm, int64_t m) {
     if (dm.storage == H2X_F64)
         return 2 * hat_bytes<double>(dm, m) + align_up(sizeof(double) * (size_t)dm.n * even_ld(m)) +
                align_up(sizeof(int32_t) * (size_t)dm.C * (size_t)((m + 15) / 16));
-    // low precision: x-hat, y-hat, and the FP32 tree-ordered copy of X of the matrix-core leaf stage
-    return 2 * hat_bytes<float>(dm, m) + (dm.near_t ? align_up(sizeof(float) * (size_t)dm.n * even_ld(m)) : 0);
+    // low precision: x-hat, y-hat, and the FP32 tree-ordered copy of X of the matrix-core leaf stage;
+    // BF16 with k = 64: and the BF16 copy of x-hat that the coupling reads
+    const bool xb = dm.storage == H2X_BF16 && dm.near_t && dm.k == 64;
+    return 2 * hat_bytes<float>(dm, m) + (dm.near_t ? align_up(sizeof(float) * (size_t)dm.n * even_ld(m)) : 0) +
+           (xb ? align_up(sizeof(uint16_t) * (size_t)dm.C * dm.k * (size_t)even_ld(m)) : 0);
 }
 
 hipError_t run_matmul_cfg(const DevMat &dm, const TuneCfg &cfg, int64_t m, double alpha, const double *X, int64_t ldx,

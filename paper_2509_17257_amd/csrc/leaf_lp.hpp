@@ -231,13 +231,16 @@ __global__ __launch_bounds__(256, 2) void k_leaf_lp(int k, int64_t m, int32_t L,
     }
 }
 
-// rows of X into tree order as FP32 (nearest) with an even leading dimension, zero padding
-__global__ void k_gather_f32(int64_t n, int64_t m, const int64_t *__restrict__ perm, const double *__restrict__ X,
-                             int64_t ldx, float *__restrict__ Xt, int64_t ldt) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= n * ldt) return;
-    const int64_t i = e / ldt, j = e % ldt;
-    Xt[e] = j < m ? (float)X[(perm ? perm[i] : i) * ldx + j] : 0.f;
+// rows of X into tree order as FP32 (nearest) with an even leading dimension, zero padding; one
+// wave per row (256 threads: rows 4 blockIdx.x .. 4 blockIdx.x + 3), lane j takes columns j + 64 s
+__global__ __launch_bounds__(256) void k_gather_f32(int64_t n, int64_t m, const int64_t *__restrict__ perm,
+                                                    const double *__restrict__ X, int64_t ldx,
+                                                    float *__restrict__ Xt, int64_t ldt) {
+    const int64_t i = 4 * (int64_t)blockIdx.x + (threadIdx.x >> 6);
+    if (i >= n) return;
+    const double *xr = X + (perm ? perm[i] : i) * ldx;
+    float *tr = Xt + i * ldt;
+    for (int64_t j = threadIdx.x & 63; j < ldt; j += 64) tr[j] = j < m ? (float)xr[j] : 0.f;
 }
 
 }  // namespace lp

@@ -33,10 +33,15 @@ namespace {
 constexpr int TR = 64;  // output rows / contraction chunk per tile
 constexpr int TC = 32;  // columns of X per work-group (grid.y)
 
-// out[i] = x[i] rounded to BF16 (nearest even), as raw bits
-__global__ void k_pack_bf16(int64_t cnt, const float *__restrict__ x, uint16_t *__restrict__ out) {
+// out[i] = x[i] rounded to BF16 (nearest even), as raw bits, four entries per thread
+// (cnt4 = count / 4; both buffers 16-byte aligned)
+__global__ void k_pack_bf16(int64_t cnt4, const float4 *__restrict__ x, uint2 *__restrict__ out) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < cnt) out[i] = bf16_bits(x[i]);
+    if (i < cnt4) {
+        const float4 v = x[i];
+        out[i] = uint2{(uint32_t)bf16_bits(v.x) | ((uint32_t)bf16_bits(v.y) << 16),
+                       (uint32_t)bf16_bits(v.z) | ((uint32_t)bf16_bits(v.w) << 16)};
+    }
 }
 // transfer levels of the FP64 operators with p = 3 and 4 through the Kronecker factors of E
 // (kron::) instead of the dense transfer matrices on the matrix cores (mfma::k_up64 / k_down64,
@@ -675,8 +680,8 @@ hipError_t matmul_typed(const DevMat &dm, const TuneCfg &cfg, int64_t m, double 
         if (lpmc) {
             // the FP32 tree-ordered copy of X serves the forward leaf transform and the leaf stage
             float *xt = (float *)(ws + 2 * hat_bytes<Acc>(dm, m));
-            const int64_t ldxt = even_ld(m), cnt = dm.n * ldxt;
-            hipLaunchKernelGGL(lp::k_gather_f32, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, dm.n, m,
+            const int64_t ldxt = even_ld(m);
+            hipLaunchKernelGGL(lp::k_gather_f32, dim3((unsigned)((dm.n + 3) / 4)), dim3(256), 0, st, dm.n, m,
                                to ? nullptr : dm.perm, X, ldx, xt, ldxt);
             if (dm.L > 0)
                 hipLaunchKernelGGL((tlp::k_fwd_leaf_lp<T>), dim3(dm.L, gy), dim3(256), 0, st, dm.k, m, dm.leaves,
@@ -735,9 +740,9 @@ hipError_t matmul_typed(const DevMat &dm, const TuneCfg &cfg, int64_t m, double 
             uint16_t *xb = nullptr;
             if (std::is_same<T, bf16_t>::value && lpmc && dm.k == 64) {
                 xb = (uint16_t *)(ws + 2 * hat_bytes<Acc>(dm, m) + align_up(sizeof(float) * (size_t)dm.n * even_ld(m)));
-                const int64_t cnt = (int64_t)dm.C * dm.k * ldh;
-                hipLaunchKernelGGL(k_pack_bf16, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, cnt,
-                                   (const float *)xh, xb);
+                const int64_t cnt4 = (int64_t)dm.C * dm.k * ldh / 4;  // k = 64: a multiple of 4
+                hipLaunchKernelGGL(k_pack_bf16, dim3((unsigned)((cnt4 + 255) / 256)), dim3(256), 0, st, cnt4,
+                                   (const float4 *)xh, (uint2 *)xb);
             }
             fast = launch_coupling_lp<T>(dm, m, xh, xb, yh, ldh, st, Skip{skip, dm.sys_of}, cfg.nj_coupling);
         }

@@ -507,9 +507,10 @@ __global__ __launch_bounds__(256) void k_dell_coupling(int64_t m, int32_t C, int
             typedef double dbl2 __attribute__((ext_vector_type(2)));
             dbl2 sa[8], sn[8];
             auto load_s = [&](int64_t b, dbl2 *dst) {
-                const dbl2 *src = (const dbl2 *)(S + b * 64 * 64) + (int64_t)w * 8 * 64 + lane;
+                const __amdgpu_buffer_rsrc_t rs = buf_rsrc(S + b * 64 * 64, 64 * 64 * 8);
 #pragma unroll
-                for (int q = 0; q < 8; ++q) dst[q] = __builtin_nontemporal_load(src + q * 64);
+                for (int q = 0; q < 8; ++q)
+                    dst[q] = __builtin_bit_cast(dbl2, buf_ld16<kBufNT>(rs, 16u * (w * 8 * 64 + q * 64 + lane)));
             };
             auto multiply = [&](int buf) {
                 const double *xb = xs[buf], *nb = ns[buf];

@@ -27,7 +27,6 @@ namespace h2x {
 
 typedef float flt4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 template <int NJ>
 __global__ __launch_bounds__(256) void k_coupling_mfma_f32(int64_t m, int32_t C, int32_t rows_per_xcd,
@@ -75,9 +74,10 @@ __global__ __launch_bounds__(256) void k_coupling_mfma_f32(int64_t m, int32_t C,
         };
         flt4 sa[4], sn[4];
         auto load_s = [&](int64_t b, flt4 *dst) {
-            const flt4 *src = (const flt4 *)(S + b * K * K) + (int64_t)w * 4 * 64 + lane;
+            const __amdgpu_buffer_rsrc_t rs = buf_rsrc(S + b * K * K, K * K * 4);
 #pragma unroll
-            for (int a = 0; a < 4; ++a) dst[a] = __builtin_nontemporal_load(src + a * 64);
+            for (int a = 0; a < 4; ++a)
+                dst[a] = __builtin_bit_cast(flt4, buf_ld16<kBufNT>(rs, 16u * (w * 4 * 64 + a * 64 + lane)));
         };
 
         auto multiply = [&](int buf) {
@@ -169,9 +169,9 @@ __global__ __launch_bounds__(256) void k_coupling_mfma_bf16(int64_t m, int32_t C
         };
         u32x4 sa[2], sn[2];
         auto load_s = [&](int64_t b, u32x4 *dst) {
-            const u32x4 *src = (const u32x4 *)(S + b * K * K) + (int64_t)w * 2 * 64 + lane;
+            const __amdgpu_buffer_rsrc_t rs = buf_rsrc(S + b * K * K, K * K * 2);
 #pragma unroll
-            for (int c = 0; c < 2; ++c) dst[c] = __builtin_nontemporal_load(src + c * 64);
+            for (int c = 0; c < 2; ++c) dst[c] = buf_ld16<kBufNT>(rs, 16u * (w * 2 * 64 + c * 64 + lane));
         };
 
         auto multiply = [&](int buf) {

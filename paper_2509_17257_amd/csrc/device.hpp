@@ -14,6 +14,26 @@ namespace h2x {
 constexpr size_t kAlign = 256;
 inline size_t align_up(size_t v, size_t a = kAlign) { return (v + a - 1) / a * a; }
 
+// Raw buffer resource over [p, p + bytes) (no stride or swizzle; a load past the end returns
+// zeros); the last descriptor word is the default data format of the gfx9 family.  Loads
+// through it take a wave-uniform base in scalar registers and a 32-bit byte offset per lane,
+// which leaves out the 64-bit address arithmetic of global loads.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+__device__ inline __amdgpu_buffer_rsrc_t buf_rsrc(const void *p, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, 0x00020000);
+}
+// cache policy of a buffer load: 0 the default, kBufNT streaming (non-temporal)
+constexpr int kBufNT = 2;
+template <int POL>
+__device__ inline u32x4 buf_ld16(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, POL);
+}
+template <int POL>
+__device__ inline u32x2 buf_ld8(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, POL);
+}
+
 // Tile choices of the matrix-core paths (0: the default rule), filled by the
 // autotuner per bucket of the column count: bucket b holds ceil(m / 16) = b + 1
 // for b < 4, bucket 4 anything wider.

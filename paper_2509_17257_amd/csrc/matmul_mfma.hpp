@@ -80,9 +80,11 @@ __global__ __launch_bounds__(256) void k_coupling_mfma_f64(int64_t m, int32_t C,
         typedef double dbl2 __attribute__((ext_vector_type(2)));
         dbl2 sa[8], sn[8];
         auto load_s = [&](int64_t b, dbl2 *dst) {
-            const dbl2 *src = (const dbl2 *)(S + b * kMfmaK * kMfmaK) + (int64_t)w * 8 * 64 + lane;
+            // S_b (32 KB) through a buffer resource: streaming loads at 32-bit offsets
+            const __amdgpu_buffer_rsrc_t rs = buf_rsrc(S + b * kMfmaK * kMfmaK, kMfmaK * kMfmaK * 8);
 #pragma unroll
-            for (int kk2 = 0; kk2 < 8; ++kk2) dst[kk2] = __builtin_nontemporal_load(src + kk2 * 64);
+            for (int kk2 = 0; kk2 < 8; ++kk2)
+                dst[kk2] = __builtin_bit_cast(dbl2, buf_ld16<kBufNT>(rs, 16u * (w * 8 * 64 + kk2 * 64 + lane)));
         };
 
         auto multiply = [&](int buf) {

@@ -30,6 +30,10 @@ __device__ inline u32x4 buf_ld16(__amdgpu_buffer_rsrc_t r, uint32_t off) {
     return __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, POL);
 }
 template <int POL>
+__device__ inline float buf_ld4f(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, POL));
+}
+template <int POL>
 __device__ inline u32x2 buf_ld8(__amdgpu_buffer_rsrc_t r, uint32_t off) {
     return __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, POL);
 }

@@ -125,9 +125,17 @@ __global__ __launch_bounds__(256, 2) void k_leaf_cat_lp(LeafCatLpArgs a) {
                     const float *ar = a.Xt + (int64_t)xrow[cc] * a.ldxt + j0;
 #pragma unroll
                     for (int p = 0; p < NP; ++p) R.a[p][u] = ld2(ar + min(32 * p + 2 * lr, xc));
-                    R.b[0][u] = nb[(int64_t)cc * nt2 + row_a];
-                    R.b[1][u] = nb[(int64_t)cc * nt2 + row_b];
-                    if constexpr (TPW == 3) R.b[TPW - 1][u] = nb[(int64_t)cc * nt2 + row_c];
+                    if constexpr (TPW == 2) {
+                        // through a buffer resource over the leaf's near blocks (32-bit offsets):
+                        // faster here, slower in the three-tile form
+                        const __amdgpu_buffer_rsrc_t rb = buf_rsrc(nb, 0xFFFFFFFFu);
+                        R.b[0][u] = buf_ld4f<0>(rb, 4u * (uint32_t)(cc * nt2 + row_a));
+                        R.b[1][u] = buf_ld4f<0>(rb, 4u * (uint32_t)(cc * nt2 + row_b));
+                    } else {
+                        R.b[0][u] = nb[(int64_t)cc * nt2 + row_a];
+                        R.b[1][u] = nb[(int64_t)cc * nt2 + row_b];
+                        R.b[TPW - 1][u] = nb[(int64_t)cc * nt2 + row_c];
+                    }
                 }
             } else {
                 const int c0 = 16 * (r - RN);

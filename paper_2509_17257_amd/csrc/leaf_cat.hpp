@@ -156,7 +156,9 @@ __device__ inline void leaf_cat_slot(int64_t slot, const LeafCatArgs &a, double 
                     const int c = c0 + 4 * u + lq, cc = min(c, lim - 1);
                     R.ok[u] = c < lim;
                     const int64_t arow = nr ? (int64_t)xrow[cc] : (int64_t)cc;
-                    R.a[u] = *(const dbl2c *)(ab + arow * lda + min(32 * ch + 2 * lr, xc));
+                    R.a[u] = __builtin_bit_cast(
+                        dbl2c, buf_ld16<0>(buf_rsrc(ab, 0xFFFFFFFFu),
+                                           8u * (uint32_t)(arow * lda + min(32 * ch + 2 * lr, xc))));
 #pragma unroll
                     for (int I = 0; I < 3; ++I) R.b[I][u] = bb[(int64_t)cc * nt2 + rw[I]];
                 }
@@ -240,7 +242,9 @@ __device__ inline void leaf_cat_slot(int64_t slot, const LeafCatArgs &a, double 
                     const int64_t arow = nr ? (int64_t)xrow[cc] : (int64_t)cc;
     #pragma unroll
                     for (int p = 0; p < NP; ++p)
-                        R.a[p][u] = *(const dbl2c *)(ab + arow * lda + min(32 * p + 2 * lr, xc));
+                        R.a[p][u] = __builtin_bit_cast(
+                            dbl2c, buf_ld16<0>(buf_rsrc(ab, 0xFFFFFFFFu),
+                                               8u * (uint32_t)(arow * lda + min(32 * p + 2 * lr, xc))));
                     R.b[0][u] = bb[(int64_t)cc * nt2 + row_a];
                     R.b[1][u] = bb[(int64_t)cc * nt2 + row_b];
                 }

@@ -122,12 +122,20 @@ __global__ __launch_bounds__(256, 2) void k_leaf_cat_lp(LeafCatLpArgs a) {
                 for (int u = 0; u < 4; ++u) {
                     const int c = c0 + 4 * u + lq, cc = min(c, rn - 1);
                     R.ok[u] = c < rn;
-                    const float *ar = a.Xt + (int64_t)xrow[cc] * a.ldxt + j0;
-#pragma unroll
-                    for (int p = 0; p < NP; ++p) R.a[p][u] = ld2(ar + min(32 * p + 2 * lr, xc));
                     if constexpr (TPW == 2) {
-                        // through a buffer resource over the leaf's near blocks (32-bit offsets):
-                        // faster here, slower in the three-tile form
+                        const __amdgpu_buffer_rsrc_t rx = buf_rsrc(a.Xt + j0, 0xFFFFFFFFu);
+                        const uint32_t xo = (uint32_t)(xrow[cc] * a.ldxt);
+#pragma unroll
+                        for (int p = 0; p < NP; ++p)
+                            R.a[p][u] = __builtin_bit_cast(flt2, buf_ld8<0>(rx, 4u * (xo + min(32 * p + 2 * lr, xc))));
+                    } else {
+                        const float *ar = a.Xt + (int64_t)xrow[cc] * a.ldxt + j0;
+#pragma unroll
+                        for (int p = 0; p < NP; ++p) R.a[p][u] = ld2(ar + min(32 * p + 2 * lr, xc));
+                    }
+                    if constexpr (TPW == 2) {
+                        // through buffer resources (32-bit offsets; X below 4 GiB, which the host
+                        // checks): faster here, slower in the three-tile form
                         const __amdgpu_buffer_rsrc_t rb = buf_rsrc(nb, 0xFFFFFFFFu);
                         R.b[0][u] = buf_ld4f<0>(rb, 4u * (uint32_t)(cc * nt2 + row_a));
                         R.b[1][u] = buf_ld4f<0>(rb, 4u * (uint32_t)(cc * nt2 + row_b));

@@ -35,7 +35,9 @@ __global__ __launch_bounds__(256) void k_coupling_mfma_f32(int64_t m, int32_t C,
                                                            const int32_t *__restrict__ adm_col,
                                                            const float *__restrict__ S, const float *__restrict__ xh,
                                                            float *__restrict__ yh, int64_t ldh, Skip skip) {
-    constexpr int K = 64, MC = 16 * NJ, LDX = MC + 1;
+    // LDS row pitch MC + 4 floats: the four row groups that one read instruction touches
+    // (rows 4 apart) land on disjoint banks
+    constexpr int K = 64, MC = 16 * NJ, LDX = MC + 4;
     __shared__ float xs[2][K * LDX];
     // the column slabs of one row cluster are consecutive work-groups of one XCD, so S_b
     // comes from HBM once and from that XCD's L2 for the other slabs
@@ -131,7 +133,7 @@ __global__ __launch_bounds__(256) void k_coupling_mfma_bf16(int64_t m, int32_t C
                                                             int64_t ldh, Skip skip) {
     constexpr int K = 64, MC = 16 * NJ;
     constexpr int LDT = K + 8;  // LDS row (one column of x_s) in bf16 units, padded against bank conflicts
-    __shared__ uint16_t xs[2][MC * LDT];
+    __shared__ __align__(16) uint16_t xs[2][MC * LDT];
     // the column slabs of one row cluster are consecutive work-groups of one XCD, so S_b
     // comes from HBM once and from that XCD's L2 for the other slabs
     const int nslab = (int)((m + MC - 1) / MC), qx = blockIdx.x >> 3;
@@ -150,21 +152,50 @@ __global__ __launch_bounds__(256) void k_coupling_mfma_bf16(int64_t m, int32_t C
     for (int J = 0; J < NJ; ++J) acc[J] = flt4{0.f, 0.f, 0.f, 0.f};
 
     if (b1 > b0) {
-        constexpr int XPT = (K * MC) / 256;
+        // MC dividing 256: thread = column xc = tid % MC of x_s and the XPT consecutive rows
+        // from xr0; each global load instruction reads whole row segments (lanes over
+        // columns), and the rows go to LDS as 16-byte (8-byte for XPT = 4) stores:
+        // consecutive lanes write LDS rows 144 bytes apart, on disjoint banks.  Otherwise
+        // (MC = 48) element e = tid + 256 u is (row e / MC, column e % MC), stored one by one.
+        constexpr bool VEC = 256 % MC == 0;
+        constexpr int XPT = (K * MC) / 256, CH = XPT % 8 == 0 ? 8 : 4;
+        static_assert(!VEC || XPT % CH == 0, "rows per thread");
+        const int xc = tid % MC, xr0 = (tid / MC) * XPT;
         uint16_t xv[XPT];
         auto load_x = [&](int32_t s) {  // x-hat already rounded to BF16 (k_pack_bf16)
-            const uint16_t *src = xb + (int64_t)s * K * ldh + j0;
+            if constexpr (VEC) {
+                const uint16_t *src = xb + ((int64_t)s * K + xr0) * ldh + j0 + (xc < mc ? xc : 0);
 #pragma unroll
-            for (int u = 0; u < XPT; ++u) {
-                const int e = tid + 256 * u, r = e / MC, c = e % MC;
-                xv[u] = src[(int64_t)r * ldh + (c < mc ? c : 0)];  // columns past mc: zeroed when stored
+                for (int u = 0; u < XPT; ++u) xv[u] = src[(int64_t)u * ldh];  // columns past mc: zeroed when stored
+            } else {
+                const uint16_t *src = xb + (int64_t)s * K * ldh + j0;
+#pragma unroll
+                for (int u = 0; u < XPT; ++u) {
+                    const int e = tid + 256 * u, r = e / MC, c = e % MC;
+                    xv[u] = src[(int64_t)r * ldh + (c < mc ? c : 0)];
+                }
             }
         };
         auto store_x = [&](int buf) {  // transposed: column c of x_s is LDS row c
+            if constexpr (VEC) {
+                uint16_t *dst = &xs[buf][xc * LDT + xr0];
 #pragma unroll
-            for (int u = 0; u < XPT; ++u) {
-                const int e = tid + 256 * u, r = e / MC, c = e % MC;
-                xs[buf][c * LDT + r] = c < mc ? xv[u] : (uint16_t)0;
+                for (int q = 0; q < XPT / CH; ++q) {
+                    uint32_t d[CH / 2];
+#pragma unroll
+                    for (int i = 0; i < CH / 2; ++i)
+                        d[i] = xc < mc ? (uint32_t)xv[CH * q + 2 * i] | ((uint32_t)xv[CH * q + 2 * i + 1] << 16) : 0u;
+                    if constexpr (CH == 8)
+                        *(u32x4 *)(dst + CH * q) = u32x4{d[0], d[1], d[2], d[3]};
+                    else
+                        *(u32x2 *)(dst + CH * q) = u32x2{d[0], d[1]};
+                }
+            } else {
+#pragma unroll
+                for (int u = 0; u < XPT; ++u) {
+                    const int e = tid + 256 * u, r = e / MC, c = e % MC;
+                    xs[buf][c * LDT + r] = c < mc ? xv[u] : (uint16_t)0;
+                }
             }
         };
         u32x4 sa[2], sn[2];

@@ -262,7 +262,8 @@ __global__ __launch_bounds__(128) void k_coupling_small_lp(int k, int64_t m, int
                                                            const int32_t *__restrict__ adm_col,
                                                            const T *__restrict__ S, const float *__restrict__ xh,
                                                            float *__restrict__ yh, int64_t ldh, Skip skip) {
-    constexpr int MC = 16 * NJ, LDX = MC + 1;
+    // LDS row pitch MC + 4 floats: the four row groups of one read (rows 4 apart) on disjoint banks
+    constexpr int MC = 16 * NJ, LDX = MC + 4;
     __shared__ float xs[2][32 * LDX];
     const int nslab = (int)((m + MC - 1) / MC), qx = blockIdx.x >> 3;
     const int slot = (blockIdx.x & 7) * rows_per_xcd + qx / nslab;

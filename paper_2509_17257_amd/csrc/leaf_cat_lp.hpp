@@ -16,19 +16,17 @@
 // "even" and an "odd" column tile) and B = N^T (one 4-byte load per row tile and k-step).
 #pragma once
 
-#include <type_traits>
-
 #include "leaf_cat.hpp"
 #include "leaf_lp.hpp"
 
 namespace h2x {
 namespace lp {
 
-template <int NP, int TPW>
+template <int NP>
 struct CatRoundLp {
-    flt2 a[NP][4];    // [column half p][k-step u]: columns 32p + 2 (l % 16) + {0, 1}
-    float b[TPW][4];  // [row tile of the wave][k-step u]: row 16 I + l % 16
-    int ok[4];        // k-row of step u inside its segment
+    flt2 a[NP][4];  // [column half p][k-step u]: columns 32p + 2 (l % 16) + {0, 1}
+    float b[2][4];  // [row tile of the wave][k-step u]: row 16 I + l % 16
+    int ok[4];      // k-row of step u inside its segment
 };
 
 __device__ inline float ld1(const float *p) { return *p; }
@@ -92,58 +90,40 @@ __global__ __launch_bounds__(256, 2) void k_leaf_cat_lp(LeafCatLpArgs a) {
     const TV *vb = (const TV *)a.Vt + a.vt_off[l];
     const int RN = (rn + 15) >> 4, RT = RN + ((k + 15) >> 4);
     const int xc = (mc - 1) & ~1;  // last even column offset of the slab
-    // row tiles per wave: with a BF16 basis, leaves of 33-48 rows are one row group of three
-    // tiles over all four waves (the BF16 basis leaves the register room to keep the
-    // occupancy); otherwise two row groups of two tiles
-    constexpr int TPW = std::is_same<TV, bf16_t>::value ? 3 : 2;
-
+    // two row tiles per wave: a 64-row chunk of more than two tiles is two row groups of two
+    // waves (k-groups), otherwise one row group of all four waves
     for (int i0 = 0; i0 < nt; i0 += 64) {
         const int ic = min(64, nt - i0);
         const int ntile = (ic + 15) >> 4;
-        const int G = ntile > TPW ? 2 : 4;     // waves per row group (k-groups)
+        const int G = ntile > 2 ? 2 : 4;       // waves per row group (k-groups)
         const int wr = w / G, g = w - wr * G;  // row group, k-group (wave-uniform)
         const int tl0 = 2 * wr;                // first row tile of the wave
-        const bool t0 = tl0 < ntile, t1 = tl0 + 1 < ntile, t2 = TPW == 3 && G == 4 && ntile > 2;
-        const int row_a = i0 + min(16 * tl0 + lr, ic - 1), row_b = i0 + min(16 * tl0 + 16 + lr, ic - 1),
-                  row_c = i0 + min(16 * tl0 + 32 + lr, ic - 1);
+        const bool t0 = tl0 < ntile, t1 = tl0 + 1 < ntile;
+        const int row_a = i0 + min(16 * tl0 + lr, ic - 1), row_b = i0 + min(16 * tl0 + 16 + lr, ic - 1);
 
-        flt4v acc[2 * NP][TPW];
+        flt4v acc[2 * NP][2];
 #pragma unroll
-        for (int J = 0; J < 2 * NP; ++J)
-#pragma unroll
-            for (int I = 0; I < TPW; ++I) acc[J][I] = flt4v{0.f, 0.f, 0.f, 0.f};
+        for (int J = 0; J < 2 * NP; ++J) acc[J][0] = acc[J][1] = flt4v{0.f, 0.f, 0.f, 0.f};
 
         // round r (clamped to the wave's rounds) -> registers; both branches issue the same
-        // number of loads from clamped in-range addresses, so the wait counts stay exact
-        auto load = [&](int r, CatRoundLp<NP, TPW> &R) {
+        // number of loads from clamped in-range addresses, so the wait counts stay exact.  The
+        // near-field operands come through buffer resources (32-bit byte offsets; the host
+        // takes this form only while X is below 4 GiB).
+        auto load = [&](int r, CatRoundLp<NP> &R) {
             if (r < RN) {
                 const int c0 = 16 * r;
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     const int c = c0 + 4 * u + lq, cc = min(c, rn - 1);
                     R.ok[u] = c < rn;
-                    if constexpr (TPW == 2) {
-                        const __amdgpu_buffer_rsrc_t rx = buf_rsrc(a.Xt + j0, 0xFFFFFFFFu);
-                        const uint32_t xo = (uint32_t)(xrow[cc] * a.ldxt);
+                    const __amdgpu_buffer_rsrc_t rx = buf_rsrc(a.Xt + j0, 0xFFFFFFFFu);
+                    const uint32_t xo = (uint32_t)(xrow[cc] * a.ldxt);
 #pragma unroll
-                        for (int p = 0; p < NP; ++p)
-                            R.a[p][u] = __builtin_bit_cast(flt2, buf_ld8<0>(rx, 4u * (xo + min(32 * p + 2 * lr, xc))));
-                    } else {
-                        const float *ar = a.Xt + (int64_t)xrow[cc] * a.ldxt + j0;
-#pragma unroll
-                        for (int p = 0; p < NP; ++p) R.a[p][u] = ld2(ar + min(32 * p + 2 * lr, xc));
-                    }
-                    if constexpr (TPW == 2) {
-                        // through buffer resources (32-bit offsets; X below 4 GiB, which the host
-                        // checks): faster here, slower in the three-tile form
-                        const __amdgpu_buffer_rsrc_t rb = buf_rsrc(nb, 0xFFFFFFFFu);
-                        R.b[0][u] = buf_ld4f<0>(rb, 4u * (uint32_t)(cc * nt2 + row_a));
-                        R.b[1][u] = buf_ld4f<0>(rb, 4u * (uint32_t)(cc * nt2 + row_b));
-                    } else {
-                        R.b[0][u] = nb[(int64_t)cc * nt2 + row_a];
-                        R.b[1][u] = nb[(int64_t)cc * nt2 + row_b];
-                        R.b[TPW - 1][u] = nb[(int64_t)cc * nt2 + row_c];
-                    }
+                    for (int p = 0; p < NP; ++p)
+                        R.a[p][u] = __builtin_bit_cast(flt2, buf_ld8<0>(rx, 4u * (xo + min(32 * p + 2 * lr, xc))));
+                    const __amdgpu_buffer_rsrc_t rb = buf_rsrc(nb, 0xFFFFFFFFu);
+                    R.b[0][u] = buf_ld4f<0>(rb, 4u * (uint32_t)(cc * nt2 + row_a));
+                    R.b[1][u] = buf_ld4f<0>(rb, 4u * (uint32_t)(cc * nt2 + row_b));
                 }
             } else {
                 const int c0 = 16 * (r - RN);
@@ -156,11 +136,10 @@ __global__ __launch_bounds__(256, 2) void k_leaf_cat_lp(LeafCatLpArgs a) {
                     for (int p = 0; p < NP; ++p) R.a[p][u] = ld2(ar + min(32 * p + 2 * lr, xc));
                     R.b[0][u] = ld1(vb + (int64_t)cc * nt2 + row_a);
                     R.b[1][u] = ld1(vb + (int64_t)cc * nt2 + row_b);
-                    if constexpr (TPW == 3) R.b[TPW - 1][u] = ld1(vb + (int64_t)cc * nt2 + row_c);
                 }
             }
         };
-        auto multiply = [&](const CatRoundLp<NP, TPW> &R, bool basis) {
+        auto multiply = [&](const CatRoundLp<NP> &R, bool basis) {
             const bool rnd = a.round_y && basis;
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
@@ -176,10 +155,6 @@ __global__ __launch_bounds__(256, 2) void k_leaf_cat_lp(LeafCatLpArgs a) {
                         if (t1)
                             acc[2 * p + hj][1] =
                                 __builtin_amdgcn_mfma_f32_16x16x4f32(v[hj], R.b[1][u], acc[2 * p + hj][1], 0, 0, 0);
-                        if constexpr (TPW == 3)
-                            if (t2)
-                                acc[2 * p + hj][TPW - 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(
-                                    v[hj], R.b[TPW - 1][u], acc[2 * p + hj][TPW - 1], 0, 0, 0);
                     }
                 }
             }
@@ -187,7 +162,7 @@ __global__ __launch_bounds__(256, 2) void k_leaf_cat_lp(LeafCatLpArgs a) {
 
         if (g < RT) {
             const int last = g + ((RT - 1 - g) / G) * G;  // the wave's last round
-            CatRoundLp<NP, TPW> s0, s1, s2;
+            CatRoundLp<NP> s0, s1, s2;
             int r = g;
             load(r, s0);
             load(min(r + G, last), s1);
@@ -209,16 +184,15 @@ __global__ __launch_bounds__(256, 2) void k_leaf_cat_lp(LeafCatLpArgs a) {
         }
         // partial tiles of the G waves of each row group, added in wave order.  Lane l,
         // register q of acc[2p + hj][I] -> column 32p + 2 (4 (l / 16) + q) + hj, row
-        // 16 (tl0 + I) + l % 16 (the third tile only in a three-tile row group).
+        // 16 (tl0 + I) + l % 16.
         for (int gg = 0; gg < G; ++gg) {
             if (g == gg)
 #pragma unroll
                 for (int J = 0; J < 2 * NP; ++J)
 #pragma unroll
-                    for (int I = 0; I < TPW; ++I)
+                    for (int I = 0; I < 2; ++I)
 #pragma unroll
                         for (int q = 0; q < 4; ++q) {
-                            if (I == 2 && !t2) continue;
                             const int col = 32 * (J >> 1) + 2 * (4 * lq + q) + (J & 1);
                             const int row = 16 * (tl0 + I) + lr;
                             float *cell = &red[row * LDR + col];

@@ -771,9 +771,9 @@ hipError_t matmul_typed(const DevMat &dm, const TuneCfg &cfg, int64_t m, double 
             // leaf_kind 3 or 0), else a 64-row tile per wave and term (leaf_kind 1 or 2)
             const size_t cat_lds = sizeof(int32_t) * (size_t)std::max(1, dm.max_near_rows);
             const size_t red = NPl == 2 ? lp::leaf_cat_lp_red_bytes<2>() : lp::leaf_cat_lp_red_bytes<1>();
-            // (the FP32 form reads the rows of X through a buffer resource: 32-bit byte offsets)
+            // (it reads the rows of X through a buffer resource: 32-bit byte offsets)
             const bool cat_ok = !dm.cplx && cat_lds + red + 64 <= 65536 &&
-                                (rb || sizeof(float) * (size_t)dm.n * (size_t)ldxt < ((size_t)1 << 32));
+                                sizeof(float) * (size_t)dm.n * (size_t)ldxt < ((size_t)1 << 32);
             if (cat_ok && (cfg.leaf_kind == 0 || cfg.leaf_kind == 3)) {
                 const lp::LeafCatLpArgs a{dm.k, m, dm.L, dm.leaf_order, dm.leaves, dm.first, dm.size, dm.perm,
                                           dm.Vt, dm.vt_off, yh, ldh, dm.near_ptr, dm.near_col, dm.near_off,

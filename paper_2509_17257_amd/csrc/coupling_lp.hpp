@@ -35,10 +35,14 @@ __global__ __launch_bounds__(256) void k_coupling_mfma_f32(int64_t m, int32_t C,
                                                            const int32_t *__restrict__ adm_col,
                                                            const float *__restrict__ S, const float *__restrict__ xh,
                                                            float *__restrict__ yh, int64_t ldh, Skip skip) {
-    // LDS row pitch MC + 4 floats: the four row groups that one read instruction touches
-    // (rows 4 apart) land on disjoint banks
-    constexpr int K = 64, MC = 16 * NJ, LDX = MC + 4;
-    __shared__ float xs[2][K * LDX];
+    // x_s in LDS, two layouts.  64 columns (TR): transposed (column c of x_s is LDS row c,
+    // pitch K + 4 floats), so a lane reads the four rows 16 a + 4 g .. + 3 of its column, the
+    // operands of four k-steps, with one 16-byte load (16 lanes of consecutive columns on
+    // disjoint banks).  Fewer columns: row-major with pitch MC + 4 floats (the four row groups
+    // of one read, rows 4 apart, on disjoint banks), which measured faster there.
+    constexpr int K = 64, MC = 16 * NJ, LDX = MC + 4, LDT = K + 4;
+    constexpr bool TR = NJ == 4;
+    __shared__ __align__(16) float xs[2][TR ? MC * LDT : K * LDX];
     // the column slabs of one row cluster are consecutive work-groups of one XCD, so S_b
     // comes from HBM once and from that XCD's L2 for the other slabs
     const int nslab = (int)((m + MC - 1) / MC), qx = blockIdx.x >> 3;
@@ -57,21 +61,39 @@ __global__ __launch_bounds__(256) void k_coupling_mfma_f32(int64_t m, int32_t C,
     for (int J = 0; J < NJ; ++J) acc[J] = flt4{0.f, 0.f, 0.f, 0.f};
 
     if (b1 > b0) {
+        // TR: thread = column xc = tid % MC and the XPT consecutive rows from xr0 (global loads
+        // read whole row segments, LDS stores are 16 bytes); otherwise element e = tid + 256 u
+        // is (row e / MC, column e % MC)
         constexpr int XPT = (K * MC) / 256;
+        const int xc = tid % MC, xr0 = (tid / MC) * XPT;
         float xv[XPT];
         auto load_x = [&](int32_t s) {
-            const float *src = xh + (int64_t)s * K * ldh + j0;
+            if constexpr (TR) {
+                const float *src = xh + ((int64_t)s * K + xr0) * ldh + j0 + (xc < mc ? xc : 0);
 #pragma unroll
-            for (int u = 0; u < XPT; ++u) {
-                const int e = tid + 256 * u, r = e / MC, c = e % MC;
-                xv[u] = src[(int64_t)r * ldh + (c < mc ? c : 0)];  // columns past mc: zeroed when stored
+                for (int u = 0; u < XPT; ++u) xv[u] = src[(int64_t)u * ldh];  // columns past mc: zeroed when stored
+            } else {
+                const float *src = xh + (int64_t)s * K * ldh + j0;
+#pragma unroll
+                for (int u = 0; u < XPT; ++u) {
+                    const int e = tid + 256 * u, r = e / MC, c = e % MC;
+                    xv[u] = src[(int64_t)r * ldh + (c < mc ? c : 0)];  // columns past mc: zeroed when stored
+                }
             }
         };
         auto store_x = [&](int buf) {
+            if constexpr (TR) {
+                float *dst = &xs[buf][xc * LDT + xr0];
 #pragma unroll
-            for (int u = 0; u < XPT; ++u) {
-                const int e = tid + 256 * u, r = e / MC, c = e % MC;
-                xs[buf][r * LDX + c] = c < mc ? xv[u] : 0.f;
+                for (int q = 0; q < XPT / 4; ++q)
+                    *(flt4 *)(dst + 4 * q) = xc < mc ? flt4{xv[4 * q], xv[4 * q + 1], xv[4 * q + 2], xv[4 * q + 3]}
+                                                     : flt4{0.f, 0.f, 0.f, 0.f};
+            } else {
+#pragma unroll
+                for (int u = 0; u < XPT; ++u) {
+                    const int e = tid + 256 * u, r = e / MC, c = e % MC;
+                    xs[buf][r * LDX + c] = c < mc ? xv[u] : 0.f;
+                }
             }
         };
         flt4 sa[4], sn[4];
@@ -82,18 +104,32 @@ __global__ __launch_bounds__(256) void k_coupling_mfma_f32(int64_t m, int32_t C,
                 dst[a] = __builtin_bit_cast(flt4, buf_ld16<kBufNT>(rs, 16u * (w * 4 * 64 + a * 64 + lane)));
         };
 
+        // the same order of products per accumulator in both layouts
         auto multiply = [&](int buf) {
             const float *xb = xs[buf];
+            if constexpr (TR) {
 #pragma unroll
-            for (int a = 0; a < 4; ++a)
+                for (int a = 0; a < 4; ++a)
 #pragma unroll
-                for (int h = 0; h < 4; ++h) {
-                    const int krow = 16 * a + 4 * g + h;
+                    for (int J = 0; J < NJ; ++J) {
+                        // rows 16 a + 4 g + h (h = 0..3) of column 16 J + lr: k-steps 4 a + h
+                        const flt4 bv = *(const flt4 *)(xb + (16 * J + lr) * LDT + 16 * a + 4 * g);
 #pragma unroll
-                    for (int J = 0; J < NJ; ++J)
-                        acc[J] = __builtin_amdgcn_mfma_f32_16x16x4f32(sa[a][h], xb[krow * LDX + 16 * J + lr], acc[J],
-                                                                       0, 0, 0);
-                }
+                        for (int h = 0; h < 4; ++h)
+                            acc[J] = __builtin_amdgcn_mfma_f32_16x16x4f32(sa[a][h], bv[h], acc[J], 0, 0, 0);
+                    }
+            } else {
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int h = 0; h < 4; ++h) {
+                        const int krow = 16 * a + 4 * g + h;
+#pragma unroll
+                        for (int J = 0; J < NJ; ++J)
+                            acc[J] = __builtin_amdgcn_mfma_f32_16x16x4f32(sa[a][h], xb[krow * LDX + 16 * J + lr],
+                                                                           acc[J], 0, 0, 0);
+                    }
+            }
         };
 
         load_x(adm_col[b0]);

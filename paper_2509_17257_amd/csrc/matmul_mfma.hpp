@@ -38,7 +38,13 @@ __global__ __launch_bounds__(256) void k_coupling_mfma_f64(int64_t m, int32_t C,
                                                            int64_t ldh, Skip skip, int jpass) {
     constexpr int MC = 16 * NJ;   // columns per work-group
     constexpr int LDX = MC + 1;   // padded LDS row
-    __shared__ double xs[2][kMfmaK * LDX];
+    // 64 columns (TR): x_s transposed in LDS (column c is LDS row c, pitch 66 doubles) with the
+    // rows of each group of eight in the order of the S operand pairs (row 8 a + 4 h + l at
+    // position 8 a + 2 l + h), so one 16-byte read gives a lane the operands of both k-steps of
+    // a pair; narrower slabs keep the row-major tile, which measured faster there
+    constexpr bool TR = NJ == 4;
+    constexpr int LDT = kMfmaK + 2;
+    __shared__ __align__(16) double xs[2][TR ? MC * LDT : kMfmaK * LDX];
     // the column slabs of one row cluster are consecutive work-groups of one XCD, so S_b
     // comes from HBM once and from that XCD's L2 for the other slabs
     const int nslab = (int)((m + MC - 1) / MC), qx = blockIdx.x >> 3;
@@ -58,26 +64,49 @@ __global__ __launch_bounds__(256) void k_coupling_mfma_f64(int64_t m, int32_t C,
 
     if (b1 > b0) {
         // x_s staging: element e = row * MC + col, MC * 64 elements over 256 threads
+        // TR: thread = column xc = tid % MC and the XPT (16) consecutive rows from xr0; else
+        // element e = tid + 256 u is (row e / MC, column e % MC)
         constexpr int XPT = (kMfmaK * MC) / 256;  // elements per thread (4 * NJ)
+        const int xc = tid % MC, xr0 = (tid / MC) * XPT;
         double xv[XPT];
+        // jpass: column c takes its partner c ^ 1 (J x = (-im, re) per complex column); columns
+        // past mc are zeroed when stored
         auto load_x = [&](int32_t s) {
-            const double *src = xh + (int64_t)s * kMfmaK * ldh + j0;
+            if constexpr (TR) {
+                const double *src = xh + ((int64_t)s * kMfmaK + xr0) * ldh + j0 + ((xc < mc ? xc : 0) ^ jpass);
 #pragma unroll
-            for (int u = 0; u < XPT; ++u) {
-                const int e = tid + 256 * u, r = e / MC, c = e % MC;
-                // jpass: column c takes its partner c ^ 1 (J x = (-im, re) per complex column)
-                xv[u] = src[(int64_t)r * ldh + ((c < mc ? c : 0) ^ jpass)];  // columns past mc: zeroed when stored
-            }
-        };
-        auto store_x = [&](int buf) {
+                for (int u = 0; u < XPT; ++u) xv[u] = src[(int64_t)u * ldh];
+            } else {
+                const double *src = xh + (int64_t)s * kMfmaK * ldh + j0;
 #pragma unroll
-            for (int u = 0; u < XPT; ++u) {
-                const int e = tid + 256 * u, r = e / MC, c = e % MC;
-                const double v = (jpass & ~c & 1) ? -xv[u] : xv[u];
-                xs[buf][r * LDX + c] = c < mc ? v : 0.0;
+                for (int u = 0; u < XPT; ++u) {
+                    const int e = tid + 256 * u, r = e / MC, c = e % MC;
+                    xv[u] = src[(int64_t)r * ldh + ((c < mc ? c : 0) ^ jpass)];
+                }
             }
         };
         typedef double dbl2 __attribute__((ext_vector_type(2)));
+        auto store_x = [&](int buf) {
+            if constexpr (TR) {
+                const bool neg = jpass & ~xc & 1;
+                double *dst = &xs[buf][xc * LDT + xr0];
+#pragma unroll
+                for (int a8 = 0; a8 < XPT / 8; ++a8)
+#pragma unroll
+                    for (int l = 0; l < 4; ++l) {
+                        const double v0 = neg ? -xv[8 * a8 + l] : xv[8 * a8 + l];
+                        const double v1 = neg ? -xv[8 * a8 + 4 + l] : xv[8 * a8 + 4 + l];
+                        *(dbl2 *)(dst + 8 * a8 + 2 * l) = xc < mc ? dbl2{v0, v1} : dbl2{0.0, 0.0};
+                    }
+            } else {
+#pragma unroll
+                for (int u = 0; u < XPT; ++u) {
+                    const int e = tid + 256 * u, r = e / MC, c = e % MC;
+                    const double v = (jpass & ~c & 1) ? -xv[u] : xv[u];
+                    xs[buf][r * LDX + c] = c < mc ? v : 0.0;
+                }
+            }
+        };
         dbl2 sa[8], sn[8];
         auto load_s = [&](int64_t b, dbl2 *dst) {
             // S_b (32 KB) through a buffer resource: streaming loads at 32-bit offsets
@@ -87,18 +116,32 @@ __global__ __launch_bounds__(256) void k_coupling_mfma_f64(int64_t m, int32_t C,
                 dst[kk2] = __builtin_bit_cast(dbl2, buf_ld16<kBufNT>(rs, 16u * (w * 8 * 64 + kk2 * 64 + lane)));
         };
 
+        // the same order of products per accumulator in both layouts
         auto multiply = [&](int buf) {
             const double *xb = xs[buf];
 #pragma unroll
             for (int kk2 = 0; kk2 < 8; ++kk2) {
+                if constexpr (TR) {
+                    dbl2 bq[NJ];  // rows 8 kk2 + lq and 8 kk2 + 4 + lq of column 16 J + lr
 #pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    const double a = h ? sa[kk2].y : sa[kk2].x;
-                    const int krow = 4 * (2 * kk2 + h) + lq;
+                    for (int J = 0; J < NJ; ++J) bq[J] = *(const dbl2 *)(xb + (16 * J + lr) * LDT + 8 * kk2 + 2 * lq);
 #pragma unroll
-                    for (int J = 0; J < NJ; ++J) {
-                        const double bv = xb[krow * LDX + 16 * J + lr];
-                        acc[J] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc[J], 0, 0, 0);
+                    for (int h = 0; h < 2; ++h) {
+                        const double a = h ? sa[kk2].y : sa[kk2].x;
+#pragma unroll
+                        for (int J = 0; J < NJ; ++J)
+                            acc[J] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, h ? bq[J].y : bq[J].x, acc[J], 0, 0, 0);
+                    }
+                } else {
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const double a = h ? sa[kk2].y : sa[kk2].x;
+                        const int krow = 4 * (2 * kk2 + h) + lq;
+#pragma unroll
+                        for (int J = 0; J < NJ; ++J) {
+                            const double bv = xb[krow * LDX + 16 * J + lr];
+                            acc[J] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc[J], 0, 0, 0);
+                        }
                     }
                 }
             }
